@@ -1,0 +1,257 @@
+/*
+ * r4d.h -- C ABI of the MI355X 4D-rotor Gaussian splatting renderer.
+ *
+ * One render slices rotor-parameterised 4D Gaussians at a time t into 3D
+ * Gaussians (paper Sec. 3.2.2, Eq. center-motion and App. A), projects them with
+ * the EWA approximation, shades them with spherical harmonics and alpha-
+ * composites them front to back in depth order (paper Sec. 3.1), tile by tile.
+ * The backward pass returns the gradient of a scalar loss with respect to every
+ * Gaussian parameter, given the loss gradient with respect to the images (the
+ * paper back-propagates image-loss gradients through this renderer, Sec. 3 and
+ * Fig. "Framework Overview").
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller, contiguous,
+ *    component-major ("SoA"): element (c, i) of an [C][n] array is ptr[c*n + i].
+ *  - r4d_view / r4d_settings / r4d_gaussians / r4d_grads structs themselves
+ *    live in HOST memory; they are read during the call and not retained.
+ *  - Every call is stream-ordered on the caller's hipStream_t (passed as
+ *    void*; NULL = the legacy default stream).  All calls on one context must
+ *    use one stream, or the caller must order them.
+ *  - No call throws or aborts.  Each returns an r4d_status; on failure the
+ *    message is available from r4d_last_error(ctx).  Inputs are never
+ *    modified.
+ *  - A failed call leaves outputs unspecified.
+ */
+#ifndef R4D_H
+#define R4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  R4D_OK = 0,
+  R4D_ERR_INVALID_ARG = -1, /* null pointer, bad size, unsupported setting   */
+  R4D_ERR_HIP = -2,         /* a HIP runtime call failed                      */
+  R4D_ERR_OOM = -3,         /* device allocation failed                       */
+  R4D_ERR_CAPACITY = -4,    /* duplicate count beyond what one render holds   */
+  R4D_ERR_STATE = -5        /* saved state does not match the call            */
+} r4d_status;
+
+/* The Gaussian set (paper Sec. 3.2.1: a 4D centre, 4D scaling, a rotor of 8
+ * coefficients, an opacity and SH coefficients).
+ *   means      [4][n]   x, y, z, t
+ *   log_scales [4][n]   log s_x, log s_y, log s_z, log s_t   (s = exp(.))
+ *   rotors     [8][n]   s, b01, b02, b12, b03, b13, b23, p   (component order of
+ *                       the rotor definition in Sec. 3.2.1; unnormalised: the
+ *                       library applies the normalisation of App. A)
+ *   opacity    [n]      already activated, in (0, 1)
+ *   sh         [3k][n]  row = coefficient*3 + channel, k = (sh_degree+1)^2
+ * n may be 0 (the image is the background). sh_degree is 0..3. */
+typedef struct {
+  int32_t n;
+  int32_t sh_degree;
+  const float *means;
+  const float *log_scales;
+  const float *rotors;
+  const float *opacity;
+  const float *sh;
+} r4d_gaussians;
+
+/* One render: a pinhole camera and a time.  world_to_cam is the row-major
+ * 3x4 [R|t] mapping world points into camera space with OpenCV axes (x right,
+ * y down, z forward).  Pixel (x, y) is sampled at (x + 0.5, y + 0.5).
+ * Images are planar [3][height][width]. */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float world_to_cam[12];
+  float t;
+  float bg[3];
+} r4d_view;
+
+/* Cut-offs and conventions (values in parentheses are the defaults that
+ * r4d_default_settings writes).
+ *   tile_size     8, 16 or 32 pixels (16)
+ *   near_plane    camera-space depth at or below which a Gaussian is dropped (0.2)
+ *   time_cull     a Gaussian is dropped if lambda (t - mu_t)^2 > time_cull (16;
+ *                 the visibility threshold of Sec. 3.2.2)
+ *   extent_sigma  a Gaussian reaches a pixel only if its Mahalanobis distance
+ *                 q satisfies q <= extent_sigma^2 (3)
+ *   alpha_min     contributions with alpha < alpha_min are skipped (1/255)
+ *   alpha_max     alpha is clamped to alpha_max (0.99)
+ *   T_min         compositing of a pixel stops before the Gaussian that would
+ *                 take the transmittance below T_min (1e-4)
+ *   dilation      added to the diagonal of every 2D covariance (0.3)
+ *   guard_band    x/z and y/z entering the projection Jacobian are clamped to
+ *                 guard_band * half image size / focal (1.3)
+ *   flags         reserved, must be 0 */
+typedef struct {
+  int32_t tile_size;
+  float near_plane;
+  float time_cull;
+  float extent_sigma;
+  float alpha_min;
+  float alpha_max;
+  float T_min;
+  float dilation;
+  float guard_band;
+  int32_t flags;
+} r4d_settings;
+
+/* Gradients, same layouts as r4d_gaussians (means [4][n], log_scales [4][n],
+ * rotors [8][n], opacity [n], sh [3k][n]); all DEVICE pointers, overwritten. */
+typedef struct {
+  float *means;
+  float *log_scales;
+  float *rotors;
+  float *opacity;
+  float *sh;
+} r4d_grads;
+
+/* Double-precision twins used by finite-difference checks.  The same kernel
+ * templates run in float64; depths are still ordered by their float32 value. */
+typedef struct {
+  int32_t n;
+  int32_t sh_degree;
+  const double *means;
+  const double *log_scales;
+  const double *rotors;
+  const double *opacity;
+  const double *sh;
+} r4d_gaussians_f64;
+
+typedef struct {
+  double *means;
+  double *log_scales;
+  double *rotors;
+  double *opacity;
+  double *sh;
+} r4d_grads_f64;
+
+typedef struct r4d_ctx r4d_ctx;
+typedef struct r4d_saved r4d_saved;
+
+/* Fills *s with the defaults listed above. */
+void r4d_default_settings(r4d_settings *s);
+
+/* Creates a context on HIP device `device`.  The context owns a grow-only
+ * device workspace and a cache of saved-state arenas; it is released by
+ * r4d_destroy.  Returns R4D_ERR_HIP if the device cannot be selected. */
+r4d_status r4d_create(r4d_ctx **ctx, int device);
+void r4d_destroy(r4d_ctx *ctx);
+
+/* Forward render of n_views >= 1 views of one Gaussian set.
+ *   images  DEVICE float, view v at offset sum_{u<v} 3*H_u*W_u, planar [3][H][W]
+ *   saved   if non-NULL, receives an opaque handle holding what the backward
+ *           pass needs (per view: projected records, sorted tile lists, tile
+ *           ranges, final transmittance and last-contributor count per pixel);
+ *           release it with r4d_saved_release.  NULL = inference only.
+ * The call reads back one integer per view (the duplicate count) and so
+ * synchronises the stream once per view.
+ * Errors: R4D_ERR_INVALID_ARG (null pointers, n < 0, bad degree, bad view size,
+ * tile_size not 8/16/32), R4D_ERR_CAPACITY (more than 2^31 tile entries in one
+ * view), R4D_ERR_OOM, R4D_ERR_HIP. */
+r4d_status r4d_render_forward(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
+                              int n_views, const r4d_settings *settings, float *images,
+                              r4d_saved **saved, void *stream);
+
+/* Backward of r4d_render_forward.  g, views, n_views and settings must be
+ * those of the forward call that produced `saved` (R4D_ERR_STATE otherwise).
+ *   dL_dimages  DEVICE float, same layout as the forward images
+ *   out         gradients w.r.t. means, log_scales, rotors, opacity and sh,
+ *               summed over the views; overwritten (not accumulated).
+ * Gradients through the alpha clamp, the rgb clamp at 0 and every cull or skip
+ * are zero.  Per-Gaussian sums are accumulated with float atomics, so the
+ * last bits can vary from run to run. */
+r4d_status r4d_render_backward(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
+                               int n_views, const r4d_settings *settings,
+                               const r4d_saved *saved, const float *dL_dimages, r4d_grads *out,
+                               void *stream);
+
+/* Same as the two calls above in float64 (test use: finite differences). */
+r4d_status r4d_render_forward_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g,
+                                  const r4d_view *views, int n_views,
+                                  const r4d_settings *settings, double *images,
+                                  r4d_saved **saved, void *stream);
+r4d_status r4d_render_backward_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g,
+                                   const r4d_view *views, int n_views,
+                                   const r4d_settings *settings, const r4d_saved *saved,
+                                   const double *dL_dimages, r4d_grads_f64 *out, void *stream);
+
+/* Returns the saved arena to its context's cache.  NULL is ignored. */
+void r4d_saved_release(r4d_saved *saved);
+
+/* Gradient of the mean absolute error L = sum |image - target| / count
+ * (the L1 term of the paper's loss, Sec. 3.3 "Total Loss"):
+ *   dL_dimage[i] = sign(image[i] - target[i]) / count   (0 where equal)
+ * image, target, dL_dimage: DEVICE float [count].  loss: DEVICE float scalar
+ * or NULL; if given it receives L (accumulated with atomics, so it is
+ * overwritten first). */
+r4d_status r4d_l1_loss_grad(r4d_ctx *ctx, const float *image, const float *target, int64_t count,
+                            float *dL_dimage, float *loss, void *stream);
+
+/* Introspection of saved state (tests and the benchmark).
+ * r4d_saved_stats writes, for view v: n_visible (Gaussians with at least one
+ * tile), n_dup (tile entries D), tiles_x, tiles_y. */
+r4d_status r4d_saved_stats(const r4d_saved *saved, int view, int64_t *n_visible, int64_t *n_dup,
+                           int32_t *tiles_x, int32_t *tiles_y);
+
+/* Copies one saved buffer of view v into dst (DEVICE, at least `bytes`).
+ *   R4D_BUF_RECORDS   per Gaussian, 12 floats (or doubles for the f64 path):
+ *                     mean2d.x, mean2d.y, conic a, conic b, conic c,
+ *                     opacity_t, depth, (unused), r, g, b, (unused) -- record i
+ *                     at [12*i]; q = a dx^2 + 2 b dx dy + c dy^2.  Only
+ *                     records with a depth key other than 0xffffffff are set.
+ *   R4D_BUF_RECT      per Gaussian, 4 uint16: tile x0, y0, x1, y1 (x1, y1
+ *                     exclusive; all zero when culled)
+ *   R4D_BUF_DEPTHKEY  per Gaussian uint32: float32 bit pattern of the depth,
+ *                     0xffffffff when culled
+ *   R4D_BUF_VALUES    D uint32: Gaussian index of each tile entry, sorted by
+ *                     (tile, depth, index)
+ *   R4D_BUF_RANGES    tiles_x*tiles_y pairs of uint32 [start, end) into VALUES
+ *   R4D_BUF_TFINAL    H*W float (double): final transmittance per pixel
+ *   R4D_BUF_NCONTRIB  H*W uint32: tile-list entries up to the last contributor
+ *   R4D_BUF_NEVAL     H*W uint32: tile-list entries the forward evaluated for the
+ *                     pixel (only if timing was enabled for the forward call,
+ *                     R4D_ERR_STATE otherwise)
+ * `bytes` must equal the buffer size (R4D_ERR_INVALID_ARG otherwise). */
+enum {
+  R4D_BUF_RECORDS = 0,
+  R4D_BUF_RECT = 1,
+  R4D_BUF_DEPTHKEY = 2,
+  R4D_BUF_VALUES = 3,
+  R4D_BUF_RANGES = 4,
+  R4D_BUF_TFINAL = 5,
+  R4D_BUF_NCONTRIB = 6,
+  R4D_BUF_NEVAL = 7
+};
+r4d_status r4d_saved_copy(const r4d_saved *saved, int view, int buffer, void *dst, size_t bytes,
+                          void *stream);
+
+/* Per-stage timing with HIP events recorded on the call's stream around each
+ * kernel launch (measurement aid; off by default, adds no synchronisation to
+ * the render calls).  Stages: 0 preprocess_fwd, 1 depth_sort, 2 count_scan,
+ * 3 emit, 4 tile_sort, 5 tile_ranges, 6 raster_fwd, 7 raster_bwd,
+ * 8 preprocess_bwd.  r4d_get_timings synchronises on the recorded events and
+ * writes, per stage, the summed milliseconds and the number of launches since
+ * the last reset (arrays of R4D_NUM_STAGES entries). */
+#define R4D_NUM_STAGES 9
+r4d_status r4d_set_timing(r4d_ctx *ctx, int enable);
+r4d_status r4d_get_timings(r4d_ctx *ctx, double *ms, int64_t *launches, int reset);
+const char *r4d_stage_name(int stage);
+
+/* Human-readable status name; never NULL. */
+const char *r4d_status_string(r4d_status s);
+/* Last error message recorded on ctx (empty string if none); never NULL. */
+const char *r4d_last_error(const r4d_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* R4D_H */

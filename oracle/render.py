@@ -303,13 +303,15 @@ def preprocess(P: dict, view: dict, st: dict) -> dict:
 AMB_Q = 1e-4          # |q - extent^2|
 AMB_ALPHA_REL = 5e-5  # |a - alpha_min| / alpha_min
 AMB_T_REL = 1e-4      # |T (1 - a) - T_min| / T_min
-AMB_DEPTH_REL = 2.0 ** -20
+AMB_DEPTH_REL = 2.0 ** -21   # a few float32 roundings of the depth
 AMB_WEIGHT = 1e-5
 
 
-def _depth_tie_flags(used, au, T_before, dep):
+def _depth_tie_flags(used, au, T_before, dep, rgb):
     """Rows in which two consecutive contributors have depths within
-    AMB_DEPTH_REL of each other (their FP32 order may differ) and enough weight."""
+    AMB_DEPTH_REL of each other (their FP32 order may differ) and swapping them
+    could move the pixel by more than AMB_WEIGHT: a swap of neighbours i, j
+    changes the colour by T_i a_i a_j (c_j - c_i)."""
     c, G = used.shape
     if G < 2:
         return torch.zeros(c, dtype=torch.bool)
@@ -320,8 +322,9 @@ def _depth_tie_flags(used, au, T_before, dep):
     ok = used & (prev >= 0)
     pi = prev.clamp(min=0)
     close = (dep[None, :] - dep[pi]).abs() <= dep[None, :] * AMB_DEPTH_REL
-    pair_w = au * au.gather(1, pi) * T_before.gather(1, pi)
-    return (ok & close & (pair_w > AMB_WEIGHT)).any(1)
+    dc = (rgb[None, :, :] - rgb[pi]).abs().amax(-1)
+    swap = au * au.gather(1, pi) * T_before.gather(1, pi) * dc
+    return (ok & close & (swap > AMB_WEIGHT)).any(1)
 
 
 def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
@@ -396,7 +399,7 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
                 col = w @ rgb.detach() + tf[:, None] * bg_t[None, :]
                 T_final[s0:s0 + c] = tf
                 n_contrib[s0:s0 + c] = used.sum(1)
-                amb_rows = amb_pix | _depth_tie_flags(used, au, T_before, dep)
+                amb_rows = amb_pix | _depth_tie_flags(used, au, T_before, dep, rgb.detach())
                 ambiguous[s0:s0 + c] = amb_rows
                 colours.append(col)
             continue
@@ -406,10 +409,8 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
             with torch.no_grad():
                 flag = bool(amb_pix[row])
                 if sel.numel() > 1:
-                    dd = dep[sel]
-                    close = (dd[1:] - dd[:-1]).abs() <= dd[1:] * AMB_DEPTH_REL
-                    pair_w = au[row, sel[1:]] * au[row, sel[:-1]] * T_before[row, sel[:-1]]
-                    flag |= bool((close & (pair_w > AMB_WEIGHT)).any())
+                    flag |= bool(_depth_tie_flags(used[row:row + 1], au[row:row + 1],
+                                                  T_before[row:row + 1], dep, rgb.detach())[0])
                 ambiguous[p] = flag
                 n_contrib[p] = sel.numel()
             # the blending equation on the contributing Gaussians, differentiably

@@ -1,0 +1,364 @@
+"""MI355X-native 4D-rotor Gaussian splatting renderer (forward + backward).
+
+Thin ctypes binding of the HIP library libr4d.so (C ABI in include/r4d.h).
+It only marshals arguments: every step of the render and of its derivative
+runs in the library's HIP kernels.  PyTorch supplies device memory and the
+current HIP stream.  If the library has not been built this module raises
+ImportError; there is no fallback implementation.
+
+    import paper_2402_03307_amd as r4d
+    images = r4d.render(params, views, settings)     # list of [3, H, W] tensors
+    loss = sum(...); loss.backward()                 # gradients via r4d_render_backward
+
+params: dict of CUDA tensors (float32, or float64 for the test-only path):
+    means [4, n], log_scales [4, n], rotors [8, n], opacity [n], sh [3k, n],
+    plus "sh_degree" (int).
+views: list of dicts with width, height, fx, fy, cx, cy, world_to_cam (3x4),
+    t and bg (3 floats).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libr4d.so")
+
+__all__ = ["render", "Renderer", "R4DError", "default_settings", "LIB_PATH",
+           "BUF_RECORDS", "BUF_RECT", "BUF_DEPTHKEY", "BUF_VALUES", "BUF_RANGES",
+           "BUF_TFINAL", "BUF_NCONTRIB", "EXPORTED_SYMBOLS"]
+
+(BUF_RECORDS, BUF_RECT, BUF_DEPTHKEY, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB,
+ BUF_NEVAL) = range(8)
+
+EXPORTED_SYMBOLS = (
+    "r4d_default_settings", "r4d_create", "r4d_destroy", "r4d_render_forward",
+    "r4d_render_backward", "r4d_render_forward_f64", "r4d_render_backward_f64",
+    "r4d_saved_release", "r4d_l1_loss_grad", "r4d_saved_stats", "r4d_saved_copy",
+    "r4d_status_string", "r4d_last_error", "r4d_set_timing", "r4d_get_timings",
+    "r4d_stage_name",
+)
+NUM_STAGES = 9
+
+
+class R4DError(RuntimeError):
+    pass
+
+
+c_i32, c_f32, c_vp = ctypes.c_int32, ctypes.c_float, ctypes.c_void_p
+
+
+class _Gaussians(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("sh_degree", c_i32), ("means", c_vp), ("log_scales", c_vp),
+                ("rotors", c_vp), ("opacity", c_vp), ("sh", c_vp)]
+
+
+class _View(ctypes.Structure):
+    _fields_ = [("width", c_i32), ("height", c_i32), ("fx", c_f32), ("fy", c_f32),
+                ("cx", c_f32), ("cy", c_f32), ("world_to_cam", c_f32 * 12), ("t", c_f32),
+                ("bg", c_f32 * 3)]
+
+
+class _Settings(ctypes.Structure):
+    _fields_ = [("tile_size", c_i32), ("near_plane", c_f32), ("time_cull", c_f32),
+                ("extent_sigma", c_f32), ("alpha_min", c_f32), ("alpha_max", c_f32),
+                ("T_min", c_f32), ("dilation", c_f32), ("guard_band", c_f32), ("flags", c_i32)]
+
+
+class _Grads(ctypes.Structure):
+    _fields_ = [("means", c_vp), ("log_scales", c_vp), ("rotors", c_vp), ("opacity", c_vp),
+                ("sh", c_vp)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2402_03307_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.r4d_default_settings.argtypes = [P(_Settings)]
+    lib.r4d_default_settings.restype = None
+    lib.r4d_create.argtypes = [P(c_vp), ctypes.c_int]
+    lib.r4d_create.restype = ctypes.c_int
+    lib.r4d_destroy.argtypes = [c_vp]
+    lib.r4d_destroy.restype = None
+    fwd_args = [c_vp, P(_Gaussians), P(_View), ctypes.c_int, P(_Settings), c_vp, P(c_vp), c_vp]
+    bwd_args = [c_vp, P(_Gaussians), P(_View), ctypes.c_int, P(_Settings), c_vp, c_vp, P(_Grads),
+                c_vp]
+    for name, args in (("r4d_render_forward", fwd_args), ("r4d_render_forward_f64", fwd_args),
+                       ("r4d_render_backward", bwd_args), ("r4d_render_backward_f64", bwd_args)):
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.r4d_saved_release.argtypes = [c_vp]
+    lib.r4d_saved_release.restype = None
+    lib.r4d_l1_loss_grad.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]
+    lib.r4d_l1_loss_grad.restype = ctypes.c_int
+    lib.r4d_saved_stats.argtypes = [c_vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_int64),
+                                    P(c_i32), P(c_i32)]
+    lib.r4d_saved_stats.restype = ctypes.c_int
+    lib.r4d_saved_copy.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]
+    lib.r4d_saved_copy.restype = ctypes.c_int
+    lib.r4d_status_string.argtypes = [ctypes.c_int]
+    lib.r4d_status_string.restype = ctypes.c_char_p
+    lib.r4d_last_error.argtypes = [c_vp]
+    lib.r4d_last_error.restype = ctypes.c_char_p
+    lib.r4d_set_timing.argtypes = [c_vp, ctypes.c_int]
+    lib.r4d_set_timing.restype = ctypes.c_int
+    lib.r4d_get_timings.argtypes = [c_vp, P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int]
+    lib.r4d_get_timings.restype = ctypes.c_int
+    lib.r4d_stage_name.argtypes = [ctypes.c_int]
+    lib.r4d_stage_name.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def library():
+    return _lib
+
+
+def default_settings() -> dict:
+    s = _Settings()
+    _lib.r4d_default_settings(ctypes.byref(s))
+    return {name: getattr(s, name) for name, _ in _Settings._fields_}
+
+
+def _settings_struct(settings: dict | None) -> _Settings:
+    s = _Settings()
+    _lib.r4d_default_settings(ctypes.byref(s))
+    for k, v in (settings or {}).items():
+        if hasattr(s, k) and k != "flags":
+            setattr(s, k, type(getattr(s, k))(v))
+    return s
+
+
+def _views_array(views):
+    arr = (_View * len(views))()
+    for i, v in enumerate(views):
+        arr[i].width = int(v["width"])
+        arr[i].height = int(v["height"])
+        arr[i].fx, arr[i].fy = float(v["fx"]), float(v["fy"])
+        arr[i].cx, arr[i].cy = float(v["cx"]), float(v["cy"])
+        w2c = np.asarray(v["world_to_cam"], dtype=np.float32).reshape(12)
+        for j in range(12):
+            arr[i].world_to_cam[j] = float(w2c[j])
+        arr[i].t = float(v["t"])
+        bg = v.get("bg", (0.0, 0.0, 0.0))
+        for j in range(3):
+            arr[i].bg[j] = float(bg[j])
+    return arr
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+_PARAM_KEYS = ("means", "log_scales", "rotors", "opacity", "sh")
+
+
+def _check_params(p: dict):
+    deg = int(p["sh_degree"])
+    n = p["opacity"].shape[-1]
+    k = (deg + 1) ** 2
+    shapes = {"means": (4, n), "log_scales": (4, n), "rotors": (8, n), "opacity": (n,),
+              "sh": (3 * k, n)}
+    dtype = p["means"].dtype
+    for key, shp in shapes.items():
+        t = p[key]
+        if tuple(t.shape) != shp:
+            raise ValueError(f"{key}: expected shape {shp}, got {tuple(t.shape)}")
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype:
+            raise ValueError(f"{key}: must be a contiguous CUDA tensor of one dtype")
+    if dtype not in (torch.float32, torch.float64):
+        raise ValueError("parameters must be float32 or float64")
+    return n, deg, dtype
+
+
+class SavedState:
+    """Opaque per-forward state kept for the backward pass."""
+
+    def __init__(self, renderer: "Renderer", handle: ctypes.c_void_p, views, dtype):
+        self.renderer = renderer
+        self.handle = handle
+        self.views = views
+        self.dtype = dtype
+
+    def release(self):
+        if self.handle is not None and self.handle.value:
+            _lib.r4d_saved_release(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def stats(self, view: int = 0) -> dict:
+        nv, nd = ctypes.c_int64(), ctypes.c_int64()
+        tx, ty = c_i32(), c_i32()
+        st = _lib.r4d_saved_stats(self.handle, view, ctypes.byref(nv), ctypes.byref(nd),
+                                  ctypes.byref(tx), ctypes.byref(ty))
+        self.renderer._check(st, "r4d_saved_stats")
+        return {"n_visible": nv.value, "n_dup": nd.value, "tiles_x": tx.value, "tiles_y": ty.value}
+
+    def copy(self, view: int, buffer: int, n_gaussians: int) -> torch.Tensor:
+        """Device copy of one saved buffer (see r4d_saved_copy)."""
+        v = self.views[view]
+        hw = int(v["width"]) * int(v["height"])
+        s = self.stats(view)
+        fdt = self.dtype
+        shapes = {BUF_RECORDS: ((n_gaussians, 12), fdt), BUF_RECT: ((n_gaussians, 4), torch.int16),
+                  BUF_DEPTHKEY: ((n_gaussians,), torch.int32),
+                  BUF_VALUES: ((s["n_dup"],), torch.int32),
+                  BUF_RANGES: ((s["tiles_x"] * s["tiles_y"], 2), torch.int32),
+                  BUF_TFINAL: ((hw,), fdt), BUF_NCONTRIB: ((hw,), torch.int32),
+                  BUF_NEVAL: ((hw,), torch.int32)}
+        shape, dt = shapes[buffer]
+        out = torch.empty(shape, dtype=dt, device=self.renderer.device)
+        st = _lib.r4d_saved_copy(self.handle, view, buffer, _ptr(out),
+                                 out.numel() * out.element_size(), _stream(self.renderer.device))
+        self.renderer._check(st, "r4d_saved_copy")
+        return out
+
+
+class Renderer:
+    """Owns one r4d context on one device."""
+
+    def __init__(self, device: int | torch.device = 0):
+        if isinstance(device, torch.device):
+            device = device.index or 0
+        self.device = torch.device("cuda", int(device))
+        h = ctypes.c_void_p()
+        st = _lib.r4d_create(ctypes.byref(h), int(device))
+        if st != 0:
+            raise R4DError(f"r4d_create failed: {_lib.r4d_status_string(st).decode()}")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            torch.cuda.synchronize(self.device)
+            _lib.r4d_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, status: int, what: str):
+        if status != 0:
+            msg = _lib.r4d_last_error(self.handle).decode()
+            raise R4DError(f"{what}: {_lib.r4d_status_string(status).decode()}: {msg}")
+
+    def forward(self, params: dict, views, settings: dict | None = None, save: bool = True):
+        n, deg, dtype = _check_params(params)
+        g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _PARAM_KEYS])
+        varr = _views_array(views)
+        st = _settings_struct(settings)
+        sizes = [3 * int(v["height"]) * int(v["width"]) for v in views]
+        flat = torch.empty(sum(sizes), dtype=dtype, device=self.device)
+        handle = ctypes.c_void_p()
+        fn = _lib.r4d_render_forward if dtype == torch.float32 else _lib.r4d_render_forward_f64
+        status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st), _ptr(flat),
+                    ctypes.byref(handle) if save else None, _stream(self.device))
+        self._check(status, "r4d_render_forward")
+        images, off = [], 0
+        for v, s in zip(views, sizes):
+            images.append(flat[off:off + s].view(3, int(v["height"]), int(v["width"])))
+            off += s
+        saved = SavedState(self, handle, views, dtype) if save else None
+        return images, saved
+
+    def backward(self, params: dict, views, settings: dict | None, saved: SavedState,
+                 grad_images) -> dict:
+        n, deg, dtype = _check_params(params)
+        g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _PARAM_KEYS])
+        varr = _views_array(views)
+        st = _settings_struct(settings)
+        dl = torch.cat([gi.reshape(-1).to(dtype) for gi in grad_images]).contiguous()
+        grads = {k: torch.empty_like(params[k]) for k in _PARAM_KEYS}
+        gs = _Grads(*[_ptr(grads[k]) for k in _PARAM_KEYS])
+        fn = _lib.r4d_render_backward if dtype == torch.float32 else _lib.r4d_render_backward_f64
+        status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st),
+                    saved.handle, _ptr(dl), ctypes.byref(gs), _stream(self.device))
+        self._check(status, "r4d_render_backward")
+        return grads
+
+    def set_timing(self, enable: bool = True):
+        self._check(_lib.r4d_set_timing(self.handle, int(bool(enable))), "r4d_set_timing")
+
+    def timings(self, reset: bool = True) -> dict:
+        """{stage name: (total ms, launches)} since the last reset."""
+        ms = (ctypes.c_double * NUM_STAGES)()
+        cnt = (ctypes.c_int64 * NUM_STAGES)()
+        self._check(_lib.r4d_get_timings(self.handle, ms, cnt, int(bool(reset))),
+                    "r4d_get_timings")
+        return {_lib.r4d_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NUM_STAGES)}
+
+    def l1_loss_grad(self, image: torch.Tensor, target: torch.Tensor):
+        """(mean |image - target|, its gradient w.r.t. image)."""
+        image = image.contiguous()
+        target = target.contiguous()
+        grad = torch.empty_like(image)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        status = _lib.r4d_l1_loss_grad(self.handle, _ptr(image), _ptr(target), image.numel(),
+                                       _ptr(grad), _ptr(loss), _stream(self.device))
+        self._check(status, "r4d_l1_loss_grad")
+        return loss[0], grad
+
+
+_default_renderers: dict = {}
+
+
+def _renderer_for(device: torch.device) -> Renderer:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    r = _default_renderers.get(idx)
+    if r is None:
+        r = Renderer(idx)
+        _default_renderers[idx] = r
+    return r
+
+
+class _Render4D(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer, views, settings, sh_degree, means, log_scales, rotors, opacity, sh):
+        params = {"means": means, "log_scales": log_scales, "rotors": rotors, "opacity": opacity,
+                  "sh": sh, "sh_degree": sh_degree}
+        images, saved = renderer.forward(params, views, settings, save=True)
+        ctx.renderer, ctx.views, ctx.settings, ctx.saved = renderer, views, settings, saved
+        ctx.save_for_backward(means, log_scales, rotors, opacity, sh)
+        ctx.sh_degree = sh_degree
+        return tuple(images)
+
+    @staticmethod
+    def backward(ctx, *grad_images):
+        means, log_scales, rotors, opacity, sh = ctx.saved_tensors
+        params = {"means": means, "log_scales": log_scales, "rotors": rotors, "opacity": opacity,
+                  "sh": sh, "sh_degree": ctx.sh_degree}
+        gi = [g if g is not None else torch.zeros(3, int(v["height"]), int(v["width"]),
+                                                  dtype=means.dtype, device=means.device)
+              for g, v in zip(grad_images, ctx.views)]
+        grads = ctx.renderer.backward(params, ctx.views, ctx.settings, ctx.saved, gi)
+        ctx.saved.release()
+        return (None, None, None, None, grads["means"], grads["log_scales"], grads["rotors"],
+                grads["opacity"], grads["sh"])
+
+
+def render(params: dict, views, settings: dict | None = None, renderer: Renderer | None = None):
+    """Render `views` of the Gaussian set `params`; differentiable w.r.t. the
+    five parameter tensors.  Returns a list of [3, H, W] tensors."""
+    dev = params["means"].device
+    renderer = renderer or _renderer_for(dev)
+    return list(_Render4D.apply(renderer, list(views), settings, int(params["sh_degree"]),
+                                params["means"], params["log_scales"], params["rotors"],
+                                params["opacity"], params["sh"]))

@@ -1,0 +1,206 @@
+// Per-Gaussian preprocess kernels: one thread per Gaussian, SoA loads that are
+// coalesced across a wavefront, SH coefficients read only for Gaussians that
+// survive the time / near-plane culls.
+//
+// Forward writes the projected record consumed by the rasteriser, the tile
+// rectangle, the tile count and the depth sort key.  Backward recomputes the
+// forward intermediates from the parameters (nothing per Gaussian is stored
+// between the passes except the 9 screen-space gradients) and chains them
+// back to the parameters.
+#include <hip/hip_runtime.h>
+
+#include "r4d_internal.hpp"
+
+namespace r4d {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Conservative tile rectangle of a projected Gaussian.  A pixel centre c can
+// receive the Gaussian only if q(c) <= Q with Q = min(extent^2, 2 ln(o / alpha_min))
+// (beyond that either the extent test or the alpha_min test skips it), so the
+// bounding box of the ellipse q <= Q of the stored conic, widened by one pixel,
+// holds every pixel the rasteriser can blend it into.  Evaluated in double from
+// the stored conic so that the box is that of the ellipse the rasteriser tests.
+template <typename T>
+__device__ __forceinline__ bool tile_rect(const Rec<T>& rec, const ViewDev& v,
+                                          const SettingsDev& st, Rect16& out) {
+  const double o = double(rec.o);
+  if (!(o >= double(st.alpha_min))) return false;
+  double Q = 2.0 * (log(o) - double(st.log_alpha_min));
+  Q = Q < double(st.ext2) ? Q : double(st.ext2);
+  const double a = double(rec.ca), b = double(rec.cb), c = double(rec.cc);
+  const double det = a * c - b * b;
+  if (!(det > 0.0) || !(Q >= 0.0)) return false;
+  const double hwx = sqrt(Q * c / det) + 1.0;
+  const double hwy = sqrt(Q * a / det) + 1.0;
+  const double mx = double(rec.mx), my = double(rec.my);
+  const double ilo = ceil(mx - hwx - 0.5), ihi = floor(mx + hwx - 0.5);
+  const double jlo = ceil(my - hwy - 0.5), jhi = floor(my + hwy - 0.5);
+  const double W1 = double(v.W - 1), H1 = double(v.H - 1);
+  const double x0 = ilo > 0.0 ? ilo : 0.0, x1 = ihi < W1 ? ihi : W1;
+  const double y0 = jlo > 0.0 ? jlo : 0.0, y1 = jhi < H1 ? jhi : H1;
+  if (!(x0 <= x1) || !(y0 <= y1)) return false;
+  const int ts = v.tile_size;
+  out.x0 = uint16_t(int(x0) / ts);
+  out.x1 = uint16_t(int(x1) / ts + 1);
+  out.y0 = uint16_t(int(y0) / ts);
+  out.y1 = uint16_t(int(y1) / ts + 1);
+  return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
+    GaussPtrs<T> g, ViewDev v, SettingsDev st, Rec<T>* __restrict__ recs,
+    Rect16* __restrict__ rects, uint32_t* __restrict__ tiles_touched,
+    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ values_iota,
+    uint32_t* __restrict__ n_visible) {
+  const int n = g.n;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  bool vis = false;
+  if (i < n) {
+    T mu[4], ls[4], rot[8];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      mu[c] = g.means[c * (long)n + i];
+      ls[c] = g.log_scales[c * (long)n + i];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) rot[c] = g.rotors[c * (long)n + i];
+    const T op = g.opacity[i];
+    Fwd<T> f;
+    gaussian_fwd<T>(mu, ls, rot, op, g.sh + i, (long)n, g.deg, v, st, f);
+    Rect16 rc = {0, 0, 0, 0};
+    uint32_t cnt = 0;
+    uint32_t key = 0xffffffffu;
+    if (f.valid) {
+      Rec<T> rec;
+      rec.mx = f.mean2[0];
+      rec.my = f.mean2[1];
+      rec.ca = f.conic[0];
+      rec.cb = f.conic[1];
+      rec.cc = f.conic[2];
+      rec.o = f.o_t;
+      rec.depth = f.p[2];
+      rec.pad0 = T(0);
+      rec.r = f.rgb[0];
+      rec.g = f.rgb[1];
+      rec.b = f.rgb[2];
+      rec.pad1 = T(0);
+      if (tile_rect(rec, v, st, rc)) {
+        cnt = uint32_t(rc.x1 - rc.x0) * uint32_t(rc.y1 - rc.y0);
+        key = __float_as_uint(float(f.p[2]));
+        recs[i] = rec;
+        vis = true;
+      } else {
+        rc = {0, 0, 0, 0};
+      }
+    }
+    rects[i] = rc;
+    tiles_touched[i] = cnt;
+    depth_keys[i] = key;
+    values_iota[i] = uint32_t(i);
+  }
+  const unsigned long long m = __ballot(vis);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_visible, uint32_t(__popcll(m)));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g, ViewDev v,
+                                                                SettingsDev st,
+                                                                const T* __restrict__ grad2d,
+                                                                GradPtrs<T> out, bool accumulate) {
+  const int n = g.n;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int k = (g.deg + 1) * (g.deg + 1);
+  T g2[9];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    g2[c] = grad2d[c * (long)n + i];
+    any |= g2[c] != T(0);
+  }
+  T gmu[4] = {0, 0, 0, 0}, gls[4] = {0, 0, 0, 0}, grot[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gop = 0;
+  T gsh[48];
+  for (int j = 0; j < 3 * k; ++j) gsh[j] = T(0);
+  if (any) {
+    T mu[4], ls[4], rot[8], shl[48];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      mu[c] = g.means[c * (long)n + i];
+      ls[c] = g.log_scales[c * (long)n + i];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) rot[c] = g.rotors[c * (long)n + i];
+    for (int j = 0; j < 3 * k; ++j) shl[j] = g.sh[j * (long)n + i];
+    const T op = g.opacity[i];
+    Fwd<T> f;
+    gaussian_fwd<T>(mu, ls, rot, op, shl, 1, g.deg, v, st, f);
+    gaussian_bwd<T>(f, shl, 1, g.deg, v, g2, gmu, gls, grot, gop, gsh);
+  }
+  if (accumulate) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      out.means[c * (long)n + i] += gmu[c];
+      out.log_scales[c * (long)n + i] += gls[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) out.rotors[c * (long)n + i] += grot[c];
+    out.opacity[i] += gop;
+    for (int j = 0; j < 3 * k; ++j) out.sh[j * (long)n + i] += gsh[j];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      out.means[c * (long)n + i] = gmu[c];
+      out.log_scales[c * (long)n + i] = gls[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) out.rotors[c * (long)n + i] = grot[c];
+    out.opacity[i] = gop;
+    for (int j = 0; j < 3 * k; ++j) out.sh[j * (long)n + i] = gsh[j];
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
+                                 Rec<T>* recs, Rect16* rects, uint32_t* tiles_touched,
+                                 uint32_t* depth_keys, uint32_t* values_iota, uint32_t* n_visible,
+                                 hipStream_t stream) {
+  if (g.n <= 0) return hipSuccess;
+  const int grid = (g.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(preprocess_fwd_kernel<T>, dim3(grid), dim3(kBlock), 0, stream, g, v, st,
+                     recs, rects, tiles_touched, depth_keys, values_iota, n_visible);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
+                                 const T* grad2d, const GradPtrs<T>& out, bool accumulate,
+                                 hipStream_t stream) {
+  if (g.n <= 0) return hipSuccess;
+  const int grid = (g.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(preprocess_bwd_kernel<T>, dim3(grid), dim3(kBlock), 0, stream, g, v, st,
+                     grad2d, out, accumulate);
+  return hipGetLastError();
+}
+
+template hipError_t launch_preprocess_fwd<float>(const GaussPtrs<float>&, const ViewDev&,
+                                                 const SettingsDev&, Rec<float>*, Rect16*,
+                                                 uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                                 hipStream_t);
+template hipError_t launch_preprocess_fwd<double>(const GaussPtrs<double>&, const ViewDev&,
+                                                  const SettingsDev&, Rec<double>*, Rect16*,
+                                                  uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                                  hipStream_t);
+template hipError_t launch_preprocess_bwd<float>(const GaussPtrs<float>&, const ViewDev&,
+                                                 const SettingsDev&, const float*,
+                                                 const GradPtrs<float>&, bool, hipStream_t);
+template hipError_t launch_preprocess_bwd<double>(const GaussPtrs<double>&, const ViewDev&,
+                                                  const SettingsDev&, const double*,
+                                                  const GradPtrs<double>&, bool, hipStream_t);
+
+}  // namespace r4d
