@@ -40,17 +40,26 @@ template <> __device__ __forceinline__ double gauss_falloff<double>(double q) {
 
 // The one place where a (pixel, Gaussian) pair is evaluated; forward and backward
 // call it with identical operands so that they take identical decisions.
+// G = exp(-q/2), a_raw = o G, alpha = min(alpha_max, a_raw).  Evaluated without
+// branches: the result says whether the pair passes the extent and alpha tests.
 template <typename T>
 __device__ __forceinline__ bool eval_pair(const Rec<T>& r, T px, T py, T ext2, T amin, T amax,
-                                          T& dx, T& dy, T& a_raw, T& alpha) {
+                                          T& dx, T& dy, T& G, T& a_raw, T& alpha) {
   dx = r.mx - px;
   dy = r.my - py;
   const T q = tfma(r.ca * dx, dx, tfma(T(2) * r.cb * dx, dy, r.cc * dy * dy));
-  if (!(q <= ext2)) return false;
-  a_raw = r.o * gauss_falloff(q);
+  G = gauss_falloff(q);
+  a_raw = r.o * G;
   alpha = a_raw < amax ? a_raw : amax;
-  return alpha >= amin;
+  return (q <= ext2) & (alpha >= amin);
 }
+
+// 1/x: the hardware reciprocal in float (about 1 ulp), exact division in double.
+template <typename T> __device__ __forceinline__ T fast_rcp(T x);
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
 
 template <int TS>
 struct TileCfg {
@@ -82,26 +91,28 @@ __global__ __launch_bounds__(TS* TS) void raster_fwd_kernel(
     const uint32_t i = base + threadIdx.x;
     if (threadIdx.x < NB && i < rg.y) s_rec[threadIdx.x] = recs[values[i]];
     __syncthreads();
-    if (!done) {
-      const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
-      int j = 0;
-      for (; j < nb; ++j) {
+    // every lane walks the batch (no divergent branches); a lane that is done
+    // keeps its state through selects
+    const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
+    const uint32_t jbase = base - rg.x;
+    if (__ballot(!done)) {
+      for (int j = 0; j < nb; ++j) {
         const Rec<T> r = s_rec[j];
-        T dx, dy, a_raw, alpha;
-        if (!eval_pair(r, px, py, ext2, amin, amax, dx, dy, a_raw, alpha)) continue;
+        T dx, dy, G, a_raw, alpha;
+        const bool pass = eval_pair(r, px, py, ext2, amin, amax, dx, dy, G, a_raw, alpha);
         const T Tn = Tr * (T(1) - alpha);
-        if (Tn < tmin) {
-          done = true;
-          break;
-        }
-        const T w = alpha * Tr;
+        evals += done ? 0u : 1u;
+        const bool live = pass & !done;
+        const bool stop = live & (Tn < tmin);
+        const bool blend = live & !stop;
+        done |= stop;
+        const T w = blend ? alpha * Tr : T(0);
         c0 = tfma(r.r, w, c0);
         c1 = tfma(r.g, w, c1);
         c2 = tfma(r.b, w, c2);
-        Tr = Tn;
-        last = base - rg.x + uint32_t(j) + 1u;
+        Tr = blend ? Tn : Tr;
+        last = blend ? jbase + uint32_t(j) + 1u : last;
       }
-      evals += uint32_t(j < nb ? j + 1 : nb);
     }
   }
   if (inside) {
@@ -121,6 +132,47 @@ __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;
+}
+
+// Sum over the 64 lanes of a wavefront with DPP lane moves (no LDS traffic);
+// the total is valid in lane 63.  Steps: pairs (quad_perm 1,0,3,2), quads
+// (quad_perm 2,3,0,1), half rows (row_half_mirror), rows of 16 (row_mirror),
+// then row 15 -> rows 1, 3 (row_bcast:15) and row 31 -> rows 2, 3 (row_bcast:31).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false);
+  return x + __int_as_float(moved);
+}
+__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+  x = dpp_add<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
+  x = dpp_add<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
+  x = dpp_add<0x141, 0xf>(x);  // row_half_mirror
+  x = dpp_add<0x140, 0xf>(x);  // row_mirror
+  x = dpp_add<0x142, 0xa>(x);  // row_bcast:15
+  x = dpp_add<0x143, 0xc>(x);  // row_bcast:31
+  return x;
+}
+__device__ __forceinline__ double wave_sum_to_lane63(double x) { return wave_sum(x); }
+
+// Nine independent reductions advanced step by step, so that the DPP moves of
+// one value fill the hazard slots of the others.
+__device__ __forceinline__ void wave_sum9_to_lane63(float (&v)[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0xb1, 0xf>(v[i]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x4e, 0xf>(v[i]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x141, 0xf>(v[i]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x140, 0xf>(v[i]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x142, 0xa>(v[i]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x143, 0xc>(v[i]);
+}
+__device__ __forceinline__ void wave_sum9_to_lane63(double (&v)[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = wave_sum(v[i]);
 }
 
 template <typename T> __device__ __forceinline__ void atomic_add_nr(T* p, T v);
@@ -185,66 +237,41 @@ __global__ __launch_bounds__(TS* TS) void raster_bwd_kernel(
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
       const Rec<T> r = s_rec[j];
-      T dx = 0, dy = 0, a_raw = 0, alpha = 0;
-      bool use = inside && (bstart + uint32_t(j) < ncon) &&
-                 eval_pair(r, px, py, ext2, amin, amax, dx, dy, a_raw, alpha);
-      T gm_x = 0, gm_y = 0, gca = 0, gcb = 0, gcc = 0, go = 0, gr = 0, gg = 0, gb = 0;
-      if (use) {
-        const T om = T(1) - alpha;
-        const T Ti = Tcur / om;
-        const T w = alpha * Ti;
-        gr = w * g0;
-        gg = w * g1;
-        gb = w * g2;
-        const T inv_om = T(1) / om;
-        const T dL_da = g0 * (Ti * r.r - acc0 * inv_om) + g1 * (Ti * r.g - acc1 * inv_om) +
-                        g2 * (Ti * r.b - acc2 * inv_om);
-        acc0 = tfma(r.r, w, acc0);
-        acc1 = tfma(r.g, w, acc1);
-        acc2 = tfma(r.b, w, acc2);
-        Tcur = Ti;
-        if (a_raw < amax) {
-          // a = o exp(-q/2): da/do = exp(-q/2), da/dq = -a/2
-          go = dL_da * (a_raw / r.o);
-          const T gq = T(-0.5) * dL_da * a_raw;
-          gca = gq * dx * dx;
-          gcb = gq * T(2) * dx * dy;
-          gcc = gq * dy * dy;
-          gm_x = gq * T(2) * (r.ca * dx + r.cb * dy);
-          gm_y = gq * T(2) * (r.cb * dx + r.cc * dy);
-        }
-      }
+      T dx, dy, G, a_raw, alpha;
+      const bool pass = eval_pair(r, px, py, ext2, amin, amax, dx, dy, G, a_raw, alpha);
+      const bool use = pass & (bstart + uint32_t(j) < ncon);
+      // everything below is computed by every lane and kept only where `use`
+      const T inv_om = fast_rcp(T(1) - alpha);
+      const T Ti = Tcur * inv_om;            // transmittance in front of this Gaussian
+      const T w = use ? alpha * Ti : T(0);
+      const T gr = w * g0, gg = w * g1, gb = w * g2;
+      // dC/da = T c - (colour behind) / (1 - a)
+      const T gc = tfma(g0, r.r, tfma(g1, r.g, g2 * r.b));
+      const T gacc = tfma(g0, acc0, tfma(g1, acc1, g2 * acc2));
+      // a = o exp(-q/2): da/do = exp(-q/2), da/dq = -a/2; no gradient through the clamp
+      const T dL_da = (use & (a_raw < amax)) ? Ti * gc - gacc * inv_om : T(0);
+      acc0 = tfma(r.r, w, acc0);
+      acc1 = tfma(r.g, w, acc1);
+      acc2 = tfma(r.b, w, acc2);
+      Tcur = use ? Ti : Tcur;
+      const T go = dL_da * G;
+      const T gq = T(-0.5) * dL_da * a_raw;
+      const T gqx = gq * dx, gqy = gq * dy;
+      const T gca = gqx * dx;
+      const T gcb = T(2) * gqx * dy;
+      const T gcc = gqy * dy;
+      const T gm_x = T(2) * (r.ca * gqx + r.cb * gqy);
+      const T gm_y = T(2) * (r.cb * gqx + r.cc * gqy);
       if (__ballot(use)) {
-        gm_x = wave_sum(gm_x);
-        gm_y = wave_sum(gm_y);
-        gca = wave_sum(gca);
-        gcb = wave_sum(gcb);
-        gcc = wave_sum(gcc);
-        go = wave_sum(go);
-        gr = wave_sum(gr);
-        gg = wave_sum(gg);
-        gb = wave_sum(gb);
-        if (lane == 0) {
-          if (NT == 64) {
-            s_grad[0][j] += gm_x;
-            s_grad[1][j] += gm_y;
-            s_grad[2][j] += gca;
-            s_grad[3][j] += gcb;
-            s_grad[4][j] += gcc;
-            s_grad[5][j] += go;
-            s_grad[6][j] += gr;
-            s_grad[7][j] += gg;
-            s_grad[8][j] += gb;
-          } else {
-            atomicAdd(&s_grad[0][j], gm_x);
-            atomicAdd(&s_grad[1][j], gm_y);
-            atomicAdd(&s_grad[2][j], gca);
-            atomicAdd(&s_grad[3][j], gcb);
-            atomicAdd(&s_grad[4][j], gcc);
-            atomicAdd(&s_grad[5][j], go);
-            atomicAdd(&s_grad[6][j], gr);
-            atomicAdd(&s_grad[7][j], gg);
-            atomicAdd(&s_grad[8][j], gb);
+        T v9[9] = {gm_x, gm_y, gca, gcb, gcc, go, gr, gg, gb};
+        wave_sum9_to_lane63(v9);
+        if (lane == 63) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            if (NT == 64)
+              s_grad[c][j] += v9[c];
+            else
+              atomicAdd(&s_grad[c][j], v9[c]);
           }
         }
       }
@@ -350,8 +377,9 @@ hipError_t launch_l1_grad(const float* image, const float* target, int64_t count
     hipError_t e = hipMemsetAsync(loss, 0, sizeof(float), stream);
     if (e != hipSuccess) return e;
   }
+  // few fat blocks: the loss is summed with one atomic per block
   int64_t blocks = (count + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(l1_grad_kernel, dim3(blocks), dim3(256), 0, stream, image, target, count,
                      1.0f / float(count), grad, loss);
   return hipGetLastError();
