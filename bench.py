@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile-size", type=int, default=16)
+    ap.add_argument("--fwd-ppt", type=int, default=0,
+                    help="forward rasteriser pixels per lane (0 = library default)")
+    ap.add_argument("--bwd-ppt", type=int, default=0,
+                    help="backward rasteriser pixels per lane (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, nargs=2, default=(16, 64),
                     help="two oracle pixel-sample sizes used to fit fixed + per-pixel cost")
@@ -89,7 +93,8 @@ def main():
 
     dev = torch.device("cuda:0")
     g, views, st = W.scene_500k_step()
-    st = dict(st, tile_size=args.tile_size)
+    st = dict(st, tile_size=args.tile_size, fwd_pixels_per_thread=args.fwd_ppt,
+              bwd_pixels_per_thread=args.bwd_ppt)
     view = views[0]
     H, Wd = int(view["height"]), int(view["width"])
     n = int(g["opacity"].shape[0])
@@ -204,6 +209,8 @@ def main():
         "config": {"workload": "500k 4D Gaussians, SH degree 3, one 1352x1014 render at t=0.5; "
                                "step = forward + L1 grad + backward",
                    "n_gaussians": n, "width": Wd, "height": H, "tile_size": args.tile_size,
+                   "fwd_pixels_per_thread": args.fwd_ppt or "auto",
+                   "bwd_pixels_per_thread": args.bwd_ppt or "auto",
                    "plain_or_batched": "plain"},
         "fwd_frames_per_s": 1e3 / fwd_ms,
         "fwd_ms": fwd_ms,

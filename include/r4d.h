@@ -89,7 +89,11 @@ typedef struct {
  *   dilation      added to the diagonal of every 2D covariance (0.3)
  *   guard_band    x/z and y/z entering the projection Jacobian are clamped to
  *                 guard_band * half image size / focal (1.3)
- *   flags         reserved, must be 0 */
+ *   fwd_pixels_per_thread, bwd_pixels_per_thread
+ *                 pixels each lane of the forward / backward rasteriser handles:
+ *                 0 = automatic (forward 1; backward 1 for tile 8, 4 for tiles 16
+ *                 and 32); otherwise 1 for tile 8 and 1, 2 or 4 for tiles 16 and
+ *                 32.  Neither changes the image. */
 typedef struct {
   int32_t tile_size;
   float near_plane;
@@ -100,7 +104,8 @@ typedef struct {
   float T_min;
   float dilation;
   float guard_band;
-  int32_t flags;
+  int32_t fwd_pixels_per_thread;
+  int32_t bwd_pixels_per_thread;
 } r4d_settings;
 
 /* Gradients, same layouts as r4d_gaussians (means [4][n], log_scales [4][n],
@@ -183,7 +188,9 @@ r4d_status r4d_render_backward_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g,
                                    const r4d_settings *settings, const r4d_saved *saved,
                                    const double *dL_dimages, r4d_grads_f64 *out, void *stream);
 
-/* Returns the saved arena to its context's cache.  NULL is ignored. */
+/* Returns the saved arena to its context's cache.  NULL is ignored.  A saved
+ * handle may outlive its context: r4d_destroy frees its device memory and a
+ * later release only frees the handle. */
 void r4d_saved_release(r4d_saved *saved);
 
 /* Gradient of the mean absolute error L = sum |image - target| / count

@@ -18,8 +18,10 @@ views: list of dicts with width, height, fx, fy, cx, cy, world_to_cam (3x4),
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -65,7 +67,8 @@ class _View(ctypes.Structure):
 class _Settings(ctypes.Structure):
     _fields_ = [("tile_size", c_i32), ("near_plane", c_f32), ("time_cull", c_f32),
                 ("extent_sigma", c_f32), ("alpha_min", c_f32), ("alpha_max", c_f32),
-                ("T_min", c_f32), ("dilation", c_f32), ("guard_band", c_f32), ("flags", c_i32)]
+                ("T_min", c_f32), ("dilation", c_f32), ("guard_band", c_f32),
+                ("fwd_pixels_per_thread", c_i32), ("bwd_pixels_per_thread", c_i32)]
 
 
 class _Grads(ctypes.Structure):
@@ -131,7 +134,7 @@ def _settings_struct(settings: dict | None) -> _Settings:
     s = _Settings()
     _lib.r4d_default_settings(ctypes.byref(s))
     for k, v in (settings or {}).items():
-        if hasattr(s, k) and k != "flags":
+        if hasattr(s, k):
             setattr(s, k, type(getattr(s, k))(v))
     return s
 
@@ -182,6 +185,20 @@ def _check_params(p: dict):
     return n, deg, dtype
 
 
+# Live library objects, released in a safe order (saved states, then contexts)
+# at interpreter exit, before the HIP runtime goes away.
+_live_saved = weakref.WeakSet()
+_live_renderers = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    for s in list(_live_saved):
+        s.release()
+    for r in list(_live_renderers):
+        r.close(sync=False)
+
+
 class SavedState:
     """Opaque per-forward state kept for the backward pass."""
 
@@ -190,6 +207,7 @@ class SavedState:
         self.handle = handle
         self.views = views
         self.dtype = dtype
+        _live_saved.add(self)
 
     def release(self):
         if self.handle is not None and self.handle.value:
@@ -203,6 +221,8 @@ class SavedState:
             pass
 
     def stats(self, view: int = 0) -> dict:
+        if self.handle is None:
+            raise R4DError("saved state already released")
         nv, nd = ctypes.c_int64(), ctypes.c_int64()
         tx, ty = c_i32(), c_i32()
         st = _lib.r4d_saved_stats(self.handle, view, ctypes.byref(nv), ctypes.byref(nd),
@@ -242,10 +262,12 @@ class Renderer:
         if st != 0:
             raise R4DError(f"r4d_create failed: {_lib.r4d_status_string(st).decode()}")
         self.handle = h
+        _live_renderers.add(self)
 
-    def close(self):
+    def close(self, sync: bool = True):
         if getattr(self, "handle", None) is not None and self.handle.value:
-            torch.cuda.synchronize(self.device)
+            if sync:
+                torch.cuda.synchronize(self.device)
             _lib.r4d_destroy(self.handle)
         self.handle = None
 

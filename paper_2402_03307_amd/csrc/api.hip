@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -39,6 +40,7 @@ struct r4d_ctx {
   std::multimap<size_t, void*> free_blocks;  // size class -> block
   std::map<void*, size_t> block_size;        // every block ever allocated
   uint64_t* host_readback = nullptr;         // pinned, 2 words
+  std::set<r4d_saved*> live_saved;           // saved states not yet released
 };
 
 namespace {
@@ -149,9 +151,19 @@ struct Scratch {
   }
 };
 
+int fwd_ppt(const r4d_settings& s) {
+  return s.fwd_pixels_per_thread ? s.fwd_pixels_per_thread : raster_default_ppt(s.tile_size, false);
+}
+int bwd_ppt(const r4d_settings& s) {
+  return s.bwd_pixels_per_thread ? s.bwd_pixels_per_thread : raster_default_ppt(s.tile_size, true);
+}
+
 bool valid_settings(const r4d_settings* s) {
   return s && (s->tile_size == 8 || s->tile_size == 16 || s->tile_size == 32) &&
-         s->flags == 0 && s->near_plane >= 0.f && s->time_cull >= 0.f && s->extent_sigma > 0.f &&
+         s->fwd_pixels_per_thread >= 0 && s->bwd_pixels_per_thread >= 0 &&
+         raster_config_supported(s->tile_size, fwd_ppt(*s)) &&
+         raster_config_supported(s->tile_size, bwd_ppt(*s)) &&
+         s->near_plane >= 0.f && s->time_cull >= 0.f && s->extent_sigma > 0.f &&
          s->alpha_min > 0.f && s->alpha_max > s->alpha_min && s->alpha_max < 1.f &&
          s->T_min > 0.f && s->T_min < 1.f && s->dilation >= 0.f && s->guard_band > 0.f;
 }
@@ -282,6 +294,7 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
   if (saved_out) {
     saved = new r4d_saved();
     saved->ctx = ctx;
+    ctx->live_saved.insert(saved);
     saved->f64 = sizeof(T) == 8;
     saved->n = g.n;
     saved->deg = g.deg;
@@ -372,8 +385,9 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
     } else {
       R4D_HIP(hipMemsetAsync(ranges, 0, size_t(n_tiles) * sizeof(uint2), stream));
     }
-    R4D_TIMED(kRasterFwd, launch_raster_fwd<T>(recs, values, ranges, vd, st, images + img_off,
-                                              T_final, n_contrib, n_eval, stream));
+    R4D_TIMED(kRasterFwd, launch_raster_fwd<T>(recs, values, ranges, vd, st, fwd_ppt(*settings),
+                                              images + img_off, T_final, n_contrib, n_eval,
+                                              stream));
     if (saved) {
       ViewSaved& vs = saved->views[vi];
       vs.view = view;
@@ -437,7 +451,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
     R4D_HIP(hipMemsetAsync(grad2d, 0, 9 * n * sizeof(T), stream));
     if (vs.n_dup > 0)
       R4D_TIMED(kRasterBwd, launch_raster_bwd<T>(static_cast<const Rec<T>*>(vs.recs), vs.values,
-                                                vs.ranges, vd, st,
+                                                vs.ranges, vd, st, bwd_ppt(*settings),
                                                 static_cast<const T*>(vs.T_final), vs.n_contrib,
                                                 dL + img_off, grad2d, uint32_t(n), stream));
     R4D_TIMED(kPreprocessBwd, launch_preprocess_bwd<T>(g, vd, st, grad2d, out, vi > 0, stream));
@@ -470,7 +484,8 @@ void r4d_default_settings(r4d_settings* s) {
   s->T_min = 1e-4f;
   s->dilation = 0.3f;
   s->guard_band = 1.3f;
-  s->flags = 0;
+  s->fwd_pixels_per_thread = 0;
+  s->bwd_pixels_per_thread = 0;
 }
 
 r4d_status r4d_create(r4d_ctx** out, int device) {
@@ -497,6 +512,13 @@ void r4d_destroy(r4d_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  // saved states that outlive the context keep only their host struct
+  for (r4d_saved* sv : ctx->live_saved) {
+    sv->ctx = nullptr;
+    sv->blocks.clear();
+    sv->views.clear();
+  }
+  ctx->live_saved.clear();
   for (auto& kv : ctx->block_size) (void)hipFree(kv.first);
   for (auto& p : ctx->pending) ctx->event_pool.push_back({p.start, p.stop});
   for (auto& e : ctx->event_pool) {
@@ -548,7 +570,10 @@ r4d_status r4d_render_backward_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
 
 void r4d_saved_release(r4d_saved* saved) {
   if (!saved) return;
-  for (void* p : saved->blocks) ctx_free(saved->ctx, p);
+  if (saved->ctx) {  // null once the context has been destroyed
+    for (void* p : saved->blocks) ctx_free(saved->ctx, p);
+    saved->ctx->live_saved.erase(saved);
+  }
   delete saved;
 }
 
@@ -575,7 +600,8 @@ r4d_status r4d_saved_stats(const r4d_saved* saved, int view, int64_t* n_visible,
 
 r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* dst, size_t bytes,
                           void* stream) {
-  if (!saved || view < 0 || view >= int(saved->views.size()) || !dst) return R4D_ERR_INVALID_ARG;
+  if (!saved || !saved->ctx || view < 0 || view >= int(saved->views.size()) || !dst)
+    return R4D_ERR_INVALID_ARG;
   r4d_ctx* ctx = saved->ctx;
   const ViewSaved& v = saved->views[view];
   const size_t scal = saved->f64 ? 8 : 4;

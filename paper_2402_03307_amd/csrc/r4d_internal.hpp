@@ -77,15 +77,20 @@ hipError_t tile_ranges(const uint32_t* sorted_keys, uint32_t d, uint32_t n_tiles
                        hipStream_t stream);
 
 // ---- rasterisation
+// (tile size, pixels per lane) pairs the rasteriser is compiled for.
+bool raster_config_supported(int tile_size, int ppt);
+int raster_default_ppt(int tile_size, bool backward);
+
 // n_eval (nullable): per pixel, the number of list entries evaluated.
 template <typename T>
 hipError_t launch_raster_fwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                             const ViewDev& v, const SettingsDev& st, T* image, T* T_final,
-                             uint32_t* n_contrib, uint32_t* n_eval, hipStream_t stream);
+                             const ViewDev& v, const SettingsDev& st, int ppt, T* image,
+                             T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
+                             hipStream_t stream);
 
 template <typename T>
 hipError_t launch_raster_bwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                             const ViewDev& v, const SettingsDev& st, const T* T_final,
+                             const ViewDev& v, const SettingsDev& st, int ppt, const T* T_final,
                              const uint32_t* n_contrib, const T* dL_dimage, T* grad2d,
                              uint32_t n_gaussians, hipStream_t stream);
 

@@ -1,11 +1,11 @@
 // Tile rasteriser: front-to-back alpha compositing (paper Sec. 3.1, blending
 // equation) and its reverse-mode derivative.
 //
-// One workgroup per tile, one pixel per lane.  The tile's list of Gaussian
-// indices (sorted by depth) is walked in batches: every lane loads one projected
-// record into LDS, then every lane reads the whole batch back (a broadcast read)
-// and updates its pixel.  A workgroup stops as soon as every pixel of the tile
-// has reached the transmittance floor.
+// One workgroup per tile.  The tile's list of Gaussian indices (sorted by depth)
+// is walked in batches: every lane loads one projected record into LDS, then
+// every lane reads the whole batch back (a broadcast read) and updates its
+// pixels.  A workgroup stops as soon as every pixel of the tile has reached the
+// transmittance floor.
 //
 // Per (pixel, Gaussian): d = mean2d - (x + .5, y + .5), q = d^T conic d; skip if
 // q > extent^2; a = min(alpha_max, o exp(-q/2)); skip if a < alpha_min; stop if
@@ -61,72 +61,6 @@ template <> __device__ __forceinline__ float fast_rcp<float>(float x) {
 }
 template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
 
-template <int TS>
-struct TileCfg {
-  static constexpr int kThreads = TS * TS;
-  static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
-};
-
-template <typename T, int TS>
-__global__ __launch_bounds__(TS* TS) void raster_fwd_kernel(
-    const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
-    const uint2* __restrict__ ranges, ViewDev v, SettingsDev st, T* __restrict__ image,
-    T* __restrict__ T_final, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval) {
-  constexpr int NT = TileCfg<TS>::kThreads;
-  constexpr int NB = TileCfg<TS>::kBatch;
-  __shared__ Rec<T> s_rec[NB];
-  const int tile = blockIdx.x;
-  const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
-  const int x = tx * TS + int(threadIdx.x % TS);
-  const int y = ty * TS + int(threadIdx.x / TS);
-  const bool inside = x < v.W && y < v.H;
-  const T px = T(x) + T(0.5), py = T(y) + T(0.5);
-  const T ext2 = T(st.ext2), amin = T(st.alpha_min), amax = T(st.alpha_max), tmin = T(st.T_min);
-  const uint2 rg = ranges[tile];
-  T Tr = T(1), c0 = T(0), c1 = T(0), c2 = T(0);
-  uint32_t last = 0, evals = 0;
-  bool done = !inside;
-  for (uint32_t base = rg.x; base < rg.y; base += NB) {
-    if (__syncthreads_count(done) == NT) break;
-    const uint32_t i = base + threadIdx.x;
-    if (threadIdx.x < NB && i < rg.y) s_rec[threadIdx.x] = recs[values[i]];
-    __syncthreads();
-    // every lane walks the batch (no divergent branches); a lane that is done
-    // keeps its state through selects
-    const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
-    const uint32_t jbase = base - rg.x;
-    if (__ballot(!done)) {
-      for (int j = 0; j < nb; ++j) {
-        const Rec<T> r = s_rec[j];
-        T dx, dy, G, a_raw, alpha;
-        const bool pass = eval_pair(r, px, py, ext2, amin, amax, dx, dy, G, a_raw, alpha);
-        const T Tn = Tr * (T(1) - alpha);
-        evals += done ? 0u : 1u;
-        const bool live = pass & !done;
-        const bool stop = live & (Tn < tmin);
-        const bool blend = live & !stop;
-        done |= stop;
-        const T w = blend ? alpha * Tr : T(0);
-        c0 = tfma(r.r, w, c0);
-        c1 = tfma(r.g, w, c1);
-        c2 = tfma(r.b, w, c2);
-        Tr = blend ? Tn : Tr;
-        last = blend ? jbase + uint32_t(j) + 1u : last;
-      }
-    }
-  }
-  if (inside) {
-    const long hw = long(v.H) * v.W;
-    const long pix = long(y) * v.W + x;
-    image[pix] = tfma(Tr, T(v.bg[0]), c0);
-    image[hw + pix] = tfma(Tr, T(v.bg[1]), c1);
-    image[2 * hw + pix] = tfma(Tr, T(v.bg[2]), c2);
-    T_final[pix] = Tr;
-    n_contrib[pix] = last;
-    if (n_eval) n_eval[pix] = evals;
-  }
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll
@@ -143,16 +77,6 @@ __device__ __forceinline__ float dpp_add(float x) {
   const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false);
   return x + __int_as_float(moved);
 }
-__device__ __forceinline__ float wave_sum_to_lane63(float x) {
-  x = dpp_add<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
-  x = dpp_add<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
-  x = dpp_add<0x141, 0xf>(x);  // row_half_mirror
-  x = dpp_add<0x140, 0xf>(x);  // row_mirror
-  x = dpp_add<0x142, 0xa>(x);  // row_bcast:15
-  x = dpp_add<0x143, 0xc>(x);  // row_bcast:31
-  return x;
-}
-__device__ __forceinline__ double wave_sum_to_lane63(double x) { return wave_sum(x); }
 
 // Nine independent reductions advanced step by step, so that the DPP moves of
 // one value fill the hazard slots of the others.
@@ -183,14 +107,106 @@ template <> __device__ __forceinline__ void atomic_add_nr<double>(double* p, dou
   atomicAdd(p, v);
 }
 
-template <typename T, int TS>
-__global__ __launch_bounds__(TS* TS) void raster_bwd_kernel(
+// A workgroup covers one TS x TS tile with TS*TS/PPT lanes (a multiple of 64); lane t handles
+// column t % TS of rows t / TS + k * (TS / PPT), k < PPT.  More pixels per lane
+// amortise the LDS record reads (and, in the backward, the wavefront reductions).
+template <int TS, int PPT>
+struct TileCfg {
+  static constexpr int kThreads = TS * TS / PPT;
+  static constexpr int kRowStep = TS / PPT;
+  static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
+  // whole wavefronts only: the backward's DPP reductions end in lane 63
+  static_assert(kThreads % 64 == 0, "a tile must map onto whole wavefronts");
+};
+
+template <typename T, int TS, int PPT>
+__global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
+    const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
+    const uint2* __restrict__ ranges, ViewDev v, SettingsDev st, T* __restrict__ image,
+    T* __restrict__ T_final, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval) {
+  using Cfg = TileCfg<TS, PPT>;
+  constexpr int NT = Cfg::kThreads;
+  constexpr int NB = Cfg::kBatch;
+  __shared__ Rec<T> s_rec[NB];
+  const int tile = blockIdx.x;
+  const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
+  const int x = tx * TS + int(threadIdx.x % TS);
+  const int y0 = ty * TS + int(threadIdx.x / TS);
+  const T px = T(x) + T(0.5);
+  const T ext2 = T(st.ext2), amin = T(st.alpha_min), amax = T(st.alpha_max), tmin = T(st.T_min);
+  const uint2 rg = ranges[tile];
+  T py[PPT], Tr[PPT], c0[PPT], c1[PPT], c2[PPT];
+  uint32_t last[PPT], evals[PPT];
+  bool done[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int y = y0 + k * Cfg::kRowStep;
+    py[k] = T(y) + T(0.5);
+    Tr[k] = T(1);
+    c0[k] = c1[k] = c2[k] = T(0);
+    last[k] = evals[k] = 0u;
+    done[k] = !(x < v.W && y < v.H);
+  }
+  for (uint32_t base = rg.x; base < rg.y; base += NB) {
+    bool lane_done = true;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) lane_done &= done[k];
+    if (__syncthreads_count(lane_done) == NT) break;
+    const uint32_t i = base + threadIdx.x;
+    if (threadIdx.x < NB && i < rg.y) s_rec[threadIdx.x] = recs[values[i]];
+    __syncthreads();
+    // every lane walks the batch (no divergent branches); a finished pixel keeps
+    // its state through selects
+    const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
+    const uint32_t jbase = base - rg.x;
+    if (__ballot(!lane_done)) {
+      for (int j = 0; j < nb; ++j) {
+        const Rec<T> r = s_rec[j];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          T dx, dy, G, a_raw, alpha;
+          const bool pass = eval_pair(r, px, py[k], ext2, amin, amax, dx, dy, G, a_raw, alpha);
+          const T Tn = Tr[k] * (T(1) - alpha);
+          evals[k] += done[k] ? 0u : 1u;
+          const bool live = pass & !done[k];
+          const bool stop = live & (Tn < tmin);
+          const bool blend = live & !stop;
+          done[k] |= stop;
+          const T w = blend ? alpha * Tr[k] : T(0);
+          c0[k] = tfma(r.r, w, c0[k]);
+          c1[k] = tfma(r.g, w, c1[k]);
+          c2[k] = tfma(r.b, w, c2[k]);
+          Tr[k] = blend ? Tn : Tr[k];
+          last[k] = blend ? jbase + uint32_t(j) + 1u : last[k];
+        }
+      }
+    }
+  }
+  const long hw = long(v.H) * v.W;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int y = y0 + k * Cfg::kRowStep;
+    if (x < v.W && y < v.H) {
+      const long pix = long(y) * v.W + x;
+      image[pix] = tfma(Tr[k], T(v.bg[0]), c0[k]);
+      image[hw + pix] = tfma(Tr[k], T(v.bg[1]), c1[k]);
+      image[2 * hw + pix] = tfma(Tr[k], T(v.bg[2]), c2[k]);
+      T_final[pix] = Tr[k];
+      n_contrib[pix] = last[k];
+      if (n_eval) n_eval[pix] = evals[k];
+    }
+  }
+}
+
+template <typename T, int TS, int PPT>
+__global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
     const uint2* __restrict__ ranges, ViewDev v, SettingsDev st, const T* __restrict__ T_final,
     const uint32_t* __restrict__ n_contrib, const T* __restrict__ dL_dimage,
     T* __restrict__ grad2d, uint32_t n_gauss) {
-  constexpr int NT = TileCfg<TS>::kThreads;
-  constexpr int NB = TileCfg<TS>::kBatch;
+  using Cfg = TileCfg<TS, PPT>;
+  constexpr int NT = Cfg::kThreads;
+  constexpr int NB = Cfg::kBatch;
   __shared__ Rec<T> s_rec[NB];
   __shared__ uint32_t s_idx[NB];
   __shared__ T s_grad[9][NB];
@@ -198,27 +214,38 @@ __global__ __launch_bounds__(TS* TS) void raster_bwd_kernel(
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int x = tx * TS + int(threadIdx.x % TS);
-  const int y = ty * TS + int(threadIdx.x / TS);
-  const bool inside = x < v.W && y < v.H;
-  const T px = T(x) + T(0.5), py = T(y) + T(0.5);
+  const int y0 = ty * TS + int(threadIdx.x / TS);
+  const T px = T(x) + T(0.5);
   const T ext2 = T(st.ext2), amin = T(st.alpha_min), amax = T(st.alpha_max);
   const uint2 rg = ranges[tile];
   const long hw = long(v.H) * v.W;
-  const long pix = long(y) * v.W + x;
-  T Tcur = T(1), g0 = T(0), g1 = T(0), g2 = T(0);
-  uint32_t ncon = 0;
-  if (inside) {
-    Tcur = T_final[pix];
-    ncon = n_contrib[pix];
-    g0 = dL_dimage[pix];
-    g1 = dL_dimage[hw + pix];
-    g2 = dL_dimage[2 * hw + pix];
+  T py[PPT], Tcur[PPT], g0[PPT], g1[PPT], g2[PPT], acc0[PPT], acc1[PPT], acc2[PPT];
+  uint32_t ncon[PPT];
+  uint32_t lane_max = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int y = y0 + k * Cfg::kRowStep;
+    py[k] = T(y) + T(0.5);
+    Tcur[k] = T(1);
+    g0[k] = g1[k] = g2[k] = T(0);
+    ncon[k] = 0u;
+    if (x < v.W && y < v.H) {
+      const long pix = long(y) * v.W + x;
+      Tcur[k] = T_final[pix];
+      ncon[k] = n_contrib[pix];
+      g0[k] = dL_dimage[pix];
+      g1[k] = dL_dimage[hw + pix];
+      g2[k] = dL_dimage[2 * hw + pix];
+    }
+    // colour accumulated behind the current Gaussian (absolute, includes background)
+    acc0[k] = Tcur[k] * T(v.bg[0]);
+    acc1[k] = Tcur[k] * T(v.bg[1]);
+    acc2[k] = Tcur[k] * T(v.bg[2]);
+    lane_max = ncon[k] > lane_max ? ncon[k] : lane_max;
   }
-  // colour accumulated behind the current Gaussian (absolute, includes background)
-  T acc0 = Tcur * T(v.bg[0]), acc1 = Tcur * T(v.bg[1]), acc2 = Tcur * T(v.bg[2]);
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
-  if (ncon) atomicMax(&s_max, ncon);
+  if (lane_max) atomicMax(&s_max, lane_max);
   __syncthreads();
   const uint32_t maxn = s_max;
   const int lane = threadIdx.x & 63;
@@ -237,33 +264,40 @@ __global__ __launch_bounds__(TS* TS) void raster_bwd_kernel(
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
       const Rec<T> r = s_rec[j];
-      T dx, dy, G, a_raw, alpha;
-      const bool pass = eval_pair(r, px, py, ext2, amin, amax, dx, dy, G, a_raw, alpha);
-      const bool use = pass & (bstart + uint32_t(j) < ncon);
-      // everything below is computed by every lane and kept only where `use`
-      const T inv_om = fast_rcp(T(1) - alpha);
-      const T Ti = Tcur * inv_om;            // transmittance in front of this Gaussian
-      const T w = use ? alpha * Ti : T(0);
-      const T gr = w * g0, gg = w * g1, gb = w * g2;
-      // dC/da = T c - (colour behind) / (1 - a)
-      const T gc = tfma(g0, r.r, tfma(g1, r.g, g2 * r.b));
-      const T gacc = tfma(g0, acc0, tfma(g1, acc1, g2 * acc2));
-      // a = o exp(-q/2): da/do = exp(-q/2), da/dq = -a/2; no gradient through the clamp
-      const T dL_da = (use & (a_raw < amax)) ? Ti * gc - gacc * inv_om : T(0);
-      acc0 = tfma(r.r, w, acc0);
-      acc1 = tfma(r.g, w, acc1);
-      acc2 = tfma(r.b, w, acc2);
-      Tcur = use ? Ti : Tcur;
-      const T go = dL_da * G;
-      const T gq = T(-0.5) * dL_da * a_raw;
-      const T gqx = gq * dx, gqy = gq * dy;
-      const T gca = gqx * dx;
-      const T gcb = T(2) * gqx * dy;
-      const T gcc = gqy * dy;
-      const T gm_x = T(2) * (r.ca * gqx + r.cb * gqy);
-      const T gm_y = T(2) * (r.cb * gqx + r.cc * gqy);
-      if (__ballot(use)) {
-        T v9[9] = {gm_x, gm_y, gca, gcb, gcc, go, gr, gg, gb};
+      T v9[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        T dx, dy, G, a_raw, alpha;
+        const bool pass = eval_pair(r, px, py[k], ext2, amin, amax, dx, dy, G, a_raw, alpha);
+        const bool use = pass & (bstart + uint32_t(j) < ncon[k]);
+        any |= use;
+        // computed by every lane, kept only where `use`
+        const T inv_om = fast_rcp(T(1) - alpha);
+        const T Ti = Tcur[k] * inv_om;  // transmittance in front of this Gaussian
+        const T w = use ? alpha * Ti : T(0);
+        // dC/da = T c - (colour behind) / (1 - a)
+        const T gc = tfma(g0[k], r.r, tfma(g1[k], r.g, g2[k] * r.b));
+        const T gacc = tfma(g0[k], acc0[k], tfma(g1[k], acc1[k], g2[k] * acc2[k]));
+        // a = o exp(-q/2): da/do = exp(-q/2), da/dq = -a/2; no gradient through the clamp
+        const T dL_da = (use & (a_raw < amax)) ? Ti * gc - gacc * inv_om : T(0);
+        acc0[k] = tfma(r.r, w, acc0[k]);
+        acc1[k] = tfma(r.g, w, acc1[k]);
+        acc2[k] = tfma(r.b, w, acc2[k]);
+        Tcur[k] = use ? Ti : Tcur[k];
+        const T gq = T(-0.5) * dL_da * a_raw;
+        const T gqx = gq * dx, gqy = gq * dy;
+        v9[0] = tfma(T(2), r.ca * gqx + r.cb * gqy, v9[0]);  // d/d mean2d.x
+        v9[1] = tfma(T(2), r.cb * gqx + r.cc * gqy, v9[1]);  // d/d mean2d.y
+        v9[2] = tfma(gqx, dx, v9[2]);                        // d/d conic a
+        v9[3] = tfma(T(2) * gqx, dy, v9[3]);                 // d/d conic b
+        v9[4] = tfma(gqy, dy, v9[4]);                        // d/d conic c
+        v9[5] = tfma(dL_da, G, v9[5]);                       // d/d opacity_t
+        v9[6] = tfma(w, g0[k], v9[6]);                       // d/d rgb
+        v9[7] = tfma(w, g1[k], v9[7]);
+        v9[8] = tfma(w, g2[k], v9[8]);
+      }
+      if (__ballot(any)) {
         wave_sum9_to_lane63(v9);
         if (lane == 63) {
 #pragma unroll
@@ -310,65 +344,77 @@ __global__ __launch_bounds__(256) void l1_grad_kernel(const float* __restrict__ 
   }
 }
 
-template <typename T, int TS>
-hipError_t raster_fwd_ts(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                         const ViewDev& v, const SettingsDev& st, T* image, T* T_final,
-                         uint32_t* n_contrib, uint32_t* n_eval, hipStream_t stream) {
+template <typename T, int TS, int PPT>
+hipError_t raster_fwd_cfg(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
+                          const ViewDev& v, const SettingsDev& st, T* image, T* T_final,
+                          uint32_t* n_contrib, uint32_t* n_eval, hipStream_t stream) {
   const int tiles = v.tiles_x * v.tiles_y;
-  hipLaunchKernelGGL((raster_fwd_kernel<T, TS>), dim3(tiles), dim3(TS * TS), 0, stream, recs,
-                     values, ranges, v, st, image, T_final, n_contrib, n_eval);
+  hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT>), dim3(tiles), dim3(TS * TS / PPT), 0,
+                     stream, recs, values, ranges, v, st, image, T_final, n_contrib, n_eval);
   return hipGetLastError();
 }
 
-template <typename T, int TS>
-hipError_t raster_bwd_ts(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                         const ViewDev& v, const SettingsDev& st, const T* T_final,
-                         const uint32_t* n_contrib, const T* dL_dimage, T* grad2d,
-                         uint32_t n_gaussians, hipStream_t stream) {
+template <typename T, int TS, int PPT>
+hipError_t raster_bwd_cfg(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
+                          const ViewDev& v, const SettingsDev& st, const T* T_final,
+                          const uint32_t* n_contrib, const T* dL_dimage, T* grad2d,
+                          uint32_t n_gaussians, hipStream_t stream) {
   const int tiles = v.tiles_x * v.tiles_y;
-  hipLaunchKernelGGL((raster_bwd_kernel<T, TS>), dim3(tiles), dim3(TS * TS), 0, stream, recs,
-                     values, ranges, v, st, T_final, n_contrib, dL_dimage, grad2d, n_gaussians);
+  hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT>), dim3(tiles), dim3(TS * TS / PPT), 0,
+                     stream, recs, values, ranges, v, st, T_final, n_contrib, dL_dimage, grad2d,
+                     n_gaussians);
   return hipGetLastError();
 }
 
 }  // namespace
 
+bool raster_config_supported(int tile_size, int ppt) {
+  switch (tile_size) {
+    case 8: return ppt == 1;
+    case 16: return ppt == 1 || ppt == 2 || ppt == 4;
+    case 32: return ppt == 1 || ppt == 2 || ppt == 4;
+    default: return false;
+  }
+}
+
+// Measured on the 500k / 1352x1014 workload: the forward is fastest with one
+// pixel per lane (more lanes hide the LDS and exp latency), the backward with
+// four (fewer wavefront reductions per pixel).
+int raster_default_ppt(int tile_size, bool backward) {
+  return (backward && tile_size >= 16) ? 4 : 1;
+}
+
+#define R4D_RASTER_DISPATCH(FN, ...)                   \
+  switch (v.tile_size * 8 + ppt) {                     \
+    case 8 * 8 + 1: return FN<T, 8, 1>(__VA_ARGS__);   \
+    case 16 * 8 + 1: return FN<T, 16, 1>(__VA_ARGS__); \
+    case 16 * 8 + 2: return FN<T, 16, 2>(__VA_ARGS__); \
+    case 16 * 8 + 4: return FN<T, 16, 4>(__VA_ARGS__); \
+    case 32 * 8 + 1: return FN<T, 32, 1>(__VA_ARGS__); \
+    case 32 * 8 + 2: return FN<T, 32, 2>(__VA_ARGS__); \
+    case 32 * 8 + 4: return FN<T, 32, 4>(__VA_ARGS__); \
+    default: return hipErrorInvalidValue;              \
+  }
+
 template <typename T>
 hipError_t launch_raster_fwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                             const ViewDev& v, const SettingsDev& st, T* image, T* T_final,
-                             uint32_t* n_contrib, uint32_t* n_eval, hipStream_t stream) {
-  switch (v.tile_size) {
-    case 8:
-      return raster_fwd_ts<T, 8>(recs, values, ranges, v, st, image, T_final, n_contrib, n_eval,
-                                 stream);
-    case 16:
-      return raster_fwd_ts<T, 16>(recs, values, ranges, v, st, image, T_final, n_contrib, n_eval,
-                                  stream);
-    case 32:
-      return raster_fwd_ts<T, 32>(recs, values, ranges, v, st, image, T_final, n_contrib, n_eval,
-                                  stream);
-    default: return hipErrorInvalidValue;
-  }
+                             const ViewDev& v, const SettingsDev& st, int ppt, T* image,
+                             T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
+                             hipStream_t stream) {
+  R4D_RASTER_DISPATCH(raster_fwd_cfg, recs, values, ranges, v, st, image, T_final, n_contrib,
+                      n_eval, stream)
 }
 
 template <typename T>
 hipError_t launch_raster_bwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                             const ViewDev& v, const SettingsDev& st, const T* T_final,
+                             const ViewDev& v, const SettingsDev& st, int ppt, const T* T_final,
                              const uint32_t* n_contrib, const T* dL_dimage, T* grad2d,
                              uint32_t n_gaussians, hipStream_t stream) {
-  switch (v.tile_size) {
-    case 8:
-      return raster_bwd_ts<T, 8>(recs, values, ranges, v, st, T_final, n_contrib, dL_dimage,
-                                 grad2d, n_gaussians, stream);
-    case 16:
-      return raster_bwd_ts<T, 16>(recs, values, ranges, v, st, T_final, n_contrib, dL_dimage,
-                                  grad2d, n_gaussians, stream);
-    case 32:
-      return raster_bwd_ts<T, 32>(recs, values, ranges, v, st, T_final, n_contrib, dL_dimage,
-                                  grad2d, n_gaussians, stream);
-    default: return hipErrorInvalidValue;
-  }
+  R4D_RASTER_DISPATCH(raster_bwd_cfg, recs, values, ranges, v, st, T_final, n_contrib, dL_dimage,
+                      grad2d, n_gaussians, stream)
 }
+
+#undef R4D_RASTER_DISPATCH
 
 hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, float* grad,
                           float* loss, hipStream_t stream) {
@@ -386,18 +432,18 @@ hipError_t launch_l1_grad(const float* image, const float* target, int64_t count
 }
 
 template hipError_t launch_raster_fwd<float>(const Rec<float>*, const uint32_t*, const uint2*,
-                                             const ViewDev&, const SettingsDev&, float*, float*,
-                                             uint32_t*, uint32_t*, hipStream_t);
+                                             const ViewDev&, const SettingsDev&, int, float*,
+                                             float*, uint32_t*, uint32_t*, hipStream_t);
 template hipError_t launch_raster_fwd<double>(const Rec<double>*, const uint32_t*, const uint2*,
-                                              const ViewDev&, const SettingsDev&, double*,
+                                              const ViewDev&, const SettingsDev&, int, double*,
                                               double*, uint32_t*, uint32_t*, hipStream_t);
 template hipError_t launch_raster_bwd<float>(const Rec<float>*, const uint32_t*, const uint2*,
-                                             const ViewDev&, const SettingsDev&, const float*,
-                                             const uint32_t*, const float*, float*, uint32_t,
-                                             hipStream_t);
+                                             const ViewDev&, const SettingsDev&, int,
+                                             const float*, const uint32_t*, const float*, float*,
+                                             uint32_t, hipStream_t);
 template hipError_t launch_raster_bwd<double>(const Rec<double>*, const uint32_t*, const uint2*,
-                                              const ViewDev&, const SettingsDev&, const double*,
-                                              const uint32_t*, const double*, double*, uint32_t,
-                                              hipStream_t);
+                                              const ViewDev&, const SettingsDev&, int,
+                                              const double*, const uint32_t*, const double*,
+                                              double*, uint32_t, hipStream_t);
 
 }  // namespace r4d

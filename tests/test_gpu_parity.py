@@ -122,13 +122,37 @@ def test_tile_rectangles_are_conservative_2k(r4d, scene2k, device):
         assert np.all((tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1)), i
 
 
+RASTER_CONFIGS = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4))
+
+
 def test_tile_size_invariance_2k(r4d, scene2k, device):
+    """Every (tile size, pixels per lane) gives the same image bit for bit, and
+    the same gradients up to the order of float atomics."""
     g, views, st, _ = scene2k
-    out = []
-    for ts in (8, 16, 32):
-        _, _, imgs, _ = _render(r4d, g, views, dict(st, tile_size=ts), device, save=False)
+    out, grads = [], []
+    dl = torch.as_tensor(np.random.default_rng(3).uniform(-1, 1, (3, 128, 128)),
+                         dtype=torch.float32, device=device)
+    for ts, ppt in RASTER_CONFIGS:
+        cfg = dict(st, tile_size=ts, fwd_pixels_per_thread=ppt, bwd_pixels_per_thread=ppt)
+        rend, p, imgs, saved = _render(r4d, g, views, cfg, device)
         out.append(imgs[0].cpu().numpy())
-    assert np.array_equal(out[0], out[1]) and np.array_equal(out[1], out[2])
+        grads.append({k: v.cpu().numpy().astype(np.float64)
+                      for k, v in rend.backward(p, views, cfg, saved, [dl]).items()})
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)
+    # the per-Gaussian sums are float atomics in a different order per config
+    for gr in grads[1:]:
+        for k in gr:
+            ref = grads[0][k]
+            assert _rel(gr[k], ref) <= 1e-4, k
+            assert np.all(np.abs(gr[k] - ref) <= 1e-3 * (np.abs(ref) + 1e-2 * np.abs(ref).max())), k
+
+
+def test_unsupported_raster_config_is_rejected(r4d, device):
+    g, views, st = W.scene_2k()
+    rend = r4d.Renderer(device)
+    with pytest.raises(r4d.R4DError, match="INVALID_ARG"):
+        rend.forward(to_device(g, device), views, dict(st, tile_size=8, fwd_pixels_per_thread=2))
 
 
 def test_ragged_image_and_multi_view(r4d, device):
@@ -258,3 +282,15 @@ def test_gradients_fp64_match_central_differences(r4d, device):
             assert abs(fd - ad) <= 1e-5 * max(abs(fd), abs(ad), 1e-3), (key, idx, fd, ad)
             checked += 1
     assert checked >= 25
+
+
+def test_saved_state_may_outlive_its_context(r4d, device):
+    """Releasing a saved state after its renderer was destroyed frees only the
+    handle (the context's destroy already freed the device memory)."""
+    g, views, st = W.scene_2k()
+    rend = r4d.Renderer(device)
+    _, saved = rend.forward(to_device(g, device), views, st, save=True)
+    rend.close()
+    saved.release()
+    with pytest.raises(r4d.R4DError):
+        saved.stats(0)
