@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--bwd-ppt", type=int, default=0,
                     help="backward rasteriser pixels per lane (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a kernel of "
+                         "known traffic, to scale hardware byte counters)")
     ap.add_argument("--cpu-pixels", type=int, nargs=2, default=(16, 64),
                     help="two oracle pixel-sample sizes used to fit fixed + per-pixel cost")
     return ap.parse_args()
@@ -103,6 +106,13 @@ def main():
     params["sh_degree"] = g["sh_degree"]
     target = torch.as_tensor(W.target_image(H, Wd)).to(dev)
     rend = r4d.Renderer(dev)
+    if args.calibration_copy_mib:
+        nbytes = args.calibration_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         imgs, saved = rend.forward(params, views, st, save=True)

@@ -29,29 +29,46 @@ template <> __device__ __forceinline__ double tfma<double>(double a, double b, d
   return __builtin_fma(a, b, c);
 }
 
-// exp(-q/2)
-template <typename T> __device__ __forceinline__ T gauss_falloff(T q);
-template <> __device__ __forceinline__ float gauss_falloff<float>(float q) {
-  return __expf(-0.5f * q);
-}
-template <> __device__ __forceinline__ double gauss_falloff<double>(double q) {
-  return exp(-0.5 * q);
+// exp2
+template <typename T> __device__ __forceinline__ T texp2(T x);
+template <> __device__ __forceinline__ float texp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ __forceinline__ double texp2<double>(double x) { return exp2(x); }
+
+// -log2(e) / 2: exp(-q/2) = exp2(kHalfLog2e * q)
+constexpr double kHalfLog2e = -0.72134752044448170368;
+
+// A record as the rasteriser keeps it in LDS: the conic is pre-multiplied by
+// -log2(e)/2 (and the off-diagonal term doubled) so that the Gaussian falloff is
+// one exp2 of a quadratic form: e = A dx^2 + B dx dy + C dy^2 = -q log2(e) / 2.
+template <typename T>
+struct Staged {
+  T mx, my, A, B;
+  T C, o, r, g;
+  T b, pad0, pad1, pad2;
+};
+
+template <typename T>
+__device__ __forceinline__ Staged<T> stage(const Rec<T>& r) {
+  const T k = T(kHalfLog2e);
+  return Staged<T>{r.mx, r.my, k * r.ca, T(2) * k * r.cb, k * r.cc, r.o, r.r, r.g, r.b,
+                   T(0), T(0), T(0)};
 }
 
 // The one place where a (pixel, Gaussian) pair is evaluated; forward and backward
 // call it with identical operands so that they take identical decisions.
 // G = exp(-q/2), a_raw = o G, alpha = min(alpha_max, a_raw).  Evaluated without
-// branches: the result says whether the pair passes the extent and alpha tests.
+// branches: the result says whether the pair passes the extent test
+// (q <= extent^2, i.e. e >= e_min) and the alpha test.
 template <typename T>
-__device__ __forceinline__ bool eval_pair(const Rec<T>& r, T px, T py, T ext2, T amin, T amax,
+__device__ __forceinline__ bool eval_pair(const Staged<T>& r, T px, T py, T e_min, T amin, T amax,
                                           T& dx, T& dy, T& G, T& a_raw, T& alpha) {
   dx = r.mx - px;
   dy = r.my - py;
-  const T q = tfma(r.ca * dx, dx, tfma(T(2) * r.cb * dx, dy, r.cc * dy * dy));
-  G = gauss_falloff(q);
+  const T e = tfma(r.A * dx, dx, tfma(r.B * dx, dy, r.C * dy * dy));
+  G = texp2(e);
   a_raw = r.o * G;
   alpha = a_raw < amax ? a_raw : amax;
-  return (q <= ext2) & (alpha >= amin);
+  return (e >= e_min) & (alpha >= amin);
 }
 
 // 1/x: the hardware reciprocal in float (about 1 ulp), exact division in double.
@@ -119,7 +136,11 @@ struct TileCfg {
   static_assert(kThreads % 64 == 0, "a tile must map onto whole wavefronts");
 };
 
-template <typename T, int TS, int PPT>
+// Forward.  A pixel that has stopped keeps its final transmittance in Tf and
+// continues with T = 0, which makes every later contribution zero and every later
+// transmittance test fail, so no per-pixel "done" flag is carried through the
+// loop.  COUNT counts the entries each pixel evaluates (measurement builds only).
+template <typename T, int TS, int PPT, bool COUNT>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
     const uint2* __restrict__ ranges, ViewDev v, SettingsDev st, T* __restrict__ image,
@@ -127,56 +148,55 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
-  __shared__ Rec<T> s_rec[NB];
+  __shared__ Staged<T> s_rec[NB];
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int x = tx * TS + int(threadIdx.x % TS);
   const int y0 = ty * TS + int(threadIdx.x / TS);
   const T px = T(x) + T(0.5);
-  const T ext2 = T(st.ext2), amin = T(st.alpha_min), amax = T(st.alpha_max), tmin = T(st.T_min);
+  const T e_min = T(kHalfLog2e) * T(st.ext2);
+  const T amin = T(st.alpha_min), amax = T(st.alpha_max), tmin = T(st.T_min);
   const uint2 rg = ranges[tile];
-  T py[PPT], Tr[PPT], c0[PPT], c1[PPT], c2[PPT];
+  T py[PPT], Tr[PPT], Tf[PPT], c0[PPT], c1[PPT], c2[PPT];
   uint32_t last[PPT], evals[PPT];
-  bool done[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int y = y0 + k * Cfg::kRowStep;
     py[k] = T(y) + T(0.5);
-    Tr[k] = T(1);
+    // pixels outside the image start finished
+    Tr[k] = (x < v.W && y < v.H) ? T(1) : T(0);
+    Tf[k] = T(1);
     c0[k] = c1[k] = c2[k] = T(0);
     last[k] = evals[k] = 0u;
-    done[k] = !(x < v.W && y < v.H);
   }
   for (uint32_t base = rg.x; base < rg.y; base += NB) {
     bool lane_done = true;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) lane_done &= done[k];
+    for (int k = 0; k < PPT; ++k) lane_done &= Tr[k] == T(0);
     if (__syncthreads_count(lane_done) == NT) break;
     const uint32_t i = base + threadIdx.x;
-    if (threadIdx.x < NB && i < rg.y) s_rec[threadIdx.x] = recs[values[i]];
+    if (threadIdx.x < NB && i < rg.y) s_rec[threadIdx.x] = stage(recs[values[i]]);
     __syncthreads();
-    // every lane walks the batch (no divergent branches); a finished pixel keeps
-    // its state through selects
     const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
     const uint32_t jbase = base - rg.x;
     if (__ballot(!lane_done)) {
       for (int j = 0; j < nb; ++j) {
-        const Rec<T> r = s_rec[j];
+        const Staged<T> r = s_rec[j];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           T dx, dy, G, a_raw, alpha;
-          const bool pass = eval_pair(r, px, py[k], ext2, amin, amax, dx, dy, G, a_raw, alpha);
+          const bool pass = eval_pair(r, px, py[k], e_min, amin, amax, dx, dy, G, a_raw, alpha);
           const T Tn = Tr[k] * (T(1) - alpha);
-          evals[k] += done[k] ? 0u : 1u;
-          const bool live = pass & !done[k];
-          const bool stop = live & (Tn < tmin);
-          const bool blend = live & !stop;
-          done[k] |= stop;
+          if (COUNT) evals[k] += Tr[k] != T(0) ? 1u : 0u;
+          const bool blend = pass & (Tn >= tmin);
+          // the first Gaussian that would take T below T_min stops the pixel
+          const bool stop = pass & !(Tn >= tmin) & (Tr[k] != T(0));
+          Tf[k] = stop ? Tr[k] : Tf[k];
           const T w = blend ? alpha * Tr[k] : T(0);
           c0[k] = tfma(r.r, w, c0[k]);
           c1[k] = tfma(r.g, w, c1[k]);
           c2[k] = tfma(r.b, w, c2[k]);
-          Tr[k] = blend ? Tn : Tr[k];
+          Tr[k] = pass ? (blend ? Tn : T(0)) : Tr[k];
           last[k] = blend ? jbase + uint32_t(j) + 1u : last[k];
         }
       }
@@ -188,12 +208,13 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     const int y = y0 + k * Cfg::kRowStep;
     if (x < v.W && y < v.H) {
       const long pix = long(y) * v.W + x;
-      image[pix] = tfma(Tr[k], T(v.bg[0]), c0[k]);
-      image[hw + pix] = tfma(Tr[k], T(v.bg[1]), c1[k]);
-      image[2 * hw + pix] = tfma(Tr[k], T(v.bg[2]), c2[k]);
-      T_final[pix] = Tr[k];
+      const T Tfin = Tr[k] != T(0) ? Tr[k] : Tf[k];
+      image[pix] = tfma(Tfin, T(v.bg[0]), c0[k]);
+      image[hw + pix] = tfma(Tfin, T(v.bg[1]), c1[k]);
+      image[2 * hw + pix] = tfma(Tfin, T(v.bg[2]), c2[k]);
+      T_final[pix] = Tfin;
       n_contrib[pix] = last[k];
-      if (n_eval) n_eval[pix] = evals[k];
+      if (COUNT) n_eval[pix] = evals[k];
     }
   }
 }
@@ -207,7 +228,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
-  __shared__ Rec<T> s_rec[NB];
+  __shared__ Staged<T> s_rec[NB];
   __shared__ uint32_t s_idx[NB];
   __shared__ T s_grad[9][NB];
   __shared__ uint32_t s_max;
@@ -216,7 +237,8 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
   const int x = tx * TS + int(threadIdx.x % TS);
   const int y0 = ty * TS + int(threadIdx.x / TS);
   const T px = T(x) + T(0.5);
-  const T ext2 = T(st.ext2), amin = T(st.alpha_min), amax = T(st.alpha_max);
+  const T e_min = T(kHalfLog2e) * T(st.ext2);
+  const T amin = T(st.alpha_min), amax = T(st.alpha_max);
   const uint2 rg = ranges[tile];
   const long hw = long(v.H) * v.W;
   T py[PPT], Tcur[PPT], g0[PPT], g1[PPT], g2[PPT], acc0[PPT], acc1[PPT], acc2[PPT];
@@ -256,20 +278,20 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
       if (int(threadIdx.x) < nb) {
         const uint32_t idx = values[rg.x + bstart + threadIdx.x];
         s_idx[threadIdx.x] = idx;
-        s_rec[threadIdx.x] = recs[idx];
+        s_rec[threadIdx.x] = stage(recs[idx]);
       }
 #pragma unroll
       for (int c = 0; c < 9; ++c) s_grad[c][threadIdx.x] = T(0);
     }
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
-      const Rec<T> r = s_rec[j];
+      const Staged<T> r = s_rec[j];
       T v9[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         T dx, dy, G, a_raw, alpha;
-        const bool pass = eval_pair(r, px, py[k], ext2, amin, amax, dx, dy, G, a_raw, alpha);
+        const bool pass = eval_pair(r, px, py[k], e_min, amin, amax, dx, dy, G, a_raw, alpha);
         const bool use = pass & (bstart + uint32_t(j) < ncon[k]);
         any |= use;
         // computed by every lane, kept only where `use`
@@ -285,13 +307,17 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
         acc1[k] = tfma(r.g, w, acc1[k]);
         acc2[k] = tfma(r.b, w, acc2[k]);
         Tcur[k] = use ? Ti : Tcur[k];
+        // dL/dq = -a/2 dL/da.  With the staged A = k a_c, B = 2 k b_c, C = k c_c
+        // (k = -log2(e)/2): dq/dmean = 2 (a_c dx + b_c dy, b_c dx + c_c dy)
+        //                          = (2 A dx + B dy, B dx + 2 C dy) / k
         const T gq = T(-0.5) * dL_da * a_raw;
         const T gqx = gq * dx, gqy = gq * dy;
-        v9[0] = tfma(T(2), r.ca * gqx + r.cb * gqy, v9[0]);  // d/d mean2d.x
-        v9[1] = tfma(T(2), r.cb * gqx + r.cc * gqy, v9[1]);  // d/d mean2d.y
-        v9[2] = tfma(gqx, dx, v9[2]);                        // d/d conic a
-        v9[3] = tfma(T(2) * gqx, dy, v9[3]);                 // d/d conic b
-        v9[4] = tfma(gqy, dy, v9[4]);                        // d/d conic c
+        const T gqk = gq * T(1.0 / kHalfLog2e);
+        v9[0] = tfma(gqk, T(2) * r.A * dx + r.B * dy, v9[0]);  // d/d mean2d.x
+        v9[1] = tfma(gqk, r.B * dx + T(2) * r.C * dy, v9[1]);  // d/d mean2d.y
+        v9[2] = tfma(gqx, dx, v9[2]);                          // d/d conic a
+        v9[3] = tfma(T(2) * gqx, dy, v9[3]);                   // d/d conic b
+        v9[4] = tfma(gqy, dy, v9[4]);                          // d/d conic c
         v9[5] = tfma(dL_da, G, v9[5]);                       // d/d opacity_t
         v9[6] = tfma(w, g0[k], v9[6]);                       // d/d rgb
         v9[7] = tfma(w, g1[k], v9[7]);
@@ -349,8 +375,12 @@ hipError_t raster_fwd_cfg(const Rec<T>* recs, const uint32_t* values, const uint
                           const ViewDev& v, const SettingsDev& st, T* image, T* T_final,
                           uint32_t* n_contrib, uint32_t* n_eval, hipStream_t stream) {
   const int tiles = v.tiles_x * v.tiles_y;
-  hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT>), dim3(tiles), dim3(TS * TS / PPT), 0,
-                     stream, recs, values, ranges, v, st, image, T_final, n_contrib, n_eval);
+  if (n_eval)
+    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, true>), dim3(tiles), dim3(TS * TS / PPT), 0,
+                       stream, recs, values, ranges, v, st, image, T_final, n_contrib, n_eval);
+  else
+    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false>), dim3(tiles), dim3(TS * TS / PPT),
+                       0, stream, recs, values, ranges, v, st, image, T_final, n_contrib, n_eval);
   return hipGetLastError();
 }
 
