@@ -429,15 +429,15 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
 
 
 def gaussian_margin_flags(pre: dict, st: dict):
-    """Per-Gaussian flags: the time cull, near cull or opacity-vs-alpha_min
-    decision is within FP32 rounding of its threshold."""
+    """Per-Gaussian flags: the time-cull or near-plane decision is within FP32
+    rounding of its threshold and the Gaussian is opaque enough to be blended
+    somewhere if kept (o_t >= alpha_min)."""
     st = settings_dict(st)
     tau = st["time_cull"]
     f = (pre["lam_dt2"] - tau).abs() < 1e-5 * tau
     f |= (pre["depth"].detach() - st["near_plane"]).abs() < 1e-6
     o = pre["opacity"].detach()
-    f |= ((o - st["alpha_min"]).abs() / st["alpha_min"]) < 1e-5
-    return f
+    return f & (o >= st["alpha_min"] * (1 - 1e-5))
 
 
 def render(g: dict, view: dict, st: dict | None = None, pixels=None,
@@ -460,7 +460,7 @@ def render(g: dict, view: dict, st: dict | None = None, pixels=None,
         pidx = torch.as_tensor(np.asarray(pixels), dtype=torch.int64)
         pix = torch.stack([pidx % W, pidx // W], dim=-1)
     col, aux = composite(pix, pre, view["bg"], st)
-    # Pixels touched by a Gaussian whose cull decision is marginal.
+    # Pixels a Gaussian with a marginal cull decision could be blended into.
     gflag = gaussian_margin_flags(pre, st)
     if bool(gflag.any()):
         with torch.no_grad():
@@ -468,8 +468,9 @@ def render(g: dict, view: dict, st: dict | None = None, pixels=None,
             d = pre["mean2"].detach()[idx][None] - (pix.to(DT) + 0.5)[:, None]
             cn = pre["conic"].detach()[idx]
             q = cn[:, 0] * d[..., 0] ** 2 + 2 * cn[:, 1] * d[..., 0] * d[..., 1] + cn[:, 2] * d[..., 1] ** 2
-            near = (q <= st["extent_sigma"] ** 2 + 1e-3).any(1)
-            aux["ambiguous"] |= near
+            o = pre["opacity"].detach()[idx]
+            reach = torch.clamp(2.0 * torch.log(o / st["alpha_min"]), max=st["extent_sigma"] ** 2)
+            aux["ambiguous"] |= (q <= reach[None, :] + 1e-3).any(1)
     image = col.T.contiguous()
     if pixels is None:
         image = image.reshape(3, H, W)

@@ -324,13 +324,10 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
     R4D_ALLOC(kB, uint32_t, nn * 4);
     R4D_ALLOC(vA, uint32_t, nn * 4);
     R4D_ALLOC(vB, uint32_t, nn * 4);
-    R4D_ALLOC(offsets, uint64_t, (nn + 1) * 8);
-    R4D_ALLOC(counter, uint32_t, 256);
+    R4D_ALLOC(totals, unsigned long long, 256);
     const size_t sort_tmp_bytes = sort_pairs_temp_bytes(n);
     R4D_ALLOC(sort_tmp, uint8_t, sort_tmp_bytes);
-    const size_t scan_tmp_bytes = count_scan_temp_bytes(n);
-    R4D_ALLOC(scan_tmp, uint8_t, scan_tmp_bytes);
-    R4D_HIP(hipMemsetAsync(counter, 0, 4, stream));
+    R4D_HIP(hipMemsetAsync(totals, 0, 2 * sizeof(unsigned long long), stream));
     uint32_t* depth_saved = nullptr;
     if (saved) {
       depth_saved = scratch.get<uint32_t>(nn * 4);
@@ -339,31 +336,26 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
     uint64_t D = 0, n_vis = 0;
     uint32_t* order = vA;
     if (n > 0) {
-      R4D_TIMED(kPreprocessFwd, launch_preprocess_fwd<T>(g, vd, st, recs, rects, tiles, kA, vA, counter, stream));
+      R4D_TIMED(kPreprocessFwd, launch_preprocess_fwd<T>(g, vd, st, recs, rects, tiles, kA, vA,
+                                                         totals, stream));
       if (depth_saved)
         R4D_HIP(hipMemcpyAsync(depth_saved, kA, size_t(n) * 4, hipMemcpyDeviceToDevice, stream));
+      R4D_HIP(hipMemcpyAsync(ctx->host_readback, totals, 2 * sizeof(uint64_t),
+                             hipMemcpyDeviceToHost, stream));
       uint32_t* kk[2] = {kA, kB};
       uint32_t* vv[2] = {vA, vB};
       int res = 0;
-      R4D_TIMED(kDepthSort, sort_pairs_u32(kk, vv, n, 32, SortTemp{sort_tmp, sort_tmp_bytes}, &res, stream));
+      R4D_TIMED(kDepthSort, sort_pairs_u32(kk, vv, n, 32, SortTemp{sort_tmp, sort_tmp_bytes},
+                                           &res, stream));
       order = vv[res];
-      R4D_TIMED(kCountScan, count_scan(order, tiles, n, offsets, SortTemp{scan_tmp, scan_tmp_bytes}, stream));
-      R4D_HIP(hipMemcpyAsync(ctx->host_readback, offsets + n, 8, hipMemcpyDeviceToHost, stream));
-      R4D_HIP(hipMemcpyAsync(ctx->host_readback + 1, counter, 4, hipMemcpyDeviceToHost, stream));
       R4D_HIP(hipStreamSynchronize(stream));
-      D = ctx->host_readback[0];
-      n_vis = ctx->host_readback[1] & 0xffffffffull;
+      n_vis = ctx->host_readback[0];
+      D = ctx->host_readback[1];
     }
     if (D >= (uint64_t(1) << 31))
       return fail(ctx, R4D_ERR_CAPACITY, "view %d has %llu tile entries (limit 2^31)", vi,
                   (unsigned long long)D);
     const size_t dd = D ? size_t(D) : 1;
-    R4D_ALLOC(tkA, uint32_t, dd * 4);
-    R4D_ALLOC(tkB, uint32_t, dd * 4);
-    R4D_ALLOC(tvA, uint32_t, dd * 4);
-    R4D_ALLOC(tvB, uint32_t, dd * 4);
-    const size_t tsort_bytes = sort_pairs_temp_bytes(uint32_t(D));
-    R4D_ALLOC(tsort_tmp, uint8_t, tsort_bytes);
     R4D_ALLOC(ranges, uint2, size_t(n_tiles) * sizeof(uint2));
     R4D_ALLOC(T_final, T, hw * sizeof(T));
     R4D_ALLOC(n_contrib, uint32_t, hw * 4);
@@ -372,9 +364,24 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
       n_eval = scratch.get<uint32_t>(hw * 4);
       if (!n_eval) return fail(ctx, R4D_ERR_OOM, "device allocation failed");
     }
+    R4D_ALLOC(tvA, uint32_t, dd * 4);
     uint32_t* values = tvA;
-    if (D > 0) {
-      R4D_TIMED(kEmit, emit_tile_keys(order, offsets, rects, n, vd.tiles_x, tkA, tvA, stream));
+    if (D == 0) {
+      R4D_HIP(hipMemsetAsync(ranges, 0, size_t(n_tiles) * sizeof(uint2), stream));
+    } else {
+      // emit (tile, index) pairs in depth order, then sort them stably by tile id
+      R4D_ALLOC(offsets, uint64_t, (nn + 1) * 8);
+      const size_t scan_tmp_bytes = count_scan_temp_bytes(n);
+      R4D_ALLOC(scan_tmp, uint8_t, scan_tmp_bytes);
+      R4D_ALLOC(tkA, uint32_t, dd * 4);
+      R4D_ALLOC(tkB, uint32_t, dd * 4);
+      R4D_ALLOC(tvB, uint32_t, dd * 4);
+      const size_t tsort_bytes = sort_pairs_temp_bytes(uint32_t(D));
+      R4D_ALLOC(tsort_tmp, uint8_t, tsort_bytes);
+      R4D_TIMED(kCountScan, count_scan(order, tiles, uint32_t(n_vis), offsets,
+                                       SortTemp{scan_tmp, scan_tmp_bytes}, stream));
+      R4D_TIMED(kEmit, emit_tile_keys(order, offsets, rects, uint32_t(n_vis), vd.tiles_x, tkA,
+                                      tvA, stream));
       uint32_t* kk[2] = {tkA, tkB};
       uint32_t* vv[2] = {tvA, tvB};
       int res = 0;
@@ -382,8 +389,6 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
                                           SortTemp{tsort_tmp, tsort_bytes}, &res, stream));
       values = vv[res];
       R4D_TIMED(kTileRanges, tile_ranges(kk[res], uint32_t(D), n_tiles, ranges, stream));
-    } else {
-      R4D_HIP(hipMemsetAsync(ranges, 0, size_t(n_tiles) * sizeof(uint2), stream));
     }
     R4D_TIMED(kRasterFwd, launch_raster_fwd<T>(recs, values, ranges, vd, st, fwd_ppt(*settings),
                                               images + img_off, T_final, n_contrib, n_eval,
@@ -442,13 +447,13 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   const SettingsDev st = make_settings(*settings);
   Scratch scratch(ctx);
   const size_t n = size_t(g.n);
-  R4D_ALLOC(grad2d, T, 9 * n * sizeof(T));
+  R4D_ALLOC(grad2d, double, 9 * n * sizeof(double));
   size_t img_off = 0;
   for (int vi = 0; vi < n_views; ++vi) {
     const ViewSaved& vs = saved->views[vi];
     const ViewDev vd = make_view(views[vi], *settings);
     const uint64_t hw = uint64_t(views[vi].width) * views[vi].height;
-    R4D_HIP(hipMemsetAsync(grad2d, 0, 9 * n * sizeof(T), stream));
+    R4D_HIP(hipMemsetAsync(grad2d, 0, 9 * n * sizeof(double), stream));
     if (vs.n_dup > 0)
       R4D_TIMED(kRasterBwd, launch_raster_bwd<T>(static_cast<const Rec<T>*>(vs.recs), vs.values,
                                                 vs.ranges, vd, st, bwd_ppt(*settings),

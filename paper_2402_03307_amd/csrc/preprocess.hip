@@ -50,15 +50,17 @@ __device__ __forceinline__ bool tile_rect(const Rec<T>& rec, const ViewDev& v,
   return true;
 }
 
-template <typename T>
+template <typename T, int DEG>
 __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     GaussPtrs<T> g, ViewDev v, SettingsDev st, Rec<T>* __restrict__ recs,
     Rect16* __restrict__ rects, uint32_t* __restrict__ tiles_touched,
     uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ values_iota,
-    uint32_t* __restrict__ n_visible) {
+    unsigned long long* __restrict__ totals) {
+  __shared__ unsigned long long s_tot[2][kBlock / 64];
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   bool vis = false;
+  uint32_t my_cnt = 0;
   if (i < n) {
     T mu[4], ls[4], rot[8];
 #pragma unroll
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     for (int c = 0; c < 8; ++c) rot[c] = g.rotors[c * (long)n + i];
     const T op = g.opacity[i];
     Fwd<T> f;
-    gaussian_fwd<T>(mu, ls, rot, op, g.sh + i, (long)n, g.deg, v, st, f);
+    gaussian_fwd<T>(mu, ls, rot, op, g.sh + i, (long)n, DEG, v, st, f);
     Rect16 rc = {0, 0, 0, 0};
     uint32_t cnt = 0;
     uint32_t key = 0xffffffffu;
@@ -101,32 +103,55 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     tiles_touched[i] = cnt;
     depth_keys[i] = key;
     values_iota[i] = uint32_t(i);
+    my_cnt = cnt;
   }
+  // block totals of visible Gaussians and tile entries, one atomic each per block
+  unsigned long long c = my_cnt;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
   const unsigned long long m = __ballot(vis);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_visible, uint32_t(__popcll(m)));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_tot[0][wave] = __popcll(m);
+    s_tot[1][wave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      a += s_tot[0][w];
+      b += s_tot[1][w];
+    }
+    if (a) atomicAdd(&totals[0], a);
+    if (b) atomicAdd(&totals[1], b);
+  }
 }
 
-template <typename T>
+// Degree-specialised so that the SH loops unroll and the coefficient arrays
+// live in registers.
+template <typename T, int DEG>
 __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g, ViewDev v,
                                                                 SettingsDev st,
-                                                                const T* __restrict__ grad2d,
+                                                                const double* __restrict__ grad2d,
                                                                 GradPtrs<T> out, bool accumulate) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const int k = (g.deg + 1) * (g.deg + 1);
   T g2[9];
   bool any = false;
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
-    g2[c] = grad2d[c * (long)n + i];
+    g2[c] = T(grad2d[c * (long)n + i]);
     any |= g2[c] != T(0);
   }
   T gmu[4] = {0, 0, 0, 0}, gls[4] = {0, 0, 0, 0}, grot[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gop = 0;
-  T gsh[48];
-  for (int j = 0; j < 3 * k; ++j) gsh[j] = T(0);
+  T gsh[3 * K];
+#pragma unroll
+  for (int j = 0; j < 3 * K; ++j) gsh[j] = T(0);
   if (any) {
-    T mu[4], ls[4], rot[8], shl[48];
+    T mu[4], ls[4], rot[8], shl[3 * K];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       mu[c] = g.means[c * (long)n + i];
@@ -134,11 +159,12 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g, 
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) rot[c] = g.rotors[c * (long)n + i];
-    for (int j = 0; j < 3 * k; ++j) shl[j] = g.sh[j * (long)n + i];
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) shl[j] = g.sh[j * (long)n + i];
     const T op = g.opacity[i];
     Fwd<T> f;
-    gaussian_fwd<T>(mu, ls, rot, op, shl, 1, g.deg, v, st, f);
-    gaussian_bwd<T>(f, shl, 1, g.deg, v, g2, gmu, gls, grot, gop, gsh);
+    gaussian_fwd<T>(mu, ls, rot, op, shl, 1, DEG, v, st, f);
+    gaussian_bwd<T>(f, shl, 1, DEG, v, g2, gmu, gls, grot, gop, gsh);
   }
   if (accumulate) {
 #pragma unroll
@@ -149,7 +175,8 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g, 
 #pragma unroll
     for (int c = 0; c < 8; ++c) out.rotors[c * (long)n + i] += grot[c];
     out.opacity[i] += gop;
-    for (int j = 0; j < 3 * k; ++j) out.sh[j * (long)n + i] += gsh[j];
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) out.sh[j * (long)n + i] += gsh[j];
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -159,45 +186,56 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g, 
 #pragma unroll
     for (int c = 0; c < 8; ++c) out.rotors[c * (long)n + i] = grot[c];
     out.opacity[i] = gop;
-    for (int j = 0; j < 3 * k; ++j) out.sh[j * (long)n + i] = gsh[j];
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) out.sh[j * (long)n + i] = gsh[j];
   }
 }
 
 }  // namespace
 
+#define R4D_DEG_DISPATCH(KERNEL, ...)                                                    \
+  switch (g.deg) {                                                                       \
+    case 0: hipLaunchKernelGGL((KERNEL<T, 0>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 1: hipLaunchKernelGGL((KERNEL<T, 1>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 3: hipLaunchKernelGGL((KERNEL<T, 3>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                \
+  }
+
 template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
                                  Rec<T>* recs, Rect16* rects, uint32_t* tiles_touched,
-                                 uint32_t* depth_keys, uint32_t* values_iota, uint32_t* n_visible,
-                                 hipStream_t stream) {
+                                 uint32_t* depth_keys, uint32_t* values_iota,
+                                 unsigned long long* totals, hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
   const int grid = (g.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(preprocess_fwd_kernel<T>, dim3(grid), dim3(kBlock), 0, stream, g, v, st,
-                     recs, rects, tiles_touched, depth_keys, values_iota, n_visible);
+  R4D_DEG_DISPATCH(preprocess_fwd_kernel, g, v, st, recs, rects, tiles_touched, depth_keys,
+                   values_iota, totals)
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
-                                 const T* grad2d, const GradPtrs<T>& out, bool accumulate,
+                                 const double* grad2d, const GradPtrs<T>& out, bool accumulate,
                                  hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
   const int grid = (g.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(preprocess_bwd_kernel<T>, dim3(grid), dim3(kBlock), 0, stream, g, v, st,
-                     grad2d, out, accumulate);
+  R4D_DEG_DISPATCH(preprocess_bwd_kernel, g, v, st, grad2d, out, accumulate)
   return hipGetLastError();
 }
 
+#undef R4D_DEG_DISPATCH
+
 template hipError_t launch_preprocess_fwd<float>(const GaussPtrs<float>&, const ViewDev&,
                                                  const SettingsDev&, Rec<float>*, Rect16*,
-                                                 uint32_t*, uint32_t*, uint32_t*, uint32_t*,
-                                                 hipStream_t);
+                                                 uint32_t*, uint32_t*, uint32_t*,
+                                                 unsigned long long*, hipStream_t);
 template hipError_t launch_preprocess_fwd<double>(const GaussPtrs<double>&, const ViewDev&,
                                                   const SettingsDev&, Rec<double>*, Rect16*,
-                                                  uint32_t*, uint32_t*, uint32_t*, uint32_t*,
-                                                  hipStream_t);
+                                                  uint32_t*, uint32_t*, uint32_t*,
+                                                  unsigned long long*, hipStream_t);
 template hipError_t launch_preprocess_bwd<float>(const GaussPtrs<float>&, const ViewDev&,
-                                                 const SettingsDev&, const float*,
+                                                 const SettingsDev&, const double*,
                                                  const GradPtrs<float>&, bool, hipStream_t);
 template hipError_t launch_preprocess_bwd<double>(const GaussPtrs<double>&, const ViewDev&,
                                                   const SettingsDev&, const double*,

@@ -34,17 +34,19 @@ struct Rect16 {
 };
 
 // ---- preprocess (per Gaussian)
+// totals[0] += number of visible Gaussians, totals[1] += number of tile entries
+// (the caller zeroes them first).
 template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
                                  Rec<T>* recs, Rect16* rects, uint32_t* tiles_touched,
-                                 uint32_t* depth_keys, uint32_t* values_iota, uint32_t* n_visible,
-                                 hipStream_t stream);
+                                 uint32_t* depth_keys, uint32_t* values_iota,
+                                 unsigned long long* totals, hipStream_t stream);
 
-// grad2d: [9][n] (mean2 x, y, conic a, b, c, opacity_t, r, g, b).  accumulate=false
-// overwrites `out`, true adds to it.
+// grad2d: [9][n] double (mean2 x, y, conic a, b, c, opacity_t, r, g, b).
+// accumulate=false overwrites `out`, true adds to it.
 template <typename T>
 hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
-                                 const T* grad2d, const GradPtrs<T>& out, bool accumulate,
+                                 const double* grad2d, const GradPtrs<T>& out, bool accumulate,
                                  hipStream_t stream);
 
 // ---- sorting and binning
@@ -88,10 +90,11 @@ hipError_t launch_raster_fwd(const Rec<T>* recs, const uint32_t* values, const u
                              T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
                              hipStream_t stream);
 
+// grad2d: [9][n] double accumulators (see launch_preprocess_bwd), added to.
 template <typename T>
 hipError_t launch_raster_bwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
                              const ViewDev& v, const SettingsDev& st, int ppt, const T* T_final,
-                             const uint32_t* n_contrib, const T* dL_dimage, T* grad2d,
+                             const uint32_t* n_contrib, const T* dL_dimage, double* grad2d,
                              uint32_t n_gaussians, hipStream_t stream);
 
 hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, float* grad,

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
     const uint2* __restrict__ ranges, ViewDev v, SettingsDev st, const T* __restrict__ T_final,
     const uint32_t* __restrict__ n_contrib, const T* __restrict__ dL_dimage,
-    T* __restrict__ grad2d, uint32_t n_gauss) {
+    double* __restrict__ grad2d, uint32_t n_gauss) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
@@ -286,62 +286,82 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
       const Staged<T> r = s_rec[j];
-      T v9[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+      // pass 1: which of this lane's pixels blended the Gaussian
+      T dx[PPT], dy[PPT], G[PPT], a_raw[PPT], alpha[PPT];
+      bool use[PPT];
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
-        T dx, dy, G, a_raw, alpha;
-        const bool pass = eval_pair(r, px, py[k], e_min, amin, amax, dx, dy, G, a_raw, alpha);
-        const bool use = pass & (bstart + uint32_t(j) < ncon[k]);
-        any |= use;
-        // computed by every lane, kept only where `use`
-        const T inv_om = fast_rcp(T(1) - alpha);
+        const bool pass =
+            eval_pair(r, px, py[k], e_min, amin, amax, dx[k], dy[k], G[k], a_raw[k], alpha[k]);
+        use[k] = pass & (bstart + uint32_t(j) < ncon[k]);
+        any |= use[k];
+      }
+      if (!__ballot(any)) continue;  // no pixel of the tile blended it
+      // pass 2: per-pixel derivatives, summed over the lane's pixels as
+      // s0..s4 = sum g (dx, dy, dx^2, dx dy, dy^2) with g = a dL/da (the
+      // screen-space mean and conic gradients are linear in these), s5 = sum
+      // dL/da exp(-q/2), s6..s8 = sum a T dL/dC
+      T sv[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        const T inv_om = fast_rcp(T(1) - alpha[k]);
         const T Ti = Tcur[k] * inv_om;  // transmittance in front of this Gaussian
-        const T w = use ? alpha * Ti : T(0);
+        const T w = use[k] ? alpha[k] * Ti : T(0);
         // dC/da = T c - (colour behind) / (1 - a)
         const T gc = tfma(g0[k], r.r, tfma(g1[k], r.g, g2[k] * r.b));
         const T gacc = tfma(g0[k], acc0[k], tfma(g1[k], acc1[k], g2[k] * acc2[k]));
-        // a = o exp(-q/2): da/do = exp(-q/2), da/dq = -a/2; no gradient through the clamp
-        const T dL_da = (use & (a_raw < amax)) ? Ti * gc - gacc * inv_om : T(0);
+        // no gradient through the alpha clamp
+        const T dL_da =
+            (use[k] & (a_raw[k] < amax)) ? inv_om * (Tcur[k] * gc - gacc) : T(0);
         acc0[k] = tfma(r.r, w, acc0[k]);
         acc1[k] = tfma(r.g, w, acc1[k]);
         acc2[k] = tfma(r.b, w, acc2[k]);
-        Tcur[k] = use ? Ti : Tcur[k];
-        // dL/dq = -a/2 dL/da.  With the staged A = k a_c, B = 2 k b_c, C = k c_c
-        // (k = -log2(e)/2): dq/dmean = 2 (a_c dx + b_c dy, b_c dx + c_c dy)
-        //                          = (2 A dx + B dy, B dx + 2 C dy) / k
-        const T gq = T(-0.5) * dL_da * a_raw;
-        const T gqx = gq * dx, gqy = gq * dy;
-        const T gqk = gq * T(1.0 / kHalfLog2e);
-        v9[0] = tfma(gqk, T(2) * r.A * dx + r.B * dy, v9[0]);  // d/d mean2d.x
-        v9[1] = tfma(gqk, r.B * dx + T(2) * r.C * dy, v9[1]);  // d/d mean2d.y
-        v9[2] = tfma(gqx, dx, v9[2]);                          // d/d conic a
-        v9[3] = tfma(T(2) * gqx, dy, v9[3]);                   // d/d conic b
-        v9[4] = tfma(gqy, dy, v9[4]);                          // d/d conic c
-        v9[5] = tfma(dL_da, G, v9[5]);                       // d/d opacity_t
-        v9[6] = tfma(w, g0[k], v9[6]);                       // d/d rgb
-        v9[7] = tfma(w, g1[k], v9[7]);
-        v9[8] = tfma(w, g2[k], v9[8]);
+        Tcur[k] = use[k] ? Ti : Tcur[k];
+        const T ga = dL_da * a_raw[k];
+        const T gx = ga * dx[k], gy = ga * dy[k];
+        sv[0] += gx;
+        sv[1] += gy;
+        sv[2] = tfma(gx, dx[k], sv[2]);
+        sv[3] = tfma(gx, dy[k], sv[3]);
+        sv[4] = tfma(gy, dy[k], sv[4]);
+        sv[5] = tfma(dL_da, G[k], sv[5]);
+        sv[6] = tfma(w, g0[k], sv[6]);
+        sv[7] = tfma(w, g1[k], sv[7]);
+        sv[8] = tfma(w, g2[k], sv[8]);
       }
-      if (__ballot(any)) {
-        wave_sum9_to_lane63(v9);
-        if (lane == 63) {
+      wave_sum9_to_lane63(sv);
+      if (lane == 63) {
+        // a = o exp(-q/2): da/dq = -a/2, dq/dconic = (dx^2, 2 dx dy, dy^2) and, with
+        // the staged A = k a_c, B = 2 k b_c, C = k c_c (k = -log2(e)/2),
+        // dq/dmean = (2 A dx + B dy, B dx + 2 C dy) / k
+        const T hk = T(-0.5 / kHalfLog2e);
+        T v9[9];
+        v9[0] = hk * (T(2) * r.A * sv[0] + r.B * sv[1]);  // d/d mean2d.x
+        v9[1] = hk * (r.B * sv[0] + T(2) * r.C * sv[1]);  // d/d mean2d.y
+        v9[2] = T(-0.5) * sv[2];                          // d/d conic a
+        v9[3] = -sv[3];                                   // d/d conic b
+        v9[4] = T(-0.5) * sv[4];                          // d/d conic c
+        v9[5] = sv[5];                                    // d/d opacity_t
+        v9[6] = sv[6];                                    // d/d rgb
+        v9[7] = sv[7];
+        v9[8] = sv[8];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) {
-            if (NT == 64)
-              s_grad[c][j] += v9[c];
-            else
-              atomicAdd(&s_grad[c][j], v9[c]);
-          }
+        for (int c = 0; c < 9; ++c) {
+          if (NT == 64)
+            s_grad[c][j] += v9[c];
+          else
+            atomicAdd(&s_grad[c][j], v9[c]);
         }
       }
     }
     __syncthreads();
-    // one global atomic per (tile, Gaussian, component)
+    // one global atomic per (tile, Gaussian, component); the sum over tiles is
+    // kept in double because its terms have mixed signs and can cancel
     for (int e = threadIdx.x; e < 9 * nb; e += NT) {
       const int c = e / nb, j = e % nb;
       const T val = s_grad[c][j];
-      if (val != T(0)) atomic_add_nr(&grad2d[long(c) * n_gauss + s_idx[j]], val);
+      if (val != T(0)) atomic_add_nr(&grad2d[long(c) * n_gauss + s_idx[j]], double(val));
     }
     __syncthreads();
     bend = bstart;
@@ -387,7 +407,7 @@ hipError_t raster_fwd_cfg(const Rec<T>* recs, const uint32_t* values, const uint
 template <typename T, int TS, int PPT>
 hipError_t raster_bwd_cfg(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
                           const ViewDev& v, const SettingsDev& st, const T* T_final,
-                          const uint32_t* n_contrib, const T* dL_dimage, T* grad2d,
+                          const uint32_t* n_contrib, const T* dL_dimage, double* grad2d,
                           uint32_t n_gaussians, hipStream_t stream) {
   const int tiles = v.tiles_x * v.tiles_y;
   hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT>), dim3(tiles), dim3(TS * TS / PPT), 0,
@@ -438,7 +458,7 @@ hipError_t launch_raster_fwd(const Rec<T>* recs, const uint32_t* values, const u
 template <typename T>
 hipError_t launch_raster_bwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
                              const ViewDev& v, const SettingsDev& st, int ppt, const T* T_final,
-                             const uint32_t* n_contrib, const T* dL_dimage, T* grad2d,
+                             const uint32_t* n_contrib, const T* dL_dimage, double* grad2d,
                              uint32_t n_gaussians, hipStream_t stream) {
   R4D_RASTER_DISPATCH(raster_bwd_cfg, recs, values, ranges, v, st, T_final, n_contrib, dL_dimage,
                       grad2d, n_gaussians, stream)
@@ -469,7 +489,7 @@ template hipError_t launch_raster_fwd<double>(const Rec<double>*, const uint32_t
                                               double*, uint32_t*, uint32_t*, hipStream_t);
 template hipError_t launch_raster_bwd<float>(const Rec<float>*, const uint32_t*, const uint2*,
                                              const ViewDev&, const SettingsDev&, int,
-                                             const float*, const uint32_t*, const float*, float*,
+                                             const float*, const uint32_t*, const float*, double*,
                                              uint32_t, hipStream_t);
 template hipError_t launch_raster_bwd<double>(const Rec<double>*, const uint32_t*, const uint2*,
                                               const ViewDev&, const SettingsDev&, int,
