@@ -394,8 +394,8 @@ R4D_HD void rotor_bwd(const Fwd<T>& f, const T* G, T* gr) {
 // Full per-Gaussian forward.  `sh` points at coefficient 0 of this Gaussian's
 // [3k] SH column (stride n between rows).
 
-template <typename T>
-R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacity, const T* shp,
+template <typename T, typename ShT>
+R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacity, const ShT* shp,
                          long sh_stride, int deg, const ViewDev& v, const SettingsDev& st,
                          Fwd<T>& f) {
   f.valid = false;
@@ -497,23 +497,31 @@ R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacit
   for (int c = 0; c < 3; ++c) f.raw[c] = T(0.5);
   for (int j = 0; j < k; ++j) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) f.raw[c] += Y[j] * shp[(3 * j + c) * sh_stride];
+    for (int c = 0; c < 3; ++c) f.raw[c] += Y[j] * T(shp[(3 * j + c) * sh_stride]);
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) f.rgb[c] = tmax(f.raw[c], T(0));
   f.valid = true;
 }
 
-// Gradients of one Gaussian.  In: dL/d(mean2 x, y), dL/d(conic a, b, c),
-// dL/d(o_t), dL/d(rgb).  Out (added): mu4[4], ls[4], rot[8], opacity, and the
-// SH column via gsh (stride sh_stride).
-template <typename T>
-R4D_HD void gaussian_bwd(const Fwd<T>& f, const T* shp, long sh_stride, int deg,
+// Gradients of one Gaussian.  In: dL/d(mean2 x, y), the gradient H of L with
+// respect to the symmetric 2x2 matrix Sigma_2D (entries (0,0), (0,1) = (1,0),
+// (1,1); a change dS of the matrix changes L by sum_ij H_ij dS_ij), dL/d(o_t),
+// dL/d(rgb).  Out (added): mu4[4], ls[4], rot[8], opacity, and the SH column via
+// gsh (stride sh_stride).
+//
+// The rasteriser hands over the Sigma_2D gradient rather than the conic one: for
+// a long thin footprint the conic gradient is dominated by a component along the
+// major axis that Sigma_2D = conic^-1 almost ignores, so forming -Q G Q from it
+// in single precision cancels badly; the rasteriser instead sums the well-scaled
+// per-pixel terms (Q d)(Q d)^T directly.
+template <typename T, typename ShT>
+R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int deg,
                          const ViewDev& v, const T g2[9], T gmu4[4], T gls[4], T grot[8],
-                         T& gop, T* gsh) {
+                         T& gop, ShT* gsh) {
   if (!f.valid) return;
   const T gm_x = g2[0], gm_y = g2[1];
-  const T gca = g2[2], gcb = g2[3], gcc = g2[4];
+  const T H00 = g2[2], H01 = g2[3], H11 = g2[4];
   const T go_t = g2[5];
   const T grgb[3] = {g2[6], g2[7], g2[8]};
   T gmu3[3] = {0, 0, 0};
@@ -530,8 +538,8 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const T* shp, long sh_stride, int deg,
       T acc = 0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        gsh[(3 * j + c) * sh_stride] += Y[j] * graw[c];
-        acc += shp[(3 * j + c) * sh_stride] * graw[c];
+        gsh[(3 * j + c) * sh_stride] += ShT(Y[j] * graw[c]);
+        acc += T(shp[(3 * j + c) * sh_stride]) * graw[c];
       }
       gY[j] = acc;
     }
@@ -542,18 +550,6 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const T* shp, long sh_stride, int deg,
     gmu3[1] += (gdy - f.d[1] * dot) * f.inv_nd;
     gmu3[2] += (gdz - f.d[2] * dot) * f.inv_nd;
   }
-  // ---- conic -> Sigma_2D:  dL/dSigma = -Q G Q, G = [[ga, gb/2], [gb/2, gc]]
-  const T qa = f.conic[0], qb = f.conic[1], qc = f.conic[2];
-  const T G00 = gca, G01 = T(0.5) * gcb, G11 = gcc;
-  // Q G
-  const T QG00 = qa * G00 + qb * G01, QG01 = qa * G01 + qb * G11;
-  const T QG10 = qb * G00 + qc * G01, QG11 = qb * G01 + qc * G11;
-  // -(Q G) Q
-  const T gA = -(QG00 * qa + QG01 * qb);
-  const T gBh = -(QG00 * qb + QG01 * qc);   // matrix entry (0,1) gradient
-  const T gC = -(QG10 * qb + QG11 * qc);
-  // symmetric matrix gradient H of Sigma_2D
-  const T H00 = gA, H01 = gBh, H11 = gC;
   // Sigma_2D = Tm S3 Tm^T: dL/dS3 = Tm^T H Tm ; dL/dTm = 2 H Tm S3
   const T* a = f.Tm;
   const T* b = f.Tm + 3;

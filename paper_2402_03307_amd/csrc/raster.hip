@@ -38,8 +38,7 @@ template <> __device__ __forceinline__ double texp2<double>(double x) { return e
 constexpr double kHalfLog2e = -0.72134752044448170368;
 
 // A record as the rasteriser keeps it in LDS: the conic is pre-multiplied by
-// -log2(e)/2 (and the off-diagonal term doubled) so that the Gaussian falloff is
-// one exp2 of a quadratic form: e = A dx^2 + B dx dy + C dy^2 = -q log2(e) / 2.
+// k = -log2(e)/2 so that the Gaussian falloff is one exp2 of a quadratic form.
 template <typename T>
 struct Staged {
   T mx, my, A, B;
@@ -50,21 +49,25 @@ struct Staged {
 template <typename T>
 __device__ __forceinline__ Staged<T> stage(const Rec<T>& r) {
   const T k = T(kHalfLog2e);
-  return Staged<T>{r.mx, r.my, k * r.ca, T(2) * k * r.cb, k * r.cc, r.o, r.r, r.g, r.b,
+  return Staged<T>{r.mx, r.my, k * r.ca, k * r.cb, k * r.cc, r.o, r.r, r.g, r.b,
                    T(0), T(0), T(0)};
 }
 
 // The one place where a (pixel, Gaussian) pair is evaluated; forward and backward
 // call it with identical operands so that they take identical decisions.
-// G = exp(-q/2), a_raw = o G, alpha = min(alpha_max, a_raw).  Evaluated without
-// branches: the result says whether the pair passes the extent test
-// (q <= extent^2, i.e. e >= e_min) and the alpha test.
+// With d = mean2d - pixel centre: u = k Q d (the offset whitened by the conic Q),
+// e = d . u = k q, G = exp2(e) = exp(-q/2), a_raw = o G, alpha = min(alpha_max,
+// a_raw).  Evaluated without branches: the result says whether the pair passes
+// the extent test (q <= extent^2, i.e. e >= e_min) and the alpha test.  The
+// backward builds its screen-space gradients from u.
 template <typename T>
 __device__ __forceinline__ bool eval_pair(const Staged<T>& r, T px, T py, T e_min, T amin, T amax,
-                                          T& dx, T& dy, T& G, T& a_raw, T& alpha) {
-  dx = r.mx - px;
-  dy = r.my - py;
-  const T e = tfma(r.A * dx, dx, tfma(r.B * dx, dy, r.C * dy * dy));
+                                          T& ux, T& uy, T& G, T& a_raw, T& alpha) {
+  const T dx = r.mx - px;
+  const T dy = r.my - py;
+  ux = tfma(r.B, dy, r.A * dx);
+  uy = tfma(r.B, dx, r.C * dy);
+  const T e = tfma(dx, ux, dy * uy);
   G = texp2(e);
   a_raw = r.o * G;
   alpha = a_raw < amax ? a_raw : amax;
@@ -184,8 +187,8 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
         const Staged<T> r = s_rec[j];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-          T dx, dy, G, a_raw, alpha;
-          const bool pass = eval_pair(r, px, py[k], e_min, amin, amax, dx, dy, G, a_raw, alpha);
+          T ux, uy, G, a_raw, alpha;
+          const bool pass = eval_pair(r, px, py[k], e_min, amin, amax, ux, uy, G, a_raw, alpha);
           const T Tn = Tr[k] * (T(1) - alpha);
           if (COUNT) evals[k] += Tr[k] != T(0) ? 1u : 0u;
           const bool blend = pass & (Tn >= tmin);
@@ -287,20 +290,20 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     for (int j = nb - 1; j >= 0; --j) {
       const Staged<T> r = s_rec[j];
       // pass 1: which of this lane's pixels blended the Gaussian
-      T dx[PPT], dy[PPT], G[PPT], a_raw[PPT], alpha[PPT];
+      T ux[PPT], uy[PPT], G[PPT], a_raw[PPT], alpha[PPT];
       bool use[PPT];
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const bool pass =
-            eval_pair(r, px, py[k], e_min, amin, amax, dx[k], dy[k], G[k], a_raw[k], alpha[k]);
+            eval_pair(r, px, py[k], e_min, amin, amax, ux[k], uy[k], G[k], a_raw[k], alpha[k]);
         use[k] = pass & (bstart + uint32_t(j) < ncon[k]);
         any |= use[k];
       }
       if (!__ballot(any)) continue;  // no pixel of the tile blended it
       // pass 2: per-pixel derivatives, summed over the lane's pixels as
-      // s0..s4 = sum g (dx, dy, dx^2, dx dy, dy^2) with g = a dL/da (the
-      // screen-space mean and conic gradients are linear in these), s5 = sum
+      // s0..s4 = sum g (ux, uy, ux^2, ux uy, uy^2) with g = a dL/da (the
+      // screen-space mean and Sigma_2D gradients are linear in these), s5 = sum
       // dL/da exp(-q/2), s6..s8 = sum a T dL/dC
       T sv[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
@@ -319,12 +322,12 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
         acc2[k] = tfma(r.b, w, acc2[k]);
         Tcur[k] = use[k] ? Ti : Tcur[k];
         const T ga = dL_da * a_raw[k];
-        const T gx = ga * dx[k], gy = ga * dy[k];
+        const T gx = ga * ux[k], gy = ga * uy[k];
         sv[0] += gx;
         sv[1] += gy;
-        sv[2] = tfma(gx, dx[k], sv[2]);
-        sv[3] = tfma(gx, dy[k], sv[3]);
-        sv[4] = tfma(gy, dy[k], sv[4]);
+        sv[2] = tfma(gx, ux[k], sv[2]);
+        sv[3] = tfma(gx, uy[k], sv[3]);
+        sv[4] = tfma(gy, uy[k], sv[4]);
         sv[5] = tfma(dL_da, G[k], sv[5]);
         sv[6] = tfma(w, g0[k], sv[6]);
         sv[7] = tfma(w, g1[k], sv[7]);
@@ -332,18 +335,19 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
       }
       wave_sum9_to_lane63(sv);
       if (lane == 63) {
-        // a = o exp(-q/2): da/dq = -a/2, dq/dconic = (dx^2, 2 dx dy, dy^2) and, with
-        // the staged A = k a_c, B = 2 k b_c, C = k c_c (k = -log2(e)/2),
-        // dq/dmean = (2 A dx + B dy, B dx + 2 C dy) / k
-        const T hk = T(-0.5 / kHalfLog2e);
+        // With u = Q d (the staged value is k u): a = o exp(-q/2) gives
+        // dL/dq = -g / 2 per pixel, dq/dmean2d = 2 u, and, since
+        // dq = -u^T dSigma_2D u for Sigma_2D = Q^-1, dL/dSigma_2D = sum g u u^T / 2.
+        const T ik = T(1.0 / kHalfLog2e);
+        const T h = T(0.5 / (kHalfLog2e * kHalfLog2e));
         T v9[9];
-        v9[0] = hk * (T(2) * r.A * sv[0] + r.B * sv[1]);  // d/d mean2d.x
-        v9[1] = hk * (r.B * sv[0] + T(2) * r.C * sv[1]);  // d/d mean2d.y
-        v9[2] = T(-0.5) * sv[2];                          // d/d conic a
-        v9[3] = -sv[3];                                   // d/d conic b
-        v9[4] = T(-0.5) * sv[4];                          // d/d conic c
-        v9[5] = sv[5];                                    // d/d opacity_t
-        v9[6] = sv[6];                                    // d/d rgb
+        v9[0] = -ik * sv[0];  // d/d mean2d.x
+        v9[1] = -ik * sv[1];  // d/d mean2d.y
+        v9[2] = h * sv[2];    // d/d Sigma_2D (0,0)
+        v9[3] = h * sv[3];    // d/d Sigma_2D (0,1), the same for (1,0)
+        v9[4] = h * sv[4];    // d/d Sigma_2D (1,1)
+        v9[5] = sv[5];        // d/d opacity_t
+        v9[6] = sv[6];        // d/d rgb
         v9[7] = sv[7];
         v9[8] = sv[8];
 #pragma unroll
