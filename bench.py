@@ -1,19 +1,33 @@
 """Benchmark: forward frames/s and forward+backward steps/s of the 4D-rotor
-Gaussian render path on one MI355X.
+Gaussian render path on one MI355X, plain and batched.
 
-Workload (default): 500,000 4D Gaussians, SH degree 3, one 1352x1014 render
-at t = 0.5 from (0, 0, -4); a step = forward render + L1 loss gradient against
-a seeded U[0,1] target + backward to all Gaussian parameters.  Inputs are
-seeded synthetic arrays resident in HBM before timing starts.
+Headline workload: 500,000 4D Gaussians, SH degree 3, one 1352x1014 render at
+t = 0.5 from (0, 0, -4); a step = forward render + L1 loss gradient against a
+seeded U[0,1] target + backward to all Gaussian parameters.  The headline value
+is the step rate of the graph mode (the launch sequence captured once in a HIP
+graph and replayed, no host synchronisation); the plain mode (one entry-count
+readback per render) is reported beside it.
 
-Prints one JSON line.  `value` is fwd+bwd steps/s; per-stage kernel times come
-from HIP events the library records on the stream it launches on.
+Batched vs plain: 200,000 Gaussians, 16 renders of mixed resolution, each
+step forward + L1 + backward of all 16 renders, once as 16 plain per-render
+call sequences and once as one graph-mode call over the 16 renders (tile 16,
+and with the autotuned tile size / sort chunking).
+
+Further lines (per_config): 2,000 Gaussians at 128x128 (forward), 300,000
+Gaussians over 30 orbit renders (forward), 3,000,000 Gaussians over 16
+renders (graph-mode forward + backward).
+
+Inputs are seeded synthetic arrays resident in HBM before timing starts.
+Prints one JSON line.  Per-stage kernel times come from HIP events the
+library records on the stream it launches on.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,15 +37,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (256 CU x 2.4 GHz x 256 flop/clk/CU)
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# FP32 FMA issue rate without packed dual-FP32 instructions (this build disables
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.  The published 157.3
+# TFLOP/s counts the packed form.
+FP32_VECTOR_PEAK_TFLOPS = 78.6
 
 # Arithmetic of one evaluated (pixel, Gaussian) pair in the forward compositing
-# loop: offset (2), quadratic form (7), exponent (2: scale + exp), opacity
-# product, clamp, two threshold tests (4), transmittance update (2),
-# weight (1) and colour accumulation (3 fma = 6).  Skipped pairs do less; the
-# count is an upper bound on useful work per evaluated pair.
-FLOPS_PER_PAIR_FWD = 24
+# loop: offset (2), whitened offset (6), exponent (3: form, scale is folded,
+# exp2), opacity product, clamp, two threshold tests (4), transmittance update
+# (2), weight (1) and colour accumulation (3 fma = 6).
+FLOPS_PER_PAIR_FWD = 26
+# Backward, per blended pair: the forward evaluation (14), transmittance
+# recovery (3), colour-behind update and alpha gradient (14), and the nine
+# moment sums (18 with fma = 2).
+FLOPS_PER_PAIR_BWD = 49
 
 
 def parse():
@@ -45,10 +65,12 @@ def parse():
     ap.add_argument("--bwd-ppt", type=int, default=0,
                     help="backward rasteriser pixels per lane (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched and per-config measurements")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
                          "known traffic, to scale hardware byte counters)")
-    ap.add_argument("--cpu-pixels", type=int, nargs=2, default=(16, 64),
+    ap.add_argument("--cpu-pixels", type=int, nargs=2, default=(512, 2048),
                     help="two oracle pixel-sample sizes used to fit fixed + per-pixel cost")
     return ap.parse_args()
 
@@ -79,8 +101,104 @@ def cpu_baseline(g, view, st, pix_counts):
         "sample": (f"FP64 oracle forward+autograd backward, all {g['opacity'].shape[0]} Gaussians "
                    f"preprocessed, {p1} and {p2} sampled pixels composited "
                    f"({t1:.1f} s, {t2:.1f} s); full {Wd}x{H} frame extrapolated linearly "
-                   f"(fixed {fixed:.2f} s + {per_pixel * 1e3:.1f} ms/pixel)"),
+                   f"(fixed {fixed:.2f} s + {per_pixel * 1e3:.2f} ms/pixel)"),
     }
+
+
+def device_params(g, dev):
+    import torch
+    p = {k: torch.as_tensor(g[k]).to(dev).contiguous()
+         for k in ("means", "log_scales", "rotors", "opacity", "sh")}
+    p["sh_degree"] = g["sh_degree"]
+    return p
+
+
+def timed(fn, steps, warmup):
+    """Mean wall time per call of fn over `steps` calls after `warmup`, with the
+    device synchronised on both sides."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+class Stepper:
+    """forward + L1 + backward of a list of renders in one mode."""
+
+    def __init__(self, r4d, rend, params, views, st, targets_flat):
+        import torch
+        self.r4d, self.rend, self.p, self.views, self.st = r4d, rend, params, views, st
+        self.targets = targets_flat
+        self.graph = st.get("mode") == "graph"
+        self.grad = torch.empty_like(targets_flat)
+        self.last = None
+
+    def step(self):
+        imgs, saved = self.rend.forward(self.p, self.views, self.st, save=True, flat=True)
+        _, dl = self.rend.l1_loss_grad_views(imgs, self.targets, self.views, self.grad)
+        self.rend.backward(self.p, self.views, self.st, saved, dl)
+        if self.last is not None and not self.graph:
+            self.last.release()
+        self.last = saved
+
+    def forward(self):
+        self.rend.forward(self.p, self.views, self.st, save=False, flat=True)
+
+    def check(self):
+        if self.last is not None:
+            self.last.check()
+
+
+def per_view_step(r4d, rend, params, views, st, targets):
+    """The plain baseline: one call sequence per render."""
+    saved_all = []
+    grads = []
+
+    def step():
+        for v, tgt in zip(views, targets):
+            imgs, saved = rend.forward(params, [v], st, save=True, flat=True)
+            _, dl = rend.l1_loss_grad(imgs, tgt)
+            grads.append(rend.backward(params, [v], st, saved, dl))
+            saved.release()
+        grads.clear()
+
+    return step
+
+
+def flat_targets(views, dev):
+    import torch
+
+    import workloads as W
+    return torch.cat([torch.as_tensor(W.target_image(int(v["height"]), int(v["width"]))).reshape(-1)
+                      for v in views]).to(dev)
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2402_03307_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    it was taken from the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"kernel sources sha256\[:16\]: (\w+)", text)
+    m_b = re.search(r"hbm bytes per launch: (\d+)", text)
+    if not m_src or not m_b or m_src.group(1) != kernel_source_digest():
+        return None
+    return int(m_b.group(1))
 
 
 def main():
@@ -101,10 +219,8 @@ def main():
     view = views[0]
     H, Wd = int(view["height"]), int(view["width"])
     n = int(g["opacity"].shape[0])
-    params = {k: torch.as_tensor(g[k]).to(dev).contiguous()
-              for k in ("means", "log_scales", "rotors", "opacity", "sh")}
-    params["sh_degree"] = g["sh_degree"]
-    target = torch.as_tensor(W.target_image(H, Wd)).to(dev)
+    params = device_params(g, dev)
+    targets = flat_targets(views, dev)
     rend = r4d.Renderer(dev)
     if args.calibration_copy_mib:
         nbytes = args.calibration_copy_mib << 20
@@ -114,44 +230,27 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def step():
-        imgs, saved = rend.forward(params, views, st, save=True)
-        _, dl = rend.l1_loss_grad(imgs[0], target)
-        rend.backward(params, views, st, saved, [dl])
-        saved.release()
-
-    def fwd():
-        rend.forward(params, views, st, save=False)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    print(f"timed {args.steps} fwd+bwd steps: {step_ms:.3f} ms/step", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        fwd()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fwd()
-    torch.cuda.synchronize()
-    fwd_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    print(f"timed {args.steps} forward renders: {fwd_ms:.3f} ms/frame", file=sys.stderr,
+    # ---- headline: graph mode; plain beside it
+    graph = Stepper(r4d, rend, params, views, dict(st, mode="graph"), targets)
+    plain = Stepper(r4d, rend, params, views, dict(st, mode="per_view"), targets)
+    step_ms = timed(graph.step, args.steps, args.warmup)
+    graph.check()
+    print(f"graph mode: {args.steps} fwd+bwd steps: {step_ms:.3f} ms/step", file=sys.stderr,
           flush=True)
+    fwd_ms = timed(graph.forward, args.steps, args.warmup)
+    plain_step_ms = timed(plain.step, args.steps, args.warmup)
+    plain_fwd_ms = timed(plain.forward, args.steps, args.warmup)
+    print(f"graph fwd {fwd_ms:.3f} ms; plain step {plain_step_ms:.3f} ms, plain fwd "
+          f"{plain_fwd_ms:.3f} ms", file=sys.stderr, flush=True)
 
-    # per-stage kernel times (separate pass: events are recorded around each stage)
+    # ---- per-stage kernel times (plain mode, events around each stage)
     rend.set_timing(True)
     rend.timings(reset=True)
     k_stage = max(3, min(args.steps, 10))
     last_saved = None
     for _ in range(k_stage):
         imgs, saved = rend.forward(params, views, st, save=True)
-        _, dl = rend.l1_loss_grad(imgs[0], target)
+        _, dl = rend.l1_loss_grad(imgs[0], targets.view(3, H, Wd))
         rend.backward(params, views, st, saved, [dl])
         if last_saved is not None:
             last_saved.release()
@@ -169,32 +268,41 @@ def main():
 
     n_vis, D = stats["n_visible"], stats["n_dup"]
     k = (g["sh_degree"] + 1) ** 2
-    # algorithmic bytes per launch of the HBM-bound stages
+    tiles = stats["tiles_x"] * stats["tiles_y"]
+    # algorithmic HBM bytes per launch of the memory-bound stages
     alg_bytes = {
-        # params 68 B/Gaussian + per-Gaussian outputs (rect 8, count 4, key 4, index 4)
+        # params 68 B/Gaussian + per-Gaussian outputs (rect 8, count 4, key 4)
         # + SH (12k B) and record (48 B) of each visible Gaussian
-        "preprocess_fwd": n * (68 + 20) + n_vis * (12 * k + 48),
-        # 4 passes x (read + write of 8 B pairs) over all Gaussians
-        "depth_sort": 4 * n * 16,
-        # 2 passes over D (u32 key, u32 value) pairs, read + write
-        "tile_sort": 2 * D * 16,
-        "emit": D * 8 + n * 16,
-        # params + 9 screen-space gradients read, 17 + 3k gradients written
-        "preprocess_bwd": n * (68 + 12 * k) + n * 36 + n * 4 * (17 + 3 * k),
+        "preprocess_fwd": n * (68 + 16) + n_vis * (12 * k + 48),
+        # 4 passes x (read + write of 8 B pairs; the first reads 4 B keys) + key histogram
+        "depth_sort": 4 * n * 16 - n * 4 + n * 4,
+        "count_scan": n * 4 * 2 + n * 8,
+        # rects + order + offsets read per Gaussian, 8 B per entry written
+        "emit": D * 8 + n * 20,
+        # pass 1: read + write 8 B; last pass: read 8 B, write the 4 B value
+        "tile_sort": D * 16 + D * 12,
+        # tile count grid + ranges
+        "tile_ranges": tiles * (4 * 2 + 8),
+        # params + 9 screen-space gradients (double) read, 17 + 3k gradients written
+        "preprocess_bwd": n * (68 + 12 * k) + n * 72 + n * 4 * (17 + 3 * k),
     }
     dominant = max(stages, key=stages.get)
     dom_ms = stages[dominant]
+    workload = "500k_1352x1014_tile16"
+    traffic = measured_traffic(dominant, workload)
     if dominant in alg_bytes:
         achieved = alg_bytes[dominant] / (dom_ms * 1e-3) / 1e9
         roofline = {"kernel": dominant, "bound": "hbm", "achieved": achieved,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": None}
+                    "traffic": traffic}
     else:
-        pairs = n_eval if dominant == "raster_fwd" else n_contrib
-        achieved = pairs * FLOPS_PER_PAIR_FWD / (dom_ms * 1e-3) / 1e12
+        fwd = dominant == "raster_fwd"
+        pairs = n_eval if fwd else n_contrib
+        flops = pairs * (FLOPS_PER_PAIR_FWD if fwd else FLOPS_PER_PAIR_BWD)
+        achieved = flops / (dom_ms * 1e-3) / 1e12
         roofline = {"kernel": dominant, "bound": "alu", "achieved": achieved,
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                    "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                     "pairs": pairs}
     hbm_stages = {}
     for name, b in alg_bytes.items():
@@ -217,13 +325,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "500k 4D Gaussians, SH degree 3, one 1352x1014 render at t=0.5; "
-                               "step = forward + L1 grad + backward",
+                               "step = forward + L1 grad + backward; graph mode",
                    "n_gaussians": n, "width": Wd, "height": H, "tile_size": args.tile_size,
                    "fwd_pixels_per_thread": args.fwd_ppt or "auto",
-                   "bwd_pixels_per_thread": args.bwd_ppt or "auto",
-                   "plain_or_batched": "plain"},
+                   "bwd_pixels_per_thread": args.bwd_ppt or "auto"},
         "fwd_frames_per_s": 1e3 / fwd_ms,
         "fwd_ms": fwd_ms,
+        "plain": {"steps_per_s": 1e3 / plain_step_ms, "ms_per_step": plain_step_ms,
+                  "fwd_frames_per_s": 1e3 / plain_fwd_ms, "fwd_ms": plain_fwd_ms},
         "n_visible": n_vis,
         "n_dup": D,
         "pairs_evaluated_fwd": n_eval,
@@ -232,9 +341,86 @@ def main():
         "hbm_stages": hbm_stages,
         "roofline": roofline,
     }
+    del graph, plain
+
+    if not args.no_extra:
+        out["batched_vs_plain"] = batched_vs_plain(r4d, rend, dev, args)
+        out["per_config"] = per_config(r4d, rend, dev, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, view, st, tuple(args.cpu_pixels))
     print(json.dumps(out), flush=True)
+
+
+def batched_vs_plain(r4d, rend, dev, args):
+    import torch
+
+    import workloads as W
+    g, views, st = W.scene_200k_batch()
+    params = device_params(g, dev)
+    targets = flat_targets(views, dev)
+    sizes = [3 * int(v["height"]) * int(v["width"]) for v in views]
+    tlist = list(torch.split(targets, sizes))
+    steps = max(3, args.steps // 2)
+    plain_ms = timed(per_view_step(r4d, rend, params, views, dict(st, mode="per_view"), tlist),
+                     steps, 2)
+    res = {"workload": "200k 4D Gaussians, SH 3, 16 renders (random cameras on the radius-4 "
+                       "sphere, t ~ U[0,1], resolutions from {800x800, 1014x1352, 1352x1014, "
+                       "960x540}); step = forward + L1 + backward of all 16",
+           "plain_ms_per_step": plain_ms, "renders": len(views)}
+    for label, ts in (("batched", 16), ("batched_autotuned", 0)):
+        s = Stepper(r4d, rend, params, views, dict(st, mode="graph", tile_size=ts), targets)
+        ms = timed(s.step, steps, 2)
+        s.check()
+        cfg = s.last.config()
+        res[f"{label}_ms_per_step"] = ms
+        res[f"{label}_speedup"] = plain_ms / ms
+        res[f"{label}_tile_size"] = cfg["tile_size"]
+        res[f"{label}_sort_items"] = cfg["sort_items"]
+        res[f"{label}_renders_per_s"] = len(views) * 1e3 / ms
+        del s
+    print(f"batched vs plain: {res}", file=sys.stderr, flush=True)
+    return res
+
+
+def per_config(r4d, rend, dev, args):
+    import torch
+
+    import workloads as W
+    res = {}
+    # 2k Gaussians, 128x128, forward only
+    g, views, st = W.scene_2k()
+    p = device_params(g, dev)
+    ms = timed(lambda: rend.forward(p, views, dict(st, mode="graph"), save=False), args.steps,
+               args.warmup)
+    res["2k_128x128_fwd"] = {"fwd_ms": ms, "frames_per_s": 1e3 / ms, "mode": "graph"}
+    # 300k Gaussians, 30 orbit renders, forward
+    g, views, st = W.scene_300k_orbit()
+    p = device_params(g, dev)
+    steps = max(2, args.steps // 4)
+    ms_plain = timed(lambda: rend.forward(p, views, dict(st, mode="per_view"), save=False,
+                                          flat=True), steps, 1)
+    ms_graph = timed(lambda: rend.forward(p, views, dict(st, mode="graph"), save=False, flat=True),
+                     steps, 1)
+    res["300k_30_orbit_fwd"] = {"plain_ms_per_30": ms_plain, "graph_ms_per_30": ms_graph,
+                                "plain_frames_per_s": 30e3 / ms_plain,
+                                "graph_frames_per_s": 30e3 / ms_graph}
+    del p
+    torch.cuda.empty_cache()
+    print(f"per config (so far): {res}", file=sys.stderr, flush=True)
+    # 3M Gaussians, 16 renders, graph-mode forward + backward
+    g, views, st = W.scene_3m_large()
+    p = device_params(g, dev)
+    targets = flat_targets(views, dev)
+    s = Stepper(r4d, rend, p, views, dict(st, mode="graph"), targets)
+    ms = timed(s.step, 3, 1)
+    s.check()
+    d_total = sum(s.last.stats(v)["n_dup"] for v in range(len(views)))
+    res["3m_16_renders_fwd_bwd"] = {"graph_ms_per_step": ms, "renders_per_s": 16e3 / ms,
+                                    "tile_entries_total": d_total}
+    del s, p
+    torch.cuda.empty_cache()
+    print(f"per config: {res}", file=sys.stderr, flush=True)
+    return res
 
 
 if __name__ == "__main__":

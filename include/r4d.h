@@ -76,7 +76,10 @@ typedef struct {
 
 /* Cut-offs and conventions (values in parentheses are the defaults that
  * r4d_default_settings writes).
- *   tile_size     8, 16 or 32 pixels (16)
+ *   tile_size     8, 16 or 32 pixels, or 0: picked by the autotuner, which times
+ *                 forward + backward of the call's renders at every tile size and
+ *                 tile-sort chunking and keeps the fastest for calls of the same
+ *                 shape (16).  The image does not depend on the tile size.
  *   near_plane    camera-space depth at or below which a Gaussian is dropped (0.2)
  *   time_cull     a Gaussian is dropped if lambda (t - mu_t)^2 > time_cull (16;
  *                 the visibility threshold of Sec. 3.2.2)
@@ -106,7 +109,32 @@ typedef struct {
   float guard_band;
   int32_t fwd_pixels_per_thread;
   int32_t bwd_pixels_per_thread;
+  int32_t mode;        /* R4D_MODE_* (R4D_MODE_PER_VIEW)                          */
+  int32_t sort_items;  /* keys per lane of the tile sort: 0 = automatic (16) or
+                          with tile_size 0 tuned; otherwise 8 or 16               */
 } r4d_settings;
+
+/* How a call with several views is executed.
+ *   R4D_MODE_PER_VIEW  one launch sequence per view; the entry count of each
+ *                      view is read back to size its tile lists exactly (one
+ *                      stream synchronisation per view).
+ *   R4D_MODE_FUSED     all views in one launch sequence (every stage is one
+ *                      launch over all views, rasterisation one persistent
+ *                      launch over the tiles of all views); one synchronisation
+ *                      per call.
+ *   R4D_MODE_GRAPH     the fused sequence captured once in a HIP graph per call
+ *                      shape (views' sizes, Gaussian count, settings, argument
+ *                      pointers) and replayed; no synchronisation.  The tile lists
+ *                      have a fixed capacity (1.25x the entry count of the call
+ *                      that captured the graph, doubled after an overflow); a
+ *                      replay that overflows renders the background only and is
+ *                      reported by r4d_saved_check.  The saved state of a graph
+ *                      forward refers to the graph's buffers: it is valid until the
+ *                      next forward of the same shape (backward returns
+ *                      R4D_ERR_STATE after that).  The backward is captured too.
+ * Images and gradients do not depend on the mode (the last bits of gradients
+ * aside, which are summed with atomics). */
+enum { R4D_MODE_PER_VIEW = 0, R4D_MODE_FUSED = 1, R4D_MODE_GRAPH = 2 };
 
 /* Gradients, same layouts as r4d_gaussians (means [4][n], log_scales [4][n],
  * rotors [8][n], opacity [n], sh [3k][n]); all DEVICE pointers, overwritten. */
@@ -150,17 +178,18 @@ void r4d_default_settings(r4d_settings *s);
 r4d_status r4d_create(r4d_ctx **ctx, int device);
 void r4d_destroy(r4d_ctx *ctx);
 
-/* Forward render of n_views >= 1 views of one Gaussian set.
+/* Forward render of 1 <= n_views <= 64 views of one Gaussian set.
  *   images  DEVICE float, view v at offset sum_{u<v} 3*H_u*W_u, planar [3][H][W]
  *   saved   if non-NULL, receives an opaque handle holding what the backward
  *           pass needs (per view: projected records, sorted tile lists, tile
  *           ranges, final transmittance and last-contributor count per pixel);
  *           release it with r4d_saved_release.  NULL = inference only.
- * The call reads back one integer per view (the duplicate count) and so
- * synchronises the stream once per view.
+ * Synchronisation: see R4D_MODE_*.
  * Errors: R4D_ERR_INVALID_ARG (null pointers, n < 0, bad degree, bad view size,
- * tile_size not 8/16/32), R4D_ERR_CAPACITY (more than 2^31 tile entries in one
- * view), R4D_ERR_OOM, R4D_ERR_HIP. */
+ * unsupported tile size / pixels per lane / mode), R4D_ERR_CAPACITY (a view
+ * with 2^30 or more tile entries, or a call with 2^32 or more), R4D_ERR_OOM,
+ * R4D_ERR_HIP (also: an earlier call's sort found a predecessor that never
+ * published, which cannot happen unless the device misbehaves). */
 r4d_status r4d_render_forward(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
                               int n_views, const r4d_settings *settings, float *images,
                               r4d_saved **saved, void *stream);
@@ -171,8 +200,8 @@ r4d_status r4d_render_forward(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_vi
  *   out         gradients w.r.t. means, log_scales, rotors, opacity and sh,
  *               summed over the views; overwritten (not accumulated).
  * Gradients through the alpha clamp, the rgb clamp at 0 and every cull or skip
- * are zero.  Per-Gaussian sums are accumulated with float atomics, so the
- * last bits can vary from run to run. */
+ * are zero.  Per-Gaussian screen-space sums are accumulated with atomics, so
+ * the last bits can vary from run to run. */
 r4d_status r4d_render_backward(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
                                int n_views, const r4d_settings *settings,
                                const r4d_saved *saved, const float *dL_dimages, r4d_grads *out,
@@ -202,9 +231,30 @@ void r4d_saved_release(r4d_saved *saved);
 r4d_status r4d_l1_loss_grad(r4d_ctx *ctx, const float *image, const float *target, int64_t count,
                             float *dL_dimage, float *loss, void *stream);
 
+/* Gradient of L = sum over views v of mean_v |image - target| (each view's
+ * mean over its own 3*H*W values), for images laid out as in
+ * r4d_render_forward: dL_dimage = sign(image - target) / (3 H_v W_v).  One
+ * launch for all views.  loss: DEVICE float scalar or NULL. */
+r4d_status r4d_l1_loss_grad_views(r4d_ctx *ctx, const float *images, const float *targets,
+                                  const r4d_view *views, int n_views, float *dL_dimages,
+                                  float *loss, void *stream);
+
+/* Waits until the forward call that produced `saved` has finished on the
+ * device and reports what it could not report when it returned:
+ * R4D_ERR_CAPACITY if its tile lists overflowed (graph mode), R4D_ERR_HIP if
+ * its sort timed out waiting for a predecessor, R4D_ERR_STATE if a later
+ * forward of the same graph shape has reused its buffers, R4D_OK otherwise. */
+r4d_status r4d_saved_check(const r4d_saved *saved);
+
+/* The tile size, tile-sort keys per lane and mode the forward call used (the
+ * autotuner's choice when tile_size was 0).  Any pointer may be NULL. */
+r4d_status r4d_saved_config(const r4d_saved *saved, int32_t *tile_size, int32_t *sort_items,
+                            int32_t *mode);
+
 /* Introspection of saved state (tests and the benchmark).
  * r4d_saved_stats writes, for view v: n_visible (Gaussians with at least one
- * tile), n_dup (tile entries D), tiles_x, tiles_y. */
+ * tile), n_dup (tile entries D), tiles_x, tiles_y.  It waits for the forward
+ * call to finish. */
 r4d_status r4d_saved_stats(const r4d_saved *saved, int view, int64_t *n_visible, int64_t *n_dup,
                            int32_t *tiles_x, int32_t *tiles_y);
 
@@ -221,12 +271,14 @@ r4d_status r4d_saved_stats(const r4d_saved *saved, int view, int64_t *n_visible,
  *   R4D_BUF_VALUES    D uint32: Gaussian index of each tile entry, sorted by
  *                     (tile, depth, index)
  *   R4D_BUF_RANGES    tiles_x*tiles_y pairs of uint32 [start, end) into VALUES
+ *                     (of this view)
  *   R4D_BUF_TFINAL    H*W float (double): final transmittance per pixel
  *   R4D_BUF_NCONTRIB  H*W uint32: tile-list entries up to the last contributor
  *   R4D_BUF_NEVAL     H*W uint32: tile-list entries the forward evaluated for the
  *                     pixel (only if timing was enabled for the forward call,
  *                     R4D_ERR_STATE otherwise)
- * `bytes` must equal the buffer size (R4D_ERR_INVALID_ARG otherwise). */
+ * `bytes` must equal the buffer size (R4D_ERR_INVALID_ARG otherwise).  The
+ * call waits for the forward call to finish. */
 enum {
   R4D_BUF_RECORDS = 0,
   R4D_BUF_RECT = 1,
@@ -242,7 +294,7 @@ r4d_status r4d_saved_copy(const r4d_saved *saved, int view, int buffer, void *ds
 
 /* Per-stage timing with HIP events recorded on the call's stream around each
  * kernel launch (measurement aid; off by default, adds no synchronisation to
- * the render calls).  Stages: 0 preprocess_fwd, 1 depth_sort, 2 count_scan,
+ * the render calls; ignored in graph mode).  Stages: 0 preprocess_fwd, 1 depth_sort, 2 count_scan,
  * 3 emit, 4 tile_sort, 5 tile_ranges, 6 raster_fwd, 7 raster_bwd,
  * 8 preprocess_bwd.  r4d_get_timings synchronises on the recorded events and
  * writes, per stage, the summed milliseconds and the number of launches since

@@ -31,17 +31,22 @@ LIB_PATH = os.path.join(_HERE, "libr4d.so")
 
 __all__ = ["render", "Renderer", "R4DError", "default_settings", "LIB_PATH",
            "BUF_RECORDS", "BUF_RECT", "BUF_DEPTHKEY", "BUF_VALUES", "BUF_RANGES",
-           "BUF_TFINAL", "BUF_NCONTRIB", "EXPORTED_SYMBOLS"]
+           "BUF_TFINAL", "BUF_NCONTRIB", "EXPORTED_SYMBOLS", "MODE_PER_VIEW", "MODE_FUSED",
+           "MODE_GRAPH"]
 
 (BUF_RECORDS, BUF_RECT, BUF_DEPTHKEY, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB,
  BUF_NEVAL) = range(8)
 
+# execution modes of a multi-view call (see R4D_MODE_* in include/r4d.h)
+MODE_PER_VIEW, MODE_FUSED, MODE_GRAPH = 0, 1, 2
+_MODE_NAMES = {"per_view": MODE_PER_VIEW, "fused": MODE_FUSED, "graph": MODE_GRAPH}
+
 EXPORTED_SYMBOLS = (
     "r4d_default_settings", "r4d_create", "r4d_destroy", "r4d_render_forward",
     "r4d_render_backward", "r4d_render_forward_f64", "r4d_render_backward_f64",
-    "r4d_saved_release", "r4d_l1_loss_grad", "r4d_saved_stats", "r4d_saved_copy",
-    "r4d_status_string", "r4d_last_error", "r4d_set_timing", "r4d_get_timings",
-    "r4d_stage_name",
+    "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
+    "r4d_saved_copy", "r4d_saved_check", "r4d_saved_config", "r4d_status_string",
+    "r4d_last_error", "r4d_set_timing", "r4d_get_timings", "r4d_stage_name",
 )
 NUM_STAGES = 9
 
@@ -68,7 +73,8 @@ class _Settings(ctypes.Structure):
     _fields_ = [("tile_size", c_i32), ("near_plane", c_f32), ("time_cull", c_f32),
                 ("extent_sigma", c_f32), ("alpha_min", c_f32), ("alpha_max", c_f32),
                 ("T_min", c_f32), ("dilation", c_f32), ("guard_band", c_f32),
-                ("fwd_pixels_per_thread", c_i32), ("bwd_pixels_per_thread", c_i32)]
+                ("fwd_pixels_per_thread", c_i32), ("bwd_pixels_per_thread", c_i32),
+                ("mode", c_i32), ("sort_items", c_i32)]
 
 
 class _Grads(ctypes.Structure):
@@ -99,6 +105,13 @@ def _load():
     lib.r4d_saved_release.restype = None
     lib.r4d_l1_loss_grad.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]
     lib.r4d_l1_loss_grad.restype = ctypes.c_int
+    lib.r4d_l1_loss_grad_views.argtypes = [c_vp, c_vp, c_vp, P(_View), ctypes.c_int, c_vp, c_vp,
+                                           c_vp]
+    lib.r4d_l1_loss_grad_views.restype = ctypes.c_int
+    lib.r4d_saved_check.argtypes = [c_vp]
+    lib.r4d_saved_check.restype = ctypes.c_int
+    lib.r4d_saved_config.argtypes = [c_vp, P(c_i32), P(c_i32), P(c_i32)]
+    lib.r4d_saved_config.restype = ctypes.c_int
     lib.r4d_saved_stats.argtypes = [c_vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_int64),
                                     P(c_i32), P(c_i32)]
     lib.r4d_saved_stats.restype = ctypes.c_int
@@ -134,6 +147,8 @@ def _settings_struct(settings: dict | None) -> _Settings:
     s = _Settings()
     _lib.r4d_default_settings(ctypes.byref(s))
     for k, v in (settings or {}).items():
+        if k == "mode" and isinstance(v, str):
+            v = _MODE_NAMES[v]
         if hasattr(s, k):
             setattr(s, k, type(getattr(s, k))(v))
     return s
@@ -220,6 +235,20 @@ class SavedState:
         except Exception:
             pass
 
+    def check(self):
+        """Waits for the forward call and raises if it overflowed or failed
+        after returning (see r4d_saved_check)."""
+        if self.handle is None:
+            raise R4DError("saved state already released")
+        self.renderer._check(_lib.r4d_saved_check(self.handle), "r4d_saved_check")
+
+    def config(self) -> dict:
+        ts, items, mode = c_i32(), c_i32(), c_i32()
+        self.renderer._check(_lib.r4d_saved_config(self.handle, ctypes.byref(ts),
+                                                   ctypes.byref(items), ctypes.byref(mode)),
+                             "r4d_saved_config")
+        return {"tile_size": ts.value, "sort_items": items.value, "mode": mode.value}
+
     def stats(self, view: int = 0) -> dict:
         if self.handle is None:
             raise R4DError("saved state already released")
@@ -262,6 +291,7 @@ class Renderer:
         if st != 0:
             raise R4DError(f"r4d_create failed: {_lib.r4d_status_string(st).decode()}")
         self.handle = h
+        self._persistent = {}
         _live_renderers.add(self)
 
     def close(self, sync: bool = True):
@@ -282,33 +312,65 @@ class Renderer:
             msg = _lib.r4d_last_error(self.handle).decode()
             raise R4DError(f"{what}: {_lib.r4d_status_string(status).decode()}: {msg}")
 
-    def forward(self, params: dict, views, settings: dict | None = None, save: bool = True):
+    def _buffer(self, key, shape, dtype, persistent: bool):
+        """A fresh tensor, or in graph mode one kept per key (graph replays
+        read and write fixed addresses)."""
+        if not persistent:
+            return torch.empty(shape, dtype=dtype, device=self.device)
+        t = self._persistent.get(key)
+        if t is None or tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+            t = torch.empty(shape, dtype=dtype, device=self.device)
+            self._persistent[key] = t
+        return t
+
+    def forward(self, params: dict, views, settings: dict | None = None, save: bool = True,
+                flat: bool = False):
+        """Renders `views`; returns (list of [3, H, W] images, SavedState or
+        None), or with flat=True the images as one 1-D tensor in the layout of
+        r4d_render_forward.  In graph mode the images live in a buffer that the
+        next graph forward of the same shape overwrites."""
         n, deg, dtype = _check_params(params)
         g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _PARAM_KEYS])
         varr = _views_array(views)
         st = _settings_struct(settings)
+        graph = st.mode == MODE_GRAPH
         sizes = [3 * int(v["height"]) * int(v["width"]) for v in views]
-        flat = torch.empty(sum(sizes), dtype=dtype, device=self.device)
+        out = self._buffer(("img", dtype, tuple(sizes), n) + tuple(params[k].data_ptr()
+                                                               for k in _PARAM_KEYS),
+                           (sum(sizes),), dtype, graph)
         handle = ctypes.c_void_p()
         fn = _lib.r4d_render_forward if dtype == torch.float32 else _lib.r4d_render_forward_f64
-        status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st), _ptr(flat),
+        status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st), _ptr(out),
                     ctypes.byref(handle) if save else None, _stream(self.device))
         self._check(status, "r4d_render_forward")
-        images, off = [], 0
-        for v, s in zip(views, sizes):
-            images.append(flat[off:off + s].view(3, int(v["height"]), int(v["width"])))
-            off += s
         saved = SavedState(self, handle, views, dtype) if save else None
+        if flat:
+            return out, saved
+        images, off = [], 0
+        for v, sz in zip(views, sizes):
+            images.append(out[off:off + sz].view(3, int(v["height"]), int(v["width"])))
+            off += sz
         return images, saved
 
     def backward(self, params: dict, views, settings: dict | None, saved: SavedState,
                  grad_images) -> dict:
+        """Gradients w.r.t. the five parameter tensors.  grad_images: list of
+        [3, H, W] tensors or one flat tensor in the forward's layout.  In graph
+        mode the returned tensors are buffers that the next graph backward of
+        the same shape overwrites."""
         n, deg, dtype = _check_params(params)
         g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _PARAM_KEYS])
         varr = _views_array(views)
         st = _settings_struct(settings)
-        dl = torch.cat([gi.reshape(-1).to(dtype) for gi in grad_images]).contiguous()
-        grads = {k: torch.empty_like(params[k]) for k in _PARAM_KEYS}
+        graph = st.mode == MODE_GRAPH
+        if isinstance(grad_images, torch.Tensor):
+            dl = grad_images.reshape(-1)
+            if dl.dtype != dtype or not dl.is_contiguous():
+                dl = dl.to(dtype).contiguous()
+        else:
+            dl = torch.cat([gi.reshape(-1).to(dtype) for gi in grad_images]).contiguous()
+        grads = {k: self._buffer(("grad", k, dtype, n), tuple(params[k].shape), dtype, graph)
+                 for k in _PARAM_KEYS}
         gs = _Grads(*[_ptr(grads[k]) for k in _PARAM_KEYS])
         fn = _lib.r4d_render_backward if dtype == torch.float32 else _lib.r4d_render_backward_f64
         status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st),
@@ -326,6 +388,21 @@ class Renderer:
         self._check(_lib.r4d_get_timings(self.handle, ms, cnt, int(bool(reset))),
                     "r4d_get_timings")
         return {_lib.r4d_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NUM_STAGES)}
+
+    def l1_loss_grad_views(self, images: torch.Tensor, targets: torch.Tensor, views,
+                           grad: torch.Tensor | None = None):
+        """L = sum over views of each view's mean |image - target| and dL/dimages,
+        for flat tensors in the forward's layout (one launch)."""
+        images = images.contiguous()
+        targets = targets.contiguous()
+        grad = torch.empty_like(images) if grad is None else grad
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        varr = _views_array(views)
+        status = _lib.r4d_l1_loss_grad_views(self.handle, _ptr(images), _ptr(targets), varr,
+                                             len(views), _ptr(grad), _ptr(loss),
+                                             _stream(self.device))
+        self._check(status, "r4d_l1_loss_grad_views")
+        return loss[0], grad
 
     def l1_loss_grad(self, image: torch.Tensor, target: torch.Tensor):
         """(mean |image - target|, its gradient w.r.t. image)."""

@@ -1,20 +1,29 @@
-// C-ABI layer: argument checking, device memory, and the order of kernel
-// launches for one render (forward) and its derivative (backward).
+// C-ABI layer: argument checking, device memory, graph capture, the autotuner
+// and the order of kernel launches.
 //
-// Forward, per view:
-//   preprocess (per Gaussian) -> stable radix sort by depth -> exclusive scan
-//   of tile counts in depth order -> read back the entry count D -> emit tile
-//   entries in depth order -> stable radix sort by tile id -> tile ranges ->
-//   raster.
-// Backward, per view: raster backward (screen-space gradients, atomics) ->
-//   preprocess backward (chain to the parameters).
+// Work is organised in runs.  A run renders a set of views with one launch per
+// stage:
+//   zero-fill -> preprocess (every view) -> depth-key histogram -> segmented
+//   depth sort -> tile counts, ranges and segment table -> scan of the tile
+//   counts in depth order -> emit tile entries -> segmented tile sort ->
+//   persistent rasteriser over the tiles of every view.
+// Backward of a run: zero-fill -> persistent raster backward (screen-space
+// gradients per view and Gaussian) -> preprocess backward (summed over views).
+//
+// Per-view mode makes every view its own run; fused and graph modes make one
+// run of all views.  Outside graph mode the host reads the per-view entry
+// counts back after the preprocess (while the depth sort runs) and sizes the
+// tile lists exactly.  Graph mode captures the run with a fixed capacity.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <set>
 #include <string>
 #include <vector>
@@ -24,10 +33,45 @@
 
 using namespace r4d;
 
+namespace {
+
+struct GraphEntry;
+
+// Sub-buffers of one run, laid out in two device blocks: `fixed` (sizes known
+// before the run) and `entries` (the tile lists, sized by the entry capacity).
+struct RunLayout {
+  // fixed block
+  size_t meta, recs, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp, ranges,
+      T_final, n_contrib, n_eval, zero_begin, totals, dhist, tickets, grids, dstatus, zero_end,
+      fixed_bytes;
+  // entries block
+  size_t tkA, tkB, tvA, tvB, tstatus, entries_bytes;
+};
+
+constexpr int kTicketTile = 4;     // tickets[0..3] depth passes, [4..6] tile passes
+constexpr int kTicketRaster = 7;   // [7] forward rasteriser
+constexpr int kErrorWord = 15;     // tickets[15]: sort look-back error flag
+constexpr int kDepthItems = 4;
+
+// Host-side plan of one run.
+struct Plan {
+  int V = 0;
+  uint32_t n = 0, n_pad = 0;
+  int deg = 0, ts = 16, fppt = 1, bppt = 4, sort_items = 16, mode = 0;
+  std::vector<ViewSlot> slots;
+  uint32_t total_tiles = 0;
+  uint64_t total_pix = 0, grid_cells = 0;
+  int tile_passes = 1;
+  SegTable dseg{};
+  size_t scal = 4;
+  bool count_evals = false;
+};
+
+}  // namespace
+
 struct r4d_ctx {
   int device = 0;
   std::string last_error;
-  // stage timing (measurement aid)
   bool timing = false;
   struct Pending {
     int stage;
@@ -39,24 +83,58 @@ struct r4d_ctx {
   int64_t stage_launches[R4D_NUM_STAGES] = {};
   std::multimap<size_t, void*> free_blocks;  // size class -> block
   std::map<void*, size_t> block_size;        // every block ever allocated
-  uint64_t* host_readback = nullptr;         // pinned, 2 words
-  std::set<r4d_saved*> live_saved;           // saved states not yet released
+  // pinned staging for per-call uploads (ring) and readbacks
+  struct Stage {
+    void* host = nullptr;
+    hipEvent_t done = nullptr;
+  };
+  std::vector<Stage> ring;
+  size_t ring_next = 0;
+  unsigned long long* readback = nullptr;    // pinned, 2 * kMaxViews words
+  hipStream_t capture_stream = nullptr;
+  std::set<r4d_saved*> live_saved;
+  std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
+  std::map<std::string, std::pair<int, int>> tuned;  // shape -> (tile size, sort items)
+  // pinned readback areas of runs with their completion events; an area is
+  // reused once its event has completed
+  struct Pinned {
+    unsigned long long* host = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+  };
+  std::vector<Pinned*> pinned_pool;
 };
 
 namespace {
 
-struct ViewSaved {
-  r4d_view view;
-  int tiles_x = 0, tiles_y = 0, tile_size = 0;
-  uint64_t n_visible = 0, n_dup = 0;
-  void* recs = nullptr;
-  Rect16* rects = nullptr;
-  uint32_t* depth_keys = nullptr;
-  uint32_t* values = nullptr;
-  uint2* ranges = nullptr;
-  void* T_final = nullptr;
-  uint32_t* n_contrib = nullptr;
-  uint32_t* n_eval = nullptr;  // only when timing was enabled
+// Device memory and flags of one executed run.
+struct RunState {
+  Plan plan;
+  RunLayout L{};
+  uint8_t* fixed = nullptr;
+  uint8_t* entries = nullptr;
+  uint64_t capacity = 0;
+  uint32_t* values = nullptr;  // sorted Gaussian indices of the tile entries
+  bool owns_memory = true;     // false for graph runs (buffers live in the entry)
+  // per-view counts (valid after `done`)
+  std::vector<uint64_t> n_visible, n_dup;
+  uint32_t flags[2] = {0, 0};  // overflow, look-back error
+  bool counts_valid = false;
+  // pinned readback of totals + flags, filled at the end of the run
+  r4d_ctx::Pinned* slot = nullptr;
+  unsigned long long* pinned = nullptr;  // [2 * V + 2] (2 * kMaxViews + 2 words)
+  hipEvent_t done = nullptr;
+  size_t image_offset = 0;     // first image element of this run in the call's images
+};
+
+struct GraphEntry {
+  RunState run;
+  hipGraphExec_t fwd = nullptr;
+  hipGraphExec_t bwd = nullptr;
+  std::string bwd_key;
+  uint8_t* bwd_block = nullptr;  // grad2d + ticket of the captured backward
+  uint64_t generation = 0;
+  bool needs_grow = false;
 };
 
 }  // namespace
@@ -65,9 +143,13 @@ struct r4d_saved {
   r4d_ctx* ctx = nullptr;
   bool f64 = false;
   int n = 0, deg = 0;
-  r4d_settings settings;
-  std::vector<ViewSaved> views;
-  std::vector<void*> blocks;
+  r4d_settings settings;        // as resolved (tile size chosen)
+  std::vector<r4d_view> views;
+  std::vector<std::unique_ptr<RunState>> runs;  // owned runs (per-view, fused)
+  GraphEntry* graph = nullptr;  // graph mode
+  uint64_t generation = 0;
+  std::vector<std::pair<int, int>> where;  // view -> (run, index within run)
+  RunState* run_of(int r) const { return graph ? &graph->run : runs[size_t(r)].get(); }
 };
 
 namespace {
@@ -101,7 +183,6 @@ void* ctx_alloc(r4d_ctx* ctx, size_t bytes) {
   void* p = nullptr;
   if (hipMalloc(&p, cls) != hipSuccess) {
     (void)hipGetLastError();
-    // release cached blocks and retry once
     for (auto& kv : ctx->free_blocks) {
       ctx->block_size.erase(kv.second);
       (void)hipFree(kv.second);
@@ -122,48 +203,36 @@ void ctx_free(r4d_ctx* ctx, void* p) {
   if (it != ctx->block_size.end()) ctx->free_blocks.insert({it->second, p});
 }
 
-// Temporary blocks of one call, returned to the cache when the call ends.
-// (Stream order makes the reuse safe: later work on the same stream runs after
-// every kernel already enqueued.)
-struct Scratch {
-  r4d_ctx* ctx;
-  std::vector<void*> blocks;
-  explicit Scratch(r4d_ctx* c) : ctx(c) {}
-  ~Scratch() {
-    for (void* p : blocks) ctx_free(ctx, p);
+void release_run(r4d_ctx* ctx, RunState* r) {
+  if (!r) return;
+  if (r->owns_memory) {
+    ctx_free(ctx, r->fixed);
+    ctx_free(ctx, r->entries);
   }
-  template <typename P>
-  P* get(size_t bytes) {
-    void* p = ctx_alloc(ctx, bytes);
-    if (p) blocks.push_back(p);
-    return static_cast<P*>(p);
-  }
-  void release(void* p) {
-    for (auto& b : blocks)
-      if (b == p) {
-        ctx_free(ctx, p);
-        b = nullptr;
-      }
-  }
-  void keep(void* p) {  // ownership moves elsewhere
-    for (auto& b : blocks)
-      if (b == p) b = nullptr;
-  }
-};
-
-int fwd_ppt(const r4d_settings& s) {
-  return s.fwd_pixels_per_thread ? s.fwd_pixels_per_thread : raster_default_ppt(s.tile_size, false);
+  r->fixed = r->entries = nullptr;
+  if (r->slot) r->slot->busy = false;  // reused once its event has completed
+  r->slot = nullptr;
+  r->pinned = nullptr;
+  r->done = nullptr;
 }
-int bwd_ppt(const r4d_settings& s) {
-  return s.bwd_pixels_per_thread ? s.bwd_pixels_per_thread : raster_default_ppt(s.tile_size, true);
+
+int default_ppt(int tile_size, int requested, bool backward) {
+  return requested ? requested : raster_default_ppt(tile_size, backward);
 }
 
 bool valid_settings(const r4d_settings* s) {
-  return s && (s->tile_size == 8 || s->tile_size == 16 || s->tile_size == 32) &&
-         s->fwd_pixels_per_thread >= 0 && s->bwd_pixels_per_thread >= 0 &&
-         raster_config_supported(s->tile_size, fwd_ppt(*s)) &&
-         raster_config_supported(s->tile_size, bwd_ppt(*s)) &&
-         s->near_plane >= 0.f && s->time_cull >= 0.f && s->extent_sigma > 0.f &&
+  if (!s) return false;
+  if (s->tile_size != 0 && s->tile_size != 8 && s->tile_size != 16 && s->tile_size != 32)
+    return false;
+  if (s->fwd_pixels_per_thread < 0 || s->bwd_pixels_per_thread < 0) return false;
+  if (s->tile_size != 0 &&
+      (!raster_config_supported(s->tile_size, default_ppt(s->tile_size, s->fwd_pixels_per_thread, false)) ||
+       !raster_config_supported(s->tile_size, default_ppt(s->tile_size, s->bwd_pixels_per_thread, true))))
+    return false;
+  if (s->tile_size == 0 && (s->fwd_pixels_per_thread || s->bwd_pixels_per_thread)) return false;
+  if (s->mode < R4D_MODE_PER_VIEW || s->mode > R4D_MODE_GRAPH) return false;
+  if (s->sort_items != 0 && s->sort_items != 8 && s->sort_items != 16) return false;
+  return s->near_plane >= 0.f && s->time_cull >= 0.f && s->extent_sigma > 0.f &&
          s->alpha_min > 0.f && s->alpha_max > s->alpha_min && s->alpha_max < 1.f &&
          s->T_min > 0.f && s->T_min < 1.f && s->dilation >= 0.f && s->guard_band > 0.f;
 }
@@ -219,6 +288,10 @@ int bits_for(uint64_t count) {  // bits needed for ids in [0, count)
   return b;
 }
 
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+uint64_t round_seg(uint64_t x) { return (x + kSegAlign - 1) / kSegAlign * kSegAlign; }
+
 enum Stage {
   kPreprocessFwd = 0,
   kDepthSort = 1,
@@ -231,14 +304,15 @@ enum Stage {
   kPreprocessBwd = 8
 };
 
-// Records a pair of events around the work enqueued between start() and stop().
+// Records a pair of events around the work enqueued between construction and
+// stop() (measurement aid; never inside a graph capture).
 struct StageTimer {
   r4d_ctx* ctx;
   int stage;
   hipStream_t stream;
   hipEvent_t a = nullptr, b = nullptr;
-  StageTimer(r4d_ctx* c, int s, hipStream_t st) : ctx(c), stage(s), stream(st) {
-    if (!ctx->timing) return;
+  StageTimer(r4d_ctx* c, int s, hipStream_t st, bool on) : ctx(c), stage(s), stream(st) {
+    if (!on || !ctx->timing) return;
     if (!ctx->event_pool.empty()) {
       a = ctx->event_pool.back().first;
       b = ctx->event_pool.back().second;
@@ -258,12 +332,6 @@ struct StageTimer {
   ~StageTimer() { stop(); }
 };
 
-#define R4D_TIMED(stage, expr)                 \
-  do {                                         \
-    StageTimer tm_(ctx, (stage), stream);      \
-    R4D_HIP(expr);                             \
-  } while (0)
-
 #define R4D_HIP(expr)                                                                  \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
@@ -271,198 +339,321 @@ struct StageTimer {
       return fail(ctx, R4D_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
   } while (0)
 
-#define R4D_ALLOC(var, type, bytes)                                                    \
-  type* var = scratch.get<type>(bytes);                                                \
-  if (!var) return fail(ctx, R4D_ERR_OOM, "device allocation of %zu bytes failed", (size_t)(bytes))
+#define R4D_TIMED(stage, expr)                      \
+  do {                                              \
+    StageTimer tm_(ctx, (stage), stream, timed);    \
+    R4D_HIP(expr);                                  \
+  } while (0)
 
+std::string view_shape_key(const r4d_view* views, int V) {
+  std::string k;
+  char buf[64];
+  for (int i = 0; i < V; ++i) {
+    snprintf(buf, sizeof(buf), "%dx%d;", views[i].width, views[i].height);
+    k += buf;
+  }
+  return k;
+}
+
+Plan make_plan(const r4d_view* views, int V, uint32_t n, int deg, const r4d_settings& s,
+               size_t scal) {
+  Plan p;
+  p.V = V;
+  p.n = n;
+  p.n_pad = uint32_t(round_seg(n));
+  p.deg = deg;
+  p.ts = s.tile_size;
+  p.fppt = default_ppt(s.tile_size, s.fwd_pixels_per_thread, false);
+  p.bppt = default_ppt(s.tile_size, s.bwd_pixels_per_thread, true);
+  p.sort_items = s.sort_items ? s.sort_items : 16;
+  p.mode = s.mode;
+  p.scal = scal;
+  int bits = 1;
+  for (int i = 0; i < V; ++i) {
+    ViewSlot sl{};
+    sl.v = make_view(views[i], s);
+    sl.tile_base = p.total_tiles;
+    sl.grid_base = uint32_t(p.grid_cells);
+    sl.pix_base = p.total_pix;
+    const uint64_t nt = uint64_t(sl.v.tiles_x) * uint64_t(sl.v.tiles_y);
+    p.total_tiles += uint32_t(nt);
+    p.grid_cells += uint64_t(sl.v.tiles_x + 1) * uint64_t(sl.v.tiles_y + 1);
+    p.total_pix += uint64_t(views[i].width) * uint64_t(views[i].height);
+    bits = std::max(bits, bits_for(nt));
+    p.slots.push_back(sl);
+  }
+  p.tile_passes = (bits + 7) / 8;
+  p.dseg.count = uint32_t(V);
+  p.dseg.overflow = 0;
+  for (int v = 0; v <= V; ++v) p.dseg.start[v] = uint32_t(uint64_t(v) * p.n_pad);
+  for (int v = 0; v < V; ++v) p.dseg.len[v] = n;
+  return p;
+}
+
+RunLayout make_layout(const Plan& p, uint64_t capacity) {
+  RunLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes ? bytes : 1);
+    return o;
+  };
+  const size_t V = size_t(p.V), n = size_t(p.n), np = size_t(p.n_pad);
+  const size_t rec_bytes = 12 * p.scal;
+  L.meta = take(sizeof(ViewSlot) * V + 2 * sizeof(SegTable));
+  L.recs = take(V * n * rec_bytes);
+  L.rects = take(V * n * sizeof(Rect16));
+  L.tiles = take(V * n * 4);
+  L.dkeys = take(V * np * 4);
+  L.kA = take(V * np * 4);
+  L.kB = take(V * np * 4);
+  L.vA = take(V * np * 4);
+  L.vB = take(V * np * 4);
+  L.thist = take(3 * size_t(kMaxViews) * 256 * 4);
+  L.offsets = take((V * np + 1) * 8);
+  L.scan_tmp = take(count_scan_seg_temp_bytes(p.n_pad, p.V));
+  L.ranges = take(size_t(p.total_tiles) * 8);
+  L.T_final = take(size_t(p.total_pix) * p.scal);
+  L.n_contrib = take(size_t(p.total_pix) * 4);
+  L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 4) : 0;
+  L.zero_begin = off;
+  L.totals = take(2 * size_t(kMaxViews) * 8);
+  L.dhist = take(4 * size_t(kMaxViews) * 256 * 4);
+  L.tickets = take(16 * 4);
+  L.grids = take(size_t(p.grid_cells) * 4);
+  L.dstatus = take(4 * size_t(sort_status_words(uint64_t(V) * np, kDepthItems)) * 4);
+  L.zero_end = off;
+  L.fixed_bytes = off;
+  off = 0;
+  const size_t cap = size_t(capacity);
+  L.tkA = take(cap * 4);
+  L.tkB = take(cap * 4);
+  L.tvA = take(cap * 4);
+  L.tvB = take(cap * 4);
+  L.tstatus = take(size_t(p.tile_passes) * sort_status_words(capacity, p.sort_items) * 4);
+  L.entries_bytes = off;
+  return L;
+}
+
+template <typename P>
+P* at(uint8_t* base, size_t off) {
+  return reinterpret_cast<P*>(base + off);
+}
+
+// Copies the run's slot table and depth segment table into device memory
+// through a ring of pinned staging buffers (the copy is stream-ordered; a
+// staging buffer is reused only after its previous copy has completed).
+r4d_status upload_meta(r4d_ctx* ctx, const Plan& p, uint8_t* fixed, const RunLayout& L,
+                       hipStream_t stream) {
+  const size_t bytes = sizeof(ViewSlot) * size_t(p.V) + sizeof(SegTable);
+  r4d_ctx::Stage& s = ctx->ring[ctx->ring_next];
+  ctx->ring_next = (ctx->ring_next + 1) % ctx->ring.size();
+  R4D_HIP(hipEventSynchronize(s.done));
+  std::memcpy(s.host, p.slots.data(), sizeof(ViewSlot) * size_t(p.V));
+  std::memcpy(static_cast<uint8_t*>(s.host) + sizeof(ViewSlot) * size_t(p.V), &p.dseg,
+              sizeof(SegTable));
+  R4D_HIP(hipMemcpyAsync(fixed + L.meta, s.host, bytes, hipMemcpyHostToDevice, stream));
+  R4D_HIP(hipEventRecord(s.done, stream));
+  return R4D_OK;
+}
+
+const ViewSlot* slots_of(uint8_t* fixed, const RunLayout& L) {
+  return at<ViewSlot>(fixed, L.meta);
+}
+SegTable* dseg_of(uint8_t* fixed, const RunLayout& L, int V) {
+  return reinterpret_cast<SegTable*>(fixed + L.meta + sizeof(ViewSlot) * size_t(V));
+}
+SegTable* tseg_of(uint8_t* fixed, const RunLayout& L, int V) {
+  return dseg_of(fixed, L, V) + 1;
+}
+
+// Enqueues the forward of a run.  sized = false: entries block and capacity
+// are already in place (graph capture); sized = true: after the preprocess the
+// per-view totals are read back and the entries block is allocated exactly.
 template <typename T>
-r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int n_views,
-                        const r4d_settings* settings, T* images, r4d_saved** saved_out,
-                        hipStream_t stream) {
-  if (saved_out) *saved_out = nullptr;
-  if (!views || n_views < 1 || !images || !valid_settings(settings))
-    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, images or settings");
-  if (g.n < 0 || g.deg < 0 || g.deg > 3)
-    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid Gaussian count or SH degree");
-  if (g.n > 0 && (!g.means || !g.log_scales || !g.rotors || !g.opacity || !g.sh))
-    return fail(ctx, R4D_ERR_INVALID_ARG, "null Gaussian array");
-  for (int i = 0; i < n_views; ++i)
-    if (!valid_view(views[i])) return fail(ctx, R4D_ERR_INVALID_ARG, "invalid view %d", i);
-  R4D_HIP(hipSetDevice(ctx->device));
-  const SettingsDev st = make_settings(*settings);
-  r4d_saved* saved = nullptr;
-  if (saved_out) {
-    saved = new r4d_saved();
-    saved->ctx = ctx;
-    ctx->live_saved.insert(saved);
-    saved->f64 = sizeof(T) == 8;
-    saved->n = g.n;
-    saved->deg = g.deg;
-    saved->settings = *settings;
-    saved->views.resize(n_views);
+r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* images,
+                           const SettingsDev& st, bool sized, bool timed, hipStream_t stream) {
+  const Plan& p = r.plan;
+  RunLayout& L = r.L;
+  uint8_t* F = r.fixed;
+  const ViewSlot* slots = slots_of(F, L);
+  SegTable* dseg = dseg_of(F, L, p.V);
+  SegTable* tseg = tseg_of(F, L, p.V);
+  auto* totals = at<unsigned long long>(F, L.totals);
+  auto* tickets = at<uint32_t>(F, L.tickets);
+  uint32_t* error = tickets + kErrorWord;
+  R4D_HIP(fill_zero(F + L.zero_begin, L.zero_end - L.zero_begin, stream));
+  const uint32_t* order = nullptr;
+  if (p.n > 0) {
+    R4D_TIMED(kPreprocessFwd,
+              launch_preprocess_fwd<T>(g, slots, p.V, st, p.n_pad, at<Rec<T>>(F, L.recs),
+                                       at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
+                                       at<uint32_t>(F, L.dkeys), totals, at<int>(F, L.grids),
+                                       stream));
   }
-  struct SavedGuard {
-    r4d_saved*& s;
-    bool ok = false;
-    ~SavedGuard() {
-      if (!ok && s) r4d_saved_release(s);
-    }
-  } guard{saved};
-  const uint32_t n = uint32_t(g.n);
-  size_t img_off = 0;
-  for (int vi = 0; vi < n_views; ++vi) {
-    Scratch scratch(ctx);
-    const r4d_view& view = views[vi];
-    const ViewDev vd = make_view(view, *settings);
-    const uint64_t hw = uint64_t(view.width) * view.height;
-    const uint32_t n_tiles = uint32_t(vd.tiles_x) * uint32_t(vd.tiles_y);
-    const size_t nn = n ? n : 1;
-    R4D_ALLOC(recs, Rec<T>, nn * sizeof(Rec<T>));
-    R4D_ALLOC(rects, Rect16, nn * sizeof(Rect16));
-    R4D_ALLOC(tiles, uint32_t, nn * 4);
-    R4D_ALLOC(kA, uint32_t, nn * 4);
-    R4D_ALLOC(kB, uint32_t, nn * 4);
-    R4D_ALLOC(vA, uint32_t, nn * 4);
-    R4D_ALLOC(vB, uint32_t, nn * 4);
-    R4D_ALLOC(totals, unsigned long long, 256);
-    const size_t sort_tmp_bytes = sort_pairs_temp_bytes(n);
-    R4D_ALLOC(sort_tmp, uint8_t, sort_tmp_bytes);
-    R4D_HIP(hipMemsetAsync(totals, 0, 2 * sizeof(unsigned long long), stream));
-    uint32_t* depth_saved = nullptr;
-    if (saved) {
-      depth_saved = scratch.get<uint32_t>(nn * 4);
-      if (!depth_saved) return fail(ctx, R4D_ERR_OOM, "device allocation failed");
-    }
-    uint64_t D = 0, n_vis = 0;
-    uint32_t* order = vA;
-    if (n > 0) {
-      R4D_TIMED(kPreprocessFwd, launch_preprocess_fwd<T>(g, vd, st, recs, rects, tiles, kA, vA,
-                                                         totals, stream));
-      if (depth_saved)
-        R4D_HIP(hipMemcpyAsync(depth_saved, kA, size_t(n) * 4, hipMemcpyDeviceToDevice, stream));
-      R4D_HIP(hipMemcpyAsync(ctx->host_readback, totals, 2 * sizeof(uint64_t),
-                             hipMemcpyDeviceToHost, stream));
-      uint32_t* kk[2] = {kA, kB};
-      uint32_t* vv[2] = {vA, vB};
-      int res = 0;
-      R4D_TIMED(kDepthSort, sort_pairs_u32(kk, vv, n, 32, SortTemp{sort_tmp, sort_tmp_bytes},
-                                           &res, stream));
-      order = vv[res];
-      R4D_HIP(hipStreamSynchronize(stream));
-      n_vis = ctx->host_readback[0];
-      D = ctx->host_readback[1];
-    }
-    if (D >= (uint64_t(1) << 31))
-      return fail(ctx, R4D_ERR_CAPACITY, "view %d has %llu tile entries (limit 2^31)", vi,
-                  (unsigned long long)D);
-    const size_t dd = D ? size_t(D) : 1;
-    R4D_ALLOC(ranges, uint2, size_t(n_tiles) * sizeof(uint2));
-    R4D_ALLOC(T_final, T, hw * sizeof(T));
-    R4D_ALLOC(n_contrib, uint32_t, hw * 4);
-    uint32_t* n_eval = nullptr;
-    if (ctx->timing) {
-      n_eval = scratch.get<uint32_t>(hw * 4);
-      if (!n_eval) return fail(ctx, R4D_ERR_OOM, "device allocation failed");
-    }
-    R4D_ALLOC(tvA, uint32_t, dd * 4);
-    uint32_t* values = tvA;
-    if (D == 0) {
-      R4D_HIP(hipMemsetAsync(ranges, 0, size_t(n_tiles) * sizeof(uint2), stream));
-    } else {
-      // emit (tile, index) pairs in depth order, then sort them stably by tile id
-      R4D_ALLOC(offsets, uint64_t, (nn + 1) * 8);
-      const size_t scan_tmp_bytes = count_scan_temp_bytes(n);
-      R4D_ALLOC(scan_tmp, uint8_t, scan_tmp_bytes);
-      R4D_ALLOC(tkA, uint32_t, dd * 4);
-      R4D_ALLOC(tkB, uint32_t, dd * 4);
-      R4D_ALLOC(tvB, uint32_t, dd * 4);
-      const size_t tsort_bytes = sort_pairs_temp_bytes(uint32_t(D));
-      R4D_ALLOC(tsort_tmp, uint8_t, tsort_bytes);
-      R4D_TIMED(kCountScan, count_scan(order, tiles, uint32_t(n_vis), offsets,
-                                       SortTemp{scan_tmp, scan_tmp_bytes}, stream));
-      R4D_TIMED(kEmit, emit_tile_keys(order, offsets, rects, uint32_t(n_vis), vd.tiles_x, tkA,
-                                      tvA, stream));
-      uint32_t* kk[2] = {tkA, tkB};
-      uint32_t* vv[2] = {tvA, tvB};
-      int res = 0;
-      R4D_TIMED(kTileSort, sort_pairs_u32(kk, vv, uint32_t(D), bits_for(n_tiles),
-                                          SortTemp{tsort_tmp, tsort_bytes}, &res, stream));
-      values = vv[res];
-      R4D_TIMED(kTileRanges, tile_ranges(kk[res], uint32_t(D), n_tiles, ranges, stream));
-    }
-    R4D_TIMED(kRasterFwd, launch_raster_fwd<T>(recs, values, ranges, vd, st, fwd_ppt(*settings),
-                                              images + img_off, T_final, n_contrib, n_eval,
-                                              stream));
-    if (saved) {
-      ViewSaved& vs = saved->views[vi];
-      vs.view = view;
-      vs.tiles_x = vd.tiles_x;
-      vs.tiles_y = vd.tiles_y;
-      vs.tile_size = vd.tile_size;
-      vs.n_visible = n_vis;
-      vs.n_dup = D;
-      vs.recs = recs;
-      vs.rects = rects;
-      vs.depth_keys = depth_saved;
-      vs.values = values;
-      vs.ranges = ranges;
-      vs.T_final = T_final;
-      vs.n_contrib = n_contrib;
-      vs.n_eval = n_eval;
-      for (void* p : {(void*)recs, (void*)rects, (void*)depth_saved, (void*)values,
-                      (void*)ranges, (void*)T_final, (void*)n_contrib, (void*)n_eval}) {
-        if (!p) continue;
-        scratch.keep(p);
-        saved->blocks.push_back(p);
-      }
-    }
-    img_off += 3 * hw;
+  hipEvent_t totals_ready = nullptr;
+  if (sized) {
+    R4D_HIP(hipMemcpyAsync(ctx->readback, totals, 2 * size_t(p.V) * 8, hipMemcpyDeviceToHost,
+                           stream));
+    totals_ready = r.done;
+    R4D_HIP(hipEventRecord(totals_ready, stream));
   }
-  guard.ok = true;
-  if (saved_out) *saved_out = saved;
+  if (p.n > 0) {
+    StageTimer tm(ctx, kDepthSort, stream, timed);
+    R4D_HIP(radix_histogram(at<uint32_t>(F, L.dkeys), dseg, p.V, p.n, 4, at<uint32_t>(F, L.dhist),
+                            stream));
+    uint32_t* kb[2] = {at<uint32_t>(F, L.kB), at<uint32_t>(F, L.kA)};
+    uint32_t* vb[2] = {at<uint32_t>(F, L.vB), at<uint32_t>(F, L.vA)};
+    int res = 0;
+    R4D_HIP(onesweep_sort(at<uint32_t>(F, L.dkeys), nullptr, kb, vb, dseg,
+                          uint64_t(p.V) * p.n_pad, 4, kDepthItems, at<uint32_t>(F, L.dhist),
+                          at<uint32_t>(F, L.dstatus), tickets, error, false, &res, stream));
+    order = vb[res];
+  }
+  if (sized) {
+    R4D_HIP(hipEventSynchronize(totals_ready));
+    uint64_t cap = 0;
+    for (int v = 0; v < p.V; ++v) {
+      const uint64_t d = ctx->readback[2 * v + 1];
+      if (d >= (uint64_t(1) << 30))
+        return fail(ctx, R4D_ERR_CAPACITY, "view %d has %llu tile entries (limit 2^30)", v,
+                    (unsigned long long)d);
+      cap += round_seg(d);
+    }
+    if (cap >= (uint64_t(1) << 32))
+      return fail(ctx, R4D_ERR_CAPACITY, "%llu tile entries in one call (limit 2^32)",
+                  (unsigned long long)cap);
+    r.capacity = cap;
+    const RunLayout L2 = make_layout(p, cap);
+    L.tkA = L2.tkA;
+    L.tkB = L2.tkB;
+    L.tvA = L2.tvA;
+    L.tvB = L2.tvB;
+    L.tstatus = L2.tstatus;
+    L.entries_bytes = L2.entries_bytes;
+    r.entries = static_cast<uint8_t*>(ctx_alloc(ctx, L.entries_bytes));
+    if (!r.entries)
+      return fail(ctx, R4D_ERR_OOM, "device allocation of %zu bytes failed", L.entries_bytes);
+  }
+  uint8_t* E = r.entries;
+  auto* ranges = at<uint2>(F, L.ranges);
+  R4D_TIMED(kTileRanges, tile_counts(slots, p.V, at<int>(F, L.grids), totals, r.capacity, ranges,
+                                     at<uint32_t>(F, L.thist), tseg, stream));
+  uint32_t* values = at<uint32_t>(E, L.tvA);
+  if (p.n > 0) {
+    auto* offsets = at<uint64_t>(F, L.offsets);
+    R4D_TIMED(kCountScan, count_scan_seg(order, at<uint32_t>(F, L.tiles), p.n, p.n_pad, p.V,
+                                         offsets, F + L.scan_tmp, stream));
+    R4D_HIP(fill_zero(E + L.tstatus, L.entries_bytes - L.tstatus, stream));
+    R4D_TIMED(kEmit, emit_tile_keys_seg(order, offsets, at<Rect16>(F, L.rects), slots, tseg, p.n,
+                                        p.n_pad, p.V, at<uint32_t>(E, L.tkA),
+                                        at<uint32_t>(E, L.tvA), stream));
+    uint32_t* kb[2] = {at<uint32_t>(E, L.tkB), at<uint32_t>(E, L.tkA)};
+    uint32_t* vb[2] = {at<uint32_t>(E, L.tvB), at<uint32_t>(E, L.tvA)};
+    int res = 0;
+    R4D_TIMED(kTileSort, onesweep_sort(at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA), kb, vb,
+                                       tseg, r.capacity, p.tile_passes, p.sort_items,
+                                       at<uint32_t>(F, L.thist), at<uint32_t>(E, L.tstatus),
+                                       tickets + kTicketTile, error, false, &res, stream));
+    values = vb[res];
+  }
+  r.values = values;
+  R4D_TIMED(kRasterFwd,
+            launch_raster_fwd<T>(at<Rec<T>>(F, L.recs), p.n, values, ranges, slots, p.V,
+                                 p.total_tiles, p.ts, st, p.fppt, images, at<T>(F, L.T_final),
+                                 at<uint32_t>(F, L.n_contrib),
+                                 p.count_evals ? at<uint32_t>(F, L.n_eval) : nullptr,
+                                 tickets + kTicketRaster, stream));
+  return R4D_OK;
+}
+
+// Copies totals and flags to the run's pinned area and records its `done`
+// event (outside any capture).
+r4d_status finish_run(r4d_ctx* ctx, RunState& r, hipStream_t stream) {
+  const Plan& p = r.plan;
+  R4D_HIP(hipMemcpyAsync(r.pinned, r.fixed + r.L.totals, 2 * size_t(p.V) * 8,
+                         hipMemcpyDeviceToHost, stream));
+  // overflow flag (SegTable.overflow) and look-back error word
+  R4D_HIP(hipMemcpyAsync(reinterpret_cast<uint32_t*>(r.pinned + 2 * p.V),
+                         &tseg_of(r.fixed, r.L, p.V)->overflow, 4, hipMemcpyDeviceToHost, stream));
+  R4D_HIP(hipMemcpyAsync(reinterpret_cast<uint32_t*>(r.pinned + 2 * p.V) + 1,
+                         at<uint32_t>(r.fixed, r.L.tickets) + kErrorWord, 4,
+                         hipMemcpyDeviceToHost, stream));
+  R4D_HIP(hipEventRecord(r.done, stream));
+  r.counts_valid = false;
+  return R4D_OK;
+}
+
+r4d_status wait_run(r4d_ctx* ctx, RunState& r) {
+  if (r.counts_valid) return R4D_OK;
+  R4D_HIP(hipEventSynchronize(r.done));
+  const int V = r.plan.V;
+  r.n_visible.assign(size_t(V), 0);
+  r.n_dup.assign(size_t(V), 0);
+  for (int v = 0; v < V; ++v) {
+    r.n_visible[size_t(v)] = r.pinned[2 * v];
+    r.n_dup[size_t(v)] = r.pinned[2 * v + 1];
+  }
+  const uint32_t* fl = reinterpret_cast<const uint32_t*>(r.pinned + 2 * V);
+  r.flags[0] = fl[0];
+  r.flags[1] = fl[1];
+  r.counts_valid = true;
+  return R4D_OK;
+}
+
+r4d_status init_run(r4d_ctx* ctx, RunState& r, const Plan& p) {
+  r.plan = p;
+  r4d_ctx::Pinned* slot = nullptr;
+  for (r4d_ctx::Pinned* q : ctx->pinned_pool) {
+    if (q->busy) continue;
+    const hipError_t e = hipEventQuery(q->done);
+    if (e == hipSuccess) {
+      slot = q;
+      break;
+    }
+    (void)hipGetLastError();
+  }
+  if (!slot) {
+    auto q = std::make_unique<r4d_ctx::Pinned>();
+    R4D_HIP(hipHostMalloc(reinterpret_cast<void**>(&q->host), (2 * size_t(kMaxViews) + 2) * 8,
+                          hipHostMallocDefault));
+    const hipError_t e = hipEventCreateWithFlags(&q->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipHostFree(q->host);
+      return fail(ctx, R4D_ERR_HIP, "event creation failed: %s", hipGetErrorString(e));
+    }
+    slot = q.release();
+    ctx->pinned_pool.push_back(slot);
+  }
+  slot->busy = true;
+  r.slot = slot;
+  r.pinned = slot->host;
+  r.done = slot->done;
   return R4D_OK;
 }
 
 template <typename T>
-r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
-                         int n_views, const r4d_settings* settings, const r4d_saved* saved,
-                         const T* dL, const GradPtrs<T>& out, hipStream_t stream) {
-  if (!views || n_views < 1 || !dL || !valid_settings(settings) || !saved)
-    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, gradients, settings or saved state");
-  if (g.n > 0 && (!g.means || !g.log_scales || !g.rotors || !g.opacity || !g.sh ||
-                  !out.means || !out.log_scales || !out.rotors || !out.opacity || !out.sh))
-    return fail(ctx, R4D_ERR_INVALID_ARG, "null Gaussian or gradient array");
-  if (saved->ctx != ctx || saved->f64 != (sizeof(T) == 8) || saved->n != g.n ||
-      saved->deg != g.deg || int(saved->views.size()) != n_views ||
-      saved->settings.tile_size != settings->tile_size)
-    return fail(ctx, R4D_ERR_STATE, "saved state does not match this backward call");
-  for (int i = 0; i < n_views; ++i) {
-    const r4d_view& a = saved->views[i].view;
-    if (a.width != views[i].width || a.height != views[i].height || a.t != views[i].t ||
-        std::memcmp(a.world_to_cam, views[i].world_to_cam, sizeof(a.world_to_cam)) != 0)
-      return fail(ctx, R4D_ERR_STATE, "view %d differs from the forward call", i);
-  }
-  R4D_HIP(hipSetDevice(ctx->device));
-  if (g.n == 0) return R4D_OK;
-  const SettingsDev st = make_settings(*settings);
-  Scratch scratch(ctx);
-  const size_t n = size_t(g.n);
-  R4D_ALLOC(grad2d, double, 9 * n * sizeof(double));
-  size_t img_off = 0;
-  for (int vi = 0; vi < n_views; ++vi) {
-    const ViewSaved& vs = saved->views[vi];
-    const ViewDev vd = make_view(views[vi], *settings);
-    const uint64_t hw = uint64_t(views[vi].width) * views[vi].height;
-    R4D_HIP(hipMemsetAsync(grad2d, 0, 9 * n * sizeof(double), stream));
-    if (vs.n_dup > 0)
-      R4D_TIMED(kRasterBwd, launch_raster_bwd<T>(static_cast<const Rec<T>*>(vs.recs), vs.values,
-                                                vs.ranges, vd, st, bwd_ppt(*settings),
-                                                static_cast<const T*>(vs.T_final), vs.n_contrib,
-                                                dL + img_off, grad2d, uint32_t(n), stream));
-    R4D_TIMED(kPreprocessBwd, launch_preprocess_bwd<T>(g, vd, st, grad2d, out, vi > 0, stream));
-    img_off += 3 * hw;
-  }
+r4d_status enqueue_backward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, const T* dL,
+                            uint8_t* bwd_block, const SettingsDev& st, const GradPtrs<T>& out,
+                            bool timed, hipStream_t stream) {
+  const Plan& p = r.plan;
+  uint8_t* F = r.fixed;
+  const size_t g2_bytes = size_t(p.V) * 9 * size_t(p.n) * 8;
+  auto* grad2d = reinterpret_cast<double*>(bwd_block);
+  auto* ticket = reinterpret_cast<uint32_t*>(bwd_block + align256(g2_bytes));
+  R4D_HIP(fill_zero(bwd_block, align256(g2_bytes) + 256, stream));
+  R4D_TIMED(kRasterBwd,
+            launch_raster_bwd<T>(at<Rec<T>>(F, r.L.recs), p.n, r.values, at<uint2>(F, r.L.ranges),
+                                 slots_of(F, r.L), p.V, p.total_tiles, p.ts, st, p.bppt,
+                                 at<T>(F, r.L.T_final), at<uint32_t>(F, r.L.n_contrib), dL,
+                                 grad2d, ticket, stream));
+  R4D_TIMED(kPreprocessBwd,
+            launch_preprocess_bwd<T>(g, slots_of(F, r.L), p.V, st, grad2d, out, stream));
   return R4D_OK;
+}
+
+size_t bwd_block_bytes(const Plan& p) {
+  return align256(size_t(p.V) * 9 * size_t(p.n) * 8) + 256;
 }
 
 GaussPtrs<float> gauss_of(const r4d_gaussians* g) {
@@ -472,6 +663,403 @@ GaussPtrs<float> gauss_of(const r4d_gaussians* g) {
 GaussPtrs<double> gauss_of(const r4d_gaussians_f64* g) {
   return GaussPtrs<double>{g->n, g->sh_degree, g->means, g->log_scales, g->rotors, g->opacity,
                            g->sh};
+}
+
+template <typename T>
+r4d_status check_gaussians(r4d_ctx* ctx, const GaussPtrs<T>& g) {
+  if (g.n < 0 || g.deg < 0 || g.deg > 3)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid Gaussian count or SH degree");
+  if (g.n > 0 && (!g.means || !g.log_scales || !g.rotors || !g.opacity || !g.sh))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "null Gaussian array");
+  return R4D_OK;
+}
+
+// ---- plain (per-view / fused) forward: allocates, runs sized, records done
+template <typename T>
+r4d_status run_sized(r4d_ctx* ctx, const GaussPtrs<T>& g, const Plan& p, T* images,
+                     const SettingsDev& st, bool timed, hipStream_t stream,
+                     std::unique_ptr<RunState>& out) {
+  auto r = std::make_unique<RunState>();
+  struct Guard {
+    r4d_ctx* ctx;
+    RunState* r;
+    bool ok = false;
+    ~Guard() {
+      if (!ok) release_run(ctx, r);
+    }
+  } guard{ctx, r.get()};
+  r4d_status s = init_run(ctx, *r, p);
+  if (s != R4D_OK) return s;
+  r->L = make_layout(p, 0);
+  r->fixed = static_cast<uint8_t*>(ctx_alloc(ctx, r->L.fixed_bytes));
+  if (!r->fixed)
+    return fail(ctx, R4D_ERR_OOM, "device allocation of %zu bytes failed", r->L.fixed_bytes);
+  if ((s = upload_meta(ctx, p, r->fixed, r->L, stream)) != R4D_OK) return s;
+  if ((s = enqueue_forward<T>(ctx, g, *r, images, st, true, timed, stream)) != R4D_OK) return s;
+  if ((s = finish_run(ctx, *r, stream)) != R4D_OK) return s;
+  guard.ok = true;
+  out = std::move(r);
+  return R4D_OK;
+}
+
+template <typename T>
+std::string fwd_graph_key(const GaussPtrs<T>& g, const void* images, const r4d_view* views,
+                          int V, const r4d_settings& s) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%zu|%d|%d|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%a|%a|%a|%a|%a|%a|%a|",
+           sizeof(T), g.n, g.deg, (const void*)g.means, (const void*)g.log_scales,
+           (const void*)g.rotors, (const void*)g.opacity, (const void*)g.sh, images, s.tile_size,
+           s.fwd_pixels_per_thread, s.bwd_pixels_per_thread, s.sort_items, s.near_plane,
+           s.time_cull, s.extent_sigma, s.alpha_min, s.alpha_max, s.T_min, s.dilation,
+           s.guard_band);
+  return std::string(buf) + view_shape_key(views, V);
+}
+
+// ---- graph forward
+template <typename T>
+r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int V,
+                     const r4d_settings& s, T* images, const SettingsDev& st, hipStream_t stream,
+                     GraphEntry** entry_out) {
+  const std::string key = fwd_graph_key(g, images, views, V, s);
+  auto it = ctx->graphs.find(key);
+  GraphEntry* e = it == ctx->graphs.end() ? nullptr : it->second.get();
+  const Plan p = make_plan(views, V, uint32_t(g.n), g.deg, s, sizeof(T));
+  if (e && e->run.done) {
+    // an overflow of an earlier replay grows the capacity (checked without waiting)
+    if (hipEventQuery(e->run.done) == hipSuccess) {
+      const uint32_t* fl = reinterpret_cast<const uint32_t*>(e->run.pinned + 2 * V);
+      if (fl[0]) e->needs_grow = true;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  if (!e || e->needs_grow) {
+    uint64_t cap = 0;
+    if (e) {
+      // the overflowed replay still counted every view's entries
+      uint64_t needed = 0;
+      for (int v = 0; v < V; ++v) needed += round_seg(e->run.pinned[2 * v + 1]);
+      cap = std::max(e->run.capacity * 2, needed + needed / 4 + uint64_t(V) * kSegAlign);
+      R4D_HIP(hipStreamSynchronize(stream));
+      if (e->fwd) (void)hipGraphExecDestroy(e->fwd);
+      if (e->bwd) (void)hipGraphExecDestroy(e->bwd);
+      e->fwd = e->bwd = nullptr;
+      e->bwd_key.clear();
+      ctx_free(ctx, e->run.entries);
+      ctx_free(ctx, e->run.fixed);
+      ctx_free(ctx, e->bwd_block);
+      e->run.fixed = e->run.entries = e->bwd_block = nullptr;
+    } else {
+      // size from one exact (fused) run
+      std::unique_ptr<RunState> probe;
+      r4d_status st_ = run_sized<T>(ctx, g, p, images, st, false, stream, probe);
+      if (st_ != R4D_OK) return st_;
+      cap = probe->capacity + probe->capacity / 4 + uint64_t(V) * kSegAlign;
+      R4D_HIP(hipEventSynchronize(probe->done));
+      release_run(ctx, probe.get());
+      auto ne = std::make_unique<GraphEntry>();
+      e = ne.get();
+      ctx->graphs[key] = std::move(ne);
+      r4d_status s2 = init_run(ctx, e->run, p);
+      if (s2 != R4D_OK) return s2;
+      e->run.owns_memory = false;
+    }
+    if (cap >= (uint64_t(1) << 32)) cap = (uint64_t(1) << 32) - kSegAlign;
+    e->needs_grow = false;
+    e->run.plan = p;
+    e->run.capacity = cap;
+    e->run.L = make_layout(p, cap);
+    e->run.fixed = static_cast<uint8_t*>(ctx_alloc(ctx, e->run.L.fixed_bytes));
+    e->run.entries = static_cast<uint8_t*>(ctx_alloc(ctx, e->run.L.entries_bytes));
+    if (!e->run.fixed || !e->run.entries)
+      return fail(ctx, R4D_ERR_OOM, "graph buffers of %zu + %zu bytes", e->run.L.fixed_bytes,
+                  e->run.L.entries_bytes);
+    // capture on the context's own stream (the caller's may be the null stream)
+    hipStream_t cs = ctx->capture_stream;
+    R4D_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    r4d_status cst = enqueue_forward<T>(ctx, g, e->run, images, st, false, false, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t end = hipStreamEndCapture(cs, &graph);
+    if (cst != R4D_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cst;
+    }
+    R4D_HIP(end);
+    const hipError_t inst = hipGraphInstantiate(&e->fwd, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    R4D_HIP(inst);
+  }
+  e->run.plan = p;  // camera and time of this call (uploaded below)
+  r4d_status s3 = upload_meta(ctx, p, e->run.fixed, e->run.L, stream);
+  if (s3 != R4D_OK) return s3;
+  R4D_HIP(hipGraphLaunch(e->fwd, stream));
+  e->generation += 1;
+  if ((s3 = finish_run(ctx, e->run, stream)) != R4D_OK) return s3;
+  // the sorted values sit where the captured sort left them
+  *entry_out = e;
+  return R4D_OK;
+}
+
+// ---- autotuner: forward + backward of the call's renders (fused), each
+// candidate (tile size, tile-sort keys per lane) timed twice after a warm-up.
+template <typename T>
+r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int V,
+                    const r4d_settings& base, T* images, hipStream_t stream, int* ts_out,
+                    int* items_out) {
+  const std::string key = std::to_string(sizeof(T)) + "|" + std::to_string(g.n) + "|" +
+                          std::to_string(g.deg) + "|" + std::to_string(base.mode) + "|" +
+                          view_shape_key(views, V);
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) {
+    *ts_out = it->second.first;
+    *items_out = it->second.second;
+    return R4D_OK;
+  }
+  const SettingsDev st = make_settings(base);
+  uint64_t pix = 0;
+  for (int v = 0; v < V; ++v) pix += uint64_t(views[v].width) * uint64_t(views[v].height);
+  // a unit image gradient and scratch parameter gradients
+  const size_t k3 = 3 * size_t((g.deg + 1) * (g.deg + 1));
+  const size_t n = size_t(std::max(g.n, 1));
+  T* dl = static_cast<T*>(ctx_alloc(ctx, 3 * pix * sizeof(T)));
+  T* gbuf = static_cast<T*>(ctx_alloc(ctx, (17 + k3) * n * sizeof(T)));
+  if (!dl || !gbuf) {
+    ctx_free(ctx, dl);
+    ctx_free(ctx, gbuf);
+    return fail(ctx, R4D_ERR_OOM, "autotuner buffers");
+  }
+  R4D_HIP(fill_const(dl, 3 * pix, 1e-3, sizeof(T) == 8, stream));
+  const GradPtrs<T> out{gbuf, gbuf + 4 * n, gbuf + 8 * n, gbuf + 16 * n, gbuf + 17 * n};
+  hipEvent_t e0, e1;
+  R4D_HIP(hipEventCreate(&e0));
+  R4D_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_ts = 16, best_items = 16;
+  r4d_status result = R4D_OK;
+  for (int ts : {8, 16, 32}) {
+    for (int items : {8, 16}) {
+      r4d_settings s = base;
+      s.tile_size = ts;
+      s.sort_items = items;
+      s.fwd_pixels_per_thread = s.bwd_pixels_per_thread = 0;
+      const Plan p = make_plan(views, V, uint32_t(g.n), g.deg, s, sizeof(T));
+      float total = 0.f;
+      for (int rep = 0; rep < 3 && result == R4D_OK; ++rep) {
+        if (rep == 1) {
+          if (hipEventRecord(e0, stream) != hipSuccess) result = R4D_ERR_HIP;
+        }
+        std::unique_ptr<RunState> r;
+        result = run_sized<T>(ctx, g, p, images, st, false, stream, r);
+        if (result != R4D_OK) break;
+        uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(p)));
+        if (!bb) {
+          release_run(ctx, r.get());
+          result = fail(ctx, R4D_ERR_OOM, "autotuner buffers");
+          break;
+        }
+        result = enqueue_backward<T>(ctx, g, *r, dl, bb, st, out, false, stream);
+        (void)hipStreamSynchronize(stream);
+        ctx_free(ctx, bb);
+        release_run(ctx, r.get());
+      }
+      if (result != R4D_OK) break;
+      if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&total, e0, e1) != hipSuccess) {
+        result = fail(ctx, R4D_ERR_HIP, "autotuner timing failed");
+        break;
+      }
+      if (total < best) {
+        best = total;
+        best_ts = ts;
+        best_items = items;
+      }
+    }
+    if (result != R4D_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx_free(ctx, dl);
+  ctx_free(ctx, gbuf);
+  if (result != R4D_OK) return result;
+  ctx->tuned[key] = {best_ts, best_items};
+  *ts_out = best_ts;
+  *items_out = best_items;
+  return R4D_OK;
+}
+
+template <typename T>
+r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int n_views,
+                        const r4d_settings* settings, T* images, r4d_saved** saved_out,
+                        hipStream_t stream) {
+  if (saved_out) *saved_out = nullptr;
+  if (!views || n_views < 1 || n_views > kMaxViews || !images || !valid_settings(settings))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, images or settings");
+  r4d_status s = check_gaussians(ctx, g);
+  if (s != R4D_OK) return s;
+  for (int i = 0; i < n_views; ++i)
+    if (!valid_view(views[i])) return fail(ctx, R4D_ERR_INVALID_ARG, "invalid view %d", i);
+  if (uint64_t(round_seg(uint64_t(g.n))) * uint64_t(n_views) >= (uint64_t(1) << 32))
+    return fail(ctx, R4D_ERR_CAPACITY, "%d views of %d Gaussians exceed 2^32 sort slots", n_views,
+                g.n);
+  R4D_HIP(hipSetDevice(ctx->device));
+  r4d_settings rs = *settings;
+  if (rs.tile_size == 0) {
+    int ts = 16, items = 16;
+    if ((s = autotune<T>(ctx, g, views, n_views, rs, images, stream, &ts, &items)) != R4D_OK)
+      return s;
+    rs.tile_size = ts;
+    rs.sort_items = items;
+  }
+  if (rs.sort_items == 0) rs.sort_items = 16;
+  const SettingsDev st = make_settings(rs);
+  auto saved = std::make_unique<r4d_saved>();
+  saved->ctx = ctx;
+  saved->f64 = sizeof(T) == 8;
+  saved->n = g.n;
+  saved->deg = g.deg;
+  saved->settings = rs;
+  saved->views.assign(views, views + n_views);
+  const bool timed = ctx->timing && rs.mode != R4D_MODE_GRAPH;
+  if (rs.mode == R4D_MODE_GRAPH) {
+    GraphEntry* e = nullptr;
+    if ((s = run_graph<T>(ctx, g, views, n_views, rs, images, st, stream, &e)) != R4D_OK)
+      return s;
+    saved->graph = e;
+    saved->generation = e->generation;
+    for (int v = 0; v < n_views; ++v) saved->where.push_back({0, v});
+  } else if (rs.mode == R4D_MODE_FUSED) {
+    Plan p = make_plan(views, n_views, uint32_t(g.n), g.deg, rs, sizeof(T));
+    p.count_evals = timed;
+    std::unique_ptr<RunState> r;
+    if ((s = run_sized<T>(ctx, g, p, images, st, timed, stream, r)) != R4D_OK) return s;
+    saved->runs.push_back(std::move(r));
+    for (int v = 0; v < n_views; ++v) saved->where.push_back({0, v});
+  } else {
+    size_t off = 0;
+    for (int v = 0; v < n_views; ++v) {
+      Plan p = make_plan(views + v, 1, uint32_t(g.n), g.deg, rs, sizeof(T));
+      p.count_evals = timed;
+      std::unique_ptr<RunState> r;
+      if ((s = run_sized<T>(ctx, g, p, images + off, st, timed, stream, r)) != R4D_OK) {
+        for (auto& rr : saved->runs) release_run(ctx, rr.get());
+        return s;
+      }
+      r->image_offset = off;
+      off += 3 * size_t(views[v].width) * size_t(views[v].height);
+      saved->runs.push_back(std::move(r));
+      saved->where.push_back({v, 0});
+    }
+  }
+  if (saved_out) {
+    r4d_saved* raw = saved.release();
+    ctx->live_saved.insert(raw);
+    *saved_out = raw;
+  } else {
+    // inference: the run buffers return to the cache (stream order keeps the
+    // queued kernels safe)
+    for (auto& rr : saved->runs) release_run(ctx, rr.get());
+  }
+  return R4D_OK;
+}
+
+bool same_view(const r4d_view& a, const r4d_view& b) {
+  return a.width == b.width && a.height == b.height && a.t == b.t &&
+         std::memcmp(a.world_to_cam, b.world_to_cam, sizeof(a.world_to_cam)) == 0 &&
+         a.fx == b.fx && a.fy == b.fy && a.cx == b.cx && a.cy == b.cy;
+}
+
+template <typename T>
+r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
+                         int n_views, const r4d_settings* settings, const r4d_saved* saved,
+                         const T* dL, const GradPtrs<T>& out, hipStream_t stream) {
+  if (!views || n_views < 1 || !dL || !valid_settings(settings) || !saved)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, gradients, settings or saved state");
+  r4d_status s = check_gaussians(ctx, g);
+  if (s != R4D_OK) return s;
+  if (g.n > 0 && (!out.means || !out.log_scales || !out.rotors || !out.opacity || !out.sh))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "null gradient array");
+  if (saved->ctx != ctx || saved->f64 != (sizeof(T) == 8) || saved->n != g.n ||
+      saved->deg != g.deg || int(saved->views.size()) != n_views ||
+      settings->mode != saved->settings.mode ||
+      (settings->tile_size != 0 && settings->tile_size != saved->settings.tile_size))
+    return fail(ctx, R4D_ERR_STATE, "saved state does not match this backward call");
+  for (int i = 0; i < n_views; ++i)
+    if (!same_view(saved->views[size_t(i)], views[i]))
+      return fail(ctx, R4D_ERR_STATE, "view %d differs from the forward call", i);
+  if (saved->graph && saved->generation != saved->graph->generation)
+    return fail(ctx, R4D_ERR_STATE, "a later graph forward of this shape reused the buffers");
+  R4D_HIP(hipSetDevice(ctx->device));
+  if (g.n == 0) return R4D_OK;
+  const SettingsDev st = make_settings(saved->settings);
+  const bool timed = ctx->timing && !saved->graph;
+  if (saved->graph) {
+    GraphEntry* e = saved->graph;
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p", (const void*)dL,
+             (const void*)out.means, (const void*)out.log_scales, (const void*)out.rotors,
+             (const void*)out.opacity, (const void*)out.sh, (const void*)g.means,
+             (const void*)g.log_scales, (const void*)g.rotors, (const void*)g.opacity,
+             (const void*)g.sh, (const void*)e->run.fixed);
+    if (!e->bwd || e->bwd_key != buf) {
+      if (e->bwd) {
+        R4D_HIP(hipStreamSynchronize(stream));
+        (void)hipGraphExecDestroy(e->bwd);
+        e->bwd = nullptr;
+      }
+      if (!e->bwd_block) {
+        e->bwd_block = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(e->run.plan)));
+        if (!e->bwd_block) return fail(ctx, R4D_ERR_OOM, "graph backward buffers");
+      }
+      hipStream_t cs = ctx->capture_stream;
+      R4D_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      r4d_status cst = enqueue_backward<T>(ctx, g, e->run, dL, e->bwd_block, st, out, false, cs);
+      hipGraph_t graph = nullptr;
+      const hipError_t end = hipStreamEndCapture(cs, &graph);
+      if (cst != R4D_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cst;
+      }
+      R4D_HIP(end);
+      const hipError_t inst = hipGraphInstantiate(&e->bwd, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      R4D_HIP(inst);
+      e->bwd_key = buf;
+    }
+    R4D_HIP(hipGraphLaunch(e->bwd, stream));
+    return R4D_OK;
+  }
+  if (saved->runs.size() == 1) {
+    RunState& r = *saved->runs[0];
+    uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan)));
+    if (!bb) return fail(ctx, R4D_ERR_OOM, "backward buffers");
+    s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, bb, st, out, timed, stream);
+    ctx_free(ctx, bb);
+    return s;
+  }
+  // several runs (per-view mode): the first run writes `out`, every later run
+  // writes a temporary that is added to `out`
+  const size_t n = size_t(g.n);
+  const size_t k3 = 3 * size_t((g.deg + 1) * (g.deg + 1));
+  T* tmp = static_cast<T*>(ctx_alloc(ctx, (17 + k3) * n * sizeof(T)));
+  if (!tmp) return fail(ctx, R4D_ERR_OOM, "backward buffers");
+  const GradPtrs<T> gt{tmp, tmp + 4 * n, tmp + 8 * n, tmp + 16 * n, tmp + 17 * n};
+  for (size_t ri = 0; ri < saved->runs.size() && s == R4D_OK; ++ri) {
+    RunState& r = *saved->runs[ri];
+    uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan)));
+    if (!bb) {
+      s = fail(ctx, R4D_ERR_OOM, "backward buffers");
+      break;
+    }
+    s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, bb, st, ri == 0 ? out : gt, timed,
+                            stream);
+    ctx_free(ctx, bb);
+    if (s == R4D_OK && ri > 0) {
+      const hipError_t e = add_grads<T>(out, tmp, n, k3, stream);
+      if (e != hipSuccess) s = fail(ctx, R4D_ERR_HIP, "gradient sum: %s", hipGetErrorString(e));
+    }
+  }
+  ctx_free(ctx, tmp);
+  return s;
 }
 
 }  // namespace
@@ -491,6 +1079,8 @@ void r4d_default_settings(r4d_settings* s) {
   s->guard_band = 1.3f;
   s->fwd_pixels_per_thread = 0;
   s->bwd_pixels_per_thread = 0;
+  s->mode = R4D_MODE_PER_VIEW;
+  s->sort_items = 0;
 }
 
 r4d_status r4d_create(r4d_ctx** out, int device) {
@@ -502,14 +1092,25 @@ r4d_status r4d_create(r4d_ctx** out, int device) {
     return R4D_ERR_HIP;
   }
   if (hipSetDevice(device) != hipSuccess) return R4D_ERR_HIP;
-  r4d_ctx* ctx = new r4d_ctx();
+  auto ctx = std::make_unique<r4d_ctx>();
   ctx->device = device;
-  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->host_readback), 2 * sizeof(uint64_t),
-                    hipHostMallocDefault) != hipSuccess) {
-    delete ctx;
+  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->readback), 2 * kMaxViews * 8,
+                    hipHostMallocDefault) != hipSuccess)
     return R4D_ERR_OOM;
+  ctx->ring.resize(8);
+  const size_t stage_bytes = sizeof(ViewSlot) * kMaxViews + sizeof(SegTable);
+  for (auto& s : ctx->ring) {
+    if (hipHostMalloc(&s.host, stage_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+      r4d_destroy(ctx.release());
+      return R4D_ERR_OOM;
+    }
   }
-  *out = ctx;
+  if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    r4d_destroy(ctx.release());
+    return R4D_ERR_HIP;
+  }
+  *out = ctx.release();
   return R4D_OK;
 }
 
@@ -519,18 +1120,41 @@ void r4d_destroy(r4d_ctx* ctx) {
   (void)hipDeviceSynchronize();
   // saved states that outlive the context keep only their host struct
   for (r4d_saved* sv : ctx->live_saved) {
+    for (auto& r : sv->runs) {
+      r->owns_memory = false;
+      release_run(ctx, r.get());
+    }
+    sv->runs.clear();
+    sv->graph = nullptr;
     sv->ctx = nullptr;
-    sv->blocks.clear();
-    sv->views.clear();
   }
   ctx->live_saved.clear();
+  for (auto& kv : ctx->graphs) {
+    GraphEntry* e = kv.second.get();
+    if (e->fwd) (void)hipGraphExecDestroy(e->fwd);
+    if (e->bwd) (void)hipGraphExecDestroy(e->bwd);
+    e->run.owns_memory = false;
+    release_run(ctx, &e->run);
+  }
+  ctx->graphs.clear();
   for (auto& kv : ctx->block_size) (void)hipFree(kv.first);
   for (auto& p : ctx->pending) ctx->event_pool.push_back({p.start, p.stop});
   for (auto& e : ctx->event_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
-  if (ctx->host_readback) (void)hipHostFree(ctx->host_readback);
+  for (auto& s : ctx->ring) {
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.done) (void)hipEventDestroy(s.done);
+  }
+  for (r4d_ctx::Pinned* q : ctx->pinned_pool) {
+    (void)hipHostFree(q->host);
+    (void)hipEventDestroy(q->done);
+    delete q;
+  }
+  ctx->pinned_pool.clear();
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  if (ctx->readback) (void)hipHostFree(ctx->readback);
   delete ctx;
 }
 
@@ -576,7 +1200,7 @@ r4d_status r4d_render_backward_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
 void r4d_saved_release(r4d_saved* saved) {
   if (!saved) return;
   if (saved->ctx) {  // null once the context has been destroyed
-    for (void* p : saved->blocks) ctx_free(saved->ctx, p);
+    for (auto& r : saved->runs) release_run(saved->ctx, r.get());
     saved->ctx->live_saved.erase(saved);
   }
   delete saved;
@@ -592,39 +1216,111 @@ r4d_status r4d_l1_loss_grad(r4d_ctx* ctx, const float* image, const float* targe
   return R4D_OK;
 }
 
+r4d_status r4d_l1_loss_grad_views(r4d_ctx* ctx, const float* images, const float* targets,
+                                  const r4d_view* views, int n_views, float* dL_dimages,
+                                  float* loss, void* stream) {
+  if (!ctx) return R4D_ERR_INVALID_ARG;
+  if (!views || n_views < 1 || n_views > kMaxViews || !images || !targets || !dL_dimages)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid L1 arguments");
+  L1Views lv{};
+  lv.n_views = n_views;
+  int64_t off = 0;
+  for (int v = 0; v < n_views; ++v) {
+    if (!valid_view(views[v])) return fail(ctx, R4D_ERR_INVALID_ARG, "invalid view %d", v);
+    lv.base[v] = off;
+    lv.count[v] = 3 * int64_t(views[v].width) * int64_t(views[v].height);
+    off += lv.count[v];
+  }
+  lv.base[n_views] = off;
+  R4D_HIP(hipSetDevice(ctx->device));
+  R4D_HIP(launch_l1_grad_views(images, targets, lv, dL_dimages, loss,
+                               static_cast<hipStream_t>(stream)));
+  return R4D_OK;
+}
+
+r4d_status r4d_saved_check(const r4d_saved* saved) {
+  if (!saved || !saved->ctx) return R4D_ERR_INVALID_ARG;
+  r4d_ctx* ctx = saved->ctx;
+  if (saved->graph && saved->generation != saved->graph->generation) return R4D_ERR_STATE;
+  const size_t nr = saved->graph ? 1 : saved->runs.size();
+  for (size_t i = 0; i < nr; ++i) {
+    RunState* r = saved->run_of(int(i));
+    r4d_status s = wait_run(ctx, *r);
+    if (s != R4D_OK) return s;
+    if (r->flags[1]) return fail(ctx, R4D_ERR_HIP, "sort look-back did not complete");
+    if (r->flags[0]) return fail(ctx, R4D_ERR_CAPACITY, "tile lists overflowed the capacity");
+  }
+  return R4D_OK;
+}
+
+r4d_status r4d_saved_config(const r4d_saved* saved, int32_t* tile_size, int32_t* sort_items,
+                            int32_t* mode) {
+  if (!saved) return R4D_ERR_INVALID_ARG;
+  if (tile_size) *tile_size = saved->settings.tile_size;
+  if (sort_items) *sort_items = saved->settings.sort_items;
+  if (mode) *mode = saved->settings.mode;
+  return R4D_OK;
+}
+
 r4d_status r4d_saved_stats(const r4d_saved* saved, int view, int64_t* n_visible, int64_t* n_dup,
                            int32_t* tiles_x, int32_t* tiles_y) {
-  if (!saved || view < 0 || view >= int(saved->views.size())) return R4D_ERR_INVALID_ARG;
-  const ViewSaved& v = saved->views[view];
-  if (n_visible) *n_visible = int64_t(v.n_visible);
-  if (n_dup) *n_dup = int64_t(v.n_dup);
-  if (tiles_x) *tiles_x = v.tiles_x;
-  if (tiles_y) *tiles_y = v.tiles_y;
+  if (!saved || !saved->ctx || view < 0 || view >= int(saved->views.size()))
+    return R4D_ERR_INVALID_ARG;
+  if (saved->graph && saved->generation != saved->graph->generation) return R4D_ERR_STATE;
+  const auto [ri, vi] = saved->where[size_t(view)];
+  RunState* r = saved->run_of(ri);
+  r4d_status s = wait_run(saved->ctx, *r);
+  if (s != R4D_OK) return s;
+  if (n_visible) *n_visible = int64_t(r->n_visible[size_t(vi)]);
+  if (n_dup) *n_dup = int64_t(r->n_dup[size_t(vi)]);
+  if (tiles_x) *tiles_x = r->plan.slots[size_t(vi)].v.tiles_x;
+  if (tiles_y) *tiles_y = r->plan.slots[size_t(vi)].v.tiles_y;
   return R4D_OK;
 }
 
 r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* dst, size_t bytes,
-                          void* stream) {
+                          void* stream_) {
   if (!saved || !saved->ctx || view < 0 || view >= int(saved->views.size()) || !dst)
     return R4D_ERR_INVALID_ARG;
   r4d_ctx* ctx = saved->ctx;
-  const ViewSaved& v = saved->views[view];
+  if (saved->graph && saved->generation != saved->graph->generation) return R4D_ERR_STATE;
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  const auto [ri, vi] = saved->where[size_t(view)];
+  RunState* r = saved->run_of(ri);
+  r4d_status s = wait_run(ctx, *r);
+  if (s != R4D_OK) return s;
+  const Plan& p = r->plan;
+  const ViewSlot& sl = p.slots[size_t(vi)];
   const size_t scal = saved->f64 ? 8 : 4;
   const size_t n = size_t(saved->n);
-  const size_t hw = size_t(v.view.width) * v.view.height;
+  const size_t hw = size_t(sl.v.W) * size_t(sl.v.H);
+  const size_t ntiles = size_t(sl.v.tiles_x) * size_t(sl.v.tiles_y);
+  uint8_t* F = r->fixed;
   const void* src = nullptr;
   size_t need = 0;
+  SegTable tseg{};
   switch (buffer) {
-    case R4D_BUF_RECORDS: src = v.recs; need = n * 12 * scal; break;
-    case R4D_BUF_RECT: src = v.rects; need = n * sizeof(Rect16); break;
-    case R4D_BUF_DEPTHKEY: src = v.depth_keys; need = n * 4; break;
-    case R4D_BUF_VALUES: src = v.values; need = size_t(v.n_dup) * 4; break;
-    case R4D_BUF_RANGES: src = v.ranges; need = size_t(v.tiles_x) * v.tiles_y * 8; break;
-    case R4D_BUF_TFINAL: src = v.T_final; need = hw * scal; break;
-    case R4D_BUF_NCONTRIB: src = v.n_contrib; need = hw * 4; break;
+    case R4D_BUF_RECORDS: src = F + r->L.recs + size_t(vi) * n * 12 * scal; need = n * 12 * scal; break;
+    case R4D_BUF_RECT: src = F + r->L.rects + size_t(vi) * n * 8; need = n * 8; break;
+    case R4D_BUF_DEPTHKEY: src = F + r->L.dkeys + size_t(vi) * size_t(p.n_pad) * 4; need = n * 4; break;
+    case R4D_BUF_VALUES:
+    case R4D_BUF_RANGES: {
+      R4D_HIP(hipSetDevice(ctx->device));
+      R4D_HIP(hipMemcpy(&tseg, tseg_of(F, r->L, p.V), sizeof(SegTable), hipMemcpyDeviceToHost));
+      if (buffer == R4D_BUF_VALUES) {
+        src = r->values + tseg.start[vi];
+        need = size_t(tseg.len[vi]);
+        need *= 4;
+      } else {
+        need = ntiles * 8;
+      }
+      break;
+    }
+    case R4D_BUF_TFINAL: src = F + r->L.T_final + size_t(sl.pix_base) * scal; need = hw * scal; break;
+    case R4D_BUF_NCONTRIB: src = F + r->L.n_contrib + size_t(sl.pix_base) * 4; need = hw * 4; break;
     case R4D_BUF_NEVAL:
-      if (!v.n_eval) return fail(ctx, R4D_ERR_STATE, "evaluation counts need timing enabled");
-      src = v.n_eval;
+      if (!p.count_evals) return fail(ctx, R4D_ERR_STATE, "evaluation counts need timing enabled");
+      src = F + r->L.n_eval + size_t(sl.pix_base) * 4;
       need = hw * 4;
       break;
     default: return fail(ctx, R4D_ERR_INVALID_ARG, "unknown buffer id %d", buffer);
@@ -634,7 +1330,12 @@ r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* ds
                 bytes);
   if (need == 0) return R4D_OK;
   R4D_HIP(hipSetDevice(ctx->device));
-  R4D_HIP(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  if (buffer == R4D_BUF_RANGES) {
+    R4D_HIP(copy_ranges_rebased(at<uint2>(F, r->L.ranges) + sl.tile_base, uint32_t(ntiles),
+                                tseg.start[vi], static_cast<uint2*>(dst), stream));
+    return R4D_OK;
+  }
+  R4D_HIP(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, stream));
   return R4D_OK;
 }
 

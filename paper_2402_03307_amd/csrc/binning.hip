@@ -1,0 +1,647 @@
+// Tile binning: per-tile entry counts, tile ranges, tile-key emission and a
+// segmented onesweep radix sort (one kernel per 8-bit digit).
+//
+// The (tile, depth) order the rasteriser needs is produced in two stable
+// stages.  The Gaussians of every render are sorted by the float32 bit pattern
+// of their depth (positive floats order like their bit patterns; culled
+// Gaussians carry 0xffffffff and sort last); each Gaussian's tiles are then
+// emitted in that depth order and the emitted list is stably sorted by tile id.
+// The result is ordered by (tile, depth, Gaussian index): a radix sort of that
+// composite key whose depth part is sorted once per Gaussian instead of once
+// per tile entry.
+//
+// Several renders are processed at once as segments of one array: segment s
+// starts at a multiple of 4096 elements and every sort pass works within
+// segments only.  Per-tile entry counts do not need the emitted keys: the
+// preprocess adds each Gaussian's tile rectangle into a 2D difference grid, and
+// its 2D prefix sum is the count of every tile.  Their exclusive scan is the
+// tile ranges, and their digit sums are the digit histograms of the tile sort.
+//
+// Onesweep pass: every workgroup takes a ticket (its position in the sort
+// order, in launch order, so that every lower ticket belongs to a workgroup
+// that is already running), ranks its 4096 keys stably in LDS, publishes its
+// per-digit counts, and adds up the counts of the workgroups before it in the
+// same segment (decoupled look-back), stopping at the first one that has
+// published its inclusive prefix.  The spin on a predecessor is bounded: past
+// the bound the pass raises an error flag and finishes with in-bounds (but
+// wrong) positions instead of hanging.
+#include <hip/hip_runtime.h>
+
+#include "r4d_internal.hpp"
+
+namespace r4d {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr uint32_t kStatAgg = 1u << 30;   // published: this workgroup's count only
+constexpr uint32_t kStatPre = 2u << 30;   // published: inclusive prefix within the segment
+constexpr uint32_t kStatMask = (1u << 30) - 1u;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_relaxed(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan of one value per thread over a workgroup of NT threads;
+// *total receives the sum.  s_w must hold NT/64 entries.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T* s_w, T* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const T inc = wave_incl_scan(x, lane);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const T s = s_w[w];
+    off += w < wave ? s : T(0);
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - x;
+}
+
+// ---- device-wide exclusive scan (multi-level: tile sums are scanned recursively)
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kThreads * kScanItems;
+
+template <typename T>
+struct LoadT {
+  const T* p;
+  uint64_t n;
+  __device__ T operator()(uint64_t i) const { return i < n ? p[i] : T(0); }
+};
+
+template <typename T, typename Loader>
+__global__ __launch_bounds__(kThreads) void scan_tiles_kernel(Loader ld, T* out, T* tile_sums,
+                                                              uint64_t n) {
+  __shared__ T s_w[kThreads / 64];
+  const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
+  T v[kScanItems];
+  T sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = ld(base + j);
+    sum += v[j];
+  }
+  T total;
+  T run = block_excl_scan<kThreads>(sum, s_w, &total);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_add_kernel(T* out, const T* tile_offsets,
+                                                            uint64_t n) {
+  const T add = tile_offsets[blockIdx.x];
+  const uint64_t base = uint64_t(blockIdx.x) * kScanTile;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const uint64_t i = base + uint64_t(j) * kThreads + threadIdx.x;
+    if (i < n) out[i] += add;
+  }
+}
+
+uint64_t scan_temp_elems(uint64_t n) {
+  uint64_t total = 0, m = n;
+  while (m > uint64_t(kScanTile)) {
+    m = (m + kScanTile - 1) / kScanTile;
+    total += m;
+  }
+  return total;
+}
+
+// Exclusive scan of ld(0..n-1) into out[0..n-1]; temp holds scan_temp_elems(n) T's.
+template <typename T, typename Loader>
+hipError_t device_exclusive_scan(Loader ld, T* out, uint64_t n, T* temp, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+  if (tiles == 1) {
+    hipLaunchKernelGGL((scan_tiles_kernel<T, Loader>), dim3(1), dim3(kThreads), 0, stream, ld,
+                       out, (T*)nullptr, n);
+    return hipGetLastError();
+  }
+  T* sums = temp;
+  hipLaunchKernelGGL((scan_tiles_kernel<T, Loader>), dim3(uint32_t(tiles)), dim3(kThreads), 0,
+                     stream, ld, out, sums, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = device_exclusive_scan<T, LoadT<T>>(LoadT<T>{sums, tiles}, sums, tiles, temp + tiles, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_add_kernel<T>, dim3(uint32_t(tiles)), dim3(kThreads), 0, stream, out,
+                     (const T*)sums, n);
+  return hipGetLastError();
+}
+
+// Largest segment whose start is <= e (empty segments share their start with
+// the next one, so the non-empty segment holding e is found).
+__device__ __forceinline__ uint32_t segment_of(const SegTable* t, uint32_t e) {
+  uint32_t lo = 0, hi = t->count - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (t->start[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void fill_zero_kernel(uint4* __restrict__ p, uint64_t n16) {
+  const uint64_t stride = uint64_t(gridDim.x) * kThreads;
+  for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Digit histograms of keys, PASSES digits of 8 bits, per segment (blockIdx.y).
+template <int PASSES>
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                              const SegTable* __restrict__ seg,
+                                                              uint32_t chunk,
+                                                              uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[PASSES][256];
+#pragma unroll
+  for (int p = 0; p < PASSES; ++p) h[p][threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t s = blockIdx.y;
+  if (s < seg->count) {
+    const uint32_t s0 = seg->start[s];
+    const uint32_t begin = s0 + blockIdx.x * chunk;
+    const uint32_t send = s0 + seg->len[s];
+    const uint32_t end = send < begin + chunk ? send : begin + chunk;
+    for (uint32_t i = begin + threadIdx.x; i < end; i += kThreads) {
+      const uint32_t key = keys[i];
+#pragma unroll
+      for (int p = 0; p < PASSES; ++p) atomicAdd(&h[p][(key >> (8 * p)) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  if (s < seg->count) {
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+      const uint32_t c = h[p][threadIdx.x];
+      if (c) atomicAdd(&hist[(size_t(p) * kMaxViews + s) * 256 + threadIdx.x], c);
+    }
+  }
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(kThreads) void onesweep_kernel(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    const SegTable* __restrict__ seg, const uint32_t* __restrict__ hist,
+    uint32_t* __restrict__ status, uint32_t* __restrict__ ticket, uint32_t* __restrict__ error,
+    int shift) {
+  constexpr uint32_t TILE = kThreads * ITEMS;
+  __shared__ uint32_t s_keys[TILE];
+  __shared__ uint32_t s_vals[TILE];
+  __shared__ uint32_t s_wh[kThreads / 64][256];  // per-wave digit counts, then wave prefixes
+  __shared__ uint32_t s_start[256];              // workgroup-local start of each digit
+  __shared__ uint32_t s_gofs[256];               // output position minus local position
+  __shared__ uint32_t s_w[kThreads / 64];
+  __shared__ uint32_t s_bid;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_bid = atomicAdd(ticket, 1u);
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) s_wh[w][tid] = 0u;
+  __syncthreads();
+  const uint32_t b = s_bid;
+  const uint32_t e0 = b * TILE;
+  if (seg->count == 0u || e0 >= seg->start[seg->count]) return;
+  const uint32_t s = segment_of(seg, e0);
+  const uint32_t sstart = seg->start[s];
+  const uint32_t send = sstart + seg->len[s];
+  const uint32_t first_b = sstart / TILE;
+  const uint32_t nvalid = send > e0 ? (send - e0 < TILE ? send - e0 : TILE) : 0u;
+
+  // load: wave w holds elements [w * 64 * ITEMS, (w + 1) * 64 * ITEMS) of the tile
+  uint32_t k[ITEMS], v[ITEMS], r[ITEMS];
+  const uint32_t wbase = uint32_t(wave) * ITEMS * 64u;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t loc = wbase + uint32_t(i) * 64u + uint32_t(lane);
+    const bool ok = loc < nvalid;
+    k[i] = ok ? keys_in[e0 + loc] : 0u;
+    v[i] = !ok ? 0u : vals_in ? vals_in[e0 + loc] : e0 + loc - sstart;
+  }
+  // stable rank within the wave: lanes with equal digits found with 8 ballots;
+  // the wave's running digit counts live in its own LDS row, so no atomics and
+  // no barriers are needed (a wave's LDS accesses complete in program order)
+  const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const bool ok = wbase + uint32_t(i) * 64u + uint32_t(lane) < nvalid;
+    const uint32_t d = (k[i] >> shift) & 255u;
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool x = (d >> bit) & 1u;
+      const unsigned long long m = __ballot(x);
+      peers &= x ? m : ~m;
+    }
+    const uint32_t base = s_wh[wave][d];
+    const unsigned long long before = peers & lt;
+    r[i] = base + uint32_t(__popcll(before));
+    if (ok && before == 0ull) s_wh[wave][d] = base + uint32_t(__popcll(peers));
+  }
+  __syncthreads();
+  // thread tid = digit: wave prefixes and the workgroup count of the digit
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const uint32_t t = s_wh[w][tid];
+    s_wh[w][tid] = cnt;
+    cnt += t;
+  }
+  uint32_t* my = status + size_t(b) * 256u + uint32_t(tid);
+  store_relaxed(my, (b == first_b ? kStatPre : kStatAgg) | cnt);
+  uint32_t tot;
+  s_start[tid] = block_excl_scan<kThreads>(cnt, s_w, &tot);
+  const uint32_t hb = block_excl_scan<kThreads>(hist[size_t(s) * 256u + uint32_t(tid)], s_w, &tot);
+  uint32_t prev = 0;
+  if (b != first_b) {
+    uint32_t j = b - 1u, spins = 0;
+    for (;;) {
+      const uint32_t val = load_relaxed(status + size_t(j) * 256u + uint32_t(tid));
+      const uint32_t fl = val & ~kStatMask;
+      if (fl == 0u) {
+        if (++spins > kSpinLimit) {
+          atomicOr(error, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        continue;
+      }
+      prev += val & kStatMask;
+      if (fl == kStatPre || j == first_b) break;
+      --j;
+    }
+    store_relaxed(my, kStatPre | (prev + cnt));
+  }
+  s_gofs[tid] = sstart + hb + prev - s_start[tid];
+  __syncthreads();
+  // local scatter into digit order, then runs of equal digits to consecutive addresses
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    if (wbase + uint32_t(i) * 64u + uint32_t(lane) < nvalid) {
+      const uint32_t d = (k[i] >> shift) & 255u;
+      const uint32_t p = s_start[d] + s_wh[wave][d] + r[i];
+      s_keys[p] = k[i];
+      s_vals[p] = v[i];
+    }
+  }
+  __syncthreads();
+  for (uint32_t p = tid; p < nvalid; p += kThreads) {
+    const uint32_t key = s_keys[p];
+    const uint32_t g = s_gofs[(key >> shift) & 255u] + p;
+    if (keys_out) keys_out[g] = key;
+    vals_out[g] = s_vals[p];
+  }
+}
+
+// One workgroup per render: 2D prefix sum of the rectangle difference grid
+// (rows, then columns) gives every tile's entry count; their exclusive scan in
+// tile order gives the tile ranges inside the render's segment of the emitted
+// list; their digit sums give the tile sort's histograms.  Also lays out the
+// segments (render v starts at the sum of the earlier renders' counts, each
+// rounded up to 4096) and reports overflow of the entry capacity, in which
+// case every segment is empty and every range is [0, 0).
+constexpr int kTcThreads = 1024;
+
+__global__ __launch_bounds__(kTcThreads) void tile_count_kernel(
+    const ViewSlot* __restrict__ slots, int n_views, int* __restrict__ grid,
+    const unsigned long long* __restrict__ totals, unsigned long long capacity,
+    uint2* __restrict__ ranges, uint32_t* __restrict__ hist, SegTable* __restrict__ seg) {
+  __shared__ uint32_t s_h[3][256];
+  __shared__ uint32_t s_w[kTcThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int v = blockIdx.x;
+  for (int i = tid; i < 3 * 256; i += kTcThreads) (&s_h[0][0])[i] = 0u;
+  unsigned long long base = 0, total = 0;
+  bool too_long = false;
+  for (int u = 0; u < n_views; ++u) {
+    const unsigned long long d = totals[2 * u + 1];
+    const unsigned long long pd = (d + kSegAlign - 1) / kSegAlign * kSegAlign;
+    if (u < v) base += pd;
+    total += pd;
+    too_long |= d > kStatMask;
+  }
+  const bool overflow = too_long || total > capacity;
+  const unsigned long long Dv = totals[2 * v + 1];
+  if (tid == 0) {
+    seg->start[v] = overflow ? 0u : uint32_t(base);
+    seg->len[v] = overflow ? 0u : uint32_t(Dv);
+    if (v == n_views - 1) seg->start[n_views] = overflow ? 0u : uint32_t(total);
+    if (v == 0) {
+      seg->count = uint32_t(n_views);
+      seg->overflow = overflow ? 1u : 0u;
+    }
+  }
+  const ViewSlot& sl = slots[v];
+  const int tx = sl.v.tiles_x, ty = sl.v.tiles_y;
+  const uint32_t ntiles = uint32_t(tx) * uint32_t(ty);
+  if (overflow) {
+    for (uint32_t t = tid; t < ntiles; t += kTcThreads) ranges[sl.tile_base + t] = make_uint2(0u, 0u);
+  } else {
+    int* gd = grid + sl.grid_base;
+    const int W1 = tx + 1, H1 = ty + 1;
+    for (int row = wave; row < H1; row += kTcThreads / 64) {
+      int carry = 0;
+      for (int c0 = 0; c0 < W1; c0 += 64) {
+        const int x = c0 + lane;
+        const int val = x < W1 ? gd[row * W1 + x] : 0;
+        const int inc = wave_incl_scan(val, lane) + carry;
+        if (x < W1) gd[row * W1 + x] = inc;
+        carry = __shfl(inc, 63, 64);
+      }
+    }
+    __syncthreads();
+    for (int col = wave; col < W1; col += kTcThreads / 64) {
+      int carry = 0;
+      for (int r0 = 0; r0 < H1; r0 += 64) {
+        const int y = r0 + lane;
+        const int val = y < H1 ? gd[y * W1 + col] : 0;
+        const int inc = wave_incl_scan(val, lane) + carry;
+        if (y < H1) gd[y * W1 + col] = inc;
+        carry = __shfl(inc, 63, 64);
+      }
+    }
+    __syncthreads();
+    uint32_t run = uint32_t(base);
+    for (uint32_t t0 = 0; t0 < ntiles; t0 += kTcThreads) {
+      const uint32_t t = t0 + tid;
+      const uint32_t c = t < ntiles ? uint32_t(gd[int(t / tx) * W1 + int(t % tx)]) : 0u;
+      uint32_t tot;
+      const uint32_t ex = block_excl_scan<kTcThreads>(c, s_w, &tot) + run;
+      if (t < ntiles) {
+        ranges[sl.tile_base + t] = c ? make_uint2(ex, ex + c) : make_uint2(0u, 0u);
+        if (c) {
+          atomicAdd(&s_h[0][t & 255u], c);
+          atomicAdd(&s_h[1][(t >> 8) & 255u], c);
+          atomicAdd(&s_h[2][(t >> 16) & 255u], c);
+        }
+      }
+      run += tot;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < 3 * 256; i += kTcThreads)
+    hist[(size_t(i >> 8) * kMaxViews + v) * 256 + (i & 255)] = (&s_h[0][0])[i];
+}
+
+// Exclusive scan input: tile counts of every render's Gaussians in depth order,
+// render-major, each render padded to n_pad entries with zeros.
+struct LoadCountGatherSeg {
+  const uint32_t* order;  // [V][n_pad] Gaussian index in depth order
+  const uint32_t* counts; // [V][n]
+  uint32_t n, n_pad;
+  uint64_t total;         // V * n_pad
+  __device__ uint64_t operator()(uint64_t i) const {
+    if (i >= total) return 0;
+    const uint32_t v = uint32_t(i / n_pad), k = uint32_t(i % n_pad);
+    return k < n ? uint64_t(counts[size_t(v) * n + order[i]]) : uint64_t(0);
+  }
+};
+
+// Tile-key emission: each wavefront takes 64 consecutive Gaussians of one
+// render's depth order and writes their tile entries one Gaussian at a time,
+// lanes on consecutive entries, so the stores are coalesced whatever the
+// rectangle size.  Keys are render-local tile ids.
+__global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ order,
+                                                   const uint64_t* __restrict__ offsets,
+                                                   const Rect16* __restrict__ rects,
+                                                   const ViewSlot* __restrict__ slots,
+                                                   const SegTable* __restrict__ seg, uint32_t n,
+                                                   uint32_t n_pad, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals) {
+  const uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  const uint32_t v = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  if (seg->overflow) return;
+  const uint32_t kk = uint32_t(i);
+  uint32_t idx = 0, cnt = 0, off = 0;
+  Rect16 rc = {0, 0, 0, 0};
+  const size_t row = size_t(v) * n_pad;
+  if (kk < n) {
+    idx = order[row + kk];
+    rc = rects[size_t(v) * n + idx];
+    cnt = uint32_t(rc.x1 - rc.x0) * uint32_t(rc.y1 - rc.y0);
+    off = seg->start[v] + uint32_t(offsets[row + kk] - offsets[row]);
+  }
+  const uint32_t tiles_x = uint32_t(slots[v].v.tiles_x);
+  unsigned long long todo = __ballot(cnt > 0);
+  while (todo) {
+    const int src = __ffsll((long long)todo) - 1;
+    todo &= todo - 1ull;
+    const uint32_t s_idx = __shfl(idx, src, 64);
+    const uint32_t s_cnt = __shfl(cnt, src, 64);
+    const uint32_t s_off = __shfl(off, src, 64);
+    const uint32_t x0 = __shfl(uint32_t(rc.x0), src, 64);
+    const uint32_t y0 = __shfl(uint32_t(rc.y0), src, 64);
+    const uint32_t w = __shfl(uint32_t(rc.x1 - rc.x0), src, 64);
+    for (uint32_t j = lane; j < s_cnt; j += 64) {
+      const uint32_t ty = y0 + j / w, tx = x0 + j % w;
+      keys[s_off + j] = ty * tiles_x + tx;
+      vals[s_off + j] = s_idx;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void fill_const_kernel(T* __restrict__ p, size_t count,
+                                                              T value) {
+  const size_t stride = size_t(gridDim.x) * kThreads;
+  for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void add_grads_kernel(GradPtrs<T> out,
+                                                             const T* __restrict__ tmp, size_t n,
+                                                             size_t k3) {
+  const size_t total = (17 + k3) * n;
+  const size_t stride = size_t(gridDim.x) * kThreads;
+  for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < total; i += stride) {
+    T* dst;
+    if (i < 4 * n)
+      dst = out.means + i;
+    else if (i < 8 * n)
+      dst = out.log_scales + (i - 4 * n);
+    else if (i < 16 * n)
+      dst = out.rotors + (i - 8 * n);
+    else if (i < 17 * n)
+      dst = out.opacity + (i - 16 * n);
+    else
+      dst = out.sh + (i - 17 * n);
+    *dst += tmp[i];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void rebase_ranges_kernel(const uint2* __restrict__ src,
+                                                                 uint32_t count, uint32_t base,
+                                                                 uint2* __restrict__ dst) {
+  const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < count) {
+    const uint2 r = src[i];
+    dst[i] = r.y > r.x ? make_uint2(r.x - base, r.y - base) : make_uint2(0u, 0u);
+  }
+}
+
+uint32_t grid_for(size_t count) {
+  const size_t b = (count + kThreads - 1) / kThreads;
+  return uint32_t(b < 4096 ? (b ? b : 1) : 4096);
+}
+
+}  // namespace
+
+hipError_t fill_const(void* p, size_t count, double value, bool f64, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(fill_const_kernel<double>, dim3(grid_for(count)), dim3(kThreads), 0, stream,
+                       static_cast<double*>(p), count, value);
+  else
+    hipLaunchKernelGGL(fill_const_kernel<float>, dim3(grid_for(count)), dim3(kThreads), 0, stream,
+                       static_cast<float*>(p), count, float(value));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t add_grads(const GradPtrs<T>& out, const T* tmp, size_t n, size_t k3,
+                     hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(add_grads_kernel<T>, dim3(grid_for((17 + k3) * n)), dim3(kThreads), 0, stream,
+                     out, tmp, n, k3);
+  return hipGetLastError();
+}
+template hipError_t add_grads<float>(const GradPtrs<float>&, const float*, size_t, size_t,
+                                     hipStream_t);
+template hipError_t add_grads<double>(const GradPtrs<double>&, const double*, size_t, size_t,
+                                      hipStream_t);
+
+hipError_t copy_ranges_rebased(const uint2* src, uint32_t count, uint32_t base, uint2* dst,
+                               hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(rebase_ranges_kernel, dim3((count + kThreads - 1) / kThreads), dim3(kThreads),
+                     0, stream, src, count, base, dst);
+  return hipGetLastError();
+}
+
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return hipSuccess;
+  if ((bytes & 15u) || (reinterpret_cast<uintptr_t>(p) & 15u)) return hipErrorInvalidValue;
+  const uint64_t n16 = bytes / 16;
+  uint64_t blocks = (n16 + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(uint32_t(blocks)), dim3(kThreads), 0, stream,
+                     static_cast<uint4*>(p), n16);
+  return hipGetLastError();
+}
+
+uint32_t sort_status_words(uint64_t capacity_elems, int items) {
+  const uint64_t tile = uint64_t(kThreads) * items;
+  return uint32_t((capacity_elems + tile - 1) / tile * 256u);
+}
+
+hipError_t radix_histogram(const uint32_t* keys, const SegTable* seg, int n_segments,
+                           uint32_t max_len, int passes, uint32_t* hist, hipStream_t stream) {
+  if (max_len == 0 || n_segments <= 0) return hipSuccess;
+  const uint32_t chunk = 16384;
+  const dim3 grid((max_len + chunk - 1) / chunk, uint32_t(n_segments));
+  switch (passes) {
+    case 1: hipLaunchKernelGGL(radix_hist_kernel<1>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
+    case 2: hipLaunchKernelGGL(radix_hist_kernel<2>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
+    case 3: hipLaunchKernelGGL(radix_hist_kernel<3>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
+    case 4: hipLaunchKernelGGL(radix_hist_kernel<4>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* key_bufs[2],
+                         uint32_t* val_bufs[2], const SegTable* seg, uint64_t capacity_elems,
+                         int passes, int items, const uint32_t* hist, uint32_t* status,
+                         uint32_t* tickets, uint32_t* error, bool keys_needed, int* result_index,
+                         hipStream_t stream) {
+  *result_index = (passes - 1) & 1;
+  if (capacity_elems == 0 || passes <= 0) return hipSuccess;
+  const uint64_t tile = uint64_t(kThreads) * items;
+  const uint32_t blocks = uint32_t((capacity_elems + tile - 1) / tile);
+  const uint32_t words = blocks * 256u;
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t* ki = p == 0 ? keys_in : key_bufs[(p - 1) & 1];
+    const uint32_t* vi = p == 0 ? vals_in : val_bufs[(p - 1) & 1];
+    uint32_t* ko = (keys_needed || p + 1 < passes) ? key_bufs[p & 1] : nullptr;
+    uint32_t* vo = val_bufs[p & 1];
+    const uint32_t* h = hist + size_t(p) * kMaxViews * 256;
+    uint32_t* st = status + size_t(p) * words;
+    switch (items) {
+      case 4:
+        hipLaunchKernelGGL(onesweep_kernel<4>, dim3(blocks), dim3(kThreads), 0, stream, ki, vi,
+                           ko, vo, seg, h, st, tickets + p, error, 8 * p);
+        break;
+      case 8:
+        hipLaunchKernelGGL(onesweep_kernel<8>, dim3(blocks), dim3(kThreads), 0, stream, ki, vi,
+                           ko, vo, seg, h, st, tickets + p, error, 8 * p);
+        break;
+      case 16:
+        hipLaunchKernelGGL(onesweep_kernel<16>, dim3(blocks), dim3(kThreads), 0, stream, ki, vi,
+                           ko, vo, seg, h, st, tickets + p, error, 8 * p);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t tile_counts(const ViewSlot* slots, int n_views, int* grid,
+                       const unsigned long long* totals, unsigned long long capacity,
+                       uint2* ranges, uint32_t* hist, SegTable* seg, hipStream_t stream) {
+  hipLaunchKernelGGL(tile_count_kernel, dim3(n_views), dim3(kTcThreads), 0, stream, slots,
+                     n_views, grid, totals, capacity, ranges, hist, seg);
+  return hipGetLastError();
+}
+
+size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views) {
+  return (scan_temp_elems(uint64_t(n_pad) * uint64_t(n_views) + 1) + 2) * sizeof(uint64_t);
+}
+
+hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts, uint32_t n,
+                          uint32_t n_pad, int n_views, uint64_t* offsets, void* temp,
+                          hipStream_t stream) {
+  const uint64_t total = uint64_t(n_pad) * uint64_t(n_views);
+  return device_exclusive_scan<uint64_t, LoadCountGatherSeg>(
+      LoadCountGatherSeg{order, counts, n, n_pad, total}, offsets, total + 1,
+      static_cast<uint64_t*>(temp), stream);
+}
+
+hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
+                              const ViewSlot* slots, const SegTable* seg, uint32_t n,
+                              uint32_t n_pad, int n_views, uint32_t* keys, uint32_t* vals,
+                              hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(emit_kernel, dim3((n + 255) / 256, uint32_t(n_views)), dim3(256), 0, stream,
+                     order, offsets, rects, slots, seg, n, n_pad, keys, vals);
+  return hipGetLastError();
+}
+
+}  // namespace r4d

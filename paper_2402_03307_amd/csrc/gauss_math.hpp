@@ -508,7 +508,7 @@ R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacit
 // respect to the symmetric 2x2 matrix Sigma_2D (entries (0,0), (0,1) = (1,0),
 // (1,1); a change dS of the matrix changes L by sum_ij H_ij dS_ij), dL/d(o_t),
 // dL/d(rgb).  Out (added): mu4[4], ls[4], rot[8], opacity, and the SH column via
-// gsh (stride sh_stride).
+// gsh (stride gsh_stride).
 //
 // The rasteriser hands over the Sigma_2D gradient rather than the conic one: for
 // a long thin footprint the conic gradient is dominated by a component along the
@@ -518,7 +518,7 @@ R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacit
 template <typename T, typename ShT>
 R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int deg,
                          const ViewDev& v, const T g2[9], T gmu4[4], T gls[4], T grot[8],
-                         T& gop, ShT* gsh) {
+                         T& gop, T* gsh, long gsh_stride) {
   if (!f.valid) return;
   const T gm_x = g2[0], gm_y = g2[1];
   const T H00 = g2[2], H01 = g2[3], H11 = g2[4];
@@ -538,7 +538,7 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int de
       T acc = 0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        gsh[(3 * j + c) * sh_stride] += ShT(Y[j] * graw[c]);
+        gsh[(3 * j + c) * gsh_stride] += Y[j] * graw[c];
         acc += T(shp[(3 * j + c) * sh_stride]) * graw[c];
       }
       gY[j] = acc;

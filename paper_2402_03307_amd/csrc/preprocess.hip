@@ -52,13 +52,16 @@ __device__ __forceinline__ bool tile_rect(const Rec<T>& rec, const ViewDev& v,
 
 template <typename T, int DEG>
 __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
-    GaussPtrs<T> g, ViewDev v, SettingsDev st, Rec<T>* __restrict__ recs,
-    Rect16* __restrict__ rects, uint32_t* __restrict__ tiles_touched,
-    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ values_iota,
-    unsigned long long* __restrict__ totals) {
+    GaussPtrs<T> g, const ViewSlot* __restrict__ slots, SettingsDev st, uint32_t n_pad,
+    Rec<T>* __restrict__ recs, Rect16* __restrict__ rects, uint32_t* __restrict__ tiles_touched,
+    uint32_t* __restrict__ depth_keys, unsigned long long* __restrict__ totals,
+    int* __restrict__ grids) {
   __shared__ unsigned long long s_tot[2][kBlock / 64];
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int vi = blockIdx.y;
+  const ViewDev v = slots[vi].v;
+  const size_t row = size_t(vi) * size_t(n);
   bool vis = false;
   uint32_t my_cnt = 0;
   if (i < n) {
@@ -93,16 +96,22 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
       if (tile_rect(rec, v, st, rc)) {
         cnt = uint32_t(rc.x1 - rc.x0) * uint32_t(rc.y1 - rc.y0);
         key = __float_as_uint(float(f.p[2]));
-        recs[i] = rec;
+        recs[row + i] = rec;
         vis = true;
+        // 2D difference of the rectangle in the render's tile count grid
+        int* gd = grids + slots[vi].grid_base;
+        const int W1 = v.tiles_x + 1;
+        atomicAdd(&gd[int(rc.y0) * W1 + int(rc.x0)], 1);
+        atomicAdd(&gd[int(rc.y0) * W1 + int(rc.x1)], -1);
+        atomicAdd(&gd[int(rc.y1) * W1 + int(rc.x0)], -1);
+        atomicAdd(&gd[int(rc.y1) * W1 + int(rc.x1)], 1);
       } else {
         rc = {0, 0, 0, 0};
       }
     }
-    rects[i] = rc;
-    tiles_touched[i] = cnt;
-    depth_keys[i] = key;
-    values_iota[i] = uint32_t(i);
+    rects[row + i] = rc;
+    tiles_touched[row + i] = cnt;
+    depth_keys[size_t(vi) * n_pad + i] = key;
     my_cnt = cnt;
   }
   // block totals of visible Gaussians and tile entries, one atomic each per block
@@ -123,35 +132,43 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
       a += s_tot[0][w];
       b += s_tot[1][w];
     }
-    if (a) atomicAdd(&totals[0], a);
-    if (b) atomicAdd(&totals[1], b);
+    if (a) atomicAdd(&totals[2 * vi], a);
+    if (b) atomicAdd(&totals[2 * vi + 1], b);
   }
 }
 
 // Degree-specialised so that the SH loops unroll and the coefficient arrays
-// live in registers.
-template <typename T, int DEG>
-__global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g, ViewDev v,
-                                                                SettingsDev st,
+// live in registers.  Each thread owns one Gaussian and sums its gradients
+// over the renders, recomputing the forward of each render it appears in.
+// With one render the SH coefficients are loaded once into registers; with
+// several they are re-read from memory (cached) in every render, which keeps
+// the register count of the render loop at that of the single-render case.
+template <typename T, int DEG, bool MULTI>
+__global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
+                                                                const ViewSlot* __restrict__ slots,
+                                                                int n_views, SettingsDev st,
                                                                 const double* __restrict__ grad2d,
-                                                                GradPtrs<T> out, bool accumulate) {
+                                                                GradPtrs<T> out) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  T g2[9];
-  bool any = false;
-#pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    g2[c] = T(grad2d[c * (long)n + i]);
-    any |= g2[c] != T(0);
-  }
   T gmu[4] = {0, 0, 0, 0}, gls[4] = {0, 0, 0, 0}, grot[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gop = 0;
   T gsh[3 * K];
 #pragma unroll
   for (int j = 0; j < 3 * K; ++j) gsh[j] = T(0);
-  if (any) {
-    T mu[4], ls[4], rot[8], shl[3 * K];
+  const int nv = MULTI ? n_views : 1;
+  for (int vi = 0; vi < nv; ++vi) {
+    const double* g2v = grad2d + size_t(vi) * 9 * size_t(n);
+    T g2[9];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      g2[c] = T(g2v[c * (long)n + i]);
+      any |= g2[c] != T(0);
+    }
+    if (!any) continue;
+    T mu[4], ls[4], rot[8];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       mu[c] = g.means[c * (long)n + i];
@@ -159,86 +176,89 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g, 
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) rot[c] = g.rotors[c * (long)n + i];
-#pragma unroll
-    for (int j = 0; j < 3 * K; ++j) shl[j] = g.sh[j * (long)n + i];
-    const T op = g.opacity[i];
+    const ViewDev v = slots[vi].v;
     Fwd<T> f;
-    gaussian_fwd<T>(mu, ls, rot, op, shl, 1, DEG, v, st, f);
-    gaussian_bwd<T>(f, shl, 1, DEG, v, g2, gmu, gls, grot, gop, gsh);
-  }
-  if (accumulate) {
+    if (MULTI) {
+      gaussian_fwd<T>(mu, ls, rot, g.opacity[i], g.sh + i, (long)n, DEG, v, st, f);
+      gaussian_bwd<T>(f, g.sh + i, (long)n, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
+    } else {
+      T shl[3 * K];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      out.means[c * (long)n + i] += gmu[c];
-      out.log_scales[c * (long)n + i] += gls[c];
+      for (int j = 0; j < 3 * K; ++j) shl[j] = g.sh[j * (long)n + i];
+      gaussian_fwd<T>(mu, ls, rot, g.opacity[i], shl, 1, DEG, v, st, f);
+      gaussian_bwd<T>(f, shl, 1, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
     }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) out.rotors[c * (long)n + i] += grot[c];
-    out.opacity[i] += gop;
-#pragma unroll
-    for (int j = 0; j < 3 * K; ++j) out.sh[j * (long)n + i] += gsh[j];
-  } else {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      out.means[c * (long)n + i] = gmu[c];
-      out.log_scales[c * (long)n + i] = gls[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) out.rotors[c * (long)n + i] = grot[c];
-    out.opacity[i] = gop;
-#pragma unroll
-    for (int j = 0; j < 3 * K; ++j) out.sh[j * (long)n + i] = gsh[j];
   }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    out.means[c * (long)n + i] = gmu[c];
+    out.log_scales[c * (long)n + i] = gls[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) out.rotors[c * (long)n + i] = grot[c];
+  out.opacity[i] = gop;
+#pragma unroll
+  for (int j = 0; j < 3 * K; ++j) out.sh[j * (long)n + i] = gsh[j];
 }
 
 }  // namespace
 
-#define R4D_DEG_DISPATCH(KERNEL, ...)                                                    \
+#define R4D_DEG_DISPATCH(KERNEL, GRID, ...)                                              \
   switch (g.deg) {                                                                       \
-    case 0: hipLaunchKernelGGL((KERNEL<T, 0>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__); break; \
-    case 1: hipLaunchKernelGGL((KERNEL<T, 1>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__); break; \
-    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__); break; \
-    case 3: hipLaunchKernelGGL((KERNEL<T, 3>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 0: hipLaunchKernelGGL((KERNEL<T, 0>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 1: hipLaunchKernelGGL((KERNEL<T, 1>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 3: hipLaunchKernelGGL((KERNEL<T, 3>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
     default: return hipErrorInvalidValue;                                                \
   }
 
 template <typename T>
-hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
-                                 Rec<T>* recs, Rect16* rects, uint32_t* tiles_touched,
-                                 uint32_t* depth_keys, uint32_t* values_iota,
-                                 unsigned long long* totals, hipStream_t stream) {
-  if (g.n <= 0) return hipSuccess;
-  const int grid = (g.n + kBlock - 1) / kBlock;
-  R4D_DEG_DISPATCH(preprocess_fwd_kernel, g, v, st, recs, rects, tiles_touched, depth_keys,
-                   values_iota, totals)
+hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
+                                 const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
+                                 Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
+                                 unsigned long long* totals, int* grids, hipStream_t stream) {
+  if (g.n <= 0 || n_views <= 0) return hipSuccess;
+  const dim3 grid((g.n + kBlock - 1) / kBlock, uint32_t(n_views));
+  R4D_DEG_DISPATCH(preprocess_fwd_kernel, grid, g, slots, st, n_pad, recs, rects, tiles_touched,
+                   depth_keys, totals, grids)
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
-                                 const double* grad2d, const GradPtrs<T>& out, bool accumulate,
-                                 hipStream_t stream) {
+hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
+                                 const SettingsDev& st, const double* grad2d,
+                                 const GradPtrs<T>& out, hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
-  const int grid = (g.n + kBlock - 1) / kBlock;
-  R4D_DEG_DISPATCH(preprocess_bwd_kernel, g, v, st, grad2d, out, accumulate)
+  const dim3 grid((g.n + kBlock - 1) / kBlock);
+#define R4D_BWD_DISPATCH(MULTI)                                                              \
+  switch (g.deg) {                                                                           \
+    case 0: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 0, MULTI>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 1: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 1, MULTI>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 2: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 2, MULTI>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 3: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 3, MULTI>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    default: return hipErrorInvalidValue;                                                    \
+  }
+  if (n_views > 1) {
+    R4D_BWD_DISPATCH(true)
+  } else {
+    R4D_BWD_DISPATCH(false)
+  }
+#undef R4D_BWD_DISPATCH
   return hipGetLastError();
 }
 
 #undef R4D_DEG_DISPATCH
 
-template hipError_t launch_preprocess_fwd<float>(const GaussPtrs<float>&, const ViewDev&,
-                                                 const SettingsDev&, Rec<float>*, Rect16*,
-                                                 uint32_t*, uint32_t*, uint32_t*,
-                                                 unsigned long long*, hipStream_t);
-template hipError_t launch_preprocess_fwd<double>(const GaussPtrs<double>&, const ViewDev&,
-                                                  const SettingsDev&, Rec<double>*, Rect16*,
-                                                  uint32_t*, uint32_t*, uint32_t*,
-                                                  unsigned long long*, hipStream_t);
-template hipError_t launch_preprocess_bwd<float>(const GaussPtrs<float>&, const ViewDev&,
-                                                 const SettingsDev&, const double*,
-                                                 const GradPtrs<float>&, bool, hipStream_t);
-template hipError_t launch_preprocess_bwd<double>(const GaussPtrs<double>&, const ViewDev&,
-                                                  const SettingsDev&, const double*,
-                                                  const GradPtrs<double>&, bool, hipStream_t);
+#define R4D_INST(T)                                                                           \
+  template hipError_t launch_preprocess_fwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
+                                               const SettingsDev&, uint32_t, Rec<T>*, Rect16*, \
+                                               uint32_t*, uint32_t*, unsigned long long*, int*, \
+                                               hipStream_t);                                   \
+  template hipError_t launch_preprocess_bwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
+                                               const SettingsDev&, const double*,              \
+                                               const GradPtrs<T>&, hipStream_t);
+R4D_INST(float)
+R4D_INST(double)
+#undef R4D_INST
 
 }  // namespace r4d

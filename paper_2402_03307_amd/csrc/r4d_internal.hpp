@@ -33,71 +33,140 @@ struct Rect16 {
   uint16_t x0, y0, x1, y1;
 };
 
-// ---- preprocess (per Gaussian)
-// totals[0] += number of visible Gaussians, totals[1] += number of tile entries
-// (the caller zeroes them first).
-template <typename T>
-hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
-                                 Rec<T>* recs, Rect16* rects, uint32_t* tiles_touched,
-                                 uint32_t* depth_keys, uint32_t* values_iota,
-                                 unsigned long long* totals, hipStream_t stream);
+// ---- several renders in one launch
+constexpr int kMaxViews = 64;      // renders per call
+constexpr uint32_t kSegAlign = 4096;  // segment starts of the segmented sorts
 
-// grad2d: [9][n] double (mean2 x, y, conic a, b, c, opacity_t, r, g, b).
-// accumulate=false overwrites `out`, true adds to it.
-template <typename T>
-hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewDev& v, const SettingsDev& st,
-                                 const double* grad2d, const GradPtrs<T>& out, bool accumulate,
-                                 hipStream_t stream);
-
-// ---- sorting and binning
-struct SortTemp {
-  void* ptr;
-  size_t bytes;
+// Device-side description of one render of a batch.
+struct ViewSlot {
+  ViewDev v;
+  uint32_t tile_base;   // index of the render's first tile among all tiles of the batch
+  uint32_t grid_base;   // offset of its (tiles_x + 1) x (tiles_y + 1) count grid
+  uint64_t pix_base;    // index of its first pixel among all pixels of the batch
 };
 
-// Bytes of temporary storage that sort_pairs_u32 needs for n elements.
-size_t sort_pairs_temp_bytes(uint32_t n);
-// Stable LSD radix sort of (key, value) pairs on key bits [0, end_bit).
-// keys/vals: in/out double buffers; on return *result_index says which of the two
-// buffers (0 or 1) holds the sorted data.
-hipError_t sort_pairs_u32(uint32_t* keys[2], uint32_t* vals[2], uint32_t n, int end_bit,
-                          SortTemp temp, int* result_index, hipStream_t stream);
+// Segments of a segmented sort: segment s holds len[s] elements starting at
+// start[s] (a multiple of kSegAlign); start[count] is the padded end.
+struct SegTable {
+  uint32_t count;
+  uint32_t overflow;  // the tile entries did not fit the capacity: all segments empty
+  uint32_t start[kMaxViews + 1];
+  uint32_t len[kMaxViews];
+};
 
-size_t count_scan_temp_bytes(uint32_t n);
-// offsets[k] = sum_{j<k} tiles_touched[order[j]] for k in [0, n]; offsets[n] = total.
-hipError_t count_scan(const uint32_t* order, const uint32_t* tiles_touched, uint32_t n,
-                      uint64_t* offsets, SortTemp temp, hipStream_t stream);
+// ---- preprocess (per Gaussian and render)
+// Render v = blockIdx.y.  Per render: recs/rects/tiles_touched at [v][n],
+// depth_keys at [v * n_pad + i]; totals[2v] += visible Gaussians, totals[2v+1]
+// += tile entries; each visible Gaussian's rectangle is added to the render's
+// tile count grid as a 2D difference (+1, -1, -1, +1 at its corners).  The
+// caller zeroes totals and the grids.
+template <typename T>
+hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
+                                 const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
+                                 Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
+                                 unsigned long long* totals, int* grids, hipStream_t stream);
 
-// Writes, for each Gaussian in `order` (first n entries), its tiles in row-major
-// order: keys = tile id, vals = Gaussian index, at offsets[k].
-hipError_t emit_tile_keys(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                          uint32_t n, int tiles_x, uint32_t* keys, uint32_t* vals,
+// grad2d: [V][9][n] double (mean2 x, y, Sigma_2D (0,0), (0,1), (1,1), opacity_t,
+// r, g, b).  Writes the parameter gradients summed over the renders.
+template <typename T>
+hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
+                                 const SettingsDev& st, const double* grad2d,
+                                 const GradPtrs<T>& out, hipStream_t stream);
+
+// ---- binning and sorting
+// Zeroes `bytes` (a multiple of 16) at p (16-byte aligned) with a kernel, so
+// that it may be captured in a graph.
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t stream);
+
+// Status words one onesweep pass needs for `capacity` elements at `items` keys
+// per lane (4 or 16).
+uint32_t sort_status_words(uint64_t capacity_elems, int items);
+
+// hist[p][s][256] += digit-p counts (bits 8p..8p+7) of the keys of each segment.
+hipError_t radix_histogram(const uint32_t* keys, const SegTable* seg, int n_segments,
+                           uint32_t max_len, int passes, uint32_t* hist, hipStream_t stream);
+
+// Stable segmented LSD radix sort, `passes` 8-bit digits.  Pass 0 reads
+// keys_in / vals_in (vals_in null: the value is the element's index within its
+// segment); pass p writes bufs[p & 1] and pass p > 0 reads bufs[(p - 1) & 1].
+// bufs[1] may alias the inputs.  The sorted data end in bufs[(passes - 1) & 1]
+// (*result_index).  hist: [passes][kMaxViews][256]; status: passes x
+// sort_status_words, zeroed; tickets: `passes` words, zeroed.  keys_needed =
+// false skips writing the keys in the last pass.
+hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* key_bufs[2],
+                         uint32_t* val_bufs[2], const SegTable* seg, uint64_t capacity_elems,
+                         int passes, int items, const uint32_t* hist, uint32_t* status,
+                         uint32_t* tickets, uint32_t* error, bool keys_needed, int* result_index,
+                         hipStream_t stream);
+
+// Per render: tile entry counts from the difference grid, tile ranges
+// (ranges[tile_base + t] = [start, end) in the emitted list, [0, 0) for a tile
+// without entries), tile-sort digit
+// histograms hist[3][kMaxViews][256] and the segment table of the emitted list.
+hipError_t tile_counts(const ViewSlot* slots, int n_views, int* grids,
+                       const unsigned long long* totals, unsigned long long capacity,
+                       uint2* ranges, uint32_t* hist, SegTable* seg, hipStream_t stream);
+
+size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
+// offsets[v * n_pad + k] = sum over renders u < v of all their entries plus the
+// entries of render v's Gaussians order[v][0..k-1]; offsets[V * n_pad] = total.
+hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts, uint32_t n,
+                          uint32_t n_pad, int n_views, uint64_t* offsets, void* temp,
                           hipStream_t stream);
 
-// ranges[t] = [start, end) of tile t in the sorted keys; tiles without entries [0,0).
-hipError_t tile_ranges(const uint32_t* sorted_keys, uint32_t d, uint32_t n_tiles, uint2* ranges,
-                       hipStream_t stream);
+// Writes every render's (tile id, Gaussian index) entries in depth order into
+// its segment of keys / vals.
+hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
+                              const ViewSlot* slots, const SegTable* seg, uint32_t n,
+                              uint32_t n_pad, int n_views, uint32_t* keys, uint32_t* vals,
+                              hipStream_t stream);
 
 // ---- rasterisation
 // (tile size, pixels per lane) pairs the rasteriser is compiled for.
 bool raster_config_supported(int tile_size, int ppt);
 int raster_default_ppt(int tile_size, bool backward);
 
-// n_eval (nullable): per pixel, the number of list entries evaluated.
+// Persistent launch over all tiles of all renders; tickets: 1 word, zeroed.
+// recs: [V][n]; image: [3][pixels of render v] at 3 * pix_base; T_final,
+// n_contrib, n_eval (nullable) per pixel at pix_base.
 template <typename T>
-hipError_t launch_raster_fwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                             const ViewDev& v, const SettingsDev& st, int ppt, T* image,
-                             T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
-                             hipStream_t stream);
+hipError_t launch_raster_fwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
+                             const uint2* ranges, const ViewSlot* slots, int n_views,
+                             uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
+                             T* image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
+                             uint32_t* tickets, hipStream_t stream);
 
-// grad2d: [9][n] double accumulators (see launch_preprocess_bwd), added to.
+// grad2d: [V][9][n] double accumulators, added to.
 template <typename T>
-hipError_t launch_raster_bwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                             const ViewDev& v, const SettingsDev& st, int ppt, const T* T_final,
-                             const uint32_t* n_contrib, const T* dL_dimage, double* grad2d,
-                             uint32_t n_gaussians, hipStream_t stream);
+hipError_t launch_raster_bwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
+                             const uint2* ranges, const ViewSlot* slots, int n_views,
+                             uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
+                             const T* T_final, const uint32_t* n_contrib, const T* dL_dimage,
+                             double* grad2d, uint32_t* tickets, hipStream_t stream);
 
 hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, float* grad,
                           float* loss, hipStream_t stream);
+
+// Per-view L1: view v covers elements [base[v], base[v + 1]) and is normalised
+// by its own count.
+struct L1Views {
+  int n_views;
+  int64_t base[kMaxViews + 1];
+  int64_t count[kMaxViews];
+};
+hipError_t launch_l1_grad_views(const float* images, const float* targets, const L1Views& lv,
+                                float* grad, float* loss, hipStream_t stream);
+
+// ---- small helpers
+// p[0..count) = value (float or double elements).
+hipError_t fill_const(void* p, size_t count, double value, bool f64, hipStream_t stream);
+// out += tmp, tmp holding the five gradient arrays back to back
+// (means 4n, log_scales 4n, rotors 8n, opacity n, sh k3 n).
+template <typename T>
+hipError_t add_grads(const GradPtrs<T>& out, const T* tmp, size_t n, size_t k3,
+                     hipStream_t stream);
+// dst[t] = src[t] - (base, base); empty ranges stay [0, 0).
+hipError_t copy_ranges_rebased(const uint2* src, uint32_t count, uint32_t base, uint2* dst,
+                               hipStream_t stream);
 
 }  // namespace r4d

@@ -144,22 +144,19 @@ struct TileCfg {
 // transmittance test fail, so no per-pixel "done" flag is carried through the
 // loop.  COUNT counts the entries each pixel evaluates (measurement builds only).
 template <typename T, int TS, int PPT, bool COUNT>
-__global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
-    const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
-    const uint2* __restrict__ ranges, ViewDev v, SettingsDev st, T* __restrict__ image,
+__device__ __forceinline__ void raster_fwd_tile(
+    Staged<T>* s_rec, const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
+    const uint2 rg, int tile, const ViewDev& v, const SettingsDev& st, T* __restrict__ image,
     T* __restrict__ T_final, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
-  __shared__ Staged<T> s_rec[NB];
-  const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int x = tx * TS + int(threadIdx.x % TS);
   const int y0 = ty * TS + int(threadIdx.x / TS);
   const T px = T(x) + T(0.5);
   const T e_min = T(kHalfLog2e) * T(st.ext2);
   const T amin = T(st.alpha_min), amax = T(st.alpha_max), tmin = T(st.T_min);
-  const uint2 rg = ranges[tile];
   T py[PPT], Tr[PPT], Tf[PPT], c0[PPT], c1[PPT], c2[PPT];
   uint32_t last[PPT], evals[PPT];
 #pragma unroll
@@ -223,26 +220,32 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
 }
 
 template <typename T, int TS, int PPT>
-__global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
-    const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
-    const uint2* __restrict__ ranges, ViewDev v, SettingsDev st, const T* __restrict__ T_final,
-    const uint32_t* __restrict__ n_contrib, const T* __restrict__ dL_dimage,
-    double* __restrict__ grad2d, uint32_t n_gauss) {
+struct BwdShared {
+  Staged<T> rec[TileCfg<TS, PPT>::kBatch];
+  uint32_t idx[TileCfg<TS, PPT>::kBatch];
+  T grad[9][TileCfg<TS, PPT>::kBatch];
+  uint32_t max;
+};
+
+template <typename T, int TS, int PPT>
+__device__ __forceinline__ void raster_bwd_tile(
+    BwdShared<T, TS, PPT>& sh, const Rec<T>* __restrict__ recs,
+    const uint32_t* __restrict__ values, const uint2 rg, int tile, const ViewDev& v,
+    const SettingsDev& st, const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
+    const T* __restrict__ dL_dimage, double* __restrict__ grad2d, uint32_t n_gauss) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
-  __shared__ Staged<T> s_rec[NB];
-  __shared__ uint32_t s_idx[NB];
-  __shared__ T s_grad[9][NB];
-  __shared__ uint32_t s_max;
-  const int tile = blockIdx.x;
+  Staged<T>* s_rec = sh.rec;
+  uint32_t* s_idx = sh.idx;
+  T(*s_grad)[NB] = sh.grad;
+  uint32_t& s_max = sh.max;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int x = tx * TS + int(threadIdx.x % TS);
   const int y0 = ty * TS + int(threadIdx.x / TS);
   const T px = T(x) + T(0.5);
   const T e_min = T(kHalfLog2e) * T(st.ext2);
   const T amin = T(st.alpha_min), amax = T(st.alpha_max);
-  const uint2 rg = ranges[tile];
   const long hw = long(v.H) * v.W;
   T py[PPT], Tcur[PPT], g0[PPT], g1[PPT], g2[PPT], acc0[PPT], acc1[PPT], acc2[PPT];
   uint32_t ncon[PPT];
@@ -372,6 +375,10 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
   }
 }
 
+__global__ void zero_one_kernel(float* p) {
+  if (threadIdx.x == 0) *p = 0.f;
+}
+
 __global__ __launch_bounds__(256) void l1_grad_kernel(const float* __restrict__ image,
                                                       const float* __restrict__ target,
                                                       int64_t count, float inv_count,
@@ -394,29 +401,149 @@ __global__ __launch_bounds__(256) void l1_grad_kernel(const float* __restrict__ 
   }
 }
 
+// Render holding global tile g: the last slot whose first tile is <= g.
+__device__ __forceinline__ int slot_of_tile(const ViewSlot* __restrict__ slots, int n_views,
+                                            uint32_t g) {
+  int lo = 0, hi = n_views - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (slots[mid].tile_base <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent launches: each workgroup takes tiles (of any render) from a
+// counter until none is left, so renders of uneven size share one launch and
+// a workgroup that drew short lists simply takes more tiles.
+template <typename T, int TS, int PPT, bool COUNT>
+__global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
+    const Rec<T>* __restrict__ recs, uint32_t n, const uint32_t* __restrict__ values,
+    const uint2* __restrict__ ranges, const ViewSlot* __restrict__ slots, int n_views,
+    uint32_t total_tiles, SettingsDev st, T* __restrict__ image, T* __restrict__ T_final,
+    uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval,
+    uint32_t* __restrict__ tickets) {
+  __shared__ Staged<T> s_rec[TileCfg<TS, PPT>::kBatch];
+  __shared__ uint32_t s_ticket;
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = atomicAdd(tickets, 1u);
+    __syncthreads();
+    const uint32_t g = s_ticket;
+    __syncthreads();
+    if (g >= total_tiles) break;
+    const int vi = slot_of_tile(slots, n_views, g);
+    const ViewSlot& sl = slots[vi];
+    const ViewDev v = sl.v;
+    const size_t pb = size_t(sl.pix_base);
+    raster_fwd_tile<T, TS, PPT, COUNT>(s_rec, recs + size_t(vi) * n, values, ranges[g],
+                                       int(g - sl.tile_base), v, st, image + 3 * pb, T_final + pb,
+                                       n_contrib + pb, COUNT ? n_eval + pb : nullptr);
+  }
+}
+
 template <typename T, int TS, int PPT>
-hipError_t raster_fwd_cfg(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                          const ViewDev& v, const SettingsDev& st, T* image, T* T_final,
-                          uint32_t* n_contrib, uint32_t* n_eval, hipStream_t stream) {
-  const int tiles = v.tiles_x * v.tiles_y;
+__global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
+    const Rec<T>* __restrict__ recs, uint32_t n, const uint32_t* __restrict__ values,
+    const uint2* __restrict__ ranges, const ViewSlot* __restrict__ slots, int n_views,
+    uint32_t total_tiles, SettingsDev st, const T* __restrict__ T_final,
+    const uint32_t* __restrict__ n_contrib, const T* __restrict__ dL_dimage,
+    double* __restrict__ grad2d, uint32_t* __restrict__ tickets) {
+  __shared__ BwdShared<T, TS, PPT> sh;
+  __shared__ uint32_t s_ticket;
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = atomicAdd(tickets, 1u);
+    __syncthreads();
+    const uint32_t g = s_ticket;
+    __syncthreads();
+    if (g >= total_tiles) break;
+    const int vi = slot_of_tile(slots, n_views, g);
+    const ViewSlot& sl = slots[vi];
+    const ViewDev v = sl.v;
+    const size_t pb = size_t(sl.pix_base);
+    raster_bwd_tile<T, TS, PPT>(sh, recs + size_t(vi) * n, values, ranges[g],
+                                int(g - sl.tile_base), v, st, T_final + pb, n_contrib + pb,
+                                dL_dimage + 3 * pb, grad2d + size_t(vi) * 9 * n, n);
+  }
+}
+
+// Workgroups resident on the whole chip at once (occupancy x compute units);
+// a persistent launch needs no more.
+template <typename K>
+uint32_t resident_groups(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return 2048u;
+  }
+  return uint32_t(per_cu) * uint32_t(cus);
+}
+
+// Per-view L1 gradient: blockIdx.y = view; the loss sums every view's mean.
+__global__ __launch_bounds__(256) void l1_grad_views_kernel(const float* __restrict__ image,
+                                                            const float* __restrict__ target,
+                                                            L1Views lv, float* __restrict__ grad,
+                                                            float* __restrict__ loss) {
+  __shared__ float s_part[4];
+  const int v = blockIdx.y;
+  const int64_t b0 = lv.base[v], cnt = lv.count[v];
+  const float inv = 1.0f / float(cnt);
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  float part = 0.f;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < cnt; i += stride) {
+    const float d = image[b0 + i] - target[b0 + i];
+    grad[b0 + i] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+    part += fabsf(d);
+  }
+  if (loss) {
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      atomic_add_nr(loss, (s_part[0] + s_part[1] + s_part[2] + s_part[3]) * inv);
+  }
+}
+
+template <typename T, int TS, int PPT>
+hipError_t raster_fwd_cfg(const Rec<T>* recs, uint32_t n, const uint32_t* values,
+                          const uint2* ranges, const ViewSlot* slots, int n_views,
+                          uint32_t total_tiles, const SettingsDev& st, T* image, T* T_final,
+                          uint32_t* n_contrib, uint32_t* n_eval, uint32_t* tickets,
+                          hipStream_t stream) {
+  constexpr int NT = TS * TS / PPT;
+  static const uint32_t cap_count = resident_groups(raster_fwd_kernel<T, TS, PPT, true>, NT);
+  static const uint32_t cap_plain = resident_groups(raster_fwd_kernel<T, TS, PPT, false>, NT);
+  const uint32_t cap = n_eval ? cap_count : cap_plain;
+  const uint32_t grid = total_tiles < cap ? total_tiles : cap;
+  if (grid == 0) return hipSuccess;
   if (n_eval)
-    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, true>), dim3(tiles), dim3(TS * TS / PPT), 0,
-                       stream, recs, values, ranges, v, st, image, T_final, n_contrib, n_eval);
+    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, true>), dim3(grid), dim3(NT), 0, stream,
+                       recs, n, values, ranges, slots, n_views, total_tiles, st, image, T_final,
+                       n_contrib, n_eval, tickets);
   else
-    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false>), dim3(tiles), dim3(TS * TS / PPT),
-                       0, stream, recs, values, ranges, v, st, image, T_final, n_contrib, n_eval);
+    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false>), dim3(grid), dim3(NT), 0, stream,
+                       recs, n, values, ranges, slots, n_views, total_tiles, st, image, T_final,
+                       n_contrib, n_eval, tickets);
   return hipGetLastError();
 }
 
 template <typename T, int TS, int PPT>
-hipError_t raster_bwd_cfg(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                          const ViewDev& v, const SettingsDev& st, const T* T_final,
+hipError_t raster_bwd_cfg(const Rec<T>* recs, uint32_t n, const uint32_t* values,
+                          const uint2* ranges, const ViewSlot* slots, int n_views,
+                          uint32_t total_tiles, const SettingsDev& st, const T* T_final,
                           const uint32_t* n_contrib, const T* dL_dimage, double* grad2d,
-                          uint32_t n_gaussians, hipStream_t stream) {
-  const int tiles = v.tiles_x * v.tiles_y;
-  hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT>), dim3(tiles), dim3(TS * TS / PPT), 0,
-                     stream, recs, values, ranges, v, st, T_final, n_contrib, dL_dimage, grad2d,
-                     n_gaussians);
+                          uint32_t* tickets, hipStream_t stream) {
+  constexpr int NT = TS * TS / PPT;
+  static const uint32_t cap = resident_groups(raster_bwd_kernel<T, TS, PPT>, NT);
+  const uint32_t grid = total_tiles < cap ? total_tiles : cap;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT>), dim3(grid), dim3(NT), 0, stream, recs, n,
+                     values, ranges, slots, n_views, total_tiles, st, T_final, n_contrib,
+                     dL_dimage, grad2d, tickets);
   return hipGetLastError();
 }
 
@@ -439,7 +566,7 @@ int raster_default_ppt(int tile_size, bool backward) {
 }
 
 #define R4D_RASTER_DISPATCH(FN, ...)                   \
-  switch (v.tile_size * 8 + ppt) {                     \
+  switch (tile_size * 8 + ppt) {                       \
     case 8 * 8 + 1: return FN<T, 8, 1>(__VA_ARGS__);   \
     case 16 * 8 + 1: return FN<T, 16, 1>(__VA_ARGS__); \
     case 16 * 8 + 2: return FN<T, 16, 2>(__VA_ARGS__); \
@@ -451,21 +578,23 @@ int raster_default_ppt(int tile_size, bool backward) {
   }
 
 template <typename T>
-hipError_t launch_raster_fwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                             const ViewDev& v, const SettingsDev& st, int ppt, T* image,
-                             T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
-                             hipStream_t stream) {
-  R4D_RASTER_DISPATCH(raster_fwd_cfg, recs, values, ranges, v, st, image, T_final, n_contrib,
-                      n_eval, stream)
+hipError_t launch_raster_fwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
+                             const uint2* ranges, const ViewSlot* slots, int n_views,
+                             uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
+                             T* image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
+                             uint32_t* tickets, hipStream_t stream) {
+  R4D_RASTER_DISPATCH(raster_fwd_cfg, recs, n, values, ranges, slots, n_views, total_tiles, st,
+                      image, T_final, n_contrib, n_eval, tickets, stream)
 }
 
 template <typename T>
-hipError_t launch_raster_bwd(const Rec<T>* recs, const uint32_t* values, const uint2* ranges,
-                             const ViewDev& v, const SettingsDev& st, int ppt, const T* T_final,
-                             const uint32_t* n_contrib, const T* dL_dimage, double* grad2d,
-                             uint32_t n_gaussians, hipStream_t stream) {
-  R4D_RASTER_DISPATCH(raster_bwd_cfg, recs, values, ranges, v, st, T_final, n_contrib, dL_dimage,
-                      grad2d, n_gaussians, stream)
+hipError_t launch_raster_bwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
+                             const uint2* ranges, const ViewSlot* slots, int n_views,
+                             uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
+                             const T* T_final, const uint32_t* n_contrib, const T* dL_dimage,
+                             double* grad2d, uint32_t* tickets, hipStream_t stream) {
+  R4D_RASTER_DISPATCH(raster_bwd_cfg, recs, n, values, ranges, slots, n_views, total_tiles, st,
+                      T_final, n_contrib, dL_dimage, grad2d, tickets, stream)
 }
 
 #undef R4D_RASTER_DISPATCH
@@ -474,7 +603,9 @@ hipError_t launch_l1_grad(const float* image, const float* target, int64_t count
                           float* loss, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   if (loss) {
-    hipError_t e = hipMemsetAsync(loss, 0, sizeof(float), stream);
+    // a kernel rather than a memset, so that the call may be captured in a graph
+    hipLaunchKernelGGL(zero_one_kernel, dim3(1), dim3(64), 0, stream, loss);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   // few fat blocks: the loss is summed with one atomic per block
@@ -485,19 +616,34 @@ hipError_t launch_l1_grad(const float* image, const float* target, int64_t count
   return hipGetLastError();
 }
 
-template hipError_t launch_raster_fwd<float>(const Rec<float>*, const uint32_t*, const uint2*,
-                                             const ViewDev&, const SettingsDev&, int, float*,
-                                             float*, uint32_t*, uint32_t*, hipStream_t);
-template hipError_t launch_raster_fwd<double>(const Rec<double>*, const uint32_t*, const uint2*,
-                                              const ViewDev&, const SettingsDev&, int, double*,
-                                              double*, uint32_t*, uint32_t*, hipStream_t);
-template hipError_t launch_raster_bwd<float>(const Rec<float>*, const uint32_t*, const uint2*,
-                                             const ViewDev&, const SettingsDev&, int,
-                                             const float*, const uint32_t*, const float*, double*,
-                                             uint32_t, hipStream_t);
-template hipError_t launch_raster_bwd<double>(const Rec<double>*, const uint32_t*, const uint2*,
-                                              const ViewDev&, const SettingsDev&, int,
-                                              const double*, const uint32_t*, const double*,
-                                              double*, uint32_t, hipStream_t);
+hipError_t launch_l1_grad_views(const float* images, const float* targets, const L1Views& lv,
+                                float* grad, float* loss, hipStream_t stream) {
+  int64_t most = 0;
+  for (int v = 0; v < lv.n_views; ++v) most = lv.count[v] > most ? lv.count[v] : most;
+  if (most == 0) return hipSuccess;
+  if (loss) {
+    hipLaunchKernelGGL(zero_one_kernel, dim3(1), dim3(64), 0, stream, loss);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  int64_t blocks = (most + 255) / 256;
+  if (blocks > 256) blocks = 256;
+  hipLaunchKernelGGL(l1_grad_views_kernel, dim3(uint32_t(blocks), uint32_t(lv.n_views)), dim3(256),
+                     0, stream, images, targets, lv, grad, loss);
+  return hipGetLastError();
+}
+
+#define R4D_INST(T)                                                                          \
+  template hipError_t launch_raster_fwd<T>(const Rec<T>*, uint32_t, const uint32_t*,          \
+                                           const uint2*, const ViewSlot*, int, uint32_t, int, \
+                                           const SettingsDev&, int, T*, T*, uint32_t*,        \
+                                           uint32_t*, uint32_t*, hipStream_t);                \
+  template hipError_t launch_raster_bwd<T>(const Rec<T>*, uint32_t, const uint32_t*,          \
+                                           const uint2*, const ViewSlot*, int, uint32_t, int, \
+                                           const SettingsDev&, int, const T*, const uint32_t*, \
+                                           const T*, double*, uint32_t*, hipStream_t);
+R4D_INST(float)
+R4D_INST(double)
+#undef R4D_INST
 
 }  // namespace r4d
