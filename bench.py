@@ -286,6 +286,12 @@ def main():
         # params + 9 screen-space gradients (double) read, 17 + 3k gradients written
         "preprocess_bwd": n * (68 + 12 * k) + n * 72 + n * 4 * (17 + 3 * k),
     }
+    if not stages.get("emit"):
+        # packed tile sort: emission fused into the low-digit pass (writes 4 B per
+        # entry), high-digit count (reads 4 B) and pass (reads 4 B, writes 4 B);
+        # rects, order and offsets read per Gaussian
+        alg_bytes.pop("emit")
+        alg_bytes["tile_sort"] = D * 16 + n * 2 * (8 + 4 + 8)
     dominant = max(stages, key=stages.get)
     dom_ms = stages[dominant]
     workload = "500k_1352x1014_tile16"

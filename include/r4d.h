@@ -110,8 +110,12 @@ typedef struct {
   int32_t fwd_pixels_per_thread;
   int32_t bwd_pixels_per_thread;
   int32_t mode;        /* R4D_MODE_* (R4D_MODE_PER_VIEW)                          */
-  int32_t sort_items;  /* keys per lane of the tile sort: 0 = automatic (16) or
-                          with tile_size 0 tuned; otherwise 8 or 16               */
+  int32_t sort_items;  /* tile sort: 0 = packed 32-bit entries with the emission
+                          fused into the first pass (renders of at most 65536
+                          tiles and at most 2^24 Gaussians; otherwise as 16);
+                          8 or 16 = (tile id, index) pairs sorted by a onesweep
+                          radix sort with this many keys per lane.  With
+                          tile_size 0 the autotuner picks 0 or 16.  (0)           */
 } r4d_settings;
 
 /* How a call with several views is executed.

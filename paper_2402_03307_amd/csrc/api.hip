@@ -42,10 +42,10 @@ struct GraphEntry;
 struct RunLayout {
   // fixed block
   size_t meta, recs, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp, ranges,
-      T_final, n_contrib, n_eval, zero_begin, totals, dhist, tickets, grids, dstatus, zero_end,
-      fixed_bytes;
+      T_final, n_contrib, n_eval, partials, zero_begin, totals, dhist, tickets, grids, dstatus,
+      zero_end, fixed_bytes;
   // entries block
-  size_t tkA, tkB, tvA, tvB, tstatus, entries_bytes;
+  size_t tkA, tkB, tvA, tvB, ptemp, tstatus, entries_bytes;
 };
 
 constexpr int kTicketTile = 4;     // tickets[0..3] depth passes, [4..6] tile passes
@@ -60,8 +60,10 @@ struct Plan {
   int deg = 0, ts = 16, fppt = 1, bppt = 4, sort_items = 16, mode = 0;
   std::vector<ViewSlot> slots;
   uint32_t total_tiles = 0;
-  uint64_t total_pix = 0, grid_cells = 0;
+  uint64_t total_pix = 0, grid_cells = 0, max_cells = 0;
+  uint32_t max_tiles = 0;
   int tile_passes = 1;
+  bool packed = true;   // packed tile sort (see packed_tile_sort_ok)
   SegTable dseg{};
   size_t scal = 4;
   bool count_evals = false;
@@ -377,12 +379,16 @@ Plan make_plan(const r4d_view* views, int V, uint32_t n, int deg, const r4d_sett
     sl.pix_base = p.total_pix;
     const uint64_t nt = uint64_t(sl.v.tiles_x) * uint64_t(sl.v.tiles_y);
     p.total_tiles += uint32_t(nt);
-    p.grid_cells += uint64_t(sl.v.tiles_x + 1) * uint64_t(sl.v.tiles_y + 1);
+    const uint64_t cells = uint64_t(sl.v.tiles_x + 1) * uint64_t(sl.v.tiles_y + 1);
+    p.grid_cells += cells;
+    p.max_cells = std::max(p.max_cells, cells);
     p.total_pix += uint64_t(views[i].width) * uint64_t(views[i].height);
     bits = std::max(bits, bits_for(nt));
+    p.max_tiles = std::max(p.max_tiles, uint32_t(nt));
     p.slots.push_back(sl);
   }
   p.tile_passes = (bits + 7) / 8;
+  p.packed = s.sort_items == 0 && packed_tile_sort_ok(n, p.max_tiles);
   p.dseg.count = uint32_t(V);
   p.dseg.overflow = 0;
   for (int v = 0; v <= V; ++v) p.dseg.start[v] = uint32_t(uint64_t(v) * p.n_pad);
@@ -416,6 +422,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.T_final = take(size_t(p.total_pix) * p.scal);
   L.n_contrib = take(size_t(p.total_pix) * 4);
   L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 4) : 0;
+  L.partials = take(size_t(p.grid_cells) * size_t(tile_grid_partials(p.n)) * 4);
   L.zero_begin = off;
   L.totals = take(2 * size_t(kMaxViews) * 8);
   L.dhist = take(4 * size_t(kMaxViews) * 256 * 4);
@@ -427,10 +434,17 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   off = 0;
   const size_t cap = size_t(capacity);
   L.tkA = take(cap * 4);
-  L.tkB = take(cap * 4);
   L.tvA = take(cap * 4);
-  L.tvB = take(cap * 4);
-  L.tstatus = take(size_t(p.tile_passes) * sort_status_words(capacity, p.sort_items) * 4);
+  if (p.packed) {
+    L.tkB = L.tvB = 0;
+    L.ptemp = take(packed_sort_temp_bytes(p.n_pad, p.V, capacity));
+    L.tstatus = off;  // nothing to zero
+  } else {
+    L.tkB = take(cap * 4);
+    L.tvB = take(cap * 4);
+    L.ptemp = 0;
+    L.tstatus = take(size_t(p.tile_passes) * sort_status_words(capacity, p.sort_items) * 4);
+  }
   L.entries_bytes = off;
   return L;
 }
@@ -488,8 +502,7 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     R4D_TIMED(kPreprocessFwd,
               launch_preprocess_fwd<T>(g, slots, p.V, st, p.n_pad, at<Rec<T>>(F, L.recs),
                                        at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
-                                       at<uint32_t>(F, L.dkeys), totals, at<int>(F, L.grids),
-                                       stream));
+                                       at<uint32_t>(F, L.dkeys), totals, stream));
   }
   hipEvent_t totals_ready = nullptr;
   if (sized) {
@@ -529,6 +542,7 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     L.tkB = L2.tkB;
     L.tvA = L2.tvA;
     L.tvB = L2.tvB;
+    L.ptemp = L2.ptemp;
     L.tstatus = L2.tstatus;
     L.entries_bytes = L2.entries_bytes;
     r.entries = static_cast<uint8_t*>(ctx_alloc(ctx, L.entries_bytes));
@@ -537,25 +551,39 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   }
   uint8_t* E = r.entries;
   auto* ranges = at<uint2>(F, L.ranges);
-  R4D_TIMED(kTileRanges, tile_counts(slots, p.V, at<int>(F, L.grids), totals, r.capacity, ranges,
-                                     at<uint32_t>(F, L.thist), tseg, stream));
+  {
+    StageTimer tm(ctx, kTileRanges, stream, timed);
+    R4D_HIP(tile_grids(at<Rect16>(F, L.rects), slots, p.V, p.n, p.max_cells, p.grid_cells,
+                       at<int>(F, L.partials), at<int>(F, L.grids), stream));
+    R4D_HIP(tile_counts(slots, p.V, p.max_cells, at<int>(F, L.grids), totals, r.capacity, ranges,
+                        at<uint32_t>(F, L.thist), tseg, stream));
+  }
   uint32_t* values = at<uint32_t>(E, L.tvA);
   if (p.n > 0) {
     auto* offsets = at<uint64_t>(F, L.offsets);
     R4D_TIMED(kCountScan, count_scan_seg(order, at<uint32_t>(F, L.tiles), p.n, p.n_pad, p.V,
                                          offsets, F + L.scan_tmp, stream));
-    R4D_HIP(fill_zero(E + L.tstatus, L.entries_bytes - L.tstatus, stream));
-    R4D_TIMED(kEmit, emit_tile_keys_seg(order, offsets, at<Rect16>(F, L.rects), slots, tseg, p.n,
-                                        p.n_pad, p.V, at<uint32_t>(E, L.tkA),
-                                        at<uint32_t>(E, L.tvA), stream));
-    uint32_t* kb[2] = {at<uint32_t>(E, L.tkB), at<uint32_t>(E, L.tkA)};
-    uint32_t* vb[2] = {at<uint32_t>(E, L.tvB), at<uint32_t>(E, L.tvA)};
-    int res = 0;
-    R4D_TIMED(kTileSort, onesweep_sort(at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA), kb, vb,
-                                       tseg, r.capacity, p.tile_passes, p.sort_items,
-                                       at<uint32_t>(F, L.thist), at<uint32_t>(E, L.tstatus),
-                                       tickets + kTicketTile, error, false, &res, stream));
-    values = vb[res];
+    if (p.packed) {
+      // emission fused with the low-digit pass, then the high-digit pass
+      StageTimer tm(ctx, kTileSort, stream, timed);
+      R4D_HIP(packed_tile_sort(order, offsets, at<Rect16>(F, L.rects), slots, tseg, p.n, p.n_pad,
+                               p.V, p.max_tiles, r.capacity, E + L.ptemp, at<uint32_t>(E, L.tkA),
+                               at<uint32_t>(E, L.tvA), stream));
+      values = at<uint32_t>(E, L.tvA);
+    } else {
+      R4D_HIP(fill_zero(E + L.tstatus, L.entries_bytes - L.tstatus, stream));
+      R4D_TIMED(kEmit, emit_tile_keys_seg(order, offsets, at<Rect16>(F, L.rects), slots, tseg,
+                                          p.n, p.n_pad, p.V, at<uint32_t>(E, L.tkA),
+                                          at<uint32_t>(E, L.tvA), stream));
+      uint32_t* kb[2] = {at<uint32_t>(E, L.tkB), at<uint32_t>(E, L.tkA)};
+      uint32_t* vb[2] = {at<uint32_t>(E, L.tvB), at<uint32_t>(E, L.tvA)};
+      int res = 0;
+      R4D_TIMED(kTileSort, onesweep_sort(at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA), kb, vb,
+                                         tseg, r.capacity, p.tile_passes, p.sort_items,
+                                         at<uint32_t>(F, L.thist), at<uint32_t>(E, L.tstatus),
+                                         tickets + kTicketTile, error, false, &res, stream));
+      values = vb[res];
+    }
   }
   r.values = values;
   R4D_TIMED(kRasterFwd,
@@ -837,7 +865,7 @@ r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, 
   int best_ts = 16, best_items = 16;
   r4d_status result = R4D_OK;
   for (int ts : {8, 16, 32}) {
-    for (int items : {8, 16}) {
+    for (int items : {0, 16}) {
       r4d_settings s = base;
       s.tile_size = ts;
       s.sort_items = items;
@@ -910,7 +938,6 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
     rs.tile_size = ts;
     rs.sort_items = items;
   }
-  if (rs.sort_items == 0) rs.sort_items = 16;
   const SettingsDev st = make_settings(rs);
   auto saved = std::make_unique<r4d_saved>();
   saved->ctx = ctx;

@@ -318,19 +318,90 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
   }
 }
 
-// One workgroup per render: 2D prefix sum of the rectangle difference grid
-// (rows, then columns) gives every tile's entry count; their exclusive scan in
-// tile order gives the tile ranges inside the render's segment of the emitted
-// list; their digit sums give the tile sort's histograms.  Also lays out the
-// segments (render v starts at the sum of the earlier renders' counts, each
-// rounded up to 4096) and reports overflow of the entry capacity, in which
-// case every segment is empty and every range is [0, 0).
+// Tile entry counts come from a 2D difference grid per render: a Gaussian
+// whose tile rectangle is [x0, x1) x [y0, y1) adds +1 at (x0, y0) and (x1, y1)
+// and -1 at (x1, y0) and (x0, y1) of a (tiles_x + 1) x (tiles_y + 1) grid, and
+// the 2D inclusive prefix sum of the grid is the number of rectangles holding
+// each tile.  Corners on the last row or column only reach grid cells outside
+// the tiles and are skipped.
+//
+// tile_grid_kernel (blockIdx.y = render): with LDS_GRID every workgroup adds
+// the corners of its share of the Gaussians into a private grid in LDS and
+// writes that grid out as one partial; otherwise (grids too large for LDS) it
+// adds them into one global grid with atomics.
+template <bool LDS_GRID>
+__global__ __launch_bounds__(kThreads) void tile_grid_kernel(const Rect16* __restrict__ rects,
+                                                             const ViewSlot* __restrict__ slots,
+                                                             uint32_t n, int* __restrict__ partials,
+                                                             int* __restrict__ grid) {
+  extern __shared__ int s_grid[];
+  const int v = blockIdx.y;
+  const ViewSlot& sl = slots[v];
+  const int tx = sl.v.tiles_x, ty = sl.v.tiles_y;
+  const int W1 = tx + 1;
+  const int cells = W1 * (ty + 1);
+  if (LDS_GRID) {
+    for (int i = threadIdx.x; i < cells; i += kThreads) s_grid[i] = 0;
+    __syncthreads();
+  }
+  int* gd = LDS_GRID ? s_grid : grid + sl.grid_base;
+  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t begin = blockIdx.x * per;
+  const uint32_t end = begin + per < n ? begin + per : n;
+  const Rect16* rv = rects + size_t(v) * n;
+  for (uint32_t i = begin + threadIdx.x; i < end; i += kThreads) {
+    const Rect16 r = rv[i];
+    if (r.x1 == r.x0) continue;  // culled: empty rectangle
+    const int x0 = r.x0, y0 = r.y0, x1 = r.x1, y1 = r.y1;
+    atomicAdd(&gd[y0 * W1 + x0], 1);
+    if (x1 < tx) atomicAdd(&gd[y0 * W1 + x1], -1);
+    if (y1 < ty) {
+      atomicAdd(&gd[y1 * W1 + x0], -1);
+      if (x1 < tx) atomicAdd(&gd[y1 * W1 + x1], 1);
+    }
+  }
+  if (LDS_GRID) {
+    __syncthreads();
+    int* out = partials + size_t(sl.grid_base) * gridDim.x + size_t(blockIdx.x) * cells;
+    for (int i = threadIdx.x; i < cells; i += kThreads) out[i] = s_grid[i];
+  }
+}
+
+// grid[c] = sum of the partial grids at cell c (cells of all renders).
+__global__ __launch_bounds__(kThreads) void grid_sum_kernel(const ViewSlot* __restrict__ slots,
+                                                            int n_views, const int* __restrict__ partials,
+                                                            int n_partials, uint32_t total_cells,
+                                                            int* __restrict__ grid) {
+  const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= total_cells) return;
+  int v = 0;
+  while (v + 1 < n_views && slots[v + 1].grid_base <= c) ++v;
+  const uint32_t gb = slots[v].grid_base;
+  const uint32_t cells = uint32_t(slots[v].v.tiles_x + 1) * uint32_t(slots[v].v.tiles_y + 1);
+  const int* pv = partials + size_t(gb) * n_partials + (c - gb);
+  int acc = 0;
+#pragma unroll 8
+  for (int b = 0; b < n_partials; ++b) acc += pv[size_t(b) * cells];
+  grid[c] = acc;
+}
+
+// One workgroup per render: takes the 2D prefix sum (in LDS when the grid
+// fits) (rows, then columns) to get every tile's entry count,
+// and scans the counts in tile order into the tile ranges inside the render's
+// segment of the emitted list; their digit sums give the tile sort's
+// histograms.  Also lays out the segments (render v starts at the sum of the
+// earlier renders' counts, each rounded up to 4096) and reports overflow of the
+// entry capacity, in which case every segment is empty and every range is
+// [0, 0).
 constexpr int kTcThreads = 1024;
 
+template <bool LDS_GRID>
 __global__ __launch_bounds__(kTcThreads) void tile_count_kernel(
     const ViewSlot* __restrict__ slots, int n_views, int* __restrict__ grid,
-    const unsigned long long* __restrict__ totals, unsigned long long capacity,
-    uint2* __restrict__ ranges, uint32_t* __restrict__ hist, SegTable* __restrict__ seg) {
+    const unsigned long long* __restrict__ totals,
+    unsigned long long capacity, uint2* __restrict__ ranges, uint32_t* __restrict__ hist,
+    SegTable* __restrict__ seg) {
+  extern __shared__ int s_grid[];
   __shared__ uint32_t s_h[3][256];
   __shared__ uint32_t s_w[kTcThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -362,8 +433,13 @@ __global__ __launch_bounds__(kTcThreads) void tile_count_kernel(
   if (overflow) {
     for (uint32_t t = tid; t < ntiles; t += kTcThreads) ranges[sl.tile_base + t] = make_uint2(0u, 0u);
   } else {
+    const int W1 = tx + 1, H1 = ty + 1, cells = W1 * H1;
     int* gd = grid + sl.grid_base;
-    const int W1 = tx + 1, H1 = ty + 1;
+    if (LDS_GRID) {
+      for (int i = tid; i < cells; i += kTcThreads) s_grid[i] = gd[i];
+      gd = s_grid;
+    }
+    __syncthreads();
     for (int row = wave; row < H1; row += kTcThreads / 64) {
       int carry = 0;
       for (int c0 = 0; c0 < W1; c0 += 64) {
@@ -510,6 +586,388 @@ uint32_t grid_for(size_t count) {
   return uint32_t(b < 4096 ? (b ? b : 1) : 4096);
 }
 
+// ---- packed tile sort
+// For renders with at most 65536 tiles and at most 2^24 Gaussians the tile
+// sort runs on one 32-bit word per entry: Gaussian index in bits 0..23, the
+// high 8 bits of the tile id in bits 24..31.  The entries of a render are
+// numbered in emission order (Gaussians in depth order, each one's tiles
+// row-major) and cut into blocks of 4096; block b of the render is also block
+// b of its segment of the sorted output.  Both passes are reduce-then-scan:
+// per-block digit counts, a column scan of those counts, then a stable
+// scatter, so no workgroup waits on another.  The first (low-digit) pass
+// generates its block's entries itself from the Gaussians' rectangles, so
+// the emitted list is never written.
+constexpr int kChunk = 4096;   // entries per block
+
+__device__ __forceinline__ bool block_span(const SegTable* seg, uint32_t e0, uint32_t& s,
+                                           uint32_t& sstart, uint32_t& nvalid) {
+  if (seg->count == 0u || e0 >= seg->start[seg->count]) return false;
+  s = segment_of(seg, e0);
+  sstart = seg->start[s];
+  const uint32_t send = sstart + seg->len[s];
+  nvalid = send > e0 ? (send - e0 < uint32_t(kChunk) ? send - e0 : uint32_t(kChunk)) : 0u;
+  return true;
+}
+
+// first[b] = depth position of the Gaussian whose entries contain the first
+// entry of block b.
+__global__ __launch_bounds__(kThreads) void first_gaussian_kernel(
+    const uint64_t* __restrict__ offsets, const SegTable* __restrict__ seg, uint32_t n,
+    uint32_t n_pad, uint32_t* __restrict__ first) {
+  const uint32_t v = blockIdx.y;
+  const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
+  if (seg->overflow || k >= n) return;
+  const size_t row = size_t(v) * n_pad;
+  const uint64_t o0 = offsets[row];
+  const uint32_t a = uint32_t(offsets[row + k] - o0), b = uint32_t(offsets[row + k + 1] - o0);
+  if (a == b) return;
+  const uint32_t sb = seg->start[v] / uint32_t(kChunk);
+  for (uint32_t blk = (a + kChunk - 1) / kChunk; blk * uint32_t(kChunk) < b; ++blk)
+    first[sb + blk] = k;
+}
+
+// Adds the low digits of tiles [t, t + len) (consecutive ids) to a 256-bin
+// difference array (plus a count added to every bin).
+__device__ __forceinline__ void add_digit_range(int* diff, uint32_t* all, uint32_t t, uint32_t len) {
+  if (len >= 256u) atomicAdd(all, len >> 8);
+  const uint32_t rem = len & 255u;
+  if (!rem) return;
+  const uint32_t a = t & 255u, e = a + rem;
+  atomicAdd(&diff[a], 1);
+  if (e <= 256u) {
+    atomicAdd(&diff[e], -1);
+  } else {
+    atomicAdd(&diff[256], -1);
+    atomicAdd(&diff[0], 1);
+    atomicAdd(&diff[e - 256u], -1);
+  }
+}
+
+// Low-digit counts of every block's entries, from the rectangles: the part of
+// a Gaussian inside a block is a run of its row-major tiles, i.e. a few row
+// segments of consecutive tile ids.
+__global__ __launch_bounds__(kThreads) void lo_count_kernel(
+    const uint32_t* __restrict__ order, const uint64_t* __restrict__ offsets,
+    const Rect16* __restrict__ rects, const ViewSlot* __restrict__ slots,
+    const SegTable* __restrict__ seg, const uint32_t* __restrict__ first, uint32_t n,
+    uint32_t n_pad, uint32_t* __restrict__ cnt) {
+  __shared__ int s_diff[257];
+  __shared__ uint32_t s_all;
+  __shared__ uint32_t s_w[kThreads / 64];
+  const uint32_t b = blockIdx.x;
+  s_diff[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    s_diff[256] = 0;
+    s_all = 0u;
+  }
+  __syncthreads();
+  uint32_t s = 0, sstart = 0, nvalid = 0;
+  if (!seg->overflow && block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) && nvalid) {
+    const uint32_t lo = b * uint32_t(kChunk) - sstart, hi = lo + nvalid;  // render-local entries
+    const size_t row = size_t(s) * n_pad;
+    const uint64_t o0 = offsets[row];
+    const uint32_t tiles_x = uint32_t(slots[s].v.tiles_x);
+    const uint32_t k0 = first[b];
+    for (uint32_t base = k0;; base += kThreads) {
+      const uint32_t k = base + threadIdx.x;
+      bool more = false;
+      if (k < n) {
+        const uint32_t a = uint32_t(offsets[row + k] - o0);
+        const uint32_t e = uint32_t(offsets[row + k + 1] - o0);
+        const uint32_t gi = order[row + k];
+        if (a < hi) {
+          more = true;
+          const uint32_t c0 = a > lo ? a : lo, c1 = e < hi ? e : hi;
+          if (c0 < c1) {
+            const Rect16 r = rects[size_t(s) * n + gi];
+            const uint32_t w = uint32_t(r.x1 - r.x0);
+            uint32_t q = c0 - a;
+            const uint32_t qe = c1 - a;
+            while (q < qe) {
+              const uint32_t y = q / w, x = q % w;
+              const uint32_t len = (w - x) < (qe - q) ? (w - x) : (qe - q);
+              add_digit_range(s_diff, &s_all, (uint32_t(r.y0) + y) * tiles_x + uint32_t(r.x0) + x,
+                              len);
+              q += len;
+            }
+          }
+        }
+      }
+      if (!__syncthreads_or(more)) break;
+    }
+  }
+  __syncthreads();
+  uint32_t tot;
+  const int x = s_diff[threadIdx.x];
+  const uint32_t incl = block_excl_scan<kThreads>(uint32_t(x), s_w, &tot) + uint32_t(x);
+  cnt[size_t(b) * 256 + threadIdx.x] = nvalid ? incl + s_all : 0u;
+}
+
+// Exclusive prefix of M[rows][256] along rows, per column: P[r][d] =
+// sum_{r' < r} M[r'][d] for r <= rows.  Three steps: per-stripe prefixes and
+// stripe totals, a scan of the stripe totals (one workgroup per column), and
+// their addition.
+constexpr int kStripe = 32;
+
+__global__ __launch_bounds__(256) void col_scan_stripes_kernel(const uint32_t* __restrict__ M,
+                                                               uint32_t rows,
+                                                               uint32_t* __restrict__ P,
+                                                               uint32_t* __restrict__ T) {
+  const uint32_t d = threadIdx.x, st = blockIdx.x;
+  const uint32_t r0 = st * kStripe;
+  uint32_t vals[kStripe];
+#pragma unroll
+  for (int i = 0; i < kStripe; ++i) {
+    const uint32_t r = r0 + i;
+    vals[i] = r < rows ? M[size_t(r) * 256 + d] : 0u;
+  }
+  uint32_t run = 0;
+#pragma unroll
+  for (int i = 0; i < kStripe; ++i) {
+    const uint32_t r = r0 + i;
+    if (r < rows) P[size_t(r) * 256 + d] = run;
+    run += vals[i];
+  }
+  T[size_t(st) * 256 + d] = run;
+}
+
+__global__ __launch_bounds__(256) void col_scan_totals_kernel(uint32_t* __restrict__ T,
+                                                              uint32_t stripes,
+                                                              uint32_t* __restrict__ P,
+                                                              uint32_t rows) {
+  __shared__ uint32_t s_w[256 / 64];
+  const uint32_t d = blockIdx.x;
+  uint32_t run = 0;
+  for (uint32_t s0 = 0; s0 < stripes; s0 += 256) {
+    const uint32_t st = s0 + threadIdx.x;
+    const uint32_t t = st < stripes ? T[size_t(st) * 256 + d] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<256>(t, s_w, &tot);
+    if (st < stripes) T[size_t(st) * 256 + d] = run + ex;
+    run += tot;
+  }
+  if (threadIdx.x == 0) P[size_t(rows) * 256 + d] = run;
+}
+
+__global__ __launch_bounds__(256) void col_scan_add_kernel(uint32_t* __restrict__ P, uint32_t rows,
+                                                           const uint32_t* __restrict__ T) {
+  const uint32_t d = threadIdx.x, st = blockIdx.x;
+  const uint32_t add = T[size_t(st) * 256 + d];
+  const uint32_t r0 = st * kStripe;
+#pragma unroll 8
+  for (int i = 0; i < kStripe; ++i) {
+    const uint32_t r = r0 + i;
+    if (r < rows) P[size_t(r) * 256 + d] += add;
+  }
+}
+
+// Per-digit output base of block b of the segment [first, end) of blocks:
+// segment start + counts of lower digits in the segment + counts of digit d
+// in the segment's earlier blocks.
+__device__ __forceinline__ uint32_t digit_out_base(const uint32_t* __restrict__ P, uint32_t first,
+                                                   uint32_t end, uint32_t b, uint32_t seg_start,
+                                                   uint32_t* s_w) {
+  const uint32_t d = threadIdx.x;
+  const uint32_t pf = P[size_t(first) * 256 + d];
+  const uint32_t tot_d = P[size_t(end) * 256 + d] - pf;
+  uint32_t tot;
+  const uint32_t lower = block_excl_scan<kThreads>(tot_d, s_w, &tot);
+  return seg_start + lower + (P[size_t(b) * 256 + d] - pf);
+}
+
+// Stable rank of a block's entries by a digit of `nbits` bits (entries held in
+// registers, wave w owning entries [w * 64 * ITEMS, (w + 1) * 64 * ITEMS)).
+// pos[i] receives the entry's position in the block sorted by digit; s_start
+// the exclusive prefix of the digit counts.
+template <int ITEMS>
+__device__ __forceinline__ void rank_block(const uint32_t (&dg)[ITEMS], uint32_t cn, int nbits,
+                                           uint32_t (*s_wh)[256], uint32_t* s_start,
+                                           uint32_t* s_w, uint32_t (&pos)[ITEMS]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) s_wh[w][tid] = 0u;
+  __syncthreads();
+  const uint32_t wbase = uint32_t(wave) * ITEMS * 64u;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const bool ok = wbase + uint32_t(i) * 64u + uint32_t(lane) < cn;
+    const uint32_t d = dg[i];
+    unsigned long long peers = __ballot(ok);
+    for (int bit = 0; bit < nbits; ++bit) {
+      const bool x = (d >> bit) & 1u;
+      const unsigned long long m = __ballot(x);
+      peers &= x ? m : ~m;
+    }
+    const uint32_t base = s_wh[wave][d];
+    const unsigned long long before = peers & lt;
+    pos[i] = base + uint32_t(__popcll(before));
+    if (ok && before == 0ull) s_wh[wave][d] = base + uint32_t(__popcll(peers));
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const uint32_t t = s_wh[w][tid];
+    s_wh[w][tid] = c;
+    c += t;
+  }
+  uint32_t tot;
+  s_start[tid] = block_excl_scan<kThreads>(c, s_w, &tot);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) pos[i] += s_start[dg[i]] + s_wh[wave][dg[i]];
+}
+
+// Low-digit pass: block b generates its entries (Gaussians from first[b] on,
+// each one's part inside the block written by the lanes of one wavefront),
+// ranks them stably by the low 8 bits of the tile id and writes them, as
+// packed words, in runs of equal digit to their place in the segment.
+__global__ __launch_bounds__(kThreads) void lo_pass_kernel(
+    const uint32_t* __restrict__ order, const uint64_t* __restrict__ offsets,
+    const Rect16* __restrict__ rects, const ViewSlot* __restrict__ slots,
+    const SegTable* __restrict__ seg, const uint32_t* __restrict__ first,
+    const uint32_t* __restrict__ P, uint32_t n, uint32_t n_pad, uint32_t* __restrict__ out) {
+  constexpr int ITEMS = kChunk / kThreads;
+  __shared__ uint32_t s_val[kChunk];
+  __shared__ uint8_t s_dig[kChunk];
+  __shared__ uint32_t s_base[256], s_start[256];
+  __shared__ uint32_t s_wh[kThreads / 64][256];
+  __shared__ uint32_t s_w[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t b = blockIdx.x;
+  uint32_t s, sstart, nvalid;
+  if (seg->overflow || !block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid)
+    return;
+  const uint32_t send = sstart + seg->len[s];
+  s_base[tid] = digit_out_base(P, sstart / uint32_t(kChunk),
+                               (send + uint32_t(kChunk) - 1) / uint32_t(kChunk), b, sstart, s_w);
+  const uint32_t lo = b * uint32_t(kChunk) - sstart, hi = lo + nvalid;  // render-local entries
+  const size_t row = size_t(s) * n_pad;
+  const uint64_t o0 = offsets[row];
+  const uint32_t tiles_x = uint32_t(slots[s].v.tiles_x);
+  // generate: wave w takes the Gaussians first[b] + 64 w + lane, then + 256, ...
+  const uint32_t k0 = first[b];
+  for (uint32_t base = k0 + uint32_t(wave) * 64u;; base += kThreads) {
+    const uint32_t k = base + uint32_t(lane);
+    uint32_t a = hi, e = hi, gi = 0;
+    if (k < n) {  // independent loads, issued together
+      a = uint32_t(offsets[row + k] - o0);
+      e = uint32_t(offsets[row + k + 1] - o0);
+      gi = order[row + k];
+    }
+    const uint32_t c0 = a > lo ? a : lo, c1 = e < hi ? e : hi;
+    const bool has = c0 < c1;
+    Rect16 r = {0, 0, 0, 0};
+    if (has) r = rects[size_t(s) * n + gi];
+    unsigned long long todo = __ballot(has);
+    while (todo) {
+      const int src = __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
+      const uint32_t sa = __shfl(a, src, 64), s0 = __shfl(c0, src, 64), s1 = __shfl(c1, src, 64);
+      const uint32_t sg = __shfl(gi, src, 64);
+      const uint32_t x0 = __shfl(uint32_t(r.x0), src, 64), y0 = __shfl(uint32_t(r.y0), src, 64);
+      const uint32_t w = __shfl(uint32_t(r.x1 - r.x0), src, 64);
+      for (uint32_t q = s0 + uint32_t(lane); q < s1; q += 64) {
+        const uint32_t local = q - sa;
+        const uint32_t tile = (y0 + local / w) * tiles_x + x0 + local % w;
+        s_val[q - lo] = sg | ((tile >> 8) << 24);
+        s_dig[q - lo] = uint8_t(tile & 255u);
+      }
+    }
+    // Gaussians start in increasing order: stop once every lane is past the block
+    if (!__any(k < n && a < hi)) break;
+  }
+  __syncthreads();
+  uint32_t v[ITEMS], dg[ITEMS], pos[ITEMS];
+  const uint32_t wbase = uint32_t(wave) * ITEMS * 64u;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t q = wbase + uint32_t(i) * 64u + uint32_t(lane);
+    v[i] = q < nvalid ? s_val[q] : 0u;
+    dg[i] = q < nvalid ? uint32_t(s_dig[q]) : 0u;
+  }
+  rank_block<ITEMS>(dg, nvalid, 8, s_wh, s_start, s_w, pos);
+  // (rank_block's barriers separate the reads above from the writes below)
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t q = wbase + uint32_t(i) * 64u + uint32_t(lane);
+    if (q < nvalid) {
+      s_val[pos[i]] = v[i];
+      s_dig[pos[i]] = uint8_t(dg[i]);
+    }
+  }
+  __syncthreads();
+  for (uint32_t p = tid; p < nvalid; p += kThreads) {
+    const uint32_t d = s_dig[p];
+    out[s_base[d] + (p - s_start[d])] = s_val[p];
+  }
+}
+
+// High-digit counts per block of the low-digit pass output.
+__global__ __launch_bounds__(kThreads) void hi_count_kernel(const uint32_t* __restrict__ in,
+                                                            const SegTable* __restrict__ seg,
+                                                            uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t s_h[kThreads / 64][256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) s_h[w][tid] = 0u;
+  __syncthreads();
+  const uint32_t b = blockIdx.x;
+  uint32_t s, sstart, nvalid = 0;
+  if (block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid)) {
+    const uint32_t e0 = b * uint32_t(kChunk);
+    for (uint32_t q = tid; q < nvalid; q += kThreads) atomicAdd(&s_h[wave][in[e0 + q] >> 24], 1u);
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) c += s_h[w][tid];
+  cnt[size_t(b) * 256 + tid] = c;
+}
+
+// High-digit pass: stable scatter of each block's entries by the high tile
+// digit (nbits significant bits); writes the Gaussian index (bits 0..23).
+__global__ __launch_bounds__(kThreads) void hi_pass_kernel(const uint32_t* __restrict__ in,
+                                                           const SegTable* __restrict__ seg,
+                                                           const uint32_t* __restrict__ P,
+                                                           int nbits,
+                                                           uint32_t* __restrict__ values) {
+  constexpr int ITEMS = kChunk / kThreads;
+  __shared__ uint32_t s_sorted[kChunk];
+  __shared__ uint32_t s_base[256], s_start[256];
+  __shared__ uint32_t s_wh[kThreads / 64][256];
+  __shared__ uint32_t s_w[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t b = blockIdx.x;
+  uint32_t s, sstart, nvalid;
+  if (!block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid) return;
+  const uint32_t send = sstart + seg->len[s];
+  const uint32_t e0 = b * uint32_t(kChunk);
+  uint32_t x[ITEMS], dg[ITEMS], pos[ITEMS];
+  const uint32_t wbase = uint32_t(wave) * ITEMS * 64u;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t q = wbase + uint32_t(i) * 64u + uint32_t(lane);
+    x[i] = q < nvalid ? in[e0 + q] : 0u;
+    dg[i] = x[i] >> 24;
+  }
+  s_base[tid] = digit_out_base(P, sstart / uint32_t(kChunk),
+                               (send + uint32_t(kChunk) - 1) / uint32_t(kChunk), b, sstart, s_w);
+  rank_block<ITEMS>(dg, nvalid, nbits, s_wh, s_start, s_w, pos);
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t q = wbase + uint32_t(i) * 64u + uint32_t(lane);
+    if (q < nvalid) s_sorted[pos[i]] = x[i];
+  }
+  __syncthreads();
+  for (uint32_t p = tid; p < nvalid; p += kThreads) {
+    const uint32_t y = s_sorted[p];
+    const uint32_t d = y >> 24;
+    values[s_base[d] + (p - s_start[d])] = y & 0xffffffu;
+  }
+}
+
 }  // namespace
 
 hipError_t fill_const(void* p, size_t count, double value, bool f64, hipStream_t stream) {
@@ -563,7 +1021,7 @@ uint32_t sort_status_words(uint64_t capacity_elems, int items) {
 hipError_t radix_histogram(const uint32_t* keys, const SegTable* seg, int n_segments,
                            uint32_t max_len, int passes, uint32_t* hist, hipStream_t stream) {
   if (max_len == 0 || n_segments <= 0) return hipSuccess;
-  const uint32_t chunk = 16384;
+  const uint32_t chunk = 4096;
   const dim3 grid((max_len + chunk - 1) / chunk, uint32_t(n_segments));
   switch (passes) {
     case 1: hipLaunchKernelGGL(radix_hist_kernel<1>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
@@ -613,11 +1071,64 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
   return hipSuccess;
 }
 
-hipError_t tile_counts(const ViewSlot* slots, int n_views, int* grid,
+int tile_grid_partials(uint32_t n) {
+  const uint32_t b = (n + 8191) / 8192;
+  return int(b < 1 ? 1 : (b > 64 ? 64 : b));
+}
+
+size_t tile_grid_lds_limit() {
+  static const size_t limit = [] {
+    int dev = 0, bytes = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      bytes = 65536;
+    }
+    // leave room for the counting kernel's static LDS
+    const size_t b = size_t(bytes) > 8192 ? size_t(bytes) - 8192 : 0;
+    if (b > 65536) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_grid_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(b));
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_count_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(b));
+      (void)hipGetLastError();
+    }
+    return b;
+  }();
+  return limit;
+}
+
+hipError_t tile_grids(const Rect16* rects, const ViewSlot* slots, int n_views, uint32_t n,
+                      uint64_t max_cells, uint64_t total_cells, int* partials, int* grid,
+                      hipStream_t stream) {
+  if (n == 0 || n_views <= 0) return hipSuccess;
+  const int B = tile_grid_partials(n);
+  const dim3 g{uint32_t(B), uint32_t(n_views), 1u};
+  const size_t lds = size_t(max_cells) * 4;
+  if (lds <= tile_grid_lds_limit()) {
+    hipLaunchKernelGGL(tile_grid_kernel<true>, g, dim3(kThreads), lds, stream, rects, slots, n,
+                       partials, grid);
+    hipLaunchKernelGGL(grid_sum_kernel, dim3(uint32_t((total_cells + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, stream, slots, n_views, partials, B,
+                       uint32_t(total_cells), grid);
+  } else {
+    hipLaunchKernelGGL(tile_grid_kernel<false>, g, dim3(kThreads), 0, stream, rects, slots, n,
+                       partials, grid);
+  }
+  return hipGetLastError();
+}
+
+hipError_t tile_counts(const ViewSlot* slots, int n_views, uint64_t max_cells, int* grid,
                        const unsigned long long* totals, unsigned long long capacity,
                        uint2* ranges, uint32_t* hist, SegTable* seg, hipStream_t stream) {
-  hipLaunchKernelGGL(tile_count_kernel, dim3(n_views), dim3(kTcThreads), 0, stream, slots,
-                     n_views, grid, totals, capacity, ranges, hist, seg);
+  const size_t lds = size_t(max_cells) * 4;
+  if (lds <= tile_grid_lds_limit())
+    hipLaunchKernelGGL(tile_count_kernel<true>, dim3(n_views), dim3(kTcThreads), lds, stream,
+                       slots, n_views, grid, totals, capacity, ranges, hist, seg);
+  else
+    hipLaunchKernelGGL(tile_count_kernel<false>, dim3(n_views), dim3(kTcThreads), 0, stream,
+                       slots, n_views, grid, totals, capacity, ranges, hist, seg);
   return hipGetLastError();
 }
 
@@ -641,6 +1152,65 @@ hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, co
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(emit_kernel, dim3((n + 255) / 256, uint32_t(n_views)), dim3(256), 0, stream,
                      order, offsets, rects, slots, seg, n, n_pad, keys, vals);
+  return hipGetLastError();
+}
+
+bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view) {
+  return n <= (1u << 24) && max_tiles_per_view <= 65536u;
+}
+
+size_t packed_sort_temp_bytes(uint32_t n_pad, int n_views, uint64_t capacity) {
+  (void)n_pad;
+  (void)n_views;
+  const uint64_t rows = (capacity + kChunk - 1) / kChunk;
+  const uint64_t stripes = (rows + kStripe - 1) / kStripe + 1;
+  // first[], and per pass: M, P, stripe totals
+  return size_t((rows + 64) * 4 + 2 * (rows * 256 + (rows + 1) * 256 + stripes * 256) * 4);
+}
+
+namespace {
+hipError_t col_scan(const uint32_t* M, uint32_t rows, uint32_t* P, uint32_t* T,
+                    hipStream_t stream) {
+  const uint32_t stripes = (rows + kStripe - 1) / kStripe;
+  if (stripes > 0)
+    hipLaunchKernelGGL(col_scan_stripes_kernel, dim3(stripes), dim3(256), 0, stream, M, rows, P,
+                       T);
+  hipLaunchKernelGGL(col_scan_totals_kernel, dim3(256), dim3(256), 0, stream, T, stripes, P, rows);
+  if (stripes > 0)
+    hipLaunchKernelGGL(col_scan_add_kernel, dim3(stripes), dim3(256), 0, stream, P, rows, T);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
+                            const ViewSlot* slots, const SegTable* seg, uint32_t n,
+                            uint32_t n_pad, int n_views, uint32_t max_tiles, uint64_t capacity,
+                            void* temp, uint32_t* lo_out, uint32_t* values, hipStream_t stream) {
+  const uint32_t rows = uint32_t((capacity + kChunk - 1) / kChunk);
+  if (n == 0 || n_views <= 0 || rows == 0) return hipSuccess;
+  const uint32_t stripes = (rows + kStripe - 1) / kStripe + 1;
+  uint32_t* first = static_cast<uint32_t*>(temp);
+  uint32_t* M1 = first + rows + 64;
+  uint32_t* P1 = M1 + size_t(rows) * 256;
+  uint32_t* T1 = P1 + size_t(rows + 1) * 256;
+  uint32_t* M2 = T1 + size_t(stripes) * 256;
+  uint32_t* P2 = M2 + size_t(rows) * 256;
+  uint32_t* T2 = P2 + size_t(rows + 1) * 256;
+  hipLaunchKernelGGL(first_gaussian_kernel, dim3((n + kThreads - 1) / kThreads, uint32_t(n_views)),
+                     dim3(kThreads), 0, stream, offsets, seg, n, n_pad, first);
+  hipLaunchKernelGGL(lo_count_kernel, dim3(rows), dim3(kThreads), 0, stream, order, offsets, rects,
+                     slots, seg, first, n, n_pad, M1);
+  hipError_t e = col_scan(M1, rows, P1, T1, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lo_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, order, offsets, rects,
+                     slots, seg, first, P1, n, n_pad, lo_out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(hi_count_kernel, dim3(rows), dim3(kThreads), 0, stream, lo_out, seg, M2);
+  if ((e = col_scan(M2, rows, P2, T2, stream)) != hipSuccess) return e;
+  int nbits = 1;
+  while ((1u << nbits) < (max_tiles + 255u) / 256u) ++nbits;
+  hipLaunchKernelGGL(hi_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, lo_out, seg, P2,
+                     nbits, values);
   return hipGetLastError();
 }
 

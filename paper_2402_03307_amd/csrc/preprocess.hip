@@ -54,8 +54,7 @@ template <typename T, int DEG>
 __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     GaussPtrs<T> g, const ViewSlot* __restrict__ slots, SettingsDev st, uint32_t n_pad,
     Rec<T>* __restrict__ recs, Rect16* __restrict__ rects, uint32_t* __restrict__ tiles_touched,
-    uint32_t* __restrict__ depth_keys, unsigned long long* __restrict__ totals,
-    int* __restrict__ grids) {
+    uint32_t* __restrict__ depth_keys, unsigned long long* __restrict__ totals) {
   __shared__ unsigned long long s_tot[2][kBlock / 64];
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -98,13 +97,6 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
         key = __float_as_uint(float(f.p[2]));
         recs[row + i] = rec;
         vis = true;
-        // 2D difference of the rectangle in the render's tile count grid
-        int* gd = grids + slots[vi].grid_base;
-        const int W1 = v.tiles_x + 1;
-        atomicAdd(&gd[int(rc.y0) * W1 + int(rc.x0)], 1);
-        atomicAdd(&gd[int(rc.y0) * W1 + int(rc.x1)], -1);
-        atomicAdd(&gd[int(rc.y1) * W1 + int(rc.x0)], -1);
-        atomicAdd(&gd[int(rc.y1) * W1 + int(rc.x1)], 1);
       } else {
         rc = {0, 0, 0, 0};
       }
@@ -216,11 +208,11 @@ template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
                                  Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
-                                 unsigned long long* totals, int* grids, hipStream_t stream) {
+                                 unsigned long long* totals, hipStream_t stream) {
   if (g.n <= 0 || n_views <= 0) return hipSuccess;
   const dim3 grid((g.n + kBlock - 1) / kBlock, uint32_t(n_views));
   R4D_DEG_DISPATCH(preprocess_fwd_kernel, grid, g, slots, st, n_pad, recs, rects, tiles_touched,
-                   depth_keys, totals, grids)
+                   depth_keys, totals)
   return hipGetLastError();
 }
 
@@ -252,7 +244,7 @@ hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
 #define R4D_INST(T)                                                                           \
   template hipError_t launch_preprocess_fwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
                                                const SettingsDev&, uint32_t, Rec<T>*, Rect16*, \
-                                               uint32_t*, uint32_t*, unsigned long long*, int*, \
+                                               uint32_t*, uint32_t*, unsigned long long*,      \
                                                hipStream_t);                                   \
   template hipError_t launch_preprocess_bwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
                                                const SettingsDev&, const double*,              \

@@ -57,14 +57,12 @@ struct SegTable {
 // ---- preprocess (per Gaussian and render)
 // Render v = blockIdx.y.  Per render: recs/rects/tiles_touched at [v][n],
 // depth_keys at [v * n_pad + i]; totals[2v] += visible Gaussians, totals[2v+1]
-// += tile entries; each visible Gaussian's rectangle is added to the render's
-// tile count grid as a 2D difference (+1, -1, -1, +1 at its corners).  The
-// caller zeroes totals and the grids.
+// += tile entries (the caller zeroes totals).
 template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
                                  Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
-                                 unsigned long long* totals, int* grids, hipStream_t stream);
+                                 unsigned long long* totals, hipStream_t stream);
 
 // grad2d: [V][9][n] double (mean2 x, y, Sigma_2D (0,0), (0,1), (1,1), opacity_t,
 // r, g, b).  Writes the parameter gradients summed over the renders.
@@ -99,11 +97,22 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
                          uint32_t* tickets, uint32_t* error, bool keys_needed, int* result_index,
                          hipStream_t stream);
 
-// Per render: tile entry counts from the difference grid, tile ranges
+// Tile count grids of every render from the Gaussians' tile rectangles
+// (rects [V][n]) into `grid` (zeroed; each render's (tiles_x + 1) x
+// (tiles_y + 1) grid at its grid_base).  max_cells: the largest grid of the
+// renders, total_cells: all of them.  When a grid fits in LDS the work goes
+// through tile_grid_partials(n) partial grids per render in `partials` ([all
+// cells] x partials); otherwise through atomics on `grid`.
+int tile_grid_partials(uint32_t n);
+hipError_t tile_grids(const Rect16* rects, const ViewSlot* slots, int n_views, uint32_t n,
+                      uint64_t max_cells, uint64_t total_cells, int* partials, int* grid,
+                      hipStream_t stream);
+
+// Per render: tile entry counts from the grids, tile ranges
 // (ranges[tile_base + t] = [start, end) in the emitted list, [0, 0) for a tile
-// without entries), tile-sort digit
-// histograms hist[3][kMaxViews][256] and the segment table of the emitted list.
-hipError_t tile_counts(const ViewSlot* slots, int n_views, int* grids,
+// without entries), tile-sort digit histograms hist[3][kMaxViews][256] and the
+// segment table of the emitted list.
+hipError_t tile_counts(const ViewSlot* slots, int n_views, uint64_t max_cells, int* grid,
                        const unsigned long long* totals, unsigned long long capacity,
                        uint2* ranges, uint32_t* hist, SegTable* seg, hipStream_t stream);
 
@@ -120,6 +129,20 @@ hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, co
                               const ViewSlot* slots, const SegTable* seg, uint32_t n,
                               uint32_t n_pad, int n_views, uint32_t* keys, uint32_t* vals,
                               hipStream_t stream);
+
+// Tile sort on packed 32-bit entries (see binning.hip), usable when
+// packed_tile_sort_ok: emission fused with the low-digit pass, then the
+// high-digit pass.  offsets: count_scan_seg's output; seg: the tile segment
+// table; max_tiles: the largest tile count of the renders; lo_out: capacity
+// words (the low-digit pass output); values: capacity
+// words, receives the sorted Gaussian indices; temp:
+// packed_sort_temp_bytes(n_pad, n_views, capacity) bytes.
+bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view);
+size_t packed_sort_temp_bytes(uint32_t n_pad, int n_views, uint64_t capacity);
+hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
+                            const ViewSlot* slots, const SegTable* seg, uint32_t n,
+                            uint32_t n_pad, int n_views, uint32_t max_tiles, uint64_t capacity,
+                            void* temp, uint32_t* lo_out, uint32_t* values, hipStream_t stream);
 
 // ---- rasterisation
 // (tile size, pixels per lane) pairs the rasteriser is compiled for.

@@ -180,6 +180,7 @@ __device__ __forceinline__ void raster_fwd_tile(
     const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
     const uint32_t jbase = base - rg.x;
     if (__ballot(!lane_done)) {
+#pragma unroll 2
       for (int j = 0; j < nb; ++j) {
         const Staged<T> r = s_rec[j];
 #pragma unroll
@@ -415,9 +416,11 @@ __device__ __forceinline__ int slot_of_tile(const ViewSlot* __restrict__ slots, 
   return lo;
 }
 
-// Persistent launches: each workgroup takes tiles (of any render) from a
-// counter until none is left, so renders of uneven size share one launch and
-// a workgroup that drew short lists simply takes more tiles.
+// Persistent launches: each workgroup starts on tile blockIdx.x and then takes
+// further tiles (of any render) from a counter until none is left, so renders
+// of uneven size share one launch and a workgroup that drew short lists simply
+// takes more tiles.  (The first tile comes from the launch itself: a counter
+// taken by every workgroup at once would serialise the start.)
 template <typename T, int TS, int PPT, bool COUNT>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     const Rec<T>* __restrict__ recs, uint32_t n, const uint32_t* __restrict__ values,
@@ -427,12 +430,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     uint32_t* __restrict__ tickets) {
   __shared__ Staged<T> s_rec[TileCfg<TS, PPT>::kBatch];
   __shared__ uint32_t s_ticket;
-  for (;;) {
-    if (threadIdx.x == 0) s_ticket = atomicAdd(tickets, 1u);
-    __syncthreads();
-    const uint32_t g = s_ticket;
-    __syncthreads();
-    if (g >= total_tiles) break;
+  for (uint32_t g = blockIdx.x; g < total_tiles;) {
     const int vi = slot_of_tile(slots, n_views, g);
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
@@ -440,6 +438,10 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     raster_fwd_tile<T, TS, PPT, COUNT>(s_rec, recs + size_t(vi) * n, values, ranges[g],
                                        int(g - sl.tile_base), v, st, image + 3 * pb, T_final + pb,
                                        n_contrib + pb, COUNT ? n_eval + pb : nullptr);
+    if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
+    __syncthreads();
+    g = s_ticket;
+    __syncthreads();
   }
 }
 
@@ -452,12 +454,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     double* __restrict__ grad2d, uint32_t* __restrict__ tickets) {
   __shared__ BwdShared<T, TS, PPT> sh;
   __shared__ uint32_t s_ticket;
-  for (;;) {
-    if (threadIdx.x == 0) s_ticket = atomicAdd(tickets, 1u);
-    __syncthreads();
-    const uint32_t g = s_ticket;
-    __syncthreads();
-    if (g >= total_tiles) break;
+  for (uint32_t g = blockIdx.x; g < total_tiles;) {
     const int vi = slot_of_tile(slots, n_views, g);
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
@@ -465,6 +462,10 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     raster_bwd_tile<T, TS, PPT>(sh, recs + size_t(vi) * n, values, ranges[g],
                                 int(g - sl.tile_base), v, st, T_final + pb, n_contrib + pb,
                                 dL_dimage + 3 * pb, grad2d + size_t(vi) * 9 * n, n);
+    if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
+    __syncthreads();
+    g = s_ticket;
+    __syncthreads();
   }
 }
 

@@ -51,17 +51,18 @@ def _run(rend, p, views, st, dl=None):
     return out, saved, grads
 
 
-@pytest.mark.parametrize("ts", [8, 16, 32])
-def test_modes_agree(r4d, device, ts):
+@pytest.mark.parametrize("ts,items", [(8, 0), (16, 0), (32, 0), (16, 16), (8, 8)])
+def test_modes_agree(r4d, device, ts, items):
     g, _, st = W.scene_2k()
     views = ragged_views()
-    print(f"case: 2k scene, 3 ragged views, tile {ts}", flush=True)
+    print(f"case: 2k scene, 3 ragged views, tile {ts}, tile sort keys per lane {items}",
+          flush=True)
     rend = r4d.Renderer(device)
     p = to_device(g, device)
     rng = np.random.default_rng(5)
     dl = [torch.as_tensor(rng.uniform(-1, 1, (3, v["height"], v["width"])),
                           dtype=torch.float32, device=device) for v in views]
-    base = dict(st, tile_size=ts)
+    base = dict(st, tile_size=ts, sort_items=items)
     ref_imgs, ref_saved, ref_grads = _run(rend, p, views, dict(base, mode="per_view"), dl)
     for mode in ("fused", "graph"):
         imgs, saved, grads = _run(rend, p, views, dict(base, mode=mode), dl)
@@ -156,7 +157,7 @@ def test_autotuner_choice_is_valid_and_image_unchanged(r4d, device):
         imgs, saved = rend.forward(p, views, dict(st, tile_size=0, mode=mode))
         cfg = saved.config()
         print(f"{mode}: autotuner picked {cfg}", flush=True)
-        assert cfg["tile_size"] in (8, 16, 32) and cfg["sort_items"] in (8, 16)
+        assert cfg["tile_size"] in (8, 16, 32) and cfg["sort_items"] in (0, 16)
         for a, b in zip(imgs, ref):
             assert torch.equal(a, b)
         dl = [torch.ones_like(i) for i in imgs]
