@@ -42,10 +42,10 @@ struct GraphEntry;
 struct RunLayout {
   // fixed block
   size_t meta, recs, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp, ranges,
-      T_final, n_contrib, n_eval, partials, zero_begin, totals, dhist, tickets, grids, dstatus,
-      zero_end, fixed_bytes;
+      T_final, n_contrib, n_eval, img_copy, walk, partials, zero_begin, totals, dhist, tickets,
+      grids, dstatus, zero_end, fixed_bytes;
   // entries block
-  size_t tkA, tkB, tvA, tvB, ptemp, tstatus, entries_bytes;
+  size_t tkA, tkB, tvA, tvB, ptemp, ck, tstatus, entries_bytes;
 };
 
 constexpr int kTicketTile = 4;     // tickets[0..3] depth passes, [4..6] tile passes
@@ -396,6 +396,16 @@ Plan make_plan(const r4d_view* views, int V, uint32_t n, int deg, const r4d_sett
   return p;
 }
 
+// Boundary-state slots of the backward's segment walks (see ck_slot).
+uint64_t ck_slots(const Plan& p, uint64_t capacity) {
+  return capacity / kSegment + uint64_t(p.total_tiles) + 2;
+}
+
+// Bound on the backward's (tile, segment) walks.
+uint64_t bwd_items(const Plan& p, uint64_t capacity) {
+  return capacity / kSegment + uint64_t(p.total_tiles) + 1;
+}
+
 RunLayout make_layout(const Plan& p, uint64_t capacity) {
   RunLayout L{};
   size_t off = 0;
@@ -422,6 +432,8 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.T_final = take(size_t(p.total_pix) * p.scal);
   L.n_contrib = take(size_t(p.total_pix) * 4);
   L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 4) : 0;
+  L.img_copy = take(3 * size_t(p.total_pix) * p.scal);
+  L.walk = take(size_t(p.total_tiles) * 4);
   L.partials = take(size_t(p.grid_cells) * size_t(tile_grid_partials(p.n)) * 4);
   L.zero_begin = off;
   L.totals = take(2 * size_t(kMaxViews) * 8);
@@ -435,6 +447,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   const size_t cap = size_t(capacity);
   L.tkA = take(cap * 4);
   L.tvA = take(cap * 4);
+  L.ck = take(size_t(ck_slots(p, capacity)) * size_t(p.ts) * size_t(p.ts) * 4 * p.scal);
   if (p.packed) {
     L.tkB = L.tvB = 0;
     L.ptemp = take(packed_sort_temp_bytes(p.n_pad, p.V, capacity));
@@ -543,6 +556,7 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     L.tvA = L2.tvA;
     L.tvB = L2.tvB;
     L.ptemp = L2.ptemp;
+    L.ck = L2.ck;
     L.tstatus = L2.tstatus;
     L.entries_bytes = L2.entries_bytes;
     r.entries = static_cast<uint8_t*>(ctx_alloc(ctx, L.entries_bytes));
@@ -586,11 +600,12 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     }
   }
   r.values = values;
+  const RasterSaved<T> sv{at<Ck<T>>(E, L.ck), at<T>(F, L.img_copy), at<uint32_t>(F, L.walk)};
   R4D_TIMED(kRasterFwd,
             launch_raster_fwd<T>(at<Rec<T>>(F, L.recs), p.n, values, ranges, slots, p.V,
                                  p.total_tiles, p.ts, st, p.fppt, images, at<T>(F, L.T_final),
                                  at<uint32_t>(F, L.n_contrib),
-                                 p.count_evals ? at<uint32_t>(F, L.n_eval) : nullptr,
+                                 p.count_evals ? at<uint32_t>(F, L.n_eval) : nullptr, sv,
                                  tickets + kTicketRaster, stream));
   return R4D_OK;
 }
@@ -666,22 +681,25 @@ r4d_status enqueue_backward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, co
                             bool timed, hipStream_t stream) {
   const Plan& p = r.plan;
   uint8_t* F = r.fixed;
-  const size_t g2_bytes = size_t(p.V) * 9 * size_t(p.n) * 8;
+  const size_t g2_bytes = align256(size_t(p.V) * 9 * size_t(p.n) * 8);
   auto* grad2d = reinterpret_cast<double*>(bwd_block);
-  auto* ticket = reinterpret_cast<uint32_t*>(bwd_block + align256(g2_bytes));
-  R4D_HIP(fill_zero(bwd_block, align256(g2_bytes) + 256, stream));
+  auto* work = reinterpret_cast<uint32_t*>(bwd_block + g2_bytes);
+  R4D_HIP(fill_zero(bwd_block, g2_bytes + 256, stream));
+  const RasterSaved<T> sv{at<Ck<T>>(r.entries, r.L.ck), at<T>(F, r.L.img_copy),
+                          at<uint32_t>(F, r.L.walk)};
   R4D_TIMED(kRasterBwd,
             launch_raster_bwd<T>(at<Rec<T>>(F, r.L.recs), p.n, r.values, at<uint2>(F, r.L.ranges),
-                                 slots_of(F, r.L), p.V, p.total_tiles, p.ts, st, p.bppt,
-                                 at<T>(F, r.L.T_final), at<uint32_t>(F, r.L.n_contrib), dL,
-                                 grad2d, ticket, stream));
+                                 slots_of(F, r.L), p.V, p.total_tiles, bwd_items(p, r.capacity),
+                                 p.ts, st, p.bppt, at<T>(F, r.L.T_final),
+                                 at<uint32_t>(F, r.L.n_contrib), sv, dL, grad2d, work, stream));
   R4D_TIMED(kPreprocessBwd,
             launch_preprocess_bwd<T>(g, slots_of(F, r.L), p.V, st, grad2d, out, stream));
   return R4D_OK;
 }
 
-size_t bwd_block_bytes(const Plan& p) {
-  return align256(size_t(p.V) * 9 * size_t(p.n) * 8) + 256;
+size_t bwd_block_bytes(const Plan& p, uint64_t capacity) {
+  return align256(size_t(p.V) * 9 * size_t(p.n) * 8) +
+         align256(raster_bwd_work_bytes(p.total_tiles, bwd_items(p, capacity)));
 }
 
 GaussPtrs<float> gauss_of(const r4d_gaussians* g) {
@@ -879,7 +897,7 @@ r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, 
         std::unique_ptr<RunState> r;
         result = run_sized<T>(ctx, g, p, images, st, false, stream, r);
         if (result != R4D_OK) break;
-        uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(p)));
+        uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(p, r->capacity)));
         if (!bb) {
           release_run(ctx, r.get());
           result = fail(ctx, R4D_ERR_OOM, "autotuner buffers");
@@ -1034,7 +1052,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
         e->bwd = nullptr;
       }
       if (!e->bwd_block) {
-        e->bwd_block = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(e->run.plan)));
+        e->bwd_block = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(e->run.plan, e->run.capacity)));
         if (!e->bwd_block) return fail(ctx, R4D_ERR_OOM, "graph backward buffers");
       }
       hipStream_t cs = ctx->capture_stream;
@@ -1057,7 +1075,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   }
   if (saved->runs.size() == 1) {
     RunState& r = *saved->runs[0];
-    uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan)));
+    uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan, r.capacity)));
     if (!bb) return fail(ctx, R4D_ERR_OOM, "backward buffers");
     s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, bb, st, out, timed, stream);
     ctx_free(ctx, bb);
@@ -1072,7 +1090,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   const GradPtrs<T> gt{tmp, tmp + 4 * n, tmp + 8 * n, tmp + 16 * n, tmp + 17 * n};
   for (size_t ri = 0; ri < saved->runs.size() && s == R4D_OK; ++ri) {
     RunState& r = *saved->runs[ri];
-    uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan)));
+    uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan, r.capacity)));
     if (!bb) {
       s = fail(ctx, R4D_ERR_OOM, "backward buffers");
       break;

@@ -1132,6 +1132,16 @@ hipError_t tile_counts(const ViewSlot* slots, int n_views, uint64_t max_cells, i
   return hipGetLastError();
 }
 
+size_t scan_u32_temp_bytes(uint32_t n) {
+  return (scan_temp_elems(uint64_t(n) + 1) + 4) * sizeof(uint32_t);
+}
+
+hipError_t scan_u32(const uint32_t* a, uint32_t n, uint32_t* out, void* temp, hipStream_t stream) {
+  return device_exclusive_scan<uint32_t, LoadT<uint32_t>>(LoadT<uint32_t>{a, n}, out,
+                                                          uint64_t(n) + 1,
+                                                          static_cast<uint32_t*>(temp), stream);
+}
+
 size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views) {
   return (scan_temp_elems(uint64_t(n_pad) * uint64_t(n_views) + 1) + 2) * sizeof(uint64_t);
 }

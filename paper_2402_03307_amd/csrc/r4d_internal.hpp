@@ -144,28 +144,65 @@ hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, cons
                             uint32_t n_pad, int n_views, uint32_t max_tiles, uint64_t capacity,
                             void* temp, uint32_t* lo_out, uint32_t* values, hipStream_t stream);
 
+// Exclusive scan of a[0..n) into out[0..n] (out[n] = total); temp holds
+// scan_u32_temp_bytes(n).
+size_t scan_u32_temp_bytes(uint32_t n);
+hipError_t scan_u32(const uint32_t* a, uint32_t n, uint32_t* out, void* temp, hipStream_t stream);
+
 // ---- rasterisation
+// The backward walks each tile's list in independent segments of kSegment
+// entries.  The forward saves, at every segment boundary inside a tile's
+// list, each pixel's transmittance and accumulated colour (Ck) in slot
+// ck_slot(list start, global tile, boundary index) of TS*TS pixels, the final
+// colour of every pixel, and each tile's walk length (its furthest last
+// contributor).  Slots stay below capacity / kSegment + tiles + 1.
+constexpr uint32_t kSegment = 256;
+
+template <typename T>
+struct Ck {
+  T t, r, g, b;
+};
+
+__host__ __device__ __forceinline__ uint32_t ck_slot(uint32_t list_start, uint32_t gtile,
+                                                     uint32_t m) {
+  return list_start / kSegment + gtile + m;
+}
+
+template <typename T>
+struct RasterSaved {
+  Ck<T>* ck;       // boundary states
+  T* img;          // final colour per pixel, laid out like the images
+  uint32_t* walk;  // per global tile
+};
+
 // (tile size, pixels per lane) pairs the rasteriser is compiled for.
 bool raster_config_supported(int tile_size, int ppt);
 int raster_default_ppt(int tile_size, bool backward);
 
 // Persistent launch over all tiles of all renders; tickets: 1 word, zeroed.
 // recs: [V][n]; image: [3][pixels of render v] at 3 * pix_base; T_final,
-// n_contrib, n_eval (nullable) per pixel at pix_base.
+// n_contrib, n_eval (nullable) per pixel at pix_base; sv: what the backward's
+// segment walks need (see kSegment).
 template <typename T>
 hipError_t launch_raster_fwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
                              const uint2* ranges, const ViewSlot* slots, int n_views,
                              uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
                              T* image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
-                             uint32_t* tickets, hipStream_t stream);
+                             const RasterSaved<T>& sv, uint32_t* tickets, hipStream_t stream);
 
-// grad2d: [V][9][n] double accumulators, added to.
+// Persistent launch over the (tile, segment) walks.  grad2d: [V][9][n] double
+// accumulators, added to.  max_items: bound on the number of walks
+// (capacity / kSegment + tiles + 1); work: raster_bwd_work_bytes, its first
+// 256 bytes zeroed.
+size_t raster_bwd_work_bytes(uint32_t total_tiles, uint64_t max_items);
 template <typename T>
 hipError_t launch_raster_bwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
                              const uint2* ranges, const ViewSlot* slots, int n_views,
-                             uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
-                             const T* T_final, const uint32_t* n_contrib, const T* dL_dimage,
-                             double* grad2d, uint32_t* tickets, hipStream_t stream);
+                             uint32_t total_tiles, uint64_t max_items, int tile_size,
+                             const SettingsDev& st, int ppt, const T* T_final,
+                             const uint32_t* n_contrib, const RasterSaved<T>& sv,
+                             const T* dL_dimage, double* grad2d, uint32_t* work,
+                             hipStream_t stream);
 
 hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, float* grad,
                           float* loss, hipStream_t stream);

@@ -145,12 +145,15 @@ struct TileCfg {
 // loop.  COUNT counts the entries each pixel evaluates (measurement builds only).
 template <typename T, int TS, int PPT, bool COUNT>
 __device__ __forceinline__ void raster_fwd_tile(
-    Staged<T>* s_rec, const Rec<T>* __restrict__ recs, const uint32_t* __restrict__ values,
-    const uint2 rg, int tile, const ViewDev& v, const SettingsDev& st, T* __restrict__ image,
-    T* __restrict__ T_final, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval) {
+    Staged<T>* s_rec, uint32_t* s_walk, const Rec<T>* __restrict__ recs,
+    const uint32_t* __restrict__ values, const uint2 rg, int tile, uint32_t gtile,
+    const ViewDev& v, const SettingsDev& st, T* __restrict__ image, T* __restrict__ T_final,
+    uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval, Ck<T>* __restrict__ ck,
+    T* __restrict__ img_copy, uint32_t* __restrict__ walk) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
+  static_assert(kSegment % NB == 0, "segment boundaries must fall on batch boundaries");
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int x = tx * TS + int(threadIdx.x % TS);
   const int y0 = ty * TS + int(threadIdx.x / TS);
@@ -169,6 +172,7 @@ __device__ __forceinline__ void raster_fwd_tile(
     c0[k] = c1[k] = c2[k] = T(0);
     last[k] = evals[k] = 0u;
   }
+  if (threadIdx.x == 0) *s_walk = 0u;
   for (uint32_t base = rg.x; base < rg.y; base += NB) {
     bool lane_done = true;
 #pragma unroll
@@ -202,22 +206,45 @@ __device__ __forceinline__ void raster_fwd_tile(
         }
       }
     }
+    // state after the first m segments of the list, for the backward's
+    // independent segment walks (only where the list goes on)
+    const uint32_t done_n = jbase + uint32_t(NB);
+    if (done_n % kSegment == 0u && base + NB < rg.y) {
+      Ck<T>* cs = ck + size_t(ck_slot(rg.x, gtile, done_n / kSegment)) * (TS * TS);
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        const int pt = (int(threadIdx.x / TS) + k * Cfg::kRowStep) * TS + int(threadIdx.x % TS);
+        cs[pt] = Ck<T>{Tr[k], c0[k], c1[k], c2[k]};
+      }
+    }
   }
   const long hw = long(v.H) * v.W;
+  uint32_t lane_walk = 0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int y = y0 + k * Cfg::kRowStep;
     if (x < v.W && y < v.H) {
       const long pix = long(y) * v.W + x;
       const T Tfin = Tr[k] != T(0) ? Tr[k] : Tf[k];
-      image[pix] = tfma(Tfin, T(v.bg[0]), c0[k]);
-      image[hw + pix] = tfma(Tfin, T(v.bg[1]), c1[k]);
-      image[2 * hw + pix] = tfma(Tfin, T(v.bg[2]), c2[k]);
+      const T o0 = tfma(Tfin, T(v.bg[0]), c0[k]);
+      const T o1 = tfma(Tfin, T(v.bg[1]), c1[k]);
+      const T o2 = tfma(Tfin, T(v.bg[2]), c2[k]);
+      image[pix] = o0;
+      image[hw + pix] = o1;
+      image[2 * hw + pix] = o2;
+      img_copy[pix] = o0;
+      img_copy[hw + pix] = o1;
+      img_copy[2 * hw + pix] = o2;
       T_final[pix] = Tfin;
       n_contrib[pix] = last[k];
       if (COUNT) n_eval[pix] = evals[k];
+      lane_walk = last[k] > lane_walk ? last[k] : lane_walk;
     }
   }
+  // the tile's backward walk: up to its furthest last contributor
+  if (lane_walk) atomicMax(s_walk, lane_walk);
+  __syncthreads();
+  if (threadIdx.x == 0) walk[gtile] = *s_walk;
 }
 
 template <typename T, int TS, int PPT>
@@ -231,9 +258,11 @@ struct BwdShared {
 template <typename T, int TS, int PPT>
 __device__ __forceinline__ void raster_bwd_tile(
     BwdShared<T, TS, PPT>& sh, const Rec<T>* __restrict__ recs,
-    const uint32_t* __restrict__ values, const uint2 rg, int tile, const ViewDev& v,
-    const SettingsDev& st, const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
-    const T* __restrict__ dL_dimage, double* __restrict__ grad2d, uint32_t n_gauss) {
+    const uint32_t* __restrict__ values, const uint2 rg, int tile, uint32_t gtile, uint32_t seg,
+    uint32_t walk, const ViewDev& v, const SettingsDev& st, const T* __restrict__ T_final,
+    const uint32_t* __restrict__ n_contrib, const T* __restrict__ img_copy,
+    const Ck<T>* __restrict__ ck, const T* __restrict__ dL_dimage, double* __restrict__ grad2d,
+    uint32_t n_gauss) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
@@ -248,9 +277,13 @@ __device__ __forceinline__ void raster_bwd_tile(
   const T e_min = T(kHalfLog2e) * T(st.ext2);
   const T amin = T(st.alpha_min), amax = T(st.alpha_max);
   const long hw = long(v.H) * v.W;
+  // this walk covers list positions [lo, hi) (segment `seg`, back to front)
+  const uint32_t lo = seg * kSegment;
+  const uint32_t seg_end = lo + kSegment;
+  const uint32_t hi = walk < seg_end ? walk : seg_end;
+  const Ck<T>* cs = ck + size_t(ck_slot(rg.x, gtile, seg + 1)) * (TS * TS);
   T py[PPT], Tcur[PPT], g0[PPT], g1[PPT], g2[PPT], acc0[PPT], acc1[PPT], acc2[PPT];
   uint32_t ncon[PPT];
-  uint32_t lane_max = 0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int y = y0 + k * Cfg::kRowStep;
@@ -258,28 +291,35 @@ __device__ __forceinline__ void raster_bwd_tile(
     Tcur[k] = T(1);
     g0[k] = g1[k] = g2[k] = T(0);
     ncon[k] = 0u;
+    acc0[k] = acc1[k] = acc2[k] = T(0);
     if (x < v.W && y < v.H) {
       const long pix = long(y) * v.W + x;
-      Tcur[k] = T_final[pix];
       ncon[k] = n_contrib[pix];
       g0[k] = dL_dimage[pix];
       g1[k] = dL_dimage[hw + pix];
       g2[k] = dL_dimage[2 * hw + pix];
+      if (ncon[k] > seg_end) {
+        // the pixel goes on past this segment: start from the forward's state
+        // at the segment's end; colour behind = final colour - colour in front
+        const int pt = (int(threadIdx.x / TS) + k * Cfg::kRowStep) * TS + int(threadIdx.x % TS);
+        const Ck<T> c = cs[pt];
+        Tcur[k] = c.t;
+        acc0[k] = img_copy[pix] - c.r;
+        acc1[k] = img_copy[hw + pix] - c.g;
+        acc2[k] = img_copy[2 * hw + pix] - c.b;
+      } else {
+        // colour accumulated behind the current Gaussian (absolute, includes background)
+        Tcur[k] = T_final[pix];
+        acc0[k] = Tcur[k] * T(v.bg[0]);
+        acc1[k] = Tcur[k] * T(v.bg[1]);
+        acc2[k] = Tcur[k] * T(v.bg[2]);
+      }
     }
-    // colour accumulated behind the current Gaussian (absolute, includes background)
-    acc0[k] = Tcur[k] * T(v.bg[0]);
-    acc1[k] = Tcur[k] * T(v.bg[1]);
-    acc2[k] = Tcur[k] * T(v.bg[2]);
-    lane_max = ncon[k] > lane_max ? ncon[k] : lane_max;
   }
-  if (threadIdx.x == 0) s_max = 0;
-  __syncthreads();
-  if (lane_max) atomicMax(&s_max, lane_max);
-  __syncthreads();
-  const uint32_t maxn = s_max;
+  (void)s_max;
   const int lane = threadIdx.x & 63;
-  for (uint32_t bend = maxn; bend > 0;) {
-    const uint32_t bstart = bend > uint32_t(NB) ? bend - NB : 0u;
+  for (uint32_t bend = hi; bend > lo;) {
+    const uint32_t bstart = bend > lo + uint32_t(NB) ? bend - NB : lo;
     const int nb = int(bend - bstart);
     if (threadIdx.x < NB) {
       if (int(threadIdx.x) < nb) {
@@ -426,18 +466,20 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     const Rec<T>* __restrict__ recs, uint32_t n, const uint32_t* __restrict__ values,
     const uint2* __restrict__ ranges, const ViewSlot* __restrict__ slots, int n_views,
     uint32_t total_tiles, SettingsDev st, T* __restrict__ image, T* __restrict__ T_final,
-    uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval,
+    uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval, RasterSaved<T> sv,
     uint32_t* __restrict__ tickets) {
   __shared__ Staged<T> s_rec[TileCfg<TS, PPT>::kBatch];
-  __shared__ uint32_t s_ticket;
+  __shared__ uint32_t s_ticket, s_walk;
   for (uint32_t g = blockIdx.x; g < total_tiles;) {
     const int vi = slot_of_tile(slots, n_views, g);
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
     const size_t pb = size_t(sl.pix_base);
-    raster_fwd_tile<T, TS, PPT, COUNT>(s_rec, recs + size_t(vi) * n, values, ranges[g],
-                                       int(g - sl.tile_base), v, st, image + 3 * pb, T_final + pb,
-                                       n_contrib + pb, COUNT ? n_eval + pb : nullptr);
+    raster_fwd_tile<T, TS, PPT, COUNT>(s_rec, &s_walk, recs + size_t(vi) * n, values, ranges[g],
+                                       int(g - sl.tile_base), g, v, st, image + 3 * pb,
+                                       T_final + pb, n_contrib + pb,
+                                       COUNT ? n_eval + pb : nullptr, sv.ck, sv.img + 3 * pb,
+                                       sv.walk);
     if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
     __syncthreads();
     g = s_ticket;
@@ -445,28 +487,56 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
   }
 }
 
+// Backward work items are (tile, segment) pairs: seg_tile[i] names the tile of
+// item i and seg_base[tile] its first item, so the segments of one long list
+// run in parallel.
 template <typename T, int TS, int PPT>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     const Rec<T>* __restrict__ recs, uint32_t n, const uint32_t* __restrict__ values,
     const uint2* __restrict__ ranges, const ViewSlot* __restrict__ slots, int n_views,
-    uint32_t total_tiles, SettingsDev st, const T* __restrict__ T_final,
-    const uint32_t* __restrict__ n_contrib, const T* __restrict__ dL_dimage,
-    double* __restrict__ grad2d, uint32_t* __restrict__ tickets) {
+    SettingsDev st, const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
+    RasterSaved<T> sv, const uint32_t* __restrict__ seg_tile,
+    const uint32_t* __restrict__ seg_base, const uint32_t* __restrict__ total_items,
+    const T* __restrict__ dL_dimage, double* __restrict__ grad2d,
+    uint32_t* __restrict__ tickets) {
   __shared__ BwdShared<T, TS, PPT> sh;
   __shared__ uint32_t s_ticket;
-  for (uint32_t g = blockIdx.x; g < total_tiles;) {
+  const uint32_t total = *total_items;
+  for (uint32_t it = blockIdx.x; it < total;) {
+    const uint32_t g = seg_tile[it];
+    const uint32_t seg = it - seg_base[g];
     const int vi = slot_of_tile(slots, n_views, g);
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
     const size_t pb = size_t(sl.pix_base);
     raster_bwd_tile<T, TS, PPT>(sh, recs + size_t(vi) * n, values, ranges[g],
-                                int(g - sl.tile_base), v, st, T_final + pb, n_contrib + pb,
-                                dL_dimage + 3 * pb, grad2d + size_t(vi) * 9 * n, n);
+                                int(g - sl.tile_base), g, seg, sv.walk[g], v, st, T_final + pb,
+                                n_contrib + pb, sv.img + 3 * pb, sv.ck, dL_dimage + 3 * pb,
+                                grad2d + size_t(vi) * 9 * n, n);
     if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
     __syncthreads();
-    g = s_ticket;
+    it = s_ticket;
     __syncthreads();
   }
+}
+
+// Segments of the backward walk: count per tile, their scan, the item -> tile
+// map.
+__global__ __launch_bounds__(256) void seg_count_kernel(const uint32_t* __restrict__ walk,
+                                                        uint32_t total_tiles,
+                                                        uint32_t* __restrict__ count) {
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t < total_tiles) count[t] = (walk[t] + kSegment - 1) / kSegment;
+}
+
+__global__ __launch_bounds__(256) void seg_map_kernel(const uint32_t* __restrict__ count,
+                                                      const uint32_t* __restrict__ base,
+                                                      uint32_t total_tiles,
+                                                      uint32_t* __restrict__ seg_tile) {
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= total_tiles) return;
+  const uint32_t b = base[t], c = count[t];
+  for (uint32_t i = 0; i < c; ++i) seg_tile[b + i] = t;
 }
 
 // Workgroups resident on the whole chip at once (occupancy x compute units);
@@ -513,8 +583,8 @@ template <typename T, int TS, int PPT>
 hipError_t raster_fwd_cfg(const Rec<T>* recs, uint32_t n, const uint32_t* values,
                           const uint2* ranges, const ViewSlot* slots, int n_views,
                           uint32_t total_tiles, const SettingsDev& st, T* image, T* T_final,
-                          uint32_t* n_contrib, uint32_t* n_eval, uint32_t* tickets,
-                          hipStream_t stream) {
+                          uint32_t* n_contrib, uint32_t* n_eval, const RasterSaved<T>& sv,
+                          uint32_t* tickets, hipStream_t stream) {
   constexpr int NT = TS * TS / PPT;
   static const uint32_t cap_count = resident_groups(raster_fwd_kernel<T, TS, PPT, true>, NT);
   static const uint32_t cap_plain = resident_groups(raster_fwd_kernel<T, TS, PPT, false>, NT);
@@ -524,31 +594,50 @@ hipError_t raster_fwd_cfg(const Rec<T>* recs, uint32_t n, const uint32_t* values
   if (n_eval)
     hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, true>), dim3(grid), dim3(NT), 0, stream,
                        recs, n, values, ranges, slots, n_views, total_tiles, st, image, T_final,
-                       n_contrib, n_eval, tickets);
+                       n_contrib, n_eval, sv, tickets);
   else
     hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false>), dim3(grid), dim3(NT), 0, stream,
                        recs, n, values, ranges, slots, n_views, total_tiles, st, image, T_final,
-                       n_contrib, n_eval, tickets);
+                       n_contrib, n_eval, sv, tickets);
   return hipGetLastError();
 }
 
 template <typename T, int TS, int PPT>
 hipError_t raster_bwd_cfg(const Rec<T>* recs, uint32_t n, const uint32_t* values,
                           const uint2* ranges, const ViewSlot* slots, int n_views,
-                          uint32_t total_tiles, const SettingsDev& st, const T* T_final,
-                          const uint32_t* n_contrib, const T* dL_dimage, double* grad2d,
-                          uint32_t* tickets, hipStream_t stream) {
+                          uint32_t total_tiles, uint64_t max_items, const SettingsDev& st,
+                          const T* T_final, const uint32_t* n_contrib, const RasterSaved<T>& sv,
+                          const T* dL_dimage, double* grad2d, uint32_t* work,
+                          hipStream_t stream) {
   constexpr int NT = TS * TS / PPT;
+  if (total_tiles == 0) return hipSuccess;
+  // work: [tickets (64 words, zeroed by the caller) | count | base | seg_tile | scan scratch]
+  uint32_t* tickets = work;
+  uint32_t* count = work + 64;
+  uint32_t* base = count + total_tiles + 1;
+  uint32_t* seg_tile = base + total_tiles + 1;
+  uint32_t* scan_tmp = seg_tile + max_items;
+  const uint32_t tb = (total_tiles + 255) / 256;
+  hipLaunchKernelGGL(seg_count_kernel, dim3(tb), dim3(256), 0, stream, sv.walk, total_tiles, count);
+  hipError_t e = scan_u32(count, total_tiles, base, scan_tmp, stream);  // base[total_tiles] = total
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(seg_map_kernel, dim3(tb), dim3(256), 0, stream, count, base, total_tiles,
+                     seg_tile);
   static const uint32_t cap = resident_groups(raster_bwd_kernel<T, TS, PPT>, NT);
-  const uint32_t grid = total_tiles < cap ? total_tiles : cap;
+  const uint32_t grid = uint32_t(max_items < cap ? max_items : cap);
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT>), dim3(grid), dim3(NT), 0, stream, recs, n,
-                     values, ranges, slots, n_views, total_tiles, st, T_final, n_contrib,
-                     dL_dimage, grad2d, tickets);
+                     values, ranges, slots, n_views, st, T_final, n_contrib, sv, seg_tile, base,
+                     base + total_tiles, dL_dimage, grad2d, tickets);
   return hipGetLastError();
 }
 
 }  // namespace
+
+size_t raster_bwd_work_bytes(uint32_t total_tiles, uint64_t max_items) {
+  return (2 * (size_t(total_tiles) + 1) + size_t(max_items) + 64) * 4 +
+         scan_u32_temp_bytes(total_tiles + 1);
+}
 
 bool raster_config_supported(int tile_size, int ppt) {
   switch (tile_size) {
@@ -583,19 +672,21 @@ hipError_t launch_raster_fwd(const Rec<T>* recs, uint32_t n, const uint32_t* val
                              const uint2* ranges, const ViewSlot* slots, int n_views,
                              uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
                              T* image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
-                             uint32_t* tickets, hipStream_t stream) {
+                             const RasterSaved<T>& sv, uint32_t* tickets, hipStream_t stream) {
   R4D_RASTER_DISPATCH(raster_fwd_cfg, recs, n, values, ranges, slots, n_views, total_tiles, st,
-                      image, T_final, n_contrib, n_eval, tickets, stream)
+                      image, T_final, n_contrib, n_eval, sv, tickets, stream)
 }
 
 template <typename T>
 hipError_t launch_raster_bwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
                              const uint2* ranges, const ViewSlot* slots, int n_views,
-                             uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
-                             const T* T_final, const uint32_t* n_contrib, const T* dL_dimage,
-                             double* grad2d, uint32_t* tickets, hipStream_t stream) {
-  R4D_RASTER_DISPATCH(raster_bwd_cfg, recs, n, values, ranges, slots, n_views, total_tiles, st,
-                      T_final, n_contrib, dL_dimage, grad2d, tickets, stream)
+                             uint32_t total_tiles, uint64_t max_items, int tile_size,
+                             const SettingsDev& st, int ppt, const T* T_final,
+                             const uint32_t* n_contrib, const RasterSaved<T>& sv,
+                             const T* dL_dimage, double* grad2d, uint32_t* work,
+                             hipStream_t stream) {
+  R4D_RASTER_DISPATCH(raster_bwd_cfg, recs, n, values, ranges, slots, n_views, total_tiles,
+                      max_items, st, T_final, n_contrib, sv, dL_dimage, grad2d, work, stream)
 }
 
 #undef R4D_RASTER_DISPATCH
@@ -638,11 +729,13 @@ hipError_t launch_l1_grad_views(const float* images, const float* targets, const
   template hipError_t launch_raster_fwd<T>(const Rec<T>*, uint32_t, const uint32_t*,          \
                                            const uint2*, const ViewSlot*, int, uint32_t, int, \
                                            const SettingsDev&, int, T*, T*, uint32_t*,        \
-                                           uint32_t*, uint32_t*, hipStream_t);                \
+                                           uint32_t*, const RasterSaved<T>&, uint32_t*,       \
+                                           hipStream_t);                                      \
   template hipError_t launch_raster_bwd<T>(const Rec<T>*, uint32_t, const uint32_t*,          \
-                                           const uint2*, const ViewSlot*, int, uint32_t, int, \
-                                           const SettingsDev&, int, const T*, const uint32_t*, \
-                                           const T*, double*, uint32_t*, hipStream_t);
+                                           const uint2*, const ViewSlot*, int, uint32_t,      \
+                                           uint64_t, int, const SettingsDev&, int, const T*,  \
+                                           const uint32_t*, const RasterSaved<T>&, const T*,  \
+                                           double*, uint32_t*, hipStream_t);
 R4D_INST(float)
 R4D_INST(double)
 #undef R4D_INST
