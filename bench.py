@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched and per-config measurements")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched-vs-plain measurement (for profiling it)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
                          "known traffic, to scale hardware byte counters)")
@@ -213,6 +215,10 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.only_batched:
+        rend = r4d.Renderer(dev)
+        print(json.dumps({"batched_vs_plain": batched_vs_plain(r4d, rend, dev, args)}), flush=True)
+        return
     g, views, st = W.scene_500k_step()
     st = dict(st, tile_size=args.tile_size, fwd_pixels_per_thread=args.fwd_ppt,
               bwd_pixels_per_thread=args.bwd_ppt)
