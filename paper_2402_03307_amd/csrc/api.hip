@@ -567,8 +567,9 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   auto* ranges = at<uint2>(F, L.ranges);
   {
     StageTimer tm(ctx, kTileRanges, stream, timed);
-    R4D_HIP(tile_grids(at<Rect16>(F, L.rects), slots, p.V, p.n, p.max_cells, p.grid_cells,
-                       at<int>(F, L.partials), at<int>(F, L.grids), stream));
+    R4D_HIP(tile_grids<T>(at<Rect16>(F, L.rects), at<Rec<T>>(F, L.recs), slots, p.V, p.n,
+                          p.max_cells, p.grid_cells, at<int>(F, L.partials), at<int>(F, L.grids),
+                          stream));
     R4D_HIP(tile_counts(slots, p.V, p.max_cells, at<int>(F, L.grids), totals, r.capacity, ranges,
                         at<uint32_t>(F, L.thist), tseg, stream));
   }
@@ -580,15 +581,17 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     if (p.packed) {
       // emission fused with the low-digit pass, then the high-digit pass
       StageTimer tm(ctx, kTileSort, stream, timed);
-      R4D_HIP(packed_tile_sort(order, offsets, at<Rect16>(F, L.rects), slots, tseg, p.n, p.n_pad,
-                               p.V, p.max_tiles, r.capacity, E + L.ptemp, at<uint32_t>(E, L.tkA),
-                               at<uint32_t>(E, L.tvA), stream));
+      R4D_HIP(packed_tile_sort<T>(order, offsets, at<Rect16>(F, L.rects), at<Rec<T>>(F, L.recs),
+                                  slots, tseg, p.n, p.n_pad, p.V, p.max_tiles, r.capacity,
+                                  E + L.ptemp, at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA),
+                                  stream));
       values = at<uint32_t>(E, L.tvA);
     } else {
       R4D_HIP(fill_zero(E + L.tstatus, L.entries_bytes - L.tstatus, stream));
-      R4D_TIMED(kEmit, emit_tile_keys_seg(order, offsets, at<Rect16>(F, L.rects), slots, tseg,
-                                          p.n, p.n_pad, p.V, at<uint32_t>(E, L.tkA),
-                                          at<uint32_t>(E, L.tvA), stream));
+      R4D_TIMED(kEmit, emit_tile_keys_seg<T>(order, offsets, at<Rect16>(F, L.rects),
+                                             at<Rec<T>>(F, L.recs), slots, tseg, p.n, p.n_pad,
+                                             p.V, at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA),
+                                             stream));
       uint32_t* kb[2] = {at<uint32_t>(E, L.tkB), at<uint32_t>(E, L.tkA)};
       uint32_t* vb[2] = {at<uint32_t>(E, L.tvB), at<uint32_t>(E, L.tvA)};
       int res = 0;

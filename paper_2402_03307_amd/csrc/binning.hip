@@ -12,10 +12,11 @@
 //
 // Several renders are processed at once as segments of one array: segment s
 // starts at a multiple of 4096 elements and every sort pass works within
-// segments only.  Per-tile entry counts do not need the emitted keys: the
-// preprocess adds each Gaussian's tile rectangle into a 2D difference grid, and
-// its 2D prefix sum is the count of every tile.  Their exclusive scan is the
-// tile ranges, and their digit sums are the digit histograms of the tile sort.
+// segments only.  Per-tile entry counts do not need the emitted keys: every
+// row run of every Gaussian (tileset.hpp) adds +1 at its first tile and -1
+// after its last into a difference grid, and the grid's prefix sum along rows
+// is the count of every tile.  Their exclusive scan is the tile ranges, and
+// their digit sums are the digit histograms of the tile sort.
 //
 // Onesweep pass: every workgroup takes a ticket (its position in the sort
 // order, in launch order, so that every lower ticket belongs to a workgroup
@@ -28,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include "r4d_internal.hpp"
+#include "tileset.hpp"
 
 namespace r4d {
 
@@ -79,6 +81,40 @@ __device__ __forceinline__ T block_excl_scan(T x, T* s_w, T* total) {
 // ---- device-wide exclusive scan (multi-level: tile sums are scanned recursively)
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kThreads * kScanItems;
+
+// Row-run constants of a Gaussian from its record and the bounding box of its
+// runs.
+template <typename T>
+__device__ __forceinline__ SpanGeom geom_of(const Rec<T>& r, const Rect16& box, const ViewDev& v) {
+  return span_geom(double(r.mx), double(r.my), double(r.ca), double(r.cb), double(r.cc),
+                   double(r.qmax), v.W, v.H, __builtin_ctz(unsigned(v.tile_size)), box.x0,
+                   box.x1);
+}
+
+// Entries [q0, q1) of one Gaussian (indices local to the Gaussian, in the
+// order of its tile list: rows top to bottom, columns left to right), the
+// whole wavefront cooperating: lane l takes tile row y0 + l (then + 64, ...),
+// a wave scan of the run lengths places every row, and each lane calls
+// put(j, tile) for the entries j of its row in [q0, q1).  Every lane must call
+// it with the same arguments.
+template <typename Put>
+__device__ __forceinline__ void wave_runs(const SpanGeom& sg, int y0, int y1, uint32_t tiles_x,
+                                          uint32_t q0, uint32_t q1, int lane, Put put) {
+  uint32_t carry = 0;
+  for (int yb = y0; yb < y1 && carry < q1; yb += 64) {
+    const int y = yb + lane;
+    int a = 0, b = 0;
+    if (y < y1) row_span(sg, y, a, b);
+    const uint32_t len = uint32_t(b - a);
+    const uint32_t incl = wave_incl_scan(len, lane);
+    const uint32_t start = carry + incl - len;
+    const uint32_t j0 = start > q0 ? start : q0;
+    const uint32_t j1 = start + len < q1 ? start + len : q1;
+    const uint32_t t0 = uint32_t(y) * tiles_x + uint32_t(a) - start;  // tile of entry j: t0 + j
+    for (uint32_t j = j0; j < j1; ++j) put(j, t0 + j);
+    carry += __shfl(incl, 63, 64);
+  }
+}
 
 template <typename T>
 struct LoadT {
@@ -318,26 +354,25 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
   }
 }
 
-// Tile entry counts come from a 2D difference grid per render: a Gaussian
-// whose tile rectangle is [x0, x1) x [y0, y1) adds +1 at (x0, y0) and (x1, y1)
-// and -1 at (x1, y0) and (x0, y1) of a (tiles_x + 1) x (tiles_y + 1) grid, and
-// the 2D inclusive prefix sum of the grid is the number of rectangles holding
-// each tile.  Corners on the last row or column only reach grid cells outside
-// the tiles and are skipped.
+// Difference grids: every row run [x0, x1) of row y adds +1 at (y, x0) and -1
+// at (y, x1) (skipped when x1 is past the last column), so the prefix sum of a
+// grid row is the entry count of each of its tiles.
 //
 // tile_grid_kernel (blockIdx.y = render): with LDS_GRID every workgroup adds
-// the corners of its share of the Gaussians into a private grid in LDS and
+// the runs of its share of the Gaussians into a private grid in LDS and
 // writes that grid out as one partial; otherwise (grids too large for LDS) it
 // adds them into one global grid with atomics.
-template <bool LDS_GRID>
+template <typename T, bool LDS_GRID>
 __global__ __launch_bounds__(kThreads) void tile_grid_kernel(const Rect16* __restrict__ rects,
+                                                             const Rec<T>* __restrict__ recs,
                                                              const ViewSlot* __restrict__ slots,
                                                              uint32_t n, int* __restrict__ partials,
                                                              int* __restrict__ grid) {
   extern __shared__ int s_grid[];
   const int v = blockIdx.y;
   const ViewSlot& sl = slots[v];
-  const int tx = sl.v.tiles_x, ty = sl.v.tiles_y;
+  const ViewDev vd = sl.v;
+  const int tx = vd.tiles_x, ty = vd.tiles_y;
   const int W1 = tx + 1;
   const int cells = W1 * (ty + 1);
   if (LDS_GRID) {
@@ -349,15 +384,16 @@ __global__ __launch_bounds__(kThreads) void tile_grid_kernel(const Rect16* __res
   const uint32_t begin = blockIdx.x * per;
   const uint32_t end = begin + per < n ? begin + per : n;
   const Rect16* rv = rects + size_t(v) * n;
+  const Rec<T>* cv = recs + size_t(v) * n;
   for (uint32_t i = begin + threadIdx.x; i < end; i += kThreads) {
     const Rect16 r = rv[i];
-    if (r.x1 == r.x0) continue;  // culled: empty rectangle
-    const int x0 = r.x0, y0 = r.y0, x1 = r.x1, y1 = r.y1;
-    atomicAdd(&gd[y0 * W1 + x0], 1);
-    if (x1 < tx) atomicAdd(&gd[y0 * W1 + x1], -1);
-    if (y1 < ty) {
-      atomicAdd(&gd[y1 * W1 + x0], -1);
-      if (x1 < tx) atomicAdd(&gd[y1 * W1 + x1], 1);
+    if (r.x1 == r.x0) continue;  // culled: empty box
+    const SpanGeom sg = geom_of(cv[i], r, vd);
+    for (int y = r.y0; y < r.y1; ++y) {
+      int x0, x1;
+      row_span(sg, y, x0, x1);
+      atomicAdd(&gd[y * W1 + x0], 1);
+      if (x1 < tx) atomicAdd(&gd[y * W1 + x1], -1);
     }
   }
   if (LDS_GRID) {
@@ -385,8 +421,8 @@ __global__ __launch_bounds__(kThreads) void grid_sum_kernel(const ViewSlot* __re
   grid[c] = acc;
 }
 
-// One workgroup per render: takes the 2D prefix sum (in LDS when the grid
-// fits) (rows, then columns) to get every tile's entry count,
+// One workgroup per render: takes the prefix sum of every grid row (in LDS when
+// the grid fits) to get every tile's entry count,
 // and scans the counts in tile order into the tile ranges inside the render's
 // segment of the emitted list; their digit sums give the tile sort's
 // histograms.  Also lays out the segments (render v starts at the sum of the
@@ -440,36 +476,30 @@ __global__ __launch_bounds__(kTcThreads) void tile_count_kernel(
       gd = s_grid;
     }
     __syncthreads();
-    for (int row = wave; row < H1; row += kTcThreads / 64) {
+    for (int row = wave; row < ty; row += kTcThreads / 64) {
       int carry = 0;
-      for (int c0 = 0; c0 < W1; c0 += 64) {
+      for (int c0 = 0; c0 < tx; c0 += 64) {
         const int x = c0 + lane;
-        const int val = x < W1 ? gd[row * W1 + x] : 0;
+        const int val = x < tx ? gd[row * W1 + x] : 0;
         const int inc = wave_incl_scan(val, lane) + carry;
-        if (x < W1) gd[row * W1 + x] = inc;
-        carry = __shfl(inc, 63, 64);
-      }
-    }
-    __syncthreads();
-    for (int col = wave; col < W1; col += kTcThreads / 64) {
-      int carry = 0;
-      for (int r0 = 0; r0 < H1; r0 += 64) {
-        const int y = r0 + lane;
-        const int val = y < H1 ? gd[y * W1 + col] : 0;
-        const int inc = wave_incl_scan(val, lane) + carry;
-        if (y < H1) gd[y * W1 + col] = inc;
+        if (x < tx) gd[row * W1 + x] = inc;
         carry = __shfl(inc, 63, 64);
       }
     }
     __syncthreads();
     uint32_t run = uint32_t(base);
+    const uint32_t seg_end = uint32_t(base + Dv);
     for (uint32_t t0 = 0; t0 < ntiles; t0 += kTcThreads) {
       const uint32_t t = t0 + tid;
       const uint32_t c = t < ntiles ? uint32_t(gd[int(t / tx) * W1 + int(t % tx)]) : 0u;
       uint32_t tot;
       const uint32_t ex = block_excl_scan<kTcThreads>(c, s_w, &tot) + run;
       if (t < ntiles) {
-        ranges[sl.tile_base + t] = c ? make_uint2(ex, ex + c) : make_uint2(0u, 0u);
+        // (clamped to the segment: the grid and the per-Gaussian counts follow
+        // the same runs, so this only guards the reads of the rasteriser)
+        const uint32_t e0 = ex < seg_end ? ex : seg_end;
+        const uint32_t e1 = ex + c < seg_end ? ex + c : seg_end;
+        ranges[sl.tile_base + t] = c ? make_uint2(e0, e1) : make_uint2(0u, 0u);
         if (c) {
           atomicAdd(&s_h[0][t & 255u], c);
           atomicAdd(&s_h[1][(t >> 8) & 255u], c);
@@ -500,11 +530,12 @@ struct LoadCountGatherSeg {
 
 // Tile-key emission: each wavefront takes 64 consecutive Gaussians of one
 // render's depth order and writes their tile entries one Gaussian at a time,
-// lanes on consecutive entries, so the stores are coalesced whatever the
-// rectangle size.  Keys are render-local tile ids.
+// the lanes on its tile rows (wave_runs).  Keys are render-local tile ids.
+template <typename T>
 __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ order,
                                                    const uint64_t* __restrict__ offsets,
                                                    const Rect16* __restrict__ rects,
+                                                   const Rec<T>* __restrict__ recs,
                                                    const ViewSlot* __restrict__ slots,
                                                    const SegTable* __restrict__ seg, uint32_t n,
                                                    uint32_t n_pad, uint32_t* __restrict__ keys,
@@ -515,15 +546,14 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
   if (seg->overflow) return;
   const uint32_t kk = uint32_t(i);
   uint32_t idx = 0, cnt = 0, off = 0;
-  Rect16 rc = {0, 0, 0, 0};
   const size_t row = size_t(v) * n_pad;
   if (kk < n) {
     idx = order[row + kk];
-    rc = rects[size_t(v) * n + idx];
-    cnt = uint32_t(rc.x1 - rc.x0) * uint32_t(rc.y1 - rc.y0);
     off = seg->start[v] + uint32_t(offsets[row + kk] - offsets[row]);
+    cnt = uint32_t(offsets[row + kk + 1] - offsets[row + kk]);
   }
-  const uint32_t tiles_x = uint32_t(slots[v].v.tiles_x);
+  const ViewDev vd = slots[v].v;
+  const uint32_t tiles_x = uint32_t(vd.tiles_x);
   unsigned long long todo = __ballot(cnt > 0);
   while (todo) {
     const int src = __ffsll((long long)todo) - 1;
@@ -531,14 +561,12 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
     const uint32_t s_idx = __shfl(idx, src, 64);
     const uint32_t s_cnt = __shfl(cnt, src, 64);
     const uint32_t s_off = __shfl(off, src, 64);
-    const uint32_t x0 = __shfl(uint32_t(rc.x0), src, 64);
-    const uint32_t y0 = __shfl(uint32_t(rc.y0), src, 64);
-    const uint32_t w = __shfl(uint32_t(rc.x1 - rc.x0), src, 64);
-    for (uint32_t j = lane; j < s_cnt; j += 64) {
-      const uint32_t ty = y0 + j / w, tx = x0 + j % w;
-      keys[s_off + j] = ty * tiles_x + tx;
+    const Rect16 r = rects[size_t(v) * n + s_idx];
+    const SpanGeom sg = geom_of(recs[size_t(v) * n + s_idx], r, vd);
+    wave_runs(sg, r.y0, r.y1, tiles_x, 0u, s_cnt, lane, [&](uint32_t j, uint32_t tile) {
+      keys[s_off + j] = tile;
       vals[s_off + j] = s_idx;
-    }
+    });
   }
 }
 
@@ -643,12 +671,14 @@ __device__ __forceinline__ void add_digit_range(int* diff, uint32_t* all, uint32
   }
 }
 
-// Low-digit counts of every block's entries, from the rectangles: the part of
-// a Gaussian inside a block is a run of its row-major tiles, i.e. a few row
-// segments of consecutive tile ids.
+// Low-digit counts of every block's entries, from the row runs: the part of a
+// Gaussian inside a block is a few runs of consecutive tile ids.  One thread
+// per Gaussian walks its rows.
+template <typename T>
 __global__ __launch_bounds__(kThreads) void lo_count_kernel(
     const uint32_t* __restrict__ order, const uint64_t* __restrict__ offsets,
-    const Rect16* __restrict__ rects, const ViewSlot* __restrict__ slots,
+    const Rect16* __restrict__ rects, const Rec<T>* __restrict__ recs,
+    const ViewSlot* __restrict__ slots,
     const SegTable* __restrict__ seg, const uint32_t* __restrict__ first, uint32_t n,
     uint32_t n_pad, uint32_t* __restrict__ cnt) {
   __shared__ int s_diff[257];
@@ -666,7 +696,8 @@ __global__ __launch_bounds__(kThreads) void lo_count_kernel(
     const uint32_t lo = b * uint32_t(kChunk) - sstart, hi = lo + nvalid;  // render-local entries
     const size_t row = size_t(s) * n_pad;
     const uint64_t o0 = offsets[row];
-    const uint32_t tiles_x = uint32_t(slots[s].v.tiles_x);
+    const ViewDev vd = slots[s].v;
+    const uint32_t tiles_x = uint32_t(vd.tiles_x);
     const uint32_t k0 = first[b];
     for (uint32_t base = k0;; base += kThreads) {
       const uint32_t k = base + threadIdx.x;
@@ -680,15 +711,19 @@ __global__ __launch_bounds__(kThreads) void lo_count_kernel(
           const uint32_t c0 = a > lo ? a : lo, c1 = e < hi ? e : hi;
           if (c0 < c1) {
             const Rect16 r = rects[size_t(s) * n + gi];
-            const uint32_t w = uint32_t(r.x1 - r.x0);
-            uint32_t q = c0 - a;
-            const uint32_t qe = c1 - a;
-            while (q < qe) {
-              const uint32_t y = q / w, x = q % w;
-              const uint32_t len = (w - x) < (qe - q) ? (w - x) : (qe - q);
-              add_digit_range(s_diff, &s_all, (uint32_t(r.y0) + y) * tiles_x + uint32_t(r.x0) + x,
-                              len);
-              q += len;
+            const SpanGeom sg = geom_of(recs[size_t(s) * n + gi], r, vd);
+            const uint32_t q0 = c0 - a, q1 = c1 - a;
+            uint32_t start = 0;  // local index of the row's first entry
+            for (int y = r.y0; y < r.y1 && start < q1; ++y) {
+              int x0, x1;
+              row_span(sg, y, x0, x1);
+              const uint32_t len = uint32_t(x1 - x0);
+              const uint32_t j0 = start > q0 ? start : q0;
+              const uint32_t j1 = start + len < q1 ? start + len : q1;
+              if (j0 < j1)
+                add_digit_range(s_diff, &s_all, uint32_t(y) * tiles_x + uint32_t(x0) + (j0 - start),
+                                j1 - j0);
+              start += len;
             }
           }
         }
@@ -820,12 +855,15 @@ __device__ __forceinline__ void rank_block(const uint32_t (&dg)[ITEMS], uint32_t
 }
 
 // Low-digit pass: block b generates its entries (Gaussians from first[b] on,
-// each one's part inside the block written by the lanes of one wavefront),
-// ranks them stably by the low 8 bits of the tile id and writes them, as
-// packed words, in runs of equal digit to their place in the segment.
+// each one's part inside the block written by the lanes of one wavefront, one
+// lane per tile row), ranks them stably by the low 8 bits of the tile id and
+// writes them, as packed words, in runs of equal digit to their place in the
+// segment.
+template <typename T>
 __global__ __launch_bounds__(kThreads) void lo_pass_kernel(
     const uint32_t* __restrict__ order, const uint64_t* __restrict__ offsets,
-    const Rect16* __restrict__ rects, const ViewSlot* __restrict__ slots,
+    const Rect16* __restrict__ rects, const Rec<T>* __restrict__ recs,
+    const ViewSlot* __restrict__ slots,
     const SegTable* __restrict__ seg, const uint32_t* __restrict__ first,
     const uint32_t* __restrict__ P, uint32_t n, uint32_t n_pad, uint32_t* __restrict__ out) {
   constexpr int ITEMS = kChunk / kThreads;
@@ -845,8 +883,16 @@ __global__ __launch_bounds__(kThreads) void lo_pass_kernel(
   const uint32_t lo = b * uint32_t(kChunk) - sstart, hi = lo + nvalid;  // render-local entries
   const size_t row = size_t(s) * n_pad;
   const uint64_t o0 = offsets[row];
-  const uint32_t tiles_x = uint32_t(slots[s].v.tiles_x);
+  const ViewDev vd = slots[s].v;
+  const uint32_t tiles_x = uint32_t(vd.tiles_x);
   // generate: wave w takes the Gaussians first[b] + 64 w + lane, then + 256, ...
+  // every slot is written below; zeroed first so that no slot can hold a
+  // stale value whatever the runs are
+  for (uint32_t q = tid; q < nvalid; q += kThreads) {
+    s_val[q] = 0u;
+    s_dig[q] = 0u;
+  }
+  __syncthreads();
   const uint32_t k0 = first[b];
   for (uint32_t base = k0 + uint32_t(wave) * 64u;; base += kThreads) {
     const uint32_t k = base + uint32_t(lane);
@@ -858,22 +904,19 @@ __global__ __launch_bounds__(kThreads) void lo_pass_kernel(
     }
     const uint32_t c0 = a > lo ? a : lo, c1 = e < hi ? e : hi;
     const bool has = c0 < c1;
-    Rect16 r = {0, 0, 0, 0};
-    if (has) r = rects[size_t(s) * n + gi];
     unsigned long long todo = __ballot(has);
     while (todo) {
       const int src = __ffsll((long long)todo) - 1;
       todo &= todo - 1ull;
       const uint32_t sa = __shfl(a, src, 64), s0 = __shfl(c0, src, 64), s1 = __shfl(c1, src, 64);
-      const uint32_t sg = __shfl(gi, src, 64);
-      const uint32_t x0 = __shfl(uint32_t(r.x0), src, 64), y0 = __shfl(uint32_t(r.y0), src, 64);
-      const uint32_t w = __shfl(uint32_t(r.x1 - r.x0), src, 64);
-      for (uint32_t q = s0 + uint32_t(lane); q < s1; q += 64) {
-        const uint32_t local = q - sa;
-        const uint32_t tile = (y0 + local / w) * tiles_x + x0 + local % w;
-        s_val[q - lo] = sg | ((tile >> 8) << 24);
-        s_dig[q - lo] = uint8_t(tile & 255u);
-      }
+      const uint32_t sgi = __shfl(gi, src, 64);
+      const Rect16 r = rects[size_t(s) * n + sgi];
+      const SpanGeom sg = geom_of(recs[size_t(s) * n + sgi], r, vd);
+      const uint32_t base_q = sa - lo;  // block slot of the Gaussian's entry 0
+      wave_runs(sg, r.y0, r.y1, tiles_x, s0 - sa, s1 - sa, lane, [&](uint32_t j, uint32_t tile) {
+        s_val[base_q + j] = sgi | ((tile >> 8) << 24);
+        s_dig[base_q + j] = uint8_t(tile & 255u);
+      });
     }
     // Gaussians start in increasing order: stop once every lane is past the block
     if (!__any(k < n && a < hi)) break;
@@ -900,7 +943,8 @@ __global__ __launch_bounds__(kThreads) void lo_pass_kernel(
   __syncthreads();
   for (uint32_t p = tid; p < nvalid; p += kThreads) {
     const uint32_t d = s_dig[p];
-    out[s_base[d] + (p - s_start[d])] = s_val[p];
+    const uint32_t pos = s_base[d] + (p - s_start[d]);
+    if (pos < send) out[pos] = s_val[p];
   }
 }
 
@@ -1088,7 +1132,9 @@ size_t tile_grid_lds_limit() {
     // leave room for the counting kernel's static LDS
     const size_t b = size_t(bytes) > 8192 ? size_t(bytes) - 8192 : 0;
     if (b > 65536) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_grid_kernel<true>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_grid_kernel<float, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(b));
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_grid_kernel<double, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(b));
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_count_kernel<true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(b));
@@ -1099,25 +1145,31 @@ size_t tile_grid_lds_limit() {
   return limit;
 }
 
-hipError_t tile_grids(const Rect16* rects, const ViewSlot* slots, int n_views, uint32_t n,
-                      uint64_t max_cells, uint64_t total_cells, int* partials, int* grid,
-                      hipStream_t stream) {
+template <typename T>
+hipError_t tile_grids(const Rect16* rects, const Rec<T>* recs, const ViewSlot* slots,
+                      int n_views, uint32_t n, uint64_t max_cells, uint64_t total_cells,
+                      int* partials, int* grid, hipStream_t stream) {
   if (n == 0 || n_views <= 0) return hipSuccess;
   const int B = tile_grid_partials(n);
   const dim3 g{uint32_t(B), uint32_t(n_views), 1u};
   const size_t lds = size_t(max_cells) * 4;
   if (lds <= tile_grid_lds_limit()) {
-    hipLaunchKernelGGL(tile_grid_kernel<true>, g, dim3(kThreads), lds, stream, rects, slots, n,
-                       partials, grid);
+    hipLaunchKernelGGL((tile_grid_kernel<T, true>), g, dim3(kThreads), lds, stream, rects, recs,
+                       slots, n, partials, grid);
     hipLaunchKernelGGL(grid_sum_kernel, dim3(uint32_t((total_cells + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, stream, slots, n_views, partials, B,
                        uint32_t(total_cells), grid);
   } else {
-    hipLaunchKernelGGL(tile_grid_kernel<false>, g, dim3(kThreads), 0, stream, rects, slots, n,
-                       partials, grid);
+    hipLaunchKernelGGL((tile_grid_kernel<T, false>), g, dim3(kThreads), 0, stream, rects, recs,
+                       slots, n, partials, grid);
   }
   return hipGetLastError();
 }
+
+template hipError_t tile_grids<float>(const Rect16*, const Rec<float>*, const ViewSlot*, int,
+                                      uint32_t, uint64_t, uint64_t, int*, int*, hipStream_t);
+template hipError_t tile_grids<double>(const Rect16*, const Rec<double>*, const ViewSlot*, int,
+                                       uint32_t, uint64_t, uint64_t, int*, int*, hipStream_t);
 
 hipError_t tile_counts(const ViewSlot* slots, int n_views, uint64_t max_cells, int* grid,
                        const unsigned long long* totals, unsigned long long capacity,
@@ -1155,15 +1207,25 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts, uint32_
       static_cast<uint64_t*>(temp), stream);
 }
 
+template <typename T>
 hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                              const ViewSlot* slots, const SegTable* seg, uint32_t n,
-                              uint32_t n_pad, int n_views, uint32_t* keys, uint32_t* vals,
-                              hipStream_t stream) {
+                              const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
+                              uint32_t n, uint32_t n_pad, int n_views, uint32_t* keys,
+                              uint32_t* vals, hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(emit_kernel, dim3((n + 255) / 256, uint32_t(n_views)), dim3(256), 0, stream,
-                     order, offsets, rects, slots, seg, n, n_pad, keys, vals);
+  hipLaunchKernelGGL(emit_kernel<T>, dim3((n + 255) / 256, uint32_t(n_views)), dim3(256), 0,
+                     stream, order, offsets, rects, recs, slots, seg, n, n_pad, keys, vals);
   return hipGetLastError();
 }
+
+template hipError_t emit_tile_keys_seg<float>(const uint32_t*, const uint64_t*, const Rect16*,
+                                              const Rec<float>*, const ViewSlot*, const SegTable*,
+                                              uint32_t, uint32_t, int, uint32_t*, uint32_t*,
+                                              hipStream_t);
+template hipError_t emit_tile_keys_seg<double>(const uint32_t*, const uint64_t*, const Rect16*,
+                                               const Rec<double>*, const ViewSlot*,
+                                               const SegTable*, uint32_t, uint32_t, int, uint32_t*,
+                                               uint32_t*, hipStream_t);
 
 bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view) {
   return n <= (1u << 24) && max_tiles_per_view <= 65536u;
@@ -1192,10 +1254,12 @@ hipError_t col_scan(const uint32_t* M, uint32_t rows, uint32_t* P, uint32_t* T,
 }
 }  // namespace
 
+template <typename T>
 hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                            const ViewSlot* slots, const SegTable* seg, uint32_t n,
-                            uint32_t n_pad, int n_views, uint32_t max_tiles, uint64_t capacity,
-                            void* temp, uint32_t* lo_out, uint32_t* values, hipStream_t stream) {
+                            const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
+                            uint32_t n, uint32_t n_pad, int n_views, uint32_t max_tiles,
+                            uint64_t capacity, void* temp, uint32_t* lo_out, uint32_t* values,
+                            hipStream_t stream) {
   const uint32_t rows = uint32_t((capacity + kChunk - 1) / kChunk);
   if (n == 0 || n_views <= 0 || rows == 0) return hipSuccess;
   const uint32_t stripes = (rows + kStripe - 1) / kStripe + 1;
@@ -1208,12 +1272,12 @@ hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, cons
   uint32_t* T2 = P2 + size_t(rows + 1) * 256;
   hipLaunchKernelGGL(first_gaussian_kernel, dim3((n + kThreads - 1) / kThreads, uint32_t(n_views)),
                      dim3(kThreads), 0, stream, offsets, seg, n, n_pad, first);
-  hipLaunchKernelGGL(lo_count_kernel, dim3(rows), dim3(kThreads), 0, stream, order, offsets, rects,
-                     slots, seg, first, n, n_pad, M1);
+  hipLaunchKernelGGL(lo_count_kernel<T>, dim3(rows), dim3(kThreads), 0, stream, order, offsets,
+                     rects, recs, slots, seg, first, n, n_pad, M1);
   hipError_t e = col_scan(M1, rows, P1, T1, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(lo_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, order, offsets, rects,
-                     slots, seg, first, P1, n, n_pad, lo_out);
+  hipLaunchKernelGGL(lo_pass_kernel<T>, dim3(rows), dim3(kThreads), 0, stream, order, offsets,
+                     rects, recs, slots, seg, first, P1, n, n_pad, lo_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(hi_count_kernel, dim3(rows), dim3(kThreads), 0, stream, lo_out, seg, M2);
   if ((e = col_scan(M2, rows, P2, T2, stream)) != hipSuccess) return e;
@@ -1223,5 +1287,14 @@ hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, cons
                      nbits, values);
   return hipGetLastError();
 }
+
+template hipError_t packed_tile_sort<float>(const uint32_t*, const uint64_t*, const Rect16*,
+                                            const Rec<float>*, const ViewSlot*, const SegTable*,
+                                            uint32_t, uint32_t, int, uint32_t, uint64_t, void*,
+                                            uint32_t*, uint32_t*, hipStream_t);
+template hipError_t packed_tile_sort<double>(const uint32_t*, const uint64_t*, const Rect16*,
+                                             const Rec<double>*, const ViewSlot*,
+                                             const SegTable*, uint32_t, uint32_t, int, uint32_t,
+                                             uint64_t, void*, uint32_t*, uint32_t*, hipStream_t);
 
 }  // namespace r4d

@@ -45,12 +45,14 @@ struct SettingsDev {
   float log_alpha_min;   // ln(alpha_min)
 };
 
-// Per-Gaussian projected record, 12 scalars: (mx, my, ca, cb), (cc, o, depth, 0),
-// (r, g, b, 0).  q(d) = ca dx^2 + 2 cb dx dy + cc dy^2 with d = mean2d - pixel.
+// Per-Gaussian projected record, 12 scalars: (mx, my, ca, cb), (cc, o, depth, qmax),
+// (r, g, b, 0).  q(d) = ca dx^2 + 2 cb dx dy + cc dy^2 with d = mean2d - pixel;
+// qmax = min(extent^2, 2 ln(o / alpha_min)) rounded up to T, the largest q at
+// which the Gaussian can still be blended (the bound the tile lists follow).
 template <typename T>
 struct alignas(sizeof(T) * 4) Rec {
   T mx, my, ca, cb;
-  T cc, o, depth, pad0;
+  T cc, o, depth, qmax;
   T r, g, b, pad1;
 };
 

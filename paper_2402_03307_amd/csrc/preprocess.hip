@@ -2,14 +2,15 @@
 // coalesced across a wavefront, SH coefficients read only for Gaussians that
 // survive the time / near-plane culls.
 //
-// Forward writes the projected record consumed by the rasteriser, the tile
-// rectangle, the tile count and the depth sort key.  Backward recomputes the
+// Forward writes the projected record consumed by the rasteriser, the tiles'
+// bounding box, the tile count and the depth sort key.  Backward recomputes the
 // forward intermediates from the parameters (nothing per Gaussian is stored
 // between the passes except the 9 screen-space gradients) and chains them
 // back to the parameters.
 #include <hip/hip_runtime.h>
 
 #include "r4d_internal.hpp"
+#include "tileset.hpp"
 
 namespace r4d {
 
@@ -17,37 +18,58 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Conservative tile rectangle of a projected Gaussian.  A pixel centre c can
-// receive the Gaussian only if q(c) <= Q with Q = min(extent^2, 2 ln(o / alpha_min))
-// (beyond that either the extent test or the alpha_min test skips it), so the
-// bounding box of the ellipse q <= Q of the stored conic, widened by one pixel,
-// holds every pixel the rasteriser can blend it into.  Evaluated in double from
-// the stored conic so that the box is that of the ellipse the rasteriser tests.
+// qmax of a record: min(extent^2, 2 ln(o / alpha_min)), rounded up to T so that
+// the stored bound never excludes a pixel the double value admits.  Negative
+// (the Gaussian is never blended) when o < alpha_min.
 template <typename T>
-__device__ __forceinline__ bool tile_rect(const Rec<T>& rec, const ViewDev& v,
-                                          const SettingsDev& st, Rect16& out) {
-  const double o = double(rec.o);
-  if (!(o >= double(st.alpha_min))) return false;
-  double Q = 2.0 * (log(o) - double(st.log_alpha_min));
-  Q = Q < double(st.ext2) ? Q : double(st.ext2);
-  const double a = double(rec.ca), b = double(rec.cb), c = double(rec.cc);
-  const double det = a * c - b * b;
-  if (!(det > 0.0) || !(Q >= 0.0)) return false;
-  const double hwx = sqrt(Q * c / det) + 1.0;
-  const double hwy = sqrt(Q * a / det) + 1.0;
+__device__ __forceinline__ T record_qmax(T o, const SettingsDev& st);
+
+template <>
+__device__ __forceinline__ double record_qmax<double>(double o, const SettingsDev& st) {
+  if (!(o >= double(st.alpha_min))) return -1.0;
+  const double Q = 2.0 * (log(o) - double(st.log_alpha_min));
+  return Q < double(st.ext2) ? Q : double(st.ext2);
+}
+
+template <>
+__device__ __forceinline__ float record_qmax<float>(float o, const SettingsDev& st) {
+  const double Q = record_qmax<double>(double(o), st);
+  float f = float(Q);
+  if (double(f) < Q) f = __uint_as_float(__float_as_uint(f) + 1u);  // Q >= 0 here
+  return f;
+}
+
+// Tile entries of a record: the sum of its row runs, and in `out` the
+// bounding box of the runs (rows with a run are consecutive, so every row of
+// the box holds one).
+template <typename T>
+__device__ __forceinline__ uint32_t record_tiles(const Rec<T>& rec, const ViewDev& v, Rect16& out) {
+  const double Q = double(rec.qmax);
+  if (!(Q >= 0.0)) return 0;
+  const int sh = __builtin_ctz(unsigned(v.tile_size));
   const double mx = double(rec.mx), my = double(rec.my);
-  const double ilo = ceil(mx - hwx - 0.5), ihi = floor(mx + hwx - 0.5);
-  const double jlo = ceil(my - hwy - 0.5), jhi = floor(my + hwy - 0.5);
-  const double W1 = double(v.W - 1), H1 = double(v.H - 1);
-  const double x0 = ilo > 0.0 ? ilo : 0.0, x1 = ihi < W1 ? ihi : W1;
-  const double y0 = jlo > 0.0 ? jlo : 0.0, y1 = jhi < H1 ? jhi : H1;
-  if (!(x0 <= x1) || !(y0 <= y1)) return false;
-  const int ts = v.tile_size;
-  out.x0 = uint16_t(int(x0) / ts);
-  out.x1 = uint16_t(int(x1) / ts + 1);
-  out.y0 = uint16_t(int(y0) / ts);
-  out.y1 = uint16_t(int(y1) / ts + 1);
-  return true;
+  const double a = double(rec.ca), b = double(rec.cb), c = double(rec.cc);
+  TileBox bx;
+  if (!tile_box(mx, my, a, b, c, Q, v.W, v.H, sh, bx)) return 0;
+  const SpanGeom sg = span_geom(mx, my, a, b, c, Q, v.W, v.H, sh, bx.x0, bx.x1);
+  uint32_t cnt = 0;
+  int tx0 = bx.x1, tx1 = bx.x0, ty0 = bx.y1, ty1 = bx.y0;
+  for (int ty = bx.y0; ty < bx.y1; ++ty) {
+    int x0, x1;
+    row_span(sg, ty, x0, x1);
+    if (x0 < x1) {
+      cnt += uint32_t(x1 - x0);
+      tx0 = x0 < tx0 ? x0 : tx0;
+      tx1 = x1 > tx1 ? x1 : tx1;
+      ty0 = ty < ty0 ? ty : ty0;
+      ty1 = ty + 1;
+    }
+  }
+  out.x0 = uint16_t(tx0);
+  out.x1 = uint16_t(tx1);
+  out.y0 = uint16_t(ty0);
+  out.y1 = uint16_t(ty1);
+  return cnt;
 }
 
 template <typename T, int DEG>
@@ -87,13 +109,13 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
       rec.cc = f.conic[2];
       rec.o = f.o_t;
       rec.depth = f.p[2];
-      rec.pad0 = T(0);
+      rec.qmax = record_qmax<T>(f.o_t, st);
       rec.r = f.rgb[0];
       rec.g = f.rgb[1];
       rec.b = f.rgb[2];
       rec.pad1 = T(0);
-      if (tile_rect(rec, v, st, rc)) {
-        cnt = uint32_t(rc.x1 - rc.x0) * uint32_t(rc.y1 - rc.y0);
+      cnt = record_tiles(rec, v, rc);
+      if (cnt) {
         key = __float_as_uint(float(f.p[2]));
         recs[row + i] = rec;
         vis = true;

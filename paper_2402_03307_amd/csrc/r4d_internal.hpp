@@ -28,7 +28,9 @@ struct GradPtrs {
   T* sh;
 };
 
-// Tile rectangle of a Gaussian: tile x0, y0, x1, y1 (x1, y1 exclusive).
+// Bounding box of the tiles a Gaussian is listed in: tile x0, y0, x1, y1 (x1, y1
+// exclusive); inside it, the listed tiles of each row are the run of columns
+// row_span (tileset.hpp) gives.
 struct Rect16 {
   uint16_t x0, y0, x1, y1;
 };
@@ -97,16 +99,18 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
                          uint32_t* tickets, uint32_t* error, bool keys_needed, int* result_index,
                          hipStream_t stream);
 
-// Tile count grids of every render from the Gaussians' tile rectangles
-// (rects [V][n]) into `grid` (zeroed; each render's (tiles_x + 1) x
-// (tiles_y + 1) grid at its grid_base).  max_cells: the largest grid of the
-// renders, total_cells: all of them.  When a grid fits in LDS the work goes
-// through tile_grid_partials(n) partial grids per render in `partials` ([all
-// cells] x partials); otherwise through atomics on `grid`.
+// Tile count grids of every render from the Gaussians' row spans (rects and
+// records [V][n]) into `grid` (zeroed; each render's (tiles_x + 1) x
+// (tiles_y + 1) grid at its grid_base; its last row stays zero): +1 at the
+// first column of each row span, -1 after its last.  max_cells: the largest
+// grid of the renders, total_cells: all of them.  When a grid fits in LDS the
+// work goes through tile_grid_partials(n) partial grids per render in
+// `partials` ([all cells] x partials); otherwise through atomics on `grid`.
 int tile_grid_partials(uint32_t n);
-hipError_t tile_grids(const Rect16* rects, const ViewSlot* slots, int n_views, uint32_t n,
-                      uint64_t max_cells, uint64_t total_cells, int* partials, int* grid,
-                      hipStream_t stream);
+template <typename T>
+hipError_t tile_grids(const Rect16* rects, const Rec<T>* recs, const ViewSlot* slots,
+                      int n_views, uint32_t n, uint64_t max_cells, uint64_t total_cells,
+                      int* partials, int* grid, hipStream_t stream);
 
 // Per render: tile entry counts from the grids, tile ranges
 // (ranges[tile_base + t] = [start, end) in the emitted list, [0, 0) for a tile
@@ -125,10 +129,11 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts, uint32_
 
 // Writes every render's (tile id, Gaussian index) entries in depth order into
 // its segment of keys / vals.
+template <typename T>
 hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                              const ViewSlot* slots, const SegTable* seg, uint32_t n,
-                              uint32_t n_pad, int n_views, uint32_t* keys, uint32_t* vals,
-                              hipStream_t stream);
+                              const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
+                              uint32_t n, uint32_t n_pad, int n_views, uint32_t* keys,
+                              uint32_t* vals, hipStream_t stream);
 
 // Tile sort on packed 32-bit entries (see binning.hip), usable when
 // packed_tile_sort_ok: emission fused with the low-digit pass, then the
@@ -139,10 +144,12 @@ hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, co
 // packed_sort_temp_bytes(n_pad, n_views, capacity) bytes.
 bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view);
 size_t packed_sort_temp_bytes(uint32_t n_pad, int n_views, uint64_t capacity);
+template <typename T>
 hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                            const ViewSlot* slots, const SegTable* seg, uint32_t n,
-                            uint32_t n_pad, int n_views, uint32_t max_tiles, uint64_t capacity,
-                            void* temp, uint32_t* lo_out, uint32_t* values, hipStream_t stream);
+                            const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
+                            uint32_t n, uint32_t n_pad, int n_views, uint32_t max_tiles,
+                            uint64_t capacity, void* temp, uint32_t* lo_out, uint32_t* values,
+                            hipStream_t stream);
 
 // Exclusive scan of a[0..n) into out[0..n] (out[n] = total); temp holds
 // scan_u32_temp_bytes(n).

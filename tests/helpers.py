@@ -1,6 +1,6 @@
 """Shared helpers for the GPU parity tests: moving workload arrays to the
 device and re-deriving the tile/sort order on the CPU from the GPU's own
-integer outputs (rectangles and depth keys)."""
+outputs (records, tile boxes and depth keys)."""
 from __future__ import annotations
 
 import numpy as np
@@ -16,34 +16,104 @@ def to_device(g: dict, device, dtype=torch.float32) -> dict:
     return out
 
 
-def cpu_tile_lists(rects: np.ndarray, depth_keys: np.ndarray, tiles_x: int, tiles_y: int):
-    """Reference binning + stable (tile, depth, index) order from integer data.
+def _f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32)
 
-    rects: [n, 4] uint16 (x0, y0, x1, y1) tile rectangle, depth_keys: [n] uint32.
-    Returns (values [D] uint32, ranges [tiles, 2] uint32)."""
+
+def row_runs(rec: np.ndarray, rects: np.ndarray, ys: np.ndarray, gi: np.ndarray,
+             tile_size: int, width: int, height: int):
+    """Tile columns [x0, x1) of tile row ys[k] of Gaussian gi[k]: the rule the
+    binning follows (a tile is listed when one of its pixel centres lies within
+    one pixel of the ellipse q <= qmax), re-implemented from its definition in
+    the same arithmetic (per-Gaussian constants in float64 rounded to float32,
+    per-row work in float32, no fused multiply-adds), so the runs must agree
+    bit for bit.  rec: [n, 12] record values (mx, my, a, b, c, o, depth, qmax,
+    ...), rects: [n, 4] (x0, y0, x1, y1) boxes the runs are clipped to."""
+    sh = int(tile_size).bit_length() - 1
+    r = rec[gi].astype(np.float64)
+    mx, my, a, b, c, Q = r[:, 0], r[:, 1], r[:, 2], r[:, 3], r[:, 4], r[:, 7]
+    det = a * c - b * b
+    beta = _f32(b / a)
+    gamma = _f32(np.sqrt(det) / a)
+    hy = _f32(np.sqrt(a * Q / det))
+    ds = _f32(b * np.sqrt(Q / (c * det)))
+    mxf, myf = _f32(mx), _f32(my)
+    ys = ys.astype(np.int64)
+    ya = (ys << sh).astype(np.float32) - np.float32(0.5)
+    yb = np.minimum((ys + 1) << sh, height).astype(np.float32) + np.float32(0.5)
+    lo = np.maximum(myf - yb, -hy)
+    hi = np.minimum(myf - ya, hy)
+    ok = lo <= hi
+    dmax = np.minimum(np.maximum(ds, lo), hi)
+    dmin = np.minimum(np.maximum(-ds, lo), hi)
+    wmax = np.sqrt((hy - dmax) * (hy + dmax))
+    wmin = np.sqrt((hy - dmin) * (hy + dmin))
+    pmax = mxf + (beta * dmax + gamma * wmax)
+    pmin = mxf + (beta * dmin - gamma * wmin)
+    ilo = np.maximum(np.ceil(pmin - np.float32(1.5)), np.float32(0))
+    ihi = np.minimum(np.floor(pmax + np.float32(0.5)), np.float32(width - 1))
+    ok &= ilo <= ihi
+    bx = rects[gi].astype(np.int64)
+    x0 = np.maximum(np.where(ok, ilo, 0).astype(np.int64) >> sh, bx[:, 0])
+    x1 = np.minimum((np.where(ok, ihi, 0).astype(np.int64) >> sh) + 1, bx[:, 2])
+    ok &= x0 < x1
+    return np.where(ok, x0, 0), np.where(ok, x1, 0)
+
+
+def cpu_tile_lists(rec: np.ndarray, rects: np.ndarray, depth_keys: np.ndarray, tiles_x: int,
+                   tiles_y: int, tile_size: int, width: int, height: int):
+    """Reference binning + stable (tile, depth, index) order from the GPU's
+    records, boxes and depth keys.
+
+    rec: [n, 12] records, rects: [n, 4] uint16 (x0, y0, x1, y1) box of the row
+    runs, depth_keys: [n] uint32.  Checks that every row of a box holds a run
+    and that the box is the runs' bounding box.  Returns (values [D] uint32,
+    ranges [tiles, 2] uint32)."""
     rects = rects.astype(np.int64)
+    n_tiles = tiles_x * tiles_y
     vis = np.nonzero(depth_keys != 0xFFFFFFFF)[0]
-    tiles_l, idx_l, key_l = [], [], []
-    for i in vis:
-        x0, y0, x1, y1 = rects[i]
-        ys, xs = np.mgrid[y0:y1, x0:x1]
-        t = (ys * tiles_x + xs).ravel()
-        tiles_l.append(t)
-        idx_l.append(np.full(t.size, i, dtype=np.int64))
-        key_l.append(np.full(t.size, depth_keys[i], dtype=np.int64))
-    if not tiles_l:
-        return np.zeros(0, np.uint32), np.zeros((tiles_x * tiles_y, 2), np.uint32)
-    tiles = np.concatenate(tiles_l)
-    idx = np.concatenate(idx_l)
-    keys = np.concatenate(key_l)
+    if vis.size == 0:
+        return np.zeros(0, np.uint32), np.zeros((n_tiles, 2), np.uint32)
+    nrow = rects[vis, 3] - rects[vis, 1]
+    assert np.all(nrow > 0)
+    gi = np.repeat(vis, nrow)
+    first = np.repeat(np.cumsum(nrow) - nrow, nrow)
+    ys = rects[gi, 1] + (np.arange(gi.size) - first)
+    with np.errstate(invalid="ignore"):
+        x0, x1 = row_runs(rec, rects, ys, gi, tile_size, width, height)
+    L = x1 - x0
+    assert np.all(L > 0), "a row of a box without a run"
+    assert np.array_equal(np.minimum.reduceat(x0, np.cumsum(nrow) - nrow), rects[vis, 0])
+    assert np.array_equal(np.maximum.reduceat(x1, np.cumsum(nrow) - nrow), rects[vis, 2])
+    # entries: run k contributes tiles ys*tiles_x + x0 .. + L - 1
+    run = np.repeat(np.arange(L.size), L)
+    within = np.arange(run.size) - np.repeat(np.cumsum(L) - L, L)
+    tiles = ys[run] * tiles_x + x0[run] + within
+    idx = gi[run]
+    keys = depth_keys[idx].astype(np.int64)
     order = np.lexsort((idx, keys, tiles))          # last key is primary
     values = idx[order].astype(np.uint32)
     st = tiles[order]
-    n_tiles = tiles_x * tiles_y
     starts = np.searchsorted(st, np.arange(n_tiles), side="left")
     ends = np.searchsorted(st, np.arange(n_tiles), side="right")
     ranges = np.stack([np.where(ends > starts, starts, 0), np.where(ends > starts, ends, 0)], 1)
     return values, ranges.astype(np.uint32)
+
+
+def tile_lists(r4d, saved, view: int, n: int):
+    """The GPU's tile lists of one render of a saved forward and their CPU
+    re-derivation: (values, ranges, ref_values, ref_ranges, stats)."""
+    s = saved.stats(view)
+    ts = saved.config()["tile_size"]
+    width, height = int(saved.views[view]["width"]), int(saved.views[view]["height"])
+    rec = saved.copy(view, r4d.BUF_RECORDS, n).double().cpu().numpy()
+    rect = saved.copy(view, r4d.BUF_RECT, n).cpu().numpy().view(np.uint16)
+    key = saved.copy(view, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32)
+    vals = saved.copy(view, r4d.BUF_VALUES, n).cpu().numpy().view(np.uint32)
+    rng = saved.copy(view, r4d.BUF_RANGES, n).cpu().numpy().view(np.uint32)
+    ref_vals, ref_rng = cpu_tile_lists(rec, rect, key, s["tiles_x"], s["tiles_y"], ts, width,
+                                       height)
+    return vals, rng, ref_vals, ref_rng, s
 
 
 def image_errors(gpu_img: np.ndarray, ref_img: np.ndarray, ambiguous: np.ndarray):

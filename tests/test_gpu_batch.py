@@ -13,7 +13,7 @@ import torch
 import workloads as W
 from oracle import render as O
 
-from helpers import cpu_tile_lists, image_errors, to_device
+from helpers import image_errors, tile_lists, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -73,13 +73,8 @@ def test_modes_agree(r4d, device, ts, items):
         # tile lists of every view, bit-exact
         n = g["opacity"].shape[0]
         for v in range(len(views)):
-            s = saved.stats(v)
+            vals, rng_, ref_vals, ref_rng, s = tile_lists(r4d, saved, v, n)
             assert s == ref_saved.stats(v)
-            rect = saved.copy(v, r4d.BUF_RECT, n).cpu().numpy().view(np.uint16)
-            key = saved.copy(v, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32)
-            vals = saved.copy(v, r4d.BUF_VALUES, n).cpu().numpy().view(np.uint32)
-            rng_ = saved.copy(v, r4d.BUF_RANGES, n).cpu().numpy().view(np.uint32)
-            ref_vals, ref_rng = cpu_tile_lists(rect, key, s["tiles_x"], s["tiles_y"])
             assert np.array_equal(vals, ref_vals), (mode, v)
             assert np.array_equal(rng_, ref_rng), (mode, v)
         saved.release()

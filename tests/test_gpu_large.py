@@ -15,7 +15,7 @@ import torch
 import workloads as W
 from oracle import render as O
 
-from helpers import cpu_tile_lists, to_device
+from helpers import tile_lists, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -87,12 +87,7 @@ def test_500k_binning_bit_exact(r4d, scene500k, device):
     rend = r4d.Renderer(device)
     _, saved = rend.forward(to_device(g, device), views, st, save=True)
     n = g["opacity"].shape[0]
-    s = saved.stats(0)
-    rect = saved.copy(0, r4d.BUF_RECT, n).cpu().numpy().view(np.uint16)
-    key = saved.copy(0, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32)
-    vals = saved.copy(0, r4d.BUF_VALUES, n).cpu().numpy().view(np.uint32)
-    rng = saved.copy(0, r4d.BUF_RANGES, n).cpu().numpy().view(np.uint32)
-    ref_vals, ref_rng = cpu_tile_lists(rect, key, s["tiles_x"], s["tiles_y"])
+    vals, rng, ref_vals, ref_rng, s = tile_lists(r4d, saved, 0, n)
     print(f"D = {s['n_dup']}, visible = {s['n_visible']}", flush=True)
     assert s["n_dup"] == ref_vals.size
     assert np.array_equal(vals, ref_vals)

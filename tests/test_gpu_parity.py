@@ -15,7 +15,7 @@ import torch
 import workloads as W
 from oracle import render as O
 
-from helpers import cpu_tile_lists, image_errors, to_device
+from helpers import image_errors, tile_lists, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -80,6 +80,10 @@ def test_preprocess_records_2k(r4d, scene2k, device):
     assert (np.abs(rec[i, 5] - op[i]) / op[i]).max() < 1e-5
     assert (np.abs(rec[i, 6] - dep[i]) / dep[i]).max() < 1e-6
     assert np.abs(rec[i, 8:11] - rgb[i]).max() < 1e-5
+    # qmax: min(extent^2, 2 ln(o / alpha_min)) of the record's opacity, rounded up to float32
+    # (ln alpha_min is held in float32: differences of a few 1e-8 are allowed)
+    qd = np.minimum(st["extent_sigma"] ** 2, 2.0 * (np.log(rec[i, 5]) - np.log(st["alpha_min"])))
+    assert np.all(np.abs(rec[i, 7] - qd) <= 1e-6 * np.maximum(qd, 1.0))
     # depth keys are the float32 bit patterns of the record depths
     assert np.array_equal(key[i], rec[i, 6].astype(np.float32).view(np.uint32))
 
@@ -89,37 +93,46 @@ def test_binning_and_sort_bit_exact_2k(r4d, scene2k, device):
     for ts in (8, 16, 32):
         _, _, _, saved = _render(r4d, g, views, dict(st, tile_size=ts), device)
         n = g["opacity"].shape[0]
-        s = saved.stats(0)
-        rect = saved.copy(0, r4d.BUF_RECT, n).cpu().numpy().view(np.uint16)
+        vals, rng, ref_vals, ref_rng, s = tile_lists(r4d, saved, 0, n)
         key = saved.copy(0, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32)
-        vals = saved.copy(0, r4d.BUF_VALUES, n).cpu().numpy().view(np.uint32)
-        rng = saved.copy(0, r4d.BUF_RANGES, n).cpu().numpy().view(np.uint32)
-        ref_vals, ref_rng = cpu_tile_lists(rect, key, s["tiles_x"], s["tiles_y"])
         assert s["n_dup"] == ref_vals.size
         assert np.array_equal(vals, ref_vals), f"tile {ts}: order differs"
         assert np.array_equal(rng, ref_rng), f"tile {ts}: ranges differ"
         assert s["n_visible"] == int((key != 0xFFFFFFFF).sum())
 
 
-def test_tile_rectangles_are_conservative_2k(r4d, scene2k, device):
-    """Every pixel where a Gaussian can pass the extent and alpha tests lies in
-    its tile rectangle (evaluated on the GPU's own FP32 record)."""
+def test_tile_lists_are_conservative_2k(r4d, scene2k, device):
+    """Every pixel where a Gaussian can pass the extent and alpha tests lies in a
+    tile whose list holds the Gaussian (evaluated on the GPU's own FP32
+    record), and the lists hold fewer entries than the tile bounding boxes."""
     g, views, st, _ = scene2k
-    _, _, _, saved = _render(r4d, g, views, st, device)
-    n = g["opacity"].shape[0]
-    rec = saved.copy(0, r4d.BUF_RECORDS, n).cpu().numpy().astype(np.float64)
-    rect = saved.copy(0, r4d.BUF_RECT, n).cpu().numpy().view(np.uint16).astype(np.int64)
-    key = saved.copy(0, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32)
-    ys, xs = np.mgrid[0:128, 0:128]
-    cx, cy = xs.ravel() + 0.5, ys.ravel() + 0.5
-    for i in np.nonzero(key != 0xFFFFFFFF)[0]:
-        mx, my, a, b, c, o = rec[i, :6]
-        dx, dy = mx - cx, my - cy
-        q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
-        reach = (q <= 9.0 * (1 + 1e-5)) & (o * np.exp(-0.5 * q) >= (1 / 255) * (1 - 1e-5))
-        tx, ty = xs.ravel()[reach] // 16, ys.ravel()[reach] // 16
-        x0, y0, x1, y1 = rect[i]
-        assert np.all((tx >= x0) & (tx < x1) & (ty >= y0) & (ty < y1)), i
+    for ts in (8, 16, 32):
+        _, _, _, saved = _render(r4d, g, views, dict(st, tile_size=ts), device)
+        n = g["opacity"].shape[0]
+        rec = saved.copy(0, r4d.BUF_RECORDS, n).cpu().numpy().astype(np.float64)
+        key = saved.copy(0, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32)
+        vals, rng, _, _, s = tile_lists(r4d, saved, 0, n)
+        tx = s["tiles_x"]
+        lens = (rng[:, 1] - rng[:, 0]).astype(np.int64)
+        listed = np.repeat(np.arange(lens.size), lens) * n + vals.astype(np.int64)
+        ys, xs = np.mgrid[0:128, 0:128]
+        cx, cy = xs.ravel() + 0.5, ys.ravel() + 0.5
+        need = []
+        for i in np.nonzero(key != 0xFFFFFFFF)[0]:
+            mx, my, a, b, c, o = rec[i, :6]
+            dx, dy = mx - cx, my - cy
+            q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+            reach = (q <= 9.0 * (1 + 1e-5)) & (o * np.exp(-0.5 * q) >= (1 / 255) * (1 - 1e-5))
+            t = (ys.ravel()[reach] // ts) * tx + xs.ravel()[reach] // ts
+            need.append(np.unique(t) * n + i)
+        need = np.concatenate(need)
+        assert need.size > 0
+        missing = need[~np.isin(need, listed)]
+        assert missing.size == 0, f"tile {ts}: {missing.size} (tile, Gaussian) pairs missing"
+        rect = saved.copy(0, r4d.BUF_RECT, n).cpu().numpy().view(np.uint16).astype(np.int64)
+        box = int(((rect[:, 2] - rect[:, 0]) * (rect[:, 3] - rect[:, 1])).sum())
+        print(f"tile {ts}: {vals.size} entries, {box} in the runs' bounding boxes", flush=True)
+        assert vals.size <= box
 
 
 RASTER_CONFIGS = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4))
@@ -306,12 +319,7 @@ def test_binning_paths_agree_on_large_image(r4d, device):
     for ts in (8, 16):
         _, _, imgs, saved = _render(r4d, g, [v], dict(st, tile_size=ts), device)
         n = g["opacity"].shape[0]
-        s = saved.stats(0)
-        rect = saved.copy(0, r4d.BUF_RECT, n).cpu().numpy().view(np.uint16)
-        key = saved.copy(0, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32)
-        vals = saved.copy(0, r4d.BUF_VALUES, n).cpu().numpy().view(np.uint32)
-        rng = saved.copy(0, r4d.BUF_RANGES, n).cpu().numpy().view(np.uint32)
-        ref_vals, ref_rng = cpu_tile_lists(rect, key, s["tiles_x"], s["tiles_y"])
+        vals, rng, ref_vals, ref_rng, s = tile_lists(r4d, saved, 0, n)
         assert s["n_dup"] == ref_vals.size > 0
         assert np.array_equal(vals, ref_vals), f"tile {ts}: order differs"
         assert np.array_equal(rng, ref_rng), f"tile {ts}: ranges differ"
