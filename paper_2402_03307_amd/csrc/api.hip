@@ -42,10 +42,10 @@ struct GraphEntry;
 struct RunLayout {
   // fixed block
   size_t meta, recs, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp, ranges,
-      T_final, n_contrib, n_eval, img_copy, walk, partials, zero_begin, totals, dhist, tickets,
-      grids, dstatus, zero_end, fixed_bytes;
+      T_final, n_contrib, n_eval, img_copy, walk, zero_begin, totals, dhist, tickets, dstatus,
+      zero_end, fixed_bytes;
   // entries block
-  size_t tkA, tkB, tvA, tvB, ptemp, ck, tstatus, entries_bytes;
+  size_t tkA, tkB, tvA, tvB, tdig, thi, t16, etemp, ptemp, ck, tstatus, entries_bytes;
 };
 
 constexpr int kTicketTile = 4;     // tickets[0..3] depth passes, [4..6] tile passes
@@ -60,7 +60,7 @@ struct Plan {
   int deg = 0, ts = 16, fppt = 1, bppt = 4, sort_items = 16, mode = 0;
   std::vector<ViewSlot> slots;
   uint32_t total_tiles = 0;
-  uint64_t total_pix = 0, grid_cells = 0, max_cells = 0;
+  uint64_t total_pix = 0;
   uint32_t max_tiles = 0;
   int tile_passes = 1;
   bool packed = true;   // packed tile sort (see packed_tile_sort_ok)
@@ -375,13 +375,9 @@ Plan make_plan(const r4d_view* views, int V, uint32_t n, int deg, const r4d_sett
     ViewSlot sl{};
     sl.v = make_view(views[i], s);
     sl.tile_base = p.total_tiles;
-    sl.grid_base = uint32_t(p.grid_cells);
     sl.pix_base = p.total_pix;
     const uint64_t nt = uint64_t(sl.v.tiles_x) * uint64_t(sl.v.tiles_y);
     p.total_tiles += uint32_t(nt);
-    const uint64_t cells = uint64_t(sl.v.tiles_x + 1) * uint64_t(sl.v.tiles_y + 1);
-    p.grid_cells += cells;
-    p.max_cells = std::max(p.max_cells, cells);
     p.total_pix += uint64_t(views[i].width) * uint64_t(views[i].height);
     bits = std::max(bits, bits_for(nt));
     p.max_tiles = std::max(p.max_tiles, uint32_t(nt));
@@ -434,12 +430,10 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 4) : 0;
   L.img_copy = take(3 * size_t(p.total_pix) * p.scal);
   L.walk = take(size_t(p.total_tiles) * 4);
-  L.partials = take(size_t(p.grid_cells) * size_t(tile_grid_partials(p.n)) * 4);
   L.zero_begin = off;
   L.totals = take(2 * size_t(kMaxViews) * 8);
   L.dhist = take(4 * size_t(kMaxViews) * 256 * 4);
   L.tickets = take(16 * 4);
-  L.grids = take(size_t(p.grid_cells) * 4);
   L.dstatus = take(4 * size_t(sort_status_words(uint64_t(V) * np, kDepthItems)) * 4);
   L.zero_end = off;
   L.fixed_bytes = off;
@@ -448,13 +442,18 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.tkA = take(cap * 4);
   L.tvA = take(cap * 4);
   L.ck = take(size_t(ck_slots(p, capacity)) * size_t(p.ts) * size_t(p.ts) * 4 * p.scal);
+  L.etemp = take(emit_temp_bytes(capacity));
   if (p.packed) {
     L.tkB = L.tvB = 0;
-    L.ptemp = take(packed_sort_temp_bytes(p.n_pad, p.V, capacity));
+    L.tdig = take(cap);
+    L.thi = take(cap);
+    L.t16 = take(cap * 2);
+    L.ptemp = take(packed_sort_temp_bytes(capacity));
     L.tstatus = off;  // nothing to zero
   } else {
     L.tkB = take(cap * 4);
     L.tvB = take(cap * 4);
+    L.tdig = L.thi = L.t16 = 0;
     L.ptemp = 0;
     L.tstatus = take(size_t(p.tile_passes) * sort_status_words(capacity, p.sort_items) * 4);
   }
@@ -555,6 +554,10 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     L.tkB = L2.tkB;
     L.tvA = L2.tvA;
     L.tvB = L2.tvB;
+    L.tdig = L2.tdig;
+    L.thi = L2.thi;
+    L.t16 = L2.t16;
+    L.etemp = L2.etemp;
     L.ptemp = L2.ptemp;
     L.ck = L2.ck;
     L.tstatus = L2.tstatus;
@@ -565,43 +568,47 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   }
   uint8_t* E = r.entries;
   auto* ranges = at<uint2>(F, L.ranges);
-  {
-    StageTimer tm(ctx, kTileRanges, stream, timed);
-    R4D_HIP(tile_grids<T>(at<Rect16>(F, L.rects), at<Rec<T>>(F, L.recs), slots, p.V, p.n,
-                          p.max_cells, p.grid_cells, at<int>(F, L.partials), at<int>(F, L.grids),
-                          stream));
-    R4D_HIP(tile_counts(slots, p.V, p.max_cells, at<int>(F, L.grids), totals, r.capacity, ranges,
-                        at<uint32_t>(F, L.thist), tseg, stream));
-  }
+  R4D_HIP(seg_table(totals, p.V, r.capacity, tseg, stream));
   uint32_t* values = at<uint32_t>(E, L.tvA);
+  const void* sorted_tiles = nullptr;
   if (p.n > 0) {
     auto* offsets = at<uint64_t>(F, L.offsets);
     R4D_TIMED(kCountScan, count_scan_seg(order, at<uint32_t>(F, L.tiles), p.n, p.n_pad, p.V,
                                          offsets, F + L.scan_tmp, stream));
+    // packed: (index | high tile byte) words into tvA and low tile bytes into
+    // tdig; otherwise tile ids into tkA and indices into tvA
+    uint32_t* out_a = p.packed ? at<uint32_t>(E, L.tvA) : at<uint32_t>(E, L.tkA);
+    void* out_b = p.packed ? static_cast<void*>(E + L.tdig) : static_cast<void*>(E + L.tvA);
+    R4D_TIMED(kEmit, emit_blocks<T>(order, offsets, at<Rect16>(F, L.rects),
+                                    at<Rec<T>>(F, L.recs), slots, tseg, p.n, p.n_pad, p.V,
+                                    r.capacity, p.packed, E + L.etemp, out_a, out_b, stream));
     if (p.packed) {
-      // emission fused with the low-digit pass, then the high-digit pass
-      StageTimer tm(ctx, kTileSort, stream, timed);
-      R4D_HIP(packed_tile_sort<T>(order, offsets, at<Rect16>(F, L.rects), at<Rec<T>>(F, L.recs),
-                                  slots, tseg, p.n, p.n_pad, p.V, p.max_tiles, r.capacity,
-                                  E + L.ptemp, at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA),
-                                  stream));
+      // low tile byte pass into (tkA, thi), high byte pass into (tvA, t16)
+      R4D_TIMED(kTileSort, packed_tile_sort(at<uint32_t>(E, L.tvA), E + L.tdig, tseg,
+                                            p.max_tiles, r.capacity, E + L.ptemp,
+                                            at<uint32_t>(E, L.tkA), E + L.thi,
+                                            at<uint32_t>(E, L.tvA), at<uint16_t>(E, L.t16),
+                                            stream));
       values = at<uint32_t>(E, L.tvA);
+      sorted_tiles = E + L.t16;
     } else {
+      StageTimer tm(ctx, kTileSort, stream, timed);
+      R4D_HIP(tile_key_histogram(at<uint32_t>(E, L.tkA), tseg, r.capacity, p.tile_passes,
+                                 at<uint32_t>(F, L.thist), stream));
       R4D_HIP(fill_zero(E + L.tstatus, L.entries_bytes - L.tstatus, stream));
-      R4D_TIMED(kEmit, emit_tile_keys_seg<T>(order, offsets, at<Rect16>(F, L.rects),
-                                             at<Rec<T>>(F, L.recs), slots, tseg, p.n, p.n_pad,
-                                             p.V, at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA),
-                                             stream));
       uint32_t* kb[2] = {at<uint32_t>(E, L.tkB), at<uint32_t>(E, L.tkA)};
       uint32_t* vb[2] = {at<uint32_t>(E, L.tvB), at<uint32_t>(E, L.tvA)};
       int res = 0;
-      R4D_TIMED(kTileSort, onesweep_sort(at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA), kb, vb,
-                                         tseg, r.capacity, p.tile_passes, p.sort_items,
-                                         at<uint32_t>(F, L.thist), at<uint32_t>(E, L.tstatus),
-                                         tickets + kTicketTile, error, false, &res, stream));
+      R4D_HIP(onesweep_sort(at<uint32_t>(E, L.tkA), at<uint32_t>(E, L.tvA), kb, vb, tseg,
+                            r.capacity, p.tile_passes, p.sort_items, at<uint32_t>(F, L.thist),
+                            at<uint32_t>(E, L.tstatus), tickets + kTicketTile, error, true, &res,
+                            stream));
       values = vb[res];
+      sorted_tiles = kb[res];
     }
   }
+  R4D_TIMED(kTileRanges, tile_ranges(sorted_tiles, p.packed, tseg, slots, p.total_tiles,
+                                     p.n > 0 ? r.capacity : 0, ranges, stream));
   r.values = values;
   const RasterSaved<T> sv{at<Ck<T>>(E, L.ck), at<T>(F, L.img_copy), at<uint32_t>(F, L.walk)};
   R4D_TIMED(kRasterFwd,

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include "r4d_internal.hpp"
+#include "rowwalk.hpp"
 #include "tileset.hpp"
 
 namespace r4d {
@@ -89,31 +90,6 @@ __device__ __forceinline__ SpanGeom geom_of(const Rec<T>& r, const Rect16& box, 
   return span_geom(double(r.mx), double(r.my), double(r.ca), double(r.cb), double(r.cc),
                    double(r.qmax), v.W, v.H, __builtin_ctz(unsigned(v.tile_size)), box.x0,
                    box.x1);
-}
-
-// Entries [q0, q1) of one Gaussian (indices local to the Gaussian, in the
-// order of its tile list: rows top to bottom, columns left to right), the
-// whole wavefront cooperating: lane l takes tile row y0 + l (then + 64, ...),
-// a wave scan of the run lengths places every row, and each lane calls
-// put(j, tile) for the entries j of its row in [q0, q1).  Every lane must call
-// it with the same arguments.
-template <typename Put>
-__device__ __forceinline__ void wave_runs(const SpanGeom& sg, int y0, int y1, uint32_t tiles_x,
-                                          uint32_t q0, uint32_t q1, int lane, Put put) {
-  uint32_t carry = 0;
-  for (int yb = y0; yb < y1 && carry < q1; yb += 64) {
-    const int y = yb + lane;
-    int a = 0, b = 0;
-    if (y < y1) row_span(sg, y, a, b);
-    const uint32_t len = uint32_t(b - a);
-    const uint32_t incl = wave_incl_scan(len, lane);
-    const uint32_t start = carry + incl - len;
-    const uint32_t j0 = start > q0 ? start : q0;
-    const uint32_t j1 = start + len < q1 ? start + len : q1;
-    const uint32_t t0 = uint32_t(y) * tiles_x + uint32_t(a) - start;  // tile of entry j: t0 + j
-    for (uint32_t j = j0; j < j1; ++j) put(j, t0 + j);
-    carry += __shfl(incl, 63, 64);
-  }
 }
 
 template <typename T>
@@ -354,164 +330,31 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
   }
 }
 
-// Difference grids: every row run [x0, x1) of row y adds +1 at (y, x0) and -1
-// at (y, x1) (skipped when x1 is past the last column), so the prefix sum of a
-// grid row is the entry count of each of its tiles.
-//
-// tile_grid_kernel (blockIdx.y = render): with LDS_GRID every workgroup adds
-// the runs of its share of the Gaussians into a private grid in LDS and
-// writes that grid out as one partial; otherwise (grids too large for LDS) it
-// adds them into one global grid with atomics.
-template <typename T, bool LDS_GRID>
-__global__ __launch_bounds__(kThreads) void tile_grid_kernel(const Rect16* __restrict__ rects,
-                                                             const Rec<T>* __restrict__ recs,
-                                                             const ViewSlot* __restrict__ slots,
-                                                             uint32_t n, int* __restrict__ partials,
-                                                             int* __restrict__ grid) {
-  extern __shared__ int s_grid[];
-  const int v = blockIdx.y;
-  const ViewSlot& sl = slots[v];
-  const ViewDev vd = sl.v;
-  const int tx = vd.tiles_x, ty = vd.tiles_y;
-  const int W1 = tx + 1;
-  const int cells = W1 * (ty + 1);
-  if (LDS_GRID) {
-    for (int i = threadIdx.x; i < cells; i += kThreads) s_grid[i] = 0;
-    __syncthreads();
-  }
-  int* gd = LDS_GRID ? s_grid : grid + sl.grid_base;
-  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
-  const uint32_t begin = blockIdx.x * per;
-  const uint32_t end = begin + per < n ? begin + per : n;
-  const Rect16* rv = rects + size_t(v) * n;
-  const Rec<T>* cv = recs + size_t(v) * n;
-  for (uint32_t i = begin + threadIdx.x; i < end; i += kThreads) {
-    const Rect16 r = rv[i];
-    if (r.x1 == r.x0) continue;  // culled: empty box
-    const SpanGeom sg = geom_of(cv[i], r, vd);
-    for (int y = r.y0; y < r.y1; ++y) {
-      int x0, x1;
-      row_span(sg, y, x0, x1);
-      atomicAdd(&gd[y * W1 + x0], 1);
-      if (x1 < tx) atomicAdd(&gd[y * W1 + x1], -1);
-    }
-  }
-  if (LDS_GRID) {
-    __syncthreads();
-    int* out = partials + size_t(sl.grid_base) * gridDim.x + size_t(blockIdx.x) * cells;
-    for (int i = threadIdx.x; i < cells; i += kThreads) out[i] = s_grid[i];
-  }
-}
-
-// grid[c] = sum of the partial grids at cell c (cells of all renders).
-__global__ __launch_bounds__(kThreads) void grid_sum_kernel(const ViewSlot* __restrict__ slots,
-                                                            int n_views, const int* __restrict__ partials,
-                                                            int n_partials, uint32_t total_cells,
-                                                            int* __restrict__ grid) {
-  const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
-  if (c >= total_cells) return;
-  int v = 0;
-  while (v + 1 < n_views && slots[v + 1].grid_base <= c) ++v;
-  const uint32_t gb = slots[v].grid_base;
-  const uint32_t cells = uint32_t(slots[v].v.tiles_x + 1) * uint32_t(slots[v].v.tiles_y + 1);
-  const int* pv = partials + size_t(gb) * n_partials + (c - gb);
-  int acc = 0;
-#pragma unroll 8
-  for (int b = 0; b < n_partials; ++b) acc += pv[size_t(b) * cells];
-  grid[c] = acc;
-}
-
-// One workgroup per render: takes the prefix sum of every grid row (in LDS when
-// the grid fits) to get every tile's entry count,
-// and scans the counts in tile order into the tile ranges inside the render's
-// segment of the emitted list; their digit sums give the tile sort's
-// histograms.  Also lays out the segments (render v starts at the sum of the
-// earlier renders' counts, each rounded up to 4096) and reports overflow of the
-// entry capacity, in which case every segment is empty and every range is
-// [0, 0).
-constexpr int kTcThreads = 1024;
-
-template <bool LDS_GRID>
-__global__ __launch_bounds__(kTcThreads) void tile_count_kernel(
-    const ViewSlot* __restrict__ slots, int n_views, int* __restrict__ grid,
-    const unsigned long long* __restrict__ totals,
-    unsigned long long capacity, uint2* __restrict__ ranges, uint32_t* __restrict__ hist,
-    SegTable* __restrict__ seg) {
-  extern __shared__ int s_grid[];
-  __shared__ uint32_t s_h[3][256];
-  __shared__ uint32_t s_w[kTcThreads / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int v = blockIdx.x;
-  for (int i = tid; i < 3 * 256; i += kTcThreads) (&s_h[0][0])[i] = 0u;
-  unsigned long long base = 0, total = 0;
+// Segment table of the emitted list: render v's entries start at the sum of
+// the earlier renders' counts, each rounded up to 4096.  When the entries do
+// not fit the capacity (or a render exceeds the per-segment limit) every
+// segment is empty and `overflow` is set.
+__global__ void seg_table_kernel(const unsigned long long* __restrict__ totals, int n_views,
+                                 unsigned long long capacity, SegTable* __restrict__ seg) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long total = 0;
   bool too_long = false;
-  for (int u = 0; u < n_views; ++u) {
-    const unsigned long long d = totals[2 * u + 1];
-    const unsigned long long pd = (d + kSegAlign - 1) / kSegAlign * kSegAlign;
-    if (u < v) base += pd;
-    total += pd;
+  for (int v = 0; v < n_views; ++v) {
+    const unsigned long long d = totals[2 * v + 1];
+    total += (d + kSegAlign - 1) / kSegAlign * kSegAlign;
     too_long |= d > kStatMask;
   }
   const bool overflow = too_long || total > capacity;
-  const unsigned long long Dv = totals[2 * v + 1];
-  if (tid == 0) {
+  unsigned long long base = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const unsigned long long d = totals[2 * v + 1];
     seg->start[v] = overflow ? 0u : uint32_t(base);
-    seg->len[v] = overflow ? 0u : uint32_t(Dv);
-    if (v == n_views - 1) seg->start[n_views] = overflow ? 0u : uint32_t(total);
-    if (v == 0) {
-      seg->count = uint32_t(n_views);
-      seg->overflow = overflow ? 1u : 0u;
-    }
+    seg->len[v] = overflow ? 0u : uint32_t(d);
+    base += (d + kSegAlign - 1) / kSegAlign * kSegAlign;
   }
-  const ViewSlot& sl = slots[v];
-  const int tx = sl.v.tiles_x, ty = sl.v.tiles_y;
-  const uint32_t ntiles = uint32_t(tx) * uint32_t(ty);
-  if (overflow) {
-    for (uint32_t t = tid; t < ntiles; t += kTcThreads) ranges[sl.tile_base + t] = make_uint2(0u, 0u);
-  } else {
-    const int W1 = tx + 1, H1 = ty + 1, cells = W1 * H1;
-    int* gd = grid + sl.grid_base;
-    if (LDS_GRID) {
-      for (int i = tid; i < cells; i += kTcThreads) s_grid[i] = gd[i];
-      gd = s_grid;
-    }
-    __syncthreads();
-    for (int row = wave; row < ty; row += kTcThreads / 64) {
-      int carry = 0;
-      for (int c0 = 0; c0 < tx; c0 += 64) {
-        const int x = c0 + lane;
-        const int val = x < tx ? gd[row * W1 + x] : 0;
-        const int inc = wave_incl_scan(val, lane) + carry;
-        if (x < tx) gd[row * W1 + x] = inc;
-        carry = __shfl(inc, 63, 64);
-      }
-    }
-    __syncthreads();
-    uint32_t run = uint32_t(base);
-    const uint32_t seg_end = uint32_t(base + Dv);
-    for (uint32_t t0 = 0; t0 < ntiles; t0 += kTcThreads) {
-      const uint32_t t = t0 + tid;
-      const uint32_t c = t < ntiles ? uint32_t(gd[int(t / tx) * W1 + int(t % tx)]) : 0u;
-      uint32_t tot;
-      const uint32_t ex = block_excl_scan<kTcThreads>(c, s_w, &tot) + run;
-      if (t < ntiles) {
-        // (clamped to the segment: the grid and the per-Gaussian counts follow
-        // the same runs, so this only guards the reads of the rasteriser)
-        const uint32_t e0 = ex < seg_end ? ex : seg_end;
-        const uint32_t e1 = ex + c < seg_end ? ex + c : seg_end;
-        ranges[sl.tile_base + t] = c ? make_uint2(e0, e1) : make_uint2(0u, 0u);
-        if (c) {
-          atomicAdd(&s_h[0][t & 255u], c);
-          atomicAdd(&s_h[1][(t >> 8) & 255u], c);
-          atomicAdd(&s_h[2][(t >> 16) & 255u], c);
-        }
-      }
-      run += tot;
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < 3 * 256; i += kTcThreads)
-    hist[(size_t(i >> 8) * kMaxViews + v) * 256 + (i & 255)] = (&s_h[0][0])[i];
+  seg->start[n_views] = overflow ? 0u : uint32_t(total);
+  seg->count = uint32_t(n_views);
+  seg->overflow = overflow ? 1u : 0u;
 }
 
 // Exclusive scan input: tile counts of every render's Gaussians in depth order,
@@ -527,48 +370,6 @@ struct LoadCountGatherSeg {
     return k < n ? uint64_t(counts[size_t(v) * n + order[i]]) : uint64_t(0);
   }
 };
-
-// Tile-key emission: each wavefront takes 64 consecutive Gaussians of one
-// render's depth order and writes their tile entries one Gaussian at a time,
-// the lanes on its tile rows (wave_runs).  Keys are render-local tile ids.
-template <typename T>
-__global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ order,
-                                                   const uint64_t* __restrict__ offsets,
-                                                   const Rect16* __restrict__ rects,
-                                                   const Rec<T>* __restrict__ recs,
-                                                   const ViewSlot* __restrict__ slots,
-                                                   const SegTable* __restrict__ seg, uint32_t n,
-                                                   uint32_t n_pad, uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals) {
-  const uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x;
-  const uint32_t v = blockIdx.y;
-  const int lane = threadIdx.x & 63;
-  if (seg->overflow) return;
-  const uint32_t kk = uint32_t(i);
-  uint32_t idx = 0, cnt = 0, off = 0;
-  const size_t row = size_t(v) * n_pad;
-  if (kk < n) {
-    idx = order[row + kk];
-    off = seg->start[v] + uint32_t(offsets[row + kk] - offsets[row]);
-    cnt = uint32_t(offsets[row + kk + 1] - offsets[row + kk]);
-  }
-  const ViewDev vd = slots[v].v;
-  const uint32_t tiles_x = uint32_t(vd.tiles_x);
-  unsigned long long todo = __ballot(cnt > 0);
-  while (todo) {
-    const int src = __ffsll((long long)todo) - 1;
-    todo &= todo - 1ull;
-    const uint32_t s_idx = __shfl(idx, src, 64);
-    const uint32_t s_cnt = __shfl(cnt, src, 64);
-    const uint32_t s_off = __shfl(off, src, 64);
-    const Rect16 r = rects[size_t(v) * n + s_idx];
-    const SpanGeom sg = geom_of(recs[size_t(v) * n + s_idx], r, vd);
-    wave_runs(sg, r.y0, r.y1, tiles_x, 0u, s_cnt, lane, [&](uint32_t j, uint32_t tile) {
-      keys[s_off + j] = tile;
-      vals[s_off + j] = s_idx;
-    });
-  }
-}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void fill_const_kernel(T* __restrict__ p, size_t count,
@@ -617,14 +418,13 @@ uint32_t grid_for(size_t count) {
 // ---- packed tile sort
 // For renders with at most 65536 tiles and at most 2^24 Gaussians the tile
 // sort runs on one 32-bit word per entry: Gaussian index in bits 0..23, the
-// high 8 bits of the tile id in bits 24..31.  The entries of a render are
-// numbered in emission order (Gaussians in depth order, each one's tiles
-// row-major) and cut into blocks of 4096; block b of the render is also block
-// b of its segment of the sorted output.  Both passes are reduce-then-scan:
-// per-block digit counts, a column scan of those counts, then a stable
-// scatter, so no workgroup waits on another.  The first (low-digit) pass
-// generates its block's entries itself from the Gaussians' rectangles, so
-// the emitted list is never written.
+// high 8 bits of the tile id in bits 24..31; the low 8 bits ride along as one
+// byte per entry for the first pass.  The entries of a render are numbered in
+// emission order (Gaussians in depth order, each one's tiles row by row) and
+// cut into blocks of 4096; block b of the render is also block b of its
+// segment of the sorted output.  Both passes are reduce-then-scan: per-block
+// digit counts, a column scan of those counts, then a stable scatter, so no
+// workgroup waits on another.
 constexpr int kChunk = 4096;   // entries per block
 
 __device__ __forceinline__ bool block_span(const SegTable* seg, uint32_t e0, uint32_t& s,
@@ -637,8 +437,8 @@ __device__ __forceinline__ bool block_span(const SegTable* seg, uint32_t e0, uin
   return true;
 }
 
-// first[b] = depth position of the Gaussian whose entries contain the first
-// entry of block b.
+// first[b] = depth position of the Gaussian whose entries hold the first
+// entry of block b (segments start at multiples of the block size).
 __global__ __launch_bounds__(kThreads) void first_gaussian_kernel(
     const uint64_t* __restrict__ offsets, const SegTable* __restrict__ seg, uint32_t n,
     uint32_t n_pad, uint32_t* __restrict__ first) {
@@ -654,88 +454,206 @@ __global__ __launch_bounds__(kThreads) void first_gaussian_kernel(
     first[sb + blk] = k;
 }
 
-// Adds the low digits of tiles [t, t + len) (consecutive ids) to a 256-bin
-// difference array (plus a count added to every bin).
-__device__ __forceinline__ void add_digit_range(int* diff, uint32_t* all, uint32_t t, uint32_t len) {
-  if (len >= 256u) atomicAdd(all, len >> 8);
-  const uint32_t rem = len & 255u;
-  if (!rem) return;
-  const uint32_t a = t & 255u, e = a + rem;
-  atomicAdd(&diff[a], 1);
-  if (e <= 256u) {
-    atomicAdd(&diff[e], -1);
-  } else {
-    atomicAdd(&diff[256], -1);
-    atomicAdd(&diff[0], 1);
-    atomicAdd(&diff[e - 256u], -1);
-  }
-}
-
-// Low-digit counts of every block's entries, from the row runs: the part of a
-// Gaussian inside a block is a few runs of consecutive tile ids.  One thread
-// per Gaussian walks its rows.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void lo_count_kernel(
+// Emission of the tile entries, one block of 4096 entries (in emission order:
+// Gaussians in depth order, each one's tiles row by row) per workgroup, so the
+// work is balanced whatever the footprints.  The block's Gaussians are taken
+// 256 at a time, one per thread; their tile rows are walked together, one row
+// per thread (the holder of a row found by a binary search over the
+// Gaussians' first row numbers), each row's run placed by a block scan of the
+// run lengths, and its entries inside the block written to LDS; the block is
+// then written out coalesced.  PACKED: out_a = Gaussian index | high tile
+// byte << 24, out_b = low tile byte (bytes); otherwise out_a = tile id, out_b
+// = Gaussian index (words).
+template <typename T, bool PACKED>
+__global__ __launch_bounds__(kThreads) void emit_block_kernel(
     const uint32_t* __restrict__ order, const uint64_t* __restrict__ offsets,
     const Rect16* __restrict__ rects, const Rec<T>* __restrict__ recs,
-    const ViewSlot* __restrict__ slots,
-    const SegTable* __restrict__ seg, const uint32_t* __restrict__ first, uint32_t n,
-    uint32_t n_pad, uint32_t* __restrict__ cnt) {
-  __shared__ int s_diff[257];
-  __shared__ uint32_t s_all;
+    const ViewSlot* __restrict__ slots, const SegTable* __restrict__ seg,
+    const uint32_t* __restrict__ first, uint32_t n, uint32_t n_pad, uint32_t* __restrict__ out_a,
+    void* __restrict__ out_b) {
+  __shared__ uint32_t s_a[kChunk];
+  __shared__ uint32_t s_b[kChunk];
+  __shared__ uint32_t s_first[kThreads];
+  __shared__ float s_geo[6][kThreads];
+  __shared__ int s_x0[kThreads], s_x1[kThreads], s_y0[kThreads];
+  __shared__ uint32_t s_gi[kThreads];
   __shared__ uint32_t s_w[kThreads / 64];
+  __shared__ uint32_t s_ga;
+  const int tid = threadIdx.x;
   const uint32_t b = blockIdx.x;
-  s_diff[threadIdx.x] = 0;
-  if (threadIdx.x == 0) {
-    s_diff[256] = 0;
-    s_all = 0u;
+  uint32_t s, sstart, nvalid;
+  if (seg->overflow || !block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid)
+    return;
+  const uint32_t lo = b * uint32_t(kChunk) - sstart, hi = lo + nvalid;  // render-local entries
+  const size_t row = size_t(s) * n_pad;
+  const uint64_t o0 = offsets[row];
+  const ViewDev vd = slots[s].v;
+  const uint32_t tx = uint32_t(vd.tiles_x);
+  for (uint32_t q = tid; q < nvalid; q += kThreads) {  // (every slot is written below)
+    s_a[q] = 0u;
+    s_b[q] = 0u;
   }
-  __syncthreads();
-  uint32_t s = 0, sstart = 0, nvalid = 0;
-  if (!seg->overflow && block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) && nvalid) {
-    const uint32_t lo = b * uint32_t(kChunk) - sstart, hi = lo + nvalid;  // render-local entries
-    const size_t row = size_t(s) * n_pad;
-    const uint64_t o0 = offsets[row];
-    const ViewDev vd = slots[s].v;
-    const uint32_t tiles_x = uint32_t(vd.tiles_x);
-    const uint32_t k0 = first[b];
-    for (uint32_t base = k0;; base += kThreads) {
-      const uint32_t k = base + threadIdx.x;
-      bool more = false;
-      if (k < n) {
-        const uint32_t a = uint32_t(offsets[row + k] - o0);
-        const uint32_t e = uint32_t(offsets[row + k + 1] - o0);
-        const uint32_t gi = order[row + k];
-        if (a < hi) {
-          more = true;
-          const uint32_t c0 = a > lo ? a : lo, c1 = e < hi ? e : hi;
-          if (c0 < c1) {
-            const Rect16 r = rects[size_t(s) * n + gi];
-            const SpanGeom sg = geom_of(recs[size_t(s) * n + gi], r, vd);
-            const uint32_t q0 = c0 - a, q1 = c1 - a;
-            uint32_t start = 0;  // local index of the row's first entry
-            for (int y = r.y0; y < r.y1 && start < q1; ++y) {
-              int x0, x1;
-              row_span(sg, y, x0, x1);
-              const uint32_t len = uint32_t(x1 - x0);
-              const uint32_t j0 = start > q0 ? start : q0;
-              const uint32_t j1 = start + len < q1 ? start + len : q1;
-              if (j0 < j1)
-                add_digit_range(s_diff, &s_all, uint32_t(y) * tiles_x + uint32_t(x0) + (j0 - start),
-                                j1 - j0);
-              start += len;
-            }
+  for (uint32_t kb = first[b];; kb += kThreads) {
+    const uint32_t k = kb + uint32_t(tid);
+    uint32_t a = hi, rows = 0;
+    if (k < n) a = uint32_t(offsets[row + k] - o0);
+    const bool has = k < n && a < hi;
+    if (has) {
+      const uint32_t gi = order[row + k];
+      const Rect16 r = rects[size_t(s) * n + gi];
+      const SpanGeom g = geom_of(recs[size_t(s) * n + gi], r, vd);
+      rows = uint32_t(r.y1 - r.y0);
+      s_geo[0][tid] = g.mx;
+      s_geo[1][tid] = g.my;
+      s_geo[2][tid] = g.beta;
+      s_geo[3][tid] = g.gamma;
+      s_geo[4][tid] = g.hy;
+      s_geo[5][tid] = g.ds;
+      s_x0[tid] = g.x0;
+      s_x1[tid] = g.x1;
+      s_y0[tid] = r.y0;
+      s_gi[tid] = gi;
+    }
+    if (tid == 0) s_ga = a;  // the group's entries start at its first Gaussian's
+    uint32_t total_rows;
+    s_first[tid] = block_excl_scan<kThreads>(rows, s_w, &total_rows);
+    __syncthreads();
+    const uint32_t ga = s_ga;
+    uint32_t carry = 0;  // entries of the rows before the current 256
+    for (uint32_t c = 0; c < total_rows; c += kThreads) {
+      const uint32_t p = c + uint32_t(tid);
+      const bool ok = p < total_rows;
+      // holder: the last thread whose first row number is <= p
+      int o = 0;
+#pragma unroll
+      for (int step = kThreads / 2; step >= 1; step >>= 1)
+        if (s_first[o + step] <= p) o += step;
+      int x0 = 0, x1 = 0, y = 0;
+      if (ok) {
+        SpanGeom g;
+        g.mx = s_geo[0][o];
+        g.my = s_geo[1][o];
+        g.beta = s_geo[2][o];
+        g.gamma = s_geo[3][o];
+        g.hy = s_geo[4][o];
+        g.ds = s_geo[5][o];
+        g.x0 = s_x0[o];
+        g.x1 = s_x1[o];
+        g.W = vd.W;
+        g.H = vd.H;
+        g.sh = __builtin_ctz(unsigned(vd.tile_size));
+        y = s_y0[o] + int(p - s_first[o]);
+        row_span(g, y, x0, x1);
+      }
+      const uint32_t len = uint32_t(x1 - x0);
+      uint32_t tot;
+      const uint32_t e0 = ga + carry + block_excl_scan<kThreads>(len, s_w, &tot);
+      const uint32_t j0 = e0 > lo ? e0 : lo, j1 = e0 + len < hi ? e0 + len : hi;
+      if (j0 < j1) {
+        const uint32_t gi = s_gi[o];
+        const uint32_t t0 = uint32_t(y) * tx + uint32_t(x0) - e0;  // tile of entry j: t0 + j
+        for (uint32_t j = j0; j < j1; ++j) {
+          const uint32_t tile = t0 + j;
+          if (PACKED) {
+            s_a[j - lo] = gi | ((tile >> 8) << 24);
+            s_b[j - lo] = tile & 255u;
+          } else {
+            s_a[j - lo] = tile;
+            s_b[j - lo] = gi;
           }
         }
       }
-      if (!__syncthreads_or(more)) break;
+      carry += tot;
+    }
+    // more Gaussians start inside the block only if the group's last one did
+    const bool more = __syncthreads_or(tid == kThreads - 1 && has);
+    if (!more) break;
+  }
+  __syncthreads();
+  const uint32_t e0 = b * uint32_t(kChunk);
+  for (uint32_t q = tid; q < nvalid; q += kThreads) {
+    out_a[e0 + q] = s_a[q];
+    if (PACKED)
+      static_cast<uint8_t*>(out_b)[e0 + q] = uint8_t(s_b[q]);
+    else
+      static_cast<uint32_t*>(out_b)[e0 + q] = s_b[q];
+  }
+}
+
+// Tile ranges from the sorted tile ids of every segment: position p starts the
+// range of its tile when p is the segment's first position or the previous
+// tile differs, and ends it likewise (ranges zeroed beforehand, so tiles
+// without entries keep [0, 0)).
+template <typename K>
+__global__ __launch_bounds__(kThreads) void ranges_kernel(const K* __restrict__ tiles,
+                                                          const SegTable* __restrict__ seg,
+                                                          const ViewSlot* __restrict__ slots,
+                                                          uint2* __restrict__ ranges) {
+  const uint32_t b = blockIdx.x;
+  uint32_t s, sstart, nvalid;
+  if (seg->overflow || !block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid)
+    return;
+  const uint32_t send = sstart + seg->len[s];
+  const uint32_t tb = slots[s].tile_base;
+  const uint32_t e0 = b * uint32_t(kChunk);
+  for (uint32_t q = threadIdx.x; q < nvalid; q += kThreads) {
+    const uint32_t p = e0 + q;
+    const uint32_t t = uint32_t(tiles[p]);
+    if (p == sstart || uint32_t(tiles[p - 1]) != t) ranges[tb + t].x = p;
+    if (p + 1 == send || uint32_t(tiles[p + 1]) != t) ranges[tb + t].y = p + 1;
+  }
+}
+
+// Digit histograms hist[p][s][256] of the emitted tile ids for the onesweep
+// tile sort (zeroed beforehand).
+template <int PASSES>
+__global__ __launch_bounds__(kThreads) void tile_hist_kernel(const uint32_t* __restrict__ keys,
+                                                             const SegTable* __restrict__ seg,
+                                                             uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[PASSES][256];
+#pragma unroll
+  for (int p = 0; p < PASSES; ++p) h[p][threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t b = blockIdx.x;
+  uint32_t s = 0, sstart, nvalid = 0;
+  if (!seg->overflow && block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid)) {
+    const uint32_t e0 = b * uint32_t(kChunk);
+    for (uint32_t q = threadIdx.x; q < nvalid; q += kThreads) {
+      const uint32_t key = keys[e0 + q];
+#pragma unroll
+      for (int p = 0; p < PASSES; ++p) atomicAdd(&h[p][(key >> (8 * p)) & 255u], 1u);
     }
   }
   __syncthreads();
-  uint32_t tot;
-  const int x = s_diff[threadIdx.x];
-  const uint32_t incl = block_excl_scan<kThreads>(uint32_t(x), s_w, &tot) + uint32_t(x);
-  cnt[size_t(b) * 256 + threadIdx.x] = nvalid ? incl + s_all : 0u;
+  if (nvalid) {
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+      const uint32_t c = h[p][threadIdx.x];
+      if (c) atomicAdd(&hist[(size_t(p) * kMaxViews + s) * 256 + threadIdx.x], c);
+    }
+  }
+}
+
+// Low-digit counts per block of the emitted entries (digits: one byte each).
+__global__ __launch_bounds__(kThreads) void lo_count_kernel(const uint8_t* __restrict__ digits,
+                                                            const SegTable* __restrict__ seg,
+                                                            uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t s_h[kThreads / 64][256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) s_h[w][tid] = 0u;
+  __syncthreads();
+  const uint32_t b = blockIdx.x;
+  uint32_t s, sstart, nvalid = 0;
+  if (!seg->overflow && block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid)) {
+    const uint32_t e0 = b * uint32_t(kChunk);
+    for (uint32_t q = tid; q < nvalid; q += kThreads) atomicAdd(&s_h[wave][digits[e0 + q]], 1u);
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) c += s_h[w][tid];
+  cnt[size_t(b) * 256 + tid] = c;
 }
 
 // Exclusive prefix of M[rows][256] along rows, per column: P[r][d] =
@@ -854,21 +772,19 @@ __device__ __forceinline__ void rank_block(const uint32_t (&dg)[ITEMS], uint32_t
   for (int i = 0; i < ITEMS; ++i) pos[i] += s_start[dg[i]] + s_wh[wave][dg[i]];
 }
 
-// Low-digit pass: block b generates its entries (Gaussians from first[b] on,
-// each one's part inside the block written by the lanes of one wavefront, one
-// lane per tile row), ranks them stably by the low 8 bits of the tile id and
-// writes them, as packed words, in runs of equal digit to their place in the
-// segment.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void lo_pass_kernel(
-    const uint32_t* __restrict__ order, const uint64_t* __restrict__ offsets,
-    const Rect16* __restrict__ rects, const Rec<T>* __restrict__ recs,
-    const ViewSlot* __restrict__ slots,
-    const SegTable* __restrict__ seg, const uint32_t* __restrict__ first,
-    const uint32_t* __restrict__ P, uint32_t n, uint32_t n_pad, uint32_t* __restrict__ out) {
+// Low-digit pass: stable scatter of each block's packed entries by the low
+// tile byte, in runs of equal digit, to their place in the segment; the
+// written word carries the low byte in place of the high one, which goes to
+// hi_out.
+__global__ __launch_bounds__(kThreads) void lo_pass_kernel(const uint32_t* __restrict__ in,
+                                                           const uint8_t* __restrict__ digits,
+                                                           const SegTable* __restrict__ seg,
+                                                           const uint32_t* __restrict__ P,
+                                                           uint32_t* __restrict__ out,
+                                                           uint8_t* __restrict__ hi_out) {
   constexpr int ITEMS = kChunk / kThreads;
-  __shared__ uint32_t s_val[kChunk];
-  __shared__ uint8_t s_dig[kChunk];
+  __shared__ uint32_t s_sorted[kChunk];
+  __shared__ uint8_t s_dsorted[kChunk];
   __shared__ uint32_t s_base[256], s_start[256];
   __shared__ uint32_t s_wh[kThreads / 64][256];
   __shared__ uint32_t s_w[kThreads / 64];
@@ -878,114 +794,57 @@ __global__ __launch_bounds__(kThreads) void lo_pass_kernel(
   if (seg->overflow || !block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid)
     return;
   const uint32_t send = sstart + seg->len[s];
-  s_base[tid] = digit_out_base(P, sstart / uint32_t(kChunk),
-                               (send + uint32_t(kChunk) - 1) / uint32_t(kChunk), b, sstart, s_w);
-  const uint32_t lo = b * uint32_t(kChunk) - sstart, hi = lo + nvalid;  // render-local entries
-  const size_t row = size_t(s) * n_pad;
-  const uint64_t o0 = offsets[row];
-  const ViewDev vd = slots[s].v;
-  const uint32_t tiles_x = uint32_t(vd.tiles_x);
-  // generate: wave w takes the Gaussians first[b] + 64 w + lane, then + 256, ...
-  // every slot is written below; zeroed first so that no slot can hold a
-  // stale value whatever the runs are
-  for (uint32_t q = tid; q < nvalid; q += kThreads) {
-    s_val[q] = 0u;
-    s_dig[q] = 0u;
-  }
-  __syncthreads();
-  const uint32_t k0 = first[b];
-  for (uint32_t base = k0 + uint32_t(wave) * 64u;; base += kThreads) {
-    const uint32_t k = base + uint32_t(lane);
-    uint32_t a = hi, e = hi, gi = 0;
-    if (k < n) {  // independent loads, issued together
-      a = uint32_t(offsets[row + k] - o0);
-      e = uint32_t(offsets[row + k + 1] - o0);
-      gi = order[row + k];
-    }
-    const uint32_t c0 = a > lo ? a : lo, c1 = e < hi ? e : hi;
-    const bool has = c0 < c1;
-    unsigned long long todo = __ballot(has);
-    while (todo) {
-      const int src = __ffsll((long long)todo) - 1;
-      todo &= todo - 1ull;
-      const uint32_t sa = __shfl(a, src, 64), s0 = __shfl(c0, src, 64), s1 = __shfl(c1, src, 64);
-      const uint32_t sgi = __shfl(gi, src, 64);
-      const Rect16 r = rects[size_t(s) * n + sgi];
-      const SpanGeom sg = geom_of(recs[size_t(s) * n + sgi], r, vd);
-      const uint32_t base_q = sa - lo;  // block slot of the Gaussian's entry 0
-      wave_runs(sg, r.y0, r.y1, tiles_x, s0 - sa, s1 - sa, lane, [&](uint32_t j, uint32_t tile) {
-        s_val[base_q + j] = sgi | ((tile >> 8) << 24);
-        s_dig[base_q + j] = uint8_t(tile & 255u);
-      });
-    }
-    // Gaussians start in increasing order: stop once every lane is past the block
-    if (!__any(k < n && a < hi)) break;
-  }
-  __syncthreads();
-  uint32_t v[ITEMS], dg[ITEMS], pos[ITEMS];
+  const uint32_t e0 = b * uint32_t(kChunk);
+  uint32_t x[ITEMS], dg[ITEMS], pos[ITEMS];
   const uint32_t wbase = uint32_t(wave) * ITEMS * 64u;
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t q = wbase + uint32_t(i) * 64u + uint32_t(lane);
-    v[i] = q < nvalid ? s_val[q] : 0u;
-    dg[i] = q < nvalid ? uint32_t(s_dig[q]) : 0u;
+    x[i] = q < nvalid ? in[e0 + q] : 0u;
+    dg[i] = q < nvalid ? uint32_t(digits[e0 + q]) : 0u;
   }
+  s_base[tid] = digit_out_base(P, sstart / uint32_t(kChunk),
+                               (send + uint32_t(kChunk) - 1) / uint32_t(kChunk), b, sstart, s_w);
   rank_block<ITEMS>(dg, nvalid, 8, s_wh, s_start, s_w, pos);
-  // (rank_block's barriers separate the reads above from the writes below)
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t q = wbase + uint32_t(i) * 64u + uint32_t(lane);
     if (q < nvalid) {
-      s_val[pos[i]] = v[i];
-      s_dig[pos[i]] = uint8_t(dg[i]);
+      s_sorted[pos[i]] = x[i];
+      s_dsorted[pos[i]] = uint8_t(dg[i]);
     }
   }
   __syncthreads();
   for (uint32_t p = tid; p < nvalid; p += kThreads) {
-    const uint32_t d = s_dig[p];
+    const uint32_t d = s_dsorted[p];
+    const uint32_t x = s_sorted[p];
     const uint32_t pos = s_base[d] + (p - s_start[d]);
-    if (pos < send) out[pos] = s_val[p];
+    out[pos] = (x & 0xffffffu) | (d << 24);
+    hi_out[pos] = uint8_t(x >> 24);
   }
-}
-
-// High-digit counts per block of the low-digit pass output.
-__global__ __launch_bounds__(kThreads) void hi_count_kernel(const uint32_t* __restrict__ in,
-                                                            const SegTable* __restrict__ seg,
-                                                            uint32_t* __restrict__ cnt) {
-  __shared__ uint32_t s_h[kThreads / 64][256];
-  const int tid = threadIdx.x, wave = tid >> 6;
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) s_h[w][tid] = 0u;
-  __syncthreads();
-  const uint32_t b = blockIdx.x;
-  uint32_t s, sstart, nvalid = 0;
-  if (block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid)) {
-    const uint32_t e0 = b * uint32_t(kChunk);
-    for (uint32_t q = tid; q < nvalid; q += kThreads) atomicAdd(&s_h[wave][in[e0 + q] >> 24], 1u);
-  }
-  __syncthreads();
-  uint32_t c = 0;
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) c += s_h[w][tid];
-  cnt[size_t(b) * 256 + tid] = c;
 }
 
 // High-digit pass: stable scatter of each block's entries by the high tile
-// digit (nbits significant bits); writes the Gaussian index (bits 0..23).
+// byte (nbits significant bits, from hi_in); writes the Gaussian index and the
+// 16-bit tile id of every sorted entry.
 __global__ __launch_bounds__(kThreads) void hi_pass_kernel(const uint32_t* __restrict__ in,
+                                                           const uint8_t* __restrict__ hi_in,
                                                            const SegTable* __restrict__ seg,
                                                            const uint32_t* __restrict__ P,
                                                            int nbits,
-                                                           uint32_t* __restrict__ values) {
+                                                           uint32_t* __restrict__ values,
+                                                           uint16_t* __restrict__ tiles) {
   constexpr int ITEMS = kChunk / kThreads;
   __shared__ uint32_t s_sorted[kChunk];
+  __shared__ uint8_t s_dsorted[kChunk];
   __shared__ uint32_t s_base[256], s_start[256];
   __shared__ uint32_t s_wh[kThreads / 64][256];
   __shared__ uint32_t s_w[kThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t b = blockIdx.x;
   uint32_t s, sstart, nvalid;
-  if (!block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid) return;
+  if (seg->overflow || !block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid)
+    return;
   const uint32_t send = sstart + seg->len[s];
   const uint32_t e0 = b * uint32_t(kChunk);
   uint32_t x[ITEMS], dg[ITEMS], pos[ITEMS];
@@ -994,7 +853,7 @@ __global__ __launch_bounds__(kThreads) void hi_pass_kernel(const uint32_t* __res
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t q = wbase + uint32_t(i) * 64u + uint32_t(lane);
     x[i] = q < nvalid ? in[e0 + q] : 0u;
-    dg[i] = x[i] >> 24;
+    dg[i] = q < nvalid ? uint32_t(hi_in[e0 + q]) : 0u;
   }
   s_base[tid] = digit_out_base(P, sstart / uint32_t(kChunk),
                                (send + uint32_t(kChunk) - 1) / uint32_t(kChunk), b, sstart, s_w);
@@ -1002,13 +861,18 @@ __global__ __launch_bounds__(kThreads) void hi_pass_kernel(const uint32_t* __res
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t q = wbase + uint32_t(i) * 64u + uint32_t(lane);
-    if (q < nvalid) s_sorted[pos[i]] = x[i];
+    if (q < nvalid) {
+      s_sorted[pos[i]] = x[i];
+      s_dsorted[pos[i]] = uint8_t(dg[i]);
+    }
   }
   __syncthreads();
   for (uint32_t p = tid; p < nvalid; p += kThreads) {
+    const uint32_t d = s_dsorted[p];
     const uint32_t y = s_sorted[p];
-    const uint32_t d = y >> 24;
-    values[s_base[d] + (p - s_start[d])] = y & 0xffffffu;
+    const uint32_t o = s_base[d] + (p - s_start[d]);
+    values[o] = y & 0xffffffu;
+    tiles[o] = uint16_t((d << 8) | (y >> 24));
   }
 }
 
@@ -1115,72 +979,74 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
   return hipSuccess;
 }
 
-int tile_grid_partials(uint32_t n) {
-  const uint32_t b = (n + 8191) / 8192;
-  return int(b < 1 ? 1 : (b > 64 ? 64 : b));
-}
-
-size_t tile_grid_lds_limit() {
-  static const size_t limit = [] {
-    int dev = 0, bytes = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-            hipSuccess) {
-      (void)hipGetLastError();
-      bytes = 65536;
-    }
-    // leave room for the counting kernel's static LDS
-    const size_t b = size_t(bytes) > 8192 ? size_t(bytes) - 8192 : 0;
-    if (b > 65536) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_grid_kernel<float, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(b));
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_grid_kernel<double, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(b));
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_count_kernel<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(b));
-      (void)hipGetLastError();
-    }
-    return b;
-  }();
-  return limit;
-}
-
-template <typename T>
-hipError_t tile_grids(const Rect16* rects, const Rec<T>* recs, const ViewSlot* slots,
-                      int n_views, uint32_t n, uint64_t max_cells, uint64_t total_cells,
-                      int* partials, int* grid, hipStream_t stream) {
-  if (n == 0 || n_views <= 0) return hipSuccess;
-  const int B = tile_grid_partials(n);
-  const dim3 g{uint32_t(B), uint32_t(n_views), 1u};
-  const size_t lds = size_t(max_cells) * 4;
-  if (lds <= tile_grid_lds_limit()) {
-    hipLaunchKernelGGL((tile_grid_kernel<T, true>), g, dim3(kThreads), lds, stream, rects, recs,
-                       slots, n, partials, grid);
-    hipLaunchKernelGGL(grid_sum_kernel, dim3(uint32_t((total_cells + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, stream, slots, n_views, partials, B,
-                       uint32_t(total_cells), grid);
-  } else {
-    hipLaunchKernelGGL((tile_grid_kernel<T, false>), g, dim3(kThreads), 0, stream, rects, recs,
-                       slots, n, partials, grid);
-  }
+hipError_t seg_table(const unsigned long long* totals, int n_views, unsigned long long capacity,
+                     SegTable* seg, hipStream_t stream) {
+  hipLaunchKernelGGL(seg_table_kernel, dim3(1), dim3(64), 0, stream, totals, n_views, capacity,
+                     seg);
   return hipGetLastError();
 }
 
-template hipError_t tile_grids<float>(const Rect16*, const Rec<float>*, const ViewSlot*, int,
-                                      uint32_t, uint64_t, uint64_t, int*, int*, hipStream_t);
-template hipError_t tile_grids<double>(const Rect16*, const Rec<double>*, const ViewSlot*, int,
-                                       uint32_t, uint64_t, uint64_t, int*, int*, hipStream_t);
+size_t emit_temp_bytes(uint64_t capacity) {
+  return size_t((capacity + kChunk - 1) / kChunk + 64) * 4;
+}
 
-hipError_t tile_counts(const ViewSlot* slots, int n_views, uint64_t max_cells, int* grid,
-                       const unsigned long long* totals, unsigned long long capacity,
-                       uint2* ranges, uint32_t* hist, SegTable* seg, hipStream_t stream) {
-  const size_t lds = size_t(max_cells) * 4;
-  if (lds <= tile_grid_lds_limit())
-    hipLaunchKernelGGL(tile_count_kernel<true>, dim3(n_views), dim3(kTcThreads), lds, stream,
-                       slots, n_views, grid, totals, capacity, ranges, hist, seg);
+template <typename T>
+hipError_t emit_blocks(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
+                       const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg, uint32_t n,
+                       uint32_t n_pad, int n_views, uint64_t capacity, bool packed, void* temp,
+                       uint32_t* out_a, void* out_b, hipStream_t stream) {
+  const uint32_t blocks = uint32_t((capacity + kChunk - 1) / kChunk);
+  if (n == 0 || n_views <= 0 || blocks == 0) return hipSuccess;
+  uint32_t* first = static_cast<uint32_t*>(temp);
+  hipLaunchKernelGGL(first_gaussian_kernel, dim3((n + kThreads - 1) / kThreads, uint32_t(n_views)),
+                     dim3(kThreads), 0, stream, offsets, seg, n, n_pad, first);
+  if (packed)
+    hipLaunchKernelGGL((emit_block_kernel<T, true>), dim3(blocks), dim3(kThreads), 0, stream,
+                       order, offsets, rects, recs, slots, seg, first, n, n_pad, out_a, out_b);
   else
-    hipLaunchKernelGGL(tile_count_kernel<false>, dim3(n_views), dim3(kTcThreads), 0, stream,
-                       slots, n_views, grid, totals, capacity, ranges, hist, seg);
+    hipLaunchKernelGGL((emit_block_kernel<T, false>), dim3(blocks), dim3(kThreads), 0, stream,
+                       order, offsets, rects, recs, slots, seg, first, n, n_pad, out_a, out_b);
+  return hipGetLastError();
+}
+
+template hipError_t emit_blocks<float>(const uint32_t*, const uint64_t*, const Rect16*,
+                                       const Rec<float>*, const ViewSlot*, const SegTable*,
+                                       uint32_t, uint32_t, int, uint64_t, bool, void*, uint32_t*,
+                                       void*, hipStream_t);
+template hipError_t emit_blocks<double>(const uint32_t*, const uint64_t*, const Rect16*,
+                                        const Rec<double>*, const ViewSlot*, const SegTable*,
+                                        uint32_t, uint32_t, int, uint64_t, bool, void*, uint32_t*,
+                                        void*, hipStream_t);
+
+hipError_t tile_ranges(const void* sorted_tiles, bool tiles16, const SegTable* seg,
+                       const ViewSlot* slots, uint32_t total_tiles, uint64_t capacity,
+                       uint2* ranges, hipStream_t stream) {
+  // (the ranges buffer is allocated in 256-byte units)
+  hipError_t e = fill_zero(ranges, (size_t(total_tiles) * sizeof(uint2) + 15) & ~size_t(15), stream);
+  if (e != hipSuccess) return e;
+  const uint32_t blocks = uint32_t((capacity + kChunk - 1) / kChunk);
+  if (blocks == 0) return hipSuccess;
+  if (tiles16)
+    hipLaunchKernelGGL(ranges_kernel<uint16_t>, dim3(blocks), dim3(kThreads), 0, stream,
+                       static_cast<const uint16_t*>(sorted_tiles), seg, slots, ranges);
+  else
+    hipLaunchKernelGGL(ranges_kernel<uint32_t>, dim3(blocks), dim3(kThreads), 0, stream,
+                       static_cast<const uint32_t*>(sorted_tiles), seg, slots, ranges);
+  return hipGetLastError();
+}
+
+hipError_t tile_key_histogram(const uint32_t* keys, const SegTable* seg, uint64_t capacity,
+                              int passes, uint32_t* hist, hipStream_t stream) {
+  hipError_t e = fill_zero(hist, size_t(passes) * kMaxViews * 256 * 4, stream);
+  if (e != hipSuccess) return e;
+  const uint32_t blocks = uint32_t((capacity + kChunk - 1) / kChunk);
+  if (blocks == 0) return hipSuccess;
+  switch (passes) {
+    case 1: hipLaunchKernelGGL(tile_hist_kernel<1>, dim3(blocks), dim3(kThreads), 0, stream, keys, seg, hist); break;
+    case 2: hipLaunchKernelGGL(tile_hist_kernel<2>, dim3(blocks), dim3(kThreads), 0, stream, keys, seg, hist); break;
+    case 3: hipLaunchKernelGGL(tile_hist_kernel<3>, dim3(blocks), dim3(kThreads), 0, stream, keys, seg, hist); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1207,37 +1073,15 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts, uint32_
       static_cast<uint64_t*>(temp), stream);
 }
 
-template <typename T>
-hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                              const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
-                              uint32_t n, uint32_t n_pad, int n_views, uint32_t* keys,
-                              uint32_t* vals, hipStream_t stream) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(emit_kernel<T>, dim3((n + 255) / 256, uint32_t(n_views)), dim3(256), 0,
-                     stream, order, offsets, rects, recs, slots, seg, n, n_pad, keys, vals);
-  return hipGetLastError();
-}
-
-template hipError_t emit_tile_keys_seg<float>(const uint32_t*, const uint64_t*, const Rect16*,
-                                              const Rec<float>*, const ViewSlot*, const SegTable*,
-                                              uint32_t, uint32_t, int, uint32_t*, uint32_t*,
-                                              hipStream_t);
-template hipError_t emit_tile_keys_seg<double>(const uint32_t*, const uint64_t*, const Rect16*,
-                                               const Rec<double>*, const ViewSlot*,
-                                               const SegTable*, uint32_t, uint32_t, int, uint32_t*,
-                                               uint32_t*, hipStream_t);
-
 bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view) {
   return n <= (1u << 24) && max_tiles_per_view <= 65536u;
 }
 
-size_t packed_sort_temp_bytes(uint32_t n_pad, int n_views, uint64_t capacity) {
-  (void)n_pad;
-  (void)n_views;
+size_t packed_sort_temp_bytes(uint64_t capacity) {
   const uint64_t rows = (capacity + kChunk - 1) / kChunk;
   const uint64_t stripes = (rows + kStripe - 1) / kStripe + 1;
-  // first[], and per pass: M, P, stripe totals
-  return size_t((rows + 64) * 4 + 2 * (rows * 256 + (rows + 1) * 256 + stripes * 256) * 4);
+  // per pass: block digit counts M, their column prefix P, stripe totals
+  return size_t(2 * (rows * 256 + (rows + 1) * 256 + stripes * 256) * 4);
 }
 
 namespace {
@@ -1254,47 +1098,32 @@ hipError_t col_scan(const uint32_t* M, uint32_t rows, uint32_t* P, uint32_t* T,
 }
 }  // namespace
 
-template <typename T>
-hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                            const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
-                            uint32_t n, uint32_t n_pad, int n_views, uint32_t max_tiles,
-                            uint64_t capacity, void* temp, uint32_t* lo_out, uint32_t* values,
+hipError_t packed_tile_sort(const uint32_t* packed, const uint8_t* digits, const SegTable* seg,
+                            uint32_t max_tiles, uint64_t capacity, void* temp, uint32_t* mid,
+                            uint8_t* mid_hi, uint32_t* values, uint16_t* tiles,
                             hipStream_t stream) {
   const uint32_t rows = uint32_t((capacity + kChunk - 1) / kChunk);
-  if (n == 0 || n_views <= 0 || rows == 0) return hipSuccess;
+  if (rows == 0) return hipSuccess;
   const uint32_t stripes = (rows + kStripe - 1) / kStripe + 1;
-  uint32_t* first = static_cast<uint32_t*>(temp);
-  uint32_t* M1 = first + rows + 64;
+  uint32_t* M1 = static_cast<uint32_t*>(temp);
   uint32_t* P1 = M1 + size_t(rows) * 256;
   uint32_t* T1 = P1 + size_t(rows + 1) * 256;
   uint32_t* M2 = T1 + size_t(stripes) * 256;
   uint32_t* P2 = M2 + size_t(rows) * 256;
   uint32_t* T2 = P2 + size_t(rows + 1) * 256;
-  hipLaunchKernelGGL(first_gaussian_kernel, dim3((n + kThreads - 1) / kThreads, uint32_t(n_views)),
-                     dim3(kThreads), 0, stream, offsets, seg, n, n_pad, first);
-  hipLaunchKernelGGL(lo_count_kernel<T>, dim3(rows), dim3(kThreads), 0, stream, order, offsets,
-                     rects, recs, slots, seg, first, n, n_pad, M1);
+  hipLaunchKernelGGL(lo_count_kernel, dim3(rows), dim3(kThreads), 0, stream, digits, seg, M1);
   hipError_t e = col_scan(M1, rows, P1, T1, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(lo_pass_kernel<T>, dim3(rows), dim3(kThreads), 0, stream, order, offsets,
-                     rects, recs, slots, seg, first, P1, n, n_pad, lo_out);
+  hipLaunchKernelGGL(lo_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, packed, digits, seg,
+                     P1, mid, mid_hi);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(hi_count_kernel, dim3(rows), dim3(kThreads), 0, stream, lo_out, seg, M2);
+  hipLaunchKernelGGL(lo_count_kernel, dim3(rows), dim3(kThreads), 0, stream, mid_hi, seg, M2);
   if ((e = col_scan(M2, rows, P2, T2, stream)) != hipSuccess) return e;
   int nbits = 1;
   while ((1u << nbits) < (max_tiles + 255u) / 256u) ++nbits;
-  hipLaunchKernelGGL(hi_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, lo_out, seg, P2,
-                     nbits, values);
+  hipLaunchKernelGGL(hi_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, mid, mid_hi, seg, P2,
+                     nbits, values, tiles);
   return hipGetLastError();
 }
-
-template hipError_t packed_tile_sort<float>(const uint32_t*, const uint64_t*, const Rect16*,
-                                            const Rec<float>*, const ViewSlot*, const SegTable*,
-                                            uint32_t, uint32_t, int, uint32_t, uint64_t, void*,
-                                            uint32_t*, uint32_t*, hipStream_t);
-template hipError_t packed_tile_sort<double>(const uint32_t*, const uint64_t*, const Rect16*,
-                                             const Rec<double>*, const ViewSlot*,
-                                             const SegTable*, uint32_t, uint32_t, int, uint32_t,
-                                             uint64_t, void*, uint32_t*, uint32_t*, hipStream_t);
 
 }  // namespace r4d

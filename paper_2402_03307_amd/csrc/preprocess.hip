@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "r4d_internal.hpp"
+#include "rowwalk.hpp"
 #include "tileset.hpp"
 
 namespace r4d {
@@ -39,37 +40,17 @@ __device__ __forceinline__ float record_qmax<float>(float o, const SettingsDev& 
   return f;
 }
 
-// Tile entries of a record: the sum of its row runs, and in `out` the
-// bounding box of the runs (rows with a run are consecutive, so every row of
-// the box holds one).
+// Tile box and run constants of a record; false when no pixel can receive it.
 template <typename T>
-__device__ __forceinline__ uint32_t record_tiles(const Rec<T>& rec, const ViewDev& v, Rect16& out) {
+__device__ __forceinline__ bool record_box(const Rec<T>& rec, const ViewDev& v, int sh,
+                                           TileBox& bx, SpanGeom& sg) {
   const double Q = double(rec.qmax);
-  if (!(Q >= 0.0)) return 0;
-  const int sh = __builtin_ctz(unsigned(v.tile_size));
+  if (!(Q >= 0.0)) return false;
   const double mx = double(rec.mx), my = double(rec.my);
   const double a = double(rec.ca), b = double(rec.cb), c = double(rec.cc);
-  TileBox bx;
-  if (!tile_box(mx, my, a, b, c, Q, v.W, v.H, sh, bx)) return 0;
-  const SpanGeom sg = span_geom(mx, my, a, b, c, Q, v.W, v.H, sh, bx.x0, bx.x1);
-  uint32_t cnt = 0;
-  int tx0 = bx.x1, tx1 = bx.x0, ty0 = bx.y1, ty1 = bx.y0;
-  for (int ty = bx.y0; ty < bx.y1; ++ty) {
-    int x0, x1;
-    row_span(sg, ty, x0, x1);
-    if (x0 < x1) {
-      cnt += uint32_t(x1 - x0);
-      tx0 = x0 < tx0 ? x0 : tx0;
-      tx1 = x1 > tx1 ? x1 : tx1;
-      ty0 = ty < ty0 ? ty : ty0;
-      ty1 = ty + 1;
-    }
-  }
-  out.x0 = uint16_t(tx0);
-  out.x1 = uint16_t(tx1);
-  out.y0 = uint16_t(ty0);
-  out.y1 = uint16_t(ty1);
-  return cnt;
+  if (!tile_box(mx, my, a, b, c, Q, v.W, v.H, sh, bx)) return false;
+  sg = span_geom(mx, my, a, b, c, Q, v.W, v.H, sh, bx.x0, bx.x1);
+  return true;
 }
 
 template <typename T, int DEG>
@@ -78,13 +59,21 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     Rec<T>* __restrict__ recs, Rect16* __restrict__ rects, uint32_t* __restrict__ tiles_touched,
     uint32_t* __restrict__ depth_keys, unsigned long long* __restrict__ totals) {
   __shared__ unsigned long long s_tot[2][kBlock / 64];
+  __shared__ uint32_t s_cnt[kBlock];
+  __shared__ int s_x0[kBlock], s_x1[kBlock], s_y0[kBlock], s_y1[kBlock];
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int vi = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const ViewDev v = slots[vi].v;
+  const int sh = __builtin_ctz(unsigned(v.tile_size));
   const size_t row = size_t(vi) * size_t(n);
-  bool vis = false;
-  uint32_t my_cnt = 0;
+  TileBox bx = {0, 0, 0, 0};
+  SpanGeom sg = {};
+  sg.W = v.W;
+  sg.H = v.H;
+  sg.sh = sh;
+  float depth = 0.0f;
   if (i < n) {
     T mu[4], ls[4], rot[8];
 #pragma unroll
@@ -97,9 +86,6 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     const T op = g.opacity[i];
     Fwd<T> f;
     gaussian_fwd<T>(mu, ls, rot, op, g.sh + i, (long)n, DEG, v, st, f);
-    Rect16 rc = {0, 0, 0, 0};
-    uint32_t cnt = 0;
-    uint32_t key = 0xffffffffu;
     if (f.valid) {
       Rec<T> rec;
       rec.mx = f.mean2[0];
@@ -114,26 +100,52 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
       rec.g = f.rgb[1];
       rec.b = f.rgb[2];
       rec.pad1 = T(0);
-      cnt = record_tiles(rec, v, rc);
-      if (cnt) {
-        key = __float_as_uint(float(f.p[2]));
+      if (record_box(rec, v, sh, bx, sg)) {
         recs[row + i] = rec;
-        vis = true;
+        depth = float(f.p[2]);
       } else {
-        rc = {0, 0, 0, 0};
+        bx = {0, 0, 0, 0};
       }
     }
+  }
+  // tile entries and the runs' bounding box: the rows of the wavefront's
+  // Gaussians walked together, aggregated per Gaussian in LDS
+  s_cnt[threadIdx.x] = 0u;
+  s_x0[threadIdx.x] = 0x7fffffff;
+  s_x1[threadIdx.x] = 0;
+  s_y0[threadIdx.x] = 0x7fffffff;
+  s_y1[threadIdx.x] = 0;
+  __syncthreads();
+  wave_rows(sg, bx.y0, bx.y1, lane, [&](bool ok, int o, int y, int x0, int x1) {
+    if (ok && x0 < x1) {
+      const int slot = wave * 64 + o;
+      atomicAdd(&s_cnt[slot], uint32_t(x1 - x0));
+      atomicMin(&s_x0[slot], x0);
+      atomicMax(&s_x1[slot], x1);
+      atomicMin(&s_y0[slot], y);
+      atomicMax(&s_y1[slot], y + 1);
+    }
+  });
+  __syncthreads();
+  const uint32_t my_cnt = s_cnt[threadIdx.x];
+  const bool vis = my_cnt > 0u;
+  if (i < n) {
+    Rect16 rc = {0, 0, 0, 0};
+    if (vis) {
+      rc.x0 = uint16_t(s_x0[threadIdx.x]);
+      rc.x1 = uint16_t(s_x1[threadIdx.x]);
+      rc.y0 = uint16_t(s_y0[threadIdx.x]);
+      rc.y1 = uint16_t(s_y1[threadIdx.x]);
+    }
     rects[row + i] = rc;
-    tiles_touched[row + i] = cnt;
-    depth_keys[size_t(vi) * n_pad + i] = key;
-    my_cnt = cnt;
+    tiles_touched[row + i] = my_cnt;
+    depth_keys[size_t(vi) * n_pad + i] = vis ? __float_as_uint(depth) : 0xffffffffu;
   }
   // block totals of visible Gaussians and tile entries, one atomic each per block
   unsigned long long c = my_cnt;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
   const unsigned long long m = __ballot(vis);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     s_tot[0][wave] = __popcll(m);
     s_tot[1][wave] = c;

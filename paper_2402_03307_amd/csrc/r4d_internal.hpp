@@ -43,7 +43,6 @@ constexpr uint32_t kSegAlign = 4096;  // segment starts of the segmented sorts
 struct ViewSlot {
   ViewDev v;
   uint32_t tile_base;   // index of the render's first tile among all tiles of the batch
-  uint32_t grid_base;   // offset of its (tiles_x + 1) x (tiles_y + 1) count grid
   uint64_t pix_base;    // index of its first pixel among all pixels of the batch
 };
 
@@ -99,26 +98,12 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
                          uint32_t* tickets, uint32_t* error, bool keys_needed, int* result_index,
                          hipStream_t stream);
 
-// Tile count grids of every render from the Gaussians' row spans (rects and
-// records [V][n]) into `grid` (zeroed; each render's (tiles_x + 1) x
-// (tiles_y + 1) grid at its grid_base; its last row stays zero): +1 at the
-// first column of each row span, -1 after its last.  max_cells: the largest
-// grid of the renders, total_cells: all of them.  When a grid fits in LDS the
-// work goes through tile_grid_partials(n) partial grids per render in
-// `partials` ([all cells] x partials); otherwise through atomics on `grid`.
-int tile_grid_partials(uint32_t n);
-template <typename T>
-hipError_t tile_grids(const Rect16* rects, const Rec<T>* recs, const ViewSlot* slots,
-                      int n_views, uint32_t n, uint64_t max_cells, uint64_t total_cells,
-                      int* partials, int* grid, hipStream_t stream);
-
-// Per render: tile entry counts from the grids, tile ranges
-// (ranges[tile_base + t] = [start, end) in the emitted list, [0, 0) for a tile
-// without entries), tile-sort digit histograms hist[3][kMaxViews][256] and the
-// segment table of the emitted list.
-hipError_t tile_counts(const ViewSlot* slots, int n_views, uint64_t max_cells, int* grid,
-                       const unsigned long long* totals, unsigned long long capacity,
-                       uint2* ranges, uint32_t* hist, SegTable* seg, hipStream_t stream);
+// Segment table of the emitted list from the per-render entry counts
+// (totals[2v + 1]): render v starts at the sum of the earlier renders' counts,
+// each rounded up to kSegAlign; all segments empty and `overflow` set when
+// they exceed `capacity`.
+hipError_t seg_table(const unsigned long long* totals, int n_views, unsigned long long capacity,
+                     SegTable* seg, hipStream_t stream);
 
 size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
 // offsets[v * n_pad + k] = sum over renders u < v of all their entries plus the
@@ -127,28 +112,42 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts, uint32_
                           uint32_t n_pad, int n_views, uint64_t* offsets, void* temp,
                           hipStream_t stream);
 
-// Writes every render's (tile id, Gaussian index) entries in depth order into
-// its segment of keys / vals.
+// Emission of every render's tile entries in depth order (each Gaussian's
+// tiles row by row, its row runs from tileset.hpp) into its segment, one
+// 4096-entry block per workgroup.  packed: out_a[e] = Gaussian index |
+// (tile >> 8) << 24 and out_b[e] = tile & 255 (bytes), the packed sort's
+// input; otherwise out_a[e] = tile id, out_b[e] = Gaussian index (words).
+// temp: emit_temp_bytes(capacity).
+size_t emit_temp_bytes(uint64_t capacity);
 template <typename T>
-hipError_t emit_tile_keys_seg(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                              const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
-                              uint32_t n, uint32_t n_pad, int n_views, uint32_t* keys,
-                              uint32_t* vals, hipStream_t stream);
+hipError_t emit_blocks(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
+                       const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg, uint32_t n,
+                       uint32_t n_pad, int n_views, uint64_t capacity, bool packed, void* temp,
+                       uint32_t* out_a, void* out_b, hipStream_t stream);
+
+// Tile ranges (ranges[tile_base + t] = [start, end) in the emitted list, [0, 0)
+// for a tile without entries) from every segment's sorted tile ids (16 or 32
+// bits).
+hipError_t tile_ranges(const void* sorted_tiles, bool tiles16, const SegTable* seg,
+                       const ViewSlot* slots, uint32_t total_tiles, uint64_t capacity,
+                       uint2* ranges, hipStream_t stream);
+
+// hist[p][s][256] = digit-p counts of the emitted tile ids of segment s
+// (zeroes hist first), for the onesweep tile sort.
+hipError_t tile_key_histogram(const uint32_t* keys, const SegTable* seg, uint64_t capacity,
+                              int passes, uint32_t* hist, hipStream_t stream);
 
 // Tile sort on packed 32-bit entries (see binning.hip), usable when
-// packed_tile_sort_ok: emission fused with the low-digit pass, then the
-// high-digit pass.  offsets: count_scan_seg's output; seg: the tile segment
-// table; max_tiles: the largest tile count of the renders; lo_out: capacity
-// words (the low-digit pass output); values: capacity
-// words, receives the sorted Gaussian indices; temp:
-// packed_sort_temp_bytes(n_pad, n_views, capacity) bytes.
+// packed_tile_sort_ok: a low-digit pass on (packed, digits) into (mid,
+// mid_hi), then a high-digit pass into values (the sorted Gaussian indices)
+// and tiles (their 16-bit tile ids).  seg: the tile segment table; max_tiles:
+// the largest tile count of the renders; temp: packed_sort_temp_bytes(capacity)
+// bytes; every other array holds capacity elements.
 bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view);
-size_t packed_sort_temp_bytes(uint32_t n_pad, int n_views, uint64_t capacity);
-template <typename T>
-hipError_t packed_tile_sort(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                            const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
-                            uint32_t n, uint32_t n_pad, int n_views, uint32_t max_tiles,
-                            uint64_t capacity, void* temp, uint32_t* lo_out, uint32_t* values,
+size_t packed_sort_temp_bytes(uint64_t capacity);
+hipError_t packed_tile_sort(const uint32_t* packed, const uint8_t* digits, const SegTable* seg,
+                            uint32_t max_tiles, uint64_t capacity, void* temp, uint32_t* mid,
+                            uint8_t* mid_hi, uint32_t* values, uint16_t* tiles,
                             hipStream_t stream);
 
 // Exclusive scan of a[0..n) into out[0..n] (out[n] = total); temp holds
