@@ -42,8 +42,8 @@ struct GraphEntry;
 struct RunLayout {
   // fixed block
   size_t meta, recs, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp, ranges,
-      T_final, n_contrib, n_eval, img_copy, walk, zero_begin, totals, dhist, tickets, dstatus,
-      zero_end, fixed_bytes;
+      T_final, n_contrib, n_eval, img_copy, walk, ptemp_fwd, zero_begin, totals, dhist, tickets,
+      dstatus, zero_end, fixed_bytes;
   // entries block
   size_t tkA, tkB, tvA, tvB, tdig, thi, t16, etemp, ptemp, ck, tstatus, entries_bytes;
 };
@@ -93,6 +93,7 @@ struct r4d_ctx {
   std::vector<Stage> ring;
   size_t ring_next = 0;
   unsigned long long* readback = nullptr;    // pinned, 2 * kMaxViews words
+  float* l1_partials = nullptr;              // device, l1_partials_floats() words
   hipStream_t capture_stream = nullptr;
   std::set<r4d_saved*> live_saved;
   std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
@@ -430,6 +431,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 4) : 0;
   L.img_copy = take(3 * size_t(p.total_pix) * p.scal);
   L.walk = take(size_t(p.total_tiles) * 4);
+  L.ptemp_fwd = take(preprocess_temp_bytes(p.n, p.V));
   L.zero_begin = off;
   L.totals = take(2 * size_t(kMaxViews) * 8);
   L.dhist = take(4 * size_t(kMaxViews) * 256 * 4);
@@ -514,7 +516,8 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     R4D_TIMED(kPreprocessFwd,
               launch_preprocess_fwd<T>(g, slots, p.V, st, p.n_pad, at<Rec<T>>(F, L.recs),
                                        at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
-                                       at<uint32_t>(F, L.dkeys), totals, stream));
+                                       at<uint32_t>(F, L.dkeys), totals, F + L.ptemp_fwd,
+                                       stream));
   }
   hipEvent_t totals_ready = nullptr;
   if (sized) {
@@ -1152,6 +1155,11 @@ r4d_status r4d_create(r4d_ctx** out, int device) {
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->readback), 2 * kMaxViews * 8,
                     hipHostMallocDefault) != hipSuccess)
     return R4D_ERR_OOM;
+  if (hipMalloc(reinterpret_cast<void**>(&ctx->l1_partials),
+                l1_partials_floats() * sizeof(float)) != hipSuccess) {
+    (void)hipHostFree(ctx->readback);
+    return R4D_ERR_OOM;
+  }
   ctx->ring.resize(8);
   const size_t stage_bytes = sizeof(ViewSlot) * kMaxViews + sizeof(SegTable);
   for (auto& s : ctx->ring) {
@@ -1210,6 +1218,7 @@ void r4d_destroy(r4d_ctx* ctx) {
   ctx->pinned_pool.clear();
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->readback) (void)hipHostFree(ctx->readback);
+  if (ctx->l1_partials) (void)hipFree(ctx->l1_partials);
   delete ctx;
 }
 
@@ -1267,7 +1276,8 @@ r4d_status r4d_l1_loss_grad(r4d_ctx* ctx, const float* image, const float* targe
   if (count < 0 || (count > 0 && (!image || !target || !dL_dimage)))
     return fail(ctx, R4D_ERR_INVALID_ARG, "invalid L1 arguments");
   R4D_HIP(hipSetDevice(ctx->device));
-  R4D_HIP(launch_l1_grad(image, target, count, dL_dimage, loss, static_cast<hipStream_t>(stream)));
+  R4D_HIP(launch_l1_grad(image, target, count, dL_dimage, loss, ctx->l1_partials,
+                         static_cast<hipStream_t>(stream)));
   return R4D_OK;
 }
 
@@ -1288,7 +1298,7 @@ r4d_status r4d_l1_loss_grad_views(r4d_ctx* ctx, const float* images, const float
   }
   lv.base[n_views] = off;
   R4D_HIP(hipSetDevice(ctx->device));
-  R4D_HIP(launch_l1_grad_views(images, targets, lv, dL_dimages, loss,
+  R4D_HIP(launch_l1_grad_views(images, targets, lv, dL_dimages, loss, ctx->l1_partials,
                                static_cast<hipStream_t>(stream)));
   return R4D_OK;
 }

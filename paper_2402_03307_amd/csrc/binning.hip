@@ -583,12 +583,13 @@ __global__ __launch_bounds__(kThreads) void emit_block_kernel(
 // Tile ranges from the sorted tile ids of every segment: position p starts the
 // range of its tile when p is the segment's first position or the previous
 // tile differs, and ends it likewise (ranges zeroed beforehand, so tiles
-// without entries keep [0, 0)).
+// without entries keep [0, 0)).  Each thread reads 16 bytes of consecutive ids.
 template <typename K>
 __global__ __launch_bounds__(kThreads) void ranges_kernel(const K* __restrict__ tiles,
                                                           const SegTable* __restrict__ seg,
                                                           const ViewSlot* __restrict__ slots,
                                                           uint2* __restrict__ ranges) {
+  constexpr int E = 16 / sizeof(K);
   const uint32_t b = blockIdx.x;
   uint32_t s, sstart, nvalid;
   if (seg->overflow || !block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid)
@@ -596,11 +597,28 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const K* __restrict__ 
   const uint32_t send = sstart + seg->len[s];
   const uint32_t tb = slots[s].tile_base;
   const uint32_t e0 = b * uint32_t(kChunk);
-  for (uint32_t q = threadIdx.x; q < nvalid; q += kThreads) {
-    const uint32_t p = e0 + q;
-    const uint32_t t = uint32_t(tiles[p]);
-    if (p == sstart || uint32_t(tiles[p - 1]) != t) ranges[tb + t].x = p;
-    if (p + 1 == send || uint32_t(tiles[p + 1]) != t) ranges[tb + t].y = p + 1;
+  for (uint32_t q0 = threadIdx.x * E; q0 < nvalid; q0 += kThreads * E) {
+    const uint32_t p0 = e0 + q0;  // a multiple of E: one aligned 16-byte load
+    K t[E];
+    *reinterpret_cast<uint4*>(t) = *reinterpret_cast<const uint4*>(tiles + p0);
+    uint32_t prev = p0 > sstart ? uint32_t(tiles[p0 - 1]) : 0xffffffffu;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t p = p0 + uint32_t(i);
+      if (p >= send) break;
+      const uint32_t ti = uint32_t(t[i]);
+      if (ti != prev) {
+        ranges[tb + ti].x = p;
+        if (p > sstart) ranges[tb + prev].y = p;
+      }
+      prev = ti;
+    }
+    const uint32_t pe = p0 + uint32_t(E) - 1u;  // the last position read
+    if (pe + 1u >= send) {
+      if (p0 < send) ranges[tb + prev].y = send;  // the segment's last tile
+    } else if (uint32_t(tiles[pe + 1u]) != prev) {
+      ranges[tb + prev].y = pe + 1u;
+    }
   }
 }
 

@@ -57,7 +57,7 @@ template <typename T, int DEG>
 __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     GaussPtrs<T> g, const ViewSlot* __restrict__ slots, SettingsDev st, uint32_t n_pad,
     Rec<T>* __restrict__ recs, Rect16* __restrict__ rects, uint32_t* __restrict__ tiles_touched,
-    uint32_t* __restrict__ depth_keys, unsigned long long* __restrict__ totals) {
+    uint32_t* __restrict__ depth_keys, ulonglong2* __restrict__ block_totals) {
   __shared__ unsigned long long s_tot[2][kBlock / 64];
   __shared__ uint32_t s_cnt[kBlock];
   __shared__ int s_x0[kBlock], s_x1[kBlock], s_y0[kBlock], s_y1[kBlock];
@@ -141,7 +141,9 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     tiles_touched[row + i] = my_cnt;
     depth_keys[size_t(vi) * n_pad + i] = vis ? __float_as_uint(depth) : 0xffffffffu;
   }
-  // block totals of visible Gaussians and tile entries, one atomic each per block
+  // block totals of visible Gaussians and tile entries, written per block and
+  // summed by totals_kernel (atomics on two addresses from every block would
+  // serialise)
   unsigned long long c = my_cnt;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
@@ -158,8 +160,42 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
       a += s_tot[0][w];
       b += s_tot[1][w];
     }
-    if (a) atomicAdd(&totals[2 * vi], a);
-    if (b) atomicAdd(&totals[2 * vi + 1], b);
+    block_totals[size_t(vi) * gridDim.x + blockIdx.x] = make_ulonglong2(a, b);
+  }
+}
+
+// totals[2v] = visible Gaussians of render v, totals[2v + 1] = its tile
+// entries: the sum of the render's block totals (one workgroup per render).
+__global__ __launch_bounds__(kBlock) void totals_kernel(const ulonglong2* __restrict__ block_totals,
+                                                         uint32_t blocks,
+                                                         unsigned long long* __restrict__ totals) {
+  __shared__ unsigned long long s_a[kBlock / 64], s_b[kBlock / 64];
+  const uint32_t v = blockIdx.x;
+  unsigned long long a = 0, b = 0;
+  for (uint32_t i = threadIdx.x; i < blocks; i += kBlock) {
+    const ulonglong2 t = block_totals[size_t(v) * blocks + i];
+    a += t.x;
+    b += t.y;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_a[threadIdx.x >> 6] = a;
+    s_b[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long ta = 0, tb = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      ta += s_a[w];
+      tb += s_b[w];
+    }
+    totals[2 * v] = ta;
+    totals[2 * v + 1] = tb;
   }
 }
 
@@ -242,12 +278,20 @@ template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
                                  Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
-                                 unsigned long long* totals, hipStream_t stream) {
+                                 unsigned long long* totals, void* temp, hipStream_t stream) {
   if (g.n <= 0 || n_views <= 0) return hipSuccess;
-  const dim3 grid((g.n + kBlock - 1) / kBlock, uint32_t(n_views));
+  const uint32_t blocks = uint32_t((g.n + kBlock - 1) / kBlock);
+  const dim3 grid(blocks, uint32_t(n_views));
+  ulonglong2* block_totals = static_cast<ulonglong2*>(temp);
   R4D_DEG_DISPATCH(preprocess_fwd_kernel, grid, g, slots, st, n_pad, recs, rects, tiles_touched,
-                   depth_keys, totals)
+                   depth_keys, block_totals)
+  hipLaunchKernelGGL(totals_kernel, dim3(uint32_t(n_views)), dim3(kBlock), 0, stream, block_totals,
+                     blocks, totals);
   return hipGetLastError();
+}
+
+size_t preprocess_temp_bytes(uint32_t n, int n_views) {
+  return size_t((n + kBlock - 1) / kBlock) * size_t(n_views) * sizeof(ulonglong2);
 }
 
 template <typename T>
@@ -279,7 +323,7 @@ hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
   template hipError_t launch_preprocess_fwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
                                                const SettingsDev&, uint32_t, Rec<T>*, Rect16*, \
                                                uint32_t*, uint32_t*, unsigned long long*,      \
-                                               hipStream_t);                                   \
+                                               void*, hipStream_t);                            \
   template hipError_t launch_preprocess_bwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
                                                const SettingsDev&, const double*,              \
                                                const GradPtrs<T>&, hipStream_t);

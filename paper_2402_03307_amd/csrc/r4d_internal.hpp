@@ -57,13 +57,14 @@ struct SegTable {
 
 // ---- preprocess (per Gaussian and render)
 // Render v = blockIdx.y.  Per render: recs/rects/tiles_touched at [v][n],
-// depth_keys at [v * n_pad + i]; totals[2v] += visible Gaussians, totals[2v+1]
-// += tile entries (the caller zeroes totals).
+// depth_keys at [v * n_pad + i]; totals[2v] = visible Gaussians, totals[2v+1]
+// = tile entries.  temp: preprocess_temp_bytes(n, n_views).
+size_t preprocess_temp_bytes(uint32_t n, int n_views);
 template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
                                  Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
-                                 unsigned long long* totals, hipStream_t stream);
+                                 unsigned long long* totals, void* temp, hipStream_t stream);
 
 // grad2d: [V][9][n] double (mean2 x, y, Sigma_2D (0,0), (0,1), (1,1), opacity_t,
 // r, g, b).  Writes the parameter gradients summed over the renders.
@@ -210,18 +211,23 @@ hipError_t launch_raster_bwd(const Rec<T>* recs, uint32_t n, const uint32_t* val
                              const T* dL_dimage, double* grad2d, uint32_t* work,
                              hipStream_t stream);
 
+// L1 loss (mean absolute difference) and its gradient.  The loss (when `loss`
+// is not null) is summed through per-workgroup partial sums in `partials`
+// (device memory of l1_partials_floats() floats), not through atomics on one
+// address.
+size_t l1_partials_floats();
 hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, float* grad,
-                          float* loss, hipStream_t stream);
+                          float* loss, float* partials, hipStream_t stream);
 
 // Per-view L1: view v covers elements [base[v], base[v + 1]) and is normalised
-// by its own count.
+// by its own count; the loss sums the views' means.
 struct L1Views {
   int n_views;
   int64_t base[kMaxViews + 1];
   int64_t count[kMaxViews];
 };
 hipError_t launch_l1_grad_views(const float* images, const float* targets, const L1Views& lv,
-                                float* grad, float* loss, hipStream_t stream);
+                                float* grad, float* loss, float* partials, hipStream_t stream);
 
 // ---- small helpers
 // p[0..count) = value (float or double elements).

@@ -88,19 +88,18 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
-// Sum over the 64 lanes of a wavefront with DPP lane moves (no LDS traffic);
-// the total is valid in lane 63.  Steps: pairs (quad_perm 1,0,3,2), quads
-// (quad_perm 2,3,0,1), half rows (row_half_mirror), rows of 16 (row_mirror),
-// then row 15 -> rows 1, 3 (row_bcast:15) and row 31 -> rows 2, 3 (row_bcast:31).
+// Sums over each row of 16 lanes with DPP lane moves (no LDS traffic): pairs
+// (quad_perm 1,0,3,2), quads (quad_perm 2,3,0,1), half rows (row_half_mirror),
+// rows (row_mirror); afterwards every lane of a row holds its row's sums.  The
+// nine reductions advance step by step, so that the DPP moves of one value
+// fill the hazard slots of the others.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float x) {
   const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false);
   return x + __int_as_float(moved);
 }
 
-// Nine independent reductions advanced step by step, so that the DPP moves of
-// one value fill the hazard slots of the others.
-__device__ __forceinline__ void wave_sum9_to_lane63(float (&v)[9]) {
+__device__ __forceinline__ void row_sum9(float (&v)[9]) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) v[i] = dpp_add<0xb1, 0xf>(v[i]);
 #pragma unroll
@@ -109,20 +108,23 @@ __device__ __forceinline__ void wave_sum9_to_lane63(float (&v)[9]) {
   for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x141, 0xf>(v[i]);
 #pragma unroll
   for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x140, 0xf>(v[i]);
+}
+
+// Sums over each half wavefront, valid in rows 1 and 3 (lanes 16..31 and
+// 48..63): the row sums, then row 15 -> rows 1, 3 (row_bcast:15).
+__device__ __forceinline__ void half_sum9(float (&v)[9]) {
+  row_sum9(v);
 #pragma unroll
   for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x142, 0xa>(v[i]);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x143, 0xc>(v[i]);
 }
-__device__ __forceinline__ void wave_sum9_to_lane63(double (&v)[9]) {
+__device__ __forceinline__ void half_sum9(double (&v)[9]) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = wave_sum(v[i]);
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
 }
 
 template <typename T> __device__ __forceinline__ void atomic_add_nr(T* p, T v);
-template <> __device__ __forceinline__ void atomic_add_nr<float>(float* p, float v) {
-  __builtin_amdgcn_global_atomic_fadd_f32(p, v);
-}
 template <> __device__ __forceinline__ void atomic_add_nr<double>(double* p, double v) {
   atomicAdd(p, v);
 }
@@ -135,7 +137,7 @@ struct TileCfg {
   static constexpr int kThreads = TS * TS / PPT;
   static constexpr int kRowStep = TS / PPT;
   static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
-  // whole wavefronts only: the backward's DPP reductions end in lane 63
+  // whole wavefronts only: the backward's DPP reductions work on half wavefronts
   static_assert(kThreads % 64 == 0, "a tile must map onto whole wavefronts");
 };
 
@@ -251,7 +253,9 @@ template <typename T, int TS, int PPT>
 struct BwdShared {
   Staged<T> rec[TileCfg<TS, PPT>::kBatch];
   uint32_t idx[TileCfg<TS, PPT>::kBatch];
-  T grad[9][TileCfg<TS, PPT>::kBatch];
+  // per component, half wavefront and batch slot (one padding slot, so that the
+  // two halves' writes fall in different banks)
+  T grad[9][2][TileCfg<TS, PPT>::kBatch + 1];
   uint32_t max;
 };
 
@@ -268,7 +272,7 @@ __device__ __forceinline__ void raster_bwd_tile(
   constexpr int NB = Cfg::kBatch;
   Staged<T>* s_rec = sh.rec;
   uint32_t* s_idx = sh.idx;
-  T(*s_grad)[NB] = sh.grad;
+  T(*s_grad)[2][NB + 1] = sh.grad;
   uint32_t& s_max = sh.max;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int x = tx * TS + int(threadIdx.x % TS);
@@ -328,23 +332,27 @@ __device__ __forceinline__ void raster_bwd_tile(
         s_rec[threadIdx.x] = stage(recs[idx]);
       }
 #pragma unroll
-      for (int c = 0; c < 9; ++c) s_grad[c][threadIdx.x] = T(0);
+      for (int c = 0; c < 9; ++c) {
+        s_grad[c][0][threadIdx.x] = T(0);
+        s_grad[c][1][threadIdx.x] = T(0);
+      }
     }
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
       const Staged<T> r = s_rec[j];
       // pass 1: which of this lane's pixels blended the Gaussian
       T ux[PPT], uy[PPT], G[PPT], a_raw[PPT], alpha[PPT];
-      bool use[PPT];
+      bool use[PPT], band[PPT];
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const bool pass =
             eval_pair(r, px, py[k], e_min, amin, amax, ux[k], uy[k], G[k], a_raw[k], alpha[k]);
         use[k] = pass & (bstart + uint32_t(j) < ncon[k]);
-        any |= use[k];
+        band[k] = __ballot(use[k]) != 0ull;  // some pixel of the wavefront's band k blended it
+        any |= band[k];
       }
-      if (!__ballot(any)) continue;  // no pixel of the tile blended it
+      if (!any) continue;  // no pixel of the wavefront blended it
       // pass 2: per-pixel derivatives, summed over the lane's pixels as
       // s0..s4 = sum g (ux, uy, ux^2, ux uy, uy^2) with g = a dL/da (the
       // screen-space mean and Sigma_2D gradients are linear in these), s5 = sum
@@ -352,6 +360,8 @@ __device__ __forceinline__ void raster_bwd_tile(
       T sv[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
+        // (a band where no pixel blended it leaves every sum and state unchanged)
+        if (!band[k]) continue;
         const T inv_om = fast_rcp(T(1) - alpha[k]);
         const T Ti = Tcur[k] * inv_om;  // transmittance in front of this Gaussian
         const T w = use[k] ? alpha[k] * Ti : T(0);
@@ -377,68 +387,38 @@ __device__ __forceinline__ void raster_bwd_tile(
         sv[7] = tfma(w, g1[k], sv[7]);
         sv[8] = tfma(w, g2[k], sv[8]);
       }
-      wave_sum9_to_lane63(sv);
-      if (lane == 63) {
-        // With u = Q d (the staged value is k u): a = o exp(-q/2) gives
-        // dL/dq = -g / 2 per pixel, dq/dmean2d = 2 u, and, since
-        // dq = -u^T dSigma_2D u for Sigma_2D = Q^-1, dL/dSigma_2D = sum g u u^T / 2.
-        const T ik = T(1.0 / kHalfLog2e);
-        const T h = T(0.5 / (kHalfLog2e * kHalfLog2e));
-        T v9[9];
-        v9[0] = -ik * sv[0];  // d/d mean2d.x
-        v9[1] = -ik * sv[1];  // d/d mean2d.y
-        v9[2] = h * sv[2];    // d/d Sigma_2D (0,0)
-        v9[3] = h * sv[3];    // d/d Sigma_2D (0,1), the same for (1,0)
-        v9[4] = h * sv[4];    // d/d Sigma_2D (1,1)
-        v9[5] = sv[5];        // d/d opacity_t
-        v9[6] = sv[6];        // d/d rgb
-        v9[7] = sv[7];
-        v9[8] = sv[8];
+      // sums over each half wavefront, kept in LDS by lanes 16 and 48 (the
+      // components' scale factors are applied when the batch is flushed);
+      // with several wavefronts per tile the halves of all of them add up
+      half_sum9(sv);
+      if ((lane & 31) == 16) {
+        const int hf = lane >> 5;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
           if (NT == 64)
-            s_grad[c][j] += v9[c];
+            s_grad[c][hf][j] = sv[c];
           else
-            atomicAdd(&s_grad[c][j], v9[c]);
+            atomicAdd(&s_grad[c][hf][j], sv[c]);
         }
       }
     }
     __syncthreads();
-    // one global atomic per (tile, Gaussian, component); the sum over tiles is
-    // kept in double because its terms have mixed signs and can cancel
+    // One global atomic per (tile, Gaussian, component); the sum over tiles is
+    // kept in double because its terms have mixed signs and can cancel.
+    // With u = Q d (the staged value is k u): a = o exp(-q/2) gives dL/dq =
+    // -g / 2 per pixel, dq/dmean2d = 2 u, and, since dq = -u^T dSigma_2D u for
+    // Sigma_2D = Q^-1, dL/dSigma_2D = sum g u u^T / 2; so the components are
+    // d/d mean2d = -s0,1 / k, d/d Sigma_2D (0,0), (0,1) = (1,0), (1,1) =
+    // s2,3,4 / (2 k^2), d/d opacity_t = s5, d/d rgb = s6,7,8.
     for (int e = threadIdx.x; e < 9 * nb; e += NT) {
       const int c = e / nb, j = e % nb;
-      const T val = s_grad[c][j];
+      const T scale = c < 2 ? T(-1.0 / kHalfLog2e)
+                            : (c < 5 ? T(0.5 / (kHalfLog2e * kHalfLog2e)) : T(1));
+      const T val = (s_grad[c][0][j] + s_grad[c][1][j]) * scale;
       if (val != T(0)) atomic_add_nr(&grad2d[long(c) * n_gauss + s_idx[j]], double(val));
     }
     __syncthreads();
     bend = bstart;
-  }
-}
-
-__global__ void zero_one_kernel(float* p) {
-  if (threadIdx.x == 0) *p = 0.f;
-}
-
-__global__ __launch_bounds__(256) void l1_grad_kernel(const float* __restrict__ image,
-                                                      const float* __restrict__ target,
-                                                      int64_t count, float inv_count,
-                                                      float* __restrict__ grad,
-                                                      float* __restrict__ loss) {
-  __shared__ float s_part[4];
-  const int64_t stride = int64_t(gridDim.x) * 256;
-  float part = 0.f;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += stride) {
-    const float d = image[i] - target[i];
-    grad[i] = d > 0.f ? inv_count : (d < 0.f ? -inv_count : 0.f);
-    part += fabsf(d);
-  }
-  if (loss) {
-    part = wave_sum(part);
-    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
-    __syncthreads();
-    if (threadIdx.x == 0)
-      atomic_add_nr(loss, (s_part[0] + s_part[1] + s_part[2] + s_part[3]) * inv_count);
   }
 }
 
@@ -554,11 +534,12 @@ uint32_t resident_groups(K kernel, int threads) {
   return uint32_t(per_cu) * uint32_t(cus);
 }
 
-// Per-view L1 gradient: blockIdx.y = view; the loss sums every view's mean.
+// Per-view L1 gradient: blockIdx.y = view.  Each workgroup writes its share
+// of the view's mean absolute difference to partials[v * gridDim.x + b].
 __global__ __launch_bounds__(256) void l1_grad_views_kernel(const float* __restrict__ image,
                                                             const float* __restrict__ target,
                                                             L1Views lv, float* __restrict__ grad,
-                                                            float* __restrict__ loss) {
+                                                            float* __restrict__ partials) {
   __shared__ float s_part[4];
   const int v = blockIdx.y;
   const int64_t b0 = lv.base[v], cnt = lv.count[v];
@@ -570,13 +551,26 @@ __global__ __launch_bounds__(256) void l1_grad_views_kernel(const float* __restr
     grad[b0 + i] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
     part += fabsf(d);
   }
-  if (loss) {
+  if (partials) {
     part = wave_sum(part);
     if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
     __syncthreads();
     if (threadIdx.x == 0)
-      atomic_add_nr(loss, (s_part[0] + s_part[1] + s_part[2] + s_part[3]) * inv);
+      partials[size_t(v) * gridDim.x + blockIdx.x] =
+          (s_part[0] + s_part[1] + s_part[2] + s_part[3]) * inv;
   }
+}
+
+// *loss = sum of partials[0..count) (one workgroup).
+__global__ __launch_bounds__(256) void sum_partials_kernel(const float* __restrict__ partials,
+                                                           uint32_t count, float* __restrict__ loss) {
+  __shared__ float s_part[4];
+  float part = 0.f;
+  for (uint32_t i = threadIdx.x; i < count; i += 256) part += partials[i];
+  part = wave_sum(part);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) *loss = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
 }
 
 template <typename T, int TS, int PPT>
@@ -691,38 +685,37 @@ hipError_t launch_raster_bwd(const Rec<T>* recs, uint32_t n, const uint32_t* val
 
 #undef R4D_RASTER_DISPATCH
 
-hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, float* grad,
-                          float* loss, hipStream_t stream) {
-  if (count <= 0) return hipSuccess;
-  if (loss) {
-    // a kernel rather than a memset, so that the call may be captured in a graph
-    hipLaunchKernelGGL(zero_one_kernel, dim3(1), dim3(64), 0, stream, loss);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  // few fat blocks: the loss is summed with one atomic per block
-  int64_t blocks = (count + 255) / 256;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(l1_grad_kernel, dim3(blocks), dim3(256), 0, stream, image, target, count,
-                     1.0f / float(count), grad, loss);
+namespace {
+constexpr int64_t kL1MaxBlocks = 1024;  // workgroups per view
+}  // namespace
+
+size_t l1_partials_floats() { return size_t(kMaxViews) * kL1MaxBlocks; }
+
+hipError_t launch_l1_grad_views(const float* images, const float* targets, const L1Views& lv,
+                                float* grad, float* loss, float* partials, hipStream_t stream) {
+  int64_t most = 0;
+  for (int v = 0; v < lv.n_views; ++v) most = lv.count[v] > most ? lv.count[v] : most;
+  if (most == 0 || lv.n_views <= 0 || lv.n_views > kMaxViews) return hipSuccess;
+  // about 8 elements per thread, at most kL1MaxBlocks workgroups per view
+  int64_t blocks = (most + 2047) / 2048;
+  if (blocks > kL1MaxBlocks) blocks = kL1MaxBlocks;
+  hipLaunchKernelGGL(l1_grad_views_kernel, dim3(uint32_t(blocks), uint32_t(lv.n_views)), dim3(256),
+                     0, stream, images, targets, lv, grad, loss ? partials : nullptr);
+  if (loss)
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, stream, partials,
+                       uint32_t(blocks * lv.n_views), loss);
   return hipGetLastError();
 }
 
-hipError_t launch_l1_grad_views(const float* images, const float* targets, const L1Views& lv,
-                                float* grad, float* loss, hipStream_t stream) {
-  int64_t most = 0;
-  for (int v = 0; v < lv.n_views; ++v) most = lv.count[v] > most ? lv.count[v] : most;
-  if (most == 0) return hipSuccess;
-  if (loss) {
-    hipLaunchKernelGGL(zero_one_kernel, dim3(1), dim3(64), 0, stream, loss);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  int64_t blocks = (most + 255) / 256;
-  if (blocks > 256) blocks = 256;
-  hipLaunchKernelGGL(l1_grad_views_kernel, dim3(uint32_t(blocks), uint32_t(lv.n_views)), dim3(256),
-                     0, stream, images, targets, lv, grad, loss);
-  return hipGetLastError();
+hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, float* grad,
+                          float* loss, float* partials, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  L1Views lv;
+  lv.n_views = 1;
+  lv.base[0] = 0;
+  lv.base[1] = count;
+  lv.count[0] = count;
+  return launch_l1_grad_views(image, target, lv, grad, loss, partials, stream);
 }
 
 #define R4D_INST(T)                                                                          \
