@@ -43,14 +43,22 @@ template <typename T>
 struct Staged {
   T mx, my, A, B;
   T C, o, r, g;
-  T b, pad0, pad1, pad2;
+  T b, e_thr, pad1, pad2;
 };
 
+template <typename T> __device__ __forceinline__ T tlog2(T x);
+template <> __device__ __forceinline__ float tlog2<float>(float x) { return __log2f(x); }
+template <> __device__ __forceinline__ double tlog2<double>(double x) { return log2(x); }
+
+// e_thr: the smallest e (= k q, see eval_pair) at which the pair passes both
+// the extent test (q <= extent^2, e >= k extent^2) and the alpha test
+// (o exp2(e) >= alpha_min, e >= log2(alpha_min / o)).
 template <typename T>
-__device__ __forceinline__ Staged<T> stage(const Rec<T>& r) {
+__device__ __forceinline__ Staged<T> stage(const Rec<T>& r, T e_min, T amin) {
   const T k = T(kHalfLog2e);
+  const T e_alpha = tlog2(amin / r.o);
   return Staged<T>{r.mx, r.my, k * r.ca, k * r.cb, k * r.cc, r.o, r.r, r.g, r.b,
-                   T(0), T(0), T(0)};
+                   e_alpha > e_min ? e_alpha : e_min, T(0), T(0)};
 }
 
 // The one place where a (pixel, Gaussian) pair is evaluated; forward and backward
@@ -58,11 +66,11 @@ __device__ __forceinline__ Staged<T> stage(const Rec<T>& r) {
 // With d = mean2d - pixel centre: u = k Q d (the offset whitened by the conic Q),
 // e = d . u = k q, G = exp2(e) = exp(-q/2), a_raw = o G, alpha = min(alpha_max,
 // a_raw).  Evaluated without branches: the result says whether the pair passes
-// the extent test (q <= extent^2, i.e. e >= e_min) and the alpha test.  The
-// backward builds its screen-space gradients from u.
+// the extent and alpha tests (e >= e_thr).  The backward builds its
+// screen-space gradients from u.
 template <typename T>
-__device__ __forceinline__ bool eval_pair(const Staged<T>& r, T px, T py, T e_min, T amin, T amax,
-                                          T& ux, T& uy, T& G, T& a_raw, T& alpha) {
+__device__ __forceinline__ bool eval_pair(const Staged<T>& r, T px, T py, T amax, T& ux, T& uy,
+                                          T& G, T& a_raw, T& alpha) {
   const T dx = r.mx - px;
   const T dy = r.my - py;
   ux = tfma(r.B, dy, r.A * dx);
@@ -70,8 +78,8 @@ __device__ __forceinline__ bool eval_pair(const Staged<T>& r, T px, T py, T e_mi
   const T e = tfma(dx, ux, dy * uy);
   G = texp2(e);
   a_raw = r.o * G;
-  alpha = a_raw < amax ? a_raw : amax;
-  return (e >= e_min) & (alpha >= amin);
+  alpha = fmin(a_raw, amax);
+  return e >= r.e_thr;
 }
 
 // 1/x: the hardware reciprocal in float (about 1 ulp), exact division in double.
@@ -162,7 +170,7 @@ __device__ __forceinline__ void raster_fwd_tile(
   const T px = T(x) + T(0.5);
   const T e_min = T(kHalfLog2e) * T(st.ext2);
   const T amin = T(st.alpha_min), amax = T(st.alpha_max), tmin = T(st.T_min);
-  T py[PPT], Tr[PPT], Tf[PPT], c0[PPT], c1[PPT], c2[PPT];
+  T py[PPT], Tr[PPT], c0[PPT], c1[PPT], c2[PPT];
   uint32_t last[PPT], evals[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -170,7 +178,6 @@ __device__ __forceinline__ void raster_fwd_tile(
     py[k] = T(y) + T(0.5);
     // pixels outside the image start finished
     Tr[k] = (x < v.W && y < v.H) ? T(1) : T(0);
-    Tf[k] = T(1);
     c0[k] = c1[k] = c2[k] = T(0);
     last[k] = evals[k] = 0u;
   }
@@ -178,10 +185,10 @@ __device__ __forceinline__ void raster_fwd_tile(
   for (uint32_t base = rg.x; base < rg.y; base += NB) {
     bool lane_done = true;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) lane_done &= Tr[k] == T(0);
+    for (int k = 0; k < PPT; ++k) lane_done &= !(Tr[k] > T(0));
     if (__syncthreads_count(lane_done) == NT) break;
     const uint32_t i = base + threadIdx.x;
-    if (threadIdx.x < NB && i < rg.y) s_rec[threadIdx.x] = stage(recs[values[i]]);
+    if (threadIdx.x < NB && i < rg.y) s_rec[threadIdx.x] = stage(recs[values[i]], e_min, amin);
     __syncthreads();
     const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
     const uint32_t jbase = base - rg.x;
@@ -192,18 +199,19 @@ __device__ __forceinline__ void raster_fwd_tile(
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           T ux, uy, G, a_raw, alpha;
-          const bool pass = eval_pair(r, px, py[k], e_min, amin, amax, ux, uy, G, a_raw, alpha);
+          const bool pass = eval_pair(r, px, py[k], amax, ux, uy, G, a_raw, alpha);
           const T Tn = Tr[k] * (T(1) - alpha);
-          if (COUNT) evals[k] += Tr[k] != T(0) ? 1u : 0u;
+          if (COUNT) evals[k] += Tr[k] > T(0) ? 1u : 0u;
           const bool blend = pass & (Tn >= tmin);
-          // the first Gaussian that would take T below T_min stops the pixel
-          const bool stop = pass & !(Tn >= tmin) & (Tr[k] != T(0));
-          Tf[k] = stop ? Tr[k] : Tf[k];
+          // The first Gaussian that would take T below T_min stops the pixel,
+          // which keeps its final transmittance negated from then on (a
+          // finished pixel has Tr <= 0, so nothing blends or stops it again).
+          const bool stop = pass & !(Tn >= tmin) & (Tr[k] > T(0));
           const T w = blend ? alpha * Tr[k] : T(0);
           c0[k] = tfma(r.r, w, c0[k]);
           c1[k] = tfma(r.g, w, c1[k]);
           c2[k] = tfma(r.b, w, c2[k]);
-          Tr[k] = pass ? (blend ? Tn : T(0)) : Tr[k];
+          Tr[k] = blend ? Tn : (stop ? -Tr[k] : Tr[k]);
           last[k] = blend ? jbase + uint32_t(j) + 1u : last[k];
         }
       }
@@ -227,7 +235,7 @@ __device__ __forceinline__ void raster_fwd_tile(
     const int y = y0 + k * Cfg::kRowStep;
     if (x < v.W && y < v.H) {
       const long pix = long(y) * v.W + x;
-      const T Tfin = Tr[k] != T(0) ? Tr[k] : Tf[k];
+      const T Tfin = Tr[k] > T(0) ? Tr[k] : -Tr[k];
       const T o0 = tfma(Tfin, T(v.bg[0]), c0[k]);
       const T o1 = tfma(Tfin, T(v.bg[1]), c1[k]);
       const T o2 = tfma(Tfin, T(v.bg[2]), c2[k]);
@@ -329,7 +337,7 @@ __device__ __forceinline__ void raster_bwd_tile(
       if (int(threadIdx.x) < nb) {
         const uint32_t idx = values[rg.x + bstart + threadIdx.x];
         s_idx[threadIdx.x] = idx;
-        s_rec[threadIdx.x] = stage(recs[idx]);
+        s_rec[threadIdx.x] = stage(recs[idx], e_min, amin);
       }
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
@@ -346,8 +354,7 @@ __device__ __forceinline__ void raster_bwd_tile(
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
-        const bool pass =
-            eval_pair(r, px, py[k], e_min, amin, amax, ux[k], uy[k], G[k], a_raw[k], alpha[k]);
+        const bool pass = eval_pair(r, px, py[k], amax, ux[k], uy[k], G[k], a_raw[k], alpha[k]);
         use[k] = pass & (bstart + uint32_t(j) < ncon[k]);
         band[k] = __ballot(use[k]) != 0ull;  // some pixel of the wavefront's band k blended it
         any |= band[k];
