@@ -51,7 +51,7 @@ struct RunLayout {
 constexpr int kTicketTile = 4;     // tickets[0..3] depth passes, [4..6] tile passes
 constexpr int kTicketRaster = 7;   // [7] forward rasteriser
 constexpr int kErrorWord = 15;     // tickets[15]: sort look-back error flag
-constexpr int kDepthItems = 4;
+constexpr int kDepthItems = 8;  // keys per thread of the depth sort passes (measured best)
 
 // Host-side plan of one run.
 struct Plan {
@@ -516,8 +516,8 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     R4D_TIMED(kPreprocessFwd,
               launch_preprocess_fwd<T>(g, slots, p.V, st, p.n_pad, at<Rec<T>>(F, L.recs),
                                        at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
-                                       at<uint32_t>(F, L.dkeys), totals, F + L.ptemp_fwd,
-                                       stream));
+                                       at<uint32_t>(F, L.dkeys), totals, at<uint32_t>(F, L.kA),
+                                       at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd, stream));
   }
   hipEvent_t totals_ready = nullptr;
   if (sized) {
@@ -528,12 +528,13 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   }
   if (p.n > 0) {
     StageTimer tm(ctx, kDepthSort, stream, timed);
-    R4D_HIP(radix_histogram(at<uint32_t>(F, L.dkeys), dseg, p.V, p.n, 4, at<uint32_t>(F, L.dhist),
+    // the visible Gaussians' keys and indices, compacted by the preprocess, in kA / vA
+    R4D_HIP(radix_histogram(at<uint32_t>(F, L.kA), dseg, p.V, p.n, 4, at<uint32_t>(F, L.dhist),
                             stream));
     uint32_t* kb[2] = {at<uint32_t>(F, L.kB), at<uint32_t>(F, L.kA)};
     uint32_t* vb[2] = {at<uint32_t>(F, L.vB), at<uint32_t>(F, L.vA)};
     int res = 0;
-    R4D_HIP(onesweep_sort(at<uint32_t>(F, L.dkeys), nullptr, kb, vb, dseg,
+    R4D_HIP(onesweep_sort(at<uint32_t>(F, L.kA), at<uint32_t>(F, L.vA), kb, vb, dseg,
                           uint64_t(p.V) * p.n_pad, 4, kDepthItems, at<uint32_t>(F, L.dhist),
                           at<uint32_t>(F, L.dstatus), tickets, error, false, &res, stream));
     order = vb[res];
@@ -576,8 +577,8 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   const void* sorted_tiles = nullptr;
   if (p.n > 0) {
     auto* offsets = at<uint64_t>(F, L.offsets);
-    R4D_TIMED(kCountScan, count_scan_seg(order, at<uint32_t>(F, L.tiles), p.n, p.n_pad, p.V,
-                                         offsets, F + L.scan_tmp, stream));
+    R4D_TIMED(kCountScan, count_scan_seg(order, at<uint32_t>(F, L.tiles), totals, p.n, p.n_pad,
+                                         p.V, offsets, F + L.scan_tmp, stream));
     // packed: (index | high tile byte) words into tvA and low tile bytes into
     // tdig; otherwise tile ids into tkA and indices into tvA
     uint32_t* out_a = p.packed ? at<uint32_t>(E, L.tvA) : at<uint32_t>(E, L.tkA);

@@ -362,12 +362,14 @@ __global__ void seg_table_kernel(const unsigned long long* __restrict__ totals, 
 struct LoadCountGatherSeg {
   const uint32_t* order;  // [V][n_pad] Gaussian index in depth order
   const uint32_t* counts; // [V][n]
+  const unsigned long long* totals;  // totals[2v]: render v's visible Gaussians
   uint32_t n, n_pad;
   uint64_t total;         // V * n_pad
   __device__ uint64_t operator()(uint64_t i) const {
     if (i >= total) return 0;
     const uint32_t v = uint32_t(i / n_pad), k = uint32_t(i % n_pad);
-    return k < n ? uint64_t(counts[size_t(v) * n + order[i]]) : uint64_t(0);
+    // only the visible Gaussians are sorted (the rest of a render's order is unset)
+    return k < uint32_t(totals[2 * v]) ? uint64_t(counts[size_t(v) * n + order[i]]) : uint64_t(0);
   }
 };
 
@@ -1082,12 +1084,12 @@ size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views) {
   return (scan_temp_elems(uint64_t(n_pad) * uint64_t(n_views) + 1) + 2) * sizeof(uint64_t);
 }
 
-hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts, uint32_t n,
-                          uint32_t n_pad, int n_views, uint64_t* offsets, void* temp,
-                          hipStream_t stream) {
+hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
+                          const unsigned long long* totals, uint32_t n, uint32_t n_pad,
+                          int n_views, uint64_t* offsets, void* temp, hipStream_t stream) {
   const uint64_t total = uint64_t(n_pad) * uint64_t(n_views);
   return device_exclusive_scan<uint64_t, LoadCountGatherSeg>(
-      LoadCountGatherSeg{order, counts, n, n_pad, total}, offsets, total + 1,
+      LoadCountGatherSeg{order, counts, totals, n, n_pad, total}, offsets, total + 1,
       static_cast<uint64_t*>(temp), stream);
 }
 

@@ -164,38 +164,83 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
   }
 }
 
-// totals[2v] = visible Gaussians of render v, totals[2v + 1] = its tile
-// entries: the sum of the render's block totals (one workgroup per render).
-__global__ __launch_bounds__(kBlock) void totals_kernel(const ulonglong2* __restrict__ block_totals,
-                                                         uint32_t blocks,
-                                                         unsigned long long* __restrict__ totals) {
-  __shared__ unsigned long long s_a[kBlock / 64], s_b[kBlock / 64];
-  const uint32_t v = blockIdx.x;
-  unsigned long long a = 0, b = 0;
-  for (uint32_t i = threadIdx.x; i < blocks; i += kBlock) {
-    const ulonglong2 t = block_totals[size_t(v) * blocks + i];
-    a += t.x;
-    b += t.y;
-  }
+// Exclusive scan of one value per thread over a workgroup of kBlock threads;
+// *total receives the sum.
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long x,
+                                                              unsigned long long* s_w,
+                                                              unsigned long long* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned long long incl = x;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    a += __shfl_xor(a, off, 64);
-    b += __shfl_xor(b, off, 64);
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
   }
-  if ((threadIdx.x & 63) == 0) {
-    s_a[threadIdx.x >> 6] = a;
-    s_b[threadIdx.x >> 6] = b;
+  if (lane == 63) s_w[wave] = incl;
+  __syncthreads();
+  unsigned long long before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    before += w < wave ? s_w[w] : 0ull;
+    all += s_w[w];
   }
   __syncthreads();
+  *total = all;
+  return before + incl - x;
+}
+
+// Per render (one workgroup each): totals[2v] = visible Gaussians, totals[2v +
+// 1] = tile entries (sums of the block totals), vis_prefix[v][b] = visible
+// Gaussians of the render's blocks before b, dseg->len[v] = totals[2v].
+__global__ __launch_bounds__(kBlock) void totals_kernel(const ulonglong2* __restrict__ block_totals,
+                                                         uint32_t blocks,
+                                                         unsigned long long* __restrict__ totals,
+                                                         uint32_t* __restrict__ vis_prefix,
+                                                         SegTable* __restrict__ dseg) {
+  __shared__ unsigned long long s_w[kBlock / 64];
+  const uint32_t v = blockIdx.x;
+  unsigned long long run = 0, mine = 0;  // visible so far; this thread's share of the entries
+  for (uint32_t b0 = 0; b0 < blocks; b0 += kBlock) {
+    const uint32_t b = b0 + threadIdx.x;
+    ulonglong2 t = make_ulonglong2(0ull, 0ull);
+    if (b < blocks) t = block_totals[size_t(v) * blocks + b];
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan(t.x, s_w, &tot);
+    if (b < blocks) vis_prefix[size_t(v) * blocks + b] = uint32_t(run + ex);
+    run += tot;
+    mine += t.y;
+  }
+  unsigned long long entries;
+  block_excl_scan(mine, s_w, &entries);
   if (threadIdx.x == 0) {
-    unsigned long long ta = 0, tb = 0;
+    totals[2 * v] = run;
+    totals[2 * v + 1] = entries;
+    dseg->len[v] = uint32_t(run);
+  }
+}
+
+// Compaction of the visible Gaussians' depth keys (index order kept): block b
+// of render v writes its visible ones from vis_prefix[v][b] on.
+__global__ __launch_bounds__(kBlock) void compact_keys_kernel(
+    const uint32_t* __restrict__ depth_keys, uint32_t n, uint32_t n_pad,
+    const uint32_t* __restrict__ vis_prefix, uint32_t* __restrict__ vis_keys,
+    uint32_t* __restrict__ vis_index) {
+  __shared__ uint32_t s_cnt[kBlock / 64];
+  const uint32_t v = blockIdx.y;
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t key = i < n ? depth_keys[size_t(v) * n_pad + i] : 0xffffffffu;
+  const bool vis = key != 0xffffffffu;
+  const unsigned long long m = __ballot(vis);
+  if (lane == 0) s_cnt[wave] = uint32_t(__popcll(m));
+  __syncthreads();
+  uint32_t pos = vis_prefix[size_t(v) * gridDim.x + blockIdx.x] +
+                 uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-      ta += s_a[w];
-      tb += s_b[w];
-    }
-    totals[2 * v] = ta;
-    totals[2 * v + 1] = tb;
+  for (int w = 0; w < kBlock / 64; ++w) pos += w < wave ? s_cnt[w] : 0u;
+  if (vis) {
+    vis_keys[size_t(v) * n_pad + pos] = key;
+    vis_index[size_t(v) * n_pad + pos] = i;
   }
 }
 
@@ -278,20 +323,26 @@ template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
                                  Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
-                                 unsigned long long* totals, void* temp, hipStream_t stream) {
+                                 unsigned long long* totals, uint32_t* vis_keys,
+                                 uint32_t* vis_index, SegTable* dseg, void* temp,
+                                 hipStream_t stream) {
   if (g.n <= 0 || n_views <= 0) return hipSuccess;
   const uint32_t blocks = uint32_t((g.n + kBlock - 1) / kBlock);
   const dim3 grid(blocks, uint32_t(n_views));
   ulonglong2* block_totals = static_cast<ulonglong2*>(temp);
+  uint32_t* vis_prefix = reinterpret_cast<uint32_t*>(block_totals + size_t(blocks) * n_views);
   R4D_DEG_DISPATCH(preprocess_fwd_kernel, grid, g, slots, st, n_pad, recs, rects, tiles_touched,
                    depth_keys, block_totals)
   hipLaunchKernelGGL(totals_kernel, dim3(uint32_t(n_views)), dim3(kBlock), 0, stream, block_totals,
-                     blocks, totals);
+                     blocks, totals, vis_prefix, dseg);
+  hipLaunchKernelGGL(compact_keys_kernel, grid, dim3(kBlock), 0, stream, depth_keys, uint32_t(g.n),
+                     n_pad, vis_prefix, vis_keys, vis_index);
   return hipGetLastError();
 }
 
 size_t preprocess_temp_bytes(uint32_t n, int n_views) {
-  return size_t((n + kBlock - 1) / kBlock) * size_t(n_views) * sizeof(ulonglong2);
+  const size_t blocks = size_t((n + kBlock - 1) / kBlock) * size_t(n_views);
+  return blocks * (sizeof(ulonglong2) + sizeof(uint32_t));
 }
 
 template <typename T>
@@ -323,7 +374,8 @@ hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
   template hipError_t launch_preprocess_fwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
                                                const SettingsDev&, uint32_t, Rec<T>*, Rect16*, \
                                                uint32_t*, uint32_t*, unsigned long long*,      \
-                                               void*, hipStream_t);                            \
+                                               uint32_t*, uint32_t*, SegTable*, void*,         \
+                                               hipStream_t);                                   \
   template hipError_t launch_preprocess_bwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
                                                const SettingsDev&, const double*,              \
                                                const GradPtrs<T>&, hipStream_t);

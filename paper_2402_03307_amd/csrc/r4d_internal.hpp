@@ -57,14 +57,20 @@ struct SegTable {
 
 // ---- preprocess (per Gaussian and render)
 // Render v = blockIdx.y.  Per render: recs/rects/tiles_touched at [v][n],
-// depth_keys at [v * n_pad + i]; totals[2v] = visible Gaussians, totals[2v+1]
-// = tile entries.  temp: preprocess_temp_bytes(n, n_views).
+// depth_keys at [v * n_pad + i] (0xffffffff for a Gaussian that is not
+// visible); totals[2v] = visible Gaussians, totals[2v+1] = tile entries.  The
+// visible Gaussians' depth keys and indices are also written compacted, in
+// index order, to vis_keys / vis_index at [v * n_pad + 0 .. totals[2v]), and
+// dseg->len[v] = totals[2v] (the depth sort sorts only them).  temp:
+// preprocess_temp_bytes(n, n_views).
 size_t preprocess_temp_bytes(uint32_t n, int n_views);
 template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
                                  Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
-                                 unsigned long long* totals, void* temp, hipStream_t stream);
+                                 unsigned long long* totals, uint32_t* vis_keys,
+                                 uint32_t* vis_index, SegTable* dseg, void* temp,
+                                 hipStream_t stream);
 
 // grad2d: [V][9][n] double (mean2 x, y, Sigma_2D (0,0), (0,1), (1,1), opacity_t,
 // r, g, b).  Writes the parameter gradients summed over the renders.
@@ -109,9 +115,10 @@ hipError_t seg_table(const unsigned long long* totals, int n_views, unsigned lon
 size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
 // offsets[v * n_pad + k] = sum over renders u < v of all their entries plus the
 // entries of render v's Gaussians order[v][0..k-1]; offsets[V * n_pad] = total.
-hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts, uint32_t n,
-                          uint32_t n_pad, int n_views, uint64_t* offsets, void* temp,
-                          hipStream_t stream);
+// order[v] holds render v's totals[2v] visible Gaussians (the rest is unset).
+hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
+                          const unsigned long long* totals, uint32_t n, uint32_t n_pad,
+                          int n_views, uint64_t* offsets, void* temp, hipStream_t stream);
 
 // Emission of every render's tile entries in depth order (each Gaussian's
 // tiles row by row, its row runs from tileset.hpp) into its segment, one
