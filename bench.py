@@ -45,9 +45,10 @@ FP32_VECTOR_PEAK_TFLOPS = 78.6
 
 # Arithmetic of one evaluated (pixel, Gaussian) pair in the forward compositing
 # loop: offset (2), whitened offset (6), exponent (3: form, scale is folded,
-# exp2), opacity product, clamp, two threshold tests (4), transmittance update
-# (2), weight (1) and colour accumulation (3 fma = 6).
-FLOPS_PER_PAIR_FWD = 26
+# exp2), opacity product, clamp (min), three tests (the combined extent/alpha
+# threshold, T_min, still running), transmittance update (2), weight (1) and
+# colour accumulation (3 fma = 6).
+FLOPS_PER_PAIR_FWD = 25
 # Backward, per blended pair: the forward evaluation (14), transmittance
 # recovery (3), colour-behind update and alpha gradient (14), and the nine
 # moment sums (18 with fma = 2).
@@ -276,28 +277,26 @@ def main():
     k = (g["sh_degree"] + 1) ** 2
     tiles = stats["tiles_x"] * stats["tiles_y"]
     # algorithmic HBM bytes per launch of the memory-bound stages
+    packed = True  # the default tile sort (sort_items 0) on renders of <= 65536 tiles
     alg_bytes = {
-        # params 68 B/Gaussian + per-Gaussian outputs (rect 8, count 4, key 4)
-        # + SH (12k B) and record (48 B) of each visible Gaussian
-        "preprocess_fwd": n * (68 + 16) + n_vis * (12 * k + 48),
-        # 4 passes x (read + write of 8 B pairs; the first reads 4 B keys) + key histogram
-        "depth_sort": 4 * n * 16 - n * 4 + n * 4,
+        # params 68 B/Gaussian + per-Gaussian outputs (box 8, count 4, key 4)
+        # + SH (12k B), record (48 B) and compacted key/index (8 B) of each visible one
+        "preprocess_fwd": n * (68 + 16) + n_vis * (12 * k + 48 + 8),
+        # visible keys only: 4 passes x (read + write of 8 B key/index pairs) + histogram
+        "depth_sort": n_vis * (4 * 16 + 4),
+        # order + gathered count read, 8 B offset written per Gaussian
         "count_scan": n * 4 * 2 + n * 8,
-        # rects + order + offsets read per Gaussian, 8 B per entry written
-        "emit": D * 8 + n * 20,
-        # pass 1: read + write 8 B; last pass: read 8 B, write the 4 B value
-        "tile_sort": D * 16 + D * 12,
-        # tile count grid + ranges
-        "tile_ranges": tiles * (4 * 2 + 8),
+        # per visible Gaussian order 4 + offset 8 + box 8 + record 32 B read; per
+        # entry the packed word + low tile byte (5 B) or the (tile, index) pair (8 B)
+        "emit": n_vis * 52 + D * (5 if packed else 8),
+        # low byte count (1) + low pass (5 in, 5 out) + high byte count (1) + high
+        # pass (5 in; index 4 + 16-bit tile 2 out) per entry
+        "tile_sort": D * 23,
+        # sorted 16-bit tile ids read, ranges zeroed and written
+        "tile_ranges": D * 2 + tiles * 16,
         # params + 9 screen-space gradients (double) read, 17 + 3k gradients written
         "preprocess_bwd": n * (68 + 12 * k) + n * 72 + n * 4 * (17 + 3 * k),
     }
-    if not stages.get("emit"):
-        # packed tile sort: emission fused into the low-digit pass (writes 4 B per
-        # entry), high-digit count (reads 4 B) and pass (reads 4 B, writes 4 B);
-        # rects, order and offsets read per Gaussian
-        alg_bytes.pop("emit")
-        alg_bytes["tile_sort"] = D * 16 + n * 2 * (8 + 4 + 8)
     dominant = max(stages, key=stages.get)
     dom_ms = stages[dominant]
     workload = "500k_1352x1014_tile16"

@@ -265,11 +265,17 @@ r4d_status r4d_saved_stats(const r4d_saved *saved, int view, int64_t *n_visible,
 /* Copies one saved buffer of view v into dst (DEVICE, at least `bytes`).
  *   R4D_BUF_RECORDS   per Gaussian, 12 floats (or doubles for the f64 path):
  *                     mean2d.x, mean2d.y, conic a, conic b, conic c,
- *                     opacity_t, depth, (unused), r, g, b, (unused) -- record i
- *                     at [12*i]; q = a dx^2 + 2 b dx dy + c dy^2.  Only
+ *                     opacity_t, depth, q_max, r, g, b, (unused) -- record i
+ *                     at [12*i]; q = a dx^2 + 2 b dx dy + c dy^2 and q_max =
+ *                     min(extent^2, 2 ln(opacity_t / alpha_min)) rounded up,
+ *                     the largest q at which the Gaussian is blended.  Only
  *                     records with a depth key other than 0xffffffff are set.
  *   R4D_BUF_RECT      per Gaussian, 4 uint16: tile x0, y0, x1, y1 (x1, y1
- *                     exclusive; all zero when culled)
+ *                     exclusive; all zero when culled), the bounding box of
+ *                     the tiles the Gaussian is listed in: in each of its
+ *                     rows, the run of tiles holding a pixel centre within one
+ *                     pixel of the ellipse q <= q_max (Sec. 3.1 compositing
+ *                     rule; every row of the box holds a run)
  *   R4D_BUF_DEPTHKEY  per Gaussian uint32: float32 bit pattern of the depth,
  *                     0xffffffff when culled
  *   R4D_BUF_VALUES    D uint32: Gaussian index of each tile entry, sorted by
