@@ -17,6 +17,10 @@ Pipeline per render (view, time t), in the paper's order:
                                             (Sec. 3.1, 3DGS preliminary)
   6. spherical-harmonic colour              (Sec. 3.1)
   7. depth-ordered alpha compositing        (Sec. 3.1, blending equation)
+  (optional) speed field: each Gaussian's speed V/W at time t (Sec. 3.2.2,
+     the motion speed of the slice) moved through the projection gives its
+     2D flow d(mean2d)/dt, composited like a colour with zero background
+     (the rendered optical flow of the paper's flow figure)
 
 Readings where the paper is silent or inconsistent (all listed in the design
 notes): the rotor storage order is the main-text one; epsilon uses the sign of
@@ -185,6 +189,23 @@ def project_ewa(mu3: torch.Tensor, cov3: torch.Tensor, view: dict, st: dict):
     return pc, mean2, pz, cov2
 
 
+def speed_flow(cov4: torch.Tensor, pc: torch.Tensor, view: dict):
+    """2D flow of each Gaussian: the time derivative of its projected mean.
+
+    The sliced mean moves as mu(t) = mu_xyz + (t - mu_t) V / W, so its speed is
+    s = V / W (Sec. 3.2.2); in camera space p' = Wv s, and the pinhole mean
+    (fx x/z + cx, fy y/z + cy) moves at (fx (x' z - x z') / z^2,
+    fy (y' z - y z') / z^2).  Returns [n, 2] in pixels per unit of t."""
+    w2c = _to64(view["world_to_cam"]).reshape(3, 4)
+    speed = cov4[:, :3, 3] / cov4[:, 3, 3][:, None]
+    vc = speed @ w2c[:, :3].T
+    px, py, pz = pc.unbind(-1)
+    vx, vy, vz = vc.unbind(-1)
+    fx, fy = float(view["fx"]), float(view["fy"])
+    return torch.stack([fx * (vx * pz - px * vz) / (pz * pz),
+                        fy * (vy * pz - py * vz) / (pz * pz)], dim=-1)
+
+
 def conic_of(cov2: torch.Tensor):
     """Inverse of the symmetric 2x2 covariance, as (a, b, c) with
     q(d) = a dx^2 + 2 b dx dy + c dy^2."""
@@ -279,6 +300,7 @@ def preprocess(P: dict, view: dict, st: dict) -> dict:
     o_t = P["opacity"] * decay
     pc, mean2, depth, cov2 = project_ewa(mu3, cov3, view, st)
     conic, det = conic_of(cov2)
+    flow = speed_flow(cov4, pc, view)
     w2c = _to64(view["world_to_cam"]).reshape(3, 4)
     cam_centre = -(w2c[:, :3].T @ w2c[:, 3])
     sh = P["sh"].reshape(k, 3, n).permute(2, 0, 1)    # [n,k,3]
@@ -287,7 +309,7 @@ def preprocess(P: dict, view: dict, st: dict) -> dict:
     near_ok = depth > st["near_plane"]
     valid = time_ok & near_ok & (det > 0)
     return {
-        "mean2": mean2, "conic": conic, "depth": depth, "opacity": o_t, "rgb": rgb,
+        "mean2": mean2, "conic": conic, "depth": depth, "opacity": o_t, "rgb": rgb, "flow": flow,
         "valid": valid.detach(), "lam_dt2": lam_dt2.detach(), "cov2": cov2,
         "mu3": mu3, "cov3": cov3, "R": R, "rotor_n": r,
     }
@@ -327,7 +349,7 @@ def _depth_tie_flags(used, au, T_before, dep, rgb):
     return (ok & close & (swap > AMB_WEIGHT)).any(1)
 
 
-def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
+def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64, flow: bool = False):
     """Front-to-back compositing of every pixel in `pix` ([P,2] pixel indices
     (x, y); the sample point is the pixel centre (x+.5, y+.5)) over all valid
     Gaussians, sorted stably by depth (ties by index).
@@ -335,9 +357,10 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
     C = sum_i c_i a_i prod_{j<i} (1 - a_j) + T_final * bg (Sec. 3.1), where a
     Gaussian is skipped if q > extent^2 or a < alpha_min, with
     a = min(alpha_max, o_t exp(-q/2)), and the walk stops (without the current
-    Gaussian) once T (1 - a) < T_min.
-    Returns (colour [P,3], aux) with aux = T_final, contributor count and an
-    ambiguity flag per pixel.
+    Gaussian) once T (1 - a) < T_min.  With flow, each Gaussian's 2D flow is
+    composited with the same weights as two more channels (background 0).
+    Returns (colour [P,3] or [P,5], aux) with aux = T_final, contributor count
+    and an ambiguity flag per pixel.
     """
     st = settings_dict(st)
     q_max = st["extent_sigma"] ** 2
@@ -349,9 +372,18 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
     cn = pre["conic"][order]
     op = pre["opacity"][order]
     rgb = pre["rgb"][order]
+    bg_t = _to64(list(bg))
+    amb_feat = rgb.detach()
+    if flow:
+        fl = pre["flow"][order]
+        rgb = torch.cat([rgb, fl], dim=1)
+        bg_t = torch.cat([bg_t, torch.zeros(2, dtype=DT)])
+        # depth-tie ambiguity judged on the flow relative to its largest value
+        scale = float(fl.detach().abs().max()) if fl.numel() else 1.0
+        amb_feat = torch.cat([amb_feat, fl.detach() / max(scale, 1e-30)], dim=1)
+    nc = rgb.shape[1]
     dep = pre["depth"].detach()[order]
     G = order.numel()
-    bg_t = _to64(list(bg))
     P = pix.shape[0]
     colours = []
     T_final = torch.ones(P, dtype=DT)
@@ -361,7 +393,7 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
     ar = torch.arange(G)
     if G == 0:
         # nothing survives: every pixel is the background
-        out = bg_t[None, :].expand(P, 3).clone()
+        out = bg_t[None, :].expand(P, nc).clone()
         return out, {"T_final": T_final, "n_contrib": n_contrib, "ambiguous": ambiguous}
     for s0 in range(0, P, chunk):
         pts = centres[s0:s0 + chunk]
@@ -399,7 +431,7 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
                 col = w @ rgb.detach() + tf[:, None] * bg_t[None, :]
                 T_final[s0:s0 + c] = tf
                 n_contrib[s0:s0 + c] = used.sum(1)
-                amb_rows = amb_pix | _depth_tie_flags(used, au, T_before, dep, rgb.detach())
+                amb_rows = amb_pix | _depth_tie_flags(used, au, T_before, dep, amb_feat)
                 ambiguous[s0:s0 + c] = amb_rows
                 colours.append(col)
             continue
@@ -410,7 +442,7 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
                 flag = bool(amb_pix[row])
                 if sel.numel() > 1:
                     flag |= bool(_depth_tie_flags(used[row:row + 1], au[row:row + 1],
-                                                  T_before[row:row + 1], dep, rgb.detach())[0])
+                                                  T_before[row:row + 1], dep, amb_feat)[0])
                 ambiguous[p] = flag
                 n_contrib[p] = sel.numel()
             # the blending equation on the contributing Gaussians, differentiably
@@ -423,7 +455,7 @@ def composite(pix: torch.Tensor, pre: dict, bg, st: dict, chunk: int = 64):
             col = (rgb[sel] * w[:, None]).sum(0) + Tex[-1] * bg_t
             T_final[p] = Tex[-1].detach()
             colours.append(col[None])
-    out = torch.cat(colours, 0) if colours else torch.zeros(0, 3, dtype=DT)
+    out = torch.cat(colours, 0) if colours else torch.zeros(0, nc, dtype=DT)
     aux = {"T_final": T_final, "n_contrib": n_contrib, "ambiguous": ambiguous}
     return out, aux
 
@@ -441,12 +473,13 @@ def gaussian_margin_flags(pre: dict, st: dict):
 
 
 def render(g: dict, view: dict, st: dict | None = None, pixels=None,
-           requires_grad: bool = False, P: dict | None = None):
+           requires_grad: bool = False, P: dict | None = None, flow: bool = False):
     """Render one view.
 
     g: SoA parameter arrays (workloads layout).  pixels: None for the full
     frame, or a 1-D array of row-major pixel indices.  Returns a dict with
-    'image' ([3,H,W] or [3,P]), 'params' (the float64 leaves), 'pre' and aux.
+    'image' ([3,H,W] or [3,P]), with flow also 'flow' ([2,H,W] or [2,P]),
+    'params' (the float64 leaves), 'pre' and aux.
     """
     st = settings_dict(st)
     if P is None:
@@ -459,7 +492,7 @@ def render(g: dict, view: dict, st: dict | None = None, pixels=None,
     else:
         pidx = torch.as_tensor(np.asarray(pixels), dtype=torch.int64)
         pix = torch.stack([pidx % W, pidx // W], dim=-1)
-    col, aux = composite(pix, pre, view["bg"], st)
+    col, aux = composite(pix, pre, view["bg"], st, flow=flow)
     # Pixels a Gaussian with a marginal cull decision could be blended into.
     gflag = gaussian_margin_flags(pre, st)
     if bool(gflag.any()):
@@ -471,9 +504,14 @@ def render(g: dict, view: dict, st: dict | None = None, pixels=None,
             o = pre["opacity"].detach()[idx]
             reach = torch.clamp(2.0 * torch.log(o / st["alpha_min"]), max=st["extent_sigma"] ** 2)
             aux["ambiguous"] |= (q <= reach[None, :] + 1e-3).any(1)
-    image = col.T.contiguous()
+    image = col[:, :3].T.contiguous()
+    out = {}
+    if flow:
+        out["flow"] = col[:, 3:].T.contiguous()
     if pixels is None:
         image = image.reshape(3, H, W)
+        if flow:
+            out["flow"] = out["flow"].reshape(2, H, W)
         for key in ("T_final", "n_contrib", "ambiguous"):
             aux[key] = aux[key].reshape(H, W)
-    return {"image": image, "params": P, "pre": pre, **aux}
+    return {"image": image, "params": P, "pre": pre, **out, **aux}
