@@ -13,6 +13,10 @@ step forward + L1 + backward of all 16 renders, once as 16 plain per-render
 call sequences and once as one graph-mode call over the 16 renders (tile 16,
 and with the autotuned tile size / sort chunking).
 
+Speed field: the headline workload rendered with its 2D flow images (the
+projected speed of each Gaussian's sliced mean, composited with the colour
+weights) in the same pass, forward + colour and flow L1 + backward.
+
 Further lines (per_config): 2,000 Gaussians at 128x128 (forward), 300,000
 Gaussians over 30 orbit renders (forward), 3,000,000 Gaussians over 16
 renders (graph-mode forward + backward).
@@ -155,6 +159,68 @@ class Stepper:
     def check(self):
         if self.last is not None:
             self.last.check()
+
+
+class FlowStepper:
+    """forward + losses + backward of the speed-field render: colour L1 against
+    the targets and L1 of the flow images against zero flow."""
+
+    def __init__(self, r4d, rend, params, views, st, targets_flat):
+        import torch
+        self.rend, self.p, self.views, self.st = rend, params, views, st
+        self.targets = targets_flat
+        self.graph = st.get("mode") == "graph"
+        self.grad = torch.empty_like(targets_flat)
+        nflow = targets_flat.numel() // 3 * 2
+        self.zero_flow = torch.zeros(nflow, dtype=targets_flat.dtype, device=targets_flat.device)
+        self.grad_flow = torch.empty_like(self.zero_flow)
+        self.last = None
+
+    def step(self):
+        imgs, flows, saved = self.rend.forward(self.p, self.views, self.st, save=True, flat=True,
+                                               flow=True)
+        _, dl = self.rend.l1_loss_grad_views(imgs, self.targets, self.views, self.grad)
+        _, dlf = self.rend.l1_loss_grad(flows, self.zero_flow, self.grad_flow)
+        self.rend.backward(self.p, self.views, self.st, saved, dl, dlf)
+        if self.last is not None and not self.graph:
+            self.last.release()
+        self.last = saved
+
+    def forward(self):
+        self.rend.forward(self.p, self.views, self.st, save=False, flat=True, flow=True)
+
+    def check(self):
+        if self.last is not None:
+            self.last.check()
+
+
+def flow_render(r4d, rend, params, views, st, args):
+    """The speed-field (optical flow) render of the headline workload: colour and
+    flow images in one pass, step = forward + colour L1 + flow L1 + backward;
+    graph mode, plus per-stage times of the plain mode."""
+    import torch
+    targets = flat_targets(views, params["means"].device)
+    s = FlowStepper(r4d, rend, params, views, dict(st, mode="graph"), targets)
+    step_ms = timed(s.step, args.steps, args.warmup)
+    s.check()
+    fwd_ms = timed(s.forward, args.steps, args.warmup)
+    del s
+    plain = FlowStepper(r4d, rend, params, views, dict(st, mode="per_view"), targets)
+    rend.set_timing(True)
+    rend.timings(reset=True)
+    for _ in range(max(3, min(args.steps, 10))):
+        plain.step()
+    torch.cuda.synchronize()
+    tim = rend.timings(reset=True)
+    rend.set_timing(False)
+    plain.last.release()
+    res = {"workload": "the headline workload rendered with its speed field: colour + 2-channel "
+                       "flow images; step = forward + colour L1 + flow L1 + backward; graph mode",
+           "ms_per_step": step_ms, "steps_per_s": 1e3 / step_ms, "fwd_ms": fwd_ms,
+           "fwd_frames_per_s": 1e3 / fwd_ms,
+           "stage_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tim.items()}}
+    print(f"flow render: {res}", file=sys.stderr, flush=True)
+    return res
 
 
 def per_view_step(r4d, rend, params, views, st, targets):
@@ -353,6 +419,7 @@ def main():
         "roofline": roofline,
     }
     del graph, plain
+    out["flow_render"] = flow_render(r4d, rend, params, views, st, args)
 
     if not args.no_extra:
         out["batched_vs_plain"] = batched_vs_plain(r4d, rend, dev, args)

@@ -221,6 +221,45 @@ r4d_status r4d_render_backward_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g,
                                    const r4d_settings *settings, const r4d_saved *saved,
                                    const double *dL_dimages, r4d_grads_f64 *out, void *stream);
 
+/* Speed-field (optical flow) render, Sec. 3.2.2: the sliced mean of a
+ * Gaussian moves with speed V / W (V the space-time block of its 4D covariance,
+ * W its time variance), so its projected mean moves at
+ *   flow = (fx (vx z - x vz) / z^2, fy (vy z - y vz) / z^2)
+ * pixels per unit of t, with (x, y, z) the camera-space mean and (vx, vy, vz)
+ * = world_to_cam rotation times V / W.  Each pixel receives the flows of the
+ * Gaussians blended there, weighted exactly as their colours (alpha times the
+ * transmittance in front), over a background of 0.  The colour images are
+ * rendered in the same pass, identical to r4d_render_forward's.
+ *   flows  DEVICE float, view v at offset sum_{u<v} 2*H_u*W_u, planar [2][H][W]
+ *          (x then y component)
+ * Other arguments, layout and errors as r4d_render_forward (flows NULL:
+ * R4D_ERR_INVALID_ARG).  The saved state also serves r4d_render_backward
+ * (colour gradient only). */
+r4d_status r4d_render_forward_flow(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
+                                   int n_views, const r4d_settings *settings, float *images,
+                                   float *flows, r4d_saved **saved, void *stream);
+
+/* Backward of r4d_render_forward_flow: gradients of a loss on both the colour
+ * images and the flow images.
+ *   dL_dflows  DEVICE float, same layout as the forward flows (not NULL)
+ * Other arguments and errors as r4d_render_backward; R4D_ERR_STATE if `saved`
+ * comes from a forward without flow. */
+r4d_status r4d_render_backward_flow(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
+                                    int n_views, const r4d_settings *settings,
+                                    const r4d_saved *saved, const float *dL_dimages,
+                                    const float *dL_dflows, r4d_grads *out, void *stream);
+
+/* The two flow calls in float64 (test use: finite differences). */
+r4d_status r4d_render_forward_flow_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g,
+                                       const r4d_view *views, int n_views,
+                                       const r4d_settings *settings, double *images,
+                                       double *flows, r4d_saved **saved, void *stream);
+r4d_status r4d_render_backward_flow_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g,
+                                        const r4d_view *views, int n_views,
+                                        const r4d_settings *settings, const r4d_saved *saved,
+                                        const double *dL_dimages, const double *dL_dflows,
+                                        r4d_grads_f64 *out, void *stream);
+
 /* Returns the saved arena to its context's cache.  NULL is ignored.  A saved
  * handle may outlive its context: r4d_destroy frees its device memory and a
  * later release only frees the handle. */
@@ -286,6 +325,9 @@ r4d_status r4d_saved_stats(const r4d_saved *saved, int view, int64_t *n_visible,
  *   R4D_BUF_NCONTRIB  H*W uint32: tile-list entries up to the last contributor
  *   R4D_BUF_NEVAL     H*W uint32: tile-list entries the forward evaluated for the
  *                     pixel (only if timing was enabled for the forward call,
+ *                     R4D_ERR_STATE otherwise; never for a flow render)
+ *   R4D_BUF_FLOW      per Gaussian, 2 floats (doubles): its 2D flow, record i
+ *                     at [2*i], set where RECORDS is (flow renders only,
  *                     R4D_ERR_STATE otherwise)
  * `bytes` must equal the buffer size (R4D_ERR_INVALID_ARG otherwise).  The
  * call waits for the forward call to finish. */
@@ -297,7 +339,8 @@ enum {
   R4D_BUF_RANGES = 4,
   R4D_BUF_TFINAL = 5,
   R4D_BUF_NCONTRIB = 6,
-  R4D_BUF_NEVAL = 7
+  R4D_BUF_NEVAL = 7,
+  R4D_BUF_FLOW = 8
 };
 r4d_status r4d_saved_copy(const r4d_saved *saved, int view, int buffer, void *dst, size_t bytes,
                           void *stream);

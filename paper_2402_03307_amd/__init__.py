@@ -29,13 +29,13 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libr4d.so")
 
-__all__ = ["render", "Renderer", "R4DError", "default_settings", "LIB_PATH",
+__all__ = ["render", "render_flow", "Renderer", "R4DError", "default_settings", "LIB_PATH",
            "BUF_RECORDS", "BUF_RECT", "BUF_DEPTHKEY", "BUF_VALUES", "BUF_RANGES",
-           "BUF_TFINAL", "BUF_NCONTRIB", "EXPORTED_SYMBOLS", "MODE_PER_VIEW", "MODE_FUSED",
-           "MODE_GRAPH"]
+           "BUF_TFINAL", "BUF_NCONTRIB", "BUF_FLOW", "EXPORTED_SYMBOLS", "MODE_PER_VIEW",
+           "MODE_FUSED", "MODE_GRAPH"]
 
 (BUF_RECORDS, BUF_RECT, BUF_DEPTHKEY, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB,
- BUF_NEVAL) = range(8)
+ BUF_NEVAL, BUF_FLOW) = range(9)
 
 # execution modes of a multi-view call (see R4D_MODE_* in include/r4d.h)
 MODE_PER_VIEW, MODE_FUSED, MODE_GRAPH = 0, 1, 2
@@ -44,7 +44,8 @@ _MODE_NAMES = {"per_view": MODE_PER_VIEW, "fused": MODE_FUSED, "graph": MODE_GRA
 EXPORTED_SYMBOLS = (
     "r4d_default_settings", "r4d_create", "r4d_destroy", "r4d_render_forward",
     "r4d_render_backward", "r4d_render_forward_f64", "r4d_render_backward_f64",
-    "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
+    "r4d_render_forward_flow", "r4d_render_backward_flow", "r4d_render_forward_flow_f64",
+    "r4d_render_backward_flow_f64", "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
     "r4d_saved_copy", "r4d_saved_check", "r4d_saved_config", "r4d_status_string",
     "r4d_last_error", "r4d_set_timing", "r4d_get_timings", "r4d_stage_name",
 )
@@ -98,6 +99,17 @@ def _load():
                 c_vp]
     for name, args in (("r4d_render_forward", fwd_args), ("r4d_render_forward_f64", fwd_args),
                        ("r4d_render_backward", bwd_args), ("r4d_render_backward_f64", bwd_args)):
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    ffwd_args = [c_vp, P(_Gaussians), P(_View), ctypes.c_int, P(_Settings), c_vp, c_vp, P(c_vp),
+                 c_vp]
+    fbwd_args = [c_vp, P(_Gaussians), P(_View), ctypes.c_int, P(_Settings), c_vp, c_vp, c_vp,
+                 P(_Grads), c_vp]
+    for name, args in (("r4d_render_forward_flow", ffwd_args),
+                       ("r4d_render_forward_flow_f64", ffwd_args),
+                       ("r4d_render_backward_flow", fbwd_args),
+                       ("r4d_render_backward_flow_f64", fbwd_args)):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
@@ -206,6 +218,26 @@ _live_saved = weakref.WeakSet()
 _live_renderers = weakref.WeakSet()
 
 
+def _split(flat: torch.Tensor, views, channels: int):
+    """Per-view [channels, H, W] views of a flat output in the forward's layout."""
+    out, off = [], 0
+    for v in views:
+        h, w = int(v["height"]), int(v["width"])
+        out.append(flat[off:off + channels * h * w].view(channels, h, w))
+        off += channels * h * w
+    return out
+
+
+def _flat(grads, dtype) -> torch.Tensor:
+    """One contiguous tensor of `dtype` from a flat tensor or a list of per-view ones."""
+    if isinstance(grads, torch.Tensor):
+        d = grads.reshape(-1)
+        if d.dtype != dtype or not d.is_contiguous():
+            d = d.to(dtype).contiguous()
+        return d
+    return torch.cat([gi.reshape(-1).to(dtype) for gi in grads]).contiguous()
+
+
 @atexit.register
 def _release_all():
     for s in list(_live_saved):
@@ -270,7 +302,7 @@ class SavedState:
                   BUF_VALUES: ((s["n_dup"],), torch.int32),
                   BUF_RANGES: ((s["tiles_x"] * s["tiles_y"], 2), torch.int32),
                   BUF_TFINAL: ((hw,), fdt), BUF_NCONTRIB: ((hw,), torch.int32),
-                  BUF_NEVAL: ((hw,), torch.int32)}
+                  BUF_NEVAL: ((hw,), torch.int32), BUF_FLOW: ((n_gaussians, 2), fdt)}
         shape, dt = shapes[buffer]
         out = torch.empty(shape, dtype=dt, device=self.renderer.device)
         st = _lib.r4d_saved_copy(self.handle, view, buffer, _ptr(out),
@@ -324,38 +356,46 @@ class Renderer:
         return t
 
     def forward(self, params: dict, views, settings: dict | None = None, save: bool = True,
-                flat: bool = False):
+                flat: bool = False, flow: bool = False):
         """Renders `views`; returns (list of [3, H, W] images, SavedState or
         None), or with flat=True the images as one 1-D tensor in the layout of
-        r4d_render_forward.  In graph mode the images live in a buffer that the
-        next graph forward of the same shape overwrites."""
+        r4d_render_forward.  With flow=True (r4d_render_forward_flow) it returns
+        (images, flow images, SavedState or None), the flow images as [2, H, W]
+        tensors (or one flat tensor).  In graph mode the outputs live in buffers
+        that the next graph forward of the same shape overwrites."""
         n, deg, dtype = _check_params(params)
         g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _PARAM_KEYS])
         varr = _views_array(views)
         st = _settings_struct(settings)
         graph = st.mode == MODE_GRAPH
         sizes = [3 * int(v["height"]) * int(v["width"]) for v in views]
-        out = self._buffer(("img", dtype, tuple(sizes), n) + tuple(params[k].data_ptr()
-                                                               for k in _PARAM_KEYS),
-                           (sum(sizes),), dtype, graph)
+        key = (dtype, tuple(sizes), n) + tuple(params[k].data_ptr() for k in _PARAM_KEYS)
+        out = self._buffer(("img", flow) + key, (sum(sizes),), dtype, graph)
         handle = ctypes.c_void_p()
-        fn = _lib.r4d_render_forward if dtype == torch.float32 else _lib.r4d_render_forward_f64
-        status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st), _ptr(out),
-                    ctypes.byref(handle) if save else None, _stream(self.device))
-        self._check(status, "r4d_render_forward")
+        hptr = ctypes.byref(handle) if save else None
+        if flow:
+            fout = self._buffer(("flow",) + key, (sum(sizes) // 3 * 2,), dtype, graph)
+            fn = (_lib.r4d_render_forward_flow if dtype == torch.float32
+                  else _lib.r4d_render_forward_flow_f64)
+            status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st),
+                        _ptr(out), _ptr(fout), hptr, _stream(self.device))
+            self._check(status, "r4d_render_forward_flow")
+        else:
+            fn = _lib.r4d_render_forward if dtype == torch.float32 else _lib.r4d_render_forward_f64
+            status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st),
+                        _ptr(out), hptr, _stream(self.device))
+            self._check(status, "r4d_render_forward")
         saved = SavedState(self, handle, views, dtype) if save else None
         if flat:
-            return out, saved
-        images, off = [], 0
-        for v, sz in zip(views, sizes):
-            images.append(out[off:off + sz].view(3, int(v["height"]), int(v["width"])))
-            off += sz
-        return images, saved
+            return (out, fout, saved) if flow else (out, saved)
+        images = _split(out, views, 3)
+        return (images, _split(fout, views, 2), saved) if flow else (images, saved)
 
     def backward(self, params: dict, views, settings: dict | None, saved: SavedState,
-                 grad_images) -> dict:
-        """Gradients w.r.t. the five parameter tensors.  grad_images: list of
-        [3, H, W] tensors or one flat tensor in the forward's layout.  In graph
+                 grad_images, grad_flows=None) -> dict:
+        """Gradients w.r.t. the five parameter tensors.  grad_images (and
+        grad_flows, for the saved state of a flow render): list of [3, H, W]
+        ([2, H, W]) tensors or one flat tensor in the forward's layout.  In graph
         mode the returned tensors are buffers that the next graph backward of
         the same shape overwrites."""
         n, deg, dtype = _check_params(params)
@@ -363,15 +403,18 @@ class Renderer:
         varr = _views_array(views)
         st = _settings_struct(settings)
         graph = st.mode == MODE_GRAPH
-        if isinstance(grad_images, torch.Tensor):
-            dl = grad_images.reshape(-1)
-            if dl.dtype != dtype or not dl.is_contiguous():
-                dl = dl.to(dtype).contiguous()
-        else:
-            dl = torch.cat([gi.reshape(-1).to(dtype) for gi in grad_images]).contiguous()
+        dl = _flat(grad_images, dtype)
         grads = {k: self._buffer(("grad", k, dtype, n), tuple(params[k].shape), dtype, graph)
                  for k in _PARAM_KEYS}
         gs = _Grads(*[_ptr(grads[k]) for k in _PARAM_KEYS])
+        if grad_flows is not None:
+            dlf = _flat(grad_flows, dtype)
+            fn = (_lib.r4d_render_backward_flow if dtype == torch.float32
+                  else _lib.r4d_render_backward_flow_f64)
+            status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st),
+                        saved.handle, _ptr(dl), _ptr(dlf), ctypes.byref(gs), _stream(self.device))
+            self._check(status, "r4d_render_backward_flow")
+            return grads
         fn = _lib.r4d_render_backward if dtype == torch.float32 else _lib.r4d_render_backward_f64
         status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st),
                     saved.handle, _ptr(dl), ctypes.byref(gs), _stream(self.device))
@@ -404,11 +447,13 @@ class Renderer:
         self._check(status, "r4d_l1_loss_grad_views")
         return loss[0], grad
 
-    def l1_loss_grad(self, image: torch.Tensor, target: torch.Tensor):
-        """(mean |image - target|, its gradient w.r.t. image)."""
+    def l1_loss_grad(self, image: torch.Tensor, target: torch.Tensor,
+                     grad: torch.Tensor | None = None):
+        """(mean |image - target|, its gradient w.r.t. image), the gradient
+        written into `grad` when given."""
         image = image.contiguous()
         target = target.contiguous()
-        grad = torch.empty_like(image)
+        grad = torch.empty_like(image) if grad is None else grad
         loss = torch.empty(1, dtype=torch.float32, device=self.device)
         status = _lib.r4d_l1_loss_grad(self.handle, _ptr(image), _ptr(target), image.numel(),
                                        _ptr(grad), _ptr(loss), _stream(self.device))
@@ -461,3 +506,46 @@ def render(params: dict, views, settings: dict | None = None, renderer: Renderer
     return list(_Render4D.apply(renderer, list(views), settings, int(params["sh_degree"]),
                                 params["means"], params["log_scales"], params["rotors"],
                                 params["opacity"], params["sh"]))
+
+
+class _Render4DFlow(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer, views, settings, sh_degree, means, log_scales, rotors, opacity, sh):
+        params = {"means": means, "log_scales": log_scales, "rotors": rotors, "opacity": opacity,
+                  "sh": sh, "sh_degree": sh_degree}
+        images, flows, saved = renderer.forward(params, views, settings, save=True, flow=True)
+        ctx.renderer, ctx.views, ctx.settings, ctx.saved = renderer, views, settings, saved
+        ctx.save_for_backward(means, log_scales, rotors, opacity, sh)
+        ctx.sh_degree = sh_degree
+        return tuple(images) + tuple(flows)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        means, log_scales, rotors, opacity, sh = ctx.saved_tensors
+        params = {"means": means, "log_scales": log_scales, "rotors": rotors, "opacity": opacity,
+                  "sh": sh, "sh_degree": ctx.sh_degree}
+        nv = len(ctx.views)
+
+        def filled(g, v, c):
+            return g if g is not None else torch.zeros(c, int(v["height"]), int(v["width"]),
+                                                       dtype=means.dtype, device=means.device)
+        gi = [filled(g, v, 3) for g, v in zip(grads[:nv], ctx.views)]
+        gf = [filled(g, v, 2) for g, v in zip(grads[nv:], ctx.views)]
+        out = ctx.renderer.backward(params, ctx.views, ctx.settings, ctx.saved, gi, gf)
+        ctx.saved.release()
+        return (None, None, None, None, out["means"], out["log_scales"], out["rotors"],
+                out["opacity"], out["sh"])
+
+
+def render_flow(params: dict, views, settings: dict | None = None,
+                renderer: Renderer | None = None):
+    """Colour and speed-field (optical flow) render of `views`; differentiable
+    w.r.t. the five parameter tensors through both outputs.  Returns (list of
+    [3, H, W] images, list of [2, H, W] flow images in pixels per unit of t)."""
+    dev = params["means"].device
+    renderer = renderer or _renderer_for(dev)
+    out = _Render4DFlow.apply(renderer, list(views), settings, int(params["sh_degree"]),
+                              params["means"], params["log_scales"], params["rotors"],
+                              params["opacity"], params["sh"])
+    nv = len(views)
+    return list(out[:nv]), list(out[nv:])

@@ -41,11 +41,11 @@ struct GraphEntry;
 // before the run) and `entries` (the tile lists, sized by the entry capacity).
 struct RunLayout {
   // fixed block
-  size_t meta, recs, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp, ranges,
-      T_final, n_contrib, n_eval, img_copy, walk, ptemp_fwd, zero_begin, totals, dhist, tickets,
-      dstatus, zero_end, fixed_bytes;
+  size_t meta, recs, flows, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp,
+      ranges, T_final, n_contrib, n_eval, img_copy, flow_copy, walk, ptemp_fwd, zero_begin,
+      totals, dhist, tickets, dstatus, zero_end, fixed_bytes;
   // entries block
-  size_t tkA, tkB, tvA, tvB, tdig, thi, t16, etemp, ptemp, ck, tstatus, entries_bytes;
+  size_t tkA, tkB, tvA, tvB, tdig, thi, t16, etemp, ptemp, ck, ckf, tstatus, entries_bytes;
 };
 
 constexpr int kTicketTile = 4;     // tickets[0..3] depth passes, [4..6] tile passes
@@ -67,6 +67,7 @@ struct Plan {
   SegTable dseg{};
   size_t scal = 4;
   bool count_evals = false;
+  bool flow = false;    // also composite the 2D flow (flow images)
 };
 
 }  // namespace
@@ -128,6 +129,7 @@ struct RunState {
   unsigned long long* pinned = nullptr;  // [2 * V + 2] (2 * kMaxViews + 2 words)
   hipEvent_t done = nullptr;
   size_t image_offset = 0;     // first image element of this run in the call's images
+  size_t flow_offset = 0;      // first flow element of this run in the call's flow images
 };
 
 struct GraphEntry {
@@ -145,6 +147,7 @@ struct GraphEntry {
 struct r4d_saved {
   r4d_ctx* ctx = nullptr;
   bool f64 = false;
+  bool flow = false;            // flow render: the backward may take flow gradients
   int n = 0, deg = 0;
   r4d_settings settings;        // as resolved (tile size chosen)
   std::vector<r4d_view> views;
@@ -359,8 +362,9 @@ std::string view_shape_key(const r4d_view* views, int V) {
 }
 
 Plan make_plan(const r4d_view* views, int V, uint32_t n, int deg, const r4d_settings& s,
-               size_t scal) {
+               size_t scal, bool flow = false) {
   Plan p;
+  p.flow = flow;
   p.V = V;
   p.n = n;
   p.n_pad = uint32_t(round_seg(n));
@@ -415,6 +419,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   const size_t rec_bytes = 12 * p.scal;
   L.meta = take(sizeof(ViewSlot) * V + 2 * sizeof(SegTable));
   L.recs = take(V * n * rec_bytes);
+  L.flows = p.flow ? take(V * n * 2 * p.scal) : 0;
   L.rects = take(V * n * sizeof(Rect16));
   L.tiles = take(V * n * 4);
   L.dkeys = take(V * np * 4);
@@ -430,6 +435,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.n_contrib = take(size_t(p.total_pix) * 4);
   L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 4) : 0;
   L.img_copy = take(3 * size_t(p.total_pix) * p.scal);
+  L.flow_copy = p.flow ? take(2 * size_t(p.total_pix) * p.scal) : 0;
   L.walk = take(size_t(p.total_tiles) * 4);
   L.ptemp_fwd = take(preprocess_temp_bytes(p.n, p.V));
   L.zero_begin = off;
@@ -444,6 +450,8 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.tkA = take(cap * 4);
   L.tvA = take(cap * 4);
   L.ck = take(size_t(ck_slots(p, capacity)) * size_t(p.ts) * size_t(p.ts) * 4 * p.scal);
+  L.ckf = p.flow ? take(size_t(ck_slots(p, capacity)) * size_t(p.ts) * size_t(p.ts) * 2 * p.scal)
+                 : 0;
   L.etemp = take(emit_temp_bytes(capacity));
   if (p.packed) {
     L.tkB = L.tvB = 0;
@@ -495,12 +503,24 @@ SegTable* tseg_of(uint8_t* fixed, const RunLayout& L, int V) {
   return dseg_of(fixed, L, V) + 1;
 }
 
+// What the backward's segment walks read, as the forward left it.
+template <typename T>
+RasterSaved<T> saved_of(const RunState& r) {
+  uint8_t* F = r.fixed;
+  uint8_t* E = r.entries;
+  const bool fl = r.plan.flow;
+  return RasterSaved<T>{at<Ck<T>>(E, r.L.ck), at<T>(F, r.L.img_copy), at<uint32_t>(F, r.L.walk),
+                        fl ? at<Vec2<T>>(E, r.L.ckf) : nullptr,
+                        fl ? at<T>(F, r.L.flow_copy) : nullptr};
+}
+
 // Enqueues the forward of a run.  sized = false: entries block and capacity
 // are already in place (graph capture); sized = true: after the preprocess the
 // per-view totals are read back and the entries block is allocated exactly.
 template <typename T>
 r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* images,
-                           const SettingsDev& st, bool sized, bool timed, hipStream_t stream) {
+                           T* flow_images, const SettingsDev& st, bool sized, bool timed,
+                           hipStream_t stream) {
   const Plan& p = r.plan;
   RunLayout& L = r.L;
   uint8_t* F = r.fixed;
@@ -515,6 +535,7 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   if (p.n > 0) {
     R4D_TIMED(kPreprocessFwd,
               launch_preprocess_fwd<T>(g, slots, p.V, st, p.n_pad, at<Rec<T>>(F, L.recs),
+                                       p.flow ? at<Vec2<T>>(F, L.flows) : nullptr,
                                        at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
                                        at<uint32_t>(F, L.dkeys), totals, at<uint32_t>(F, L.kA),
                                        at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd, stream));
@@ -564,6 +585,7 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     L.etemp = L2.etemp;
     L.ptemp = L2.ptemp;
     L.ck = L2.ck;
+    L.ckf = L2.ckf;
     L.tstatus = L2.tstatus;
     L.entries_bytes = L2.entries_bytes;
     r.entries = static_cast<uint8_t*>(ctx_alloc(ctx, L.entries_bytes));
@@ -614,10 +636,12 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   R4D_TIMED(kTileRanges, tile_ranges(sorted_tiles, p.packed, tseg, slots, p.total_tiles,
                                      p.n > 0 ? r.capacity : 0, ranges, stream));
   r.values = values;
-  const RasterSaved<T> sv{at<Ck<T>>(E, L.ck), at<T>(F, L.img_copy), at<uint32_t>(F, L.walk)};
+  const RasterSaved<T> sv = saved_of<T>(r);
   R4D_TIMED(kRasterFwd,
-            launch_raster_fwd<T>(at<Rec<T>>(F, L.recs), p.n, values, ranges, slots, p.V,
-                                 p.total_tiles, p.ts, st, p.fppt, images, at<T>(F, L.T_final),
+            launch_raster_fwd<T>(at<Rec<T>>(F, L.recs),
+                                 p.flow ? at<Vec2<T>>(F, L.flows) : nullptr, p.n, values, ranges,
+                                 slots, p.V, p.total_tiles, p.ts, st, p.fppt, images,
+                                 p.flow ? flow_images : nullptr, at<T>(F, L.T_final),
                                  at<uint32_t>(F, L.n_contrib),
                                  p.count_evals ? at<uint32_t>(F, L.n_eval) : nullptr, sv,
                                  tickets + kTicketRaster, stream));
@@ -689,30 +713,37 @@ r4d_status init_run(r4d_ctx* ctx, RunState& r, const Plan& p) {
   return R4D_OK;
 }
 
+// Screen-space gradient components per Gaussian and render.
+size_t grad_comps(const Plan& p, bool flow_grads) { return p.flow && flow_grads ? 11 : 9; }
+
+// dLf: the flow images' gradient (flow runs; null = colour loss only).
 template <typename T>
 r4d_status enqueue_backward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, const T* dL,
-                            uint8_t* bwd_block, const SettingsDev& st, const GradPtrs<T>& out,
-                            bool timed, hipStream_t stream) {
+                            const T* dLf, uint8_t* bwd_block, const SettingsDev& st,
+                            const GradPtrs<T>& out, bool timed, hipStream_t stream) {
   const Plan& p = r.plan;
   uint8_t* F = r.fixed;
-  const size_t g2_bytes = align256(size_t(p.V) * 9 * size_t(p.n) * 8);
+  if (dLf && !p.flow) return fail(ctx, R4D_ERR_STATE, "flow gradients for a render without flow");
+  const size_t nc = grad_comps(p, dLf != nullptr);
+  const size_t g2_bytes = align256(size_t(p.V) * nc * size_t(p.n) * 8);
   auto* grad2d = reinterpret_cast<double*>(bwd_block);
   auto* work = reinterpret_cast<uint32_t*>(bwd_block + g2_bytes);
   R4D_HIP(fill_zero(bwd_block, g2_bytes + 256, stream));
-  const RasterSaved<T> sv{at<Ck<T>>(r.entries, r.L.ck), at<T>(F, r.L.img_copy),
-                          at<uint32_t>(F, r.L.walk)};
+  const RasterSaved<T> sv = saved_of<T>(r);
   R4D_TIMED(kRasterBwd,
-            launch_raster_bwd<T>(at<Rec<T>>(F, r.L.recs), p.n, r.values, at<uint2>(F, r.L.ranges),
-                                 slots_of(F, r.L), p.V, p.total_tiles, bwd_items(p, r.capacity),
-                                 p.ts, st, p.bppt, at<T>(F, r.L.T_final),
-                                 at<uint32_t>(F, r.L.n_contrib), sv, dL, grad2d, work, stream));
-  R4D_TIMED(kPreprocessBwd,
-            launch_preprocess_bwd<T>(g, slots_of(F, r.L), p.V, st, grad2d, out, stream));
+            launch_raster_bwd<T>(at<Rec<T>>(F, r.L.recs),
+                                 p.flow ? at<Vec2<T>>(F, r.L.flows) : nullptr, p.n, r.values,
+                                 at<uint2>(F, r.L.ranges), slots_of(F, r.L), p.V, p.total_tiles,
+                                 bwd_items(p, r.capacity), p.ts, st, p.bppt,
+                                 at<T>(F, r.L.T_final), at<uint32_t>(F, r.L.n_contrib), sv, dL,
+                                 dLf, grad2d, work, stream));
+  R4D_TIMED(kPreprocessBwd, launch_preprocess_bwd<T>(g, slots_of(F, r.L), p.V, st, grad2d,
+                                                     nc == 11, out, stream));
   return R4D_OK;
 }
 
 size_t bwd_block_bytes(const Plan& p, uint64_t capacity) {
-  return align256(size_t(p.V) * 9 * size_t(p.n) * 8) +
+  return align256(size_t(p.V) * grad_comps(p, true) * size_t(p.n) * 8) +
          align256(raster_bwd_work_bytes(p.total_tiles, bwd_items(p, capacity)));
 }
 
@@ -737,7 +768,7 @@ r4d_status check_gaussians(r4d_ctx* ctx, const GaussPtrs<T>& g) {
 // ---- plain (per-view / fused) forward: allocates, runs sized, records done
 template <typename T>
 r4d_status run_sized(r4d_ctx* ctx, const GaussPtrs<T>& g, const Plan& p, T* images,
-                     const SettingsDev& st, bool timed, hipStream_t stream,
+                     T* flow_images, const SettingsDev& st, bool timed, hipStream_t stream,
                      std::unique_ptr<RunState>& out) {
   auto r = std::make_unique<RunState>();
   struct Guard {
@@ -755,7 +786,9 @@ r4d_status run_sized(r4d_ctx* ctx, const GaussPtrs<T>& g, const Plan& p, T* imag
   if (!r->fixed)
     return fail(ctx, R4D_ERR_OOM, "device allocation of %zu bytes failed", r->L.fixed_bytes);
   if ((s = upload_meta(ctx, p, r->fixed, r->L, stream)) != R4D_OK) return s;
-  if ((s = enqueue_forward<T>(ctx, g, *r, images, st, true, timed, stream)) != R4D_OK) return s;
+  if ((s = enqueue_forward<T>(ctx, g, *r, images, flow_images, st, true, timed, stream)) !=
+      R4D_OK)
+    return s;
   if ((s = finish_run(ctx, *r, stream)) != R4D_OK) return s;
   guard.ok = true;
   out = std::move(r);
@@ -763,12 +796,13 @@ r4d_status run_sized(r4d_ctx* ctx, const GaussPtrs<T>& g, const Plan& p, T* imag
 }
 
 template <typename T>
-std::string fwd_graph_key(const GaussPtrs<T>& g, const void* images, const r4d_view* views,
-                          int V, const r4d_settings& s) {
+std::string fwd_graph_key(const GaussPtrs<T>& g, const void* images, const void* flows,
+                          const r4d_view* views, int V, const r4d_settings& s) {
   char buf[512];
-  snprintf(buf, sizeof(buf), "%zu|%d|%d|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%a|%a|%a|%a|%a|%a|%a|",
+  snprintf(buf, sizeof(buf), "%zu|%d|%d|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%a|%a|%a|%a|%a|%a|%a|",
            sizeof(T), g.n, g.deg, (const void*)g.means, (const void*)g.log_scales,
-           (const void*)g.rotors, (const void*)g.opacity, (const void*)g.sh, images, s.tile_size,
+           (const void*)g.rotors, (const void*)g.opacity, (const void*)g.sh, images, flows,
+           s.tile_size,
            s.fwd_pixels_per_thread, s.bwd_pixels_per_thread, s.sort_items, s.near_plane,
            s.time_cull, s.extent_sigma, s.alpha_min, s.alpha_max, s.T_min, s.dilation,
            s.guard_band);
@@ -778,12 +812,12 @@ std::string fwd_graph_key(const GaussPtrs<T>& g, const void* images, const r4d_v
 // ---- graph forward
 template <typename T>
 r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int V,
-                     const r4d_settings& s, T* images, const SettingsDev& st, hipStream_t stream,
-                     GraphEntry** entry_out) {
-  const std::string key = fwd_graph_key(g, images, views, V, s);
+                     const r4d_settings& s, T* images, T* flow_images, const SettingsDev& st,
+                     hipStream_t stream, GraphEntry** entry_out) {
+  const std::string key = fwd_graph_key(g, images, flow_images, views, V, s);
   auto it = ctx->graphs.find(key);
   GraphEntry* e = it == ctx->graphs.end() ? nullptr : it->second.get();
-  const Plan p = make_plan(views, V, uint32_t(g.n), g.deg, s, sizeof(T));
+  const Plan p = make_plan(views, V, uint32_t(g.n), g.deg, s, sizeof(T), flow_images != nullptr);
   if (e && e->run.done) {
     // an overflow of an earlier replay grows the capacity (checked without waiting)
     if (hipEventQuery(e->run.done) == hipSuccess) {
@@ -812,7 +846,7 @@ r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
     } else {
       // size from one exact (fused) run
       std::unique_ptr<RunState> probe;
-      r4d_status st_ = run_sized<T>(ctx, g, p, images, st, false, stream, probe);
+      r4d_status st_ = run_sized<T>(ctx, g, p, images, flow_images, st, false, stream, probe);
       if (st_ != R4D_OK) return st_;
       cap = probe->capacity + probe->capacity / 4 + uint64_t(V) * kSegAlign;
       R4D_HIP(hipEventSynchronize(probe->done));
@@ -837,7 +871,7 @@ r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
     // capture on the context's own stream (the caller's may be the null stream)
     hipStream_t cs = ctx->capture_stream;
     R4D_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    r4d_status cst = enqueue_forward<T>(ctx, g, e->run, images, st, false, false, cs);
+    r4d_status cst = enqueue_forward<T>(ctx, g, e->run, images, flow_images, st, false, false, cs);
     hipGraph_t graph = nullptr;
     const hipError_t end = hipStreamEndCapture(cs, &graph);
     if (cst != R4D_OK) {
@@ -909,7 +943,7 @@ r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, 
           if (hipEventRecord(e0, stream) != hipSuccess) result = R4D_ERR_HIP;
         }
         std::unique_ptr<RunState> r;
-        result = run_sized<T>(ctx, g, p, images, st, false, stream, r);
+        result = run_sized<T>(ctx, g, p, images, nullptr, st, false, stream, r);
         if (result != R4D_OK) break;
         uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(p, r->capacity)));
         if (!bb) {
@@ -917,7 +951,7 @@ r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, 
           result = fail(ctx, R4D_ERR_OOM, "autotuner buffers");
           break;
         }
-        result = enqueue_backward<T>(ctx, g, *r, dl, bb, st, out, false, stream);
+        result = enqueue_backward<T>(ctx, g, *r, dl, nullptr, bb, st, out, false, stream);
         (void)hipStreamSynchronize(stream);
         ctx_free(ctx, bb);
         release_run(ctx, r.get());
@@ -947,9 +981,11 @@ r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, 
   return R4D_OK;
 }
 
+// flows: null for a colour render, else the flow images ([2][H][W] per view,
+// views back to back).
 template <typename T>
 r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int n_views,
-                        const r4d_settings* settings, T* images, r4d_saved** saved_out,
+                        const r4d_settings* settings, T* images, T* flows, r4d_saved** saved_out,
                         hipStream_t stream) {
   if (saved_out) *saved_out = nullptr;
   if (!views || n_views < 1 || n_views > kMaxViews || !images || !valid_settings(settings))
@@ -974,37 +1010,42 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
   auto saved = std::make_unique<r4d_saved>();
   saved->ctx = ctx;
   saved->f64 = sizeof(T) == 8;
+  saved->flow = flows != nullptr;
   saved->n = g.n;
   saved->deg = g.deg;
   saved->settings = rs;
   saved->views.assign(views, views + n_views);
   const bool timed = ctx->timing && rs.mode != R4D_MODE_GRAPH;
+  const bool flow = flows != nullptr;
   if (rs.mode == R4D_MODE_GRAPH) {
     GraphEntry* e = nullptr;
-    if ((s = run_graph<T>(ctx, g, views, n_views, rs, images, st, stream, &e)) != R4D_OK)
+    if ((s = run_graph<T>(ctx, g, views, n_views, rs, images, flows, st, stream, &e)) != R4D_OK)
       return s;
     saved->graph = e;
     saved->generation = e->generation;
     for (int v = 0; v < n_views; ++v) saved->where.push_back({0, v});
   } else if (rs.mode == R4D_MODE_FUSED) {
-    Plan p = make_plan(views, n_views, uint32_t(g.n), g.deg, rs, sizeof(T));
-    p.count_evals = timed;
+    Plan p = make_plan(views, n_views, uint32_t(g.n), g.deg, rs, sizeof(T), flow);
+    p.count_evals = timed && !flow;
     std::unique_ptr<RunState> r;
-    if ((s = run_sized<T>(ctx, g, p, images, st, timed, stream, r)) != R4D_OK) return s;
+    if ((s = run_sized<T>(ctx, g, p, images, flows, st, timed, stream, r)) != R4D_OK) return s;
     saved->runs.push_back(std::move(r));
     for (int v = 0; v < n_views; ++v) saved->where.push_back({0, v});
   } else {
-    size_t off = 0;
+    size_t off = 0, foff = 0;
     for (int v = 0; v < n_views; ++v) {
-      Plan p = make_plan(views + v, 1, uint32_t(g.n), g.deg, rs, sizeof(T));
-      p.count_evals = timed;
+      Plan p = make_plan(views + v, 1, uint32_t(g.n), g.deg, rs, sizeof(T), flow);
+      p.count_evals = timed && !flow;
       std::unique_ptr<RunState> r;
-      if ((s = run_sized<T>(ctx, g, p, images + off, st, timed, stream, r)) != R4D_OK) {
+      if ((s = run_sized<T>(ctx, g, p, images + off, flow ? flows + foff : nullptr, st, timed,
+                            stream, r)) != R4D_OK) {
         for (auto& rr : saved->runs) release_run(ctx, rr.get());
         return s;
       }
       r->image_offset = off;
+      r->flow_offset = foff;
       off += 3 * size_t(views[v].width) * size_t(views[v].height);
+      foff += 2 * size_t(views[v].width) * size_t(views[v].height);
       saved->runs.push_back(std::move(r));
       saved->where.push_back({v, 0});
     }
@@ -1027,10 +1068,11 @@ bool same_view(const r4d_view& a, const r4d_view& b) {
          a.fx == b.fx && a.fy == b.fy && a.cx == b.cx && a.cy == b.cy;
 }
 
+// dLf: the flow images' gradient (null: none; needs a flow render otherwise).
 template <typename T>
 r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
                          int n_views, const r4d_settings* settings, const r4d_saved* saved,
-                         const T* dL, const GradPtrs<T>& out, hipStream_t stream) {
+                         const T* dL, const T* dLf, const GradPtrs<T>& out, hipStream_t stream) {
   if (!views || n_views < 1 || !dL || !valid_settings(settings) || !saved)
     return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, gradients, settings or saved state");
   r4d_status s = check_gaussians(ctx, g);
@@ -1047,6 +1089,8 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
       return fail(ctx, R4D_ERR_STATE, "view %d differs from the forward call", i);
   if (saved->graph && saved->generation != saved->graph->generation)
     return fail(ctx, R4D_ERR_STATE, "a later graph forward of this shape reused the buffers");
+  if (dLf && !saved->flow)
+    return fail(ctx, R4D_ERR_STATE, "flow gradients given for a forward without flow");
   R4D_HIP(hipSetDevice(ctx->device));
   if (g.n == 0) return R4D_OK;
   const SettingsDev st = make_settings(saved->settings);
@@ -1054,8 +1098,8 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   if (saved->graph) {
     GraphEntry* e = saved->graph;
     char buf[256];
-    snprintf(buf, sizeof(buf), "%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p", (const void*)dL,
-             (const void*)out.means, (const void*)out.log_scales, (const void*)out.rotors,
+    snprintf(buf, sizeof(buf), "%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p", (const void*)dL,
+             (const void*)dLf, (const void*)out.means, (const void*)out.log_scales, (const void*)out.rotors,
              (const void*)out.opacity, (const void*)out.sh, (const void*)g.means,
              (const void*)g.log_scales, (const void*)g.rotors, (const void*)g.opacity,
              (const void*)g.sh, (const void*)e->run.fixed);
@@ -1071,7 +1115,8 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
       }
       hipStream_t cs = ctx->capture_stream;
       R4D_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      r4d_status cst = enqueue_backward<T>(ctx, g, e->run, dL, e->bwd_block, st, out, false, cs);
+      r4d_status cst =
+          enqueue_backward<T>(ctx, g, e->run, dL, dLf, e->bwd_block, st, out, false, cs);
       hipGraph_t graph = nullptr;
       const hipError_t end = hipStreamEndCapture(cs, &graph);
       if (cst != R4D_OK) {
@@ -1091,7 +1136,8 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
     RunState& r = *saved->runs[0];
     uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan, r.capacity)));
     if (!bb) return fail(ctx, R4D_ERR_OOM, "backward buffers");
-    s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, bb, st, out, timed, stream);
+    s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, dLf ? dLf + r.flow_offset : nullptr,
+                            bb, st, out, timed, stream);
     ctx_free(ctx, bb);
     return s;
   }
@@ -1109,8 +1155,8 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
       s = fail(ctx, R4D_ERR_OOM, "backward buffers");
       break;
     }
-    s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, bb, st, ri == 0 ? out : gt, timed,
-                            stream);
+    s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, dLf ? dLf + r.flow_offset : nullptr,
+                            bb, st, ri == 0 ? out : gt, timed, stream);
     ctx_free(ctx, bb);
     if (s == R4D_OK && ri > 0) {
       const hipError_t e = add_grads<T>(out, tmp, n, k3, stream);
@@ -1227,8 +1273,27 @@ r4d_status r4d_render_forward(r4d_ctx* ctx, const r4d_gaussians* g, const r4d_vi
                               int n_views, const r4d_settings* settings, float* images,
                               r4d_saved** saved, void* stream) {
   if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
-  return forward_impl<float>(ctx, gauss_of(g), views, n_views, settings, images, saved,
+  return forward_impl<float>(ctx, gauss_of(g), views, n_views, settings, images, nullptr, saved,
                              static_cast<hipStream_t>(stream));
+}
+
+r4d_status r4d_render_forward_flow(r4d_ctx* ctx, const r4d_gaussians* g, const r4d_view* views,
+                                   int n_views, const r4d_settings* settings, float* images,
+                                   float* flows, r4d_saved** saved, void* stream) {
+  if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  if (!flows) return fail(ctx, R4D_ERR_INVALID_ARG, "null flow images");
+  return forward_impl<float>(ctx, gauss_of(g), views, n_views, settings, images, flows, saved,
+                             static_cast<hipStream_t>(stream));
+}
+
+r4d_status r4d_render_forward_flow_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
+                                       const r4d_view* views, int n_views,
+                                       const r4d_settings* settings, double* images,
+                                       double* flows, r4d_saved** saved, void* stream) {
+  if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  if (!flows) return fail(ctx, R4D_ERR_INVALID_ARG, "null flow images");
+  return forward_impl<double>(ctx, gauss_of(g), views, n_views, settings, images, flows, saved,
+                              static_cast<hipStream_t>(stream));
 }
 
 r4d_status r4d_render_forward_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
@@ -1236,7 +1301,7 @@ r4d_status r4d_render_forward_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
                                   const r4d_settings* settings, double* images,
                                   r4d_saved** saved, void* stream) {
   if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
-  return forward_impl<double>(ctx, gauss_of(g), views, n_views, settings, images, saved,
+  return forward_impl<double>(ctx, gauss_of(g), views, n_views, settings, images, nullptr, saved,
                               static_cast<hipStream_t>(stream));
 }
 
@@ -1247,8 +1312,33 @@ r4d_status r4d_render_backward(r4d_ctx* ctx, const r4d_gaussians* g, const r4d_v
   if (!ctx || !g || !out)
     return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
   const GradPtrs<float> o{out->means, out->log_scales, out->rotors, out->opacity, out->sh};
-  return backward_impl<float>(ctx, gauss_of(g), views, n_views, settings, saved, dL_dimages, o,
-                              static_cast<hipStream_t>(stream));
+  return backward_impl<float>(ctx, gauss_of(g), views, n_views, settings, saved, dL_dimages,
+                              nullptr, o, static_cast<hipStream_t>(stream));
+}
+
+r4d_status r4d_render_backward_flow(r4d_ctx* ctx, const r4d_gaussians* g, const r4d_view* views,
+                                    int n_views, const r4d_settings* settings,
+                                    const r4d_saved* saved, const float* dL_dimages,
+                                    const float* dL_dflows, r4d_grads* out, void* stream) {
+  if (!ctx || !g || !out)
+    return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  if (!dL_dflows) return fail(ctx, R4D_ERR_INVALID_ARG, "null flow gradient");
+  const GradPtrs<float> o{out->means, out->log_scales, out->rotors, out->opacity, out->sh};
+  return backward_impl<float>(ctx, gauss_of(g), views, n_views, settings, saved, dL_dimages,
+                              dL_dflows, o, static_cast<hipStream_t>(stream));
+}
+
+r4d_status r4d_render_backward_flow_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
+                                        const r4d_view* views, int n_views,
+                                        const r4d_settings* settings, const r4d_saved* saved,
+                                        const double* dL_dimages, const double* dL_dflows,
+                                        r4d_grads_f64* out, void* stream) {
+  if (!ctx || !g || !out)
+    return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  if (!dL_dflows) return fail(ctx, R4D_ERR_INVALID_ARG, "null flow gradient");
+  const GradPtrs<double> o{out->means, out->log_scales, out->rotors, out->opacity, out->sh};
+  return backward_impl<double>(ctx, gauss_of(g), views, n_views, settings, saved, dL_dimages,
+                               dL_dflows, o, static_cast<hipStream_t>(stream));
 }
 
 r4d_status r4d_render_backward_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
@@ -1258,8 +1348,8 @@ r4d_status r4d_render_backward_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
   if (!ctx || !g || !out)
     return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
   const GradPtrs<double> o{out->means, out->log_scales, out->rotors, out->opacity, out->sh};
-  return backward_impl<double>(ctx, gauss_of(g), views, n_views, settings, saved, dL_dimages, o,
-                               static_cast<hipStream_t>(stream));
+  return backward_impl<double>(ctx, gauss_of(g), views, n_views, settings, saved, dL_dimages,
+                               nullptr, o, static_cast<hipStream_t>(stream));
 }
 
 void r4d_saved_release(r4d_saved* saved) {
@@ -1384,6 +1474,11 @@ r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* ds
     }
     case R4D_BUF_TFINAL: src = F + r->L.T_final + size_t(sl.pix_base) * scal; need = hw * scal; break;
     case R4D_BUF_NCONTRIB: src = F + r->L.n_contrib + size_t(sl.pix_base) * 4; need = hw * 4; break;
+    case R4D_BUF_FLOW:
+      if (!p.flow) return fail(ctx, R4D_ERR_STATE, "the forward rendered no flow");
+      src = F + r->L.flows + size_t(vi) * n * 2 * scal;
+      need = n * 2 * scal;
+      break;
     case R4D_BUF_NEVAL:
       if (!p.count_evals) return fail(ctx, R4D_ERR_STATE, "evaluation counts need timing enabled");
       src = F + r->L.n_eval + size_t(sl.pix_base) * 4;

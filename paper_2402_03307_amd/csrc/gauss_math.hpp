@@ -17,7 +17,9 @@
 //   view transform, near-plane drop, EWA projection Sigma_2D = J Wv Sigma Wv^T J^T
 //     + dilation I (Sec. 3.1), conic = Sigma_2D^-1;
 //   SH colour rgb = max(0, sum Y_lm(d) c_lm + 0.5), d the unit direction from the
-//     camera centre to mu(t) (Sec. 3.1).
+//     camera centre to mu(t) (Sec. 3.1);
+//   2D flow: the sliced mean moves with speed V / W (Sec. 3.2.2); its projection
+//     is the time derivative of the pinhole mean, in pixels per unit of t.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,6 +56,12 @@ struct alignas(sizeof(T) * 4) Rec {
   T mx, my, ca, cb;
   T cc, o, depth, qmax;
   T r, g, b, pad1;
+};
+
+// A pair of scalars stored together (a Gaussian's 2D flow, a pixel's flow state).
+template <typename T>
+struct alignas(sizeof(T) * 2) Vec2 {
+  T x, y;
 };
 
 template <typename T> R4D_HD T r4d_sqrt(T x);
@@ -98,6 +106,8 @@ struct Fwd {
   // colour
   T dir[3], inv_nd, d[3];
   T raw[3], rgb[3];
+  // camera-space speed of the sliced mean and its projection
+  T vc[3], flow[2];
   bool valid;
 };
 
@@ -486,6 +496,13 @@ R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacit
   f.conic[2] = f.A * idet;
   f.mean2[0] = fx * f.p[0] * f.ipz + T(v.cx);
   f.mean2[1] = fy * f.p[1] * f.ipz + T(v.cy);
+  // flow: d/dt of (fx x / z, fy y / z) with d p / dt = Wv vel
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    f.vc[i] = T(v.M[3 * i]) * f.vel[0] + T(v.M[3 * i + 1]) * f.vel[1] +
+              T(v.M[3 * i + 2]) * f.vel[2];
+  f.flow[0] = fx * f.ipz * (f.vc[0] - f.p[0] * f.ipz * f.vc[2]);
+  f.flow[1] = fy * f.ipz * (f.vc[1] - f.p[1] * f.ipz * f.vc[2]);
   // colour
 #pragma unroll
   for (int i = 0; i < 3; ++i) f.dir[i] = mu[i] - T(v.cam[i]);
@@ -509,17 +526,17 @@ R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacit
 // Gradients of one Gaussian.  In: dL/d(mean2 x, y), the gradient H of L with
 // respect to the symmetric 2x2 matrix Sigma_2D (entries (0,0), (0,1) = (1,0),
 // (1,1); a change dS of the matrix changes L by sum_ij H_ij dS_ij), dL/d(o_t),
-// dL/d(rgb).  Out (added): mu4[4], ls[4], rot[8], opacity, and the SH column via
-// gsh (stride gsh_stride).
+// dL/d(rgb), and with FLOW dL/d(flow x, y) in g2[9], g2[10].  Out (added):
+// mu4[4], ls[4], rot[8], opacity, and the SH column via gsh (stride gsh_stride).
 //
 // The rasteriser hands over the Sigma_2D gradient rather than the conic one: for
 // a long thin footprint the conic gradient is dominated by a component along the
 // major axis that Sigma_2D = conic^-1 almost ignores, so forming -Q G Q from it
 // in single precision cancels badly; the rasteriser instead sums the well-scaled
 // per-pixel terms (Q d)(Q d)^T directly.
-template <typename T, typename ShT>
+template <typename T, typename ShT, bool FLOW = false>
 R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int deg,
-                         const ViewDev& v, const T g2[9], T gmu4[4], T gls[4], T grot[8],
+                         const ViewDev& v, const T* g2, T gmu4[4], T gls[4], T grot[8],
                          T& gop, T* gsh, long gsh_stride) {
   if (!f.valid) return;
   const T gm_x = g2[0], gm_y = g2[1];
@@ -615,12 +632,28 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int de
   gp[0] += gm_x * fx * ipz;
   gp[1] += gm_y * fy * ipz;
   gp[2] += -(gm_x * fx * f.p[0] + gm_y * fy * f.p[1]) * ipz2;
+  // flow = (fx (vx/z - x vz/z^2), fy (vy/z - y vz/z^2)), vc = Wv vel
+  T gvel[3] = {0, 0, 0};
+  if (FLOW) {
+    const T hx = g2[9] * fx, hy = g2[10] * fy;
+    const T ipz3 = ipz2 * ipz;
+    const T gvc0 = hx * ipz, gvc1 = hy * ipz;
+    const T gvc2 = -(hx * f.p[0] + hy * f.p[1]) * ipz2;
+    gp[0] += -hx * f.vc[2] * ipz2;
+    gp[1] += -hy * f.vc[2] * ipz2;
+    gp[2] += hx * (2 * f.p[0] * f.vc[2] * ipz3 - f.vc[0] * ipz2) +
+             hy * (2 * f.p[1] * f.vc[2] * ipz3 - f.vc[1] * ipz2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      gvel[c] = T(v.M[c]) * gvc0 + T(v.M[3 + c]) * gvc1 + T(v.M[6 + c]) * gvc2;
+  }
   // p = Wv mu3 + tw
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     gmu3[c] += T(v.M[c]) * gp[0] + T(v.M[3 + c]) * gp[1] + T(v.M[6 + c]) * gp[2];
   // ---- temporal slice
-  // mu3 = mu_xyz + dt V/W ; S3 = U - V V^T / W ; o_t = o exp(-dt^2/(2W))
+  // mu3 = mu_xyz + dt vel, vel = V/W (also the flow's speed) ; S3 = U - V V^T / W ;
+  // o_t = o exp(-dt^2/(2W))
   T gV[3], gW = 0, gdt = 0;
   {
     // gS3 holds the symmetric full-matrix gradient Tm^T H Tm (entry (i,j) and
@@ -633,10 +666,15 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int de
     for (int i = 0; i < 3; ++i)
       GV[i] = Gs[3 * i] * f.V[0] + Gs[3 * i + 1] * f.V[1] + Gs[3 * i + 2] * f.V[2];
     const T VGV = f.V[0] * GV[0] + f.V[1] * GV[1] + f.V[2] * GV[2];
+    // dL/dvel = dt dL/dmu3 + (flow part)
+    T gv[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) gV[i] = -2 * GV[i] * f.invW + f.dt * gmu3[i] * f.invW;
+    for (int i = 0; i < 3; ++i) gv[i] = f.dt * gmu3[i] + gvel[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gV[i] = -2 * GV[i] * f.invW + gv[i] * f.invW;
     const T vdot = f.vel[0] * gmu3[0] + f.vel[1] * gmu3[1] + f.vel[2] * gmu3[2];
-    gW += VGV * f.invW * f.invW - f.dt * vdot * f.invW;
+    const T vgv = f.vel[0] * gv[0] + f.vel[1] * gv[1] + f.vel[2] * gv[2];
+    gW += VGV * f.invW * f.invW - vgv * f.invW;
     gW += go_t * f.o_t * T(0.5) * f.dt * f.dt * f.invW * f.invW;
     gdt += vdot - go_t * f.o_t * f.dt * f.invW;
   }

@@ -3,10 +3,11 @@
 // survive the time / near-plane culls.
 //
 // Forward writes the projected record consumed by the rasteriser, the tiles'
-// bounding box, the tile count and the depth sort key.  Backward recomputes the
-// forward intermediates from the parameters (nothing per Gaussian is stored
-// between the passes except the 9 screen-space gradients) and chains them
-// back to the parameters.
+// bounding box, the tile count and the depth sort key (and, for a flow render,
+// the Gaussian's 2D flow).  Backward recomputes the forward intermediates from
+// the parameters (nothing per Gaussian is stored between the passes except the
+// 9, or with flow 11, screen-space gradients) and chains them back to the
+// parameters.
 #include <hip/hip_runtime.h>
 
 #include "r4d_internal.hpp"
@@ -56,8 +57,9 @@ __device__ __forceinline__ bool record_box(const Rec<T>& rec, const ViewDev& v, 
 template <typename T, int DEG>
 __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     GaussPtrs<T> g, const ViewSlot* __restrict__ slots, SettingsDev st, uint32_t n_pad,
-    Rec<T>* __restrict__ recs, Rect16* __restrict__ rects, uint32_t* __restrict__ tiles_touched,
-    uint32_t* __restrict__ depth_keys, ulonglong2* __restrict__ block_totals) {
+    Rec<T>* __restrict__ recs, Vec2<T>* __restrict__ flows, Rect16* __restrict__ rects,
+    uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_keys,
+    ulonglong2* __restrict__ block_totals) {
   __shared__ unsigned long long s_tot[2][kBlock / 64];
   __shared__ uint32_t s_cnt[kBlock];
   __shared__ int s_x0[kBlock], s_x1[kBlock], s_y0[kBlock], s_y1[kBlock];
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
       rec.pad1 = T(0);
       if (record_box(rec, v, sh, bx, sg)) {
         recs[row + i] = rec;
+        if (flows) flows[row + i] = Vec2<T>{f.flow[0], f.flow[1]};
         depth = float(f.p[2]);
       } else {
         bx = {0, 0, 0, 0};
@@ -250,13 +253,14 @@ __global__ __launch_bounds__(kBlock) void compact_keys_kernel(
 // With one render the SH coefficients are loaded once into registers; with
 // several they are re-read from memory (cached) in every render, which keeps
 // the register count of the render loop at that of the single-render case.
-template <typename T, int DEG, bool MULTI>
+template <typename T, int DEG, bool MULTI, bool FLOW>
 __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
                                                                 const ViewSlot* __restrict__ slots,
                                                                 int n_views, SettingsDev st,
                                                                 const double* __restrict__ grad2d,
                                                                 GradPtrs<T> out) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr int NC = FLOW ? 11 : 9;
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -266,11 +270,11 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
   for (int j = 0; j < 3 * K; ++j) gsh[j] = T(0);
   const int nv = MULTI ? n_views : 1;
   for (int vi = 0; vi < nv; ++vi) {
-    const double* g2v = grad2d + size_t(vi) * 9 * size_t(n);
-    T g2[9];
+    const double* g2v = grad2d + size_t(vi) * NC * size_t(n);
+    T g2[NC];
     bool any = false;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
+    for (int c = 0; c < NC; ++c) {
       g2[c] = T(g2v[c * (long)n + i]);
       any |= g2[c] != T(0);
     }
@@ -287,13 +291,13 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
     Fwd<T> f;
     if (MULTI) {
       gaussian_fwd<T>(mu, ls, rot, g.opacity[i], g.sh + i, (long)n, DEG, v, st, f);
-      gaussian_bwd<T>(f, g.sh + i, (long)n, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
+      gaussian_bwd<T, T, FLOW>(f, g.sh + i, (long)n, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
     } else {
       T shl[3 * K];
 #pragma unroll
       for (int j = 0; j < 3 * K; ++j) shl[j] = g.sh[j * (long)n + i];
       gaussian_fwd<T>(mu, ls, rot, g.opacity[i], shl, 1, DEG, v, st, f);
-      gaussian_bwd<T>(f, shl, 1, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
+      gaussian_bwd<T, T, FLOW>(f, shl, 1, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
     }
   }
 #pragma unroll
@@ -322,17 +326,17 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
 template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
-                                 Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
-                                 unsigned long long* totals, uint32_t* vis_keys,
-                                 uint32_t* vis_index, SegTable* dseg, void* temp,
-                                 hipStream_t stream) {
+                                 Vec2<T>* flows, Rect16* rects, uint32_t* tiles_touched,
+                                 uint32_t* depth_keys, unsigned long long* totals,
+                                 uint32_t* vis_keys, uint32_t* vis_index, SegTable* dseg,
+                                 void* temp, hipStream_t stream) {
   if (g.n <= 0 || n_views <= 0) return hipSuccess;
   const uint32_t blocks = uint32_t((g.n + kBlock - 1) / kBlock);
   const dim3 grid(blocks, uint32_t(n_views));
   ulonglong2* block_totals = static_cast<ulonglong2*>(temp);
   uint32_t* vis_prefix = reinterpret_cast<uint32_t*>(block_totals + size_t(blocks) * n_views);
-  R4D_DEG_DISPATCH(preprocess_fwd_kernel, grid, g, slots, st, n_pad, recs, rects, tiles_touched,
-                   depth_keys, block_totals)
+  R4D_DEG_DISPATCH(preprocess_fwd_kernel, grid, g, slots, st, n_pad, recs, flows, rects,
+                   tiles_touched, depth_keys, block_totals)
   hipLaunchKernelGGL(totals_kernel, dim3(uint32_t(n_views)), dim3(kBlock), 0, stream, block_totals,
                      blocks, totals, vis_prefix, dseg);
   hipLaunchKernelGGL(compact_keys_kernel, grid, dim3(kBlock), 0, stream, depth_keys, uint32_t(g.n),
@@ -347,22 +351,28 @@ size_t preprocess_temp_bytes(uint32_t n, int n_views) {
 
 template <typename T>
 hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
-                                 const SettingsDev& st, const double* grad2d,
+                                 const SettingsDev& st, const double* grad2d, bool flow,
                                  const GradPtrs<T>& out, hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
   const dim3 grid((g.n + kBlock - 1) / kBlock);
-#define R4D_BWD_DISPATCH(MULTI)                                                              \
+#define R4D_BWD_DISPATCH(MULTI, FLOW)                                                        \
   switch (g.deg) {                                                                           \
-    case 0: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 0, MULTI>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
-    case 1: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 1, MULTI>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
-    case 2: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 2, MULTI>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
-    case 3: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 3, MULTI>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 0: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 0, MULTI, FLOW>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 1: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 1, MULTI, FLOW>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 2: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 2, MULTI, FLOW>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 3: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 3, MULTI, FLOW>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
     default: return hipErrorInvalidValue;                                                    \
   }
-  if (n_views > 1) {
-    R4D_BWD_DISPATCH(true)
+  if (flow) {
+    if (n_views > 1) {
+      R4D_BWD_DISPATCH(true, true)
+    } else {
+      R4D_BWD_DISPATCH(false, true)
+    }
+  } else if (n_views > 1) {
+    R4D_BWD_DISPATCH(true, false)
   } else {
-    R4D_BWD_DISPATCH(false)
+    R4D_BWD_DISPATCH(false, false)
   }
 #undef R4D_BWD_DISPATCH
   return hipGetLastError();
@@ -372,12 +382,12 @@ hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
 
 #define R4D_INST(T)                                                                           \
   template hipError_t launch_preprocess_fwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
-                                               const SettingsDev&, uint32_t, Rec<T>*, Rect16*, \
-                                               uint32_t*, uint32_t*, unsigned long long*,      \
-                                               uint32_t*, uint32_t*, SegTable*, void*,         \
-                                               hipStream_t);                                   \
+                                               const SettingsDev&, uint32_t, Rec<T>*, Vec2<T>*, \
+                                               Rect16*, uint32_t*, uint32_t*,                  \
+                                               unsigned long long*, uint32_t*, uint32_t*,      \
+                                               SegTable*, void*, hipStream_t);                 \
   template hipError_t launch_preprocess_bwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
-                                               const SettingsDev&, const double*,              \
+                                               const SettingsDev&, const double*, bool,        \
                                                const GradPtrs<T>&, hipStream_t);
 R4D_INST(float)
 R4D_INST(double)

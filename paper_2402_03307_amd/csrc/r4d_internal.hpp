@@ -61,22 +61,24 @@ struct SegTable {
 // visible); totals[2v] = visible Gaussians, totals[2v+1] = tile entries.  The
 // visible Gaussians' depth keys and indices are also written compacted, in
 // index order, to vis_keys / vis_index at [v * n_pad + 0 .. totals[2v]), and
-// dseg->len[v] = totals[2v] (the depth sort sorts only them).  temp:
+// dseg->len[v] = totals[2v] (the depth sort sorts only them).  flows
+// (nullable): [v][n] 2D flow of each visible Gaussian.  temp:
 // preprocess_temp_bytes(n, n_views).
 size_t preprocess_temp_bytes(uint32_t n, int n_views);
 template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, uint32_t n_pad, Rec<T>* recs,
-                                 Rect16* rects, uint32_t* tiles_touched, uint32_t* depth_keys,
-                                 unsigned long long* totals, uint32_t* vis_keys,
-                                 uint32_t* vis_index, SegTable* dseg, void* temp,
-                                 hipStream_t stream);
+                                 Vec2<T>* flows, Rect16* rects, uint32_t* tiles_touched,
+                                 uint32_t* depth_keys, unsigned long long* totals,
+                                 uint32_t* vis_keys, uint32_t* vis_index, SegTable* dseg,
+                                 void* temp, hipStream_t stream);
 
-// grad2d: [V][9][n] double (mean2 x, y, Sigma_2D (0,0), (0,1), (1,1), opacity_t,
-// r, g, b).  Writes the parameter gradients summed over the renders.
+// grad2d: [V][C][n] double, C = 9 (mean2 x, y, Sigma_2D (0,0), (0,1), (1,1),
+// opacity_t, r, g, b) or, with flow, 11 (then flow x, y).  Writes the parameter
+// gradients summed over the renders.
 template <typename T>
 hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
-                                 const SettingsDev& st, const double* grad2d,
+                                 const SettingsDev& st, const double* grad2d, bool flow,
                                  const GradPtrs<T>& out, hipStream_t stream);
 
 // ---- binning and sorting
@@ -187,6 +189,10 @@ struct RasterSaved {
   Ck<T>* ck;       // boundary states
   T* img;          // final colour per pixel, laid out like the images
   uint32_t* walk;  // per global tile
+  // flow renders: boundary flow sums (slots like ck) and the final flow per
+  // pixel, laid out like the flow images; null otherwise
+  Vec2<T>* ckf;
+  T* flow;
 };
 
 // (tile size, pixels per lane) pairs the rasteriser is compiled for.
@@ -196,27 +202,32 @@ int raster_default_ppt(int tile_size, bool backward);
 // Persistent launch over all tiles of all renders; tickets: 1 word, zeroed.
 // recs: [V][n]; image: [3][pixels of render v] at 3 * pix_base; T_final,
 // n_contrib, n_eval (nullable) per pixel at pix_base; sv: what the backward's
-// segment walks need (see kSegment).
+// segment walks need (see kSegment).  A flow render (flows: [V][n] per-Gaussian
+// 2D flow, not null) also composites the flow into flow_image ([2][pixels] at
+// 2 * pix_base, background 0) and fills sv.ckf and sv.flow; it counts no
+// evaluations (n_eval must be null).
 template <typename T>
-hipError_t launch_raster_fwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
-                             const uint2* ranges, const ViewSlot* slots, int n_views,
-                             uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
-                             T* image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
-                             const RasterSaved<T>& sv, uint32_t* tickets, hipStream_t stream);
+hipError_t launch_raster_fwd(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
+                             const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
+                             int n_views, uint32_t total_tiles, int tile_size,
+                             const SettingsDev& st, int ppt, T* image, T* flow_image, T* T_final,
+                             uint32_t* n_contrib, uint32_t* n_eval, const RasterSaved<T>& sv,
+                             uint32_t* tickets, hipStream_t stream);
 
-// Persistent launch over the (tile, segment) walks.  grad2d: [V][9][n] double
-// accumulators, added to.  max_items: bound on the number of walks
-// (capacity / kSegment + tiles + 1); work: raster_bwd_work_bytes, its first
-// 256 bytes zeroed.
+// Persistent launch over the (tile, segment) walks.  grad2d: [V][C][n] double
+// accumulators, added to, C = 9, or 11 when dL_dflow is given (a flow render's
+// saved state with the flow images' gradient, laid out like them).  max_items:
+// bound on the number of walks (capacity / kSegment + tiles + 1); work:
+// raster_bwd_work_bytes, its first 256 bytes zeroed.
 size_t raster_bwd_work_bytes(uint32_t total_tiles, uint64_t max_items);
 template <typename T>
-hipError_t launch_raster_bwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
-                             const uint2* ranges, const ViewSlot* slots, int n_views,
-                             uint32_t total_tiles, uint64_t max_items, int tile_size,
-                             const SettingsDev& st, int ppt, const T* T_final,
+hipError_t launch_raster_bwd(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
+                             const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
+                             int n_views, uint32_t total_tiles, uint64_t max_items,
+                             int tile_size, const SettingsDev& st, int ppt, const T* T_final,
                              const uint32_t* n_contrib, const RasterSaved<T>& sv,
-                             const T* dL_dimage, double* grad2d, uint32_t* work,
-                             hipStream_t stream);
+                             const T* dL_dimage, const T* dL_dflow, double* grad2d,
+                             uint32_t* work, hipStream_t stream);
 
 // L1 loss (mean absolute difference) and its gradient.  The loss (when `loss`
 // is not null) is summed through per-workgroup partial sums in `partials`

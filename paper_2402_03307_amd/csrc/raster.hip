@@ -13,6 +13,10 @@
 // final T.  The forward stores, per pixel, the final T and the number of list
 // entries up to the last blended one; the backward walks the list back to front
 // from there, recovering T by division by (1 - a).
+//
+// A flow render composites each Gaussian's 2D flow with the same weights as two
+// more channels (background 0): the rendered optical flow of the speed field
+// (Sec. 3.2.2), which the backward differentiates like a colour.
 #include <hip/hip_runtime.h>
 
 #include "r4d_internal.hpp"
@@ -43,7 +47,7 @@ template <typename T>
 struct Staged {
   T mx, my, A, B;
   T C, o, r, g;
-  T b, e_thr, pad1, pad2;
+  T b, e_thr, fu, fv;  // fu, fv: the 2D flow (flow renders; 0 otherwise)
 };
 
 template <typename T> __device__ __forceinline__ T tlog2(T x);
@@ -99,35 +103,38 @@ __device__ __forceinline__ T wave_sum(T x) {
 // Sums over each row of 16 lanes with DPP lane moves (no LDS traffic): pairs
 // (quad_perm 1,0,3,2), quads (quad_perm 2,3,0,1), half rows (row_half_mirror),
 // rows (row_mirror); afterwards every lane of a row holds its row's sums.  The
-// nine reductions advance step by step, so that the DPP moves of one value
-// fill the hazard slots of the others.
+// N reductions advance step by step, so that the DPP moves of one value fill
+// the hazard slots of the others.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float x) {
   const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false);
   return x + __int_as_float(moved);
 }
 
-__device__ __forceinline__ void row_sum9(float (&v)[9]) {
+template <int N>
+__device__ __forceinline__ void row_sums(float (&v)[N]) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0xb1, 0xf>(v[i]);
+  for (int i = 0; i < N; ++i) v[i] = dpp_add<0xb1, 0xf>(v[i]);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x4e, 0xf>(v[i]);
+  for (int i = 0; i < N; ++i) v[i] = dpp_add<0x4e, 0xf>(v[i]);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x141, 0xf>(v[i]);
+  for (int i = 0; i < N; ++i) v[i] = dpp_add<0x141, 0xf>(v[i]);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x140, 0xf>(v[i]);
+  for (int i = 0; i < N; ++i) v[i] = dpp_add<0x140, 0xf>(v[i]);
 }
 
 // Sums over each half wavefront, valid in rows 1 and 3 (lanes 16..31 and
 // 48..63): the row sums, then row 15 -> rows 1, 3 (row_bcast:15).
-__device__ __forceinline__ void half_sum9(float (&v)[9]) {
-  row_sum9(v);
+template <int N>
+__device__ __forceinline__ void half_sums(float (&v)[N]) {
+  row_sums(v);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = dpp_add<0x142, 0xa>(v[i]);
+  for (int i = 0; i < N; ++i) v[i] = dpp_add<0x142, 0xa>(v[i]);
 }
-__device__ __forceinline__ void half_sum9(double (&v)[9]) {
+template <int N>
+__device__ __forceinline__ void half_sums(double (&v)[N]) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int off = 16; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
 }
@@ -153,13 +160,14 @@ struct TileCfg {
 // continues with T = 0, which makes every later contribution zero and every later
 // transmittance test fail, so no per-pixel "done" flag is carried through the
 // loop.  COUNT counts the entries each pixel evaluates (measurement builds only).
-template <typename T, int TS, int PPT, bool COUNT>
+template <typename T, int TS, int PPT, bool COUNT, bool FLOW>
 __device__ __forceinline__ void raster_fwd_tile(
     Staged<T>* s_rec, uint32_t* s_walk, const Rec<T>* __restrict__ recs,
-    const uint32_t* __restrict__ values, const uint2 rg, int tile, uint32_t gtile,
-    const ViewDev& v, const SettingsDev& st, T* __restrict__ image, T* __restrict__ T_final,
-    uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval, Ck<T>* __restrict__ ck,
-    T* __restrict__ img_copy, uint32_t* __restrict__ walk) {
+    const Vec2<T>* __restrict__ flows, const uint32_t* __restrict__ values, const uint2 rg,
+    int tile, uint32_t gtile, const ViewDev& v, const SettingsDev& st, T* __restrict__ image,
+    T* __restrict__ flow_image, T* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
+    uint32_t* __restrict__ n_eval, Ck<T>* __restrict__ ck, Vec2<T>* __restrict__ ckf,
+    T* __restrict__ img_copy, T* __restrict__ flow_copy, uint32_t* __restrict__ walk) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
@@ -170,7 +178,7 @@ __device__ __forceinline__ void raster_fwd_tile(
   const T px = T(x) + T(0.5);
   const T e_min = T(kHalfLog2e) * T(st.ext2);
   const T amin = T(st.alpha_min), amax = T(st.alpha_max), tmin = T(st.T_min);
-  T py[PPT], Tr[PPT], c0[PPT], c1[PPT], c2[PPT];
+  T py[PPT], Tr[PPT], c0[PPT], c1[PPT], c2[PPT], c3[PPT], c4[PPT];
   uint32_t last[PPT], evals[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -178,7 +186,7 @@ __device__ __forceinline__ void raster_fwd_tile(
     py[k] = T(y) + T(0.5);
     // pixels outside the image start finished
     Tr[k] = (x < v.W && y < v.H) ? T(1) : T(0);
-    c0[k] = c1[k] = c2[k] = T(0);
+    c0[k] = c1[k] = c2[k] = c3[k] = c4[k] = T(0);
     last[k] = evals[k] = 0u;
   }
   if (threadIdx.x == 0) *s_walk = 0u;
@@ -188,7 +196,16 @@ __device__ __forceinline__ void raster_fwd_tile(
     for (int k = 0; k < PPT; ++k) lane_done &= !(Tr[k] > T(0));
     if (__syncthreads_count(lane_done) == NT) break;
     const uint32_t i = base + threadIdx.x;
-    if (threadIdx.x < NB && i < rg.y) s_rec[threadIdx.x] = stage(recs[values[i]], e_min, amin);
+    if (threadIdx.x < NB && i < rg.y) {
+      const uint32_t idx = values[i];
+      Staged<T> sr = stage(recs[idx], e_min, amin);
+      if (FLOW) {
+        const Vec2<T> fl = flows[idx];
+        sr.fu = fl.x;
+        sr.fv = fl.y;
+      }
+      s_rec[threadIdx.x] = sr;
+    }
     __syncthreads();
     const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
     const uint32_t jbase = base - rg.x;
@@ -211,6 +228,10 @@ __device__ __forceinline__ void raster_fwd_tile(
           c0[k] = tfma(r.r, w, c0[k]);
           c1[k] = tfma(r.g, w, c1[k]);
           c2[k] = tfma(r.b, w, c2[k]);
+          if (FLOW) {
+            c3[k] = tfma(r.fu, w, c3[k]);
+            c4[k] = tfma(r.fv, w, c4[k]);
+          }
           Tr[k] = blend ? Tn : (stop ? -Tr[k] : Tr[k]);
           last[k] = blend ? jbase + uint32_t(j) + 1u : last[k];
         }
@@ -220,11 +241,12 @@ __device__ __forceinline__ void raster_fwd_tile(
     // independent segment walks (only where the list goes on)
     const uint32_t done_n = jbase + uint32_t(NB);
     if (done_n % kSegment == 0u && base + NB < rg.y) {
-      Ck<T>* cs = ck + size_t(ck_slot(rg.x, gtile, done_n / kSegment)) * (TS * TS);
+      const size_t slot = size_t(ck_slot(rg.x, gtile, done_n / kSegment)) * (TS * TS);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const int pt = (int(threadIdx.x / TS) + k * Cfg::kRowStep) * TS + int(threadIdx.x % TS);
-        cs[pt] = Ck<T>{Tr[k], c0[k], c1[k], c2[k]};
+        ck[slot + pt] = Ck<T>{Tr[k], c0[k], c1[k], c2[k]};
+        if (FLOW) ckf[slot + pt] = Vec2<T>{c3[k], c4[k]};
       }
     }
   }
@@ -245,6 +267,12 @@ __device__ __forceinline__ void raster_fwd_tile(
       img_copy[pix] = o0;
       img_copy[hw + pix] = o1;
       img_copy[2 * hw + pix] = o2;
+      if (FLOW) {
+        flow_image[pix] = c3[k];
+        flow_image[hw + pix] = c4[k];
+        flow_copy[pix] = c3[k];
+        flow_copy[hw + pix] = c4[k];
+      }
       T_final[pix] = Tfin;
       n_contrib[pix] = last[k];
       if (COUNT) n_eval[pix] = evals[k];
@@ -257,27 +285,35 @@ __device__ __forceinline__ void raster_fwd_tile(
   if (threadIdx.x == 0) walk[gtile] = *s_walk;
 }
 
-template <typename T, int TS, int PPT>
+// Screen-space gradient components per Gaussian: 9, and 2 more (flow) for a
+// flow render.
+template <bool FLOW>
+constexpr int kComps = FLOW ? 11 : 9;
+
+template <typename T, int TS, int PPT, bool FLOW>
 struct BwdShared {
   Staged<T> rec[TileCfg<TS, PPT>::kBatch];
   uint32_t idx[TileCfg<TS, PPT>::kBatch];
   // per component, half wavefront and batch slot (one padding slot, so that the
   // two halves' writes fall in different banks)
-  T grad[9][2][TileCfg<TS, PPT>::kBatch + 1];
+  T grad[kComps<FLOW>][2][TileCfg<TS, PPT>::kBatch + 1];
   uint32_t max;
 };
 
-template <typename T, int TS, int PPT>
+template <typename T, int TS, int PPT, bool FLOW>
 __device__ __forceinline__ void raster_bwd_tile(
-    BwdShared<T, TS, PPT>& sh, const Rec<T>* __restrict__ recs,
-    const uint32_t* __restrict__ values, const uint2 rg, int tile, uint32_t gtile, uint32_t seg,
-    uint32_t walk, const ViewDev& v, const SettingsDev& st, const T* __restrict__ T_final,
-    const uint32_t* __restrict__ n_contrib, const T* __restrict__ img_copy,
-    const Ck<T>* __restrict__ ck, const T* __restrict__ dL_dimage, double* __restrict__ grad2d,
+    BwdShared<T, TS, PPT, FLOW>& sh, const Rec<T>* __restrict__ recs,
+    const Vec2<T>* __restrict__ flows, const uint32_t* __restrict__ values, const uint2 rg,
+    int tile, uint32_t gtile, uint32_t seg, uint32_t walk, const ViewDev& v,
+    const SettingsDev& st, const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
+    const T* __restrict__ img_copy, const T* __restrict__ flow_copy,
+    const Ck<T>* __restrict__ ck, const Vec2<T>* __restrict__ ckf,
+    const T* __restrict__ dL_dimage, const T* __restrict__ dL_dflow, double* __restrict__ grad2d,
     uint32_t n_gauss) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
+  constexpr int NC = kComps<FLOW>;
   Staged<T>* s_rec = sh.rec;
   uint32_t* s_idx = sh.idx;
   T(*s_grad)[2][NB + 1] = sh.grad;
@@ -293,33 +329,44 @@ __device__ __forceinline__ void raster_bwd_tile(
   const uint32_t lo = seg * kSegment;
   const uint32_t seg_end = lo + kSegment;
   const uint32_t hi = walk < seg_end ? walk : seg_end;
-  const Ck<T>* cs = ck + size_t(ck_slot(rg.x, gtile, seg + 1)) * (TS * TS);
+  const size_t cslot = size_t(ck_slot(rg.x, gtile, seg + 1)) * (TS * TS);
   T py[PPT], Tcur[PPT], g0[PPT], g1[PPT], g2[PPT], acc0[PPT], acc1[PPT], acc2[PPT];
+  T g3[PPT], g4[PPT], acc3[PPT], acc4[PPT];  // flow channels
   uint32_t ncon[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int y = y0 + k * Cfg::kRowStep;
     py[k] = T(y) + T(0.5);
     Tcur[k] = T(1);
-    g0[k] = g1[k] = g2[k] = T(0);
+    g0[k] = g1[k] = g2[k] = g3[k] = g4[k] = T(0);
     ncon[k] = 0u;
-    acc0[k] = acc1[k] = acc2[k] = T(0);
+    acc0[k] = acc1[k] = acc2[k] = acc3[k] = acc4[k] = T(0);
     if (x < v.W && y < v.H) {
       const long pix = long(y) * v.W + x;
       ncon[k] = n_contrib[pix];
       g0[k] = dL_dimage[pix];
       g1[k] = dL_dimage[hw + pix];
       g2[k] = dL_dimage[2 * hw + pix];
+      if (FLOW) {
+        g3[k] = dL_dflow[pix];
+        g4[k] = dL_dflow[hw + pix];
+      }
       if (ncon[k] > seg_end) {
         // the pixel goes on past this segment: start from the forward's state
         // at the segment's end; colour behind = final colour - colour in front
         const int pt = (int(threadIdx.x / TS) + k * Cfg::kRowStep) * TS + int(threadIdx.x % TS);
-        const Ck<T> c = cs[pt];
+        const Ck<T> c = ck[cslot + pt];
         Tcur[k] = c.t;
         acc0[k] = img_copy[pix] - c.r;
         acc1[k] = img_copy[hw + pix] - c.g;
         acc2[k] = img_copy[2 * hw + pix] - c.b;
+        if (FLOW) {
+          const Vec2<T> cf = ckf[cslot + pt];
+          acc3[k] = flow_copy[pix] - cf.x;
+          acc4[k] = flow_copy[hw + pix] - cf.y;
+        }
       } else {
+        // (the flow's background is 0: nothing behind the last contributor)
         // colour accumulated behind the current Gaussian (absolute, includes background)
         Tcur[k] = T_final[pix];
         acc0[k] = Tcur[k] * T(v.bg[0]);
@@ -337,10 +384,16 @@ __device__ __forceinline__ void raster_bwd_tile(
       if (int(threadIdx.x) < nb) {
         const uint32_t idx = values[rg.x + bstart + threadIdx.x];
         s_idx[threadIdx.x] = idx;
-        s_rec[threadIdx.x] = stage(recs[idx], e_min, amin);
+        Staged<T> sr = stage(recs[idx], e_min, amin);
+        if (FLOW) {
+          const Vec2<T> fl = flows[idx];
+          sr.fu = fl.x;
+          sr.fv = fl.y;
+        }
+        s_rec[threadIdx.x] = sr;
       }
 #pragma unroll
-      for (int c = 0; c < 9; ++c) {
+      for (int c = 0; c < NC; ++c) {
         s_grad[c][0][threadIdx.x] = T(0);
         s_grad[c][1][threadIdx.x] = T(0);
       }
@@ -363,8 +416,10 @@ __device__ __forceinline__ void raster_bwd_tile(
       // pass 2: per-pixel derivatives, summed over the lane's pixels as
       // s0..s4 = sum g (ux, uy, ux^2, ux uy, uy^2) with g = a dL/da (the
       // screen-space mean and Sigma_2D gradients are linear in these), s5 = sum
-      // dL/da exp(-q/2), s6..s8 = sum a T dL/dC
-      T sv[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+      // dL/da exp(-q/2), s6..s8 = sum a T dL/dC (s9, s10 the same for the flow)
+      T sv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sv[c] = T(0);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         // (a band where no pixel blended it leaves every sum and state unchanged)
@@ -373,14 +428,22 @@ __device__ __forceinline__ void raster_bwd_tile(
         const T Ti = Tcur[k] * inv_om;  // transmittance in front of this Gaussian
         const T w = use[k] ? alpha[k] * Ti : T(0);
         // dC/da = T c - (colour behind) / (1 - a)
-        const T gc = tfma(g0[k], r.r, tfma(g1[k], r.g, g2[k] * r.b));
-        const T gacc = tfma(g0[k], acc0[k], tfma(g1[k], acc1[k], g2[k] * acc2[k]));
+        T gc = tfma(g0[k], r.r, tfma(g1[k], r.g, g2[k] * r.b));
+        T gacc = tfma(g0[k], acc0[k], tfma(g1[k], acc1[k], g2[k] * acc2[k]));
+        if (FLOW) {
+          gc = tfma(g3[k], r.fu, tfma(g4[k], r.fv, gc));
+          gacc = tfma(g3[k], acc3[k], tfma(g4[k], acc4[k], gacc));
+        }
         // no gradient through the alpha clamp
         const T dL_da =
             (use[k] & (a_raw[k] < amax)) ? inv_om * (Tcur[k] * gc - gacc) : T(0);
         acc0[k] = tfma(r.r, w, acc0[k]);
         acc1[k] = tfma(r.g, w, acc1[k]);
         acc2[k] = tfma(r.b, w, acc2[k]);
+        if (FLOW) {
+          acc3[k] = tfma(r.fu, w, acc3[k]);
+          acc4[k] = tfma(r.fv, w, acc4[k]);
+        }
         Tcur[k] = use[k] ? Ti : Tcur[k];
         const T ga = dL_da * a_raw[k];
         const T gx = ga * ux[k], gy = ga * uy[k];
@@ -393,15 +456,19 @@ __device__ __forceinline__ void raster_bwd_tile(
         sv[6] = tfma(w, g0[k], sv[6]);
         sv[7] = tfma(w, g1[k], sv[7]);
         sv[8] = tfma(w, g2[k], sv[8]);
+        if (FLOW) {
+          sv[9] = tfma(w, g3[k], sv[9]);
+          sv[10] = tfma(w, g4[k], sv[10]);
+        }
       }
       // sums over each half wavefront, kept in LDS by lanes 16 and 48 (the
       // components' scale factors are applied when the batch is flushed);
       // with several wavefronts per tile the halves of all of them add up
-      half_sum9(sv);
+      half_sums(sv);
       if ((lane & 31) == 16) {
         const int hf = lane >> 5;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
+        for (int c = 0; c < NC; ++c) {
           if (NT == 64)
             s_grad[c][hf][j] = sv[c];
           else
@@ -416,8 +483,8 @@ __device__ __forceinline__ void raster_bwd_tile(
     // -g / 2 per pixel, dq/dmean2d = 2 u, and, since dq = -u^T dSigma_2D u for
     // Sigma_2D = Q^-1, dL/dSigma_2D = sum g u u^T / 2; so the components are
     // d/d mean2d = -s0,1 / k, d/d Sigma_2D (0,0), (0,1) = (1,0), (1,1) =
-    // s2,3,4 / (2 k^2), d/d opacity_t = s5, d/d rgb = s6,7,8.
-    for (int e = threadIdx.x; e < 9 * nb; e += NT) {
+    // s2,3,4 / (2 k^2), d/d opacity_t = s5, d/d rgb = s6,7,8 (d/d flow = s9,10).
+    for (int e = threadIdx.x; e < NC * nb; e += NT) {
       const int c = e / nb, j = e % nb;
       const T scale = c < 2 ? T(-1.0 / kHalfLog2e)
                             : (c < 5 ? T(0.5 / (kHalfLog2e * kHalfLog2e)) : T(1));
@@ -448,11 +515,12 @@ __device__ __forceinline__ int slot_of_tile(const ViewSlot* __restrict__ slots, 
 // of uneven size share one launch and a workgroup that drew short lists simply
 // takes more tiles.  (The first tile comes from the launch itself: a counter
 // taken by every workgroup at once would serialise the start.)
-template <typename T, int TS, int PPT, bool COUNT>
+template <typename T, int TS, int PPT, bool COUNT, bool FLOW>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
-    const Rec<T>* __restrict__ recs, uint32_t n, const uint32_t* __restrict__ values,
-    const uint2* __restrict__ ranges, const ViewSlot* __restrict__ slots, int n_views,
-    uint32_t total_tiles, SettingsDev st, T* __restrict__ image, T* __restrict__ T_final,
+    const Rec<T>* __restrict__ recs, const Vec2<T>* __restrict__ flows, uint32_t n,
+    const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
+    const ViewSlot* __restrict__ slots, int n_views, uint32_t total_tiles, SettingsDev st,
+    T* __restrict__ image, T* __restrict__ flow_image, T* __restrict__ T_final,
     uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval, RasterSaved<T> sv,
     uint32_t* __restrict__ tickets) {
   __shared__ Staged<T> s_rec[TileCfg<TS, PPT>::kBatch];
@@ -462,11 +530,12 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
     const size_t pb = size_t(sl.pix_base);
-    raster_fwd_tile<T, TS, PPT, COUNT>(s_rec, &s_walk, recs + size_t(vi) * n, values, ranges[g],
-                                       int(g - sl.tile_base), g, v, st, image + 3 * pb,
-                                       T_final + pb, n_contrib + pb,
-                                       COUNT ? n_eval + pb : nullptr, sv.ck, sv.img + 3 * pb,
-                                       sv.walk);
+    raster_fwd_tile<T, TS, PPT, COUNT, FLOW>(
+        s_rec, &s_walk, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr, values,
+        ranges[g], int(g - sl.tile_base), g, v, st, image + 3 * pb,
+        FLOW ? flow_image + 2 * pb : nullptr, T_final + pb, n_contrib + pb,
+        COUNT ? n_eval + pb : nullptr, sv.ck, sv.ckf, sv.img + 3 * pb,
+        FLOW ? sv.flow + 2 * pb : nullptr, sv.walk);
     if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
     __syncthreads();
     g = s_ticket;
@@ -477,16 +546,17 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
 // Backward work items are (tile, segment) pairs: seg_tile[i] names the tile of
 // item i and seg_base[tile] its first item, so the segments of one long list
 // run in parallel.
-template <typename T, int TS, int PPT>
+template <typename T, int TS, int PPT, bool FLOW>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
-    const Rec<T>* __restrict__ recs, uint32_t n, const uint32_t* __restrict__ values,
-    const uint2* __restrict__ ranges, const ViewSlot* __restrict__ slots, int n_views,
-    SettingsDev st, const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
-    RasterSaved<T> sv, const uint32_t* __restrict__ seg_tile,
-    const uint32_t* __restrict__ seg_base, const uint32_t* __restrict__ total_items,
-    const T* __restrict__ dL_dimage, double* __restrict__ grad2d,
+    const Rec<T>* __restrict__ recs, const Vec2<T>* __restrict__ flows, uint32_t n,
+    const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
+    const ViewSlot* __restrict__ slots, int n_views, SettingsDev st,
+    const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, RasterSaved<T> sv,
+    const uint32_t* __restrict__ seg_tile, const uint32_t* __restrict__ seg_base,
+    const uint32_t* __restrict__ total_items, const T* __restrict__ dL_dimage,
+    const T* __restrict__ dL_dflow, double* __restrict__ grad2d,
     uint32_t* __restrict__ tickets) {
-  __shared__ BwdShared<T, TS, PPT> sh;
+  __shared__ BwdShared<T, TS, PPT, FLOW> sh;
   __shared__ uint32_t s_ticket;
   const uint32_t total = *total_items;
   for (uint32_t it = blockIdx.x; it < total;) {
@@ -496,10 +566,11 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
     const size_t pb = size_t(sl.pix_base);
-    raster_bwd_tile<T, TS, PPT>(sh, recs + size_t(vi) * n, values, ranges[g],
-                                int(g - sl.tile_base), g, seg, sv.walk[g], v, st, T_final + pb,
-                                n_contrib + pb, sv.img + 3 * pb, sv.ck, dL_dimage + 3 * pb,
-                                grad2d + size_t(vi) * 9 * n, n);
+    raster_bwd_tile<T, TS, PPT, FLOW>(
+        sh, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr, values, ranges[g],
+        int(g - sl.tile_base), g, seg, sv.walk[g], v, st, T_final + pb, n_contrib + pb,
+        sv.img + 3 * pb, FLOW ? sv.flow + 2 * pb : nullptr, sv.ck, sv.ckf, dL_dimage + 3 * pb,
+        FLOW ? dL_dflow + 2 * pb : nullptr, grad2d + size_t(vi) * kComps<FLOW> * n, n);
     if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
     __syncthreads();
     it = s_ticket;
@@ -581,35 +652,43 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const float* __restri
 }
 
 template <typename T, int TS, int PPT>
-hipError_t raster_fwd_cfg(const Rec<T>* recs, uint32_t n, const uint32_t* values,
-                          const uint2* ranges, const ViewSlot* slots, int n_views,
-                          uint32_t total_tiles, const SettingsDev& st, T* image, T* T_final,
-                          uint32_t* n_contrib, uint32_t* n_eval, const RasterSaved<T>& sv,
-                          uint32_t* tickets, hipStream_t stream) {
+hipError_t raster_fwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
+                          const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
+                          int n_views, uint32_t total_tiles, const SettingsDev& st, T* image,
+                          T* flow_image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
+                          const RasterSaved<T>& sv, uint32_t* tickets, hipStream_t stream) {
   constexpr int NT = TS * TS / PPT;
-  static const uint32_t cap_count = resident_groups(raster_fwd_kernel<T, TS, PPT, true>, NT);
-  static const uint32_t cap_plain = resident_groups(raster_fwd_kernel<T, TS, PPT, false>, NT);
-  const uint32_t cap = n_eval ? cap_count : cap_plain;
+  if (flows && (n_eval || !flow_image || !sv.ckf || !sv.flow)) return hipErrorInvalidValue;
+  static const uint32_t cap_count =
+      resident_groups(raster_fwd_kernel<T, TS, PPT, true, false>, NT);
+  static const uint32_t cap_plain =
+      resident_groups(raster_fwd_kernel<T, TS, PPT, false, false>, NT);
+  static const uint32_t cap_flow = resident_groups(raster_fwd_kernel<T, TS, PPT, false, true>, NT);
+  const uint32_t cap = flows ? cap_flow : (n_eval ? cap_count : cap_plain);
   const uint32_t grid = total_tiles < cap ? total_tiles : cap;
   if (grid == 0) return hipSuccess;
-  if (n_eval)
-    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, true>), dim3(grid), dim3(NT), 0, stream,
-                       recs, n, values, ranges, slots, n_views, total_tiles, st, image, T_final,
-                       n_contrib, n_eval, sv, tickets);
+  if (flows)
+    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false, true>), dim3(grid), dim3(NT), 0,
+                       stream, recs, flows, n, values, ranges, slots, n_views, total_tiles, st,
+                       image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
+  else if (n_eval)
+    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, true, false>), dim3(grid), dim3(NT), 0,
+                       stream, recs, flows, n, values, ranges, slots, n_views, total_tiles, st,
+                       image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
   else
-    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false>), dim3(grid), dim3(NT), 0, stream,
-                       recs, n, values, ranges, slots, n_views, total_tiles, st, image, T_final,
-                       n_contrib, n_eval, sv, tickets);
+    hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false, false>), dim3(grid), dim3(NT), 0,
+                       stream, recs, flows, n, values, ranges, slots, n_views, total_tiles, st,
+                       image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
   return hipGetLastError();
 }
 
 template <typename T, int TS, int PPT>
-hipError_t raster_bwd_cfg(const Rec<T>* recs, uint32_t n, const uint32_t* values,
-                          const uint2* ranges, const ViewSlot* slots, int n_views,
-                          uint32_t total_tiles, uint64_t max_items, const SettingsDev& st,
-                          const T* T_final, const uint32_t* n_contrib, const RasterSaved<T>& sv,
-                          const T* dL_dimage, double* grad2d, uint32_t* work,
-                          hipStream_t stream) {
+hipError_t raster_bwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
+                          const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
+                          int n_views, uint32_t total_tiles, uint64_t max_items,
+                          const SettingsDev& st, const T* T_final, const uint32_t* n_contrib,
+                          const RasterSaved<T>& sv, const T* dL_dimage, const T* dL_dflow,
+                          double* grad2d, uint32_t* work, hipStream_t stream) {
   constexpr int NT = TS * TS / PPT;
   if (total_tiles == 0) return hipSuccess;
   // work: [tickets (64 words, zeroed by the caller) | count | base | seg_tile | scan scratch]
@@ -624,12 +703,21 @@ hipError_t raster_bwd_cfg(const Rec<T>* recs, uint32_t n, const uint32_t* values
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(seg_map_kernel, dim3(tb), dim3(256), 0, stream, count, base, total_tiles,
                      seg_tile);
-  static const uint32_t cap = resident_groups(raster_bwd_kernel<T, TS, PPT>, NT);
+  const bool flow = dL_dflow != nullptr;
+  if (flow && (!flows || !sv.ckf || !sv.flow)) return hipErrorInvalidValue;
+  static const uint32_t cap_plain = resident_groups(raster_bwd_kernel<T, TS, PPT, false>, NT);
+  static const uint32_t cap_flow = resident_groups(raster_bwd_kernel<T, TS, PPT, true>, NT);
+  const uint32_t cap = flow ? cap_flow : cap_plain;
   const uint32_t grid = uint32_t(max_items < cap ? max_items : cap);
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT>), dim3(grid), dim3(NT), 0, stream, recs, n,
-                     values, ranges, slots, n_views, st, T_final, n_contrib, sv, seg_tile, base,
-                     base + total_tiles, dL_dimage, grad2d, tickets);
+  if (flow)
+    hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT, true>), dim3(grid), dim3(NT), 0, stream,
+                       recs, flows, n, values, ranges, slots, n_views, st, T_final, n_contrib, sv,
+                       seg_tile, base, base + total_tiles, dL_dimage, dL_dflow, grad2d, tickets);
+  else
+    hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT, false>), dim3(grid), dim3(NT), 0, stream,
+                       recs, flows, n, values, ranges, slots, n_views, st, T_final, n_contrib, sv,
+                       seg_tile, base, base + total_tiles, dL_dimage, dL_dflow, grad2d, tickets);
   return hipGetLastError();
 }
 
@@ -669,25 +757,28 @@ int raster_default_ppt(int tile_size, bool backward) {
   }
 
 template <typename T>
-hipError_t launch_raster_fwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
-                             const uint2* ranges, const ViewSlot* slots, int n_views,
-                             uint32_t total_tiles, int tile_size, const SettingsDev& st, int ppt,
-                             T* image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
-                             const RasterSaved<T>& sv, uint32_t* tickets, hipStream_t stream) {
-  R4D_RASTER_DISPATCH(raster_fwd_cfg, recs, n, values, ranges, slots, n_views, total_tiles, st,
-                      image, T_final, n_contrib, n_eval, sv, tickets, stream)
+hipError_t launch_raster_fwd(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
+                             const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
+                             int n_views, uint32_t total_tiles, int tile_size,
+                             const SettingsDev& st, int ppt, T* image, T* flow_image, T* T_final,
+                             uint32_t* n_contrib, uint32_t* n_eval, const RasterSaved<T>& sv,
+                             uint32_t* tickets, hipStream_t stream) {
+  R4D_RASTER_DISPATCH(raster_fwd_cfg, recs, flows, n, values, ranges, slots, n_views,
+                      total_tiles, st, image, flow_image, T_final, n_contrib, n_eval, sv, tickets,
+                      stream)
 }
 
 template <typename T>
-hipError_t launch_raster_bwd(const Rec<T>* recs, uint32_t n, const uint32_t* values,
-                             const uint2* ranges, const ViewSlot* slots, int n_views,
-                             uint32_t total_tiles, uint64_t max_items, int tile_size,
-                             const SettingsDev& st, int ppt, const T* T_final,
+hipError_t launch_raster_bwd(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
+                             const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
+                             int n_views, uint32_t total_tiles, uint64_t max_items,
+                             int tile_size, const SettingsDev& st, int ppt, const T* T_final,
                              const uint32_t* n_contrib, const RasterSaved<T>& sv,
-                             const T* dL_dimage, double* grad2d, uint32_t* work,
-                             hipStream_t stream) {
-  R4D_RASTER_DISPATCH(raster_bwd_cfg, recs, n, values, ranges, slots, n_views, total_tiles,
-                      max_items, st, T_final, n_contrib, sv, dL_dimage, grad2d, work, stream)
+                             const T* dL_dimage, const T* dL_dflow, double* grad2d,
+                             uint32_t* work, hipStream_t stream) {
+  R4D_RASTER_DISPATCH(raster_bwd_cfg, recs, flows, n, values, ranges, slots, n_views,
+                      total_tiles, max_items, st, T_final, n_contrib, sv, dL_dimage, dL_dflow,
+                      grad2d, work, stream)
 }
 
 #undef R4D_RASTER_DISPATCH
@@ -726,15 +817,16 @@ hipError_t launch_l1_grad(const float* image, const float* target, int64_t count
 }
 
 #define R4D_INST(T)                                                                          \
-  template hipError_t launch_raster_fwd<T>(const Rec<T>*, uint32_t, const uint32_t*,          \
-                                           const uint2*, const ViewSlot*, int, uint32_t, int, \
-                                           const SettingsDev&, int, T*, T*, uint32_t*,        \
-                                           uint32_t*, const RasterSaved<T>&, uint32_t*,       \
-                                           hipStream_t);                                      \
-  template hipError_t launch_raster_bwd<T>(const Rec<T>*, uint32_t, const uint32_t*,          \
-                                           const uint2*, const ViewSlot*, int, uint32_t,      \
-                                           uint64_t, int, const SettingsDev&, int, const T*,  \
-                                           const uint32_t*, const RasterSaved<T>&, const T*,  \
+  template hipError_t launch_raster_fwd<T>(const Rec<T>*, const Vec2<T>*, uint32_t,           \
+                                           const uint32_t*, const uint2*, const ViewSlot*,    \
+                                           int, uint32_t, int, const SettingsDev&, int, T*,   \
+                                           T*, T*, uint32_t*, uint32_t*,                      \
+                                           const RasterSaved<T>&, uint32_t*, hipStream_t);    \
+  template hipError_t launch_raster_bwd<T>(const Rec<T>*, const Vec2<T>*, uint32_t,           \
+                                           const uint32_t*, const uint2*, const ViewSlot*,    \
+                                           int, uint32_t, uint64_t, int, const SettingsDev&,  \
+                                           int, const T*, const uint32_t*,                    \
+                                           const RasterSaved<T>&, const T*, const T*,         \
                                            double*, uint32_t*, hipStream_t);
 R4D_INST(float)
 R4D_INST(double)
