@@ -260,6 +260,45 @@ r4d_status r4d_render_backward_flow_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g
                                         const double *dL_dimages, const double *dL_dflows,
                                         r4d_grads_f64 *out, void *stream);
 
+/* 4D nearest neighbours for the 4D consistency loss (Sec. 3.3, "4D Consistency
+ * Loss"): the neighbour set of Gaussian i is its k nearest other Gaussians in
+ * 4D, Euclidean distance after dividing x, y, z by spatial_scale and t by
+ * temporal_scale.  Computed exactly in float32: coordinates u = x * fl(1 /
+ * scale), squared distance ((d0^2 + d1^2) + d2^2) + d3^2 with every operation
+ * rounded to float32, ties broken by the smaller index, i itself excluded.
+ *   means       DEVICE float [4][n] (the Gaussians' means, component-major;
+ *               finite values)
+ *   neighbours  DEVICE int32 [n][k], written: row i = the k neighbours of i,
+ *               nearest first
+ * Requires n >= 2, 1 <= k <= 32, k < n, n * k < 2^31 and positive finite
+ * scales (R4D_ERR_INVALID_ARG / R4D_ERR_CAPACITY otherwise).  Temporary
+ * buffers come from the context's cache; the call is ordered on `stream`. */
+r4d_status r4d_knn4d(r4d_ctx *ctx, const float *means, int32_t n, int32_t k,
+                     float spatial_scale, float temporal_scale, int32_t *neighbours,
+                     void *stream);
+
+/* The 4D consistency loss (Sec. 3.3, "4D Consistency Loss") and its gradient:
+ *   L = (1/n) sum_i || s_i - (1/k) sum_{j in neighbours[i]} s_j ||_1,
+ * s_i = V_i / W_i the speed of Gaussian i's slice (Sec. 3.2.2; V the
+ * space-time block of Sigma_4, W its time variance), computed from g's rotors
+ * and log-scales (the other arrays of g are not read).
+ *   neighbours  DEVICE int32 [n][k] (e.g. from r4d_knn4d); entries outside
+ *               [0, n) are skipped
+ *   loss        DEVICE float scalar receiving L, or NULL
+ *   grads       NULL, or gradient arrays of which only rotors [8][n] and
+ *               log_scales [4][n] are used: they are ADDED to, += weight *
+ *               dL/d(rotors, log_scales).  The neighbour lists are constants
+ *               (no gradient reaches the means); |.| has derivative 0 at 0.
+ * Requires n >= 2 and 1 <= k < n.  The gradient's neighbour sums are exact
+ * (integer atomics): results do not depend on the order of execution. */
+r4d_status r4d_consistency4d_loss_grad(r4d_ctx *ctx, const r4d_gaussians *g,
+                                       const int32_t *neighbours, int32_t k, float weight,
+                                       float *loss, r4d_grads *grads, void *stream);
+/* The same in float64 (test use: finite differences). */
+r4d_status r4d_consistency4d_loss_grad_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g,
+                                           const int32_t *neighbours, int32_t k, double weight,
+                                           double *loss, r4d_grads_f64 *grads, void *stream);
+
 /* Returns the saved arena to its context's cache.  NULL is ignored.  A saved
  * handle may outlive its context: r4d_destroy frees its device memory and a
  * later release only frees the handle. */

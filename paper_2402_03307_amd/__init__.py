@@ -45,7 +45,8 @@ EXPORTED_SYMBOLS = (
     "r4d_default_settings", "r4d_create", "r4d_destroy", "r4d_render_forward",
     "r4d_render_backward", "r4d_render_forward_f64", "r4d_render_backward_f64",
     "r4d_render_forward_flow", "r4d_render_backward_flow", "r4d_render_forward_flow_f64",
-    "r4d_render_backward_flow_f64", "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
+    "r4d_render_backward_flow_f64", "r4d_knn4d", "r4d_consistency4d_loss_grad",
+    "r4d_consistency4d_loss_grad_f64", "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
     "r4d_saved_copy", "r4d_saved_check", "r4d_saved_config", "r4d_status_string",
     "r4d_last_error", "r4d_set_timing", "r4d_get_timings", "r4d_stage_name",
 )
@@ -113,6 +114,14 @@ def _load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.r4d_knn4d.argtypes = [c_vp, c_vp, c_i32, c_i32, c_f32, c_f32, c_vp, c_vp]
+    lib.r4d_knn4d.restype = ctypes.c_int
+    lib.r4d_consistency4d_loss_grad.argtypes = [c_vp, P(_Gaussians), c_vp, c_i32, c_f32, c_vp,
+                                                P(_Grads), c_vp]
+    lib.r4d_consistency4d_loss_grad.restype = ctypes.c_int
+    lib.r4d_consistency4d_loss_grad_f64.argtypes = [c_vp, P(_Gaussians), c_vp, c_i32,
+                                                    ctypes.c_double, c_vp, P(_Grads), c_vp]
+    lib.r4d_consistency4d_loss_grad_f64.restype = ctypes.c_int
     lib.r4d_saved_release.argtypes = [c_vp]
     lib.r4d_saved_release.restype = None
     lib.r4d_l1_loss_grad.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]
@@ -420,6 +429,44 @@ class Renderer:
                     saved.handle, _ptr(dl), ctypes.byref(gs), _stream(self.device))
         self._check(status, "r4d_render_backward")
         return grads
+
+    def knn4d(self, means: torch.Tensor, k: int = 8, spatial_scale: float = 1.0,
+              temporal_scale: float = 1.0) -> torch.Tensor:
+        """[n, k] int32 indices of each Gaussian's k nearest other Gaussians in
+        scaled 4D space (r4d_knn4d); means: [4, n] float32 on this device."""
+        if means.dtype != torch.float32 or means.dim() != 2 or means.shape[0] != 4:
+            raise ValueError("means must be a [4, n] float32 tensor")
+        means = means.contiguous()
+        n = int(means.shape[1])
+        out = torch.empty((n, int(k)), dtype=torch.int32, device=self.device)
+        st = _lib.r4d_knn4d(self.handle, _ptr(means), n, int(k), float(spatial_scale),
+                            float(temporal_scale), _ptr(out), _stream(self.device))
+        self._check(st, "r4d_knn4d")
+        return out
+
+    def consistency4d(self, params: dict, neighbours: torch.Tensor, weight: float = 1.0,
+                      grads: dict | None = None, need_grad: bool = True):
+        """4D consistency loss (r4d_consistency4d_loss_grad): returns (loss
+        tensor, grads) where grads["rotors"] and grads["log_scales"] have had
+        weight * dL/d(.) added (fresh zero tensors when `grads` is None; no
+        gradient when need_grad is False)."""
+        n, deg, dtype = _check_params(params)
+        g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _PARAM_KEYS])
+        nb = neighbours.to(torch.int32).contiguous()
+        if nb.dim() != 2 or nb.shape[0] != n:
+            raise ValueError("neighbours must be [n, k]")
+        loss = torch.empty(1, dtype=dtype, device=self.device)
+        gs = None
+        if need_grad:
+            if grads is None:
+                grads = {k: torch.zeros_like(params[k]) for k in ("rotors", "log_scales")}
+            gs = _Grads(None, _ptr(grads["log_scales"]), _ptr(grads["rotors"]), None, None)
+        fn = (_lib.r4d_consistency4d_loss_grad if dtype == torch.float32
+              else _lib.r4d_consistency4d_loss_grad_f64)
+        st = fn(self.handle, ctypes.byref(g), _ptr(nb), int(nb.shape[1]), float(weight),
+                _ptr(loss), ctypes.byref(gs) if gs is not None else None, _stream(self.device))
+        self._check(st, "r4d_consistency4d_loss_grad")
+        return loss[0], grads
 
     def set_timing(self, enable: bool = True):
         self._check(_lib.r4d_set_timing(self.handle, int(bool(enable))), "r4d_set_timing")

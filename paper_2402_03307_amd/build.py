@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libr4d.so")
-SOURCES = ("api.hip", "preprocess.hip", "binning.hip", "raster.hip")
+SOURCES = ("api.hip", "preprocess.hip", "binning.hip", "raster.hip", "consistency.hip")
 ARCH = "gfx950"
 
 

@@ -1167,6 +1167,28 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   return s;
 }
 
+template <typename T>
+r4d_status consistency_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const int32_t* neighbours,
+                            int32_t k, T weight, T* loss, T* grad_rotors, T* grad_log_scales,
+                            void* stream) {
+  if (g.n < 2 || k < 1 || k >= g.n || !g.rotors || !g.log_scales || !neighbours)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "need n >= 2, 1 <= k < n, rotors, log_scales, neighbours");
+  if ((grad_rotors == nullptr) != (grad_log_scales == nullptr))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "give both gradient arrays or neither");
+  if (uint64_t(g.n) * uint64_t(k) >= (uint64_t(1) << 31))
+    return fail(ctx, R4D_ERR_CAPACITY, "n * k must stay below 2^31");
+  R4D_HIP(hipSetDevice(ctx->device));
+  void* temp = ctx_alloc(ctx, consistency_temp_bytes<T>(uint32_t(g.n)));
+  if (!temp) return fail(ctx, R4D_ERR_OOM, "consistency-loss buffers");
+  const hipError_t e = launch_consistency<T>(g, neighbours, k, weight, loss, grad_rotors,
+                                             grad_log_scales, temp,
+                                             static_cast<hipStream_t>(stream));
+  ctx_free(ctx, temp);
+  if (e != hipSuccess)
+    return fail(ctx, R4D_ERR_HIP, "consistency-loss launch: %s", hipGetErrorString(e));
+  return R4D_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1350,6 +1372,49 @@ r4d_status r4d_render_backward_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
   const GradPtrs<double> o{out->means, out->log_scales, out->rotors, out->opacity, out->sh};
   return backward_impl<double>(ctx, gauss_of(g), views, n_views, settings, saved, dL_dimages,
                                nullptr, o, static_cast<hipStream_t>(stream));
+}
+
+r4d_status r4d_knn4d(r4d_ctx* ctx, const float* means, int32_t n, int32_t k,
+                     float spatial_scale, float temporal_scale, int32_t* neighbours,
+                     void* stream) {
+  if (!ctx) return R4D_ERR_INVALID_ARG;
+  if (!means || !neighbours) return fail(ctx, R4D_ERR_INVALID_ARG, "null argument");
+  if (n < 2 || k < 1 || k > 32 || k >= n)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "need n >= 2 and 1 <= k <= min(32, n - 1)");
+  if (!(spatial_scale > 0.f) || !(temporal_scale > 0.f) || !std::isfinite(spatial_scale) ||
+      !std::isfinite(temporal_scale))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "scene scales must be positive and finite");
+  if (uint64_t(n) * uint64_t(k) >= (uint64_t(1) << 31))
+    return fail(ctx, R4D_ERR_CAPACITY, "n * k must stay below 2^31");
+  R4D_HIP(hipSetDevice(ctx->device));
+  const float inv_s = float(1.0 / double(spatial_scale));
+  const float inv_t = float(1.0 / double(temporal_scale));
+  void* temp = ctx_alloc(ctx, knn4d_temp_bytes(uint32_t(n)));
+  if (!temp) return fail(ctx, R4D_ERR_OOM, "KNN buffers");
+  const hipError_t e = launch_knn4d(means, uint32_t(n), k, inv_s, inv_t, neighbours, temp,
+                                    static_cast<hipStream_t>(stream));
+  ctx_free(ctx, temp);
+  if (e != hipSuccess) return fail(ctx, R4D_ERR_HIP, "KNN launch: %s", hipGetErrorString(e));
+  return R4D_OK;
+}
+
+
+r4d_status r4d_consistency4d_loss_grad(r4d_ctx* ctx, const r4d_gaussians* g,
+                                       const int32_t* neighbours, int32_t k, float weight,
+                                       float* loss, r4d_grads* grads, void* stream) {
+  if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  return consistency_impl<float>(ctx, gauss_of(g), neighbours, k, weight, loss,
+                                 grads ? grads->rotors : nullptr,
+                                 grads ? grads->log_scales : nullptr, stream);
+}
+
+r4d_status r4d_consistency4d_loss_grad_f64(r4d_ctx* ctx, const r4d_gaussians_f64* g,
+                                           const int32_t* neighbours, int32_t k, double weight,
+                                           double* loss, r4d_grads_f64* grads, void* stream) {
+  if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  return consistency_impl<double>(ctx, gauss_of(g), neighbours, k, weight, loss,
+                                  grads ? grads->rotors : nullptr,
+                                  grads ? grads->log_scales : nullptr, stream);
 }
 
 void r4d_saved_release(r4d_saved* saved) {

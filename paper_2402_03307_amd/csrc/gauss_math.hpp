@@ -403,14 +403,10 @@ R4D_HD void rotor_bwd(const Fwd<T>& f, const T* G, T* gr) {
 }
 
 // ---------------------------------------------------------------------------
-// Full per-Gaussian forward.  `sh` points at coefficient 0 of this Gaussian's
-// [3k] SH column (stride n between rows).
-
-template <typename T, typename ShT>
-R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacity, const ShT* shp,
-                         long sh_stride, int deg, const ViewDev& v, const SettingsDev& st,
-                         Fwd<T>& f) {
-  f.valid = false;
+// Sigma_4 = R diag(s^2) R^T of one Gaussian from its raw rotor and log-scales
+// (Sec. 3.2.1): fills the rotor, rotation, s^2, U, V and W fields of f.
+template <typename T>
+R4D_HD void cov4_fwd(const T ls[4], const T rot[8], Fwd<T>& f) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) f.r[i] = rot[i];
   rotor_fwd(f);
@@ -434,6 +430,45 @@ R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacit
   f.V[1] = sig(1, 3);
   f.V[2] = sig(2, 3);
   f.W = sig(3, 3);
+}
+
+// Given G4, the full symmetric gradient of L with respect to Sigma_4, adds
+// dL/d(log-scales) and dL/d(raw rotor).
+template <typename T>
+R4D_HD void cov4_bwd(const Fwd<T>& f, const T G4[16], T gls[4], T grot[8]) {
+  const T* R = f.R;
+  // G4 R
+  T GR[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      GR[4 * i + k] = G4[4 * i] * R[k] + G4[4 * i + 1] * R[4 + k] + G4[4 * i + 2] * R[8 + k] +
+                      G4[4 * i + 3] * R[12 + k];
+  // dL/dR_ik = 2 (G4 R)_ik s2_k ; dL/ds2_k = (R^T G4 R)_kk
+  T gR[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gR[4 * i + k] = 2 * GR[4 * i + k] * f.s2[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T gs2 = R[k] * GR[k] + R[4 + k] * GR[4 + k] + R[8 + k] * GR[8 + k] + R[12 + k] * GR[12 + k];
+    gls[k] += gs2 * 2 * f.s2[k];
+  }
+  rotor_bwd(f, gR, grot);
+}
+
+// ---------------------------------------------------------------------------
+// Full per-Gaussian forward.  `sh` points at coefficient 0 of this Gaussian's
+// [3k] SH column (stride n between rows).
+
+template <typename T, typename ShT>
+R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacity, const ShT* shp,
+                         long sh_stride, int deg, const ViewDev& v, const SettingsDev& st,
+                         Fwd<T>& f) {
+  f.valid = false;
+  cov4_fwd(ls, rot, f);
   // temporal slice
   f.dt = T(v.t) - mu4[3];
   f.invW = T(1) / f.W;
@@ -696,27 +731,7 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int de
   G4[11] = G4[14] = T(0.5) * gV[2];
   G4[15] = gW;
   // the U block of Sigma_4 enters Sigma_3D directly: dL/dU = dL/dS3 (already in G4)
-  const T* R = f.R;
-  // G4 R
-  T GR[16];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      GR[4 * i + k] = G4[4 * i] * R[k] + G4[4 * i + 1] * R[4 + k] + G4[4 * i + 2] * R[8 + k] +
-                      G4[4 * i + 3] * R[12 + k];
-  // dL/dR_ik = 2 (G4 R)_ik s2_k ; dL/ds2_k = (R^T G4 R)_kk
-  T gR[16];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) gR[4 * i + k] = 2 * GR[4 * i + k] * f.s2[k];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const T gs2 = R[k] * GR[k] + R[4 + k] * GR[4 + k] + R[8 + k] * GR[8 + k] + R[12 + k] * GR[12 + k];
-    gls[k] += gs2 * 2 * f.s2[k];
-  }
-  rotor_bwd(f, gR, grot);
+  cov4_bwd(f, G4, gls, grot);
 }
 
 }  // namespace r4d

@@ -247,6 +247,26 @@ struct L1Views {
 hipError_t launch_l1_grad_views(const float* images, const float* targets, const L1Views& lv,
                                 float* grad, float* loss, float* partials, hipStream_t stream);
 
+// ---- 4D nearest neighbours and the 4D consistency loss
+// out: [n][k] int32, the k nearest other points of each point (nearest first,
+// ties by index) in the scaled coordinates u = x * inv (inv_spatial for x, y,
+// z; inv_temporal for t) of means ([4][n] float32).  1 <= k <= 32, k < n.
+// temp: knn4d_temp_bytes(n).
+size_t knn4d_temp_bytes(uint32_t n);
+hipError_t launch_knn4d(const float* means, uint32_t n, int k, float inv_spatial,
+                        float inv_temporal, int32_t* out, void* temp, hipStream_t stream);
+
+// L = (1/n) sum_i |s_i - mean_{j in nb[i]} s_j|_1, s = V / W; *loss = L (when
+// not null); grad_rotors / grad_log_scales (when both are given) += weight *
+// dL/d(raw rotor, log-scales).  nb: [n][k]; entries outside [0, n) are
+// skipped.  temp: consistency_temp_bytes<T>(n).
+template <typename T>
+size_t consistency_temp_bytes(uint32_t n);
+template <typename T>
+hipError_t launch_consistency(const GaussPtrs<T>& g, const int32_t* nb, int k, T weight, T* loss,
+                              T* grad_rotors, T* grad_log_scales, void* temp,
+                              hipStream_t stream);
+
 // ---- small helpers
 // p[0..count) = value (float or double elements).
 hipError_t fill_const(void* p, size_t count, double value, bool f64, hipStream_t stream);
