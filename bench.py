@@ -17,6 +17,9 @@ Speed field: the headline workload rendered with its 2D flow images (the
 projected speed of each Gaussian's sliced mean, composited with the colour
 weights) in the same pass, forward + colour and flow L1 + backward.
 
+4D consistency loss (Sec. 3.3) of the headline Gaussian set: the exact 4D KNN
+(K = 8) and the loss with its gradient.
+
 Further lines (per_config): 2,000 Gaussians at 128x128 (forward), 300,000
 Gaussians over 30 orbit renders (forward), 3,000,000 Gaussians over 16
 renders (graph-mode forward + backward).
@@ -223,6 +226,31 @@ def flow_render(r4d, rend, params, views, st, args):
     return res
 
 
+def consistency4d(r4d, rend, params, args):
+    """4D consistency loss of the headline Gaussian set (Sec. 3.3): the 4D KNN
+    (K = 8, unit scene scales) and the loss with its gradient."""
+    import torch
+    n = int(params["means"].shape[1])
+    k = 8
+    nb = rend.knn4d(params["means"], k)
+    grads = {key: torch.zeros_like(params[key]) for key in ("rotors", "log_scales")}
+    knn_ms = timed(lambda: rend.knn4d(params["means"], k), args.steps, args.warmup)
+    loss_ms = timed(lambda: rend.consistency4d(params, nb, 0.05, grads), args.steps, args.warmup)
+    # algorithmic bytes of the loss + gradient: speeds (48 B parameters in, 16 B
+    # out), the pass over the neighbour lists (4k B indices, 16(k + 1) B speeds,
+    # 4 B signs, 12 B atomics per neighbour), the gradient (48 B parameters and
+    # 16 B signs/sums in, 48 B gradients read and written twice)
+    alg = n * (64 + 4 * k + 16 * (k + 1) + 4 + 12 * k + 64 + 96)
+    res = {"workload": "500k 4D Gaussians (the headline set): KNN with K = 8 in 4D (unit "
+                       "scales), then the 4D consistency loss and its gradient",
+           "n": n, "k": k, "knn_ms": knn_ms, "knn_points_per_s": n / (knn_ms * 1e-3),
+           "loss_grad_ms": loss_ms,
+           "loss_grad_hbm": {"alg_bytes": alg, "GB/s": alg / (loss_ms * 1e-3) / 1e9,
+                             "frac": alg / (loss_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    print(f"consistency4d: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def per_view_step(r4d, rend, params, views, st, targets):
     """The plain baseline: one call sequence per render."""
     saved_all = []
@@ -420,6 +448,7 @@ def main():
     }
     del graph, plain
     out["flow_render"] = flow_render(r4d, rend, params, views, st, args)
+    out["consistency4d"] = consistency4d(r4d, rend, params, args)
 
     if not args.no_extra:
         out["batched_vs_plain"] = batched_vs_plain(r4d, rend, dev, args)

@@ -18,8 +18,9 @@
 // Loss: L = (1/N) sum_i |s_i - mean_{j in Omega_i} s_j|_1.  Its gradient with
 // respect to s_i is (sign(d_i) - (1/K) sum_{m : i in Omega_m} sign(d_m)) / N,
 // d_i = s_i - mean_j s_j; the second sum is gathered with integer atomics
-// (exact, order-independent) and the result chained through s = V / W into
-// Sigma_4 and on to the rotor and log-scales.
+// (exact, order-independent; the three components packed in one 64-bit word
+// when n <= 2^20) and the result chained through s = V / W into Sigma_4 and on
+// to the rotor and log-scales.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -32,6 +33,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kBoundBlocks = 1024;
+// Target points per grid cell of the KNN (the grid has about n / this cells).
+#ifndef R4D_KNN_CELL_POINTS
+#define R4D_KNN_CELL_POINTS 2
+#endif
+constexpr uint32_t kCellPoints = R4D_KNN_CELL_POINTS;
 
 struct Grid4 {
   float lo[4];    // lower corner of the box (scaled coordinates)
@@ -110,12 +116,28 @@ __global__ __launch_bounds__(kBlock) void bounds_kernel(const float* __restrict_
 __global__ __launch_bounds__(kBlock) void grid_setup_kernel(const float* __restrict__ partials,
                                                             uint32_t blocks, uint32_t target,
                                                             Grid4* __restrict__ grid) {
+  __shared__ float s_v[kBlock / 64][8];
   __shared__ float s_box[8];
+  float v[8] = {INFINITY, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (uint32_t b = threadIdx.x; b < blocks; b += kBlock)
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      v[c] = c < 4 ? fminf(v[c], partials[b * 8 + c]) : fmaxf(v[c], partials[b * 8 + c]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float o = __shfl_xor(v[c], off, 64);
+      v[c] = c < 4 ? fminf(v[c], o) : fmaxf(v[c], o);
+    }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s_v[threadIdx.x >> 6][c] = v[c];
+  __syncthreads();
   if (threadIdx.x < 8) {
     const int c = threadIdx.x;
-    float r = partials[c];
-    for (uint32_t b = 1; b < blocks; ++b)
-      r = c < 4 ? fminf(r, partials[b * 8 + c]) : fmaxf(r, partials[b * 8 + c]);
+    float r = s_v[0][c];
+    for (int w = 1; w < kBlock / 64; ++w) r = c < 4 ? fminf(r, s_v[w][c]) : fmaxf(r, s_v[w][c]);
     s_box[c] = r;
   }
   __syncthreads();
@@ -232,10 +254,10 @@ __global__ __launch_bounds__(kBlock) void knn_query_kernel(const float4* __restr
     const int a = c[d] > g.G[d] - 1 - c[d] ? c[d] : g.G[d] - 1 - c[d];
     rmax = a > rmax ? a : rmax;
   }
-  auto scan_cell = [&](const int a[4]) {
-    const uint32_t id = cell_id(a, g);
-    const uint32_t e = starts[id + 1];
-    for (uint32_t t = starts[id]; t < e; ++t) {
+  // the points of sorted positions [b, e): cells that follow each other in x
+  // are contiguous in the sorted order, so a run of cells is one range
+  auto scan_range = [&](uint32_t b, uint32_t e) {
+    for (uint32_t t = b; t < e; ++t) {
       const uint32_t j = sidx[t];
       const float dd = dist2(q, su[t]);
       if (j == qi || !better(dd, j, bd[KMAX - 1], bi[KMAX - 1])) continue;
@@ -252,23 +274,22 @@ __global__ __launch_bounds__(kBlock) void knn_query_kernel(const float4* __restr
       }
     }
   };
-  // far: the smallest squared distance any point of cell a can have from q
-  // (its box widened by the slack), scaled down by a float32 rounding margin
-  // (in coordinates relative to the box corner, so that every rounding is
-  // relative to the box size, not to the coordinates' magnitude)
-  auto far = [&](const int a[4]) {
-    float m = 0.f;
+  // gap2(d, a): the squared distance from q to the slab of cells with
+  // coordinate a in dimension d (widened by the slack), in coordinates relative
+  // to the box corner so that every rounding is relative to the box size; the
+  // sum over the four dimensions bounds the distance to any point of a cell
+  // from below (after a float32 rounding margin, applied in `pruned`)
+  float qr[4];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const float lo = float(a[d]) * g.h;
-      const float hi = float(a[d] + 1) * g.h;
-      const float qd = comp(q, d) - g.lo[d];
-      float gap = fmaxf(lo - qd, qd - hi) - g.slack;
-      gap = gap > 0.f ? gap : 0.f;
-      m += gap * gap;
-    }
-    return m * (1.0f - 1e-6f);
+  for (int d = 0; d < 4; ++d) qr[d] = comp(q, d) - g.lo[d];
+  auto gap2 = [&](int d, int a) {
+    const float lo = float(a) * g.h;
+    const float hi = float(a + 1) * g.h;
+    float gap = fmaxf(lo - qr[d], qr[d] - hi) - g.slack;
+    gap = gap > 0.f ? gap : 0.f;
+    return gap * gap;
   };
+  auto pruned = [&](float m) { return m * (1.0f - 1e-6f) > bd[KMAX - 1]; };
   for (int r = 0; r <= rmax; ++r) {
     if (r > 1 && bd[KMAX - 1] < INFINITY) {
       // shells 0 .. r - 1 are done: every unvisited point lies in a cell at
@@ -284,24 +305,42 @@ __global__ __launch_bounds__(kBlock) void knn_query_kernel(const float4* __restr
       lo[d] = c[d] - r > 0 ? c[d] - r : 0;
       hi[d] = c[d] + r < g.G[d] - 1 ? c[d] + r : g.G[d] - 1;
     }
-    auto visit = [&](const int a[4]) {
-      if (bd[KMAX - 1] < INFINITY && far(a) > bd[KMAX - 1]) return;
-      scan_cell(a);
+    // the loop nest prunes whole slabs once their partial distance bound
+    // exceeds the current k-th distance (the bound only grows inwards)
+    auto visit = [&](int a[4], float m3) {
+      if (pruned(m3 + gap2(0, a[0]))) return;
+      const uint32_t id = cell_id(a, g);
+      scan_range(starts[id], starts[id + 1]);
     };
     int a[4];
     for (a[3] = lo[3]; a[3] <= hi[3]; ++a[3]) {
+      const float m3 = gap2(3, a[3]);
+      if (pruned(m3)) continue;
       for (a[2] = lo[2]; a[2] <= hi[2]; ++a[2]) {
+        const float m2 = m3 + gap2(2, a[2]);
+        if (pruned(m2)) continue;
         for (a[1] = lo[1]; a[1] <= hi[1]; ++a[1]) {
+          const float m1 = m2 + gap2(1, a[1]);
+          if (pruned(m1)) continue;
           // with the other three strictly inside, only a0 = c0 - r and c0 + r
           const bool inner = r > 0 && abs(a[1] - c[1]) < r && abs(a[2] - c[2]) < r &&
                              abs(a[3] - c[3]) < r;
           if (inner) {
             a[0] = c[0] - r;
-            if (a[0] >= 0) visit(a);
+            if (a[0] >= 0) visit(a, m1);
             a[0] = c[0] + r;
-            if (a[0] < g.G[0]) visit(a);
+            if (a[0] < g.G[0]) visit(a, m1);
           } else {
-            for (a[0] = lo[0]; a[0] <= hi[0]; ++a[0]) visit(a);
+            // the x-run of cells lo[0] .. hi[0], trimmed at both ends to the
+            // cells the bound does not prune (gap2 along x falls then rises)
+            int x0 = lo[0], x1 = hi[0];
+            while (x0 <= x1 && pruned(m1 + gap2(0, x0))) ++x0;
+            while (x1 >= x0 && pruned(m1 + gap2(0, x1))) --x1;
+            if (x0 <= x1) {
+              a[0] = x0;
+              const uint32_t id0 = cell_id(a, g);
+              scan_range(starts[id0], starts[id0 + uint32_t(x1 - x0) + 1]);
+            }
           }
         }
       }
@@ -341,11 +380,36 @@ __device__ __forceinline__ int sgn(T x) {
   return x > T(0) ? 1 : (x < T(0) ? -1 : 0);
 }
 
+// The three sign sums of a Gaussian packed in one 64-bit word, 21-bit two's
+// complement fields at bits 0, 21 and 42: adding packed words adds the fields
+// as long as no field's sum leaves [-2^20, 2^20), which holds when fewer than
+// 2^20 Gaussians can name it as a neighbour (n <= 2^20).  One atomic per
+// neighbour instead of three.
+constexpr uint32_t kPackedSignsMaxN = 1u << 20;
+
+__device__ __forceinline__ unsigned long long pack_signs(int g0, int g1, int g2) {
+  return uint64_t(int64_t(g0)) + (uint64_t(int64_t(g1)) << 21) + (uint64_t(int64_t(g2)) << 42);
+}
+
+__device__ __forceinline__ int sext21(uint64_t v) {
+  const int x = int(v & 0x1fffffu);
+  return x >= (1 << 20) ? x - (1 << 21) : x;
+}
+
+__device__ __forceinline__ void unpack_signs(uint64_t w, int& g0, int& g1, int& g2) {
+  g0 = sext21(w);
+  w = (w - uint64_t(int64_t(g0))) >> 21;
+  g1 = sext21(w);
+  w = (w - uint64_t(int64_t(g1))) >> 21;
+  g2 = sext21(w);
+}
+
 // Per Gaussian: d = s_i - mean of its neighbours' speeds; |d|_1 summed per
 // workgroup into partials; sign(d) stored; sign(d) gathered onto every
-// neighbour with integer atomics.  Neighbour indices outside [0, n) are
-// skipped.
-template <typename T>
+// neighbour with integer atomics (one packed 64-bit atomic each when PACKED,
+// else one 32-bit atomic per component).  Neighbour indices outside [0, n)
+// are skipped.
+template <typename T, bool PACKED>
 __global__ __launch_bounds__(kBlock) void consistency_fwd_kernel(
     const Speed<T>* __restrict__ sp, const int32_t* __restrict__ nb, int k, uint32_t n,
     char4* __restrict__ sign_out, int32_t* __restrict__ gather, T* __restrict__ partials) {
@@ -369,13 +433,18 @@ __global__ __launch_bounds__(kBlock) void consistency_fwd_kernel(
     part = fabs(d0) + fabs(d1) + fabs(d2);
     const int g0 = sgn(d0), g1 = sgn(d1), g2 = sgn(d2);
     sign_out[i] = make_char4(char(g0), char(g1), char(g2), 0);
+    const unsigned long long pk = pack_signs(g0, g1, g2);
     for (int a = 0; a < k; ++a) {
       const uint32_t j = uint32_t(row[a]);
       if (j >= n) continue;
       int32_t* gj = gather + 4 * size_t(j);
-      if (g0) atomicAdd(gj, g0);
-      if (g1) atomicAdd(gj + 1, g1);
-      if (g2) atomicAdd(gj + 2, g2);
+      if (PACKED) {
+        if (pk) atomicAdd(reinterpret_cast<unsigned long long*>(gj), pk);
+      } else {
+        if (g0) atomicAdd(gj, g0);
+        if (g1) atomicAdd(gj + 1, g1);
+        if (g2) atomicAdd(gj + 2, g2);
+      }
     }
   }
 #pragma unroll
@@ -403,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void loss_total_kernel(const T* __restrict_
 // dL/ds_i = (sign(d_i) - gather_i / K) / N, times `weight`, through s = V / W
 // (dV = ds / W, dW = -(ds . s) / W) into Sigma_4, then to the log-scales and
 // raw rotor; added to the outputs.
-template <typename T>
+template <typename T, bool PACKED>
 __global__ __launch_bounds__(kBlock) void consistency_bwd_kernel(
     GaussPtrs<T> g, const char4* __restrict__ signs, const int32_t* __restrict__ gather, int k,
     T scale, T* __restrict__ grot, T* __restrict__ gls) {
@@ -411,7 +480,16 @@ __global__ __launch_bounds__(kBlock) void consistency_bwd_kernel(
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const char4 sg = signs[i];
-  const int32_t* ga = gather + 4 * size_t(i);
+  int ga[3];
+  if (PACKED) {
+    unpack_signs(*reinterpret_cast<const unsigned long long*>(gather + 4 * size_t(i)), ga[0],
+                 ga[1], ga[2]);
+  } else {
+    const int4 w = *reinterpret_cast<const int4*>(gather + 4 * size_t(i));
+    ga[0] = w.x;
+    ga[1] = w.y;
+    ga[2] = w.z;
+  }
   const T ik = T(1) / T(k);
   const T gs[3] = {scale * (T(sg.x) - T(ga[0]) * ik), scale * (T(sg.y) - T(ga[1]) * ik),
                    scale * (T(sg.z) - T(ga[2]) * ik)};
@@ -442,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void consistency_bwd_kernel(
   for (int c = 0; c < 8; ++c) grot[c * (long)n + i] += gr[c];
 }
 
-uint32_t knn_cells_cap(uint32_t n) { return n / 2 > 1u ? n / 2 : 1u; }
+uint32_t knn_cells_cap(uint32_t n) { return n / kCellPoints > 1u ? n / kCellPoints : 1u; }
 
 }  // namespace
 
@@ -533,14 +611,25 @@ hipError_t launch_consistency(const GaussPtrs<T>& g, const int32_t* nb, int k, T
   hipError_t e = fill_zero(gather, a(size_t(n) * 16), stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(speed_kernel<T>, dim3(blocks), dim3(kBlock), 0, stream, g, sp);
-  hipLaunchKernelGGL(consistency_fwd_kernel<T>, dim3(blocks), dim3(kBlock), 0, stream, sp, nb, k,
-                     n, signs, gather, partials);
+  const bool packed = n <= kPackedSignsMaxN;
+  if (packed)
+    hipLaunchKernelGGL((consistency_fwd_kernel<T, true>), dim3(blocks), dim3(kBlock), 0, stream,
+                       sp, nb, k, n, signs, gather, partials);
+  else
+    hipLaunchKernelGGL((consistency_fwd_kernel<T, false>), dim3(blocks), dim3(kBlock), 0, stream,
+                       sp, nb, k, n, signs, gather, partials);
   if (loss)
     hipLaunchKernelGGL(loss_total_kernel<T>, dim3(1), dim3(kBlock), 0, stream, partials, blocks, n,
                        loss);
-  if (grad_rotors && grad_log_scales)
-    hipLaunchKernelGGL(consistency_bwd_kernel<T>, dim3(blocks), dim3(kBlock), 0, stream, g, signs,
-                       gather, k, weight / T(n), grad_rotors, grad_log_scales);
+  if (grad_rotors && grad_log_scales) {
+    if (packed)
+      hipLaunchKernelGGL((consistency_bwd_kernel<T, true>), dim3(blocks), dim3(kBlock), 0, stream,
+                         g, signs, gather, k, weight / T(n), grad_rotors, grad_log_scales);
+    else
+      hipLaunchKernelGGL((consistency_bwd_kernel<T, false>), dim3(blocks), dim3(kBlock), 0,
+                         stream, g, signs, gather, k, weight / T(n), grad_rotors,
+                         grad_log_scales);
+  }
   return hipGetLastError();
 }
 

@@ -153,6 +153,30 @@ def test_loss_and_gradients_vs_oracle(rend, device):
         assert torch.allclose(grads[k], 2 * before[k], rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("n", [5000, 1_100_000])
+def test_loss_with_arbitrary_lists_both_sign_sum_paths(rend, device, n):
+    """Any neighbour lists (seeded random, repeats allowed) through the packed
+    sign sums (n <= 2^20) and the per-component ones (n > 2^20)."""
+    print(f"case: consistency n={n} random lists", flush=True)
+    g = W.gaussians(n, 0)
+    nb = np.random.default_rng(14).integers(0, n, size=(n, 8))
+    P = O.params_to_torch(g, requires_grad=True)
+    ref = C.consistency_loss(P, nb)
+    ref.backward()
+    p = to_device(g, device)
+    loss, grads = rend.consistency4d(p, torch.as_tensor(nb).to(device), 1.0)
+    torch.cuda.synchronize()
+    assert abs(float(loss) - float(ref)) <= 1e-5 * float(ref)
+    skip = _ambiguous_gaussians(P, nb)
+    assert skip.sum() <= 0.01 * n
+    for k in ("rotors", "log_scales"):
+        gg = grads[k].cpu().numpy().astype(np.float64)[:, ~skip]
+        gr = P[k].grad.numpy()[:, ~skip]
+        rel = float(np.linalg.norm(gg - gr) / np.linalg.norm(gr))
+        print(f"{k}: rel {rel:.3g}")
+        assert rel <= 1e-4, k
+
+
 def test_gpu_neighbours_feed_the_loss(rend, device):
     """KNN and loss chained on the device, as a training step would: the
     result equals the oracle with its own neighbour lists."""
