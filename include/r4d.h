@@ -299,6 +299,78 @@ r4d_status r4d_consistency4d_loss_grad_f64(r4d_ctx *ctx, const r4d_gaussians_f64
                                            const int32_t *neighbours, int32_t k, double weight,
                                            double *loss, r4d_grads_f64 *grads, void *stream);
 
+/* ---- optimisation step (Sec. 3.3 losses; the optimiser conventions the paper
+ * takes from 3D Gaussian Splatting, Sec. 4 "Implementation Details") ---- */
+
+/* Adam settings.  Learning rates per parameter group; the position (4D mean)
+ * rate decays exponentially from lr_means_init at step 0 to lr_means_final at
+ * step lr_means_steps (constant after): lr(t) = exp((1 - u) ln init + u ln
+ * final), u = min(t / steps, 1).  SH degree-0 coefficients (rows 0..2 of the
+ * [3k][n] array) use lr_sh_dc, the higher bands lr_sh_rest.  Update:
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t the 1-based step. */
+typedef struct {
+  float lr_means_init;
+  float lr_means_final;
+  int32_t lr_means_steps;
+  float lr_log_scales;
+  float lr_rotors;
+  float lr_opacity;
+  float lr_sh_dc;
+  float lr_sh_rest;
+  float beta1;
+  float beta2;
+  float eps;
+} r4d_adam_config;
+
+/* 3D Gaussian Splatting's values: means 1.6e-4 -> 1.6e-6 over 30000 steps
+ * (before any scene-extent factor, which the caller applies), log-scales
+ * 5e-3, rotors 1e-3, opacity 0.05, SH degree 0 2.5e-3 and higher bands
+ * 2.5e-3 / 20, betas 0.9 / 0.999, eps 1e-15. */
+void r4d_default_adam_config(r4d_adam_config *c);
+
+/* Optimiser state of n Gaussians (all DEVICE float unless noted):
+ *   means..sh      the render's parameter arrays (layouts of r4d_gaussians),
+ *                  updated in place
+ *   opacity_logit  [n]: the optimiser's opacity parameter l, with
+ *                  opacity = 1 / (1 + exp(-l)) kept in sync by every call
+ *   adam_m, adam_v [n (17 + 3k)]: the moments, groups back to back in the
+ *                  order means, log_scales, rotors, opacity (of the logit),
+ *                  sh, each laid out like its parameter; zero initially
+ *   step           DEVICE int32: steps taken (0 initially), incremented by
+ *                  every r4d_adam_step on the device (so a step can be
+ *                  captured in a graph and replayed) */
+typedef struct {
+  int32_t n;
+  int32_t sh_degree;
+  float *means;
+  float *log_scales;
+  float *rotors;
+  float *opacity;
+  float *sh;
+  float *opacity_logit;
+  float *adam_m;
+  float *adam_v;
+  int32_t *step;
+} r4d_train_state;
+
+/* One Adam step of all five groups (one fused launch).  grads: the gradients
+ * of r4d_render_backward (plus any regulariser's), the opacity one w.r.t. the
+ * activated opacity (the call multiplies by o (1 - o) for the logit). */
+r4d_status r4d_adam_step(r4d_ctx *ctx, const r4d_train_state *state, const r4d_grads *grads,
+                         const r4d_adam_config *cfg, void *stream);
+
+/* Opacity reset: opacity = min(opacity, cap) (through the logit), and the
+ * opacity moments cleared for every Gaussian; 0 < cap < 1. */
+r4d_status r4d_opacity_reset(r4d_ctx *ctx, const r4d_train_state *state, float cap, void *stream);
+
+/* Entropy loss (Sec. 3.3 "Entropy Loss"): L = (1/n) sum_i -o_i ln o_i over
+ * DEVICE float opacity [n] (values in (0, 1]).  loss: DEVICE float scalar or
+ * NULL; grad_opacity: DEVICE float [n] or NULL, += weight * dL/do
+ * (= -weight (ln o + 1) / n). */
+r4d_status r4d_entropy_loss_grad(r4d_ctx *ctx, const float *opacity, int32_t n, float weight,
+                                 float *loss, float *grad_opacity, void *stream);
+
 /* Returns the saved arena to its context's cache.  NULL is ignored.  A saved
  * handle may outlive its context: r4d_destroy frees its device memory and a
  * later release only frees the handle. */

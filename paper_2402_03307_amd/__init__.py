@@ -29,7 +29,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libr4d.so")
 
-__all__ = ["render", "render_flow", "Renderer", "R4DError", "default_settings", "LIB_PATH",
+__all__ = ["render", "render_flow", "Renderer", "TrainState", "adam_config", "R4DError", "default_settings", "LIB_PATH",
            "BUF_RECORDS", "BUF_RECT", "BUF_DEPTHKEY", "BUF_VALUES", "BUF_RANGES",
            "BUF_TFINAL", "BUF_NCONTRIB", "BUF_FLOW", "EXPORTED_SYMBOLS", "MODE_PER_VIEW",
            "MODE_FUSED", "MODE_GRAPH"]
@@ -46,7 +46,8 @@ EXPORTED_SYMBOLS = (
     "r4d_render_backward", "r4d_render_forward_f64", "r4d_render_backward_f64",
     "r4d_render_forward_flow", "r4d_render_backward_flow", "r4d_render_forward_flow_f64",
     "r4d_render_backward_flow_f64", "r4d_knn4d", "r4d_consistency4d_loss_grad",
-    "r4d_consistency4d_loss_grad_f64", "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
+    "r4d_consistency4d_loss_grad_f64", "r4d_default_adam_config", "r4d_adam_step",
+    "r4d_opacity_reset", "r4d_entropy_loss_grad", "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
     "r4d_saved_copy", "r4d_saved_check", "r4d_saved_config", "r4d_status_string",
     "r4d_last_error", "r4d_set_timing", "r4d_get_timings", "r4d_stage_name",
 )
@@ -77,6 +78,19 @@ class _Settings(ctypes.Structure):
                 ("T_min", c_f32), ("dilation", c_f32), ("guard_band", c_f32),
                 ("fwd_pixels_per_thread", c_i32), ("bwd_pixels_per_thread", c_i32),
                 ("mode", c_i32), ("sort_items", c_i32)]
+
+
+class _AdamConfig(ctypes.Structure):
+    _fields_ = [("lr_means_init", c_f32), ("lr_means_final", c_f32), ("lr_means_steps", c_i32),
+                ("lr_log_scales", c_f32), ("lr_rotors", c_f32), ("lr_opacity", c_f32),
+                ("lr_sh_dc", c_f32), ("lr_sh_rest", c_f32), ("beta1", c_f32), ("beta2", c_f32),
+                ("eps", c_f32)]
+
+
+class _TrainState(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("sh_degree", c_i32), ("means", c_vp), ("log_scales", c_vp),
+                ("rotors", c_vp), ("opacity", c_vp), ("sh", c_vp), ("opacity_logit", c_vp),
+                ("adam_m", c_vp), ("adam_v", c_vp), ("step", c_vp)]
 
 
 class _Grads(ctypes.Structure):
@@ -122,6 +136,14 @@ def _load():
     lib.r4d_consistency4d_loss_grad_f64.argtypes = [c_vp, P(_Gaussians), c_vp, c_i32,
                                                     ctypes.c_double, c_vp, P(_Grads), c_vp]
     lib.r4d_consistency4d_loss_grad_f64.restype = ctypes.c_int
+    lib.r4d_default_adam_config.argtypes = [P(_AdamConfig)]
+    lib.r4d_default_adam_config.restype = None
+    lib.r4d_adam_step.argtypes = [c_vp, P(_TrainState), P(_Grads), P(_AdamConfig), c_vp]
+    lib.r4d_adam_step.restype = ctypes.c_int
+    lib.r4d_opacity_reset.argtypes = [c_vp, P(_TrainState), c_f32, c_vp]
+    lib.r4d_opacity_reset.restype = ctypes.c_int
+    lib.r4d_entropy_loss_grad.argtypes = [c_vp, c_vp, c_i32, c_f32, c_vp, c_vp, c_vp]
+    lib.r4d_entropy_loss_grad.restype = ctypes.c_int
     lib.r4d_saved_release.argtypes = [c_vp]
     lib.r4d_saved_release.restype = None
     lib.r4d_l1_loss_grad.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]
@@ -468,6 +490,32 @@ class Renderer:
         self._check(st, "r4d_consistency4d_loss_grad")
         return loss[0], grads
 
+    def entropy_loss_grad(self, opacity: torch.Tensor, weight: float = 1.0,
+                          grad: torch.Tensor | None = None):
+        """Entropy loss (r4d_entropy_loss_grad): returns (loss, grad) with
+        grad += weight * dL/do (a fresh zero tensor when None)."""
+        opacity = opacity.contiguous()
+        grad = torch.zeros_like(opacity) if grad is None else grad
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        st = _lib.r4d_entropy_loss_grad(self.handle, _ptr(opacity), int(opacity.numel()),
+                                        float(weight), _ptr(loss), _ptr(grad),
+                                        _stream(self.device))
+        self._check(st, "r4d_entropy_loss_grad")
+        return loss[0], grad
+
+    def adam_step(self, state: "TrainState", grads: dict, config: dict | None = None):
+        """One fused Adam step (r4d_adam_step) of the train state's parameters."""
+        gs = _Grads(*[_ptr(grads[k]) for k in _PARAM_KEYS])
+        cfg = adam_config(config)
+        st = _lib.r4d_adam_step(self.handle, ctypes.byref(state.struct()), ctypes.byref(gs),
+                                ctypes.byref(cfg), _stream(self.device))
+        self._check(st, "r4d_adam_step")
+
+    def opacity_reset(self, state: "TrainState", cap: float = 0.01):
+        st = _lib.r4d_opacity_reset(self.handle, ctypes.byref(state.struct()), float(cap),
+                                    _stream(self.device))
+        self._check(st, "r4d_opacity_reset")
+
     def set_timing(self, enable: bool = True):
         self._check(_lib.r4d_set_timing(self.handle, int(bool(enable))), "r4d_set_timing")
 
@@ -506,6 +554,40 @@ class Renderer:
                                        _ptr(grad), _ptr(loss), _stream(self.device))
         self._check(status, "r4d_l1_loss_grad")
         return loss[0], grad
+
+
+def adam_config(overrides: dict | None = None) -> _AdamConfig:
+    """The library's default Adam settings with `overrides` applied."""
+    c = _AdamConfig()
+    _lib.r4d_default_adam_config(ctypes.byref(c))
+    for k, val in (overrides or {}).items():
+        setattr(c, k, val)
+    return c
+
+
+class TrainState:
+    """Optimiser state around a parameter dict (float32 CUDA tensors, updated
+    in place): the opacity logit, the Adam moments and the device step count."""
+
+    def __init__(self, params: dict):
+        n, deg, dtype = _check_params(params)
+        if dtype != torch.float32:
+            raise ValueError("the optimiser works on float32 parameters")
+        self.params = params
+        self.n, self.deg = n, deg
+        o = params["opacity"].double().clamp(1e-7, 1 - 1e-7)
+        self.opacity_logit = (torch.log(o) - torch.log1p(-o)).float().contiguous()
+        total = sum(params[k].numel() for k in _PARAM_KEYS)
+        dev = params["means"].device
+        self.m = torch.zeros(total, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(total, dtype=torch.float32, device=dev)
+        self.step = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def struct(self) -> _TrainState:
+        p = self.params
+        return _TrainState(self.n, self.deg, _ptr(p["means"]), _ptr(p["log_scales"]),
+                           _ptr(p["rotors"]), _ptr(p["opacity"]), _ptr(p["sh"]),
+                           _ptr(self.opacity_logit), _ptr(self.m), _ptr(self.v), _ptr(self.step))
 
 
 _default_renderers: dict = {}

@@ -19,7 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libr4d.so")
-SOURCES = ("api.hip", "preprocess.hip", "binning.hip", "raster.hip", "consistency.hip")
+SOURCES = ("api.hip", "preprocess.hip", "binning.hip", "raster.hip", "consistency.hip",
+           "training.hip")
 ARCH = "gfx950"
 
 

@@ -1417,6 +1417,89 @@ r4d_status r4d_consistency4d_loss_grad_f64(r4d_ctx* ctx, const r4d_gaussians_f64
                                   grads ? grads->log_scales : nullptr, stream);
 }
 
+void r4d_default_adam_config(r4d_adam_config* c) {
+  if (!c) return;
+  c->lr_means_init = 1.6e-4f;
+  c->lr_means_final = 1.6e-6f;
+  c->lr_means_steps = 30000;
+  c->lr_log_scales = 5e-3f;
+  c->lr_rotors = 1e-3f;
+  c->lr_opacity = 0.05f;
+  c->lr_sh_dc = 2.5e-3f;
+  c->lr_sh_rest = 2.5e-3f / 20.0f;
+  c->beta1 = 0.9f;
+  c->beta2 = 0.999f;
+  c->eps = 1e-15f;
+}
+
+r4d_status r4d_adam_step(r4d_ctx* ctx, const r4d_train_state* st, const r4d_grads* grads,
+                         const r4d_adam_config* cfg, void* stream) {
+  if (!ctx) return R4D_ERR_INVALID_ARG;
+  if (!st || !grads || !cfg) return fail(ctx, R4D_ERR_INVALID_ARG, "null argument");
+  if (st->n < 0 || st->sh_degree < 0 || st->sh_degree > 3)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid Gaussian count or SH degree");
+  if (st->n == 0) return R4D_OK;
+  if (!st->means || !st->log_scales || !st->rotors || !st->opacity || !st->sh ||
+      !st->opacity_logit || !st->adam_m || !st->adam_v || !st->step || !grads->means ||
+      !grads->log_scales || !grads->rotors || !grads->opacity || !grads->sh)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "null array in the train state or gradients");
+  if (!(cfg->lr_means_init > 0.f) || !(cfg->lr_means_final > 0.f) || !(cfg->beta1 >= 0.f) ||
+      !(cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f) || !(cfg->beta2 < 1.f) || !(cfg->eps >= 0.f))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid Adam settings");
+  const uint64_t n = uint64_t(st->n);
+  const uint64_t k3 = 3 * uint64_t((st->sh_degree + 1) * (st->sh_degree + 1));
+  AdamGroups G{};
+  float* ps[5] = {st->means, st->log_scales, st->rotors, st->opacity, st->sh};
+  const float* gs[5] = {grads->means, grads->log_scales, grads->rotors, grads->opacity, grads->sh};
+  const uint64_t rows[5] = {4, 4, 8, 1, k3};
+  uint64_t off = 0;
+  for (int q = 0; q < 5; ++q) {
+    G.p[q] = ps[q];
+    G.g[q] = gs[q];
+    G.off[q] = off;
+    off += rows[q] * n;
+  }
+  G.off[5] = off;
+  G.n = uint32_t(n);
+  const AdamConfig c{cfg->lr_means_init, cfg->lr_means_final, cfg->lr_means_steps,
+                     cfg->lr_log_scales, cfg->lr_rotors,      cfg->lr_opacity,
+                     cfg->lr_sh_dc,      cfg->lr_sh_rest,     cfg->beta1,
+                     cfg->beta2,         cfg->eps};
+  R4D_HIP(hipSetDevice(ctx->device));
+  R4D_HIP(launch_adam(G, st->opacity_logit, st->adam_m, st->adam_v, st->step, c,
+                      static_cast<hipStream_t>(stream)));
+  return R4D_OK;
+}
+
+r4d_status r4d_opacity_reset(r4d_ctx* ctx, const r4d_train_state* st, float cap, void* stream) {
+  if (!ctx) return R4D_ERR_INVALID_ARG;
+  if (!st || !st->opacity_logit || !st->opacity || !st->adam_m || !st->adam_v || st->n < 0 ||
+      st->sh_degree < 0 || st->sh_degree > 3 || !(cap > 0.f) || !(cap < 1.f))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid opacity reset arguments");
+  const uint64_t n = uint64_t(st->n);
+  const uint64_t op_off = 16 * n;  // after means, log_scales, rotors
+  R4D_HIP(hipSetDevice(ctx->device));
+  R4D_HIP(launch_opacity_reset(uint32_t(n), cap, st->opacity_logit, st->opacity,
+                               st->adam_m + op_off, st->adam_v + op_off,
+                               static_cast<hipStream_t>(stream)));
+  return R4D_OK;
+}
+
+r4d_status r4d_entropy_loss_grad(r4d_ctx* ctx, const float* opacity, int32_t n, float weight,
+                                 float* loss, float* grad_opacity, void* stream) {
+  if (!ctx) return R4D_ERR_INVALID_ARG;
+  if (n < 0 || (n > 0 && !opacity)) return fail(ctx, R4D_ERR_INVALID_ARG, "invalid entropy arguments");
+  if (n == 0) return R4D_OK;
+  R4D_HIP(hipSetDevice(ctx->device));
+  void* temp = ctx_alloc(ctx, entropy_temp_bytes(uint32_t(n)));
+  if (!temp) return fail(ctx, R4D_ERR_OOM, "entropy buffers");
+  const hipError_t e = launch_entropy(opacity, uint32_t(n), weight, loss, grad_opacity, temp,
+                                      static_cast<hipStream_t>(stream));
+  ctx_free(ctx, temp);
+  if (e != hipSuccess) return fail(ctx, R4D_ERR_HIP, "entropy launch: %s", hipGetErrorString(e));
+  return R4D_OK;
+}
+
 void r4d_saved_release(r4d_saved* saved) {
   if (!saved) return;
   if (saved->ctx) {  // null once the context has been destroyed

@@ -267,6 +267,36 @@ hipError_t launch_consistency(const GaussPtrs<T>& g, const int32_t* nb, int k, T
                               T* grad_rotors, T* grad_log_scales, void* temp,
                               hipStream_t stream);
 
+// ---- optimisation step
+// The five parameter groups (means, log_scales, rotors, opacity, sh) of n
+// Gaussians: p[k] the render's arrays, g[k] their gradients (the opacity one
+// w.r.t. the activated opacity), off[k] the group's first element in the
+// concatenated moment arrays (off[5] = total).
+struct AdamGroups {
+  float* p[5];
+  const float* g[5];
+  uint64_t off[6];
+  uint32_t n;
+};
+struct AdamConfig {
+  float lr_means_init, lr_means_final;
+  int32_t lr_means_steps;
+  float lr_log_scales, lr_rotors, lr_opacity, lr_sh_dc, lr_sh_rest;
+  float beta1, beta2, eps;
+};
+// One Adam step of every group at step count *step (steps already taken),
+// then *step += 1.  The opacity group updates `logit` and writes the activated
+// opacity back into p[3].
+hipError_t launch_adam(const AdamGroups& groups, float* logit, float* m, float* v, int32_t* step,
+                       const AdamConfig& cfg, hipStream_t stream);
+hipError_t launch_opacity_reset(uint32_t n, float cap, float* logit, float* opacity, float* m_op,
+                                float* v_op, hipStream_t stream);
+// Entropy (1/n) sum -o ln o into *loss (nullable); grad (nullable) += weight *
+// its gradient.  temp: entropy_temp_bytes(n).
+size_t entropy_temp_bytes(uint32_t n);
+hipError_t launch_entropy(const float* opacity, uint32_t n, float weight, float* loss, float* grad,
+                          void* temp, hipStream_t stream);
+
 // ---- small helpers
 // p[0..count) = value (float or double elements).
 hipError_t fill_const(void* p, size_t count, double value, bool f64, hipStream_t stream);

@@ -1,0 +1,164 @@
+"""The optimisation step on the GPU against the CPU oracle, and a synthetic
+fit-to-target run of the whole step (render, L1, entropy and 4D consistency
+losses, Adam).
+
+Tolerances (float32 GPU vs float64 oracle from the same float32 start):
+  * parameters after s Adam steps: |GPU - oracle| <= 1e-6 |p| + 1e-4 lr s per
+    group (an update is lr times a ratio of order 1 computed to a few float32
+    roundings; the stored parameter rounds once per step); moments relative
+    1e-5 of the group's largest (the oracle takes the settings as the library
+    receives them, rounded to float32); the step counter exact;
+  * entropy: loss and gradient relative 1e-5;
+  * opacity reset: opacities and logits to float32 rounding, moments exactly 0.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import training as T
+
+from helpers import to_device
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("means", "log_scales", "rotors", "opacity", "sh")
+CFG = {"lr_means_init": 1.6e-4, "lr_means_final": 1.6e-6, "lr_means_steps": 4,
+       "lr_log_scales": 5e-3, "lr_rotors": 1e-3, "lr_opacity": 0.05, "lr_sh_dc": 2.5e-3,
+       "lr_sh_rest": 2.5e-3 / 20, "beta1": 0.9, "beta2": 0.999, "eps": 1e-15}
+
+
+# the settings as the library receives them (float32 fields)
+CFG32 = {k: (float(np.float32(v)) if isinstance(v, float) else v) for k, v in CFG.items()}
+
+
+@pytest.fixture(scope="module")
+def r4d():
+    import paper_2402_03307_amd as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def rend(r4d, device):
+    return r4d.Renderer(device)
+
+
+def _split_moments(flat, g):
+    out, off = {}, 0
+    for k in KEYS:
+        sz = g[k].size
+        out[k] = flat[off:off + sz].reshape(g[k].shape)
+        off += sz
+    return out
+
+
+def test_adam_steps_match_oracle(r4d, rend, device):
+    g = W.gaussians(3000, 3)
+    p = to_device(g, device)
+    state = r4d.TrainState(p)
+    rng = np.random.default_rng(21)
+    cur = {k: g[k].astype(np.float64) for k in KEYS}
+    cur_l = T.logit(g["opacity"].astype(np.float64))
+    m = {k: np.zeros_like(cur[k]) for k in KEYS}
+    v = {k: np.zeros_like(cur[k]) for k in KEYS}
+    steps = 6
+    for s in range(steps):
+        gr = {k: (rng.normal(size=g[k].shape) * 10.0 ** rng.uniform(-4, 0)).astype(np.float32)
+              for k in KEYS}
+        rend.adam_step(state, {k: torch.as_tensor(gr[k]).to(device) for k in KEYS}, CFG)
+        cur, cur_l, m, v = T.adam_step(cur, cur_l, gr, m, v, s, CFG32)
+    torch.cuda.synchronize()
+    assert int(state.step.item()) == steps
+    lr_max = {"means": CFG["lr_means_init"], "log_scales": CFG["lr_log_scales"],
+              "rotors": CFG["lr_rotors"], "opacity": CFG["lr_opacity"], "sh": CFG["lr_sh_dc"]}
+    for k in KEYS:
+        gp = p[k].cpu().numpy().astype(np.float64)
+        err = np.abs(gp - cur[k])
+        tol = 1e-6 * np.abs(cur[k]) + 1e-4 * lr_max[k] * steps
+        print(f"{k}: max err {err.max():.3g}")
+        bad = np.argwhere(err > tol)[:5]
+        for idx in bad:
+            idx = tuple(idx)
+            print(f"  {k}{idx}: gpu {gp[idx]!r} oracle {cur[k][idx]!r} err {err[idx]:.3g} tol {tol[idx]:.3g}")
+        assert np.all(err <= tol), k
+    gl = state.opacity_logit.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(gl - cur_l) <= 1e-6 * np.abs(cur_l) + 1e-4 * CFG["lr_opacity"] * steps)
+    gm = _split_moments(state.m.cpu().numpy().astype(np.float64), g)
+    gv = _split_moments(state.v.cpu().numpy().astype(np.float64), g)
+    for k in KEYS:
+        assert np.abs(gm[k] - m[k]).max() <= 1e-5 * np.abs(m[k]).max(), k
+        assert np.abs(gv[k] - v[k]).max() <= 1e-5 * np.abs(v[k]).max(), k
+
+
+def test_opacity_reset_matches_oracle(r4d, rend, device):
+    g = W.gaussians(5000, 0)
+    p = to_device(g, device)
+    state = r4d.TrainState(p)
+    state.m.fill_(1.0)
+    state.v.fill_(2.0)
+    l0 = state.opacity_logit.cpu().numpy().astype(np.float64)
+    rend.opacity_reset(state, 0.01)
+    torch.cuda.synchronize()
+    n = 5000
+    lr_, o, _, _ = T.opacity_reset(l0, np.ones(n), np.ones(n), 0.01)
+    assert np.allclose(p["opacity"].cpu().numpy(), o, rtol=1e-6, atol=1e-9)
+    assert np.allclose(state.opacity_logit.cpu().numpy(), lr_, rtol=1e-6, atol=1e-6)
+    mo = state.m[16 * n:17 * n]
+    assert float(mo.abs().max()) == 0.0 and float(state.v[16 * n:17 * n].abs().max()) == 0.0
+    # the other groups' moments untouched
+    assert float((state.m[:16 * n] - 1).abs().max()) == 0.0
+    assert float((state.m[17 * n:] - 1).abs().max()) == 0.0
+
+
+def test_entropy_matches_oracle(rend, device):
+    o = np.random.default_rng(22).uniform(1e-4, 1.0, 100_000).astype(np.float32)
+    ot = torch.as_tensor(o).to(device)
+    loss, grad = rend.entropy_loss_grad(ot, 0.01)
+    ref_o = torch.tensor(o.astype(np.float64), requires_grad=True)
+    ref = T.entropy_loss(ref_o)
+    ref.backward()
+    assert abs(float(loss) - float(ref)) <= 1e-5 * float(ref)
+    gg = grad.cpu().numpy().astype(np.float64)
+    gr = 0.01 * ref_o.grad.numpy()
+    assert np.abs(gg - gr).max() <= 1e-5 * np.abs(gr).max()
+    # the gradient is added
+    _, grad = rend.entropy_loss_grad(ot, 0.01, grad)
+    assert torch.allclose(grad, 2 * torch.as_tensor(gg, dtype=torch.float32, device=device),
+                          rtol=1e-6, atol=0)
+
+
+def test_fit_to_target_training_steps(r4d, rend, device):
+    """Fit a Gaussian set to the renders of a perturbed copy (two views, two
+    times): the full step -- graph-mode render, per-view L1, entropy and 4D
+    consistency terms, fused Adam -- lowers the image loss."""
+    g = W.gaussians(3000, 1)
+    views = [W.view((0.0, 0.0, -4.0), 96, 80, 90.0, 0.3), W.view((1.5, -0.5, -3.5), 80, 96, 90.0, 0.7)]
+    st = dict(W.settings(), mode="graph")
+    target_g = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in g.items()}
+    rng = np.random.default_rng(23)
+    target_g["sh"][:3] = rng.uniform(-1, 1, target_g["sh"][:3].shape).astype(np.float32)
+    target_g["means"][:3] += rng.normal(0, 0.02, (3, 3000)).astype(np.float32)
+    tp = to_device(target_g, device)
+    targets, _ = rend.forward(tp, views, dict(st, mode="per_view"), save=False, flat=True)
+    targets = targets.clone()
+    p = to_device(g, device)
+    state = r4d.TrainState(p)
+    nb = rend.knn4d(p["means"], 8)
+    cfg = dict(CFG, lr_means_steps=30000, lr_sh_dc=2e-2, lr_sh_rest=1e-3)
+    grad_img = torch.empty_like(targets)
+    losses = []
+    for it in range(60):
+        imgs, saved = rend.forward(p, views, st, save=True, flat=True)
+        loss, dl = rend.l1_loss_grad_views(imgs, targets, views, grad_img)
+        grads = rend.backward(p, views, st, saved, dl)
+        grads = {k: v.clone() for k, v in grads.items()}
+        rend.entropy_loss_grad(p["opacity"], 0.01, grads["opacity"])
+        rend.consistency4d(p, nb, 0.05, grads)
+        rend.adam_step(state, grads, cfg)
+        losses.append(float(loss))
+    torch.cuda.synchronize()
+    print(f"image loss: first {losses[0]:.4f}, last {losses[-1]:.4f}")
+    assert int(state.step.item()) == 60
+    assert losses[-1] < 0.6 * losses[0]
+    assert all(np.isfinite(losses))
+    assert float(p["opacity"].min()) > 0.0 and float(p["opacity"].max()) < 1.0
