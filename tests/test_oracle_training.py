@@ -119,3 +119,78 @@ def test_opacity_reset():
     assert np.allclose(o, [0.01, 0.005, 0.01, 0.01], rtol=1e-14, atol=0)
     assert np.allclose(T.sigmoid(lnew), o, rtol=1e-13, atol=0)
     assert not m2.any() and not v2.any()
+
+
+DCFG = {"grad_threshold": 2e-4, "size_threshold": 0.05, "min_opacity": 0.005, "max_size": 0.0}
+
+
+def _dstate(n, seed=5, k=4):
+    rng = np.random.default_rng(seed)
+    f = np.float32
+    p = {"means": rng.uniform(-1, 1, (4, n)).astype(f),
+         "log_scales": rng.normal(-3.5, 0.5, (4, n)).astype(f),
+         "rotors": rng.normal(size=(8, n)).astype(f),
+         "opacity": rng.uniform(0.01, 0.99, n).astype(f),
+         "sh": rng.normal(size=(3 * k, n)).astype(f)}
+    m = {key: rng.normal(size=p[key].shape) for key in T.GROUPS}
+    v = {key: rng.uniform(size=p[key].shape) for key in T.GROUPS}
+    return p, T.logit(p["opacity"].astype(np.float64)).astype(f), m, v
+
+
+def test_densify_hand_case():
+    p, lg, m, v = _dstate(4)
+    p["log_scales"][:3, :] = np.log(0.02)           # small ...
+    p["log_scales"][:3, 2] = np.log(0.2)            # ... except #2
+    p["opacity"][3] = 0.001                         # #3 below the prune threshold
+    accum = np.array([1e-4, 9e-4, 9e-4, 9e-4], dtype=np.float32)
+    count = np.array([1, 3, 3, 3])
+    z = np.random.default_rng(6).normal(size=(4, 8))
+    out, ol, om, ov = T.densify(p, lg, m, v, accum, count, z, DCFG)
+    # kept: 0, 1 (2 split, 3 pruned); clones: 1; children: 2, 2
+    assert out["opacity"].shape == (5,)
+    src = [0, 1, 1, 2, 2]
+    for key in ("rotors", "opacity", "sh"):
+        assert np.array_equal(out[key], p[key][..., src])
+    assert np.array_equal(out["means"][:, :3], p["means"][:, [0, 1, 1]])
+    assert np.array_equal(out["log_scales"][:, :3], p["log_scales"][:, [0, 1, 1]])
+    shrink = np.float32(math.log(1.6))
+    assert np.array_equal(out["log_scales"][:, 3:], np.repeat((p["log_scales"][:, 2:3] - shrink), 2, 1))
+    assert np.array_equal(ol, lg[src])
+    for key in T.GROUPS:
+        assert np.array_equal(om[key][..., :2], m[key][..., :2])
+        assert not om[key][..., 2:].any() and not ov[key][..., 2:].any()
+    # children at mu + R diag(s) z with the parent's (unshrunk) scales
+    from oracle import render as O
+    R = O.rotor_to_matrix(O.rotor_normalize(torch.tensor(p["rotors"][:, 2:3].T.astype(np.float64)))).numpy()[0]
+    s = np.exp(p["log_scales"][:, 2].astype(np.float64))
+    for c in range(2):
+        want = p["means"][:, 2].astype(np.float64) + R @ (s * z[:, 4 + c])
+        assert np.abs(out["means"][:, 3 + c] - want).max() < 1e-6
+
+
+def test_split_children_follow_the_4d_covariance():
+    """Children of many copies of one Gaussian sample N(mu, Sigma_4)."""
+    p, lg, m, v = _dstate(1, seed=7)
+    p["log_scales"][:, 0] = np.log([0.3, 0.1, 0.2, 0.4])
+    n = 3000
+    P = {key: np.repeat(p[key], n, axis=-1) for key in T.GROUPS}
+    M = {key: np.zeros_like(P[key], dtype=np.float64) for key in T.GROUPS}
+    z = np.random.default_rng(8).normal(size=(4, 2 * n))
+    out, _, _, _ = T.densify(P, np.repeat(lg, n), M, M, np.ones(n, np.float32), np.ones(n), z, DCFG)
+    x = out["means"].astype(np.float64)
+    assert x.shape == (4, 2 * n)
+    from oracle import render as O
+    r = O.rotor_normalize(torch.tensor(p["rotors"][:, :1].T.astype(np.float64)))
+    S4 = O.covariance_4d(O.rotor_to_matrix(r), torch.tensor(p["log_scales"][:, :1].T.astype(np.float64)))[0].numpy()
+    C = np.cov(x)
+    assert np.abs(C - S4).max() < 0.08 * np.abs(S4).max()
+    assert np.abs(x.mean(1) - p["means"][:, 0]).max() < 0.05
+
+
+def test_prune_by_size():
+    p, lg, m, v = _dstate(3, seed=9)
+    p["log_scales"][:3] = np.log(0.01)
+    p["log_scales"][1, 1] = np.log(0.5)
+    out, _, _, _ = T.densify(p, lg, m, v, np.zeros(3, np.float32), np.zeros(3), np.zeros((4, 6)),
+                             dict(DCFG, max_size=0.3))
+    assert np.array_equal(out["opacity"], p["opacity"][[0, 2]])
