@@ -371,6 +371,57 @@ r4d_status r4d_opacity_reset(r4d_ctx *ctx, const r4d_train_state *state, float c
 r4d_status r4d_entropy_loss_grad(r4d_ctx *ctx, const float *opacity, int32_t n, float weight,
                                  float *loss, float *grad_opacity, void *stream);
 
+/* ---- density control (3D Gaussian Splatting's adaptive density control,
+ * which the paper applies to its 4D Gaussians, Sec. 4) ---- */
+
+/* r4d_render_backward (or, with dL_dflows non-NULL, r4d_render_backward_flow)
+ * that also accumulates the densification statistics: for every render in
+ * which Gaussian i is listed in some tile,
+ *   grad_accum[i] += || (dL/dmean2d.x * W/2, dL/dmean2d.y * H/2) ||
+ * (the projected-mean gradient in normalised device coordinates) and
+ * vis_count[i] += 1.  grad_accum: DEVICE float [n]; vis_count: DEVICE int32
+ * [n]; both added to (the caller zeroes them when a statistics period starts). */
+r4d_status r4d_render_backward_stats(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
+                                     int n_views, const r4d_settings *settings,
+                                     const r4d_saved *saved, const float *dL_dimages,
+                                     const float *dL_dflows, r4d_grads *out, float *grad_accum,
+                                     int32_t *vis_count, void *stream);
+
+typedef struct {
+  float grad_threshold;  /* densify when accum / count >= this (2e-4)         */
+  float size_threshold;  /* clone when the largest spatial scale <= this,
+                            else split (0.01; 3DGS: 0.01 x scene extent)       */
+  float min_opacity;     /* drop Gaussians with opacity below this (0.005)     */
+  float max_size;        /* drop Gaussians whose largest spatial scale exceeds
+                            this; 0 disables (0)                               */
+} r4d_densify_config;
+void r4d_default_densify_config(r4d_densify_config *c);
+
+/* Clone, split and prune.  Decisions in float32 on the stored values:
+ * selected = count > 0 and accum / count >= grad_threshold; a selected
+ * Gaussian whose largest spatial log-scale <= fl(ln size_threshold) is cloned
+ * (identical copy, zero moments); a larger one is split into 2 children
+ * placed at mu + R diag(s) z_c (mu the 4D mean, R the rotor's 4x4 rotation, s
+ * the scales, z_c = normals[:, 2i + c]), log-scales reduced by fl(ln 1.6),
+ * everything else copied, zero moments, the parent removed.  Every result is
+ * then dropped if its opacity < min_opacity or (max_size > 0 and its largest
+ * spatial log-scale > fl(ln max_size)).  Order of the new set: surviving
+ * originals (moments kept), then clones, then children (two per parent), each
+ * in index order.
+ *   in       the current train state (read)
+ *   normals  DEVICE float [4][2 n] standard normal draws (the caller's random
+ *            numbers)
+ *   out      a second train state: out->n is its capacity in Gaussians (every
+ *            array sized for it, e.g. 2 n, which always suffices); the new set
+ *            is written with row stride *n_out; out->step receives in->step
+ *   n_out    HOST: the new Gaussian count
+ * Synchronises with `stream` once (to learn the count).  R4D_ERR_CAPACITY with
+ * *n_out = the count needed when it exceeds the capacity (nothing written). */
+r4d_status r4d_densify(r4d_ctx *ctx, const r4d_train_state *in, const float *grad_accum,
+                       const int32_t *vis_count, const float *normals,
+                       const r4d_densify_config *cfg, const r4d_train_state *out,
+                       int32_t *n_out, void *stream);
+
 /* Returns the saved arena to its context's cache.  NULL is ignored.  A saved
  * handle may outlive its context: r4d_destroy frees its device memory and a
  * later release only frees the handle. */

@@ -47,7 +47,8 @@ EXPORTED_SYMBOLS = (
     "r4d_render_forward_flow", "r4d_render_backward_flow", "r4d_render_forward_flow_f64",
     "r4d_render_backward_flow_f64", "r4d_knn4d", "r4d_consistency4d_loss_grad",
     "r4d_consistency4d_loss_grad_f64", "r4d_default_adam_config", "r4d_adam_step",
-    "r4d_opacity_reset", "r4d_entropy_loss_grad", "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
+    "r4d_opacity_reset", "r4d_entropy_loss_grad", "r4d_render_backward_stats",
+    "r4d_default_densify_config", "r4d_densify", "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
     "r4d_saved_copy", "r4d_saved_check", "r4d_saved_config", "r4d_status_string",
     "r4d_last_error", "r4d_set_timing", "r4d_get_timings", "r4d_stage_name",
 )
@@ -91,6 +92,11 @@ class _TrainState(ctypes.Structure):
     _fields_ = [("n", c_i32), ("sh_degree", c_i32), ("means", c_vp), ("log_scales", c_vp),
                 ("rotors", c_vp), ("opacity", c_vp), ("sh", c_vp), ("opacity_logit", c_vp),
                 ("adam_m", c_vp), ("adam_v", c_vp), ("step", c_vp)]
+
+
+class _DensifyConfig(ctypes.Structure):
+    _fields_ = [("grad_threshold", c_f32), ("size_threshold", c_f32), ("min_opacity", c_f32),
+                ("max_size", c_f32)]
 
 
 class _Grads(ctypes.Structure):
@@ -144,6 +150,15 @@ def _load():
     lib.r4d_opacity_reset.restype = ctypes.c_int
     lib.r4d_entropy_loss_grad.argtypes = [c_vp, c_vp, c_i32, c_f32, c_vp, c_vp, c_vp]
     lib.r4d_entropy_loss_grad.restype = ctypes.c_int
+    lib.r4d_render_backward_stats.argtypes = [c_vp, P(_Gaussians), P(_View), ctypes.c_int,
+                                              P(_Settings), c_vp, c_vp, c_vp, P(_Grads), c_vp,
+                                              c_vp, c_vp]
+    lib.r4d_render_backward_stats.restype = ctypes.c_int
+    lib.r4d_default_densify_config.argtypes = [P(_DensifyConfig)]
+    lib.r4d_default_densify_config.restype = None
+    lib.r4d_densify.argtypes = [c_vp, P(_TrainState), c_vp, c_vp, c_vp, P(_DensifyConfig),
+                                P(_TrainState), P(c_i32), c_vp]
+    lib.r4d_densify.restype = ctypes.c_int
     lib.r4d_saved_release.argtypes = [c_vp]
     lib.r4d_saved_release.restype = None
     lib.r4d_l1_loss_grad.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]
@@ -423,7 +438,7 @@ class Renderer:
         return (images, _split(fout, views, 2), saved) if flow else (images, saved)
 
     def backward(self, params: dict, views, settings: dict | None, saved: SavedState,
-                 grad_images, grad_flows=None) -> dict:
+                 grad_images, grad_flows=None, stats=None) -> dict:
         """Gradients w.r.t. the five parameter tensors.  grad_images (and
         grad_flows, for the saved state of a flow render): list of [3, H, W]
         ([2, H, W]) tensors or one flat tensor in the forward's layout.  In graph
@@ -438,6 +453,16 @@ class Renderer:
         grads = {k: self._buffer(("grad", k, dtype, n), tuple(params[k].shape), dtype, graph)
                  for k in _PARAM_KEYS}
         gs = _Grads(*[_ptr(grads[k]) for k in _PARAM_KEYS])
+        if stats is not None:
+            # densification statistics (grad_accum float [n], vis_count int32 [n]), added to
+            accum, count = stats
+            dlf = _flat(grad_flows, dtype) if grad_flows is not None else None
+            status = _lib.r4d_render_backward_stats(
+                self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st), saved.handle,
+                _ptr(dl), _ptr(dlf), ctypes.byref(gs), _ptr(accum), _ptr(count),
+                _stream(self.device))
+            self._check(status, "r4d_render_backward_stats")
+            return grads
         if grad_flows is not None:
             dlf = _flat(grad_flows, dtype)
             fn = (_lib.r4d_render_backward_flow if dtype == torch.float32
@@ -510,6 +535,44 @@ class Renderer:
         st = _lib.r4d_adam_step(self.handle, ctypes.byref(state.struct()), ctypes.byref(gs),
                                 ctypes.byref(cfg), _stream(self.device))
         self._check(st, "r4d_adam_step")
+
+    def densify(self, state: "TrainState", grad_accum: torch.Tensor, vis_count: torch.Tensor,
+                normals: torch.Tensor, config: dict | None = None) -> "TrainState":
+        """Clone / split / prune (r4d_densify); returns the new TrainState (its
+        tensors freshly allocated).  normals: [4, 2n] float32 N(0, 1) draws."""
+        n, deg = state.n, state.deg
+        cap = max(2 * n, 1)
+        dev = state.params["means"].device
+        rows = {k: int(state.params[k].shape[0]) if state.params[k].dim() == 2 else 1
+                for k in _PARAM_KEYS}
+        flat = {k: torch.empty(rows[k] * cap, dtype=torch.float32, device=dev) for k in _PARAM_KEYS}
+        total_rows = sum(rows.values())
+        logit = torch.empty(cap, dtype=torch.float32, device=dev)
+        m = torch.empty(total_rows * cap, dtype=torch.float32, device=dev)
+        v = torch.empty(total_rows * cap, dtype=torch.float32, device=dev)
+        step = torch.zeros(1, dtype=torch.int32, device=dev)
+        out = _TrainState(cap, deg, *[_ptr(flat[k]) for k in _PARAM_KEYS], _ptr(logit), _ptr(m),
+                          _ptr(v), _ptr(step))
+        cfg = _DensifyConfig()
+        _lib.r4d_default_densify_config(ctypes.byref(cfg))
+        for key, val in (config or {}).items():
+            setattr(cfg, key, val)
+        n_out = c_i32()
+        st = _lib.r4d_densify(self.handle, ctypes.byref(state.struct()), _ptr(grad_accum),
+                              _ptr(vis_count), _ptr(normals.contiguous()), ctypes.byref(cfg),
+                              ctypes.byref(out), ctypes.byref(n_out), _stream(self.device))
+        self._check(st, "r4d_densify")
+        k = n_out.value
+        params = {key: (flat[key][:rows[key] * k].view(rows[key], k) if state.params[key].dim() == 2
+                        else flat[key][:k]) for key in _PARAM_KEYS}
+        params["sh_degree"] = deg
+        new = TrainState.__new__(TrainState)
+        new.params, new.n, new.deg = params, k, deg
+        new.opacity_logit = logit[:k]
+        new.m = m[:total_rows * k]
+        new.v = v[:total_rows * k]
+        new.step = step
+        return new
 
     def opacity_reset(self, state: "TrainState", cap: float = 0.01):
         st = _lib.r4d_opacity_reset(self.handle, ctypes.byref(state.struct()), float(cap),

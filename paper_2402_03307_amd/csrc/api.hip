@@ -717,10 +717,17 @@ r4d_status init_run(r4d_ctx* ctx, RunState& r, const Plan& p) {
 size_t grad_comps(const Plan& p, bool flow_grads) { return p.flow && flow_grads ? 11 : 9; }
 
 // dLf: the flow images' gradient (flow runs; null = colour loss only).
+// Densification statistics accumulated by a backward (both null: none).
+struct StatsOut {
+  float* accum = nullptr;
+  int32_t* count = nullptr;
+};
+
 template <typename T>
 r4d_status enqueue_backward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, const T* dL,
                             const T* dLf, uint8_t* bwd_block, const SettingsDev& st,
-                            const GradPtrs<T>& out, bool timed, hipStream_t stream) {
+                            const GradPtrs<T>& out, bool timed, hipStream_t stream,
+                            StatsOut stats = StatsOut{}) {
   const Plan& p = r.plan;
   uint8_t* F = r.fixed;
   if (dLf && !p.flow) return fail(ctx, R4D_ERR_STATE, "flow gradients for a render without flow");
@@ -737,6 +744,9 @@ r4d_status enqueue_backward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, co
                                  bwd_items(p, r.capacity), p.ts, st, p.bppt,
                                  at<T>(F, r.L.T_final), at<uint32_t>(F, r.L.n_contrib), sv, dL,
                                  dLf, grad2d, work, stream));
+  if (stats.accum)
+    R4D_HIP(launch_densify_stats(grad2d, int(nc), at<uint32_t>(F, r.L.dkeys), p.n_pad,
+                                 slots_of(F, r.L), p.V, p.n, stats.accum, stats.count, stream));
   R4D_TIMED(kPreprocessBwd, launch_preprocess_bwd<T>(g, slots_of(F, r.L), p.V, st, grad2d,
                                                      nc == 11, out, stream));
   return R4D_OK;
@@ -1072,7 +1082,8 @@ bool same_view(const r4d_view& a, const r4d_view& b) {
 template <typename T>
 r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
                          int n_views, const r4d_settings* settings, const r4d_saved* saved,
-                         const T* dL, const T* dLf, const GradPtrs<T>& out, hipStream_t stream) {
+                         const T* dL, const T* dLf, const GradPtrs<T>& out, hipStream_t stream,
+                         StatsOut stats = StatsOut{}) {
   if (!views || n_views < 1 || !dL || !valid_settings(settings) || !saved)
     return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, gradients, settings or saved state");
   r4d_status s = check_gaussians(ctx, g);
@@ -1097,9 +1108,10 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   const bool timed = ctx->timing && !saved->graph;
   if (saved->graph) {
     GraphEntry* e = saved->graph;
-    char buf[256];
-    snprintf(buf, sizeof(buf), "%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p", (const void*)dL,
-             (const void*)dLf, (const void*)out.means, (const void*)out.log_scales, (const void*)out.rotors,
+    char buf[320];
+    snprintf(buf, sizeof(buf), "%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p", (const void*)dL,
+             (const void*)dLf, (const void*)stats.accum, (const void*)stats.count,
+             (const void*)out.means, (const void*)out.log_scales, (const void*)out.rotors,
              (const void*)out.opacity, (const void*)out.sh, (const void*)g.means,
              (const void*)g.log_scales, (const void*)g.rotors, (const void*)g.opacity,
              (const void*)g.sh, (const void*)e->run.fixed);
@@ -1116,7 +1128,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
       hipStream_t cs = ctx->capture_stream;
       R4D_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       r4d_status cst =
-          enqueue_backward<T>(ctx, g, e->run, dL, dLf, e->bwd_block, st, out, false, cs);
+          enqueue_backward<T>(ctx, g, e->run, dL, dLf, e->bwd_block, st, out, false, cs, stats);
       hipGraph_t graph = nullptr;
       const hipError_t end = hipStreamEndCapture(cs, &graph);
       if (cst != R4D_OK) {
@@ -1137,7 +1149,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
     uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan, r.capacity)));
     if (!bb) return fail(ctx, R4D_ERR_OOM, "backward buffers");
     s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, dLf ? dLf + r.flow_offset : nullptr,
-                            bb, st, out, timed, stream);
+                            bb, st, out, timed, stream, stats);
     ctx_free(ctx, bb);
     return s;
   }
@@ -1156,7 +1168,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
       break;
     }
     s = enqueue_backward<T>(ctx, g, r, dL + r.image_offset, dLf ? dLf + r.flow_offset : nullptr,
-                            bb, st, ri == 0 ? out : gt, timed, stream);
+                            bb, st, ri == 0 ? out : gt, timed, stream, stats);
     ctx_free(ctx, bb);
     if (s == R4D_OK && ri > 0) {
       const hipError_t e = add_grads<T>(out, tmp, n, k3, stream);
@@ -1497,6 +1509,106 @@ r4d_status r4d_entropy_loss_grad(r4d_ctx* ctx, const float* opacity, int32_t n, 
                                       static_cast<hipStream_t>(stream));
   ctx_free(ctx, temp);
   if (e != hipSuccess) return fail(ctx, R4D_ERR_HIP, "entropy launch: %s", hipGetErrorString(e));
+  return R4D_OK;
+}
+
+r4d_status r4d_render_backward_stats(r4d_ctx* ctx, const r4d_gaussians* g,
+                                     const r4d_view* views, int n_views,
+                                     const r4d_settings* settings, const r4d_saved* saved,
+                                     const float* dL_dimages, const float* dL_dflows,
+                                     r4d_grads* out, float* grad_accum, int32_t* vis_count,
+                                     void* stream) {
+  if (!ctx || !g || !out)
+    return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  if (g->n > 0 && (!grad_accum || !vis_count))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "null statistics array");
+  const GradPtrs<float> o{out->means, out->log_scales, out->rotors, out->opacity, out->sh};
+  return backward_impl<float>(ctx, gauss_of(g), views, n_views, settings, saved, dL_dimages,
+                              dL_dflows, o, static_cast<hipStream_t>(stream),
+                              StatsOut{grad_accum, vis_count});
+}
+
+void r4d_default_densify_config(r4d_densify_config* c) {
+  if (!c) return;
+  c->grad_threshold = 2e-4f;
+  c->size_threshold = 0.01f;
+  c->min_opacity = 0.005f;
+  c->max_size = 0.0f;
+}
+
+r4d_status r4d_densify(r4d_ctx* ctx, const r4d_train_state* in, const float* grad_accum,
+                       const int32_t* vis_count, const float* normals,
+                       const r4d_densify_config* cfg, const r4d_train_state* out, int32_t* n_out,
+                       void* stream_) {
+  if (!ctx) return R4D_ERR_INVALID_ARG;
+  if (!in || !out || !cfg || !n_out || !grad_accum || !vis_count || !normals)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "null argument");
+  if (in->n < 0 || in->sh_degree < 0 || in->sh_degree > 3 || out->sh_degree != in->sh_degree ||
+      out->n < 0)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid Gaussian counts or SH degrees");
+  if (!(cfg->grad_threshold >= 0.f) || !(cfg->size_threshold > 0.f) || !(cfg->max_size >= 0.f) ||
+      !std::isfinite(cfg->min_opacity))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid densification settings");
+  const float* pin[5] = {in->means, in->log_scales, in->rotors, in->opacity, in->sh};
+  float* pout[5] = {out->means, out->log_scales, out->rotors, out->opacity, out->sh};
+  for (int q = 0; q < 5; ++q)
+    if ((in->n > 0 && !pin[q]) || (out->n > 0 && !pout[q]))
+      return fail(ctx, R4D_ERR_INVALID_ARG, "null parameter array");
+  if ((in->n > 0 && (!in->opacity_logit || !in->adam_m || !in->adam_v || !in->step)) ||
+      (out->n > 0 && (!out->opacity_logit || !out->adam_m || !out->adam_v)) || !out->step)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "null optimiser array");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  R4D_HIP(hipSetDevice(ctx->device));
+  *n_out = 0;
+  if (in->n == 0) return R4D_OK;
+  const uint32_t k3 = 3 * uint32_t((in->sh_degree + 1) * (in->sh_degree + 1));
+  DensifyArgs d{};
+  d.n_in = uint32_t(in->n);
+  d.log_scales = in->log_scales;
+  d.opacity = in->opacity;
+  d.accum = grad_accum;
+  d.count = vis_count;
+  d.normals = normals;
+  d.grad_threshold = cfg->grad_threshold;
+  d.size_log = float(std::log(double(cfg->size_threshold)));
+  d.min_opacity = cfg->min_opacity;
+  d.has_big = cfg->max_size > 0.f ? 1 : 0;
+  d.big_log = d.has_big ? float(std::log(double(cfg->max_size))) : 0.f;
+  d.shrink = float(std::log(1.6));
+  const uint32_t rows[5] = {4, 4, 8, 1, k3};
+  for (int q = 0; q < 5; ++q) {
+    d.pin[q] = pin[q];
+    d.pout[q] = pout[q];
+    d.rows[q] = rows[q];
+  }
+  d.logit_in = in->opacity_logit;
+  d.logit_out = out->opacity_logit;
+  d.m_in = in->adam_m;
+  d.v_in = in->adam_v;
+  d.m_out = out->adam_m;
+  d.v_out = out->adam_v;
+  void* temp = ctx_alloc(ctx, densify_temp_bytes(d.n_in));
+  if (!temp) return fail(ctx, R4D_ERR_OOM, "densification buffers");
+  struct Free {
+    r4d_ctx* c;
+    void* p;
+    ~Free() { ctx_free(c, p); }
+  } guard{ctx, temp};
+  // the three totals come back through the context's pinned read-back words
+  uint32_t* totals = reinterpret_cast<uint32_t*>(ctx->readback);
+  R4D_HIP(densify_count(d, temp, totals, stream));
+  R4D_HIP(hipStreamSynchronize(stream));
+  const uint64_t total = uint64_t(totals[0]) + totals[1] + totals[2];
+  const uint32_t keep = totals[0], clone = totals[1];
+  if (total > uint64_t(out->n)) {
+    *n_out = int32_t(total);
+    return fail(ctx, R4D_ERR_CAPACITY, "densification makes %llu Gaussians, capacity %d",
+                (unsigned long long)total, out->n);
+  }
+  *n_out = int32_t(total);
+  R4D_HIP(hipMemcpyAsync(out->step, in->step, sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+  if (total == 0) return R4D_OK;
+  R4D_HIP(densify_scatter(d, temp, keep, clone, uint32_t(total), stream));
   return R4D_OK;
 }
 

@@ -297,6 +297,42 @@ size_t entropy_temp_bytes(uint32_t n);
 hipError_t launch_entropy(const float* opacity, uint32_t n, float weight, float* loss, float* grad,
                           void* temp, hipStream_t stream);
 
+// ---- density control
+// accum[i] += sum over the renders where Gaussian i is listed (dkeys not
+// 0xffffffff) of the NDC norm of its projected-mean gradient (grad2d
+// components 0, 1 of C = nc per render); count[i] += those renders.
+hipError_t launch_densify_stats(const double* grad2d, int nc, const uint32_t* dkeys,
+                                uint32_t n_pad, const ViewSlot* slots, int n_views, uint32_t n,
+                                float* accum, int32_t* count, hipStream_t stream);
+
+// Clone / split / prune (see r4d_densify).  densify_count classifies and scans
+// and copies the three totals (kept, clones, children) to pinned host memory;
+// after they have arrived, densify_scatter writes the new set.
+struct DensifyArgs {
+  uint32_t n_in;
+  const float* log_scales;
+  const float* opacity;
+  const float* accum;
+  const int32_t* count;
+  const float* normals;
+  float grad_threshold, size_log, min_opacity, big_log, shrink;
+  int has_big;
+  const float* pin[5];
+  float* pout[5];
+  uint32_t rows[5];
+  const float* logit_in;
+  float* logit_out;
+  const float* m_in;
+  const float* v_in;
+  float* m_out;
+  float* v_out;
+};
+size_t densify_temp_bytes(uint32_t n);
+hipError_t densify_count(const DensifyArgs& d, void* temp, uint32_t* totals_host,
+                         hipStream_t stream);
+hipError_t densify_scatter(const DensifyArgs& d, const void* temp, uint32_t total_keep,
+                           uint32_t total_clone, uint32_t n_out, hipStream_t stream);
+
 // ---- small helpers
 // p[0..count) = value (float or double elements).
 hipError_t fill_const(void* p, size_t count, double value, bool f64, hipStream_t stream);

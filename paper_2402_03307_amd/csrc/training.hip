@@ -163,3 +163,229 @@ hipError_t launch_entropy(const float* opacity, uint32_t n, float weight, float*
 }
 
 }  // namespace r4d
+
+// ---- density control (3D Gaussian Splatting's, applied to 4D Gaussians)
+
+namespace r4d {
+
+namespace {
+
+// Per Gaussian, over the renders where it is listed in some tile: the norm of
+// the projected-mean gradient in normalised device coordinates (pixel
+// gradient times (W/2, H/2)) added to accum, and the count of such renders.
+__global__ __launch_bounds__(kBlock) void densify_stats_kernel(
+    const double* __restrict__ grad2d, int nc, const uint32_t* __restrict__ dkeys, uint32_t n_pad,
+    const ViewSlot* __restrict__ slots, int n_views, uint32_t n, float* __restrict__ accum,
+    int32_t* __restrict__ count) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  int32_t c = 0;
+  for (int v = 0; v < n_views; ++v) {
+    if (dkeys[size_t(v) * n_pad + i] == 0xffffffffu) continue;
+    const double* g = grad2d + size_t(v) * size_t(nc) * n;
+    const double gx = g[i] * (0.5 * double(slots[v].v.W));
+    const double gy = g[size_t(n) + i] * (0.5 * double(slots[v].v.H));
+    a += sqrt(gx * gx + gy * gy);
+    c += 1;
+  }
+  if (c) {
+    accum[i] += float(a);
+    count[i] += c;
+  }
+}
+
+struct DensifyDev {
+  float grad_threshold, size_log, min_opacity, big_log, shrink;
+  int has_big;
+};
+
+__device__ __forceinline__ bool survives(float o, float max_log_scale, const DensifyDev& c) {
+  return !(o < c.min_opacity) && !(c.has_big && max_log_scale > c.big_log);
+}
+
+// Per Gaussian: how many copies it keeps (0 / 1), clones (0 / 1) and children
+// (0 / 2) contribute to the new set.
+__global__ __launch_bounds__(kBlock) void densify_classify_kernel(
+    const float* __restrict__ log_scales, const float* __restrict__ opacity,
+    const float* __restrict__ accum, const int32_t* __restrict__ count, uint32_t n, DensifyDev c,
+    uint32_t* __restrict__ n_keep, uint32_t* __restrict__ n_clone, uint32_t* __restrict__ n_child) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t cnt = count[i];
+  const float avg = cnt > 0 ? accum[i] / float(cnt) : 0.f;
+  const bool selected = cnt > 0 && avg >= c.grad_threshold;
+  const float l0 = log_scales[i], l1 = log_scales[size_t(n) + i], l2 = log_scales[2 * size_t(n) + i];
+  const float mls = fmaxf(fmaxf(l0, l1), l2);
+  const bool small = mls <= c.size_log;
+  const bool split = selected && !small;
+  const float o = opacity[i];
+  const bool ok = survives(o, mls, c);
+  const float cm = fmaxf(fmaxf(l0 - c.shrink, l1 - c.shrink), l2 - c.shrink);
+  n_keep[i] = (!split && ok) ? 1u : 0u;
+  n_clone[i] = (selected && small && ok) ? 1u : 0u;
+  n_child[i] = (split && survives(o, cm, c)) ? 2u : 0u;
+}
+
+struct DensifyIO {
+  // parameter groups in / out (means, log_scales, rotors, opacity, sh)
+  const float* pin[5];
+  float* pout[5];
+  uint32_t rows[5];
+  const float* logit_in;
+  float* logit_out;
+  const float* m_in;
+  const float* v_in;
+  float* m_out;
+  float* v_out;
+  uint32_t n_in, n_out;
+};
+
+__global__ __launch_bounds__(kBlock) void densify_scatter_kernel(
+    DensifyIO io, const uint32_t* __restrict__ off_keep, const uint32_t* __restrict__ off_clone,
+    const uint32_t* __restrict__ off_child, uint32_t total_keep, uint32_t total_clone,
+    const float* __restrict__ normals, DensifyDev c) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= io.n_in) return;
+  const uint32_t nk = off_keep[i + 1] - off_keep[i];
+  const uint32_t nc = off_clone[i + 1] - off_clone[i];
+  const uint32_t nh = off_child[i + 1] - off_child[i];
+  if (!(nk | nc | nh)) return;
+  const size_t ni = io.n_in, no = io.n_out;
+  // destinations: the kept copy (moments carried), the clone, the children
+  const uint32_t dk = off_keep[i];
+  const uint32_t dc = total_keep + off_clone[i];
+  const uint32_t dh = total_keep + total_clone + off_child[i];
+  size_t base_in = 0, base_out = 0;  // group's first element in the moment arrays
+  for (int q = 0; q < 5; ++q) {
+    for (uint32_t r = 0; r < io.rows[q]; ++r) {
+      const float x = io.pin[q][r * ni + i];
+      if (nk) {
+        io.pout[q][r * no + dk] = x;
+        io.m_out[base_out + r * no + dk] = io.m_in[base_in + r * ni + i];
+        io.v_out[base_out + r * no + dk] = io.v_in[base_in + r * ni + i];
+      }
+      if (nc) {
+        io.pout[q][r * no + dc] = x;
+        io.m_out[base_out + r * no + dc] = 0.f;
+        io.v_out[base_out + r * no + dc] = 0.f;
+      }
+      if (nh) {
+        for (uint32_t h = 0; h < 2; ++h) {
+          float y = x;
+          if (q == 1) y = x - c.shrink;  // log-scales of a child
+          io.pout[q][r * no + dh + h] = y;  // means are overwritten below
+          io.m_out[base_out + r * no + dh + h] = 0.f;
+          io.v_out[base_out + r * no + dh + h] = 0.f;
+        }
+      }
+    }
+    base_in += size_t(io.rows[q]) * ni;
+    base_out += size_t(io.rows[q]) * no;
+  }
+  const float lg = io.logit_in[i];
+  if (nk) io.logit_out[dk] = lg;
+  if (nc) io.logit_out[dc] = lg;
+  if (nh) {
+    io.logit_out[dh] = lg;
+    io.logit_out[dh + 1] = lg;
+    // children at mu + R diag(s) z_h, R the normalised rotor's rotation and s
+    // the parent's scales
+    float ls[4], rot[8];
+    for (int k = 0; k < 4; ++k) ls[k] = io.pin[1][k * ni + i];
+    for (int k = 0; k < 8; ++k) rot[k] = io.pin[2][k * ni + i];
+    Fwd<float> f;
+    cov4_fwd(ls, rot, f);
+    for (uint32_t h = 0; h < 2; ++h) {
+      float sz[4];
+      for (int k = 0; k < 4; ++k)
+        sz[k] = expf(ls[k]) * normals[size_t(k) * 2 * ni + 2 * size_t(i) + h];
+      for (int row = 0; row < 4; ++row) {
+        float acc = io.pin[0][row * ni + i];
+        for (int k = 0; k < 4; ++k) acc += f.R[4 * row + k] * sz[k];
+        io.pout[0][row * no + dh + h] = acc;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_densify_stats(const double* grad2d, int nc, const uint32_t* dkeys,
+                                uint32_t n_pad, const ViewSlot* slots, int n_views, uint32_t n,
+                                float* accum, int32_t* count, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(densify_stats_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     stream, grad2d, nc, dkeys, n_pad, slots, n_views, n, accum, count);
+  return hipGetLastError();
+}
+
+size_t densify_temp_bytes(uint32_t n) {
+  auto a = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return 6 * a((size_t(n) + 1) * 4) + 3 * a(scan_u32_temp_bytes(n)) + 256;
+}
+
+hipError_t densify_count(const DensifyArgs& d, void* temp, uint32_t* totals_host,
+                         hipStream_t stream) {
+  auto a = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const uint32_t n = d.n_in;
+  uint8_t* p = static_cast<uint8_t*>(temp);
+  uint32_t* cnt[3];
+  uint32_t* off[3];
+  void* scr[3];
+  for (int q = 0; q < 3; ++q) {
+    cnt[q] = reinterpret_cast<uint32_t*>(p);
+    p += a((size_t(n) + 1) * 4);
+    off[q] = reinterpret_cast<uint32_t*>(p);
+    p += a((size_t(n) + 1) * 4);
+    scr[q] = p;
+    p += a(scan_u32_temp_bytes(n));
+  }
+  const DensifyDev c{d.grad_threshold, d.size_log, d.min_opacity, d.big_log, d.shrink, d.has_big};
+  hipLaunchKernelGGL(densify_classify_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     stream, d.log_scales, d.opacity, d.accum, d.count, n, c, cnt[0], cnt[1],
+                     cnt[2]);
+  for (int q = 0; q < 3; ++q) {
+    const hipError_t e = scan_u32(cnt[q], n, off[q], scr[q], stream);
+    if (e != hipSuccess) return e;
+  }
+  for (int q = 0; q < 3; ++q) {
+    const hipError_t e = hipMemcpyAsync(totals_host + q, off[q] + n, 4, hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t densify_scatter(const DensifyArgs& d, const void* temp, uint32_t total_keep,
+                           uint32_t total_clone, uint32_t n_out, hipStream_t stream) {
+  auto a = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const uint32_t n = d.n_in;
+  const uint8_t* p = static_cast<const uint8_t*>(temp);
+  const uint32_t* off[3];
+  for (int q = 0; q < 3; ++q) {
+    p += a((size_t(n) + 1) * 4);
+    off[q] = reinterpret_cast<const uint32_t*>(p);
+    p += a((size_t(n) + 1) * 4);
+    p += a(scan_u32_temp_bytes(n));
+  }
+  DensifyIO io{};
+  for (int q = 0; q < 5; ++q) {
+    io.pin[q] = d.pin[q];
+    io.pout[q] = d.pout[q];
+    io.rows[q] = d.rows[q];
+  }
+  io.logit_in = d.logit_in;
+  io.logit_out = d.logit_out;
+  io.m_in = d.m_in;
+  io.v_in = d.v_in;
+  io.m_out = d.m_out;
+  io.v_out = d.v_out;
+  io.n_in = n;
+  io.n_out = n_out;
+  const DensifyDev c{d.grad_threshold, d.size_log, d.min_opacity, d.big_log, d.shrink, d.has_big};
+  hipLaunchKernelGGL(densify_scatter_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     stream, io, off[0], off[1], off[2], total_keep, total_clone, d.normals, c);
+  return hipGetLastError();
+}
+
+}  // namespace r4d

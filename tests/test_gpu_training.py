@@ -162,3 +162,98 @@ def test_fit_to_target_training_steps(r4d, rend, device):
     assert losses[-1] < 0.6 * losses[0]
     assert all(np.isfinite(losses))
     assert float(p["opacity"].min()) > 0.0 and float(p["opacity"].max()) < 1.0
+
+
+DCFG = {"grad_threshold": 2e-4, "size_threshold": 0.05, "min_opacity": 0.005, "max_size": 0.3}
+
+
+def test_densify_matches_oracle(r4d, rend, device):
+    n = 4000
+    g = W.gaussians(n, 1)
+    rng = np.random.default_rng(31)
+    g["log_scales"][:3] += rng.normal(0.6, 1.0, (3, n)).astype(np.float32)   # small and large
+    g["opacity"][rng.choice(n, 200, replace=False)] = 0.002                    # some to prune
+    p = to_device(g, device)
+    state = r4d.TrainState(p)
+    lg = T.logit(g["opacity"].astype(np.float64)).astype(np.float32)
+    state.opacity_logit.copy_(torch.as_tensor(lg))
+    total = state.m.numel()
+    m = rng.normal(size=total).astype(np.float32)
+    v = rng.uniform(size=total).astype(np.float32)
+    state.m.copy_(torch.as_tensor(m))
+    state.v.copy_(torch.as_tensor(v))
+    state.step.fill_(17)
+    accum = (rng.uniform(0, 8e-4, n) * rng.integers(1, 4, n)).astype(np.float32)
+    count = rng.integers(0, 4, n).astype(np.int32)
+    normals = rng.normal(size=(4, 2 * n)).astype(np.float32)
+    new = rend.densify(state, torch.as_tensor(accum).to(device), torch.as_tensor(count).to(device),
+                       torch.as_tensor(normals).to(device), DCFG)
+    torch.cuda.synchronize()
+    ms = _split_moments(m, g)
+    vs = _split_moments(v, g)
+    ref, ref_l, ref_m, ref_v = T.densify(g, lg, ms, vs, accum, count, normals, DCFG)
+    n_out = ref["opacity"].shape[0]
+    print(f"densify: {n} -> {n_out} Gaussians (gpu {new.n})")
+    assert new.n == n_out and n_out != n
+    assert int(new.step.item()) == 17
+    for k in KEYS:
+        got = new.params[k].cpu().numpy()
+        if k == "means":
+            # originals and clones are copies (exact); children are sampled in
+            # float32: mu + R diag(s) z to a few roundings of |mu| + |R s z|
+            err = np.abs(got.astype(np.float64) - ref[k])
+            assert err.max() <= 1e-5, err.max()
+            kept = (ref_m["means"] != 0).any(axis=0)   # kept originals carry their moments
+            assert kept.sum() > 0.2 * n
+            assert np.array_equal(got[:, kept], ref[k][:, kept].astype(np.float32))
+        else:
+            assert np.array_equal(got, ref[k]), k
+    assert np.array_equal(new.opacity_logit.cpu().numpy(), ref_l.astype(np.float32))
+    gm = _split_moments(new.m.cpu().numpy(), ref)
+    gv = _split_moments(new.v.cpu().numpy(), ref)
+    for k in KEYS:
+        assert np.array_equal(gm[k], ref_m[k].astype(np.float32)), k
+        assert np.array_equal(gv[k], ref_v[k].astype(np.float32)), k
+
+
+def test_densify_capacity_and_identity(r4d, rend, device):
+    g = W.gaussians(500, 0)
+    p = to_device(g, device)
+    state = r4d.TrainState(p)
+    zero = torch.zeros(500, dtype=torch.float32, device=device)
+    cnt = torch.zeros(500, dtype=torch.int32, device=device)
+    normals = torch.zeros(4, 1000, dtype=torch.float32, device=device)
+    # nothing selected or pruned: the same set
+    new = rend.densify(state, zero, cnt, normals, dict(DCFG, max_size=0.0, min_opacity=0.0))
+    assert new.n == 500
+    for k in KEYS:
+        assert torch.equal(new.params[k], p[k]), k
+    assert torch.equal(new.m, state.m)
+
+
+def test_backward_statistics_vs_oracle(r4d, rend, device):
+    from oracle import render as O
+    g, views, st = W.scene_fd_subset()
+    weight = np.random.default_rng(2).uniform(-1, 1, (3, 32, 32))
+    ref = O.render(g, views[0], st, requires_grad=True)
+    ref["pre"]["mean2"].retain_grad()
+    (ref["image"] * torch.as_tensor(weight)).sum().backward()
+    inc = T.densify_stat_increment(ref["pre"]["mean2"].grad.numpy(), 32, 32)
+    p = to_device(g, device)
+    n = g["opacity"].shape[0]
+    accum = torch.zeros(n, dtype=torch.float32, device=device)
+    count = torch.zeros(n, dtype=torch.int32, device=device)
+    w = torch.as_tensor(weight, dtype=torch.float32, device=device)
+    for _ in range(2):
+        _, saved = rend.forward(p, views, st)
+        rend.backward(p, views, st, saved, [w], stats=(accum, count))
+    torch.cuda.synchronize()
+    a = accum.cpu().numpy().astype(np.float64) / 2
+    c = count.cpu().numpy()
+    assert set(np.unique(c)) <= {0, 2}
+    listed = c == 2
+    assert listed.sum() >= 10
+    assert np.all(inc[~listed] == 0.0)
+    err = np.abs(a - inc)
+    print(f"statistics: max err {err.max():.3g}, max {inc.max():.3g}")
+    assert np.all(err <= 1e-3 * (inc + 1e-2 * inc.max()))
