@@ -20,6 +20,8 @@ weights) in the same pass, forward + colour and flow L1 + backward.
 4D consistency loss (Sec. 3.3) of the headline Gaussian set: the exact 4D KNN
 (K = 8) and the loss with its gradient.  A whole optimisation step of the
 headline workload: render step, entropy and consistency terms, fused Adam.
+A static scene: 500k static 3D Gaussians (no time dimension) through the
+static path at the headline camera and resolution.
 
 Further lines (per_config): 2,000 Gaussians at 128x128 (forward), 300,000
 Gaussians over 30 orbit renders (forward), 3,000,000 Gaussians over 16
@@ -291,6 +293,47 @@ def training_step(r4d, rend, params, views, st, args):
     return res
 
 
+def static_scene(r4d, rend, dev, st, args):
+    """Static 3D Gaussians (the 3D/4D unification): 500k static Gaussians, SH 3,
+    the headline camera and resolution; graph-mode forward + L1 + backward, and
+    the preprocess stage times of the plain mode."""
+    import torch
+
+    import workloads as W
+    g, views, _ = W.scene_static_500k()
+    p = {k: torch.as_tensor(g[k]).to(dev).contiguous()
+         for k in ("means", "log_scales", "quats", "opacity", "sh")}
+    p["sh_degree"] = g["sh_degree"]
+    targets = flat_targets(views, dev)
+    grad = torch.empty_like(targets)
+    sg = dict(st, mode="graph")
+
+    def step(s_):
+        imgs, saved = rend.forward_static(p, views, s_, save=True, flat=True)
+        _, dl = rend.l1_loss_grad_views(imgs, targets, views, grad)
+        rend.backward_static(p, views, s_, saved, dl)
+        if s_.get("mode") != "graph":
+            saved.release()
+
+    ms = timed(lambda: step(sg), args.steps, args.warmup)
+    fwd_ms = timed(lambda: rend.forward_static(p, views, sg, save=False, flat=True), args.steps,
+                   args.warmup)
+    rend.set_timing(True)
+    rend.timings(reset=True)
+    for _ in range(max(3, min(args.steps, 10))):
+        step(dict(st, mode="per_view"))
+    torch.cuda.synchronize()
+    tim = rend.timings(reset=True)
+    rend.set_timing(False)
+    res = {"workload": "500k static 3D Gaussians, SH degree 3, one 1352x1014 render; step = "
+                       "forward + L1 + backward; graph mode",
+           "ms_per_step": ms, "steps_per_s": 1e3 / ms, "fwd_ms": fwd_ms,
+           "stage_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tim.items()}}
+    print(f"static scene: {res}", file=sys.stderr, flush=True)
+    del p
+    return res
+
+
 def per_view_step(r4d, rend, params, views, st, targets):
     """The plain baseline: one call sequence per render."""
     saved_all = []
@@ -490,6 +533,7 @@ def main():
     out["flow_render"] = flow_render(r4d, rend, params, views, st, args)
     out["consistency4d"] = consistency4d(r4d, rend, params, args)
     out["training_step"] = training_step(r4d, rend, params, views, st, args)
+    out["static_scene"] = static_scene(r4d, rend, dev, st, args)
 
     if not args.no_extra:
         out["batched_vs_plain"] = batched_vs_plain(r4d, rend, dev, args)

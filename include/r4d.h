@@ -422,6 +422,72 @@ r4d_status r4d_densify(r4d_ctx *ctx, const r4d_train_state *in, const float *gra
                        const r4d_densify_config *cfg, const r4d_train_state *out,
                        int32_t *n_out, void *stream);
 
+/* ---- static 3D Gaussians (the 3D/4D unification of Sec. 3.2.1: a rotor with
+ * no temporal part is a quaternion and the Gaussian does not move) ---- */
+
+/* A static set: means [3][n], log_scales [3][n], quats [4][n] as (w, x, y, z)
+ * (any norm; normalised inside; |q|^2 < 1e-12 acts as the identity), opacity
+ * [n], sh [3k][n]; all DEVICE, component-major like r4d_gaussians. */
+typedef struct {
+  int32_t n;
+  int32_t sh_degree;
+  const float *means;
+  const float *log_scales;
+  const float *quats;
+  const float *opacity;
+  const float *sh;
+} r4d_gaussians3d;
+typedef struct {
+  float *means;
+  float *log_scales;
+  float *quats;
+  float *opacity;
+  float *sh;
+} r4d_grads3d;
+typedef struct {
+  int32_t n;
+  int32_t sh_degree;
+  const double *means;
+  const double *log_scales;
+  const double *quats;
+  const double *opacity;
+  const double *sh;
+} r4d_gaussians3d_f64;
+typedef struct {
+  double *means;
+  double *log_scales;
+  double *quats;
+  double *opacity;
+  double *sh;
+} r4d_grads3d_f64;
+
+/* Render of a static set: every view at every time sees the same 3D
+ * Gaussians, Sigma_3D = R(q) diag(s^2) R(q)^T, no opacity decay and no time
+ * cull -- the 4D render of the rotors (w, -z, y, -x, 0, 0, 0, 0) with an
+ * unbounded time scale, computed without the rotor, Sigma_4 and the slice.
+ * Same binning, sort and rasteriser as r4d_render_forward; arguments, layout,
+ * modes and errors as there (views' t is ignored).  The saved state serves
+ * only r4d_render_backward_3d (R4D_ERR_STATE otherwise, and vice versa). */
+r4d_status r4d_render_forward_3d(r4d_ctx *ctx, const r4d_gaussians3d *g, const r4d_view *views,
+                                 int n_views, const r4d_settings *settings, float *images,
+                                 r4d_saved **saved, void *stream);
+/* Backward of r4d_render_forward_3d: gradients w.r.t. means, log_scales,
+ * quats (raw), opacity and sh, overwritten, summed over the views. */
+r4d_status r4d_render_backward_3d(r4d_ctx *ctx, const r4d_gaussians3d *g, const r4d_view *views,
+                                  int n_views, const r4d_settings *settings,
+                                  const r4d_saved *saved, const float *dL_dimages,
+                                  r4d_grads3d *out, void *stream);
+/* The two static calls in float64 (test use: finite differences). */
+r4d_status r4d_render_forward_3d_f64(r4d_ctx *ctx, const r4d_gaussians3d_f64 *g,
+                                     const r4d_view *views, int n_views,
+                                     const r4d_settings *settings, double *images,
+                                     r4d_saved **saved, void *stream);
+r4d_status r4d_render_backward_3d_f64(r4d_ctx *ctx, const r4d_gaussians3d_f64 *g,
+                                      const r4d_view *views, int n_views,
+                                      const r4d_settings *settings, const r4d_saved *saved,
+                                      const double *dL_dimages, r4d_grads3d_f64 *out,
+                                      void *stream);
+
 /* Returns the saved arena to its context's cache.  NULL is ignored.  A saved
  * handle may outlive its context: r4d_destroy frees its device memory and a
  * later release only frees the handle. */

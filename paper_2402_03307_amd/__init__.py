@@ -48,7 +48,9 @@ EXPORTED_SYMBOLS = (
     "r4d_render_backward_flow_f64", "r4d_knn4d", "r4d_consistency4d_loss_grad",
     "r4d_consistency4d_loss_grad_f64", "r4d_default_adam_config", "r4d_adam_step",
     "r4d_opacity_reset", "r4d_entropy_loss_grad", "r4d_render_backward_stats",
-    "r4d_default_densify_config", "r4d_densify", "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
+    "r4d_default_densify_config", "r4d_densify", "r4d_render_forward_3d",
+    "r4d_render_backward_3d", "r4d_render_forward_3d_f64", "r4d_render_backward_3d_f64",
+    "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
     "r4d_saved_copy", "r4d_saved_check", "r4d_saved_config", "r4d_status_string",
     "r4d_last_error", "r4d_set_timing", "r4d_get_timings", "r4d_stage_name",
 )
@@ -159,6 +161,12 @@ def _load():
     lib.r4d_densify.argtypes = [c_vp, P(_TrainState), c_vp, c_vp, c_vp, P(_DensifyConfig),
                                 P(_TrainState), P(c_i32), c_vp]
     lib.r4d_densify.restype = ctypes.c_int
+    for name, args in (("r4d_render_forward_3d", fwd_args), ("r4d_render_forward_3d_f64", fwd_args),
+                       ("r4d_render_backward_3d", bwd_args),
+                       ("r4d_render_backward_3d_f64", bwd_args)):
+        fn = getattr(lib, name)       # same argument layouts as the 4D calls
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
     lib.r4d_saved_release.argtypes = [c_vp]
     lib.r4d_saved_release.restype = None
     lib.r4d_l1_loss_grad.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int64, c_vp, c_vp, c_vp]
@@ -240,12 +248,19 @@ def _stream(device) -> ctypes.c_void_p:
 _PARAM_KEYS = ("means", "log_scales", "rotors", "opacity", "sh")
 
 
-def _check_params(p: dict):
+_STATIC_KEYS = ("means", "log_scales", "quats", "opacity", "sh")
+
+
+def _check_params(p: dict, static: bool = False):
     deg = int(p["sh_degree"])
     n = p["opacity"].shape[-1]
     k = (deg + 1) ** 2
-    shapes = {"means": (4, n), "log_scales": (4, n), "rotors": (8, n), "opacity": (n,),
-              "sh": (3 * k, n)}
+    if static:
+        shapes = {"means": (3, n), "log_scales": (3, n), "quats": (4, n), "opacity": (n,),
+                  "sh": (3 * k, n)}
+    else:
+        shapes = {"means": (4, n), "log_scales": (4, n), "rotors": (8, n), "opacity": (n,),
+                  "sh": (3 * k, n)}
     dtype = p["means"].dtype
     for key, shp in shapes.items():
         t = p[key]
@@ -578,6 +593,47 @@ class Renderer:
         st = _lib.r4d_opacity_reset(self.handle, ctypes.byref(state.struct()), float(cap),
                                     _stream(self.device))
         self._check(st, "r4d_opacity_reset")
+
+    def forward_static(self, params: dict, views, settings: dict | None = None,
+                       save: bool = True, flat: bool = False):
+        """Render of static 3D Gaussians (r4d_render_forward_3d); params: means
+        [3, n], log_scales [3, n], quats [4, n] (w, x, y, z), opacity [n], sh
+        [3k, n], sh_degree.  Returns (images, SavedState or None)."""
+        n, deg, dtype = _check_params(params, static=True)
+        g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _STATIC_KEYS])
+        varr = _views_array(views)
+        st = _settings_struct(settings)
+        graph = st.mode == MODE_GRAPH
+        sizes = [3 * int(v["height"]) * int(v["width"]) for v in views]
+        key = ("img3d", dtype, tuple(sizes), n) + tuple(params[k].data_ptr() for k in _STATIC_KEYS)
+        out = self._buffer(key, (sum(sizes),), dtype, graph)
+        handle = ctypes.c_void_p()
+        fn = _lib.r4d_render_forward_3d if dtype == torch.float32 else _lib.r4d_render_forward_3d_f64
+        status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st), _ptr(out),
+                    ctypes.byref(handle) if save else None, _stream(self.device))
+        self._check(status, "r4d_render_forward_3d")
+        saved = SavedState(self, handle, views, dtype) if save else None
+        return (out, saved) if flat else (_split(out, views, 3), saved)
+
+    def backward_static(self, params: dict, views, settings: dict | None, saved: SavedState,
+                        grad_images) -> dict:
+        """Gradients of a static render w.r.t. means, log_scales, quats, opacity
+        and sh (r4d_render_backward_3d)."""
+        n, deg, dtype = _check_params(params, static=True)
+        g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _STATIC_KEYS])
+        varr = _views_array(views)
+        st = _settings_struct(settings)
+        graph = st.mode == MODE_GRAPH
+        dl = _flat(grad_images, dtype)
+        grads = {k: self._buffer(("grad3d", k, dtype, n), tuple(params[k].shape), dtype, graph)
+                 for k in _STATIC_KEYS}
+        gs = _Grads(*[_ptr(grads[k]) for k in _STATIC_KEYS])
+        fn = (_lib.r4d_render_backward_3d if dtype == torch.float32
+              else _lib.r4d_render_backward_3d_f64)
+        status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st),
+                    saved.handle, _ptr(dl), ctypes.byref(gs), _stream(self.device))
+        self._check(status, "r4d_render_backward_3d")
+        return grads
 
     def set_timing(self, enable: bool = True):
         self._check(_lib.r4d_set_timing(self.handle, int(bool(enable))), "r4d_set_timing")

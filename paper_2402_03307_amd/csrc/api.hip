@@ -68,6 +68,7 @@ struct Plan {
   size_t scal = 4;
   bool count_evals = false;
   bool flow = false;    // also composite the 2D flow (flow images)
+  bool static3d = false;  // static 3D Gaussians (means 3, log-scales 3, quaternions 4 rows)
 };
 
 }  // namespace
@@ -148,6 +149,7 @@ struct r4d_saved {
   r4d_ctx* ctx = nullptr;
   bool f64 = false;
   bool flow = false;            // flow render: the backward may take flow gradients
+  bool static3d = false;        // static 3D Gaussians
   int n = 0, deg = 0;
   r4d_settings settings;        // as resolved (tile size chosen)
   std::vector<r4d_view> views;
@@ -362,9 +364,10 @@ std::string view_shape_key(const r4d_view* views, int V) {
 }
 
 Plan make_plan(const r4d_view* views, int V, uint32_t n, int deg, const r4d_settings& s,
-               size_t scal, bool flow = false) {
+               size_t scal, bool flow, bool static3d) {
   Plan p;
   p.flow = flow;
+  p.static3d = static3d;
   p.V = V;
   p.n = n;
   p.n_pad = uint32_t(round_seg(n));
@@ -538,7 +541,8 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
                                        p.flow ? at<Vec2<T>>(F, L.flows) : nullptr,
                                        at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
                                        at<uint32_t>(F, L.dkeys), totals, at<uint32_t>(F, L.kA),
-                                       at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd, stream));
+                                       at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd, p.static3d,
+                                       stream));
   }
   hipEvent_t totals_ready = nullptr;
   if (sized) {
@@ -748,7 +752,7 @@ r4d_status enqueue_backward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, co
     R4D_HIP(launch_densify_stats(grad2d, int(nc), at<uint32_t>(F, r.L.dkeys), p.n_pad,
                                  slots_of(F, r.L), p.V, p.n, stats.accum, stats.count, stream));
   R4D_TIMED(kPreprocessBwd, launch_preprocess_bwd<T>(g, slots_of(F, r.L), p.V, st, grad2d,
-                                                     nc == 11, out, stream));
+                                                     nc == 11, p.static3d, out, stream));
   return R4D_OK;
 }
 
@@ -807,10 +811,10 @@ r4d_status run_sized(r4d_ctx* ctx, const GaussPtrs<T>& g, const Plan& p, T* imag
 
 template <typename T>
 std::string fwd_graph_key(const GaussPtrs<T>& g, const void* images, const void* flows,
-                          const r4d_view* views, int V, const r4d_settings& s) {
+                          const r4d_view* views, int V, const r4d_settings& s, bool static3d) {
   char buf[512];
-  snprintf(buf, sizeof(buf), "%zu|%d|%d|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%a|%a|%a|%a|%a|%a|%a|",
-           sizeof(T), g.n, g.deg, (const void*)g.means, (const void*)g.log_scales,
+  snprintf(buf, sizeof(buf), "%zu|%d|%d|%d|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%a|%a|%a|%a|%a|%a|%a|",
+           sizeof(T), int(static3d), g.n, g.deg, (const void*)g.means, (const void*)g.log_scales,
            (const void*)g.rotors, (const void*)g.opacity, (const void*)g.sh, images, flows,
            s.tile_size,
            s.fwd_pixels_per_thread, s.bwd_pixels_per_thread, s.sort_items, s.near_plane,
@@ -823,11 +827,12 @@ std::string fwd_graph_key(const GaussPtrs<T>& g, const void* images, const void*
 template <typename T>
 r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int V,
                      const r4d_settings& s, T* images, T* flow_images, const SettingsDev& st,
-                     hipStream_t stream, GraphEntry** entry_out) {
-  const std::string key = fwd_graph_key(g, images, flow_images, views, V, s);
+                     bool static3d, hipStream_t stream, GraphEntry** entry_out) {
+  const std::string key = fwd_graph_key(g, images, flow_images, views, V, s, static3d);
   auto it = ctx->graphs.find(key);
   GraphEntry* e = it == ctx->graphs.end() ? nullptr : it->second.get();
-  const Plan p = make_plan(views, V, uint32_t(g.n), g.deg, s, sizeof(T), flow_images != nullptr);
+  const Plan p = make_plan(views, V, uint32_t(g.n), g.deg, s, sizeof(T), flow_images != nullptr,
+                           static3d);
   if (e && e->run.done) {
     // an overflow of an earlier replay grows the capacity (checked without waiting)
     if (hipEventQuery(e->run.done) == hipSuccess) {
@@ -908,9 +913,10 @@ r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
 // candidate (tile size, tile-sort keys per lane) timed twice after a warm-up.
 template <typename T>
 r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int V,
-                    const r4d_settings& base, T* images, hipStream_t stream, int* ts_out,
-                    int* items_out) {
-  const std::string key = std::to_string(sizeof(T)) + "|" + std::to_string(g.n) + "|" +
+                    const r4d_settings& base, T* images, bool static3d, hipStream_t stream,
+                    int* ts_out, int* items_out) {
+  const std::string key = std::to_string(sizeof(T)) + "|" + std::to_string(int(static3d)) + "|" +
+                          std::to_string(g.n) + "|" +
                           std::to_string(g.deg) + "|" + std::to_string(base.mode) + "|" +
                           view_shape_key(views, V);
   auto it = ctx->tuned.find(key);
@@ -946,7 +952,7 @@ r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, 
       s.tile_size = ts;
       s.sort_items = items;
       s.fwd_pixels_per_thread = s.bwd_pixels_per_thread = 0;
-      const Plan p = make_plan(views, V, uint32_t(g.n), g.deg, s, sizeof(T));
+      const Plan p = make_plan(views, V, uint32_t(g.n), g.deg, s, sizeof(T), false, static3d);
       float total = 0.f;
       for (int rep = 0; rep < 3 && result == R4D_OK; ++rep) {
         if (rep == 1) {
@@ -996,7 +1002,7 @@ r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, 
 template <typename T>
 r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int n_views,
                         const r4d_settings* settings, T* images, T* flows, r4d_saved** saved_out,
-                        hipStream_t stream) {
+                        hipStream_t stream, bool static3d = false) {
   if (saved_out) *saved_out = nullptr;
   if (!views || n_views < 1 || n_views > kMaxViews || !images || !valid_settings(settings))
     return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, images or settings");
@@ -1011,7 +1017,8 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
   r4d_settings rs = *settings;
   if (rs.tile_size == 0) {
     int ts = 16, items = 16;
-    if ((s = autotune<T>(ctx, g, views, n_views, rs, images, stream, &ts, &items)) != R4D_OK)
+    if ((s = autotune<T>(ctx, g, views, n_views, rs, images, static3d, stream, &ts, &items)) !=
+        R4D_OK)
       return s;
     rs.tile_size = ts;
     rs.sort_items = items;
@@ -1021,6 +1028,7 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
   saved->ctx = ctx;
   saved->f64 = sizeof(T) == 8;
   saved->flow = flows != nullptr;
+  saved->static3d = static3d;
   saved->n = g.n;
   saved->deg = g.deg;
   saved->settings = rs;
@@ -1029,13 +1037,14 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
   const bool flow = flows != nullptr;
   if (rs.mode == R4D_MODE_GRAPH) {
     GraphEntry* e = nullptr;
-    if ((s = run_graph<T>(ctx, g, views, n_views, rs, images, flows, st, stream, &e)) != R4D_OK)
+    if ((s = run_graph<T>(ctx, g, views, n_views, rs, images, flows, st, static3d, stream, &e)) !=
+        R4D_OK)
       return s;
     saved->graph = e;
     saved->generation = e->generation;
     for (int v = 0; v < n_views; ++v) saved->where.push_back({0, v});
   } else if (rs.mode == R4D_MODE_FUSED) {
-    Plan p = make_plan(views, n_views, uint32_t(g.n), g.deg, rs, sizeof(T), flow);
+    Plan p = make_plan(views, n_views, uint32_t(g.n), g.deg, rs, sizeof(T), flow, static3d);
     p.count_evals = timed && !flow;
     std::unique_ptr<RunState> r;
     if ((s = run_sized<T>(ctx, g, p, images, flows, st, timed, stream, r)) != R4D_OK) return s;
@@ -1044,7 +1053,7 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
   } else {
     size_t off = 0, foff = 0;
     for (int v = 0; v < n_views; ++v) {
-      Plan p = make_plan(views + v, 1, uint32_t(g.n), g.deg, rs, sizeof(T), flow);
+      Plan p = make_plan(views + v, 1, uint32_t(g.n), g.deg, rs, sizeof(T), flow, static3d);
       p.count_evals = timed && !flow;
       std::unique_ptr<RunState> r;
       if ((s = run_sized<T>(ctx, g, p, images + off, flow ? flows + foff : nullptr, st, timed,
@@ -1083,7 +1092,7 @@ template <typename T>
 r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
                          int n_views, const r4d_settings* settings, const r4d_saved* saved,
                          const T* dL, const T* dLf, const GradPtrs<T>& out, hipStream_t stream,
-                         StatsOut stats = StatsOut{}) {
+                         StatsOut stats = StatsOut{}, bool static3d = false) {
   if (!views || n_views < 1 || !dL || !valid_settings(settings) || !saved)
     return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, gradients, settings or saved state");
   r4d_status s = check_gaussians(ctx, g);
@@ -1102,6 +1111,8 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
     return fail(ctx, R4D_ERR_STATE, "a later graph forward of this shape reused the buffers");
   if (dLf && !saved->flow)
     return fail(ctx, R4D_ERR_STATE, "flow gradients given for a forward without flow");
+  if (saved->static3d != static3d)
+    return fail(ctx, R4D_ERR_STATE, "static and 4D Gaussian calls do not mix");
   R4D_HIP(hipSetDevice(ctx->device));
   if (g.n == 0) return R4D_OK;
   const SettingsDev st = make_settings(saved->settings);
@@ -1159,7 +1170,10 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   const size_t k3 = 3 * size_t((g.deg + 1) * (g.deg + 1));
   T* tmp = static_cast<T*>(ctx_alloc(ctx, (17 + k3) * n * sizeof(T)));
   if (!tmp) return fail(ctx, R4D_ERR_OOM, "backward buffers");
-  const GradPtrs<T> gt{tmp, tmp + 4 * n, tmp + 8 * n, tmp + 16 * n, tmp + 17 * n};
+  // the five arrays back to back (static 3D Gaussians: 3, 3, 4 rows)
+  const size_t rm = static3d ? 3 : 4, rl = rm, rr = static3d ? 4 : 8;
+  const GradPtrs<T> gt{tmp, tmp + rm * n, tmp + (rm + rl) * n, tmp + (rm + rl + rr) * n,
+                       tmp + (rm + rl + rr + 1) * n};
   for (size_t ri = 0; ri < saved->runs.size() && s == R4D_OK; ++ri) {
     RunState& r = *saved->runs[ri];
     uint8_t* bb = static_cast<uint8_t*>(ctx_alloc(ctx, bwd_block_bytes(r.plan, r.capacity)));
@@ -1171,7 +1185,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
                             bb, st, ri == 0 ? out : gt, timed, stream, stats);
     ctx_free(ctx, bb);
     if (s == R4D_OK && ri > 0) {
-      const hipError_t e = add_grads<T>(out, tmp, n, k3, stream);
+      const hipError_t e = add_grads<T>(out, tmp, n, k3, static3d, stream);
       if (e != hipSuccess) s = fail(ctx, R4D_ERR_HIP, "gradient sum: %s", hipGetErrorString(e));
     }
   }
@@ -1610,6 +1624,54 @@ r4d_status r4d_densify(r4d_ctx* ctx, const r4d_train_state* in, const float* gra
   if (total == 0) return R4D_OK;
   R4D_HIP(densify_scatter(d, temp, keep, clone, uint32_t(total), stream));
   return R4D_OK;
+}
+
+r4d_status r4d_render_forward_3d(r4d_ctx* ctx, const r4d_gaussians3d* g, const r4d_view* views,
+                                 int n_views, const r4d_settings* settings, float* images,
+                                 r4d_saved** saved, void* stream) {
+  if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  const GaussPtrs<float> gp{g->n, g->sh_degree, g->means, g->log_scales, g->quats, g->opacity,
+                            g->sh};
+  return forward_impl<float>(ctx, gp, views, n_views, settings, images, nullptr, saved,
+                             static_cast<hipStream_t>(stream), true);
+}
+
+r4d_status r4d_render_forward_3d_f64(r4d_ctx* ctx, const r4d_gaussians3d_f64* g,
+                                     const r4d_view* views, int n_views,
+                                     const r4d_settings* settings, double* images,
+                                     r4d_saved** saved, void* stream) {
+  if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  const GaussPtrs<double> gp{g->n, g->sh_degree, g->means, g->log_scales, g->quats, g->opacity,
+                             g->sh};
+  return forward_impl<double>(ctx, gp, views, n_views, settings, images, nullptr, saved,
+                              static_cast<hipStream_t>(stream), true);
+}
+
+r4d_status r4d_render_backward_3d(r4d_ctx* ctx, const r4d_gaussians3d* g, const r4d_view* views,
+                                  int n_views, const r4d_settings* settings,
+                                  const r4d_saved* saved, const float* dL_dimages,
+                                  r4d_grads3d* out, void* stream) {
+  if (!ctx || !g || !out)
+    return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  const GaussPtrs<float> gp{g->n, g->sh_degree, g->means, g->log_scales, g->quats, g->opacity,
+                            g->sh};
+  const GradPtrs<float> o{out->means, out->log_scales, out->quats, out->opacity, out->sh};
+  return backward_impl<float>(ctx, gp, views, n_views, settings, saved, dL_dimages, nullptr, o,
+                              static_cast<hipStream_t>(stream), StatsOut{}, true);
+}
+
+r4d_status r4d_render_backward_3d_f64(r4d_ctx* ctx, const r4d_gaussians3d_f64* g,
+                                      const r4d_view* views, int n_views,
+                                      const r4d_settings* settings, const r4d_saved* saved,
+                                      const double* dL_dimages, r4d_grads3d_f64* out,
+                                      void* stream) {
+  if (!ctx || !g || !out)
+    return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  const GaussPtrs<double> gp{g->n, g->sh_degree, g->means, g->log_scales, g->quats, g->opacity,
+                             g->sh};
+  const GradPtrs<double> o{out->means, out->log_scales, out->quats, out->opacity, out->sh};
+  return backward_impl<double>(ctx, gp, views, n_views, settings, saved, dL_dimages, nullptr, o,
+                               static_cast<hipStream_t>(stream), StatsOut{}, true);
 }
 
 void r4d_saved_release(r4d_saved* saved) {

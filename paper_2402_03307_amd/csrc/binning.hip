@@ -383,21 +383,23 @@ __global__ __launch_bounds__(kThreads) void fill_const_kernel(T* __restrict__ p,
 template <typename T>
 __global__ __launch_bounds__(kThreads) void add_grads_kernel(GradPtrs<T> out,
                                                              const T* __restrict__ tmp, size_t n,
-                                                             size_t k3) {
-  const size_t total = (17 + k3) * n;
+                                                             size_t k3, uint32_t rm, uint32_t rl,
+                                                             uint32_t rr) {
+  const size_t e1 = rm * n, e2 = e1 + rl * n, e3 = e2 + rr * n, e4 = e3 + n;
+  const size_t total = e4 + k3 * n;
   const size_t stride = size_t(gridDim.x) * kThreads;
   for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < total; i += stride) {
     T* dst;
-    if (i < 4 * n)
+    if (i < e1)
       dst = out.means + i;
-    else if (i < 8 * n)
-      dst = out.log_scales + (i - 4 * n);
-    else if (i < 16 * n)
-      dst = out.rotors + (i - 8 * n);
-    else if (i < 17 * n)
-      dst = out.opacity + (i - 16 * n);
+    else if (i < e2)
+      dst = out.log_scales + (i - e1);
+    else if (i < e3)
+      dst = out.rotors + (i - e2);
+    else if (i < e4)
+      dst = out.opacity + (i - e3);
     else
-      dst = out.sh + (i - 17 * n);
+      dst = out.sh + (i - e4);
     *dst += tmp[i];
   }
 }
@@ -910,17 +912,18 @@ hipError_t fill_const(void* p, size_t count, double value, bool f64, hipStream_t
 }
 
 template <typename T>
-hipError_t add_grads(const GradPtrs<T>& out, const T* tmp, size_t n, size_t k3,
+hipError_t add_grads(const GradPtrs<T>& out, const T* tmp, size_t n, size_t k3, bool static3d,
                      hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(add_grads_kernel<T>, dim3(grid_for((17 + k3) * n)), dim3(kThreads), 0, stream,
-                     out, tmp, n, k3);
+  const uint32_t rm = static3d ? 3 : 4, rl = static3d ? 3 : 4, rr = static3d ? 4 : 8;
+  hipLaunchKernelGGL(add_grads_kernel<T>, dim3(grid_for((rm + rl + rr + 1 + k3) * n)),
+                     dim3(kThreads), 0, stream, out, tmp, n, k3, rm, rl, rr);
   return hipGetLastError();
 }
-template hipError_t add_grads<float>(const GradPtrs<float>&, const float*, size_t, size_t,
+template hipError_t add_grads<float>(const GradPtrs<float>&, const float*, size_t, size_t, bool,
                                      hipStream_t);
 template hipError_t add_grads<double>(const GradPtrs<double>&, const double*, size_t, size_t,
-                                      hipStream_t);
+                                      bool, hipStream_t);
 
 hipError_t copy_ranges_rebased(const uint2* src, uint32_t count, uint32_t base, uint2* dst,
                                hipStream_t stream) {

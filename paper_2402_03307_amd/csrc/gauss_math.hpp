@@ -460,33 +460,12 @@ R4D_HD void cov4_bwd(const Fwd<T>& f, const T G4[16], T gls[4], T grot[8]) {
 }
 
 // ---------------------------------------------------------------------------
-// Full per-Gaussian forward.  `sh` points at coefficient 0 of this Gaussian's
-// [3k] SH column (stride n between rows).
-
+// Projection and colour of a 3D Gaussian (f.mu3, f.S3, f.vel, f.o_t set): view
+// transform, near-plane drop, EWA projection, conic, 2D flow, SH colour
+// (Sec. 3.1).  Sets f.valid when the Gaussian survives.
 template <typename T, typename ShT>
-R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacity, const ShT* shp,
-                         long sh_stride, int deg, const ViewDev& v, const SettingsDev& st,
-                         Fwd<T>& f) {
-  f.valid = false;
-  cov4_fwd(ls, rot, f);
-  // temporal slice
-  f.dt = T(v.t) - mu4[3];
-  f.invW = T(1) / f.W;
-  f.lam_dt2 = f.dt * f.dt * f.invW;
-  if (!(f.lam_dt2 <= T(st.time_cull))) return;
-  f.decay = r4d_exp(T(-0.5) * f.lam_dt2);
-  f.o_t = opacity * f.decay;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    f.vel[i] = f.V[i] * f.invW;
-    f.mu3[i] = mu4[i] + f.dt * f.vel[i];
-  }
-  f.S3[0] = f.U[0] - f.V[0] * f.vel[0];
-  f.S3[1] = f.U[1] - f.V[0] * f.vel[1];
-  f.S3[2] = f.U[2] - f.V[0] * f.vel[2];
-  f.S3[3] = f.U[3] - f.V[1] * f.vel[1];
-  f.S3[4] = f.U[4] - f.V[1] * f.vel[2];
-  f.S3[5] = f.U[5] - f.V[2] * f.vel[2];
+R4D_HD void project_fwd(const ShT* shp, long sh_stride, int deg, const ViewDev& v,
+                        const SettingsDev& st, Fwd<T>& f) {
   // view transform
   const T* mu = f.mu3;
 #pragma unroll
@@ -558,6 +537,93 @@ R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacit
   f.valid = true;
 }
 
+// ---------------------------------------------------------------------------
+// Full per-Gaussian forward.  `sh` points at coefficient 0 of this Gaussian's
+// [3k] SH column (stride n between rows).
+
+template <typename T, typename ShT>
+R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacity, const ShT* shp,
+                         long sh_stride, int deg, const ViewDev& v, const SettingsDev& st,
+                         Fwd<T>& f) {
+  f.valid = false;
+  cov4_fwd(ls, rot, f);
+  // temporal slice
+  f.dt = T(v.t) - mu4[3];
+  f.invW = T(1) / f.W;
+  f.lam_dt2 = f.dt * f.dt * f.invW;
+  if (!(f.lam_dt2 <= T(st.time_cull))) return;
+  f.decay = r4d_exp(T(-0.5) * f.lam_dt2);
+  f.o_t = opacity * f.decay;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    f.vel[i] = f.V[i] * f.invW;
+    f.mu3[i] = mu4[i] + f.dt * f.vel[i];
+  }
+  f.S3[0] = f.U[0] - f.V[0] * f.vel[0];
+  f.S3[1] = f.U[1] - f.V[0] * f.vel[1];
+  f.S3[2] = f.U[2] - f.V[0] * f.vel[2];
+  f.S3[3] = f.U[3] - f.V[1] * f.vel[1];
+  f.S3[4] = f.U[4] - f.V[1] * f.vel[2];
+  f.S3[5] = f.U[5] - f.V[2] * f.vel[2];
+  project_fwd(shp, sh_stride, deg, v, st, f);
+}
+
+// Static 3D Gaussian (the paper's 3D/4D unification, Sec. 3.2.1: a rotor with
+// no temporal part acts as a quaternion and the Gaussian does not move, so its
+// slice at every time is the 3D Gaussian itself, with no opacity decay).
+// q = (w, x, y, z), normalised here; R3 the usual quaternion rotation, equal to
+// the rotor rotation of (s, b01, b02, b12) = (w, -z, y, -x);
+// Sigma_3D = R3 diag(s^2) R3^T.  R3 is kept in f.R[0..8] (row-major), the
+// normalised quaternion in f.rn[0..3].
+template <typename T>
+R4D_HD void quat_fwd(const T q[4], Fwd<T>& f) {
+  const T n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  f.degenerate = !(n2 >= T(1e-12));
+  f.inv_n1 = f.degenerate ? T(0) : T(1) / r4d_sqrt(n2);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f.rn[i] = f.degenerate ? (i == 0 ? T(1) : T(0)) : q[i] * f.inv_n1;
+  const T w = f.rn[0], x = f.rn[1], y = f.rn[2], z = f.rn[3];
+  T* R = f.R;
+  R[0] = 1 - 2 * (y * y + z * z);
+  R[1] = 2 * (x * y - w * z);
+  R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);
+  R[4] = 1 - 2 * (x * x + z * z);
+  R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);
+  R[7] = 2 * (y * z + w * x);
+  R[8] = 1 - 2 * (x * x + y * y);
+}
+
+template <typename T, typename ShT>
+R4D_HD void gaussian_fwd_static(const T mu[3], const T ls[3], const T q[4], T opacity,
+                                const ShT* shp, long sh_stride, int deg, const ViewDev& v,
+                                const SettingsDev& st, Fwd<T>& f) {
+  f.valid = false;
+  quat_fwd(q, f);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f.s2[k] = r4d_exp(2 * ls[k]);
+  const T* R = f.R;
+  auto sig = [&](int i, int j) {
+    return R[3 * i] * R[3 * j] * f.s2[0] + R[3 * i + 1] * R[3 * j + 1] * f.s2[1] +
+           R[3 * i + 2] * R[3 * j + 2] * f.s2[2];
+  };
+  f.S3[0] = sig(0, 0);
+  f.S3[1] = sig(0, 1);
+  f.S3[2] = sig(0, 2);
+  f.S3[3] = sig(1, 1);
+  f.S3[4] = sig(1, 2);
+  f.S3[5] = sig(2, 2);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    f.mu3[i] = mu[i];
+    f.vel[i] = T(0);
+  }
+  f.decay = T(1);
+  f.o_t = opacity;
+  project_fwd(shp, sh_stride, deg, v, st, f);
+}
+
 // Gradients of one Gaussian.  In: dL/d(mean2 x, y), the gradient H of L with
 // respect to the symmetric 2x2 matrix Sigma_2D (entries (0,0), (0,1) = (1,0),
 // (1,1); a change dS of the matrix changes L by sum_ij H_ij dS_ij), dL/d(o_t),
@@ -569,16 +635,21 @@ R4D_HD void gaussian_fwd(const T mu4[4], const T ls[4], const T rot[8], T opacit
 // major axis that Sigma_2D = conic^-1 almost ignores, so forming -Q G Q from it
 // in single precision cancels badly; the rasteriser instead sums the well-scaled
 // per-pixel terms (Q d)(Q d)^T directly.
-template <typename T, typename ShT, bool FLOW = false>
-R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int deg,
-                         const ViewDev& v, const T* g2, T gmu4[4], T gls[4], T grot[8],
-                         T& gop, T* gsh, long gsh_stride) {
-  if (!f.valid) return;
+//
+// project_bwd is the part shared by 4D and static Gaussians: it leaves
+// dL/d(mu3), the symmetric full-matrix gradient dL/d(Sigma_3D) (6 unique
+// entries), dL/d(vel) of the flow (FLOW) and dL/d(o_t), and adds the SH
+// gradient.
+template <typename T, typename ShT, bool FLOW>
+R4D_HD void project_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int deg,
+                        const ViewDev& v, const T* g2, T gmu3[3], T gS3[6], T gvel[3], T& go_t,
+                        T* gsh, long gsh_stride) {
   const T gm_x = g2[0], gm_y = g2[1];
   const T H00 = g2[2], H01 = g2[3], H11 = g2[4];
-  const T go_t = g2[5];
+  go_t = g2[5];
   const T grgb[3] = {g2[6], g2[7], g2[8]};
-  T gmu3[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) gmu3[i] = gvel[i] = T(0);
   // ---- SH colour
   {
     T graw[3];
@@ -607,7 +678,6 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int de
   // Sigma_2D = Tm S3 Tm^T: dL/dS3 = Tm^T H Tm ; dL/dTm = 2 H Tm S3
   const T* a = f.Tm;
   const T* b = f.Tm + 3;
-  T gS3[6];
   // (Tm^T H Tm)_ij = a_i (H00 a_j + H01 b_j) + b_i (H01 a_j + H11 b_j)
   {
     T ha[3], hb[3];
@@ -668,7 +738,6 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int de
   gp[1] += gm_y * fy * ipz;
   gp[2] += -(gm_x * fx * f.p[0] + gm_y * fy * f.p[1]) * ipz2;
   // flow = (fx (vx/z - x vz/z^2), fy (vy/z - y vz/z^2)), vc = Wv vel
-  T gvel[3] = {0, 0, 0};
   if (FLOW) {
     const T hx = g2[9] * fx, hy = g2[10] * fy;
     const T ipz3 = ipz2 * ipz;
@@ -686,6 +755,16 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int de
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     gmu3[c] += T(v.M[c]) * gp[0] + T(v.M[3 + c]) * gp[1] + T(v.M[6 + c]) * gp[2];
+}
+
+template <typename T, typename ShT, bool FLOW = false>
+R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int deg,
+                         const ViewDev& v, const T* g2, T gmu4[4], T gls[4], T grot[8],
+                         T& gop, T* gsh, long gsh_stride) {
+  if (!f.valid) return;
+  T gmu3[3], gS3[6], gvel[3], go_t;
+  project_bwd<T, ShT, FLOW>(f, shp, sh_stride, deg, v, g2, gmu3, gS3, gvel, go_t, gsh,
+                            gsh_stride);
   // ---- temporal slice
   // mu3 = mu_xyz + dt vel, vel = V/W (also the flow's speed) ; S3 = U - V V^T / W ;
   // o_t = o exp(-dt^2/(2W))
@@ -732,6 +811,63 @@ R4D_HD void gaussian_bwd(const Fwd<T>& f, const ShT* shp, long sh_stride, int de
   G4[15] = gW;
   // the U block of Sigma_4 enters Sigma_3D directly: dL/dU = dL/dS3 (already in G4)
   cov4_bwd(f, G4, gls, grot);
+}
+
+// dL/dR3 (9, row-major) of the normalised quaternion's rotation -> dL/d(raw
+// quaternion), added to gq.
+template <typename T>
+R4D_HD void quat_bwd(const Fwd<T>& f, const T G[9], T gq[4]) {
+  if (f.degenerate) return;
+  const T w = f.rn[0], x = f.rn[1], y = f.rn[2], z = f.rn[3];
+  // derivatives of the nine entries written out per component
+  const T gw = 2 * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+  const T gx = 2 * (y * G[1] + z * G[2] + y * G[3] - 2 * x * G[4] - w * G[5] + z * G[6] +
+                    w * G[7] - 2 * x * G[8]);
+  const T gy = 2 * (-2 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] +
+                    z * G[7] - 2 * y * G[8]);
+  const T gz = 2 * (-2 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2 * z * G[4] + y * G[5] +
+                    x * G[6] + y * G[7]);
+  // q_hat = q / |q|
+  const T dot = w * gw + x * gx + y * gy + z * gz;
+  gq[0] += (gw - w * dot) * f.inv_n1;
+  gq[1] += (gx - x * dot) * f.inv_n1;
+  gq[2] += (gy - y * dot) * f.inv_n1;
+  gq[3] += (gz - z * dot) * f.inv_n1;
+}
+
+// Gradients of a static 3D Gaussian (see gaussian_fwd_static): g2 as for
+// gaussian_bwd (no flow); out (added): mu[3], ls[3], q[4], opacity, SH column.
+template <typename T, typename ShT>
+R4D_HD void gaussian_bwd_static(const Fwd<T>& f, const ShT* shp, long sh_stride, int deg,
+                                const ViewDev& v, const T* g2, T gmu[3], T gls[3], T gq[4],
+                                T& gop, T* gsh, long gsh_stride) {
+  if (!f.valid) return;
+  T gmu3[3], gS3[6], gvel[3], go_t;
+  project_bwd<T, ShT, false>(f, shp, sh_stride, deg, v, g2, gmu3, gS3, gvel, go_t, gsh,
+                             gsh_stride);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) gmu[i] += gmu3[i];
+  gop += go_t;
+  // Sigma_3D = R3 diag(s2) R3^T with the full symmetric gradient G
+  const T G[9] = {gS3[0], gS3[1], gS3[2], gS3[1], gS3[3], gS3[4], gS3[2], gS3[4], gS3[5]};
+  const T* R = f.R;
+  T GR[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      GR[3 * i + k] = G[3 * i] * R[k] + G[3 * i + 1] * R[3 + k] + G[3 * i + 2] * R[6 + k];
+  T gR[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gR[3 * i + k] = 2 * GR[3 * i + k] * f.s2[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T gs2 = R[k] * GR[k] + R[3 + k] * GR[3 + k] + R[6 + k] * GR[6 + k];
+    gls[k] += gs2 * 2 * f.s2[k];
+  }
+  quat_bwd(f, gR, gq);
 }
 
 }  // namespace r4d

@@ -4,7 +4,8 @@
 //
 // Forward writes the projected record consumed by the rasteriser, the tiles'
 // bounding box, the tile count and the depth sort key (and, for a flow render,
-// the Gaussian's 2D flow).  Backward recomputes the forward intermediates from
+// the Gaussian's 2D flow).  A static set (3D Gaussians: means, log-scales and
+// quaternions with 3, 3 and 4 rows) skips the rotor, Sigma_4 and the slice.  Backward recomputes the forward intermediates from
 // the parameters (nothing per Gaussian is stored between the passes except the
 // 9, or with flow 11, screen-space gradients) and chains them back to the
 // parameters.
@@ -54,7 +55,9 @@ __device__ __forceinline__ bool record_box(const Rec<T>& rec, const ViewDev& v, 
   return true;
 }
 
-template <typename T, int DEG>
+// STATIC: a set of static 3D Gaussians (means [3][n], log-scales [3][n],
+// quaternions [4][n] in the rotor slot) rendered with no slicing.
+template <typename T, int DEG, bool STATIC>
 __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     GaussPtrs<T> g, const ViewSlot* __restrict__ slots, SettingsDev st, uint32_t n_pad,
     Rec<T>* __restrict__ recs, Vec2<T>* __restrict__ flows, Rect16* __restrict__ rects,
@@ -77,17 +80,29 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
   sg.sh = sh;
   float depth = 0.0f;
   if (i < n) {
-    T mu[4], ls[4], rot[8];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      mu[c] = g.means[c * (long)n + i];
-      ls[c] = g.log_scales[c * (long)n + i];
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) rot[c] = g.rotors[c * (long)n + i];
     const T op = g.opacity[i];
     Fwd<T> f;
-    gaussian_fwd<T>(mu, ls, rot, op, g.sh + i, (long)n, DEG, v, st, f);
+    if (STATIC) {
+      T mu[3], ls[3], q[4];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        mu[c] = g.means[c * (long)n + i];
+        ls[c] = g.log_scales[c * (long)n + i];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[c] = g.rotors[c * (long)n + i];
+      gaussian_fwd_static<T>(mu, ls, q, op, g.sh + i, (long)n, DEG, v, st, f);
+    } else {
+      T mu[4], ls[4], rot[8];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        mu[c] = g.means[c * (long)n + i];
+        ls[c] = g.log_scales[c * (long)n + i];
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) rot[c] = g.rotors[c * (long)n + i];
+      gaussian_fwd<T>(mu, ls, rot, op, g.sh + i, (long)n, DEG, v, st, f);
+    }
     if (f.valid) {
       Rec<T> rec;
       rec.mx = f.mean2[0];
@@ -253,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void compact_keys_kernel(
 // With one render the SH coefficients are loaded once into registers; with
 // several they are re-read from memory (cached) in every render, which keeps
 // the register count of the render loop at that of the single-render case.
-template <typename T, int DEG, bool MULTI, bool FLOW>
+template <typename T, int DEG, bool MULTI, bool FLOW, bool STATIC>
 __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
                                                                 const ViewSlot* __restrict__ slots,
                                                                 int n_views, SettingsDev st,
@@ -264,7 +279,9 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
+  // (a static Gaussian uses the first 3, 3 and 4 entries)
   T gmu[4] = {0, 0, 0, 0}, gls[4] = {0, 0, 0, 0}, grot[8] = {0, 0, 0, 0, 0, 0, 0, 0}, gop = 0;
+  constexpr int RM = STATIC ? 3 : 4, RL = STATIC ? 3 : 4, RR = STATIC ? 4 : 8;
   T gsh[3 * K];
 #pragma unroll
   for (int j = 0; j < 3 * K; ++j) gsh[j] = T(0);
@@ -281,32 +298,37 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
     if (!any) continue;
     T mu[4], ls[4], rot[8];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      mu[c] = g.means[c * (long)n + i];
-      ls[c] = g.log_scales[c * (long)n + i];
-    }
+    for (int c = 0; c < RM; ++c) mu[c] = g.means[c * (long)n + i];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) rot[c] = g.rotors[c * (long)n + i];
+    for (int c = 0; c < RL; ++c) ls[c] = g.log_scales[c * (long)n + i];
+#pragma unroll
+    for (int c = 0; c < RR; ++c) rot[c] = g.rotors[c * (long)n + i];
     const ViewDev v = slots[vi].v;
     Fwd<T> f;
+    auto fwd_bwd = [&](const T* shp, long stride) {
+      if (STATIC) {
+        gaussian_fwd_static<T>(mu, ls, rot, g.opacity[i], shp, stride, DEG, v, st, f);
+        gaussian_bwd_static<T>(f, shp, stride, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
+      } else {
+        gaussian_fwd<T>(mu, ls, rot, g.opacity[i], shp, stride, DEG, v, st, f);
+        gaussian_bwd<T, T, FLOW>(f, shp, stride, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
+      }
+    };
     if (MULTI) {
-      gaussian_fwd<T>(mu, ls, rot, g.opacity[i], g.sh + i, (long)n, DEG, v, st, f);
-      gaussian_bwd<T, T, FLOW>(f, g.sh + i, (long)n, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
+      fwd_bwd(g.sh + i, (long)n);
     } else {
       T shl[3 * K];
 #pragma unroll
       for (int j = 0; j < 3 * K; ++j) shl[j] = g.sh[j * (long)n + i];
-      gaussian_fwd<T>(mu, ls, rot, g.opacity[i], shl, 1, DEG, v, st, f);
-      gaussian_bwd<T, T, FLOW>(f, shl, 1, DEG, v, g2, gmu, gls, grot, gop, gsh, 1L);
+      fwd_bwd(shl, 1L);
     }
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    out.means[c * (long)n + i] = gmu[c];
-    out.log_scales[c * (long)n + i] = gls[c];
-  }
+  for (int c = 0; c < RM; ++c) out.means[c * (long)n + i] = gmu[c];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) out.rotors[c * (long)n + i] = grot[c];
+  for (int c = 0; c < RL; ++c) out.log_scales[c * (long)n + i] = gls[c];
+#pragma unroll
+  for (int c = 0; c < RR; ++c) out.rotors[c * (long)n + i] = grot[c];
   out.opacity[i] = gop;
 #pragma unroll
   for (int j = 0; j < 3 * K; ++j) out.sh[j * (long)n + i] = gsh[j];
@@ -314,12 +336,12 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
 
 }  // namespace
 
-#define R4D_DEG_DISPATCH(KERNEL, GRID, ...)                                              \
+#define R4D_DEG_DISPATCH(KERNEL, S, GRID, ...)                                           \
   switch (g.deg) {                                                                       \
-    case 0: hipLaunchKernelGGL((KERNEL<T, 0>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
-    case 1: hipLaunchKernelGGL((KERNEL<T, 1>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
-    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
-    case 3: hipLaunchKernelGGL((KERNEL<T, 3>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 0: hipLaunchKernelGGL((KERNEL<T, 0, S>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 1: hipLaunchKernelGGL((KERNEL<T, 1, S>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<T, 2, S>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+    case 3: hipLaunchKernelGGL((KERNEL<T, 3, S>), GRID, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
     default: return hipErrorInvalidValue;                                                \
   }
 
@@ -329,14 +351,20 @@ hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
                                  Vec2<T>* flows, Rect16* rects, uint32_t* tiles_touched,
                                  uint32_t* depth_keys, unsigned long long* totals,
                                  uint32_t* vis_keys, uint32_t* vis_index, SegTable* dseg,
-                                 void* temp, hipStream_t stream) {
+                                 void* temp, bool static3d, hipStream_t stream) {
   if (g.n <= 0 || n_views <= 0) return hipSuccess;
   const uint32_t blocks = uint32_t((g.n + kBlock - 1) / kBlock);
   const dim3 grid(blocks, uint32_t(n_views));
   ulonglong2* block_totals = static_cast<ulonglong2*>(temp);
   uint32_t* vis_prefix = reinterpret_cast<uint32_t*>(block_totals + size_t(blocks) * n_views);
-  R4D_DEG_DISPATCH(preprocess_fwd_kernel, grid, g, slots, st, n_pad, recs, flows, rects,
-                   tiles_touched, depth_keys, block_totals)
+  if (static3d) {
+    if (flows) return hipErrorInvalidValue;  // static Gaussians do not move
+    R4D_DEG_DISPATCH(preprocess_fwd_kernel, true, grid, g, slots, st, n_pad, recs, flows, rects,
+                     tiles_touched, depth_keys, block_totals)
+  } else {
+    R4D_DEG_DISPATCH(preprocess_fwd_kernel, false, grid, g, slots, st, n_pad, recs, flows, rects,
+                     tiles_touched, depth_keys, block_totals)
+  }
   hipLaunchKernelGGL(totals_kernel, dim3(uint32_t(n_views)), dim3(kBlock), 0, stream, block_totals,
                      blocks, totals, vis_prefix, dseg);
   hipLaunchKernelGGL(compact_keys_kernel, grid, dim3(kBlock), 0, stream, depth_keys, uint32_t(g.n),
@@ -352,27 +380,34 @@ size_t preprocess_temp_bytes(uint32_t n, int n_views) {
 template <typename T>
 hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, const double* grad2d, bool flow,
-                                 const GradPtrs<T>& out, hipStream_t stream) {
+                                 bool static3d, const GradPtrs<T>& out, hipStream_t stream) {
   if (g.n <= 0) return hipSuccess;
+  if (flow && static3d) return hipErrorInvalidValue;
   const dim3 grid((g.n + kBlock - 1) / kBlock);
-#define R4D_BWD_DISPATCH(MULTI, FLOW)                                                        \
+#define R4D_BWD_DISPATCH(MULTI, FLOW, S)                                                     \
   switch (g.deg) {                                                                           \
-    case 0: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 0, MULTI, FLOW>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
-    case 1: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 1, MULTI, FLOW>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
-    case 2: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 2, MULTI, FLOW>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
-    case 3: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 3, MULTI, FLOW>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 0: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 0, MULTI, FLOW, S>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 1: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 1, MULTI, FLOW, S>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 2: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 2, MULTI, FLOW, S>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
+    case 3: hipLaunchKernelGGL((preprocess_bwd_kernel<T, 3, MULTI, FLOW, S>), grid, dim3(kBlock), 0, stream, g, slots, n_views, st, grad2d, out); break; \
     default: return hipErrorInvalidValue;                                                    \
   }
-  if (flow) {
+  if (static3d) {
     if (n_views > 1) {
-      R4D_BWD_DISPATCH(true, true)
+      R4D_BWD_DISPATCH(true, false, true)
     } else {
-      R4D_BWD_DISPATCH(false, true)
+      R4D_BWD_DISPATCH(false, false, true)
+    }
+  } else if (flow) {
+    if (n_views > 1) {
+      R4D_BWD_DISPATCH(true, true, false)
+    } else {
+      R4D_BWD_DISPATCH(false, true, false)
     }
   } else if (n_views > 1) {
-    R4D_BWD_DISPATCH(true, false)
+    R4D_BWD_DISPATCH(true, false, false)
   } else {
-    R4D_BWD_DISPATCH(false, false)
+    R4D_BWD_DISPATCH(false, false, false)
   }
 #undef R4D_BWD_DISPATCH
   return hipGetLastError();
@@ -385,9 +420,9 @@ hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
                                                const SettingsDev&, uint32_t, Rec<T>*, Vec2<T>*, \
                                                Rect16*, uint32_t*, uint32_t*,                  \
                                                unsigned long long*, uint32_t*, uint32_t*,      \
-                                               SegTable*, void*, hipStream_t);                 \
+                                               SegTable*, void*, bool, hipStream_t);           \
   template hipError_t launch_preprocess_bwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
-                                               const SettingsDev&, const double*, bool,        \
+                                               const SettingsDev&, const double*, bool, bool,  \
                                                const GradPtrs<T>&, hipStream_t);
 R4D_INST(float)
 R4D_INST(double)

@@ -71,7 +71,7 @@ hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
                                  Vec2<T>* flows, Rect16* rects, uint32_t* tiles_touched,
                                  uint32_t* depth_keys, unsigned long long* totals,
                                  uint32_t* vis_keys, uint32_t* vis_index, SegTable* dseg,
-                                 void* temp, hipStream_t stream);
+                                 void* temp, bool static3d, hipStream_t stream);
 
 // grad2d: [V][C][n] double, C = 9 (mean2 x, y, Sigma_2D (0,0), (0,1), (1,1),
 // opacity_t, r, g, b) or, with flow, 11 (then flow x, y).  Writes the parameter
@@ -79,7 +79,7 @@ hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
 template <typename T>
 hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
                                  const SettingsDev& st, const double* grad2d, bool flow,
-                                 const GradPtrs<T>& out, hipStream_t stream);
+                                 bool static3d, const GradPtrs<T>& out, hipStream_t stream);
 
 // ---- binning and sorting
 // Zeroes `bytes` (a multiple of 16) at p (16-byte aligned) with a kernel, so
@@ -337,9 +337,10 @@ hipError_t densify_scatter(const DensifyArgs& d, const void* temp, uint32_t tota
 // p[0..count) = value (float or double elements).
 hipError_t fill_const(void* p, size_t count, double value, bool f64, hipStream_t stream);
 // out += tmp, tmp holding the five gradient arrays back to back
-// (means 4n, log_scales 4n, rotors 8n, opacity n, sh k3 n).
+// (means 4n, log_scales 4n, rotors 8n, opacity n, sh k3 n; for static 3D
+// Gaussians 3n, 3n, 4n, n, k3 n).
 template <typename T>
-hipError_t add_grads(const GradPtrs<T>& out, const T* tmp, size_t n, size_t k3,
+hipError_t add_grads(const GradPtrs<T>& out, const T* tmp, size_t n, size_t k3, bool static3d,
                      hipStream_t stream);
 // dst[t] = src[t] - (base, base); empty ranges stay [0, 0).
 hipError_t copy_ranges_rebased(const uint2* src, uint32_t count, uint32_t base, uint2* dst,

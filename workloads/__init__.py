@@ -83,6 +83,35 @@ def gaussians(n: int, sh_degree: int, *, seed: int = GAUSSIAN_SEED,
     }
 
 
+def static_gaussians(n: int, sh_degree: int, *, seed: int = GAUSSIAN_SEED,
+                     xyz_half_extent: float = 1.0) -> dict:
+    """Draw n static 3D Gaussians (a 3D Gaussian Splatting scene).
+
+    Draw order: mu ~ U[-e, e]^3, log s ~ N(-3, .5)^3, q ~ N(0, I4) (stored as
+    drawn, (w, x, y, z)), opacity = sigmoid(N(0,1)), SH DC ~ U[0,1], higher
+    bands ~ N(0, 0.05)."""
+    rng = np.random.default_rng(seed)
+    k = sh_coeffs(sh_degree)
+    mu = rng.uniform(-xyz_half_extent, xyz_half_extent, size=(3, n))
+    ls = rng.normal(-3.0, 0.5, size=(3, n))
+    q = rng.normal(0.0, 1.0, size=(4, n))
+    opacity = 1.0 / (1.0 + np.exp(-rng.normal(0.0, 1.0, size=n)))
+    sh = np.zeros((k, 3, n))
+    sh[0] = rng.uniform(0.0, 1.0, size=(3, n))
+    if k > 1:
+        sh[1:] = rng.normal(0.0, 0.05, size=(k - 1, 3, n))
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return {"means": f32(mu), "log_scales": f32(ls), "quats": f32(q), "opacity": f32(opacity),
+            "sh": f32(sh.reshape(3 * k, n)), "sh_degree": int(sh_degree)}
+
+
+def scene_static_500k(n: int = 500_000):
+    """500k static 3D Gaussians, SH degree 3, 1352x1014, f=1000, camera (0,0,-4)."""
+    g = static_gaussians(n, 3)
+    v = view(orbit_position(0), 1352, 1014, 1000.0, 0.5)
+    return g, [v], settings()
+
+
 def subset(g: dict, count: int) -> dict:
     """The first `count` Gaussians of a set (used for the finite-difference scene)."""
     out = {key: (np.ascontiguousarray(v[..., :count]) if isinstance(v, np.ndarray) else v)
