@@ -43,14 +43,13 @@ struct RunLayout {
   // fixed block
   size_t meta, recs, flows, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp,
       ranges, T_final, n_contrib, n_eval, img_copy, flow_copy, walk, ptemp_fwd, zero_begin,
-      totals, dhist, tickets, dstatus, zero_end, fixed_bytes;
+      status, totals, dhist, tickets, dstatus, zero_end, fixed_bytes;
   // entries block
   size_t tkA, tkB, tvA, tvB, tdig, thi, t16, etemp, ptemp, ck, ckf, tstatus, entries_bytes;
 };
 
 constexpr int kTicketTile = 4;     // tickets[0..3] depth passes, [4..6] tile passes
 constexpr int kTicketRaster = 7;   // [7] forward rasteriser
-constexpr int kErrorWord = 15;     // tickets[15]: sort look-back error flag
 constexpr int kDepthItems = 8;  // keys per thread of the depth sort passes (measured best)
 
 // Host-side plan of one run.
@@ -127,7 +126,7 @@ struct RunState {
   bool counts_valid = false;
   // pinned readback of totals + flags, filled at the end of the run
   r4d_ctx::Pinned* slot = nullptr;
-  unsigned long long* pinned = nullptr;  // [2 * V + 2] (2 * kMaxViews + 2 words)
+  unsigned long long* pinned = nullptr;  // status word pair, then 2 V totals (2 kMaxViews + 2 words)
   hipEvent_t done = nullptr;
   size_t image_offset = 0;     // first image element of this run in the call's images
   size_t flow_offset = 0;      // first flow element of this run in the call's flow images
@@ -442,7 +441,10 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.walk = take(size_t(p.total_tiles) * 4);
   L.ptemp_fwd = take(preprocess_temp_bytes(p.n, p.V));
   L.zero_begin = off;
-  L.totals = take(2 * size_t(kMaxViews) * 8);
+  // status words (overflow, sort look-back error) followed by the per-render
+  // totals, so that one copy returns all a run reports
+  L.status = take(16 + 2 * size_t(kMaxViews) * 8);
+  L.totals = L.status + 16;
   L.dhist = take(4 * size_t(kMaxViews) * 256 * 4);
   L.tickets = take(16 * 4);
   L.dstatus = take(4 * size_t(sort_status_words(uint64_t(V) * np, kDepthItems)) * 4);
@@ -532,7 +534,8 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   SegTable* tseg = tseg_of(F, L, p.V);
   auto* totals = at<unsigned long long>(F, L.totals);
   auto* tickets = at<uint32_t>(F, L.tickets);
-  uint32_t* error = tickets + kErrorWord;
+  uint32_t* status = at<uint32_t>(F, L.status);  // [0] overflow, [1] look-back error
+  uint32_t* error = status + 1;
   R4D_HIP(fill_zero(F + L.zero_begin, L.zero_end - L.zero_begin, stream));
   const uint32_t* order = nullptr;
   if (p.n > 0) {
@@ -598,7 +601,7 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   }
   uint8_t* E = r.entries;
   auto* ranges = at<uint2>(F, L.ranges);
-  R4D_HIP(seg_table(totals, p.V, r.capacity, tseg, stream));
+  R4D_HIP(seg_table(totals, p.V, r.capacity, tseg, status, stream));
   uint32_t* values = at<uint32_t>(E, L.tvA);
   const void* sorted_tiles = nullptr;
   if (p.n > 0) {
@@ -656,13 +659,9 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
 // event (outside any capture).
 r4d_status finish_run(r4d_ctx* ctx, RunState& r, hipStream_t stream) {
   const Plan& p = r.plan;
-  R4D_HIP(hipMemcpyAsync(r.pinned, r.fixed + r.L.totals, 2 * size_t(p.V) * 8,
-                         hipMemcpyDeviceToHost, stream));
-  // overflow flag (SegTable.overflow) and look-back error word
-  R4D_HIP(hipMemcpyAsync(reinterpret_cast<uint32_t*>(r.pinned + 2 * p.V),
-                         &tseg_of(r.fixed, r.L, p.V)->overflow, 4, hipMemcpyDeviceToHost, stream));
-  R4D_HIP(hipMemcpyAsync(reinterpret_cast<uint32_t*>(r.pinned + 2 * p.V) + 1,
-                         at<uint32_t>(r.fixed, r.L.tickets) + kErrorWord, 4,
+  // status words and totals in one copy: pinned[0] = (overflow, error),
+  // pinned[1] unused, pinned[2 + 2v], [3 + 2v] = render v's totals
+  R4D_HIP(hipMemcpyAsync(r.pinned, r.fixed + r.L.status, 16 + 2 * size_t(p.V) * 8,
                          hipMemcpyDeviceToHost, stream));
   R4D_HIP(hipEventRecord(r.done, stream));
   r.counts_valid = false;
@@ -676,10 +675,10 @@ r4d_status wait_run(r4d_ctx* ctx, RunState& r) {
   r.n_visible.assign(size_t(V), 0);
   r.n_dup.assign(size_t(V), 0);
   for (int v = 0; v < V; ++v) {
-    r.n_visible[size_t(v)] = r.pinned[2 * v];
-    r.n_dup[size_t(v)] = r.pinned[2 * v + 1];
+    r.n_visible[size_t(v)] = r.pinned[2 + 2 * v];
+    r.n_dup[size_t(v)] = r.pinned[3 + 2 * v];
   }
-  const uint32_t* fl = reinterpret_cast<const uint32_t*>(r.pinned + 2 * V);
+  const uint32_t* fl = reinterpret_cast<const uint32_t*>(r.pinned);
   r.flags[0] = fl[0];
   r.flags[1] = fl[1];
   r.counts_valid = true;
@@ -836,7 +835,7 @@ r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
   if (e && e->run.done) {
     // an overflow of an earlier replay grows the capacity (checked without waiting)
     if (hipEventQuery(e->run.done) == hipSuccess) {
-      const uint32_t* fl = reinterpret_cast<const uint32_t*>(e->run.pinned + 2 * V);
+      const uint32_t* fl = reinterpret_cast<const uint32_t*>(e->run.pinned);
       if (fl[0]) e->needs_grow = true;
     } else {
       (void)hipGetLastError();
@@ -847,7 +846,7 @@ r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
     if (e) {
       // the overflowed replay still counted every view's entries
       uint64_t needed = 0;
-      for (int v = 0; v < V; ++v) needed += round_seg(e->run.pinned[2 * v + 1]);
+      for (int v = 0; v < V; ++v) needed += round_seg(e->run.pinned[3 + 2 * v]);
       cap = std::max(e->run.capacity * 2, needed + needed / 4 + uint64_t(V) * kSegAlign);
       R4D_HIP(hipStreamSynchronize(stream));
       if (e->fwd) (void)hipGraphExecDestroy(e->fwd);

@@ -335,7 +335,8 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
 // not fit the capacity (or a render exceeds the per-segment limit) every
 // segment is empty and `overflow` is set.
 __global__ void seg_table_kernel(const unsigned long long* __restrict__ totals, int n_views,
-                                 unsigned long long capacity, SegTable* __restrict__ seg) {
+                                 unsigned long long capacity, SegTable* __restrict__ seg,
+                                 uint32_t* __restrict__ overflow_out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   unsigned long long total = 0;
   bool too_long = false;
@@ -355,6 +356,7 @@ __global__ void seg_table_kernel(const unsigned long long* __restrict__ totals, 
   seg->start[n_views] = overflow ? 0u : uint32_t(total);
   seg->count = uint32_t(n_views);
   seg->overflow = overflow ? 1u : 0u;
+  if (overflow_out) *overflow_out = overflow ? 1u : 0u;
 }
 
 // Exclusive scan input: tile counts of every render's Gaussians in depth order,
@@ -1003,9 +1005,9 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
 }
 
 hipError_t seg_table(const unsigned long long* totals, int n_views, unsigned long long capacity,
-                     SegTable* seg, hipStream_t stream) {
+                     SegTable* seg, uint32_t* overflow_out, hipStream_t stream) {
   hipLaunchKernelGGL(seg_table_kernel, dim3(1), dim3(64), 0, stream, totals, n_views, capacity,
-                     seg);
+                     seg, overflow_out);
   return hipGetLastError();
 }
 

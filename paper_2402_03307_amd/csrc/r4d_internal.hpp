@@ -110,9 +110,9 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
 // Segment table of the emitted list from the per-render entry counts
 // (totals[2v + 1]): render v starts at the sum of the earlier renders' counts,
 // each rounded up to kSegAlign; all segments empty and `overflow` set when
-// they exceed `capacity`.
+// they exceed `capacity` (also written to *overflow_out when not null).
 hipError_t seg_table(const unsigned long long* totals, int n_views, unsigned long long capacity,
-                     SegTable* seg, hipStream_t stream);
+                     SegTable* seg, uint32_t* overflow_out, hipStream_t stream);
 
 size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
 // offsets[v * n_pad + k] = sum over renders u < v of all their entries plus the

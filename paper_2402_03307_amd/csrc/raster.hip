@@ -597,6 +597,47 @@ __global__ __launch_bounds__(256) void seg_map_kernel(const uint32_t* __restrict
   for (uint32_t i = 0; i < c; ++i) seg_tile[b + i] = t;
 }
 
+// The three steps above in one workgroup, for runs of at most kSegPlanOne tiles
+// (a dependent launch costs several microseconds, more than this scan): the
+// tiles are taken 1024 at a time, each chunk scanned across the workgroup and
+// offset by the total of the chunks before it.
+constexpr uint32_t kSegPlanOne = 16384;
+
+__global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restrict__ walk,
+                                                        uint32_t total_tiles,
+                                                        uint32_t* __restrict__ base,
+                                                        uint32_t* __restrict__ seg_tile) {
+  __shared__ uint32_t s_wave[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < total_tiles; c0 += 1024) {
+    const uint32_t t = c0 + threadIdx.x;
+    const uint32_t cnt = t < total_tiles ? (walk[t] + kSegment - 1) / kSegment : 0u;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, chunk = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      before += w < wave ? s_wave[w] : 0u;
+      chunk += s_wave[w];
+    }
+    __syncthreads();
+    if (t < total_tiles) {
+      const uint32_t b = carry + before + incl - cnt;
+      base[t] = b;
+      for (uint32_t i = 0; i < cnt; ++i) seg_tile[b + i] = t;
+    }
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) base[total_tiles] = carry;
+}
+
 // Workgroups resident on the whole chip at once (occupancy x compute units);
 // a persistent launch needs no more.
 template <typename K>
@@ -697,12 +738,18 @@ hipError_t raster_bwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
   uint32_t* base = count + total_tiles + 1;
   uint32_t* seg_tile = base + total_tiles + 1;
   uint32_t* scan_tmp = seg_tile + max_items;
-  const uint32_t tb = (total_tiles + 255) / 256;
-  hipLaunchKernelGGL(seg_count_kernel, dim3(tb), dim3(256), 0, stream, sv.walk, total_tiles, count);
-  hipError_t e = scan_u32(count, total_tiles, base, scan_tmp, stream);  // base[total_tiles] = total
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(seg_map_kernel, dim3(tb), dim3(256), 0, stream, count, base, total_tiles,
-                     seg_tile);
+  if (total_tiles <= kSegPlanOne) {
+    hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(1024), 0, stream, sv.walk, total_tiles, base,
+                       seg_tile);
+  } else {
+    const uint32_t tb = (total_tiles + 255) / 256;
+    hipLaunchKernelGGL(seg_count_kernel, dim3(tb), dim3(256), 0, stream, sv.walk, total_tiles,
+                       count);
+    const hipError_t e = scan_u32(count, total_tiles, base, scan_tmp, stream);  // base[T] = total
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(seg_map_kernel, dim3(tb), dim3(256), 0, stream, count, base, total_tiles,
+                       seg_tile);
+  }
   const bool flow = dL_dflow != nullptr;
   if (flow && (!flows || !sv.ckf || !sv.flow)) return hipErrorInvalidValue;
   static const uint32_t cap_plain = resident_groups(raster_bwd_kernel<T, TS, PPT, false>, NT);
