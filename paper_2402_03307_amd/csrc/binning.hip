@@ -680,10 +680,11 @@ __global__ __launch_bounds__(kThreads) void lo_count_kernel(const uint8_t* __res
   cnt[size_t(b) * 256 + tid] = c;
 }
 
-// Exclusive prefix of M[rows][256] along rows, per column: P[r][d] =
-// sum_{r' < r} M[r'][d] for r <= rows.  Three steps: per-stripe prefixes and
-// stripe totals, a scan of the stripe totals (one workgroup per column), and
-// their addition.
+// Exclusive prefix of M[rows][256] along rows, per column: sum_{r' < r} M[r'][d]
+// for r <= rows, in two launches: per-stripe prefixes P and stripe totals T,
+// then a scan of the stripe totals (one workgroup per column, which also
+// writes the column totals to P[rows]).  The prefix of row r < rows is then
+// P[r][d] + T[r / kStripe][d] (col_prefix), added where it is read.
 constexpr int kStripe = 32;
 
 __global__ __launch_bounds__(256) void col_scan_stripes_kernel(const uint32_t* __restrict__ M,
@@ -726,30 +727,26 @@ __global__ __launch_bounds__(256) void col_scan_totals_kernel(uint32_t* __restri
   if (threadIdx.x == 0) P[size_t(rows) * 256 + d] = run;
 }
 
-__global__ __launch_bounds__(256) void col_scan_add_kernel(uint32_t* __restrict__ P, uint32_t rows,
-                                                           const uint32_t* __restrict__ T) {
-  const uint32_t d = threadIdx.x, st = blockIdx.x;
-  const uint32_t add = T[size_t(st) * 256 + d];
-  const uint32_t r0 = st * kStripe;
-#pragma unroll 8
-  for (int i = 0; i < kStripe; ++i) {
-    const uint32_t r = r0 + i;
-    if (r < rows) P[size_t(r) * 256 + d] += add;
-  }
+__device__ __forceinline__ uint32_t col_prefix(const uint32_t* __restrict__ P,
+                                               const uint32_t* __restrict__ T, uint32_t rows,
+                                               uint32_t r, uint32_t d) {
+  return r >= rows ? P[size_t(rows) * 256 + d]
+                   : P[size_t(r) * 256 + d] + T[size_t(r / kStripe) * 256 + d];
 }
 
 // Per-digit output base of block b of the segment [first, end) of blocks:
 // segment start + counts of lower digits in the segment + counts of digit d
 // in the segment's earlier blocks.
-__device__ __forceinline__ uint32_t digit_out_base(const uint32_t* __restrict__ P, uint32_t first,
-                                                   uint32_t end, uint32_t b, uint32_t seg_start,
-                                                   uint32_t* s_w) {
+__device__ __forceinline__ uint32_t digit_out_base(const uint32_t* __restrict__ P,
+                                                   const uint32_t* __restrict__ T, uint32_t rows,
+                                                   uint32_t first, uint32_t end, uint32_t b,
+                                                   uint32_t seg_start, uint32_t* s_w) {
   const uint32_t d = threadIdx.x;
-  const uint32_t pf = P[size_t(first) * 256 + d];
-  const uint32_t tot_d = P[size_t(end) * 256 + d] - pf;
+  const uint32_t pf = col_prefix(P, T, rows, first, d);
+  const uint32_t tot_d = col_prefix(P, T, rows, end, d) - pf;
   uint32_t tot;
   const uint32_t lower = block_excl_scan<kThreads>(tot_d, s_w, &tot);
-  return seg_start + lower + (P[size_t(b) * 256 + d] - pf);
+  return seg_start + lower + (col_prefix(P, T, rows, b, d) - pf);
 }
 
 // Stable rank of a block's entries by a digit of `nbits` bits (entries held in
@@ -804,6 +801,7 @@ __global__ __launch_bounds__(kThreads) void lo_pass_kernel(const uint32_t* __res
                                                            const uint8_t* __restrict__ digits,
                                                            const SegTable* __restrict__ seg,
                                                            const uint32_t* __restrict__ P,
+                                                           const uint32_t* __restrict__ T,
                                                            uint32_t* __restrict__ out,
                                                            uint8_t* __restrict__ hi_out) {
   constexpr int ITEMS = kChunk / kThreads;
@@ -827,7 +825,7 @@ __global__ __launch_bounds__(kThreads) void lo_pass_kernel(const uint32_t* __res
     x[i] = q < nvalid ? in[e0 + q] : 0u;
     dg[i] = q < nvalid ? uint32_t(digits[e0 + q]) : 0u;
   }
-  s_base[tid] = digit_out_base(P, sstart / uint32_t(kChunk),
+  s_base[tid] = digit_out_base(P, T, gridDim.x, sstart / uint32_t(kChunk),
                                (send + uint32_t(kChunk) - 1) / uint32_t(kChunk), b, sstart, s_w);
   rank_block<ITEMS>(dg, nvalid, 8, s_wh, s_start, s_w, pos);
 #pragma unroll
@@ -855,6 +853,7 @@ __global__ __launch_bounds__(kThreads) void hi_pass_kernel(const uint32_t* __res
                                                            const uint8_t* __restrict__ hi_in,
                                                            const SegTable* __restrict__ seg,
                                                            const uint32_t* __restrict__ P,
+                                                           const uint32_t* __restrict__ T,
                                                            int nbits,
                                                            uint32_t* __restrict__ values,
                                                            uint16_t* __restrict__ tiles) {
@@ -879,7 +878,7 @@ __global__ __launch_bounds__(kThreads) void hi_pass_kernel(const uint32_t* __res
     x[i] = q < nvalid ? in[e0 + q] : 0u;
     dg[i] = q < nvalid ? uint32_t(hi_in[e0 + q]) : 0u;
   }
-  s_base[tid] = digit_out_base(P, sstart / uint32_t(kChunk),
+  s_base[tid] = digit_out_base(P, T, gridDim.x, sstart / uint32_t(kChunk),
                                (send + uint32_t(kChunk) - 1) / uint32_t(kChunk), b, sstart, s_w);
   rank_block<ITEMS>(dg, nvalid, nbits, s_wh, s_start, s_w, pos);
 #pragma unroll
@@ -1117,8 +1116,6 @@ hipError_t col_scan(const uint32_t* M, uint32_t rows, uint32_t* P, uint32_t* T,
     hipLaunchKernelGGL(col_scan_stripes_kernel, dim3(stripes), dim3(256), 0, stream, M, rows, P,
                        T);
   hipLaunchKernelGGL(col_scan_totals_kernel, dim3(256), dim3(256), 0, stream, T, stripes, P, rows);
-  if (stripes > 0)
-    hipLaunchKernelGGL(col_scan_add_kernel, dim3(stripes), dim3(256), 0, stream, P, rows, T);
   return hipGetLastError();
 }
 }  // namespace
@@ -1140,14 +1137,14 @@ hipError_t packed_tile_sort(const uint32_t* packed, const uint8_t* digits, const
   hipError_t e = col_scan(M1, rows, P1, T1, stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(lo_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, packed, digits, seg,
-                     P1, mid, mid_hi);
+                     P1, T1, mid, mid_hi);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(lo_count_kernel, dim3(rows), dim3(kThreads), 0, stream, mid_hi, seg, M2);
   if ((e = col_scan(M2, rows, P2, T2, stream)) != hipSuccess) return e;
   int nbits = 1;
   while ((1u << nbits) < (max_tiles + 255u) / 256u) ++nbits;
   hipLaunchKernelGGL(hi_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, mid, mid_hi, seg, P2,
-                     nbits, values, tiles);
+                     T2, nbits, values, tiles);
   return hipGetLastError();
 }
 
