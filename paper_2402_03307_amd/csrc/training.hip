@@ -20,6 +20,31 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// One element's update (shared by the scalar and the 4-wide kernels).
+__device__ __forceinline__ void adam_one(float& p, float g, float& mo, float& vo, float& l,
+                                         bool is_logit, float lr, float bc1, float bc2,
+                                         const AdamConfig& c) {
+  if (is_logit) {  // opacity: the update acts on the logit
+    const float o = 1.0f / (1.0f + expf(-l));
+    g *= o * (1.0f - o);
+  }
+  const float mm = c.beta1 * mo + (1.0f - c.beta1) * g;
+  const float vv = c.beta2 * vo + (1.0f - c.beta2) * g * g;
+  mo = mm;
+  vo = vv;
+  const float upd = lr * (mm / bc1) / (sqrtf(vv / bc2) + c.eps);
+  if (is_logit) {
+    l -= upd;
+    p = 1.0f / (1.0f + expf(-l));
+  } else {
+    p -= upd;
+  }
+}
+
+// VEC = 4: four consecutive elements per thread with 16-byte accesses (valid
+// when n is a multiple of 4 and every array is 16-byte aligned, so that the
+// four fall in one group and one row); VEC = 1 otherwise.
+template <int VEC>
 __global__ __launch_bounds__(kBlock) void adam_kernel(AdamGroups G, float* __restrict__ logit,
                                                       float* __restrict__ m,
                                                       float* __restrict__ v,
@@ -33,37 +58,40 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(AdamGroups G, float* __res
   u = u < 1.0f ? u : 1.0f;
   const float lr_means = expf((1.0f - u) * logf(c.lr_means_init) + u * logf(c.lr_means_final));
   const float lrs[4] = {lr_means, c.lr_log_scales, c.lr_rotors, c.lr_opacity};
-  const uint64_t total = G.off[5];
+  const uint64_t total = G.off[5] / VEC;
   const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-  for (uint64_t e = uint64_t(blockIdx.x) * kBlock + threadIdx.x; e < total; e += stride) {
+  for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < total; i += stride) {
+    const uint64_t e = i * VEC;
     int k = 0;
 #pragma unroll
     for (int q = 1; q < 5; ++q) k += e >= G.off[q] ? 1 : 0;
     const uint64_t local = e - G.off[k];
-    float g = G.g[k][local];
-    float lr;
-    if (k == 4) {
-      lr = local < 3ull * G.n ? c.lr_sh_dc : c.lr_sh_rest;  // rows 0..2: degree 0
+    // rows 0..2 of the SH array: degree 0
+    const float lr = k == 4 ? (local < 3ull * G.n ? c.lr_sh_dc : c.lr_sh_rest) : lrs[k];
+    const bool is_logit = k == 3;
+    if (VEC == 4) {
+      float4 p = *reinterpret_cast<const float4*>(G.p[k] + local);
+      const float4 g = *reinterpret_cast<const float4*>(G.g[k] + local);
+      float4 mo = *reinterpret_cast<const float4*>(m + e);
+      float4 vo = *reinterpret_cast<const float4*>(v + e);
+      float4 l = is_logit ? *reinterpret_cast<const float4*>(logit + local)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+      adam_one(p.x, g.x, mo.x, vo.x, l.x, is_logit, lr, bc1, bc2, c);
+      adam_one(p.y, g.y, mo.y, vo.y, l.y, is_logit, lr, bc1, bc2, c);
+      adam_one(p.z, g.z, mo.z, vo.z, l.z, is_logit, lr, bc1, bc2, c);
+      adam_one(p.w, g.w, mo.w, vo.w, l.w, is_logit, lr, bc1, bc2, c);
+      *reinterpret_cast<float4*>(G.p[k] + local) = p;
+      *reinterpret_cast<float4*>(m + e) = mo;
+      *reinterpret_cast<float4*>(v + e) = vo;
+      if (is_logit) *reinterpret_cast<float4*>(logit + local) = l;
     } else {
-      lr = lrs[k];
-    }
-    float l = 0.f;
-    if (k == 3) {  // opacity: the update acts on the logit
-      l = logit[local];
-      const float o = 1.0f / (1.0f + expf(-l));
-      g *= o * (1.0f - o);
-    }
-    const float mm = c.beta1 * m[e] + (1.0f - c.beta1) * g;
-    const float vv = c.beta2 * v[e] + (1.0f - c.beta2) * g * g;
-    m[e] = mm;
-    v[e] = vv;
-    const float upd = lr * (mm / bc1) / (sqrtf(vv / bc2) + c.eps);
-    if (k == 3) {
-      l -= upd;
-      logit[local] = l;
-      G.p[3][local] = 1.0f / (1.0f + expf(-l));
-    } else {
-      G.p[k][local] -= upd;
+      float p = G.p[k][local], mo = m[e], vo = v[e];
+      float l = is_logit ? logit[local] : 0.f;
+      adam_one(p, G.g[k][local], mo, vo, l, is_logit, lr, bc1, bc2, c);
+      G.p[k][local] = p;
+      m[e] = mo;
+      v[e] = vo;
+      if (is_logit) logit[local] = l;
     }
   }
 }
@@ -130,10 +158,17 @@ hipError_t launch_adam(const AdamGroups& groups, float* logit, float* m, float* 
                        const AdamConfig& cfg, hipStream_t stream) {
   const uint64_t total = groups.off[5];
   if (total == 0) return hipSuccess;
-  uint64_t blocks = (total + kBlock - 1) / kBlock;
+  auto aligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+  bool vec = groups.n % 4 == 0 && aligned(logit) && aligned(m) && aligned(v);
+  for (int q = 0; q < 5; ++q) vec = vec && aligned(groups.p[q]) && aligned(groups.g[q]);
+  uint64_t blocks = (total / (vec ? 4 : 1) + kBlock - 1) / kBlock;
   if (blocks > 8192) blocks = 8192;  // grid-stride beyond: 2M threads cover HBM latency
-  hipLaunchKernelGGL(adam_kernel, dim3(uint32_t(blocks)), dim3(kBlock), 0, stream, groups, logit,
-                     m, v, step, cfg);
+  if (vec)
+    hipLaunchKernelGGL(adam_kernel<4>, dim3(uint32_t(blocks)), dim3(kBlock), 0, stream, groups,
+                       logit, m, v, step, cfg);
+  else
+    hipLaunchKernelGGL(adam_kernel<1>, dim3(uint32_t(blocks)), dim3(kBlock), 0, stream, groups,
+                       logit, m, v, step, cfg);
   hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(1), 0, stream, step);
   return hipGetLastError();
 }

@@ -52,8 +52,9 @@ def _split_moments(flat, g):
     return out
 
 
-def test_adam_steps_match_oracle(r4d, rend, device):
-    g = W.gaussians(3000, 3)
+@pytest.mark.parametrize("n", [3000, 3001])   # the 4-wide and the scalar kernel
+def test_adam_steps_match_oracle(r4d, rend, device, n):
+    g = W.gaussians(n, 3)
     p = to_device(g, device)
     state = r4d.TrainState(p)
     rng = np.random.default_rng(21)
