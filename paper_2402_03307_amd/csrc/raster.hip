@@ -123,20 +123,99 @@ __device__ __forceinline__ void row_sums(float (&v)[N]) {
   for (int i = 0; i < N; ++i) v[i] = dpp_add<0x140, 0xf>(v[i]);
 }
 
-// Sums over each half wavefront, valid in rows 1 and 3 (lanes 16..31 and
-// 48..63): the row sums, then row 15 -> rows 1, 3 (row_bcast:15).
+// x plus the value the lane move CTRL brings, all rows written (a lane with no
+// source adds 0), so that the move folds into the addition.
+template <int CTRL>
+__device__ __forceinline__ float dpp_add_all(float x) {
+  const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true);
+  return x + __int_as_float(moved);
+}
+
+// Sums over the whole wavefront, valid in row 3 (lanes 48..63) only: the row
+// sums r0..r3, then row_bcast:15 (lane 47 -> row 3, lane 15 -> row 1), which
+// leaves r2 + r3 in row 3 and r0 + r1 in lane 31, then row_bcast:31 (lane 31
+// -> row 3).  The other rows end up with partial sums that nothing reads.
 template <int N>
-__device__ __forceinline__ void half_sums(float (&v)[N]) {
+__device__ __forceinline__ void wave_sums(float (&v)[N]) {
   row_sums(v);
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = dpp_add<0x142, 0xa>(v[i]);
+  for (int i = 0; i < N; ++i) v[i] = dpp_add_all<0x142>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = dpp_add_all<0x143>(v[i]);
 }
 template <int N>
-__device__ __forceinline__ void half_sums(double (&v)[N]) {
+__device__ __forceinline__ void wave_sums(double (&v)[N]) {
 #pragma unroll
-  for (int i = 0; i < N; ++i)
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+}
+
+// gfx950 lane swaps.  permlane32_swap(x, y) exchanges the upper 32 lanes of x
+// with the lower 32 lanes of y, so the sum of the two results holds x folded
+// in half (lane l: x[l] + x[l + 32]) in lanes 0..31 and y folded in lanes
+// 32..63.  permlane16_swap does the same with the odd 16-lane rows of x and the
+// even rows of y: the sum holds rows (x0 + x1, y0 + y1, x2 + x3, y2 + y3).
+__device__ __forceinline__ float fold32(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float fold16(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wavefront sums of the NC per-Gaussian components, stored to s_grad[c][j]
+// (added, when several wavefronts share a tile).  Float: components are
+// folded four at a time, fold16(fold32(a, b), fold32(c, d)), which leaves a,
+// c, b, d partial sums in rows 0..3, and the row sums finish them; a ninth
+// component alone takes the row sums and two row broadcasts (total in row 3).
+// Lane 16 r stores row r's totals.
+template <int NC, int NT, int NB>
+__device__ __forceinline__ void store_wave_sums(float (&sv)[NC], float (*s_grad)[NB], int j,
+                                                int lane) {
+  static_assert(NC == 9 || NC == 11, "component groups of 4 + 1 or 4 + 3");
+  float q[3];  // two groups of 4, then the rest
+  q[0] = fold16(fold32(sv[0], sv[1]), fold32(sv[2], sv[3]));
+  q[1] = fold16(fold32(sv[4], sv[5]), fold32(sv[6], sv[7]));
+  if constexpr (NC == 9)
+    q[2] = sv[8];
+  else
+    q[2] = fold16(fold32(sv[8], sv[9]), fold32(sv[10], 0.0f));
+  row_sums(q);
+  if constexpr (NC == 9) {
+    q[2] = dpp_add_all<0x142>(q[2]);
+    q[2] = dpp_add_all<0x143>(q[2]);
+  }
+  if ((lane & 15) == 0) {
+    const int r = lane >> 4;
+    const int c = ((r & 1) << 1) | (r >> 1);  // row r holds component 4 g + c of group g
+    if (NT == 64) {
+      s_grad[c][j] = q[0];
+      s_grad[4 + c][j] = q[1];
+      if (NC == 9 && r == 3) s_grad[8][j] = q[2];
+      if (NC == 11 && c < 3) s_grad[8 + c][j] = q[2];
+    } else {
+      atomicAdd(&s_grad[c][j], q[0]);
+      atomicAdd(&s_grad[4 + c][j], q[1]);
+      if (NC == 9 && r == 3) atomicAdd(&s_grad[8][j], q[2]);
+      if (NC == 11 && c < 3) atomicAdd(&s_grad[8 + c][j], q[2]);
+    }
+  }
+}
+template <int NC, int NT, int NB>
+__device__ __forceinline__ void store_wave_sums(double (&sv)[NC], double (*s_grad)[NB], int j,
+                                                int lane) {
+  wave_sums(sv);
+  if (lane == 63) {
 #pragma unroll
-    for (int off = 16; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    for (int c = 0; c < NC; ++c) {
+      if (NT == 64)
+        s_grad[c][j] = sv[c];
+      else
+        atomicAdd(&s_grad[c][j], sv[c]);
+    }
+  }
 }
 
 template <typename T> __device__ __forceinline__ void atomic_add_nr(T* p, T v);
@@ -151,8 +230,11 @@ template <int TS, int PPT>
 struct TileCfg {
   static constexpr int kThreads = TS * TS / PPT;
   static constexpr int kRowStep = TS / PPT;
-  static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
-  // whole wavefronts only: the backward's DPP reductions work on half wavefronts
+  // records staged in LDS per batch: small batches waste few loads on a tile
+  // that saturates early in its list (measured faster than 128 or 256 on the
+  // 500k / 1352x1014 render)
+  static constexpr int kBatch = 64;
+  // whole wavefronts only: the backward's reductions work on whole wavefronts
   static_assert(kThreads % 64 == 0, "a tile must map onto whole wavefronts");
 };
 
@@ -294,9 +376,8 @@ template <typename T, int TS, int PPT, bool FLOW>
 struct BwdShared {
   Staged<T> rec[TileCfg<TS, PPT>::kBatch];
   uint32_t idx[TileCfg<TS, PPT>::kBatch];
-  // per component, half wavefront and batch slot (one padding slot, so that the
-  // two halves' writes fall in different banks)
-  T grad[kComps<FLOW>][2][TileCfg<TS, PPT>::kBatch + 1];
+  // per component and batch slot
+  T grad[kComps<FLOW>][TileCfg<TS, PPT>::kBatch];
   uint32_t max;
 };
 
@@ -316,7 +397,7 @@ __device__ __forceinline__ void raster_bwd_tile(
   constexpr int NC = kComps<FLOW>;
   Staged<T>* s_rec = sh.rec;
   uint32_t* s_idx = sh.idx;
-  T(*s_grad)[2][NB + 1] = sh.grad;
+  T(*s_grad)[NB] = sh.grad;
   uint32_t& s_max = sh.max;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int x = tx * TS + int(threadIdx.x % TS);
@@ -330,8 +411,12 @@ __device__ __forceinline__ void raster_bwd_tile(
   const uint32_t seg_end = lo + kSegment;
   const uint32_t hi = walk < seg_end ? walk : seg_end;
   const size_t cslot = size_t(ck_slot(rg.x, gtile, seg + 1)) * (TS * TS);
-  T py[PPT], Tcur[PPT], g0[PPT], g1[PPT], g2[PPT], acc0[PPT], acc1[PPT], acc2[PPT];
-  T g3[PPT], g4[PPT], acc3[PPT], acc4[PPT];  // flow channels
+  // Per pixel: the upstream gradients g (colour, then flow) and gacc = g . (colour
+  // accumulated behind the current Gaussian, background included).  Only that
+  // dot product enters dL/da, and g is fixed per pixel, so one running sum
+  // gacc += w (g . c) stands for the per-channel accumulators.
+  T py[PPT], Tcur[PPT], g0[PPT], g1[PPT], g2[PPT], gacc[PPT];
+  T g3[PPT], g4[PPT];  // flow channels
   uint32_t ncon[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -340,7 +425,7 @@ __device__ __forceinline__ void raster_bwd_tile(
     Tcur[k] = T(1);
     g0[k] = g1[k] = g2[k] = g3[k] = g4[k] = T(0);
     ncon[k] = 0u;
-    acc0[k] = acc1[k] = acc2[k] = acc3[k] = acc4[k] = T(0);
+    gacc[k] = T(0);
     if (x < v.W && y < v.H) {
       const long pix = long(y) * v.W + x;
       ncon[k] = n_contrib[pix];
@@ -357,21 +442,17 @@ __device__ __forceinline__ void raster_bwd_tile(
         const int pt = (int(threadIdx.x / TS) + k * Cfg::kRowStep) * TS + int(threadIdx.x % TS);
         const Ck<T> c = ck[cslot + pt];
         Tcur[k] = c.t;
-        acc0[k] = img_copy[pix] - c.r;
-        acc1[k] = img_copy[hw + pix] - c.g;
-        acc2[k] = img_copy[2 * hw + pix] - c.b;
+        gacc[k] = tfma(g0[k], img_copy[pix] - c.r,
+                       tfma(g1[k], img_copy[hw + pix] - c.g, g2[k] * (img_copy[2 * hw + pix] - c.b)));
         if (FLOW) {
           const Vec2<T> cf = ckf[cslot + pt];
-          acc3[k] = flow_copy[pix] - cf.x;
-          acc4[k] = flow_copy[hw + pix] - cf.y;
+          gacc[k] = tfma(g3[k], flow_copy[pix] - cf.x, tfma(g4[k], flow_copy[hw + pix] - cf.y, gacc[k]));
         }
       } else {
-        // (the flow's background is 0: nothing behind the last contributor)
-        // colour accumulated behind the current Gaussian (absolute, includes background)
+        // behind the last contributor: the background seen through T_final
+        // (the flow's background is 0)
         Tcur[k] = T_final[pix];
-        acc0[k] = Tcur[k] * T(v.bg[0]);
-        acc1[k] = Tcur[k] * T(v.bg[1]);
-        acc2[k] = Tcur[k] * T(v.bg[2]);
+        gacc[k] = Tcur[k] * tfma(g0[k], T(v.bg[0]), tfma(g1[k], T(v.bg[1]), g2[k] * T(v.bg[2])));
       }
     }
   }
@@ -394,8 +475,7 @@ __device__ __forceinline__ void raster_bwd_tile(
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        s_grad[c][0][threadIdx.x] = T(0);
-        s_grad[c][1][threadIdx.x] = T(0);
+        s_grad[c][threadIdx.x] = T(0);
       }
     }
     __syncthreads();
@@ -408,8 +488,11 @@ __device__ __forceinline__ void raster_bwd_tile(
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const bool pass = eval_pair(r, px, py[k], amax, ux[k], uy[k], G[k], a_raw[k], alpha[k]);
-        use[k] = pass & (bstart + uint32_t(j) < ncon[k]);
-        band[k] = __ballot(use[k]) != 0ull;  // some pixel of the wavefront's band k blended it
+        const bool in_front = bstart + uint32_t(j) < ncon[k];
+        use[k] = pass & in_front;
+        // some pixel of the wavefront's band k blended it (the two masks are
+        // taken apart, so that each is the comparison's own lane mask)
+        band[k] = (__builtin_amdgcn_ballot_w64(pass) & __builtin_amdgcn_ballot_w64(in_front)) != 0ull;
         any |= band[k];
       }
       if (!any) continue;  // no pixel of the wavefront blended it
@@ -427,23 +510,13 @@ __device__ __forceinline__ void raster_bwd_tile(
         const T inv_om = fast_rcp(T(1) - alpha[k]);
         const T Ti = Tcur[k] * inv_om;  // transmittance in front of this Gaussian
         const T w = use[k] ? alpha[k] * Ti : T(0);
-        // dC/da = T c - (colour behind) / (1 - a)
+        // dC/da = T c - (colour behind) / (1 - a), dotted with g
         T gc = tfma(g0[k], r.r, tfma(g1[k], r.g, g2[k] * r.b));
-        T gacc = tfma(g0[k], acc0[k], tfma(g1[k], acc1[k], g2[k] * acc2[k]));
-        if (FLOW) {
-          gc = tfma(g3[k], r.fu, tfma(g4[k], r.fv, gc));
-          gacc = tfma(g3[k], acc3[k], tfma(g4[k], acc4[k], gacc));
-        }
+        if (FLOW) gc = tfma(g3[k], r.fu, tfma(g4[k], r.fv, gc));
         // no gradient through the alpha clamp
         const T dL_da =
-            (use[k] & (a_raw[k] < amax)) ? inv_om * (Tcur[k] * gc - gacc) : T(0);
-        acc0[k] = tfma(r.r, w, acc0[k]);
-        acc1[k] = tfma(r.g, w, acc1[k]);
-        acc2[k] = tfma(r.b, w, acc2[k]);
-        if (FLOW) {
-          acc3[k] = tfma(r.fu, w, acc3[k]);
-          acc4[k] = tfma(r.fv, w, acc4[k]);
-        }
+            (use[k] & (a_raw[k] < amax)) ? inv_om * (Tcur[k] * gc - gacc[k]) : T(0);
+        gacc[k] = tfma(gc, w, gacc[k]);
         Tcur[k] = use[k] ? Ti : Tcur[k];
         const T ga = dL_da * a_raw[k];
         const T gx = ga * ux[k], gy = ga * uy[k];
@@ -461,20 +534,10 @@ __device__ __forceinline__ void raster_bwd_tile(
           sv[10] = tfma(w, g4[k], sv[10]);
         }
       }
-      // sums over each half wavefront, kept in LDS by lanes 16 and 48 (the
-      // components' scale factors are applied when the batch is flushed);
-      // with several wavefronts per tile the halves of all of them add up
-      half_sums(sv);
-      if ((lane & 31) == 16) {
-        const int hf = lane >> 5;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          if (NT == 64)
-            s_grad[c][hf][j] = sv[c];
-          else
-            atomicAdd(&s_grad[c][hf][j], sv[c]);
-        }
-      }
+      // sums over the wavefront, kept in LDS (the components' scale factors
+      // are applied when the batch is flushed); with several wavefronts per
+      // tile the sums of all of them add up
+      store_wave_sums<NC, NT, NB>(sv, s_grad, j, lane);
     }
     __syncthreads();
     // One global atomic per (tile, Gaussian, component); the sum over tiles is
@@ -488,7 +551,7 @@ __device__ __forceinline__ void raster_bwd_tile(
       const int c = e / nb, j = e % nb;
       const T scale = c < 2 ? T(-1.0 / kHalfLog2e)
                             : (c < 5 ? T(0.5 / (kHalfLog2e * kHalfLog2e)) : T(1));
-      const T val = (s_grad[c][0][j] + s_grad[c][1][j]) * scale;
+      const T val = s_grad[c][j] * scale;
       if (val != T(0)) atomic_add_nr(&grad2d[long(c) * n_gauss + s_idx[j]], double(val));
     }
     __syncthreads();
