@@ -608,7 +608,9 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
 
 // Backward work items are (tile, segment) pairs: seg_tile[i] names the tile of
 // item i and seg_base[tile] its first item, so the segments of one long list
-// run in parallel.
+// run in parallel.  order (or null: item order) lists the items in the order
+// they are taken, longest first, so that the short ones fill the gaps at the
+// end of the launch.
 template <typename T, int TS, int PPT, bool FLOW>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     const Rec<T>* __restrict__ recs, const Vec2<T>* __restrict__ flows, uint32_t n,
@@ -616,15 +618,16 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     const ViewSlot* __restrict__ slots, int n_views, SettingsDev st,
     const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, RasterSaved<T> sv,
     const uint32_t* __restrict__ seg_tile, const uint32_t* __restrict__ seg_base,
-    const uint32_t* __restrict__ total_items, const T* __restrict__ dL_dimage,
-    const T* __restrict__ dL_dflow, double* __restrict__ grad2d,
-    uint32_t* __restrict__ tickets) {
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ total_items,
+    const T* __restrict__ dL_dimage, const T* __restrict__ dL_dflow,
+    double* __restrict__ grad2d, uint32_t* __restrict__ tickets) {
   __shared__ BwdShared<T, TS, PPT, FLOW> sh;
   __shared__ uint32_t s_ticket;
   const uint32_t total = *total_items;
   for (uint32_t it = blockIdx.x; it < total;) {
-    const uint32_t g = seg_tile[it];
-    const uint32_t seg = it - seg_base[g];
+    const uint32_t item = order ? order[it] : it;
+    const uint32_t g = seg_tile[item];
+    const uint32_t seg = item - seg_base[g];
     const int vi = slot_of_tile(slots, n_views, g);
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
@@ -663,15 +666,28 @@ __global__ __launch_bounds__(256) void seg_map_kernel(const uint32_t* __restrict
 // The three steps above in one workgroup, for runs of at most kSegPlanOne tiles
 // (a dependent launch costs several microseconds, more than this scan): the
 // tiles are taken 1024 at a time, each chunk scanned across the workgroup and
-// offset by the total of the chunks before it.
+// offset by the total of the chunks before it.  The same workgroup then writes
+// the order in which the items are taken: every segment but a tile's last is
+// full (kSegment entries) and goes first; the last segments follow in
+// kLenBuckets classes of decreasing length (within a class, in any order).
 constexpr uint32_t kSegPlanOne = 16384;
+constexpr uint32_t kLenBuckets = 8;
+
+__device__ __forceinline__ uint32_t len_bucket(uint32_t len) {
+  const uint32_t b = (kSegment - len) * kLenBuckets / kSegment;
+  return b < kLenBuckets ? b : kLenBuckets - 1;
+}
 
 __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restrict__ walk,
                                                         uint32_t total_tiles,
                                                         uint32_t* __restrict__ base,
-                                                        uint32_t* __restrict__ seg_tile) {
+                                                        uint32_t* __restrict__ seg_tile,
+                                                        uint32_t* __restrict__ order) {
   __shared__ uint32_t s_wave[16];
+  __shared__ uint32_t s_next[kLenBuckets + 1];  // [0]: full segments, [1 + b]: class b
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x <= kLenBuckets) s_next[threadIdx.x] = 0u;
+  __syncthreads();
   uint32_t carry = 0;
   for (uint32_t c0 = 0; c0 < total_tiles; c0 += 1024) {
     const uint32_t t = c0 + threadIdx.x;
@@ -695,11 +711,49 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restri
       const uint32_t b = carry + before + incl - cnt;
       base[t] = b;
       for (uint32_t i = 0; i < cnt; ++i) seg_tile[b + i] = t;
+      if (cnt > 0) atomicAdd(&s_next[1 + len_bucket(walk[t] - (cnt - 1) * kSegment)], 1u);
     }
     carry += chunk;
   }
   if (threadIdx.x == 0) base[total_tiles] = carry;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // starts: full segments at 0, class b after the full ones and classes < b
+    uint32_t last = 0;
+    for (uint32_t b = 1; b <= kLenBuckets; ++b) last += s_next[b];
+    uint32_t off = carry - last;
+    s_next[0] = 0u;
+    for (uint32_t b = 1; b <= kLenBuckets; ++b) {
+      const uint32_t c = s_next[b];
+      s_next[b] = off;
+      off += c;
+    }
+  }
+  __syncthreads();
+  // each thread revisits its own tiles (base[t] is its own earlier write)
+  for (uint32_t t = threadIdx.x; t < total_tiles; t += 1024) {
+    const uint32_t cnt = (walk[t] + kSegment - 1) / kSegment;
+    if (cnt == 0) continue;
+    const uint32_t b = base[t];
+    const uint32_t f = atomicAdd(&s_next[0], cnt - 1);
+    for (uint32_t i = 0; i + 1 < cnt; ++i) order[f + i] = b + i;
+    const uint32_t q = atomicAdd(&s_next[1 + len_bucket(walk[t] - (cnt - 1) * kSegment)], 1u);
+    order[q] = b + cnt - 1;
+  }
 }
+
+int compute_units() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return cus;
+}
+
+// Wavefronts per compute unit of the backward's persistent launch.
+constexpr uint32_t kBwdWavesPerCu = 16;
 
 // Workgroups resident on the whole chip at once (occupancy x compute units);
 // a persistent launch needs no more.
@@ -795,16 +849,19 @@ hipError_t raster_bwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
                           double* grad2d, uint32_t* work, hipStream_t stream) {
   constexpr int NT = TS * TS / PPT;
   if (total_tiles == 0) return hipSuccess;
-  // work: [tickets (64 words, zeroed by the caller) | count | base | seg_tile | scan scratch]
+  // work: [tickets (64 words, zeroed by the caller) | count | base | seg_tile | order |
+  //        scan scratch]
   uint32_t* tickets = work;
   uint32_t* count = work + 64;
   uint32_t* base = count + total_tiles + 1;
   uint32_t* seg_tile = base + total_tiles + 1;
-  uint32_t* scan_tmp = seg_tile + max_items;
+  uint32_t* order = seg_tile + max_items;
+  uint32_t* scan_tmp = order + max_items;
   if (total_tiles <= kSegPlanOne) {
     hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(1024), 0, stream, sv.walk, total_tiles, base,
-                       seg_tile);
+                       seg_tile, order);
   } else {
+    order = nullptr;  // many more items than resident workgroups: taken in item order
     const uint32_t tb = (total_tiles + 255) / 256;
     hipLaunchKernelGGL(seg_count_kernel, dim3(tb), dim3(256), 0, stream, sv.walk, total_tiles,
                        count);
@@ -817,24 +874,29 @@ hipError_t raster_bwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
   if (flow && (!flows || !sv.ckf || !sv.flow)) return hipErrorInvalidValue;
   static const uint32_t cap_plain = resident_groups(raster_bwd_kernel<T, TS, PPT, false>, NT);
   static const uint32_t cap_flow = resident_groups(raster_bwd_kernel<T, TS, PPT, true>, NT);
-  const uint32_t cap = flow ? cap_flow : cap_plain;
+  // fewer workgroups than fit, so that the queue has items left to balance
+  static const uint32_t limit = uint32_t(compute_units()) * (kBwdWavesPerCu * 64u / NT);
+  uint32_t cap = flow ? cap_flow : cap_plain;
+  if (limit > 0 && limit < cap) cap = limit;
   const uint32_t grid = uint32_t(max_items < cap ? max_items : cap);
   if (grid == 0) return hipSuccess;
   if (flow)
     hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT, true>), dim3(grid), dim3(NT), 0, stream,
                        recs, flows, n, values, ranges, slots, n_views, st, T_final, n_contrib, sv,
-                       seg_tile, base, base + total_tiles, dL_dimage, dL_dflow, grad2d, tickets);
+                       seg_tile, base, order, base + total_tiles, dL_dimage, dL_dflow, grad2d,
+                       tickets);
   else
     hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT, false>), dim3(grid), dim3(NT), 0, stream,
                        recs, flows, n, values, ranges, slots, n_views, st, T_final, n_contrib, sv,
-                       seg_tile, base, base + total_tiles, dL_dimage, dL_dflow, grad2d, tickets);
+                       seg_tile, base, order, base + total_tiles, dL_dimage, dL_dflow, grad2d,
+                       tickets);
   return hipGetLastError();
 }
 
 }  // namespace
 
 size_t raster_bwd_work_bytes(uint32_t total_tiles, uint64_t max_items) {
-  return (2 * (size_t(total_tiles) + 1) + size_t(max_items) + 64) * 4 +
+  return (2 * (size_t(total_tiles) + 1) + 2 * size_t(max_items) + 64) * 4 +
          scan_u32_temp_bytes(total_tiles + 1);
 }
 
