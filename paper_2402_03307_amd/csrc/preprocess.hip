@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_bwd_kernel(GaussPtrs<T> g,
     bool any = false;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      g2[c] = T(g2v[c * (long)n + i]);
+      g2[c] = T(g2v[size_t(i) * NC + c]);
       any |= g2[c] != T(0);
     }
     if (!any) continue;

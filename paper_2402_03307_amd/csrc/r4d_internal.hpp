@@ -73,8 +73,8 @@ hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
                                  uint32_t* vis_keys, uint32_t* vis_index, SegTable* dseg,
                                  void* temp, bool static3d, hipStream_t stream);
 
-// grad2d: [V][C][n] double, C = 9 (mean2 x, y, Sigma_2D (0,0), (0,1), (1,1),
-// opacity_t, r, g, b) or, with flow, 11 (then flow x, y).  Writes the parameter
+// grad2d: [V][n][C] double (Gaussian-major), C = 9 (mean2 x, y, Sigma_2D (0,0),
+// (0,1), (1,1), opacity_t, r, g, b) or, with flow, 11 (then flow x, y).  Writes the parameter
 // gradients summed over the renders.
 template <typename T>
 hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
@@ -214,7 +214,7 @@ hipError_t launch_raster_fwd(const Rec<T>* recs, const Vec2<T>* flows, uint32_t 
                              uint32_t* n_contrib, uint32_t* n_eval, const RasterSaved<T>& sv,
                              uint32_t* tickets, hipStream_t stream);
 
-// Persistent launch over the (tile, segment) walks.  grad2d: [V][C][n] double
+// Persistent launch over the (tile, segment) walks.  grad2d: [V][n][C] double
 // accumulators, added to, C = 9, or 11 when dL_dflow is given (a flow render's
 // saved state with the flow images' gradient, laid out like them).  max_items:
 // bound on the number of walks (capacity / kSegment + tiles + 1); work:
@@ -300,7 +300,7 @@ hipError_t launch_entropy(const float* opacity, uint32_t n, float weight, float*
 // ---- density control
 // accum[i] += sum over the renders where Gaussian i is listed (dkeys not
 // 0xffffffff) of the NDC norm of its projected-mean gradient (grad2d
-// components 0, 1 of C = nc per render); count[i] += those renders.
+// components 0, 1 of the nc per Gaussian and render); count[i] += those renders.
 hipError_t launch_densify_stats(const double* grad2d, int nc, const uint32_t* dkeys,
                                 uint32_t n_pad, const ViewSlot* slots, int n_views, uint32_t n,
                                 float* accum, int32_t* count, hipStream_t stream);

@@ -165,15 +165,14 @@ __device__ __forceinline__ float fold16(float x, float y) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Wavefront sums of the NC per-Gaussian components, stored to s_grad[c][j]
-// (added, when several wavefronts share a tile).  Float: components are
+// Wavefront sums of the NC per-Gaussian components, stored to s_slot[c] (added,
+// when several wavefronts share a tile).  Float: components are
 // folded four at a time, fold16(fold32(a, b), fold32(c, d)), which leaves a,
 // c, b, d partial sums in rows 0..3, and the row sums finish them; a ninth
 // component alone takes the row sums and two row broadcasts (total in row 3).
 // Lane 16 r stores row r's totals.
-template <int NC, int NT, int NB>
-__device__ __forceinline__ void store_wave_sums(float (&sv)[NC], float (*s_grad)[NB], int j,
-                                                int lane) {
+template <int NC, int NT>
+__device__ __forceinline__ void store_wave_sums(float (&sv)[NC], float* s_slot, int lane) {
   static_assert(NC == 9 || NC == 11, "component groups of 4 + 1 or 4 + 3");
   float q[3];  // two groups of 4, then the rest
   q[0] = fold16(fold32(sv[0], sv[1]), fold32(sv[2], sv[3]));
@@ -191,29 +190,28 @@ __device__ __forceinline__ void store_wave_sums(float (&sv)[NC], float (*s_grad)
     const int r = lane >> 4;
     const int c = ((r & 1) << 1) | (r >> 1);  // row r holds component 4 g + c of group g
     if (NT == 64) {
-      s_grad[c][j] = q[0];
-      s_grad[4 + c][j] = q[1];
-      if (NC == 9 && r == 3) s_grad[8][j] = q[2];
-      if (NC == 11 && c < 3) s_grad[8 + c][j] = q[2];
+      s_slot[c] = q[0];
+      s_slot[4 + c] = q[1];
+      if (NC == 9 && r == 3) s_slot[8] = q[2];
+      if (NC == 11 && c < 3) s_slot[8 + c] = q[2];
     } else {
-      atomicAdd(&s_grad[c][j], q[0]);
-      atomicAdd(&s_grad[4 + c][j], q[1]);
-      if (NC == 9 && r == 3) atomicAdd(&s_grad[8][j], q[2]);
-      if (NC == 11 && c < 3) atomicAdd(&s_grad[8 + c][j], q[2]);
+      atomicAdd(&s_slot[c], q[0]);
+      atomicAdd(&s_slot[4 + c], q[1]);
+      if (NC == 9 && r == 3) atomicAdd(&s_slot[8], q[2]);
+      if (NC == 11 && c < 3) atomicAdd(&s_slot[8 + c], q[2]);
     }
   }
 }
-template <int NC, int NT, int NB>
-__device__ __forceinline__ void store_wave_sums(double (&sv)[NC], double (*s_grad)[NB], int j,
-                                                int lane) {
+template <int NC, int NT>
+__device__ __forceinline__ void store_wave_sums(double (&sv)[NC], double* s_slot, int lane) {
   wave_sums(sv);
   if (lane == 63) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (NT == 64)
-        s_grad[c][j] = sv[c];
+        s_slot[c] = sv[c];
       else
-        atomicAdd(&s_grad[c][j], sv[c]);
+        atomicAdd(&s_slot[c], sv[c]);
     }
   }
 }
@@ -376,8 +374,8 @@ template <typename T, int TS, int PPT, bool FLOW>
 struct BwdShared {
   Staged<T> rec[TileCfg<TS, PPT>::kBatch];
   uint32_t idx[TileCfg<TS, PPT>::kBatch];
-  // per component and batch slot
-  T grad[kComps<FLOW>][TileCfg<TS, PPT>::kBatch];
+  // per batch slot and component
+  T grad[TileCfg<TS, PPT>::kBatch][kComps<FLOW>];
   uint32_t max;
 };
 
@@ -389,15 +387,14 @@ __device__ __forceinline__ void raster_bwd_tile(
     const SettingsDev& st, const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const T* __restrict__ img_copy, const T* __restrict__ flow_copy,
     const Ck<T>* __restrict__ ck, const Vec2<T>* __restrict__ ckf,
-    const T* __restrict__ dL_dimage, const T* __restrict__ dL_dflow, double* __restrict__ grad2d,
-    uint32_t n_gauss) {
+    const T* __restrict__ dL_dimage, const T* __restrict__ dL_dflow, double* __restrict__ grad2d) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
   constexpr int NC = kComps<FLOW>;
   Staged<T>* s_rec = sh.rec;
   uint32_t* s_idx = sh.idx;
-  T(*s_grad)[NB] = sh.grad;
+  T(*s_grad)[NC] = sh.grad;
   uint32_t& s_max = sh.max;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int x = tx * TS + int(threadIdx.x % TS);
@@ -474,9 +471,7 @@ __device__ __forceinline__ void raster_bwd_tile(
         s_rec[threadIdx.x] = sr;
       }
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        s_grad[c][threadIdx.x] = T(0);
-      }
+      for (int c = 0; c < NC; ++c) s_grad[threadIdx.x][c] = T(0);
     }
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
@@ -537,7 +532,7 @@ __device__ __forceinline__ void raster_bwd_tile(
       // sums over the wavefront, kept in LDS (the components' scale factors
       // are applied when the batch is flushed); with several wavefronts per
       // tile the sums of all of them add up
-      store_wave_sums<NC, NT, NB>(sv, s_grad, j, lane);
+      store_wave_sums<NC, NT>(sv, s_grad[j], lane);
     }
     __syncthreads();
     // One global atomic per (tile, Gaussian, component); the sum over tiles is
@@ -547,12 +542,14 @@ __device__ __forceinline__ void raster_bwd_tile(
     // Sigma_2D = Q^-1, dL/dSigma_2D = sum g u u^T / 2; so the components are
     // d/d mean2d = -s0,1 / k, d/d Sigma_2D (0,0), (0,1) = (1,0), (1,1) =
     // s2,3,4 / (2 k^2), d/d opacity_t = s5, d/d rgb = s6,7,8 (d/d flow = s9,10).
+    // grad2d is Gaussian-major, so the lanes of one instruction cover a few
+    // Gaussians' components in a few cache lines rather than one line each.
     for (int e = threadIdx.x; e < NC * nb; e += NT) {
-      const int c = e / nb, j = e % nb;
+      const int j = e / NC, c = e % NC;
       const T scale = c < 2 ? T(-1.0 / kHalfLog2e)
                             : (c < 5 ? T(0.5 / (kHalfLog2e * kHalfLog2e)) : T(1));
-      const T val = s_grad[c][j] * scale;
-      if (val != T(0)) atomic_add_nr(&grad2d[long(c) * n_gauss + s_idx[j]], double(val));
+      const T val = s_grad[j][c] * scale;
+      if (val != T(0)) atomic_add_nr(&grad2d[size_t(s_idx[j]) * NC + c], double(val));
     }
     __syncthreads();
     bend = bstart;
@@ -636,7 +633,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
         sh, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr, values, ranges[g],
         int(g - sl.tile_base), g, seg, sv.walk[g], v, st, T_final + pb, n_contrib + pb,
         sv.img + 3 * pb, FLOW ? sv.flow + 2 * pb : nullptr, sv.ck, sv.ckf, dL_dimage + 3 * pb,
-        FLOW ? dL_dflow + 2 * pb : nullptr, grad2d + size_t(vi) * kComps<FLOW> * n, n);
+        FLOW ? dL_dflow + 2 * pb : nullptr, grad2d + size_t(vi) * kComps<FLOW> * n);
     if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
     __syncthreads();
     it = s_ticket;

@@ -219,8 +219,8 @@ __global__ __launch_bounds__(kBlock) void densify_stats_kernel(
   for (int v = 0; v < n_views; ++v) {
     if (dkeys[size_t(v) * n_pad + i] == 0xffffffffu) continue;
     const double* g = grad2d + size_t(v) * size_t(nc) * n;
-    const double gx = g[i] * (0.5 * double(slots[v].v.W));
-    const double gy = g[size_t(n) + i] * (0.5 * double(slots[v].v.H));
+    const double gx = g[size_t(i) * nc] * (0.5 * double(slots[v].v.W));
+    const double gy = g[size_t(i) * nc + 1] * (0.5 * double(slots[v].v.H));
     a += sqrt(gx * gx + gy * gy);
     c += 1;
   }
