@@ -750,7 +750,7 @@ int compute_units() {
 }
 
 // Wavefronts per compute unit of the backward's persistent launch.
-constexpr uint32_t kBwdWavesPerCu = 16;
+constexpr uint32_t kBwdWavesPerCu = 24;
 
 // Workgroups resident on the whole chip at once (occupancy x compute units);
 // a persistent launch needs no more.
