@@ -708,7 +708,14 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restri
       const uint32_t b = carry + before + incl - cnt;
       base[t] = b;
       for (uint32_t i = 0; i < cnt; ++i) seg_tile[b + i] = t;
-      if (cnt > 0) atomicAdd(&s_next[1 + len_bucket(walk[t] - (cnt - 1) * kSegment)], 1u);
+    }
+    // last segments per length class: one LDS atomic per wavefront and class
+    const uint32_t cls =
+        cnt > 0 ? len_bucket(walk[t] - (cnt - 1) * kSegment) : kLenBuckets;  // none
+#pragma unroll
+    for (uint32_t k = 0; k < kLenBuckets; ++k) {
+      const unsigned long long m = __ballot(cls == k);
+      if (m != 0ull && lane == 0) atomicAdd(&s_next[1 + k], uint32_t(__popcll(m)));
     }
     carry += chunk;
   }
@@ -727,15 +734,38 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restri
     }
   }
   __syncthreads();
-  // each thread revisits its own tiles (base[t] is its own earlier write)
-  for (uint32_t t = threadIdx.x; t < total_tiles; t += 1024) {
-    const uint32_t cnt = (walk[t] + kSegment - 1) / kSegment;
-    if (cnt == 0) continue;
-    const uint32_t b = base[t];
-    const uint32_t f = atomicAdd(&s_next[0], cnt - 1);
-    for (uint32_t i = 0; i + 1 < cnt; ++i) order[f + i] = b + i;
-    const uint32_t q = atomicAdd(&s_next[1 + len_bucket(walk[t] - (cnt - 1) * kSegment)], 1u);
-    order[q] = b + cnt - 1;
+  // each thread revisits its own tiles (base[t] is its own earlier write); a
+  // wavefront places its full segments with a scan and one atomic, and its last
+  // segments of each class with a ballot rank and one atomic
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (uint32_t c0 = 0; c0 < total_tiles; c0 += 1024) {
+    const uint32_t t = c0 + threadIdx.x;
+    const uint32_t w = t < total_tiles ? walk[t] : 0u;
+    const uint32_t cnt = (w + kSegment - 1) / kSegment;
+    const uint32_t f = cnt > 0 ? cnt - 1 : 0u;
+    const uint32_t b = t < total_tiles ? base[t] : 0u;
+    uint32_t incl = f;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    uint32_t wfull = 0;
+    if (lane == 63 && incl != 0u) wfull = atomicAdd(&s_next[0], incl);
+    wfull = __shfl(wfull, 63, 64);
+    const uint32_t fpos = wfull + incl - f;
+    for (uint32_t i = 0; i < f; ++i) order[fpos + i] = b + i;
+    const uint32_t cls = cnt > 0 ? len_bucket(w - (cnt - 1) * kSegment) : kLenBuckets;
+#pragma unroll
+    for (uint32_t k = 0; k < kLenBuckets; ++k) {
+      const unsigned long long m = __ballot(cls == k);
+      if (m == 0ull) continue;
+      const int leader = __ffsll(static_cast<long long>(m)) - 1;
+      uint32_t cb = 0;
+      if (lane == leader) cb = atomicAdd(&s_next[1 + k], uint32_t(__popcll(m)));
+      cb = __shfl(cb, leader, 64);
+      if (cls == k) order[cb + uint32_t(__popcll(m & lt))] = b + cnt - 1;
+    }
   }
 }
 
