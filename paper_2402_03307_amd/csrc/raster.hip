@@ -662,13 +662,14 @@ __global__ __launch_bounds__(256) void seg_map_kernel(const uint32_t* __restrict
 
 // The three steps above in one workgroup, for runs of at most kSegPlanOne tiles
 // (a dependent launch costs several microseconds, more than this scan): the
-// tiles are taken 1024 at a time, each chunk scanned across the workgroup and
-// offset by the total of the chunks before it.  The same workgroup then writes
+// tiles are taken 4096 at a time, four consecutive ones per thread, each chunk
+// scanned across the workgroup and offset by the total of the chunks before it.  The same workgroup then writes
 // the order in which the items are taken: every segment but a tile's last is
 // full (kSegment entries) and goes first; the last segments follow in
 // kLenBuckets classes of decreasing length (within a class, in any order).
 constexpr uint32_t kSegPlanOne = 16384;
 constexpr uint32_t kLenBuckets = 8;
+constexpr uint32_t kPlanTilesPerThread = 4;  // fewer dependent chunk steps
 
 __device__ __forceinline__ uint32_t len_bucket(uint32_t len) {
   const uint32_t b = (kSegment - len) * kLenBuckets / kSegment;
@@ -680,16 +681,27 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restri
                                                         uint32_t* __restrict__ base,
                                                         uint32_t* __restrict__ seg_tile,
                                                         uint32_t* __restrict__ order) {
+  constexpr uint32_t Q = kPlanTilesPerThread, CH = 1024u * Q;
   __shared__ uint32_t s_wave[16];
   __shared__ uint32_t s_next[kLenBuckets + 1];  // [0]: full segments, [1 + b]: class b
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
   if (threadIdx.x <= kLenBuckets) s_next[threadIdx.x] = 0u;
   __syncthreads();
+  // pass 1: segment counts and first items (thread: Q consecutive tiles of a
+  // chunk of CH), seg_tile, and the last segments per length class
   uint32_t carry = 0;
-  for (uint32_t c0 = 0; c0 < total_tiles; c0 += 1024) {
-    const uint32_t t = c0 + threadIdx.x;
-    const uint32_t cnt = t < total_tiles ? (walk[t] + kSegment - 1) / kSegment : 0u;
-    uint32_t incl = cnt;
+  for (uint32_t c0 = 0; c0 < total_tiles; c0 += CH) {
+    const uint32_t t0 = c0 + threadIdx.x * Q;
+    uint32_t cnt[Q], cls[Q], tsum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < Q; ++q) {
+      const uint32_t w = t0 + q < total_tiles ? walk[t0 + q] : 0u;
+      cnt[q] = (w + kSegment - 1) / kSegment;
+      cls[q] = cnt[q] > 0 ? len_bucket(w - (cnt[q] - 1) * kSegment) : kLenBuckets;  // none
+      tsum += cnt[q];
+    }
+    uint32_t incl = tsum;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(incl, off, 64);
@@ -704,18 +716,20 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restri
       chunk += s_wave[w];
     }
     __syncthreads();
-    if (t < total_tiles) {
-      const uint32_t b = carry + before + incl - cnt;
-      base[t] = b;
-      for (uint32_t i = 0; i < cnt; ++i) seg_tile[b + i] = t;
-    }
-    // last segments per length class: one LDS atomic per wavefront and class
-    const uint32_t cls =
-        cnt > 0 ? len_bucket(walk[t] - (cnt - 1) * kSegment) : kLenBuckets;  // none
+    uint32_t run = carry + before + incl - tsum;
 #pragma unroll
-    for (uint32_t k = 0; k < kLenBuckets; ++k) {
-      const unsigned long long m = __ballot(cls == k);
-      if (m != 0ull && lane == 0) atomicAdd(&s_next[1 + k], uint32_t(__popcll(m)));
+    for (uint32_t q = 0; q < Q; ++q) {
+      if (t0 + q < total_tiles) {
+        base[t0 + q] = run;
+        for (uint32_t i = 0; i < cnt[q]; ++i) seg_tile[run + i] = t0 + q;
+      }
+      run += cnt[q];
+      // one LDS atomic per wavefront and class
+#pragma unroll
+      for (uint32_t k = 0; k < kLenBuckets; ++k) {
+        const unsigned long long m = __ballot(cls[q] == k);
+        if (m != 0ull && lane == 0) atomicAdd(&s_next[1 + k], uint32_t(__popcll(m)));
+      }
     }
     carry += chunk;
   }
@@ -734,17 +748,22 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restri
     }
   }
   __syncthreads();
-  // each thread revisits its own tiles (base[t] is its own earlier write); a
-  // wavefront places its full segments with a scan and one atomic, and its last
-  // segments of each class with a ballot rank and one atomic
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  for (uint32_t c0 = 0; c0 < total_tiles; c0 += 1024) {
-    const uint32_t t = c0 + threadIdx.x;
-    const uint32_t w = t < total_tiles ? walk[t] : 0u;
-    const uint32_t cnt = (w + kSegment - 1) / kSegment;
-    const uint32_t f = cnt > 0 ? cnt - 1 : 0u;
-    const uint32_t b = t < total_tiles ? base[t] : 0u;
-    uint32_t incl = f;
+  // pass 2: each thread revisits its own tiles (base[t] is its own earlier
+  // write); a wavefront places its full segments with a scan and one atomic,
+  // and its last segments of each class with a ballot rank and one atomic
+  for (uint32_t c0 = 0; c0 < total_tiles; c0 += CH) {
+    const uint32_t t0 = c0 + threadIdx.x * Q;
+    uint32_t cnt[Q], cls[Q], b[Q], fsum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < Q; ++q) {
+      const bool in = t0 + q < total_tiles;
+      const uint32_t w = in ? walk[t0 + q] : 0u;
+      b[q] = in ? base[t0 + q] : 0u;
+      cnt[q] = (w + kSegment - 1) / kSegment;
+      cls[q] = cnt[q] > 0 ? len_bucket(w - (cnt[q] - 1) * kSegment) : kLenBuckets;
+      fsum += cnt[q] > 0 ? cnt[q] - 1 : 0u;
+    }
+    uint32_t incl = fsum;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(incl, off, 64);
@@ -753,18 +772,22 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restri
     uint32_t wfull = 0;
     if (lane == 63 && incl != 0u) wfull = atomicAdd(&s_next[0], incl);
     wfull = __shfl(wfull, 63, 64);
-    const uint32_t fpos = wfull + incl - f;
-    for (uint32_t i = 0; i < f; ++i) order[fpos + i] = b + i;
-    const uint32_t cls = cnt > 0 ? len_bucket(w - (cnt - 1) * kSegment) : kLenBuckets;
+    uint32_t fpos = wfull + incl - fsum;
 #pragma unroll
-    for (uint32_t k = 0; k < kLenBuckets; ++k) {
-      const unsigned long long m = __ballot(cls == k);
-      if (m == 0ull) continue;
-      const int leader = __ffsll(static_cast<long long>(m)) - 1;
-      uint32_t cb = 0;
-      if (lane == leader) cb = atomicAdd(&s_next[1 + k], uint32_t(__popcll(m)));
-      cb = __shfl(cb, leader, 64);
-      if (cls == k) order[cb + uint32_t(__popcll(m & lt))] = b + cnt - 1;
+    for (uint32_t q = 0; q < Q; ++q) {
+      const uint32_t f = cnt[q] > 0 ? cnt[q] - 1 : 0u;
+      for (uint32_t i = 0; i < f; ++i) order[fpos + i] = b[q] + i;
+      fpos += f;
+#pragma unroll
+      for (uint32_t k = 0; k < kLenBuckets; ++k) {
+        const unsigned long long m = __ballot(cls[q] == k);
+        if (m == 0ull) continue;
+        const int leader = __ffsll(static_cast<long long>(m)) - 1;
+        uint32_t cb = 0;
+        if (lane == leader) cb = atomicAdd(&s_next[1 + k], uint32_t(__popcll(m)));
+        cb = __shfl(cb, leader, 64);
+        if (cls[q] == k) order[cb + uint32_t(__popcll(m & lt))] = b[q] + cnt[q] - 1;
+      }
     }
   }
 }
