@@ -132,7 +132,11 @@ typedef struct {
  *                      have a fixed capacity (1.25x the entry count of the call
  *                      that captured the graph, doubled after an overflow); a
  *                      replay that overflows renders the background only and is
- *                      reported by r4d_saved_check.  The saved state of a graph
+ *                      reported by the backward of its saved state (or
+ *                      r4d_saved_check); one without saved state, by the
+ *                      context's next render call (or r4d_check_pending).  The
+ *                      next forward of that shape grows the capacity and
+ *                      captures again.  The saved state of a graph
  *                      forward refers to the graph's buffers: it is valid until the
  *                      next forward of the same shape (backward returns
  *                      R4D_ERR_STATE after that).  The backward is captured too.
@@ -192,8 +196,13 @@ void r4d_destroy(r4d_ctx *ctx);
  * Errors: R4D_ERR_INVALID_ARG (null pointers, n < 0, bad degree, bad view size,
  * unsupported tile size / pixels per lane / mode), R4D_ERR_CAPACITY (a view
  * with 2^30 or more tile entries, or a call with 2^32 or more), R4D_ERR_OOM,
- * R4D_ERR_HIP (also: an earlier call's sort found a predecessor that never
- * published, which cannot happen unless the device misbehaves). */
+ * R4D_ERR_HIP.  A forward's own overflow or sort failure is found on the
+ * device after the call returns; it is reported by the backward of its saved
+ * state, by r4d_saved_check, or -- for a call without saved state, or a saved
+ * state released unchecked -- by the context's next forward or backward call
+ * (which then does nothing else and returns R4D_ERR_CAPACITY for an
+ * overflow, R4D_ERR_HIP for a sort whose predecessor never published) or by
+ * r4d_check_pending. */
 r4d_status r4d_render_forward(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
                               int n_views, const r4d_settings *settings, float *images,
                               r4d_saved **saved, void *stream);
@@ -205,7 +214,13 @@ r4d_status r4d_render_forward(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_vi
  *               summed over the views; overwritten (not accumulated).
  * Gradients through the alpha clamp, the rgb clamp at 0 and every cull or skip
  * are zero.  Per-Gaussian screen-space sums are accumulated with atomics, so
- * the last bits can vary from run to run. */
+ * the last bits can vary from run to run.
+ * After enqueueing its kernels the call waits for the forward to finish on the
+ * device (the backward is queued behind it, so the device stays busy) and
+ * returns R4D_ERR_CAPACITY if the forward's tile lists overflowed (graph mode)
+ * or R4D_ERR_HIP if its sort failed: the gradients in `out` are then invalid.
+ * It also returns an unreported failure of an earlier forward of the context
+ * (see r4d_render_forward), before enqueueing anything. */
 r4d_status r4d_render_backward(r4d_ctx *ctx, const r4d_gaussians *g, const r4d_view *views,
                                int n_views, const r4d_settings *settings,
                                const r4d_saved *saved, const float *dL_dimages, r4d_grads *out,
@@ -490,7 +505,8 @@ r4d_status r4d_render_backward_3d_f64(r4d_ctx *ctx, const r4d_gaussians3d_f64 *g
 
 /* Returns the saved arena to its context's cache.  NULL is ignored.  A saved
  * handle may outlive its context: r4d_destroy frees its device memory and a
- * later release only frees the handle. */
+ * later release only frees the handle.  If neither a backward nor
+ * r4d_saved_check read the forward's status, the context's next call does. */
 void r4d_saved_release(r4d_saved *saved);
 
 /* Gradient of the mean absolute error L = sum |image - target| / count
@@ -513,9 +529,17 @@ r4d_status r4d_l1_loss_grad_views(r4d_ctx *ctx, const float *images, const float
 /* Waits until the forward call that produced `saved` has finished on the
  * device and reports what it could not report when it returned:
  * R4D_ERR_CAPACITY if its tile lists overflowed (graph mode), R4D_ERR_HIP if
- * its sort timed out waiting for a predecessor, R4D_ERR_STATE if a later
- * forward of the same graph shape has reused its buffers, R4D_OK otherwise. */
+ * its sort timed out waiting for a predecessor, R4D_OK otherwise.  Each graph
+ * replay keeps its own status words, so this also answers for a saved state
+ * whose buffers a later forward has reused. */
 r4d_status r4d_saved_check(const r4d_saved *saved);
+
+/* Waits for every forward of the context whose status nobody has read yet
+ * (calls without saved state, saved states released unchecked) and reports
+ * the first overflow (R4D_ERR_CAPACITY) or sort failure (R4D_ERR_HIP) among
+ * them; R4D_OK if none.  Each such forward is reported once, here or by the
+ * context's next forward or backward call. */
+r4d_status r4d_check_pending(r4d_ctx *ctx);
 
 /* The tile size, tile-sort keys per lane and mode the forward call used (the
  * autotuner's choice when tile_size was 0).  Any pointer may be NULL. */

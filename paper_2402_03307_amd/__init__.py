@@ -51,7 +51,8 @@ EXPORTED_SYMBOLS = (
     "r4d_default_densify_config", "r4d_densify", "r4d_render_forward_3d",
     "r4d_render_backward_3d", "r4d_render_forward_3d_f64", "r4d_render_backward_3d_f64",
     "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
-    "r4d_saved_copy", "r4d_saved_check", "r4d_saved_config", "r4d_status_string",
+    "r4d_saved_copy", "r4d_saved_check", "r4d_check_pending", "r4d_saved_config",
+    "r4d_status_string",
     "r4d_last_error", "r4d_set_timing", "r4d_get_timings", "r4d_stage_name",
 )
 NUM_STAGES = 9
@@ -176,6 +177,8 @@ def _load():
     lib.r4d_l1_loss_grad_views.restype = ctypes.c_int
     lib.r4d_saved_check.argtypes = [c_vp]
     lib.r4d_saved_check.restype = ctypes.c_int
+    lib.r4d_check_pending.argtypes = [c_vp]
+    lib.r4d_check_pending.restype = ctypes.c_int
     lib.r4d_saved_config.argtypes = [c_vp, P(c_i32), P(c_i32), P(c_i32)]
     lib.r4d_saved_config.restype = ctypes.c_int
     lib.r4d_saved_stats.argtypes = [c_vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_int64),
@@ -399,6 +402,12 @@ class Renderer:
             self.close()
         except Exception:
             pass
+
+    def check_pending(self):
+        """Waits for the forwards whose status nobody has read (calls with
+        save=False, saved states released unchecked) and raises if one of them
+        overflowed its tile lists or failed to sort (r4d_check_pending)."""
+        self._check(_lib.r4d_check_pending(self.handle), "r4d_check_pending")
 
     def _check(self, status: int, what: str):
         if status != 0:

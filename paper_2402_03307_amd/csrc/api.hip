@@ -104,9 +104,13 @@ struct r4d_ctx {
   struct Pinned {
     unsigned long long* host = nullptr;
     hipEvent_t done = nullptr;
-    bool busy = false;
+    int refs = 0;  // holders: a run, a graph's latest replay, a saved state, `unchecked`
   };
   std::vector<Pinned*> pinned_pool;
+  // readback areas of forwards whose status words nobody has read yet (calls
+  // without saved state, saved states released unchecked); read, without
+  // waiting, by the next render call, which reports an overflow or sort failure
+  std::vector<Pinned*> unchecked;
 };
 
 namespace {
@@ -151,6 +155,8 @@ struct r4d_saved {
   bool static3d = false;        // static 3D Gaussians
   int n = 0, deg = 0;
   r4d_settings settings;        // as resolved (tile size chosen)
+  r4d_ctx::Pinned* graph_slot = nullptr;  // graph mode: the replay's readback area
+  mutable bool checked = false; // status words read (backward or r4d_saved_check)
   std::vector<r4d_view> views;
   std::vector<std::unique_ptr<RunState>> runs;  // owned runs (per-view, fused)
   GraphEntry* graph = nullptr;  // graph mode
@@ -210,14 +216,25 @@ void ctx_free(r4d_ctx* ctx, void* p) {
   if (it != ctx->block_size.end()) ctx->free_blocks.insert({it->second, p});
 }
 
-void release_run(r4d_ctx* ctx, RunState* r) {
+void unref_slot(r4d_ctx::Pinned* q) {
+  if (q && q->refs > 0) q->refs -= 1;  // reused once unheld and its event has completed
+}
+
+// unchecked: the run's status words have not been read; its readback area
+// moves to the context's unchecked list instead of being freed.
+void release_run(r4d_ctx* ctx, RunState* r, bool unchecked = false) {
   if (!r) return;
   if (r->owns_memory) {
     ctx_free(ctx, r->fixed);
     ctx_free(ctx, r->entries);
   }
   r->fixed = r->entries = nullptr;
-  if (r->slot) r->slot->busy = false;  // reused once its event has completed
+  if (r->slot) {
+    if (unchecked)
+      ctx->unchecked.push_back(r->slot);
+    else
+      unref_slot(r->slot);
+  }
   r->slot = nullptr;
   r->pinned = nullptr;
   r->done = nullptr;
@@ -685,11 +702,12 @@ r4d_status wait_run(r4d_ctx* ctx, RunState& r) {
   return R4D_OK;
 }
 
-r4d_status init_run(r4d_ctx* ctx, RunState& r, const Plan& p) {
-  r.plan = p;
+// A readback area nobody holds whose last copy has completed (or a new one),
+// returned with one reference.
+r4d_status acquire_slot(r4d_ctx* ctx, r4d_ctx::Pinned** out) {
   r4d_ctx::Pinned* slot = nullptr;
   for (r4d_ctx::Pinned* q : ctx->pinned_pool) {
-    if (q->busy) continue;
+    if (q->refs) continue;
     const hipError_t e = hipEventQuery(q->done);
     if (e == hipSuccess) {
       slot = q;
@@ -709,11 +727,57 @@ r4d_status init_run(r4d_ctx* ctx, RunState& r, const Plan& p) {
     slot = q.release();
     ctx->pinned_pool.push_back(slot);
   }
-  slot->busy = true;
+  slot->refs = 1;
+  *out = slot;
+  return R4D_OK;
+}
+
+void attach_slot(RunState& r, r4d_ctx::Pinned* slot) {
   r.slot = slot;
   r.pinned = slot->host;
   r.done = slot->done;
+}
+
+r4d_status init_run(r4d_ctx* ctx, RunState& r, const Plan& p) {
+  r.plan = p;
+  r4d_ctx::Pinned* slot = nullptr;
+  r4d_status s = acquire_slot(ctx, &slot);
+  if (s != R4D_OK) return s;
+  attach_slot(r, slot);
   return R4D_OK;
+}
+
+// Status of a forward from its status words: (overflow, look-back error).
+r4d_status flags_status(r4d_ctx* ctx, const unsigned long long* pinned, const char* what) {
+  const uint32_t* fl = reinterpret_cast<const uint32_t*>(pinned);
+  if (fl[1]) return fail(ctx, R4D_ERR_HIP, "%ssort look-back did not complete", what);
+  if (fl[0]) return fail(ctx, R4D_ERR_CAPACITY, "%stile lists overflowed the capacity", what);
+  return R4D_OK;
+}
+
+// Reads the status words of unchecked forwards that have completed (all of
+// them with wait = true) and reports the first failure among them.
+r4d_status drain_unchecked(r4d_ctx* ctx, bool wait) {
+  r4d_status result = R4D_OK;
+  std::vector<r4d_ctx::Pinned*> keep;
+  for (r4d_ctx::Pinned* q : ctx->unchecked) {
+    const hipError_t e = wait ? hipEventSynchronize(q->done) : hipEventQuery(q->done);
+    if (e == hipErrorNotReady) {
+      (void)hipGetLastError();
+      keep.push_back(q);
+      continue;
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      if (result == R4D_OK)
+        result = fail(ctx, R4D_ERR_HIP, "waiting for an earlier forward: %s", hipGetErrorString(e));
+    } else if (result == R4D_OK) {
+      result = flags_status(ctx, q->host, "an earlier forward whose state was not checked: ");
+    }
+    unref_slot(q);
+  }
+  ctx->unchecked.swap(keep);
+  return result;
 }
 
 // Screen-space gradient components per Gaussian and render.
@@ -900,6 +964,12 @@ r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
   e->run.plan = p;  // camera and time of this call (uploaded below)
   r4d_status s3 = upload_meta(ctx, p, e->run.fixed, e->run.L, stream);
   if (s3 != R4D_OK) return s3;
+  // each replay reports into a readback area of its own, so that the status
+  // words of an earlier replay survive until whoever holds them reads them
+  r4d_ctx::Pinned* slot = nullptr;
+  if ((s3 = acquire_slot(ctx, &slot)) != R4D_OK) return s3;
+  unref_slot(e->run.slot);
+  attach_slot(e->run, slot);
   R4D_HIP(hipGraphLaunch(e->fwd, stream));
   e->generation += 1;
   if ((s3 = finish_run(ctx, e->run, stream)) != R4D_OK) return s3;
@@ -1013,6 +1083,7 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
     return fail(ctx, R4D_ERR_CAPACITY, "%d views of %d Gaussians exceed 2^32 sort slots", n_views,
                 g.n);
   R4D_HIP(hipSetDevice(ctx->device));
+  if ((s = drain_unchecked(ctx, false)) != R4D_OK) return s;
   r4d_settings rs = *settings;
   if (rs.tile_size == 0) {
     int ts = 16, items = 16;
@@ -1041,6 +1112,8 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
       return s;
     saved->graph = e;
     saved->generation = e->generation;
+    saved->graph_slot = e->run.slot;
+    saved->graph_slot->refs += 1;
     for (int v = 0; v < n_views; ++v) saved->where.push_back({0, v});
   } else if (rs.mode == R4D_MODE_FUSED) {
     Plan p = make_plan(views, n_views, uint32_t(g.n), g.deg, rs, sizeof(T), flow, static3d);
@@ -1074,9 +1147,32 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
     *saved_out = raw;
   } else {
     // inference: the run buffers return to the cache (stream order keeps the
-    // queued kernels safe)
-    for (auto& rr : saved->runs) release_run(ctx, rr.get());
+    // queued kernels safe); the status words are read by a later call
+    for (auto& rr : saved->runs) release_run(ctx, rr.get(), true);
+    if (saved->graph_slot) ctx->unchecked.push_back(saved->graph_slot);
+    saved->graph_slot = nullptr;
   }
+  return R4D_OK;
+}
+
+// Waits for the forward of a saved state and reports its overflow or sort
+// failure.
+r4d_status check_saved(r4d_ctx* ctx, const r4d_saved* saved) {
+  if (saved->graph) {
+    if (!saved->graph_slot) return fail(ctx, R4D_ERR_STATE, "saved state without readback");
+    R4D_HIP(hipEventSynchronize(saved->graph_slot->done));
+    saved->checked = true;
+    return flags_status(ctx, saved->graph_slot->host, "");
+  }
+  for (const auto& r : saved->runs) {
+    r4d_status s = wait_run(ctx, *r);
+    if (s != R4D_OK) return s;
+    if ((s = flags_status(ctx, r->pinned, "")) != R4D_OK) {
+      saved->checked = true;
+      return s;
+    }
+  }
+  saved->checked = true;
   return R4D_OK;
 }
 
@@ -1088,10 +1184,10 @@ bool same_view(const r4d_view& a, const r4d_view& b) {
 
 // dLf: the flow images' gradient (null: none; needs a flow render otherwise).
 template <typename T>
-r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
-                         int n_views, const r4d_settings* settings, const r4d_saved* saved,
-                         const T* dL, const T* dLf, const GradPtrs<T>& out, hipStream_t stream,
-                         StatsOut stats = StatsOut{}, bool static3d = false) {
+r4d_status backward_enqueue(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
+                            int n_views, const r4d_settings* settings, const r4d_saved* saved,
+                            const T* dL, const T* dLf, const GradPtrs<T>& out, hipStream_t stream,
+                            StatsOut stats, bool static3d) {
   if (!views || n_views < 1 || !dL || !valid_settings(settings) || !saved)
     return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, gradients, settings or saved state");
   r4d_status s = check_gaussians(ctx, g);
@@ -1113,6 +1209,7 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   if (saved->static3d != static3d)
     return fail(ctx, R4D_ERR_STATE, "static and 4D Gaussian calls do not mix");
   R4D_HIP(hipSetDevice(ctx->device));
+  if ((s = drain_unchecked(ctx, false)) != R4D_OK) return s;
   if (g.n == 0) return R4D_OK;
   const SettingsDev st = make_settings(saved->settings);
   const bool timed = ctx->timing && !saved->graph;
@@ -1190,6 +1287,21 @@ r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vi
   }
   ctx_free(ctx, tmp);
   return s;
+}
+
+// The backward is enqueued first, then the forward's status words are read
+// (the forward precedes the backward on the stream, so the device stays busy
+// while the host waits): gradients of a forward whose tile lists overflowed or
+// whose sort failed are reported as an error, not returned as zeros.
+template <typename T>
+r4d_status backward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
+                         int n_views, const r4d_settings* settings, const r4d_saved* saved,
+                         const T* dL, const T* dLf, const GradPtrs<T>& out, hipStream_t stream,
+                         StatsOut stats = StatsOut{}, bool static3d = false) {
+  r4d_status s = backward_enqueue<T>(ctx, g, views, n_views, settings, saved, dL, dLf, out, stream,
+                                     stats, static3d);
+  if (s != R4D_OK) return s;
+  return check_saved(ctx, saved);
 }
 
 template <typename T>
@@ -1283,6 +1395,7 @@ void r4d_destroy(r4d_ctx* ctx) {
     }
     sv->runs.clear();
     sv->graph = nullptr;
+    sv->graph_slot = nullptr;
     sv->ctx = nullptr;
   }
   ctx->live_saved.clear();
@@ -1310,6 +1423,7 @@ void r4d_destroy(r4d_ctx* ctx) {
     delete q;
   }
   ctx->pinned_pool.clear();
+  ctx->unchecked.clear();
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->readback) (void)hipHostFree(ctx->readback);
   if (ctx->l1_partials) (void)hipFree(ctx->l1_partials);
@@ -1676,7 +1790,16 @@ r4d_status r4d_render_backward_3d_f64(r4d_ctx* ctx, const r4d_gaussians3d_f64* g
 void r4d_saved_release(r4d_saved* saved) {
   if (!saved) return;
   if (saved->ctx) {  // null once the context has been destroyed
-    for (auto& r : saved->runs) release_run(saved->ctx, r.get());
+    // status words nobody has read are reported by the context's next call
+    const bool unchecked = !saved->checked;
+    for (auto& r : saved->runs) release_run(saved->ctx, r.get(), unchecked);
+    if (saved->graph_slot) {
+      if (unchecked)
+        saved->ctx->unchecked.push_back(saved->graph_slot);
+      else
+        unref_slot(saved->graph_slot);
+    }
+    saved->graph_slot = nullptr;
     saved->ctx->live_saved.erase(saved);
   }
   delete saved;
@@ -1718,16 +1841,14 @@ r4d_status r4d_l1_loss_grad_views(r4d_ctx* ctx, const float* images, const float
 r4d_status r4d_saved_check(const r4d_saved* saved) {
   if (!saved || !saved->ctx) return R4D_ERR_INVALID_ARG;
   r4d_ctx* ctx = saved->ctx;
-  if (saved->graph && saved->generation != saved->graph->generation) return R4D_ERR_STATE;
-  const size_t nr = saved->graph ? 1 : saved->runs.size();
-  for (size_t i = 0; i < nr; ++i) {
-    RunState* r = saved->run_of(int(i));
-    r4d_status s = wait_run(ctx, *r);
-    if (s != R4D_OK) return s;
-    if (r->flags[1]) return fail(ctx, R4D_ERR_HIP, "sort look-back did not complete");
-    if (r->flags[0]) return fail(ctx, R4D_ERR_CAPACITY, "tile lists overflowed the capacity");
-  }
-  return R4D_OK;
+  R4D_HIP(hipSetDevice(ctx->device));
+  return check_saved(ctx, saved);
+}
+
+r4d_status r4d_check_pending(r4d_ctx* ctx) {
+  if (!ctx) return R4D_ERR_INVALID_ARG;
+  R4D_HIP(hipSetDevice(ctx->device));
+  return drain_unchecked(ctx, true);
 }
 
 r4d_status r4d_saved_config(const r4d_saved* saved, int32_t* tile_size, int32_t* sort_items,

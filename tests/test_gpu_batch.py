@@ -13,7 +13,7 @@ import torch
 import workloads as W
 from oracle import render as O
 
-from helpers import image_errors, tile_lists, to_device
+from helpers import PARAM_KEYS, image_errors, tile_lists, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -100,10 +100,10 @@ def test_graph_replays_follow_new_cameras(r4d, device):
         assert torch.equal(a, b)
     for a, b in zip(imgs_b, ref_b):
         assert torch.equal(a, b)
-    # the first saved state refers to buffers the second forward reused
-    with pytest.raises(r4d.R4DError):
-        saved_a.check()
-    with pytest.raises(r4d.R4DError):
+    # the first saved state refers to buffers the second forward reused: its
+    # backward is refused; its own status words are still readable
+    saved_a.check()
+    with pytest.raises(r4d.R4DError, match="STATE"):
         rend.backward(p, views_a, gst, saved_a, [torch.zeros_like(i) for i in imgs_a])
     saved_b.check()
 
@@ -139,6 +139,52 @@ def test_graph_capacity_overflow_is_reported_then_grown(r4d, device):
             continue
     s2.check()
     assert torch.equal(imgs[0], ref[0])
+
+
+def test_overflow_is_reported_by_backward_and_by_the_next_call(r4d, device):
+    """A graph replay that overflows its capacity must not hand back zero
+    gradients: the backward of its saved state (here through the autograd
+    Function) raises; a replay without saved state is reported by
+    check_pending, or by the context's next call."""
+    g, _, st = W.scene_2k()
+    far = [W.view((0.0, 0.0, -12.0), 320, 320, 300.0, 0.5)]
+    near = [W.view((0.0, 0.0, -2.2), 320, 320, 300.0, 0.5)]
+    rend = r4d.Renderer(device)
+    gst = dict(st, mode="graph")
+    p = to_device(g, device)
+    _, s_far = rend.forward(p, far, gst)
+    s_far.check()
+    s_far.release()
+    for k in PARAM_KEYS:
+        p[k].requires_grad_(True)
+    print("case: overflowed replay through render() + backward", flush=True)
+    imgs = r4d.render(p, near, gst, renderer=rend)
+    with pytest.raises(r4d.R4DError, match="CAPACITY"):
+        imgs[0].sum().backward()
+    # the next forward grows the capacity; the result is right again
+    ref, _ = rend.forward(p, near, st, save=False)
+    ref = [i.clone() for i in ref]
+    imgs = r4d.render(p, near, gst, renderer=rend)
+    imgs[0].sum().backward()
+    assert torch.equal(imgs[0].detach(), ref[0])
+
+    print("case: overflowed replay without saved state", flush=True)
+    q = to_device(g, device)          # other pointers: a graph of its own
+    rend.forward(q, far, gst, save=False)
+    rend.check_pending()
+    rend.forward(q, near, gst, save=False)
+    with pytest.raises(r4d.R4DError, match="CAPACITY"):
+        rend.check_pending()
+    rend.check_pending()              # reported once
+    q2 = to_device(g, device)
+    rend.forward(q2, far, gst, save=False)
+    rend.check_pending()
+    rend.forward(q2, near, gst, save=False)
+    torch.cuda.synchronize()
+    with pytest.raises(r4d.R4DError, match="CAPACITY"):
+        rend.forward(q2, far, st, save=False)
+    rend.forward(q2, far, st, save=False)
+    rend.check_pending()
 
 
 def test_autotuner_choice_is_valid_and_image_unchanged(r4d, device):
