@@ -76,12 +76,19 @@ def rotor_normalize(r: torch.Tensor) -> torch.Tensor:
 
     delta solves eps(r + delta grad eps) = eps (1 + delta^2) + l^2 delta = 0 with
     the root that tends to 0; written in the rationalised form.  A rotor whose
-    squared norm is below 1e-12 before or after the update maps to the identity.
+    squared norm is below 1e-12 before or after the update maps to the identity,
+    with zero gradient.  (The updated norm is |r + delta grad eps|^2 =
+    (l^4 - 4 eps^2) / l^2, so a zero discriminant always takes that branch.)
     """
     eps = rotor_epsilon(r)
     l2 = (r * r).sum(-1)
     disc = torch.clamp(l2 * l2 - 4.0 * eps * eps, min=0.0)
-    denom = l2 + torch.sqrt(disc)
+    # sqrt(disc), with a finite derivative where disc = 0 (there the update
+    # lands on 0, see below, and the identity is returned)
+    pos = disc > 0
+    root = torch.where(pos, torch.sqrt(torch.where(pos, disc, torch.ones_like(disc))),
+                       torch.zeros_like(disc))
+    denom = l2 + root
     safe = denom > 1e-300
     delta = torch.where(safe, -2.0 * eps / torch.where(safe, denom, torch.ones_like(denom)),
                         torch.zeros_like(denom))

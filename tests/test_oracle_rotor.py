@@ -115,6 +115,31 @@ def test_degenerate_rotor_maps_to_identity():
     assert torch.equal(rn, expect)
 
 
+def test_degenerate_rotors_have_zero_gradient():
+    """Identity with zero gradient for rotors of squared norm below 1e-12
+    before the update (0, all 1e-7) or after it: r = 1 +- e0123, i.e.
+    (s, p) = (1, +-1), has 2|eps| = l^2, the step lands on 0 (the updated squared
+    norm is (l^4 - 4 eps^2) / l^2); also a scaled copy.  A regular rotor
+    beside them keeps a finite, nonzero gradient."""
+    r = torch.zeros(6, 8, dtype=torch.float64)
+    r[1] = 1e-7
+    r[2, 0], r[2, 7] = 1.0, 1.0
+    r[3, 0], r[3, 7] = 1.0, -1.0
+    r[4, 0], r[4, 7] = 3.0, 3.0
+    r[5] = torch.tensor([0.3, -0.2, 0.5, 0.1, 0.4, -0.3, 0.2, 0.6], dtype=torch.float64)
+    r.requires_grad_(True)
+    rn = O.rotor_normalize(r)
+    ident = torch.zeros(8, dtype=torch.float64)
+    ident[0] = 1
+    for i in range(5):
+        assert torch.equal(rn[i].detach(), ident), i
+    w = torch.as_tensor(np.random.default_rng(0).normal(size=(6, 8)))
+    (rn * w).sum().backward()
+    assert bool(torch.isfinite(r.grad).all())
+    assert torch.equal(r.grad[:5], torch.zeros(5, 8, dtype=torch.float64))
+    assert float(r.grad[5].abs().max()) > 1e-3
+
+
 def test_fmap_equals_sandwich_product():
     rn = O.rotor_normalize(rand_rotors(40, seed=5))
     R = O.rotor_to_matrix(rn)
