@@ -109,8 +109,13 @@ def cpu_baseline(g, view, st, pix_counts):
     per_pixel = max((t2 - t1) / (p2 - p1), 1e-12)
     fixed = max(t1 - per_pixel * p1, 0.0)
     step_s = fixed + per_pixel * H * Wd
+    try:
+        host_cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        host_cores = os.cpu_count()
     return {
-        "value": 1.0 / step_s, "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+        "value": 1.0 / step_s, "unit": "steps/s", "cores": torch.get_num_threads(),
+        "host_cores": host_cores, "kind": "oracle",
         "sample": (f"FP64 oracle forward+autograd backward, all {g['opacity'].shape[0]} Gaussians "
                    f"preprocessed, {p1} and {p2} sampled pixels composited "
                    f"({t1:.1f} s, {t2:.1f} s); full {Wd}x{H} frame extrapolated linearly "

@@ -369,6 +369,15 @@ typedef struct {
   int32_t *step;
 } r4d_train_state;
 
+/* Initial optimiser state of a parameter set (the opacity-as-logit
+ * convention the paper takes from 3D Gaussian Splatting, Sec. 4): writes
+ * opacity_logit[i] = ln(o_i / (1 - o_i)) from state->opacity (o clamped to
+ * [1e-7, 1 - 1e-7], evaluated in float64 and rounded to float32), zeroes
+ * adam_m and adam_v over all n (17 + 3k) elements and sets *step = 0.  One
+ * launch, ordered on `stream`; opacity and the other parameters are read
+ * only.  n = 0 only resets the step count. */
+r4d_status r4d_train_state_init(r4d_ctx *ctx, const r4d_train_state *state, void *stream);
+
 /* One Adam step of all five groups (one fused launch).  grads: the gradients
  * of r4d_render_backward (plus any regulariser's), the opacity one w.r.t. the
  * activated opacity (the call multiplies by o (1 - o) for the logit). */

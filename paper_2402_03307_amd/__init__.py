@@ -47,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "r4d_render_forward_flow", "r4d_render_backward_flow", "r4d_render_forward_flow_f64",
     "r4d_render_backward_flow_f64", "r4d_knn4d", "r4d_consistency4d_loss_grad",
     "r4d_consistency4d_loss_grad_f64", "r4d_default_adam_config", "r4d_adam_step",
-    "r4d_opacity_reset", "r4d_entropy_loss_grad", "r4d_render_backward_stats",
+    "r4d_train_state_init", "r4d_opacity_reset", "r4d_entropy_loss_grad", "r4d_render_backward_stats",
     "r4d_default_densify_config", "r4d_densify", "r4d_render_forward_3d",
     "r4d_render_backward_3d", "r4d_render_forward_3d_f64", "r4d_render_backward_3d_f64",
     "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
@@ -149,6 +149,8 @@ def _load():
     lib.r4d_default_adam_config.restype = None
     lib.r4d_adam_step.argtypes = [c_vp, P(_TrainState), P(_Grads), P(_AdamConfig), c_vp]
     lib.r4d_adam_step.restype = ctypes.c_int
+    lib.r4d_train_state_init.argtypes = [c_vp, P(_TrainState), c_vp]
+    lib.r4d_train_state_init.restype = ctypes.c_int
     lib.r4d_opacity_reset.argtypes = [c_vp, P(_TrainState), c_f32, c_vp]
     lib.r4d_opacity_reset.restype = ctypes.c_int
     lib.r4d_entropy_loss_grad.argtypes = [c_vp, c_vp, c_i32, c_f32, c_vp, c_vp, c_vp]
@@ -697,19 +699,22 @@ class TrainState:
     """Optimiser state around a parameter dict (float32 CUDA tensors, updated
     in place): the opacity logit, the Adam moments and the device step count."""
 
-    def __init__(self, params: dict):
+    def __init__(self, params: dict, renderer: "Renderer | None" = None):
         n, deg, dtype = _check_params(params)
         if dtype != torch.float32:
             raise ValueError("the optimiser works on float32 parameters")
         self.params = params
         self.n, self.deg = n, deg
-        o = params["opacity"].double().clamp(1e-7, 1 - 1e-7)
-        self.opacity_logit = (torch.log(o) - torch.log1p(-o)).float().contiguous()
         total = sum(params[k].numel() for k in _PARAM_KEYS)
         dev = params["means"].device
-        self.m = torch.zeros(total, dtype=torch.float32, device=dev)
-        self.v = torch.zeros(total, dtype=torch.float32, device=dev)
-        self.step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.opacity_logit = torch.empty(n, dtype=torch.float32, device=dev)
+        self.m = torch.empty(total, dtype=torch.float32, device=dev)
+        self.v = torch.empty(total, dtype=torch.float32, device=dev)
+        self.step = torch.empty(1, dtype=torch.int32, device=dev)
+        # logit of the opacity, zero moments and step count: r4d_train_state_init
+        rend = renderer if renderer is not None else _renderer_for(dev)
+        st = _lib.r4d_train_state_init(rend.handle, ctypes.byref(self.struct()), _stream(dev))
+        rend._check(st, "r4d_train_state_init")
 
     def struct(self) -> _TrainState:
         p = self.params

@@ -1610,6 +1610,19 @@ r4d_status r4d_adam_step(r4d_ctx* ctx, const r4d_train_state* st, const r4d_grad
   return R4D_OK;
 }
 
+r4d_status r4d_train_state_init(r4d_ctx* ctx, const r4d_train_state* st, void* stream) {
+  if (!ctx) return R4D_ERR_INVALID_ARG;
+  if (!st || !st->step || st->n < 0 || st->sh_degree < 0 || st->sh_degree > 3 ||
+      (st->n > 0 && (!st->opacity || !st->opacity_logit || !st->adam_m || !st->adam_v)))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid optimiser state");
+  const uint64_t n = uint64_t(st->n);
+  const uint64_t k = uint64_t(st->sh_degree + 1) * uint64_t(st->sh_degree + 1);
+  R4D_HIP(hipSetDevice(ctx->device));
+  R4D_HIP(launch_state_init(uint32_t(n), n * (17 + 3 * k), st->opacity, st->opacity_logit,
+                            st->adam_m, st->adam_v, st->step, static_cast<hipStream_t>(stream)));
+  return R4D_OK;
+}
+
 r4d_status r4d_opacity_reset(r4d_ctx* ctx, const r4d_train_state* st, float cap, void* stream) {
   if (!ctx) return R4D_ERR_INVALID_ARG;
   if (!st || !st->opacity_logit || !st->opacity || !st->adam_m || !st->adam_v || st->n < 0 ||

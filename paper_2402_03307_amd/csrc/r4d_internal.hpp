@@ -289,6 +289,8 @@ struct AdamConfig {
 // opacity back into p[3].
 hipError_t launch_adam(const AdamGroups& groups, float* logit, float* m, float* v, int32_t* step,
                        const AdamConfig& cfg, hipStream_t stream);
+hipError_t launch_state_init(uint32_t n, uint64_t total, const float* opacity, float* logit,
+                             float* m, float* v, int32_t* step, hipStream_t stream);
 hipError_t launch_opacity_reset(uint32_t n, float cap, float* logit, float* opacity, float* m_op,
                                 float* v_op, hipStream_t stream);
 // Entropy (1/n) sum -o ln o into *loss (nullable); grad (nullable) += weight *

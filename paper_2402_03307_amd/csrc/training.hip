@@ -117,6 +117,27 @@ __global__ __launch_bounds__(kBlock) void opacity_reset_kernel(uint32_t n, float
   v_op[i] = 0.f;
 }
 
+// Optimiser state of a fresh parameter set: the opacity logit
+// ln(o / (1 - o)) of the activated opacity (o clamped to [1e-7, 1 - 1e-7], in
+// float64), both Adam moments zero over every element, the step count zero.
+__global__ __launch_bounds__(kBlock) void state_init_kernel(uint32_t n, uint64_t total,
+                                                            const float* __restrict__ opacity,
+                                                            float* __restrict__ logit,
+                                                            float* __restrict__ m,
+                                                            float* __restrict__ v,
+                                                            int32_t* __restrict__ step) {
+  const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+  for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < total; i += stride) {
+    m[i] = 0.f;
+    v[i] = 0.f;
+    if (i < n) {
+      const double o = fmin(fmax(double(opacity[i]), 1e-7), 1.0 - 1e-7);
+      logit[i] = float(log(o) - log1p(-o));
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *step = 0;
+}
+
 // Per workgroup: sum of -o ln o into partials; grad += weight * d/do of the
 // mean, -(ln o + 1) / n.
 __global__ __launch_bounds__(kBlock) void entropy_kernel(const float* __restrict__ opacity,
@@ -179,6 +200,16 @@ hipError_t launch_opacity_reset(uint32_t n, float cap, float* logit, float* opac
   const float cap_logit = float(log(double(cap)) - log1p(-double(cap)));
   hipLaunchKernelGGL(opacity_reset_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
                      stream, n, cap, cap_logit, logit, opacity, m_op, v_op);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(uint32_t n, uint64_t total, const float* opacity, float* logit,
+                             float* m, float* v, int32_t* step, hipStream_t stream) {
+  uint64_t blocks = (total + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(state_init_kernel, dim3(uint32_t(blocks)), dim3(kBlock), 0, stream, n, total,
+                     opacity, logit, m, v, step);
   return hipGetLastError();
 }
 

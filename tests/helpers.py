@@ -100,6 +100,62 @@ def cpu_tile_lists(rec: np.ndarray, rects: np.ndarray, depth_keys: np.ndarray, t
     return values, ranges.astype(np.uint32)
 
 
+def cpu_tile_rows(rec: np.ndarray, rects: np.ndarray, depth_keys: np.ndarray, tiles_x: int,
+                  tile_rows, tile_size: int, width: int, height: int, chunk: int = 1 << 20):
+    """The reference binning of cpu_tile_lists restricted to whole tile rows:
+    (total entry count over all rows, {tile id: values in (depth, index)
+    order} for every tile of `tile_rows`).  For renders whose full lists are
+    too long to sort on the host; every Gaussian's row runs are still derived
+    (in chunks of rows) so the total is exact."""
+    rects = rects.astype(np.int64)
+    vis = np.nonzero(depth_keys != 0xFFFFFFFF)[0]
+    want = np.zeros(int(rects[:, 3].max(initial=0)) + 1, dtype=bool)
+    for r in tile_rows:
+        if r < want.size:
+            want[r] = True
+    nrow = rects[vis, 3] - rects[vis, 1]
+    assert np.all(nrow > 0)
+    total = 0
+    parts_t, parts_i = [], []
+    csum = np.concatenate([[0], np.cumsum(nrow)])
+    g0 = 0
+    while g0 < vis.size:
+        g1 = int(np.searchsorted(csum, csum[g0] + chunk, side="right")) - 1
+        g1 = max(g1, g0 + 1)
+        v = vis[g0:g1]
+        nr = nrow[g0:g1]
+        gi = np.repeat(v, nr)
+        first = np.repeat(np.cumsum(nr) - nr, nr)
+        ys = rects[gi, 1] + (np.arange(gi.size) - first)
+        with np.errstate(invalid="ignore"):
+            x0, x1 = row_runs(rec, rects, ys, gi, tile_size, width, height)
+        L = x1 - x0
+        assert np.all(L > 0), "a row of a box without a run"
+        heads = np.cumsum(nr) - nr
+        assert np.array_equal(np.minimum.reduceat(x0, heads), rects[v, 0])
+        assert np.array_equal(np.maximum.reduceat(x1, heads), rects[v, 2])
+        total += int(L.sum())
+        sel = want[ys]
+        if sel.any():
+            ys_s, x0_s, L_s, gi_s = ys[sel], x0[sel], L[sel], gi[sel]
+            run = np.repeat(np.arange(L_s.size), L_s)
+            within = np.arange(run.size) - np.repeat(np.cumsum(L_s) - L_s, L_s)
+            parts_t.append(ys_s[run] * tiles_x + x0_s[run] + within)
+            parts_i.append(gi_s[run])
+        g0 = g1
+    tiles = np.concatenate(parts_t) if parts_t else np.zeros(0, np.int64)
+    idx = np.concatenate(parts_i) if parts_i else np.zeros(0, np.int64)
+    keys = depth_keys[idx].astype(np.int64)
+    order = np.lexsort((idx, keys, tiles))
+    tiles, idx = tiles[order], idx[order]
+    out = {}
+    for r in tile_rows:
+        for t in range(r * tiles_x, (r + 1) * tiles_x):
+            lo, hi = np.searchsorted(tiles, t, "left"), np.searchsorted(tiles, t, "right")
+            out[t] = idx[lo:hi].astype(np.uint32)
+    return total, out
+
+
 def tile_lists(r4d, saved, view: int, n: int):
     """The GPU's tile lists of one render of a saved forward and their CPU
     re-derivation: (values, ranges, ref_values, ref_ranges, stats)."""

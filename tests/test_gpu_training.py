@@ -52,6 +52,28 @@ def _split_moments(flat, g):
     return out
 
 
+def test_train_state_init(r4d, rend, device):
+    """r4d_train_state_init: the opacity logit ln(o / (1 - o)) (o clamped to
+    [1e-7, 1 - 1e-7], float64 then float32), zero moments and step, written
+    over stale values (the state's tensors come from torch.empty)."""
+    g = W.gaussians(5000, 3)
+    g["opacity"][:4] = np.array([0.0, 1.0, 1e-9, 0.5], dtype=np.float32)
+    p = to_device(g, device)
+    junk = torch.full((1 << 20,), 7.0, device=device)   # dirty the caching allocator's blocks
+    del junk
+    state = r4d.TrainState(p, rend)
+    torch.cuda.synchronize()
+    o = np.clip(g["opacity"].astype(np.float64), 1e-7, 1 - 1e-7)
+    ref = (np.log(o) - np.log1p(-o)).astype(np.float32)
+    got = state.opacity_logit.cpu().numpy()
+    # the device's float64 log may differ from numpy's in the last bit, which
+    # can move the float32 rounding by one unit
+    assert np.all(np.abs(got - ref) <= np.spacing(np.abs(ref)))
+    assert state.m.numel() == 5000 * (17 + 48)
+    assert float(state.m.abs().max()) == 0.0 and float(state.v.abs().max()) == 0.0
+    assert int(state.step.item()) == 0
+
+
 @pytest.mark.parametrize("n", [3000, 3001])   # the 4-wide and the scalar kernel
 def test_adam_steps_match_oracle(r4d, rend, device, n):
     g = W.gaussians(n, 3)
