@@ -201,7 +201,8 @@ int raster_default_ppt(int tile_size, bool backward);
 
 // Persistent launch over all tiles of all renders; tickets: 1 word, zeroed.
 // recs: [V][n]; image: [3][pixels of render v] at 3 * pix_base; T_final,
-// n_contrib, n_eval (nullable) per pixel at pix_base; sv: what the backward's
+// n_contrib per pixel at pix_base, n_eval (nullable) per pixel the pair
+// (entries evaluated, entries blended) at 2 * pix_base; sv: what the backward's
 // segment walks need (see kSegment).  A flow render (flows: [V][n] per-Gaussian
 // 2D flow, not null) also composites the flow into flow_image ([2][pixels] at
 // 2 * pix_base, background 0) and fills sv.ckf and sv.flow; it counts no

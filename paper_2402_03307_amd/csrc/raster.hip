@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "r4d_internal.hpp"
+#include "rowwalk.hpp"
 
 namespace r4d {
 
@@ -239,7 +240,8 @@ struct TileCfg {
 // Forward.  A pixel that has stopped keeps its final transmittance in Tf and
 // continues with T = 0, which makes every later contribution zero and every later
 // transmittance test fail, so no per-pixel "done" flag is carried through the
-// loop.  COUNT counts the entries each pixel evaluates (measurement builds only).
+// loop.  COUNT counts, per pixel, the entries evaluated and the entries
+// blended, stored as a pair in n_eval (measurement builds only).
 template <typename T, int TS, int PPT, bool COUNT, bool FLOW>
 __device__ __forceinline__ void raster_fwd_tile(
     Staged<T>* s_rec, uint32_t* s_walk, const Rec<T>* __restrict__ recs,
@@ -259,7 +261,7 @@ __device__ __forceinline__ void raster_fwd_tile(
   const T e_min = T(kHalfLog2e) * T(st.ext2);
   const T amin = T(st.alpha_min), amax = T(st.alpha_max), tmin = T(st.T_min);
   T py[PPT], Tr[PPT], c0[PPT], c1[PPT], c2[PPT], c3[PPT], c4[PPT];
-  uint32_t last[PPT], evals[PPT];
+  uint32_t last[PPT], evals[PPT], blends[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int y = y0 + k * Cfg::kRowStep;
@@ -267,7 +269,7 @@ __device__ __forceinline__ void raster_fwd_tile(
     // pixels outside the image start finished
     Tr[k] = (x < v.W && y < v.H) ? T(1) : T(0);
     c0[k] = c1[k] = c2[k] = c3[k] = c4[k] = T(0);
-    last[k] = evals[k] = 0u;
+    last[k] = evals[k] = blends[k] = 0u;
   }
   if (threadIdx.x == 0) *s_walk = 0u;
   for (uint32_t base = rg.x; base < rg.y; base += NB) {
@@ -300,6 +302,7 @@ __device__ __forceinline__ void raster_fwd_tile(
           const T Tn = Tr[k] * (T(1) - alpha);
           if (COUNT) evals[k] += Tr[k] > T(0) ? 1u : 0u;
           const bool blend = pass & (Tn >= tmin);
+          if (COUNT) blends[k] += blend ? 1u : 0u;
           // The first Gaussian that would take T below T_min stops the pixel,
           // which keeps its final transmittance negated from then on (a
           // finished pixel has Tr <= 0, so nothing blends or stops it again).
@@ -355,7 +358,10 @@ __device__ __forceinline__ void raster_fwd_tile(
       }
       T_final[pix] = Tfin;
       n_contrib[pix] = last[k];
-      if (COUNT) n_eval[pix] = evals[k];
+      if (COUNT) {
+        n_eval[2 * pix] = evals[k];
+        n_eval[2 * pix + 1] = blends[k];
+      }
       lane_walk = last[k] > lane_walk ? last[k] : lane_walk;
     }
   }
@@ -594,7 +600,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
         s_rec, &s_walk, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr, values,
         ranges[g], int(g - sl.tile_base), g, v, st, image + 3 * pb,
         FLOW ? flow_image + 2 * pb : nullptr, T_final + pb, n_contrib + pb,
-        COUNT ? n_eval + pb : nullptr, sv.ck, sv.ckf, sv.img + 3 * pb,
+        COUNT ? n_eval + 2 * pb : nullptr, sv.ck, sv.ckf, sv.img + 3 * pb,
         FLOW ? sv.flow + 2 * pb : nullptr, sv.walk);
     if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
     __syncthreads();
@@ -603,28 +609,49 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
   }
 }
 
-// Backward work items are (tile, segment) pairs: seg_tile[i] names the tile of
-// item i and seg_base[tile] its first item, so the segments of one long list
-// run in parallel.  order (or null: item order) lists the items in the order
-// they are taken, longest first, so that the short ones fill the gaps at the
-// end of the launch.
+// Length classes of the tiles' last segments (seg_queue_kernel) and where the
+// queue lengths sit in the backward's ticket words.
+constexpr uint32_t kLenBuckets = 8;
+constexpr int kQueueCounts = 8;
+
+// Backward work items are (tile, segment) pairs, so the segments of one long
+// list run in parallel; they are taken from the queues of seg_queue_kernel in
+// queue order (q_count: the nine queue lengths).
 template <typename T, int TS, int PPT, bool FLOW>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     const Rec<T>* __restrict__ recs, const Vec2<T>* __restrict__ flows, uint32_t n,
     const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
     const ViewSlot* __restrict__ slots, int n_views, SettingsDev st,
     const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, RasterSaved<T> sv,
-    const uint32_t* __restrict__ seg_tile, const uint32_t* __restrict__ seg_base,
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ total_items,
+    const uint2* __restrict__ q_full, const uint2* __restrict__ q_last, uint32_t total_tiles,
     const T* __restrict__ dL_dimage, const T* __restrict__ dL_dflow,
     double* __restrict__ grad2d, uint32_t* __restrict__ tickets) {
   __shared__ BwdShared<T, TS, PPT, FLOW> sh;
   __shared__ uint32_t s_ticket;
-  const uint32_t total = *total_items;
+  uint32_t qn[1 + kLenBuckets], total = 0;
+#pragma unroll
+  for (uint32_t k = 0; k <= kLenBuckets; ++k) {
+    qn[k] = tickets[kQueueCounts + k];
+    total += qn[k];
+  }
   for (uint32_t it = blockIdx.x; it < total;) {
-    const uint32_t item = order ? order[it] : it;
-    const uint32_t g = seg_tile[item];
-    const uint32_t seg = item - seg_base[g];
+    uint2 item;
+    if (it < qn[0]) {
+      item = q_full[it];
+    } else {
+      // queue 1 + k holding position r (it < total, so k stays below kLenBuckets)
+      uint32_t r = it - qn[0], k = 0;
+#pragma unroll
+      for (uint32_t b = 0; b + 1 < kLenBuckets; ++b) {
+        if (k == b && r >= qn[1 + b]) {
+          r -= qn[1 + b];
+          k = b + 1;
+        }
+      }
+      item = q_last[size_t(k) * total_tiles + r];
+    }
+    const uint32_t g = item.x;
+    const uint32_t seg = item.y;
     const int vi = slot_of_tile(slots, n_views, g);
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
@@ -641,154 +668,60 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
   }
 }
 
-// Segments of the backward walk: count per tile, their scan, the item -> tile
-// map.
-__global__ __launch_bounds__(256) void seg_count_kernel(const uint32_t* __restrict__ walk,
-                                                        uint32_t total_tiles,
-                                                        uint32_t* __restrict__ count) {
-  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-  if (t < total_tiles) count[t] = (walk[t] + kSegment - 1) / kSegment;
-}
-
-__global__ __launch_bounds__(256) void seg_map_kernel(const uint32_t* __restrict__ count,
-                                                      const uint32_t* __restrict__ base,
-                                                      uint32_t total_tiles,
-                                                      uint32_t* __restrict__ seg_tile) {
-  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= total_tiles) return;
-  const uint32_t b = base[t], c = count[t];
-  for (uint32_t i = 0; i < c; ++i) seg_tile[b + i] = t;
-}
-
-// The three steps above in one workgroup, for runs of at most kSegPlanOne tiles
-// (a dependent launch costs several microseconds, more than this scan): the
-// tiles are taken 4096 at a time, four consecutive ones per thread, each chunk
-// scanned across the workgroup and offset by the total of the chunks before it.  The same workgroup then writes
-// the order in which the items are taken: every segment but a tile's last is
-// full (kSegment entries) and goes first; the last segments follow in
-// kLenBuckets classes of decreasing length (within a class, in any order).
-constexpr uint32_t kSegPlanOne = 16384;
-constexpr uint32_t kLenBuckets = 8;
-constexpr uint32_t kPlanTilesPerThread = 4;  // fewer dependent chunk steps
+// Work items of the backward: the 256-entry segments of every tile's list up
+// to its furthest last contributor, as (tile, segment) pairs in nine queues:
+// queue 0 holds every segment but a tile's last (all full, kSegment entries),
+// queue 1 + b the tiles' last segments of length class b (longer first).  The
+// backward takes queue 0, then queues 1..8, so the short items fill the end of
+// its launch; the order within a queue does not matter.  One thread per tile;
+// a wavefront reserves its places with one atomic per queue.  q_count: 9
+// counters, zeroed by the caller; q_full: capacity >= the segments in all;
+// q_last: kLenBuckets arrays of total_tiles pairs.
 
 __device__ __forceinline__ uint32_t len_bucket(uint32_t len) {
   const uint32_t b = (kSegment - len) * kLenBuckets / kSegment;
   return b < kLenBuckets ? b : kLenBuckets - 1;
 }
 
-__global__ __launch_bounds__(1024) void seg_plan_kernel(const uint32_t* __restrict__ walk,
+__global__ __launch_bounds__(256) void seg_queue_kernel(const uint32_t* __restrict__ walk,
                                                         uint32_t total_tiles,
-                                                        uint32_t* __restrict__ base,
-                                                        uint32_t* __restrict__ seg_tile,
-                                                        uint32_t* __restrict__ order) {
-  constexpr uint32_t Q = kPlanTilesPerThread, CH = 1024u * Q;
-  __shared__ uint32_t s_wave[16];
-  __shared__ uint32_t s_next[kLenBuckets + 1];  // [0]: full segments, [1 + b]: class b
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                                        uint32_t* __restrict__ q_count,
+                                                        uint2* __restrict__ q_full,
+                                                        uint2* __restrict__ q_last) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t w = t < total_tiles ? walk[t] : 0u;
+  const uint32_t cnt = (w + kSegment - 1) / kSegment;
+  const uint32_t f = cnt > 0u ? cnt - 1u : 0u;
+  // full segments: a wavefront scan of the counts, one reservation, then the
+  // wavefront writes its segments 64 at a time, each lane finding the tile of
+  // its segment by a binary search over the tiles' first positions
+  const uint32_t incl = wave_incl_scan_u32(f, lane);
+  const uint32_t excl = incl - f;
+  const uint32_t total_w = __shfl(incl, 63, 64);
+  uint32_t base = 0;
+  if (lane == 63 && total_w) base = atomicAdd(&q_count[0], total_w);
+  base = __shfl(base, 63, 64);
+  for (uint32_t c = 0; c < total_w; c += 64) {
+    const uint32_t i = c + uint32_t(lane);
+    const int o = wave_upper_lane(excl, i);
+    const uint32_t tile = __shfl(t, o, 64);
+    const uint32_t seg = i - __shfl(excl, o, 64);
+    if (i < total_w) q_full[base + i] = make_uint2(tile, seg);
+  }
+  // last segments by length class: a ballot rank and one atomic per class
+  const uint32_t cls = cnt > 0u ? len_bucket(w - f * kSegment) : kLenBuckets;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  if (threadIdx.x <= kLenBuckets) s_next[threadIdx.x] = 0u;
-  __syncthreads();
-  // pass 1: segment counts and first items (thread: Q consecutive tiles of a
-  // chunk of CH), seg_tile, and the last segments per length class
-  uint32_t carry = 0;
-  for (uint32_t c0 = 0; c0 < total_tiles; c0 += CH) {
-    const uint32_t t0 = c0 + threadIdx.x * Q;
-    uint32_t cnt[Q], cls[Q], tsum = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < Q; ++q) {
-      const uint32_t w = t0 + q < total_tiles ? walk[t0 + q] : 0u;
-      cnt[q] = (w + kSegment - 1) / kSegment;
-      cls[q] = cnt[q] > 0 ? len_bucket(w - (cnt[q] - 1) * kSegment) : kLenBuckets;  // none
-      tsum += cnt[q];
-    }
-    uint32_t incl = tsum;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += y;
-    }
-    if (lane == 63) s_wave[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, chunk = 0;
-#pragma unroll
-    for (int w = 0; w < 16; ++w) {
-      before += w < wave ? s_wave[w] : 0u;
-      chunk += s_wave[w];
-    }
-    __syncthreads();
-    uint32_t run = carry + before + incl - tsum;
-#pragma unroll
-    for (uint32_t q = 0; q < Q; ++q) {
-      if (t0 + q < total_tiles) {
-        base[t0 + q] = run;
-        for (uint32_t i = 0; i < cnt[q]; ++i) seg_tile[run + i] = t0 + q;
-      }
-      run += cnt[q];
-      // one LDS atomic per wavefront and class
-#pragma unroll
-      for (uint32_t k = 0; k < kLenBuckets; ++k) {
-        const unsigned long long m = __ballot(cls[q] == k);
-        if (m != 0ull && lane == 0) atomicAdd(&s_next[1 + k], uint32_t(__popcll(m)));
-      }
-    }
-    carry += chunk;
-  }
-  if (threadIdx.x == 0) base[total_tiles] = carry;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // starts: full segments at 0, class b after the full ones and classes < b
-    uint32_t last = 0;
-    for (uint32_t b = 1; b <= kLenBuckets; ++b) last += s_next[b];
-    uint32_t off = carry - last;
-    s_next[0] = 0u;
-    for (uint32_t b = 1; b <= kLenBuckets; ++b) {
-      const uint32_t c = s_next[b];
-      s_next[b] = off;
-      off += c;
-    }
-  }
-  __syncthreads();
-  // pass 2: each thread revisits its own tiles (base[t] is its own earlier
-  // write); a wavefront places its full segments with a scan and one atomic,
-  // and its last segments of each class with a ballot rank and one atomic
-  for (uint32_t c0 = 0; c0 < total_tiles; c0 += CH) {
-    const uint32_t t0 = c0 + threadIdx.x * Q;
-    uint32_t cnt[Q], cls[Q], b[Q], fsum = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < Q; ++q) {
-      const bool in = t0 + q < total_tiles;
-      const uint32_t w = in ? walk[t0 + q] : 0u;
-      b[q] = in ? base[t0 + q] : 0u;
-      cnt[q] = (w + kSegment - 1) / kSegment;
-      cls[q] = cnt[q] > 0 ? len_bucket(w - (cnt[q] - 1) * kSegment) : kLenBuckets;
-      fsum += cnt[q] > 0 ? cnt[q] - 1 : 0u;
-    }
-    uint32_t incl = fsum;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += y;
-    }
-    uint32_t wfull = 0;
-    if (lane == 63 && incl != 0u) wfull = atomicAdd(&s_next[0], incl);
-    wfull = __shfl(wfull, 63, 64);
-    uint32_t fpos = wfull + incl - fsum;
-#pragma unroll
-    for (uint32_t q = 0; q < Q; ++q) {
-      const uint32_t f = cnt[q] > 0 ? cnt[q] - 1 : 0u;
-      for (uint32_t i = 0; i < f; ++i) order[fpos + i] = b[q] + i;
-      fpos += f;
-#pragma unroll
-      for (uint32_t k = 0; k < kLenBuckets; ++k) {
-        const unsigned long long m = __ballot(cls[q] == k);
-        if (m == 0ull) continue;
-        const int leader = __ffsll(static_cast<long long>(m)) - 1;
-        uint32_t cb = 0;
-        if (lane == leader) cb = atomicAdd(&s_next[1 + k], uint32_t(__popcll(m)));
-        cb = __shfl(cb, leader, 64);
-        if (cls[q] == k) order[cb + uint32_t(__popcll(m & lt))] = b[q] + cnt[q] - 1;
-      }
-    }
+  for (uint32_t k = 0; k < kLenBuckets; ++k) {
+    const unsigned long long m = __ballot(cls == k);
+    if (m == 0ull) continue;
+    const int leader = __ffsll(static_cast<long long>(m)) - 1;
+    uint32_t cb = 0;
+    if (lane == leader) cb = atomicAdd(&q_count[1 + k], uint32_t(__popcll(m)));
+    cb = __shfl(cb, leader, 64);
+    if (cls == k)
+      q_last[size_t(k) * total_tiles + cb + uint32_t(__popcll(m & lt))] = make_uint2(t, f);
   }
 }
 
@@ -899,27 +832,13 @@ hipError_t raster_bwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
                           double* grad2d, uint32_t* work, hipStream_t stream) {
   constexpr int NT = TS * TS / PPT;
   if (total_tiles == 0) return hipSuccess;
-  // work: [tickets (64 words, zeroed by the caller) | count | base | seg_tile | order |
-  //        scan scratch]
+  // work: [tickets and queue counts (64 words, zeroed by the caller) | full-segment
+  //        queue (max_items pairs) | last-segment queues (kLenBuckets x tiles pairs)]
   uint32_t* tickets = work;
-  uint32_t* count = work + 64;
-  uint32_t* base = count + total_tiles + 1;
-  uint32_t* seg_tile = base + total_tiles + 1;
-  uint32_t* order = seg_tile + max_items;
-  uint32_t* scan_tmp = order + max_items;
-  if (total_tiles <= kSegPlanOne) {
-    hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(1024), 0, stream, sv.walk, total_tiles, base,
-                       seg_tile, order);
-  } else {
-    order = nullptr;  // many more items than resident workgroups: taken in item order
-    const uint32_t tb = (total_tiles + 255) / 256;
-    hipLaunchKernelGGL(seg_count_kernel, dim3(tb), dim3(256), 0, stream, sv.walk, total_tiles,
-                       count);
-    const hipError_t e = scan_u32(count, total_tiles, base, scan_tmp, stream);  // base[T] = total
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(seg_map_kernel, dim3(tb), dim3(256), 0, stream, count, base, total_tiles,
-                       seg_tile);
-  }
+  uint2* q_full = reinterpret_cast<uint2*>(work + 64);
+  uint2* q_last = q_full + max_items;
+  hipLaunchKernelGGL(seg_queue_kernel, dim3((total_tiles + 255) / 256), dim3(256), 0, stream,
+                     sv.walk, total_tiles, tickets + kQueueCounts, q_full, q_last);
   const bool flow = dL_dflow != nullptr;
   if (flow && (!flows || !sv.ckf || !sv.flow)) return hipErrorInvalidValue;
   static const uint32_t cap_plain = resident_groups(raster_bwd_kernel<T, TS, PPT, false>, NT);
@@ -933,21 +852,18 @@ hipError_t raster_bwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
   if (flow)
     hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT, true>), dim3(grid), dim3(NT), 0, stream,
                        recs, flows, n, values, ranges, slots, n_views, st, T_final, n_contrib, sv,
-                       seg_tile, base, order, base + total_tiles, dL_dimage, dL_dflow, grad2d,
-                       tickets);
+                       q_full, q_last, total_tiles, dL_dimage, dL_dflow, grad2d, tickets);
   else
     hipLaunchKernelGGL((raster_bwd_kernel<T, TS, PPT, false>), dim3(grid), dim3(NT), 0, stream,
                        recs, flows, n, values, ranges, slots, n_views, st, T_final, n_contrib, sv,
-                       seg_tile, base, order, base + total_tiles, dL_dimage, dL_dflow, grad2d,
-                       tickets);
+                       q_full, q_last, total_tiles, dL_dimage, dL_dflow, grad2d, tickets);
   return hipGetLastError();
 }
 
 }  // namespace
 
 size_t raster_bwd_work_bytes(uint32_t total_tiles, uint64_t max_items) {
-  return (2 * (size_t(total_tiles) + 1) + 2 * size_t(max_items) + 64) * 4 +
-         scan_u32_temp_bytes(total_tiles + 1);
+  return 64 * 4 + (size_t(max_items) + size_t(kLenBuckets) * total_tiles) * 8;
 }
 
 bool raster_config_supported(int tile_size, int ppt) {
