@@ -53,16 +53,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # TFLOP/s counts the packed form.
 FP32_VECTOR_PEAK_TFLOPS = 78.6
 
-# Arithmetic of one evaluated (pixel, Gaussian) pair in the forward compositing
-# loop: offset (2), whitened offset (6), exponent (3: form, scale is folded,
-# exp2), opacity product, clamp (min), three tests (the combined extent/alpha
-# threshold, T_min, still running), transmittance update (2), weight (1) and
-# colour accumulation (3 fma = 6).
-FLOPS_PER_PAIR_FWD = 25
-# Backward, per blended pair: the forward evaluation (14), transmittance
-# recovery (3), colour-behind update and alpha gradient (14), and the nine
-# moment sums (18 with fma = 2).
-FLOPS_PER_PAIR_BWD = 49
+# Arithmetic of the compositing loops, counted per (pixel, Gaussian) pair as
+# the algorithm needs it (fma = 2, exp2 / rcp / min / compare = 1; the lane
+# reductions, ballots and masks of the kernels are not counted).
+# Forward, every evaluated pair: offset (2), whitened offset (6), exponent (3),
+# exp2, opacity product, clamp, the extent/alpha test, transmittance product
+# (2) and the T_min test = 18; every blended pair adds its weight (1) and the
+# colour accumulation (3 fma = 6) = 7.
+FLOPS_PER_EVAL_FWD = 18
+FLOPS_PER_BLEND_FWD = 7
+# Backward, every pair up to the pixel's last contributor: the forward
+# evaluation = 15; every blended pair: 1 / (1 - a) (2), transmittance in front
+# (1), weight (1), g . colour (5), dL/da (3), colour-behind update (2), the
+# alpha-weighted gradient (1), the two offset products (2) and the nine moment
+# sums (2 adds + 7 fma = 16) = 33.
+FLOPS_PER_WALK_BWD = 15
+FLOPS_PER_BLEND_BWD = 33
 
 
 def parse():
@@ -474,6 +480,7 @@ def main():
     rend.set_timing(False)
     stats = last_saved.stats(0)
     n_eval = last_saved.copy(0, r4d.BUF_NEVAL, n).to(torch.int64).sum().item()
+    n_blend = last_saved.copy(0, r4d.BUF_NBLEND, n).to(torch.int64).sum().item()
     n_contrib = last_saved.copy(0, r4d.BUF_NCONTRIB, n).to(torch.int64).sum().item()
     last_saved.release()
     stages = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tim.items()}
@@ -515,13 +522,13 @@ def main():
                     "traffic": traffic}
     else:
         fwd = dominant == "raster_fwd"
-        pairs = n_eval if fwd else n_contrib
-        flops = pairs * (FLOPS_PER_PAIR_FWD if fwd else FLOPS_PER_PAIR_BWD)
+        flops = (n_eval * FLOPS_PER_EVAL_FWD + n_blend * FLOPS_PER_BLEND_FWD if fwd else
+                 n_contrib * FLOPS_PER_WALK_BWD + n_blend * FLOPS_PER_BLEND_BWD)
         achieved = flops / (dom_ms * 1e-3) / 1e12
         roofline = {"kernel": dominant, "bound": "alu", "achieved": achieved,
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                    "pairs": pairs}
+                    "flops": flops}
     hbm_stages = {}
     for name, b in alg_bytes.items():
         if stages.get(name):
@@ -554,7 +561,13 @@ def main():
         "n_visible": n_vis,
         "n_dup": D,
         "pairs_evaluated_fwd": n_eval,
-        "pairs_blended": n_contrib,
+        "pairs_walked_bwd": n_contrib,
+        "pairs_blended": n_blend,
+        "raster_tflops": {
+            "raster_fwd": (n_eval * FLOPS_PER_EVAL_FWD + n_blend * FLOPS_PER_BLEND_FWD)
+            / (stages["raster_fwd"] * 1e-3) / 1e12,
+            "raster_bwd": (n_contrib * FLOPS_PER_WALK_BWD + n_blend * FLOPS_PER_BLEND_BWD)
+            / (stages["raster_bwd"] * 1e-3) / 1e12},
         "stage_ms": stages,
         "hbm_stages": hbm_stages,
         "roofline": roofline,

@@ -79,7 +79,13 @@ typedef struct {
  *   tile_size     8, 16 or 32 pixels, or 0: picked by the autotuner, which times
  *                 forward + backward of the call's renders at every tile size and
  *                 tile-sort chunking and keeps the fastest for calls of the same
- *                 shape (16).  The image does not depend on the tile size.
+ *                 shape: device, float type, views' sizes, SH degree, mode and
+ *                 Gaussian count within a half octave (16).  Choices persist
+ *                 across processes in a text file: the path in the environment
+ *                 variable R4D_TUNE_CACHE (empty: none), else
+ *                 $XDG_CACHE_HOME/r4d/autotune.txt or ~/.cache/r4d/autotune.txt;
+ *                 a call whose shape the file holds is not tuned again.
+ *                 The image does not depend on the tile size.
  *   near_plane    camera-space depth at or below which a Gaussian is dropped (0.2)
  *   time_cull     a Gaussian is dropped if lambda (t - mu_t)^2 > time_cull (16;
  *                 the visibility threshold of Sec. 3.2.2)
@@ -587,6 +593,8 @@ r4d_status r4d_saved_stats(const r4d_saved *saved, int view, int64_t *n_visible,
  *   R4D_BUF_NEVAL     H*W uint32: tile-list entries the forward evaluated for the
  *                     pixel (only if timing was enabled for the forward call,
  *                     R4D_ERR_STATE otherwise; never for a flow render)
+ *   R4D_BUF_NBLEND    H*W uint32: Gaussians the forward blended into the pixel
+ *                     (conditions as R4D_BUF_NEVAL)
  *   R4D_BUF_FLOW      per Gaussian, 2 floats (doubles): its 2D flow, record i
  *                     at [2*i], set where RECORDS is (flow renders only,
  *                     R4D_ERR_STATE otherwise)
@@ -601,7 +609,8 @@ enum {
   R4D_BUF_TFINAL = 5,
   R4D_BUF_NCONTRIB = 6,
   R4D_BUF_NEVAL = 7,
-  R4D_BUF_FLOW = 8
+  R4D_BUF_FLOW = 8,
+  R4D_BUF_NBLEND = 9
 };
 r4d_status r4d_saved_copy(const r4d_saved *saved, int view, int buffer, void *dst, size_t bytes,
                           void *stream);

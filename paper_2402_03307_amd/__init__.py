@@ -29,13 +29,13 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libr4d.so")
 
-__all__ = ["render", "render_flow", "Renderer", "TrainState", "adam_config", "R4DError", "default_settings", "LIB_PATH",
-           "BUF_RECORDS", "BUF_RECT", "BUF_DEPTHKEY", "BUF_VALUES", "BUF_RANGES",
-           "BUF_TFINAL", "BUF_NCONTRIB", "BUF_FLOW", "EXPORTED_SYMBOLS", "MODE_PER_VIEW",
-           "MODE_FUSED", "MODE_GRAPH"]
+__all__ = ["render", "render_flow", "Renderer", "TrainState", "adam_config", "R4DError",
+           "default_settings", "LIB_PATH", "BUF_RECORDS", "BUF_RECT", "BUF_DEPTHKEY",
+           "BUF_VALUES", "BUF_RANGES", "BUF_TFINAL", "BUF_NCONTRIB", "BUF_NEVAL", "BUF_FLOW",
+           "BUF_NBLEND", "EXPORTED_SYMBOLS", "MODE_PER_VIEW", "MODE_FUSED", "MODE_GRAPH"]
 
 (BUF_RECORDS, BUF_RECT, BUF_DEPTHKEY, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB,
- BUF_NEVAL, BUF_FLOW) = range(9)
+ BUF_NEVAL, BUF_FLOW, BUF_NBLEND) = range(10)
 
 # execution modes of a multi-view call (see R4D_MODE_* in include/r4d.h)
 MODE_PER_VIEW, MODE_FUSED, MODE_GRAPH = 0, 1, 2
@@ -368,7 +368,8 @@ class SavedState:
                   BUF_VALUES: ((s["n_dup"],), torch.int32),
                   BUF_RANGES: ((s["tiles_x"] * s["tiles_y"], 2), torch.int32),
                   BUF_TFINAL: ((hw,), fdt), BUF_NCONTRIB: ((hw,), torch.int32),
-                  BUF_NEVAL: ((hw,), torch.int32), BUF_FLOW: ((n_gaussians, 2), fdt)}
+                  BUF_NEVAL: ((hw,), torch.int32), BUF_NBLEND: ((hw,), torch.int32),
+                  BUF_FLOW: ((n_gaussians, 2), fdt)}
         shape, dt = shapes[buffer]
         out = torch.empty(shape, dtype=dt, device=self.renderer.device)
         st = _lib.r4d_saved_copy(self.handle, view, buffer, _ptr(out),

@@ -54,6 +54,29 @@ def test_image_2k_full_frame(r4d, scene2k, device):
     assert err <= IMG_TOL
 
 
+def test_blend_and_evaluation_counts_2k(r4d, scene2k, device):
+    """The measurement build's per-pixel counts: Gaussians blended equal the
+    oracle's contributor count on every unambiguous pixel; entries evaluated
+    and entries up to the last contributor bound it from above."""
+    g, views, st, ref = scene2k
+    print("case: 2k scene blend / evaluation counts", flush=True)
+    rend = r4d.Renderer(device)
+    p = to_device(g, device)
+    rend.set_timing(True)
+    imgs, saved = rend.forward(p, views, dict(st, mode="per_view"), save=True)
+    rend.set_timing(False)
+    n = g["opacity"].shape[0]
+    blend = saved.copy(0, r4d.BUF_NBLEND, n).cpu().numpy().astype(np.int64)
+    evals = saved.copy(0, r4d.BUF_NEVAL, n).cpu().numpy().astype(np.int64)
+    ncon = saved.copy(0, r4d.BUF_NCONTRIB, n).cpu().numpy().astype(np.int64)
+    amb = ref["ambiguous"].numpy().reshape(-1)
+    want = ref["n_contrib"].numpy().reshape(-1)
+    print(f"blended pairs {blend.sum()}, evaluated {evals.sum()}, walked {ncon.sum()}")
+    assert np.array_equal(blend[~amb], want[~amb])
+    assert (evals >= ncon).all() and (ncon >= blend).all()
+    assert blend.sum() > 10 * 128 * 128 // 100
+
+
 def test_preprocess_records_2k(r4d, scene2k, device):
     g, views, st, ref = scene2k
     _, _, _, saved = _render(r4d, g, views, st, device)
