@@ -21,12 +21,15 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <set>
 #include <string>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "r4d.h"
 #include "r4d_internal.hpp"
@@ -99,6 +102,8 @@ struct r4d_ctx {
   std::set<r4d_saved*> live_saved;
   std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
   std::map<std::string, std::pair<int, int>> tuned;  // shape -> (tile size, sort items)
+  bool tuned_loaded = false;  // the autotuner's cache file has been read
+  std::string device_tag;     // architecture and compute-unit count (cache keys)
   // pinned readback areas of runs with their completion events; an area is
   // reused once its event has completed
   struct Pinned {
@@ -452,7 +457,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.ranges = take(size_t(p.total_tiles) * 8);
   L.T_final = take(size_t(p.total_pix) * p.scal);
   L.n_contrib = take(size_t(p.total_pix) * 4);
-  L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 4) : 0;
+  L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 8) : 0;
   L.img_copy = take(3 * size_t(p.total_pix) * p.scal);
   L.flow_copy = p.flow ? take(2 * size_t(p.total_pix) * p.scal) : 0;
   L.walk = take(size_t(p.total_tiles) * 4);
@@ -978,16 +983,68 @@ r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
   return R4D_OK;
 }
 
+// ---- the autotuner's choices, kept across processes in a text file of lines
+// "key<TAB>tile size<TAB>sort items" (path: R4D_TUNE_CACHE; unset: under
+// XDG_CACHE_HOME or HOME; empty: nothing is read or written).  Keys carry the
+// cache format, the device and the call shape; unreadable lines are ignored.
+constexpr const char* kTuneVersion = "r4d-tune-1";
+
+std::string tune_cache_path() {
+  if (const char* e = std::getenv("R4D_TUNE_CACHE")) return std::string(e);
+  const char* xdg = std::getenv("XDG_CACHE_HOME");
+  if (xdg && *xdg) return std::string(xdg) + "/r4d/autotune.txt";
+  const char* home = std::getenv("HOME");
+  if (home && *home) return std::string(home) + "/.cache/r4d/autotune.txt";
+  return std::string();
+}
+
+void load_tune_cache(r4d_ctx* ctx) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[4096];
+  while (std::fgets(line, sizeof(line), f)) {
+    char* tab1 = std::strchr(line, '\t');
+    if (!tab1) continue;
+    *tab1 = '\0';
+    int ts = 0, items = -1;
+    if (std::sscanf(tab1 + 1, "%d\t%d", &ts, &items) != 2) continue;
+    if ((ts != 8 && ts != 16 && ts != 32) || (items != 0 && items != 8 && items != 16)) continue;
+    ctx->tuned[std::string(line)] = {ts, items};  // later lines win
+  }
+  std::fclose(f);
+}
+
+void store_tune_cache(const std::string& key, int ts, int items) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  // create the missing directories of the path (errors show up at fopen)
+  for (size_t p = path.find('/', 1); p != std::string::npos; p = path.find('/', p + 1))
+    (void)mkdir(path.substr(0, p).c_str(), 0755);
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;  // the choice still holds for this context
+  std::fprintf(f, "%s\t%d\t%d\n", key.c_str(), ts, items);
+  std::fclose(f);
+}
+
 // ---- autotuner: forward + backward of the call's renders (fused), each
 // candidate (tile size, tile-sort keys per lane) timed twice after a warm-up.
 template <typename T>
 r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, int V,
                     const r4d_settings& base, T* images, bool static3d, hipStream_t stream,
                     int* ts_out, int* items_out) {
-  const std::string key = std::to_string(sizeof(T)) + "|" + std::to_string(int(static3d)) + "|" +
-                          std::to_string(g.n) + "|" +
-                          std::to_string(g.deg) + "|" + std::to_string(base.mode) + "|" +
-                          view_shape_key(views, V);
+  // Gaussian counts in half-octave buckets: a set that densification grows or
+  // prunes a little keeps its choice
+  const int nbucket = g.n > 0 ? int(std::floor(2.0 * std::log2(double(g.n)))) : -1;
+  const std::string key = std::string(kTuneVersion) + "|" + ctx->device_tag + "|" +
+                          std::to_string(sizeof(T)) + "|" + std::to_string(int(static3d)) + "|" +
+                          std::to_string(nbucket) + "|" + std::to_string(g.deg) + "|" +
+                          std::to_string(base.mode) + "|" + view_shape_key(views, V);
+  if (!ctx->tuned_loaded) {
+    load_tune_cache(ctx);
+    ctx->tuned_loaded = true;
+  }
   auto it = ctx->tuned.find(key);
   if (it != ctx->tuned.end()) {
     *ts_out = it->second.first;
@@ -1061,6 +1118,7 @@ r4d_status autotune(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views, 
   ctx_free(ctx, gbuf);
   if (result != R4D_OK) return result;
   ctx->tuned[key] = {best_ts, best_items};
+  store_tune_cache(key, best_ts, best_items);
   *ts_out = best_ts;
   *items_out = best_items;
   return R4D_OK;
@@ -1358,6 +1416,17 @@ r4d_status r4d_create(r4d_ctx** out, int device) {
   if (hipSetDevice(device) != hipSuccess) return R4D_ERR_HIP;
   auto ctx = std::make_unique<r4d_ctx>();
   ctx->device = device;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      char tag[320];
+      snprintf(tag, sizeof(tag), "%s:%d", prop.gcnArchName, prop.multiProcessorCount);
+      ctx->device_tag = tag;
+    } else {
+      (void)hipGetLastError();
+      ctx->device_tag = "unknown";
+    }
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->readback), 2 * kMaxViews * 8,
                     hipHostMallocDefault) != hipSuccess)
     return R4D_ERR_OOM;
@@ -1935,8 +2004,10 @@ r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* ds
       need = n * 2 * scal;
       break;
     case R4D_BUF_NEVAL:
+    case R4D_BUF_NBLEND:
       if (!p.count_evals) return fail(ctx, R4D_ERR_STATE, "evaluation counts need timing enabled");
-      src = F + r->L.n_eval + size_t(sl.pix_base) * 4;
+      // (evaluated, blended) pairs per pixel
+      src = F + r->L.n_eval + size_t(sl.pix_base) * 8 + (buffer == R4D_BUF_NBLEND ? 4 : 0);
       need = hw * 4;
       break;
     default: return fail(ctx, R4D_ERR_INVALID_ARG, "unknown buffer id %d", buffer);
@@ -1949,6 +2020,10 @@ r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* ds
   if (buffer == R4D_BUF_RANGES) {
     R4D_HIP(copy_ranges_rebased(at<uint2>(F, r->L.ranges) + sl.tile_base, uint32_t(ntiles),
                                 tseg.start[vi], static_cast<uint2*>(dst), stream));
+    return R4D_OK;
+  }
+  if (buffer == R4D_BUF_NEVAL || buffer == R4D_BUF_NBLEND) {
+    R4D_HIP(hipMemcpy2DAsync(dst, 4, src, 8, 4, hw, hipMemcpyDeviceToDevice, stream));
     return R4D_OK;
   }
   R4D_HIP(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, stream));

@@ -206,6 +206,65 @@ def test_autotuner_choice_is_valid_and_image_unchanged(r4d, device):
         saved.check()
 
 
+_TUNE_SCRIPT = r"""
+import json, sys, time
+sys.path.insert(0, {root!r})
+sys.path.insert(0, {tests!r})
+import torch
+import paper_2402_03307_amd as r4d
+import workloads as W
+from helpers import to_device
+g, _, st = W.scene_2k()
+views = [W.view((0.0, 0.0, -3.0), 128, 96, 150.0, 0.5),
+         W.view((2.5, -1.0, -2.0), 77, 131, 120.0, 0.2)]
+dev = torch.device("cuda:0")
+rend = r4d.Renderer(dev)
+p = to_device(g, dev)
+torch.cuda.synchronize()
+t0 = time.perf_counter()
+imgs, saved = rend.forward(p, views, dict(st, tile_size=0, mode="fused"))
+saved.check()
+ms = (time.perf_counter() - t0) * 1e3
+print(json.dumps(dict(saved.config(), ms=ms)), flush=True)
+"""
+
+
+def _tune_in_new_process(cache):
+    import json
+    import os
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = _TUNE_SCRIPT.format(root=os.path.dirname(here), tests=here)
+    env = dict(os.environ, R4D_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def test_autotuner_choice_persists_across_processes(tmp_path):
+    """A process that tunes a call shape records the choice in the cache file;
+    a later process with the same shape takes it from there instead of tuning.
+    The recorded choice is rewritten in between, so only a process that read
+    the file can report the rewritten one."""
+    cache = tmp_path / "r4d" / "autotune.txt"
+    print("case: autotuner cache, first process", flush=True)
+    first = _tune_in_new_process(cache)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1, lines
+    key, ts, items = lines[0].split("\t")
+    assert (int(ts), int(items)) == (first["tile_size"], first["sort_items"])
+    assert "gfx" in key
+    forced = (8, 16) if (int(ts), int(items)) != (8, 16) else (32, 0)
+    cache.write_text(f"{key}\t{forced[0]}\t{forced[1]}\n")
+    print("case: autotuner cache, second process", flush=True)
+    second = _tune_in_new_process(cache)
+    print(f"first {first}, second {second}", flush=True)
+    assert (second["tile_size"], second["sort_items"]) == forced
+    assert cache.read_text().splitlines() == [f"{key}\t{forced[0]}\t{forced[1]}"]
+
+
 def test_l1_views_matches_per_view_means(r4d, device):
     views = ragged_views()
     rend = r4d.Renderer(device)
