@@ -93,18 +93,21 @@ def _fp32_scales(g, pre, view):
     """Magnitudes that set the float32 error of each Gaussian's record, from
     the oracle's FP64 intermediates (the record is computed in float32 from
     float32 inputs); a rounding contributes the unit roundoff times them:
-      * p_scale: of the camera-space position.  mu(t) = mu_xyz + (t - mu_t) V / W
-        takes V and W from Sigma_4 = R S^2 R^T, whose entries carry roundings of
-        the magnitudes of their terms (|R| S^2 |R|^T), so (t - mu_t) V / W
-        carries them of |t - mu_t| (|V| + |V| W_terms / W) / W; the sum with
-        mu_xyz, of |mu(t)|; p = M mu(t) + t_w, of |M| |mu(t)| + |t_w|;
+      * p_scale: of the camera-space position.  The rotation R from the
+        normalised rotor has entries of unit scale, each carrying roundings of
+        1 (absolute, however small the entry), so an entry of Sigma_4 =
+        R S^2 R^T, sum_k R_ik R_jk s_k^2, carries them of
+        sum_k (|R_ik| + |R_jk|) s_k^2; mu(t) = mu_xyz + (t - mu_t) V / W then
+        carries them of |t - mu_t| (V_terms + |V| W_terms / W) / W and of
+        |mu(t)|; p = M mu(t) + t_w, of |M| |mu(t)| + |t_w| on top;
       * gamma: cancellation factor of Sigma_3D = U - V V^T / W, the magnitude
         of the terms over the magnitude of the result;
       * kappa: condition number of the (dilated) Sigma_2D, by which the
         inversion to the conic multiplies relative errors."""
     R = pre["R"].detach().numpy()
     s2 = np.exp(2.0 * g["log_scales"].T.astype(np.float64))
-    terms = np.einsum("nik,njk,nk->nij", np.abs(R), np.abs(R), s2)
+    aR = np.abs(R)
+    terms = np.einsum("nik,nk->ni", aR, s2)[:, :, None] + np.einsum("njk,nk->nj", aR, s2)[:, None, :]
     cov4 = np.einsum("nik,njk,nk->nij", R, R, s2)
     V, W = cov4[:, :3, 3], cov4[:, 3, 3]
     dt = np.abs(view["t"] - g["means"][3].astype(np.float64))
