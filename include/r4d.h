@@ -242,6 +242,33 @@ r4d_status r4d_render_backward_f64(r4d_ctx *ctx, const r4d_gaussians_f64 *g,
                                    const r4d_settings *settings, const r4d_saved *saved,
                                    const double *dL_dimages, r4d_grads_f64 *out, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): r4d_render_forward without saved state
+ * (inference), allocating nothing.  Every buffer of the call lives in one
+ * region of R4D_NOALLOC_BYTES that the library reserves statically on each GPU
+ * it runs on (held until the process ends; r4d_create looks up its address).
+ * The caller passes the inputs and `images` as for r4d_render_forward.
+ *   settings  tile_size must be 8, 16 or 32 (the autotuner allocates);
+ *             mode R4D_MODE_FUSED renders all views in one run,
+ *             R4D_MODE_PER_VIEW one view after the other, each in the whole
+ *             region; R4D_MODE_GRAPH is rejected (R4D_ERR_INVALID_ARG).
+ * Images equal those of r4d_render_forward with the same settings.
+ * Limits: the per-Gaussian and per-pixel buffers of a run (about 100 bytes per
+ * Gaussian and 20 per pixel, per view) and its tile lists (about 30 bytes per
+ * tile entry at tile 16) must fit in the region together.  A call whose
+ * Gaussians and pixels do not fit returns R4D_ERR_CAPACITY before launching
+ * anything; one whose tile entries (known after the preprocess, which the call
+ * waits for, like plain mode) do not fit returns R4D_ERR_CAPACITY without
+ * rasterising.  Other errors as r4d_render_forward; a sort failure is reported
+ * by the context's next call.
+ * Every call on one GPU uses that GPU's one region, whatever the context:
+ * calls that overlap on one GPU (other streams, other host threads, other
+ * contexts) race and give wrong images.  Calls on one stream are ordered. */
+#define R4D_NOALLOC_BYTES (256u << 20)
+r4d_status r4d_render_forward_noalloc(r4d_ctx *ctx, const r4d_gaussians *g,
+                                      const r4d_view *views, int n_views,
+                                      const r4d_settings *settings, float *images, void *stream);
+
 /* Speed-field (optical flow) render, Sec. 3.2.2: the sliced mean of a
  * Gaussian moves with speed V / W (V the space-time block of its 4D covariance,
  * W its time variance), so its projected mean moves at

@@ -44,6 +44,7 @@ _MODE_NAMES = {"per_view": MODE_PER_VIEW, "fused": MODE_FUSED, "graph": MODE_GRA
 EXPORTED_SYMBOLS = (
     "r4d_default_settings", "r4d_create", "r4d_destroy", "r4d_render_forward",
     "r4d_render_backward", "r4d_render_forward_f64", "r4d_render_backward_f64",
+    "r4d_render_forward_noalloc",
     "r4d_render_forward_flow", "r4d_render_backward_flow", "r4d_render_forward_flow_f64",
     "r4d_render_backward_flow_f64", "r4d_knn4d", "r4d_consistency4d_loss_grad",
     "r4d_consistency4d_loss_grad_f64", "r4d_default_adam_config", "r4d_adam_step",
@@ -126,6 +127,9 @@ def _load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.r4d_render_forward_noalloc.argtypes = [c_vp, P(_Gaussians), P(_View), ctypes.c_int,
+                                               P(_Settings), c_vp, c_vp]
+    lib.r4d_render_forward_noalloc.restype = ctypes.c_int
     ffwd_args = [c_vp, P(_Gaussians), P(_View), ctypes.c_int, P(_Settings), c_vp, c_vp, P(c_vp),
                  c_vp]
     fbwd_args = [c_vp, P(_Gaussians), P(_View), ctypes.c_int, P(_Settings), c_vp, c_vp, c_vp,
@@ -463,6 +467,31 @@ class Renderer:
             return (out, fout, saved) if flow else (out, saved)
         images = _split(out, views, 3)
         return (images, _split(fout, views, 2), saved) if flow else (images, saved)
+
+    def forward_noalloc(self, params: dict, views, settings: dict | None = None,
+                        out: torch.Tensor | None = None, flat: bool = False):
+        """Inference render through r4d_render_forward_noalloc: no device memory
+        is allocated by the library (every buffer lies in its fixed region).
+        `out`: optional preallocated float32 image buffer (views' [3, H, W]
+        images back to back), so that the call allocates nothing at all."""
+        n, deg, dtype = _check_params(params)
+        if dtype != torch.float32:
+            raise R4DError("the no-allocation forward is float32 only")
+        g = _Gaussians(n, deg, *[_ptr(params[k]) for k in _PARAM_KEYS])
+        varr = _views_array(views)
+        st = _settings_struct(settings)
+        total = sum(3 * int(v["height"]) * int(v["width"]) for v in views)
+        if out is None:
+            out = torch.empty((total,), dtype=dtype, device=self.device)
+        if (out.dtype != dtype or out.device != self.device or not out.is_contiguous()
+                or out.numel() < total):
+            raise R4DError("out must be a contiguous float32 tensor of the images' size "
+                           "on the renderer's device")
+        status = _lib.r4d_render_forward_noalloc(self.handle, ctypes.byref(g), varr, len(views),
+                                                 ctypes.byref(st), _ptr(out),
+                                                 _stream(self.device))
+        self._check(status, "r4d_render_forward_noalloc")
+        return out if flat else _split(out, views, 3)
 
     def backward(self, params: dict, views, settings: dict | None, saved: SavedState,
                  grad_images, grad_flows=None, stats=None) -> dict:

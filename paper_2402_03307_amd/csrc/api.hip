@@ -25,6 +25,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -35,6 +36,38 @@
 #include "r4d_internal.hpp"
 
 using namespace r4d;
+
+// Device memory of r4d_render_forward_noalloc: every buffer of its runs lives
+// in this region, one copy per GPU, held until the process ends.  Host code
+// never passes `scratch` itself to a kernel or a copy (in host code it names a
+// host-side stand-in); it uses the device address that r4d_create looks up on
+// each GPU (noalloc_region).
+constexpr size_t kNoallocBytes = size_t(R4D_NOALLOC_BYTES);
+static __device__ __align__(256) uint8_t scratch[kNoallocBytes];
+
+namespace {
+
+// Device address of `scratch` on each GPU, looked up once per device with that
+// device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+uint8_t* g_noalloc_ptr[kMaxDevices] = {};
+
+hipError_t noalloc_region(int device, uint8_t** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[device] = static_cast<uint8_t*>(p);
+  }
+  *out = g_noalloc_ptr[device];
+  return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -116,6 +149,10 @@ struct r4d_ctx {
   // without saved state, saved states released unchecked); read, without
   // waiting, by the next render call, which reports an overflow or sort failure
   std::vector<Pinned*> unchecked;
+  // no-allocation forward: the device address of this GPU's region and the
+  // readback area of its runs (set up by r4d_create, outside the pinned pool)
+  uint8_t* noalloc = nullptr;
+  Pinned* noalloc_slot = nullptr;
 };
 
 namespace {
@@ -129,6 +166,10 @@ struct RunState {
   uint64_t capacity = 0;
   uint32_t* values = nullptr;  // sorted Gaussian indices of the tile entries
   bool owns_memory = true;     // false for graph runs (buffers live in the entry)
+                               // and for runs in the no-allocation region
+  // no-allocation runs: bytes available to the entries block, which the sized
+  // path checks instead of allocating (0: the block is allocated)
+  size_t entries_limit = 0;
   // per-view counts (valid after `done`)
   std::vector<uint64_t> n_visible, n_dup;
   uint32_t flags[2] = {0, 0};  // overflow, look-back error
@@ -617,9 +658,18 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     L.ckf = L2.ckf;
     L.tstatus = L2.tstatus;
     L.entries_bytes = L2.entries_bytes;
-    r.entries = static_cast<uint8_t*>(ctx_alloc(ctx, L.entries_bytes));
-    if (!r.entries)
-      return fail(ctx, R4D_ERR_OOM, "device allocation of %zu bytes failed", L.entries_bytes);
+    if (r.entries_limit) {
+      // no-allocation run: the entries block is already in place
+      if (L.entries_bytes > r.entries_limit)
+        return fail(ctx, R4D_ERR_CAPACITY,
+                    "%llu tile entries need %zu bytes of tile lists; the no-allocation region "
+                    "has %zu left after the per-Gaussian buffers",
+                    (unsigned long long)cap, L.entries_bytes, r.entries_limit);
+    } else {
+      r.entries = static_cast<uint8_t*>(ctx_alloc(ctx, L.entries_bytes));
+      if (!r.entries)
+        return fail(ctx, R4D_ERR_OOM, "device allocation of %zu bytes failed", L.entries_bytes);
+    }
   }
   uint8_t* E = r.entries;
   auto* ranges = at<uint2>(F, L.ranges);
@@ -1213,6 +1263,88 @@ r4d_status forward_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* vie
   return R4D_OK;
 }
 
+// Waits for the previous no-allocation call's runs to finish (if their status
+// is still unread) and reports its sort failure; its readback area is then free.
+r4d_status settle_noalloc(r4d_ctx* ctx) {
+  r4d_ctx::Pinned* q = ctx->noalloc_slot;
+  if (!q->refs) return R4D_OK;
+  auto it = std::find(ctx->unchecked.begin(), ctx->unchecked.end(), q);
+  if (it != ctx->unchecked.end()) ctx->unchecked.erase(it);
+  q->refs = 0;
+  R4D_HIP(hipEventSynchronize(q->done));
+  return flags_status(ctx, q->host, "the previous no-allocation forward: ");
+}
+
+// Forward without saved state whose buffers all lie in the no-allocation
+// region: one run of every view (fused mode) or one run per view in turn
+// (per-view mode), each sized from its entry count like a plain run.
+template <typename T>
+r4d_status forward_noalloc_impl(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
+                                int n_views, const r4d_settings* settings, T* images,
+                                hipStream_t stream) {
+  if (!views || n_views < 1 || n_views > kMaxViews || !images || !valid_settings(settings))
+    return fail(ctx, R4D_ERR_INVALID_ARG, "invalid views, images or settings");
+  if (settings->tile_size == 0)
+    return fail(ctx, R4D_ERR_INVALID_ARG,
+                "the no-allocation forward needs a tile size (the autotuner allocates)");
+  if (settings->mode == R4D_MODE_GRAPH)
+    return fail(ctx, R4D_ERR_INVALID_ARG, "the no-allocation forward has no graph mode");
+  r4d_status s = check_gaussians(ctx, g);
+  if (s != R4D_OK) return s;
+  for (int i = 0; i < n_views; ++i)
+    if (!valid_view(views[i])) return fail(ctx, R4D_ERR_INVALID_ARG, "invalid view %d", i);
+  if (uint64_t(round_seg(uint64_t(g.n))) * uint64_t(n_views) >= (uint64_t(1) << 32))
+    return fail(ctx, R4D_ERR_CAPACITY, "%d views of %d Gaussians exceed 2^32 sort slots", n_views,
+                g.n);
+  const bool fused = settings->mode == R4D_MODE_FUSED;
+  // the per-Gaussian and per-pixel buffers must fit before anything is launched
+  for (int v = 0; v < (fused ? 1 : n_views); ++v) {
+    const Plan p = make_plan(fused ? views : views + v, fused ? n_views : 1, uint32_t(g.n), g.deg,
+                             *settings, sizeof(T), false, false);
+    const size_t fixed = align256(make_layout(p, 0).fixed_bytes);
+    if (fixed >= kNoallocBytes)
+      return fail(ctx, R4D_ERR_CAPACITY,
+                  "%d Gaussians in %d view(s) need %zu bytes of per-Gaussian and per-pixel "
+                  "buffers; the no-allocation region holds %zu",
+                  g.n, p.V, fixed, kNoallocBytes);
+  }
+  R4D_HIP(hipSetDevice(ctx->device));
+  if ((s = drain_unchecked(ctx, false)) != R4D_OK) return s;
+  if ((s = settle_noalloc(ctx)) != R4D_OK) return s;
+  const SettingsDev st = make_settings(*settings);
+  size_t off = 0;
+  for (int v = 0; v < (fused ? 1 : n_views); ++v) {
+    if (v > 0) {
+      // the previous view's run reads the region until it completes; its
+      // status words are read before this run's readback reuses the area
+      R4D_HIP(hipEventSynchronize(ctx->noalloc_slot->done));
+      if ((s = flags_status(ctx, ctx->noalloc_slot->host, "")) != R4D_OK) return s;
+    }
+    RunState r;
+    r.plan = make_plan(fused ? views : views + v, fused ? n_views : 1, uint32_t(g.n), g.deg,
+                       *settings, sizeof(T), false, false);
+    r.owns_memory = false;
+    attach_slot(r, ctx->noalloc_slot);
+    r.L = make_layout(r.plan, 0);
+    const size_t fixed = align256(r.L.fixed_bytes);
+    r.fixed = ctx->noalloc;
+    r.entries = ctx->noalloc + fixed;
+    r.entries_limit = kNoallocBytes - fixed;
+    if ((s = upload_meta(ctx, r.plan, r.fixed, r.L, stream)) != R4D_OK) return s;
+    if ((s = enqueue_forward<T>(ctx, g, r, images + off, nullptr, st, true, false, stream)) !=
+        R4D_OK)
+      return s;
+    if ((s = finish_run(ctx, r, stream)) != R4D_OK) return s;
+    for (int u = v; u < (fused ? n_views : v + 1); ++u)
+      off += 3 * size_t(views[u].width) * size_t(views[u].height);
+  }
+  // the last run's status words are read by the next call (this entry point's,
+  // any render call of the context, or r4d_check_pending)
+  ctx->noalloc_slot->refs = 1;
+  ctx->unchecked.push_back(ctx->noalloc_slot);
+  return R4D_OK;
+}
+
 // Waits for the forward of a saved state and reports its overflow or sort
 // failure.
 r4d_status check_saved(r4d_ctx* ctx, const r4d_saved* saved) {
@@ -1448,6 +1580,20 @@ r4d_status r4d_create(r4d_ctx** out, int device) {
     r4d_destroy(ctx.release());
     return R4D_ERR_HIP;
   }
+  // the no-allocation forward's region (this device's copy) and readback area
+  if (noalloc_region(device, &ctx->noalloc) != hipSuccess) {
+    (void)hipGetLastError();
+    r4d_destroy(ctx.release());
+    return R4D_ERR_HIP;
+  }
+  ctx->noalloc_slot = new r4d_ctx::Pinned();
+  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->noalloc_slot->host),
+                    (2 * size_t(kMaxViews) + 2) * 8, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->noalloc_slot->done, hipEventDisableTiming) != hipSuccess) {
+    r4d_destroy(ctx.release());
+    return R4D_ERR_OOM;
+  }
+  ctx->unchecked.reserve(64);
   *out = ctx.release();
   return R4D_OK;
 }
@@ -1492,6 +1638,12 @@ void r4d_destroy(r4d_ctx* ctx) {
     delete q;
   }
   ctx->pinned_pool.clear();
+  if (ctx->noalloc_slot) {
+    if (ctx->noalloc_slot->host) (void)hipHostFree(ctx->noalloc_slot->host);
+    if (ctx->noalloc_slot->done) (void)hipEventDestroy(ctx->noalloc_slot->done);
+    delete ctx->noalloc_slot;
+    ctx->noalloc_slot = nullptr;
+  }
   ctx->unchecked.clear();
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->readback) (void)hipHostFree(ctx->readback);
@@ -1505,6 +1657,14 @@ r4d_status r4d_render_forward(r4d_ctx* ctx, const r4d_gaussians* g, const r4d_vi
   if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
   return forward_impl<float>(ctx, gauss_of(g), views, n_views, settings, images, nullptr, saved,
                              static_cast<hipStream_t>(stream));
+}
+
+r4d_status r4d_render_forward_noalloc(r4d_ctx* ctx, const r4d_gaussians* g,
+                                      const r4d_view* views, int n_views,
+                                      const r4d_settings* settings, float* images, void* stream) {
+  if (!ctx || !g) return ctx ? fail(ctx, R4D_ERR_INVALID_ARG, "null argument") : R4D_ERR_INVALID_ARG;
+  return forward_noalloc_impl<float>(ctx, gauss_of(g), views, n_views, settings, images,
+                                     static_cast<hipStream_t>(stream));
 }
 
 r4d_status r4d_render_forward_flow(r4d_ctx* ctx, const r4d_gaussians* g, const r4d_view* views,
