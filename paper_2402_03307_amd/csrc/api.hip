@@ -599,7 +599,10 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   auto* tickets = at<uint32_t>(F, L.tickets);
   uint32_t* status = at<uint32_t>(F, L.status);  // [0] overflow, [1] look-back error
   uint32_t* error = status + 1;
-  R4D_HIP(fill_zero(F + L.zero_begin, L.zero_end - L.zero_begin, stream));
+  // the run's counters and status words: cleared by the preprocess, or here
+  // when there is nothing to preprocess
+  const size_t zero_bytes = L.zero_end - L.zero_begin;
+  if (p.n == 0) R4D_HIP(fill_zero(F + L.zero_begin, zero_bytes, stream));
   const uint32_t* order = nullptr;
   if (p.n > 0) {
     R4D_TIMED(kPreprocessFwd,
@@ -607,8 +610,8 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
                                        p.flow ? at<Vec2<T>>(F, L.flows) : nullptr,
                                        at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
                                        at<uint32_t>(F, L.dkeys), totals, at<uint32_t>(F, L.kA),
-                                       at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd, p.static3d,
-                                       stream));
+                                       at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd,
+                                       F + L.zero_begin, zero_bytes, p.static3d, stream));
   }
   hipEvent_t totals_ready = nullptr;
   if (sized) {
@@ -673,20 +676,23 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   }
   uint8_t* E = r.entries;
   auto* ranges = at<uint2>(F, L.ranges);
-  R4D_HIP(seg_table(totals, p.V, r.capacity, tseg, status, stream));
+  // the segment table of the emitted list (with the count scan when there are Gaussians)
+  if (p.n == 0) R4D_HIP(seg_table(totals, p.V, r.capacity, tseg, status, stream));
   uint32_t* values = at<uint32_t>(E, L.tvA);
   const void* sorted_tiles = nullptr;
   if (p.n > 0) {
     auto* offsets = at<uint64_t>(F, L.offsets);
     R4D_TIMED(kCountScan, count_scan_seg(order, at<uint32_t>(F, L.tiles), totals, p.n, p.n_pad,
-                                         p.V, offsets, F + L.scan_tmp, stream));
+                                         p.V, offsets, F + L.scan_tmp, r.capacity, tseg, status,
+                                         at<uint32_t>(E, L.etemp), stream));
     // packed: (index | high tile byte) words into tvA and low tile bytes into
     // tdig; otherwise tile ids into tkA and indices into tvA
     uint32_t* out_a = p.packed ? at<uint32_t>(E, L.tvA) : at<uint32_t>(E, L.tkA);
     void* out_b = p.packed ? static_cast<void*>(E + L.tdig) : static_cast<void*>(E + L.tvA);
     R4D_TIMED(kEmit, emit_blocks<T>(order, offsets, at<Rect16>(F, L.rects),
                                     at<Rec<T>>(F, L.recs), slots, tseg, p.n, p.n_pad, p.V,
-                                    r.capacity, p.packed, E + L.etemp, out_a, out_b, stream));
+                                    r.capacity, p.packed, E + L.etemp, out_a, out_b,
+                                    p.packed ? E + L.ptemp : nullptr, stream));
     if (p.packed) {
       // low tile byte pass into (tkA, thi), high byte pass into (tvA, t16)
       R4D_TIMED(kTileSort, packed_tile_sort(at<uint32_t>(E, L.tvA), E + L.tdig, tseg,

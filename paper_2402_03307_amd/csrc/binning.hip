@@ -28,6 +28,8 @@
 // wrong) positions instead of hanging.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "r4d_internal.hpp"
 #include "rowwalk.hpp"
 #include "tileset.hpp"
@@ -334,10 +336,9 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
 // the earlier renders' counts, each rounded up to 4096.  When the entries do
 // not fit the capacity (or a render exceeds the per-segment limit) every
 // segment is empty and `overflow` is set.
-__global__ void seg_table_kernel(const unsigned long long* __restrict__ totals, int n_views,
-                                 unsigned long long capacity, SegTable* __restrict__ seg,
-                                 uint32_t* __restrict__ overflow_out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void write_seg_table(const unsigned long long* __restrict__ totals, int n_views,
+                                unsigned long long capacity, SegTable* __restrict__ seg,
+                                uint32_t* __restrict__ overflow_out) {
   unsigned long long total = 0;
   bool too_long = false;
   for (int v = 0; v < n_views; ++v) {
@@ -357,6 +358,13 @@ __global__ void seg_table_kernel(const unsigned long long* __restrict__ totals, 
   seg->count = uint32_t(n_views);
   seg->overflow = overflow ? 1u : 0u;
   if (overflow_out) *overflow_out = overflow ? 1u : 0u;
+}
+
+__global__ void seg_table_kernel(const unsigned long long* __restrict__ totals, int n_views,
+                                 unsigned long long capacity, SegTable* __restrict__ seg,
+                                 uint32_t* __restrict__ overflow_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  write_seg_table(totals, n_views, capacity, seg, overflow_out);
 }
 
 // Exclusive scan input: tile counts of every render's Gaussians in depth order,
@@ -443,21 +451,90 @@ __device__ __forceinline__ bool block_span(const SegTable* seg, uint32_t e0, uin
   return true;
 }
 
-// first[b] = depth position of the Gaussian whose entries hold the first
-// entry of block b (segments start at multiples of the block size).
-__global__ __launch_bounds__(kThreads) void first_gaussian_kernel(
-    const uint64_t* __restrict__ offsets, const SegTable* __restrict__ seg, uint32_t n,
-    uint32_t n_pad, uint32_t* __restrict__ first) {
-  const uint32_t v = blockIdx.y;
-  const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
-  if (seg->overflow || k >= n) return;
-  const size_t row = size_t(v) * n_pad;
-  const uint64_t o0 = offsets[row];
-  const uint32_t a = uint32_t(offsets[row + k] - o0), b = uint32_t(offsets[row + k + 1] - o0);
-  if (a == b) return;
-  const uint32_t sb = seg->start[v] / uint32_t(kChunk);
-  for (uint32_t blk = (a + kChunk - 1) / kChunk; blk * uint32_t(kChunk) < b; ++blk)
-    first[sb + blk] = k;
+// ---- the count scan: offsets[i] = exclusive prefix of the tile counts in depth
+// order (renders back to back, each padded to n_pad), in two launches over
+// tiles of kScanTile elements; the first also writes the segment table of the
+// emitted list (workgroup 0), the second the first Gaussian of every emission
+// block (first_gaussian_kernel's map).  With at most kCountDirectTiles tiles
+// every tile adds up the sums of the tiles before it itself; beyond, the tile
+// sums are scanned in between (device_exclusive_scan).
+constexpr uint32_t kCountDirectTiles = 2048;
+
+__global__ __launch_bounds__(kThreads) void count_sums_kernel(
+    LoadCountGatherSeg ld, uint64_t* __restrict__ tile_sums,
+    const unsigned long long* __restrict__ totals, int n_views, unsigned long long capacity,
+    SegTable* __restrict__ seg, uint32_t* __restrict__ overflow_out) {
+  __shared__ uint64_t s_w[kThreads / 64];
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    write_seg_table(totals, n_views, capacity, seg, overflow_out);
+  const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
+  uint64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) sum += ld(base + j);
+  uint64_t total;
+  block_excl_scan<kThreads>(sum, s_w, &total);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// scanned: exclusive scan of the tile sums, or null (direct: add them here).
+__global__ __launch_bounds__(kThreads) void count_offsets_kernel(
+    LoadCountGatherSeg ld, uint64_t n_elems, const uint64_t* __restrict__ tile_sums,
+    const uint64_t* __restrict__ scanned, const SegTable* __restrict__ seg,
+    uint64_t* __restrict__ offsets, uint32_t* __restrict__ first) {
+  __shared__ uint64_t s_w[kThreads / 64];
+  __shared__ uint64_t s_pre[2];
+  const uint32_t b = blockIdx.x;
+  // the render of this tile (tiles never straddle renders: n_pad is a
+  // multiple of kScanTile) and the tile where the render starts
+  const uint64_t e_first = uint64_t(b) * kScanTile;
+  const uint32_t v = uint32_t(e_first / ld.n_pad);
+  const uint64_t row = uint64_t(v) * ld.n_pad;
+  const uint32_t rt = uint32_t(row / kScanTile);
+  if (scanned) {
+    if (threadIdx.x == 0) {
+      s_pre[0] = scanned[b];
+      s_pre[1] = scanned[rt];
+    }
+  } else {
+    uint64_t pre = 0, pre_row = 0;
+    for (uint32_t t = threadIdx.x; t < b; t += kThreads) {
+      const uint64_t x = tile_sums[t];
+      pre += x;
+      pre_row += t < rt ? x : 0ull;
+    }
+    uint64_t tot;
+    block_excl_scan<kThreads>(pre, s_w, &tot);
+    if (threadIdx.x == 0) s_pre[0] = tot;
+    block_excl_scan<kThreads>(pre_row, s_w, &tot);
+    if (threadIdx.x == 0) s_pre[1] = tot;
+  }
+  const uint64_t base = e_first + uint64_t(threadIdx.x) * kScanItems;
+  uint64_t x[kScanItems];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    x[j] = ld(base + j);
+    sum += x[j];
+  }
+  uint64_t total;
+  uint64_t run = block_excl_scan<kThreads>(sum, s_w, &total) + s_pre[0];
+  const uint64_t o0 = s_pre[1];  // offsets[row]: where the render's entries start
+  const bool map = !seg->overflow && v < seg->count;
+  const uint32_t sb = map ? seg->start[v] / uint32_t(kChunk) : 0u;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const uint64_t i = base + j;
+    if (i < n_elems) offsets[i] = run;
+    // the Gaussian at depth position k holds entries [a, b) of its render;
+    // it starts block blk when blk * kChunk lies in [a, b)
+    const uint32_t k = uint32_t(i - row);
+    if (map && i < n_elems && k < ld.n && x[j] != 0) {
+      const uint32_t a = uint32_t(run - o0), e = uint32_t(run + x[j] - o0);
+      for (uint32_t blk = (a + kChunk - 1) / kChunk; blk * uint32_t(kChunk) < e; ++blk)
+        first[sb + blk] = k;
+    }
+    run += x[j];
+  }
 }
 
 // Emission of the tile entries, one block of 4096 entries (in emission order:
@@ -476,9 +553,12 @@ __global__ __launch_bounds__(kThreads) void emit_block_kernel(
     const Rect16* __restrict__ rects, const Rec<T>* __restrict__ recs,
     const ViewSlot* __restrict__ slots, const SegTable* __restrict__ seg,
     const uint32_t* __restrict__ first, uint32_t n, uint32_t n_pad, uint32_t* __restrict__ out_a,
-    void* __restrict__ out_b) {
+    void* __restrict__ out_b, uint32_t* __restrict__ lo_counts) {
+  // (packed: the low tile bytes as bytes, so that more workgroups fit a CU)
+  using BType = typename std::conditional<PACKED, uint8_t, uint32_t>::type;
   __shared__ uint32_t s_a[kChunk];
-  __shared__ uint32_t s_b[kChunk];
+  __shared__ BType s_b[kChunk];
+  __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_first[kThreads];
   __shared__ float s_geo[6][kThreads];
   __shared__ int s_x0[kThreads], s_x1[kThreads], s_y0[kThreads];
@@ -487,9 +567,14 @@ __global__ __launch_bounds__(kThreads) void emit_block_kernel(
   __shared__ uint32_t s_ga;
   const int tid = threadIdx.x;
   const uint32_t b = blockIdx.x;
+  // packed: the block's low-tile-byte counts, the tile sort's first histogram
+  const bool count = PACKED && lo_counts;
+  if (count) s_hist[tid] = 0u;
   uint32_t s, sstart, nvalid;
-  if (seg->overflow || !block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid)
+  if (seg->overflow || !block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid) || !nvalid) {
+    if (count) lo_counts[size_t(b) * 256 + tid] = 0u;
     return;
+  }
   const uint32_t lo = b * uint32_t(kChunk) - sstart, hi = lo + nvalid;  // render-local entries
   const size_t row = size_t(s) * n_pad;
   const uint64_t o0 = offsets[row];
@@ -562,7 +647,7 @@ __global__ __launch_bounds__(kThreads) void emit_block_kernel(
           const uint32_t tile = t0 + j;
           if (PACKED) {
             s_a[j - lo] = gi | ((tile >> 8) << 24);
-            s_b[j - lo] = tile & 255u;
+            s_b[j - lo] = BType(tile & 255u);
           } else {
             s_a[j - lo] = tile;
             s_b[j - lo] = gi;
@@ -579,10 +664,12 @@ __global__ __launch_bounds__(kThreads) void emit_block_kernel(
   const uint32_t e0 = b * uint32_t(kChunk);
   for (uint32_t q = tid; q < nvalid; q += kThreads) {
     out_a[e0 + q] = s_a[q];
-    if (PACKED)
-      static_cast<uint8_t*>(out_b)[e0 + q] = uint8_t(s_b[q]);
-    else
-      static_cast<uint32_t*>(out_b)[e0 + q] = s_b[q];
+    static_cast<BType*>(out_b)[e0 + q] = s_b[q];
+    if (count) atomicAdd(&s_hist[uint32_t(s_b[q]) & 255u], 1u);
+  }
+  if (count) {
+    __syncthreads();
+    lo_counts[size_t(b) * 256 + tid] = s_hist[tid];
   }
 }
 
@@ -1018,29 +1105,29 @@ template <typename T>
 hipError_t emit_blocks(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
                        const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg, uint32_t n,
                        uint32_t n_pad, int n_views, uint64_t capacity, bool packed, void* temp,
-                       uint32_t* out_a, void* out_b, hipStream_t stream) {
+                       uint32_t* out_a, void* out_b, void* sort_temp, hipStream_t stream) {
   const uint32_t blocks = uint32_t((capacity + kChunk - 1) / kChunk);
   if (n == 0 || n_views <= 0 || blocks == 0) return hipSuccess;
-  uint32_t* first = static_cast<uint32_t*>(temp);
-  hipLaunchKernelGGL(first_gaussian_kernel, dim3((n + kThreads - 1) / kThreads, uint32_t(n_views)),
-                     dim3(kThreads), 0, stream, offsets, seg, n, n_pad, first);
+  const uint32_t* first = static_cast<const uint32_t*>(temp);  // written by the count scan
   if (packed)
     hipLaunchKernelGGL((emit_block_kernel<T, true>), dim3(blocks), dim3(kThreads), 0, stream,
-                       order, offsets, rects, recs, slots, seg, first, n, n_pad, out_a, out_b);
+                       order, offsets, rects, recs, slots, seg, first, n, n_pad, out_a, out_b,
+                       static_cast<uint32_t*>(sort_temp));
   else
     hipLaunchKernelGGL((emit_block_kernel<T, false>), dim3(blocks), dim3(kThreads), 0, stream,
-                       order, offsets, rects, recs, slots, seg, first, n, n_pad, out_a, out_b);
+                       order, offsets, rects, recs, slots, seg, first, n, n_pad, out_a, out_b,
+                       (uint32_t*)nullptr);
   return hipGetLastError();
 }
 
 template hipError_t emit_blocks<float>(const uint32_t*, const uint64_t*, const Rect16*,
                                        const Rec<float>*, const ViewSlot*, const SegTable*,
                                        uint32_t, uint32_t, int, uint64_t, bool, void*, uint32_t*,
-                                       void*, hipStream_t);
+                                       void*, void*, hipStream_t);
 template hipError_t emit_blocks<double>(const uint32_t*, const uint64_t*, const Rect16*,
                                         const Rec<double>*, const ViewSlot*, const SegTable*,
                                         uint32_t, uint32_t, int, uint64_t, bool, void*, uint32_t*,
-                                        void*, hipStream_t);
+                                        void*, void*, hipStream_t);
 
 hipError_t tile_ranges(const void* sorted_tiles, bool tiles16, const SegTable* seg,
                        const ViewSlot* slots, uint32_t total_tiles, uint64_t capacity,
@@ -1085,16 +1172,34 @@ hipError_t scan_u32(const uint32_t* a, uint32_t n, uint32_t* out, void* temp, hi
 }
 
 size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views) {
-  return (scan_temp_elems(uint64_t(n_pad) * uint64_t(n_views) + 1) + 2) * sizeof(uint64_t);
+  const uint64_t tiles = (uint64_t(n_pad) * uint64_t(n_views) + 1 + kScanTile - 1) / kScanTile;
+  return (2 * tiles + scan_temp_elems(tiles) + 2) * sizeof(uint64_t);
 }
 
 hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
                           const unsigned long long* totals, uint32_t n, uint32_t n_pad,
-                          int n_views, uint64_t* offsets, void* temp, hipStream_t stream) {
+                          int n_views, uint64_t* offsets, void* temp, unsigned long long capacity,
+                          SegTable* seg, uint32_t* overflow_out, uint32_t* first,
+                          hipStream_t stream) {
   const uint64_t total = uint64_t(n_pad) * uint64_t(n_views);
-  return device_exclusive_scan<uint64_t, LoadCountGatherSeg>(
-      LoadCountGatherSeg{order, counts, totals, n, n_pad, total}, offsets, total + 1,
-      static_cast<uint64_t*>(temp), stream);
+  const uint64_t n_elems = total + 1;
+  const uint64_t tiles = (n_elems + kScanTile - 1) / kScanTile;
+  const LoadCountGatherSeg ld{order, counts, totals, n, n_pad, total};
+  uint64_t* sums = static_cast<uint64_t*>(temp);
+  uint64_t* scanned = sums + tiles;
+  hipLaunchKernelGGL(count_sums_kernel, dim3(uint32_t(tiles)), dim3(kThreads), 0, stream, ld,
+                     sums, totals, n_views, capacity, seg, overflow_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const bool direct = tiles <= kCountDirectTiles;
+  if (!direct) {
+    e = device_exclusive_scan<uint64_t, LoadT<uint64_t>>(LoadT<uint64_t>{sums, tiles}, scanned,
+                                                         tiles, scanned + tiles, stream);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(count_offsets_kernel, dim3(uint32_t(tiles)), dim3(kThreads), 0, stream, ld,
+                     n_elems, sums, direct ? nullptr : scanned, seg, offsets, first);
+  return hipGetLastError();
 }
 
 bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view) {
@@ -1133,7 +1238,7 @@ hipError_t packed_tile_sort(const uint32_t* packed, const uint8_t* digits, const
   uint32_t* M2 = T1 + size_t(stripes) * 256;
   uint32_t* P2 = M2 + size_t(rows) * 256;
   uint32_t* T2 = P2 + size_t(rows + 1) * 256;
-  hipLaunchKernelGGL(lo_count_kernel, dim3(rows), dim3(kThreads), 0, stream, digits, seg, M1);
+  // (the emission wrote M1, the low-byte counts of its blocks)
   hipError_t e = col_scan(M1, rows, P1, T1, stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(lo_pass_kernel, dim3(rows), dim3(kThreads), 0, stream, packed, digits, seg,

@@ -62,13 +62,17 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     GaussPtrs<T> g, const ViewSlot* __restrict__ slots, SettingsDev st, uint32_t n_pad,
     Rec<T>* __restrict__ recs, Vec2<T>* __restrict__ flows, Rect16* __restrict__ rects,
     uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_keys,
-    ulonglong2* __restrict__ block_totals) {
+    ulonglong2* __restrict__ block_totals, uint4* __restrict__ zero, uint64_t zero16) {
   __shared__ unsigned long long s_tot[2][kBlock / 64];
   __shared__ uint32_t s_cnt[kBlock];
   __shared__ int s_x0[kBlock], s_x1[kBlock], s_y0[kBlock], s_y1[kBlock];
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int vi = blockIdx.y;
+  // the run's counters and status words, cleared here for the later stages
+  for (uint64_t z = (uint64_t(blockIdx.y) * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
+       z < zero16; z += uint64_t(gridDim.x) * gridDim.y * kBlock)
+    zero[z] = make_uint4(0u, 0u, 0u, 0u);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const ViewDev v = slots[vi].v;
   const int sh = __builtin_ctz(unsigned(v.tile_size));
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     depth_keys[size_t(vi) * n_pad + i] = vis ? __float_as_uint(depth) : 0xffffffffu;
   }
   // block totals of visible Gaussians and tile entries, written per block and
-  // summed by totals_kernel (atomics on two addresses from every block would
+  // summed by the compaction (atomics on two addresses from every block would
   // serialise)
   unsigned long long c = my_cnt;
 #pragma unroll
@@ -207,58 +211,61 @@ __device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long
   return before + incl - x;
 }
 
-// Per render (one workgroup each): totals[2v] = visible Gaussians, totals[2v +
-// 1] = tile entries (sums of the block totals), vis_prefix[v][b] = visible
-// Gaussians of the render's blocks before b, dseg->len[v] = totals[2v].
-__global__ __launch_bounds__(kBlock) void totals_kernel(const ulonglong2* __restrict__ block_totals,
-                                                         uint32_t blocks,
-                                                         unsigned long long* __restrict__ totals,
-                                                         uint32_t* __restrict__ vis_prefix,
-                                                         SegTable* __restrict__ dseg) {
-  __shared__ unsigned long long s_w[kBlock / 64];
-  const uint32_t v = blockIdx.x;
-  unsigned long long run = 0, mine = 0;  // visible so far; this thread's share of the entries
-  for (uint32_t b0 = 0; b0 < blocks; b0 += kBlock) {
-    const uint32_t b = b0 + threadIdx.x;
-    ulonglong2 t = make_ulonglong2(0ull, 0ull);
-    if (b < blocks) t = block_totals[size_t(v) * blocks + b];
-    unsigned long long tot;
-    const unsigned long long ex = block_excl_scan(t.x, s_w, &tot);
-    if (b < blocks) vis_prefix[size_t(v) * blocks + b] = uint32_t(run + ex);
-    run += tot;
-    mine += t.y;
-  }
-  unsigned long long entries;
-  block_excl_scan(mine, s_w, &entries);
-  if (threadIdx.x == 0) {
-    totals[2 * v] = run;
-    totals[2 * v + 1] = entries;
-    dseg->len[v] = uint32_t(run);
-  }
-}
-
-// Compaction of the visible Gaussians' depth keys (index order kept): block b
-// of render v writes its visible ones from vis_prefix[v][b] on.
+// Compaction of the visible Gaussians' depth keys (index order kept), and the
+// per-render totals.  Block b of render v adds up the block totals of the
+// render's earlier blocks itself (a few loads per thread, no separate scan
+// launch), writes its visible Gaussians from there on, and the render's last
+// block writes totals[2v] = visible Gaussians, totals[2v + 1] = tile entries
+// and dseg->len[v] = totals[2v].
 __global__ __launch_bounds__(kBlock) void compact_keys_kernel(
     const uint32_t* __restrict__ depth_keys, uint32_t n, uint32_t n_pad,
-    const uint32_t* __restrict__ vis_prefix, uint32_t* __restrict__ vis_keys,
+    const ulonglong2* __restrict__ block_totals, unsigned long long* __restrict__ totals,
+    SegTable* __restrict__ dseg, uint32_t* __restrict__ vis_keys,
     uint32_t* __restrict__ vis_index) {
   __shared__ uint32_t s_cnt[kBlock / 64];
-  const uint32_t v = blockIdx.y;
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  __shared__ unsigned long long s_sum[2][kBlock / 64];
+  const uint32_t v = blockIdx.y, b = blockIdx.x, nb = gridDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool last = b + 1 == nb;
+  const ulonglong2* bt = block_totals + size_t(v) * nb;
+  unsigned long long before = 0, entries = 0;
+  for (uint32_t j = threadIdx.x; j < (last ? nb : b); j += kBlock) {
+    const ulonglong2 t = bt[j];
+    before += j < b ? t.x : 0ull;
+    entries += t.y;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    before += __shfl_xor(before, off, 64);
+    entries += __shfl_xor(entries, off, 64);
+  }
+  const uint32_t i = b * kBlock + threadIdx.x;
   const uint32_t key = i < n ? depth_keys[size_t(v) * n_pad + i] : 0xffffffffu;
   const bool vis = key != 0xffffffffu;
   const unsigned long long m = __ballot(vis);
-  if (lane == 0) s_cnt[wave] = uint32_t(__popcll(m));
+  if (lane == 0) {
+    s_cnt[wave] = uint32_t(__popcll(m));
+    s_sum[0][wave] = before;
+    s_sum[1][wave] = entries;
+  }
   __syncthreads();
-  uint32_t pos = vis_prefix[size_t(v) * gridDim.x + blockIdx.x] +
-                 uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
+  unsigned long long start = 0, all_entries = 0;
+  uint32_t mine = uint32_t(__popcll(m & ((1ull << lane) - 1ull))), in_block = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) pos += w < wave ? s_cnt[w] : 0u;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    start += s_sum[0][w];
+    all_entries += s_sum[1][w];
+    mine += w < wave ? s_cnt[w] : 0u;
+    in_block += s_cnt[w];
+  }
   if (vis) {
-    vis_keys[size_t(v) * n_pad + pos] = key;
-    vis_index[size_t(v) * n_pad + pos] = i;
+    vis_keys[size_t(v) * n_pad + start + mine] = key;
+    vis_index[size_t(v) * n_pad + start + mine] = i;
+  }
+  if (last && threadIdx.x == 0) {
+    totals[2 * v] = start + in_block;
+    totals[2 * v + 1] = all_entries;
+    dseg->len[v] = uint32_t(start + in_block);
   }
 }
 
@@ -351,30 +358,32 @@ hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
                                  Vec2<T>* flows, Rect16* rects, uint32_t* tiles_touched,
                                  uint32_t* depth_keys, unsigned long long* totals,
                                  uint32_t* vis_keys, uint32_t* vis_index, SegTable* dseg,
-                                 void* temp, bool static3d, hipStream_t stream) {
+                                 void* temp, void* zero, size_t zero_bytes, bool static3d,
+                                 hipStream_t stream) {
   if (g.n <= 0 || n_views <= 0) return hipSuccess;
+  if ((zero_bytes & 15u) || (reinterpret_cast<uintptr_t>(zero) & 15u))
+    return hipErrorInvalidValue;
   const uint32_t blocks = uint32_t((g.n + kBlock - 1) / kBlock);
   const dim3 grid(blocks, uint32_t(n_views));
   ulonglong2* block_totals = static_cast<ulonglong2*>(temp);
-  uint32_t* vis_prefix = reinterpret_cast<uint32_t*>(block_totals + size_t(blocks) * n_views);
+  uint4* z = static_cast<uint4*>(zero);
+  const uint64_t z16 = zero_bytes / 16;
   if (static3d) {
     if (flows) return hipErrorInvalidValue;  // static Gaussians do not move
     R4D_DEG_DISPATCH(preprocess_fwd_kernel, true, grid, g, slots, st, n_pad, recs, flows, rects,
-                     tiles_touched, depth_keys, block_totals)
+                     tiles_touched, depth_keys, block_totals, z, z16)
   } else {
     R4D_DEG_DISPATCH(preprocess_fwd_kernel, false, grid, g, slots, st, n_pad, recs, flows, rects,
-                     tiles_touched, depth_keys, block_totals)
+                     tiles_touched, depth_keys, block_totals, z, z16)
   }
-  hipLaunchKernelGGL(totals_kernel, dim3(uint32_t(n_views)), dim3(kBlock), 0, stream, block_totals,
-                     blocks, totals, vis_prefix, dseg);
   hipLaunchKernelGGL(compact_keys_kernel, grid, dim3(kBlock), 0, stream, depth_keys, uint32_t(g.n),
-                     n_pad, vis_prefix, vis_keys, vis_index);
+                     n_pad, block_totals, totals, dseg, vis_keys, vis_index);
   return hipGetLastError();
 }
 
 size_t preprocess_temp_bytes(uint32_t n, int n_views) {
   const size_t blocks = size_t((n + kBlock - 1) / kBlock) * size_t(n_views);
-  return blocks * (sizeof(ulonglong2) + sizeof(uint32_t));
+  return blocks * sizeof(ulonglong2);
 }
 
 template <typename T>
@@ -420,7 +429,8 @@ hipError_t launch_preprocess_bwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
                                                const SettingsDev&, uint32_t, Rec<T>*, Vec2<T>*, \
                                                Rect16*, uint32_t*, uint32_t*,                  \
                                                unsigned long long*, uint32_t*, uint32_t*,      \
-                                               SegTable*, void*, bool, hipStream_t);           \
+                                               SegTable*, void*, void*, size_t, bool,          \
+                                               hipStream_t);                                   \
   template hipError_t launch_preprocess_bwd<T>(const GaussPtrs<T>&, const ViewSlot*, int,      \
                                                const SettingsDev&, const double*, bool, bool,  \
                                                const GradPtrs<T>&, hipStream_t);

@@ -63,7 +63,8 @@ struct SegTable {
 // index order, to vis_keys / vis_index at [v * n_pad + 0 .. totals[2v]), and
 // dseg->len[v] = totals[2v] (the depth sort sorts only them).  flows
 // (nullable): [v][n] 2D flow of each visible Gaussian.  temp:
-// preprocess_temp_bytes(n, n_views).
+// preprocess_temp_bytes(n, n_views).  zero / zero_bytes (16-byte aligned and
+// sized): memory the preprocess clears for the later stages of the run.
 size_t preprocess_temp_bytes(uint32_t n, int n_views);
 template <typename T>
 hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, int n_views,
@@ -71,7 +72,8 @@ hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
                                  Vec2<T>* flows, Rect16* rects, uint32_t* tiles_touched,
                                  uint32_t* depth_keys, unsigned long long* totals,
                                  uint32_t* vis_keys, uint32_t* vis_index, SegTable* dseg,
-                                 void* temp, bool static3d, hipStream_t stream);
+                                 void* temp, void* zero, size_t zero_bytes, bool static3d,
+                                 hipStream_t stream);
 
 // grad2d: [V][n][C] double (Gaussian-major), C = 9 (mean2 x, y, Sigma_2D (0,0),
 // (0,1), (1,1), opacity_t, r, g, b) or, with flow, 11 (then flow x, y).  Writes the parameter
@@ -118,22 +120,29 @@ size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
 // offsets[v * n_pad + k] = sum over renders u < v of all their entries plus the
 // entries of render v's Gaussians order[v][0..k-1]; offsets[V * n_pad] = total.
 // order[v] holds render v's totals[2v] visible Gaussians (the rest is unset).
+// Also writes the segment table of the emitted list (as seg_table, for
+// `capacity`) and first[b], the depth position of the Gaussian whose entries
+// hold the first entry of emission block b (emit_blocks' temp).
 hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
                           const unsigned long long* totals, uint32_t n, uint32_t n_pad,
-                          int n_views, uint64_t* offsets, void* temp, hipStream_t stream);
+                          int n_views, uint64_t* offsets, void* temp, unsigned long long capacity,
+                          SegTable* seg, uint32_t* overflow_out, uint32_t* first,
+                          hipStream_t stream);
 
 // Emission of every render's tile entries in depth order (each Gaussian's
 // tiles row by row, its row runs from tileset.hpp) into its segment, one
 // 4096-entry block per workgroup.  packed: out_a[e] = Gaussian index |
 // (tile >> 8) << 24 and out_b[e] = tile & 255 (bytes), the packed sort's
 // input; otherwise out_a[e] = tile id, out_b[e] = Gaussian index (words).
-// temp: emit_temp_bytes(capacity).
+// temp: emit_temp_bytes(capacity), holding the first-Gaussian map of the count
+// scan.  packed: sort_temp is packed_tile_sort's temp, where the emission
+// writes the low-byte digit counts of its blocks (the sort's first histogram).
 size_t emit_temp_bytes(uint64_t capacity);
 template <typename T>
 hipError_t emit_blocks(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
                        const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg, uint32_t n,
                        uint32_t n_pad, int n_views, uint64_t capacity, bool packed, void* temp,
-                       uint32_t* out_a, void* out_b, hipStream_t stream);
+                       uint32_t* out_a, void* out_b, void* sort_temp, hipStream_t stream);
 
 // Tile ranges (ranges[tile_base + t] = [start, end) in the emitted list, [0, 0)
 // for a tile without entries) from every segment's sorted tile ids (16 or 32
