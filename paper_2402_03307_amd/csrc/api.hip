@@ -495,7 +495,6 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.thist = take(3 * size_t(kMaxViews) * 256 * 4);
   L.offsets = take((V * np + 1) * 8);
   L.scan_tmp = take(count_scan_seg_temp_bytes(p.n_pad, p.V));
-  L.ranges = take(size_t(p.total_tiles) * 8);
   L.T_final = take(size_t(p.total_pix) * p.scal);
   L.n_contrib = take(size_t(p.total_pix) * 4);
   L.n_eval = p.count_evals ? take(size_t(p.total_pix) * 8) : 0;
@@ -504,6 +503,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.walk = take(size_t(p.total_tiles) * 4);
   L.ptemp_fwd = take(preprocess_temp_bytes(p.n, p.V));
   L.zero_begin = off;
+  L.ranges = take(size_t(p.total_tiles) * 8);  // tiles without entries keep [0, 0)
   // status words (overflow, sort look-back error) followed by the per-render
   // totals, so that one copy returns all a run reports
   L.status = take(16 + 2 * size_t(kMaxViews) * 8);

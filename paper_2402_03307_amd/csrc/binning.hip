@@ -1132,9 +1132,6 @@ template hipError_t emit_blocks<double>(const uint32_t*, const uint64_t*, const 
 hipError_t tile_ranges(const void* sorted_tiles, bool tiles16, const SegTable* seg,
                        const ViewSlot* slots, uint32_t total_tiles, uint64_t capacity,
                        uint2* ranges, hipStream_t stream) {
-  // (the ranges buffer is allocated in 256-byte units)
-  hipError_t e = fill_zero(ranges, (size_t(total_tiles) * sizeof(uint2) + 15) & ~size_t(15), stream);
-  if (e != hipSuccess) return e;
   const uint32_t blocks = uint32_t((capacity + kChunk - 1) / kChunk);
   if (blocks == 0) return hipSuccess;
   if (tiles16)

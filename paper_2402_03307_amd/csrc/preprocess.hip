@@ -63,9 +63,15 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     Rec<T>* __restrict__ recs, Vec2<T>* __restrict__ flows, Rect16* __restrict__ rects,
     uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_keys,
     ulonglong2* __restrict__ block_totals, uint4* __restrict__ zero, uint64_t zero16) {
+  // per-Gaussian aggregates of the row walk, in kCopies copies picked by the
+  // row's lane (consecutive rows of one Gaussian sit in consecutive lanes, so
+  // its atomics spread over the copies instead of piling onto one address);
+  // copies kStride words apart, so that one slot's copies fall in different banks
+  constexpr int kCopies = 4, kStride = kBlock + 1;
   __shared__ unsigned long long s_tot[2][kBlock / 64];
-  __shared__ uint32_t s_cnt[kBlock];
-  __shared__ int s_x0[kBlock], s_x1[kBlock], s_y0[kBlock], s_y1[kBlock];
+  __shared__ uint32_t s_cnt[kCopies * kStride];
+  __shared__ int s_x0[kCopies * kStride], s_x1[kCopies * kStride], s_y0[kCopies * kStride],
+      s_y1[kCopies * kStride];
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int vi = blockIdx.y;
@@ -132,15 +138,19 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
   }
   // tile entries and the runs' bounding box: the rows of the wavefront's
   // Gaussians walked together, aggregated per Gaussian in LDS
-  s_cnt[threadIdx.x] = 0u;
-  s_x0[threadIdx.x] = 0x7fffffff;
-  s_x1[threadIdx.x] = 0;
-  s_y0[threadIdx.x] = 0x7fffffff;
-  s_y1[threadIdx.x] = 0;
+#pragma unroll
+  for (int c = 0; c < kCopies; ++c) {
+    const int q = c * kStride + int(threadIdx.x);
+    s_cnt[q] = 0u;
+    s_x0[q] = 0x7fffffff;
+    s_x1[q] = 0;
+    s_y0[q] = 0x7fffffff;
+    s_y1[q] = 0;
+  }
   __syncthreads();
   wave_rows(sg, bx.y0, bx.y1, lane, [&](bool ok, int o, int y, int x0, int x1) {
     if (ok && x0 < x1) {
-      const int slot = wave * 64 + o;
+      const int slot = (lane & (kCopies - 1)) * kStride + wave * 64 + o;
       atomicAdd(&s_cnt[slot], uint32_t(x1 - x0));
       atomicMin(&s_x0[slot], x0);
       atomicMax(&s_x1[slot], x1);
@@ -149,15 +159,25 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     }
   });
   __syncthreads();
-  const uint32_t my_cnt = s_cnt[threadIdx.x];
+  uint32_t my_cnt = 0;
+  int ax0 = 0x7fffffff, ax1 = 0, ay0 = 0x7fffffff, ay1 = 0;
+#pragma unroll
+  for (int c = 0; c < kCopies; ++c) {
+    const int q = c * kStride + int(threadIdx.x);
+    my_cnt += s_cnt[q];
+    ax0 = min(ax0, s_x0[q]);
+    ax1 = max(ax1, s_x1[q]);
+    ay0 = min(ay0, s_y0[q]);
+    ay1 = max(ay1, s_y1[q]);
+  }
   const bool vis = my_cnt > 0u;
   if (i < n) {
     Rect16 rc = {0, 0, 0, 0};
     if (vis) {
-      rc.x0 = uint16_t(s_x0[threadIdx.x]);
-      rc.x1 = uint16_t(s_x1[threadIdx.x]);
-      rc.y0 = uint16_t(s_y0[threadIdx.x]);
-      rc.y1 = uint16_t(s_y1[threadIdx.x]);
+      rc.x0 = uint16_t(ax0);
+      rc.x1 = uint16_t(ax1);
+      rc.y0 = uint16_t(ay0);
+      rc.y1 = uint16_t(ay1);
     }
     rects[row + i] = rc;
     tiles_touched[row + i] = my_cnt;

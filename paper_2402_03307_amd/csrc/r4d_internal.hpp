@@ -146,7 +146,8 @@ hipError_t emit_blocks(const uint32_t* order, const uint64_t* offsets, const Rec
 
 // Tile ranges (ranges[tile_base + t] = [start, end) in the emitted list, [0, 0)
 // for a tile without entries) from every segment's sorted tile ids (16 or 32
-// bits).
+// bits).  ranges must be zero on entry (only the tiles with entries are
+// written).
 hipError_t tile_ranges(const void* sorted_tiles, bool tiles16, const SegTable* seg,
                        const ViewSlot* slots, uint32_t total_tiles, uint64_t capacity,
                        uint2* ranges, hipStream_t stream);
