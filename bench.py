@@ -403,6 +403,37 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
+def stage_alg_bytes(n, k, renders, packed=True):
+    """Algorithmic HBM bytes per launch of the memory-bound stages of one run.
+    n Gaussians, k SH coefficients per channel; renders: (visible Gaussians,
+    tile entries, tiles) of each render in the run.  Every render reads the
+    parameters once; the preprocess backward reads them once for the run."""
+    V = len(renders)
+    vis = sum(r[0] for r in renders)
+    D = sum(r[1] for r in renders)
+    tiles = sum(r[2] for r in renders)
+    return {
+        # params 68 B/Gaussian + per-Gaussian outputs (box 8, count 4, key 4)
+        # + SH (12k B), record (48 B) and compacted key/index (8 B) of each visible one
+        "preprocess_fwd": V * n * (68 + 16) + vis * (12 * k + 48 + 8),
+        # visible keys only: 4 passes x (read + write of 8 B key/index pairs) + histogram
+        "depth_sort": vis * (4 * 16 + 4),
+        # order + gathered count read, 8 B offset written per Gaussian
+        "count_scan": V * (n * 4 * 2 + n * 8),
+        # per visible Gaussian order 4 + offset 8 + box 8 + record 32 B read; per
+        # entry the packed word + low tile byte (5 B) or the (tile, index) pair (8 B)
+        "emit": vis * 52 + D * (5 if packed else 8),
+        # low pass (5 in, 5 out) + high byte count (1) + high pass (5 in; index 4
+        # + 16-bit tile 2 out) per entry, the emission's low byte counts aside
+        "tile_sort": D * 22,
+        # sorted 16-bit tile ids read; ranges written, and cleared by the preprocess
+        "tile_ranges": D * 2 + tiles * 16,
+        # params + screen-space gradients (9 doubles per render) read, 17 + 3k
+        # gradients written
+        "preprocess_bwd": n * (68 + 12 * k) + V * n * 72 + n * 4 * (17 + 3 * k),
+    }
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed counter summary, if
     it was taken from the current kernel sources (else None)."""
@@ -490,27 +521,7 @@ def main():
     n_vis, D = stats["n_visible"], stats["n_dup"]
     k = (g["sh_degree"] + 1) ** 2
     tiles = stats["tiles_x"] * stats["tiles_y"]
-    # algorithmic HBM bytes per launch of the memory-bound stages
-    packed = True  # the default tile sort (sort_items 0) on renders of <= 65536 tiles
-    alg_bytes = {
-        # params 68 B/Gaussian + per-Gaussian outputs (box 8, count 4, key 4)
-        # + SH (12k B), record (48 B) and compacted key/index (8 B) of each visible one
-        "preprocess_fwd": n * (68 + 16) + n_vis * (12 * k + 48 + 8),
-        # visible keys only: 4 passes x (read + write of 8 B key/index pairs) + histogram
-        "depth_sort": n_vis * (4 * 16 + 4),
-        # order + gathered count read, 8 B offset written per Gaussian
-        "count_scan": n * 4 * 2 + n * 8,
-        # per visible Gaussian order 4 + offset 8 + box 8 + record 32 B read; per
-        # entry the packed word + low tile byte (5 B) or the (tile, index) pair (8 B)
-        "emit": n_vis * 52 + D * (5 if packed else 8),
-        # low byte count (1) + low pass (5 in, 5 out) + high byte count (1) + high
-        # pass (5 in; index 4 + 16-bit tile 2 out) per entry
-        "tile_sort": D * 23,
-        # sorted 16-bit tile ids read, ranges zeroed and written
-        "tile_ranges": D * 2 + tiles * 16,
-        # params + 9 screen-space gradients (double) read, 17 + 3k gradients written
-        "preprocess_bwd": n * (68 + 12 * k) + n * 72 + n * 4 * (17 + 3 * k),
-    }
+    alg_bytes = stage_alg_bytes(n, k, [(n_vis, D, tiles)])
     dominant = max(stages, key=stages.get)
     dom_ms = stages[dominant]
     workload = "500k_1352x1014_tile16"
@@ -652,6 +663,31 @@ def per_config(r4d, rend, dev, args):
     d_total = sum(s.last.stats(v)["n_dup"] for v in range(len(views)))
     res["3m_16_renders_fwd_bwd"] = {"graph_ms_per_step": ms, "renders_per_s": 16e3 / ms,
                                     "tile_entries_total": d_total}
+    # per-stage times of the same step in fused mode (one launch per stage over
+    # all 16 renders), and the memory-bound stages' share of HBM peak
+    fused = Stepper(r4d, rend, p, views, dict(st, mode="fused"), targets)
+    fused.step()
+    rend.set_timing(True)
+    rend.timings(reset=True)
+    for _ in range(3):
+        fused.step()
+    torch.cuda.synchronize()
+    tim = rend.timings(reset=True)
+    rend.set_timing(False)
+    stages = {k_: (v[0] / v[1] if v[1] else 0.0) for k_, v in tim.items()}
+    renders = []
+    for v in range(len(views)):
+        sv = fused.last.stats(v)
+        renders.append((sv["n_visible"], sv["n_dup"], sv["tiles_x"] * sv["tiles_y"]))
+    fused.last.release()
+    alg = stage_alg_bytes(int(g["opacity"].shape[0]), (g["sh_degree"] + 1) ** 2, renders)
+    hbm = {}
+    for name, b in alg.items():
+        if stages.get(name):
+            gbs = b / (stages[name] * 1e-3) / 1e9
+            hbm[name] = {"alg_bytes": b, "ms": stages[name], "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    res["3m_16_renders_fwd_bwd"].update({"fused_stage_ms": stages, "hbm_stages": hbm,
+                                         "visible_total": sum(r[0] for r in renders)})
     del s, p
     torch.cuda.empty_cache()
     print(f"per config: {res}", file=sys.stderr, flush=True)

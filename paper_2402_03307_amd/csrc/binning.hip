@@ -234,7 +234,9 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
   __shared__ uint32_t s_w[kThreads / 64];
   __shared__ uint32_t s_bid;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_bid = atomicAdd(ticket, 1u);
+  // position in the sort order: the launch order (ticket), or, when every
+  // workgroup of the grid is resident at once (ticket null), the block index
+  if (tid == 0) s_bid = ticket ? atomicAdd(ticket, 1u) : blockIdx.x;
 #pragma unroll
   for (int w = 0; w < kThreads / 64; ++w) s_wh[w][tid] = 0u;
   __syncthreads();
@@ -245,7 +247,11 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
   const uint32_t sstart = seg->start[s];
   const uint32_t send = sstart + seg->len[s];
   const uint32_t first_b = sstart / TILE;
-  const uint32_t nvalid = send > e0 ? (send - e0 < TILE ? send - e0 : TILE) : 0u;
+  // past its segment's keys (every later workgroup of the segment is too, and
+  // the next segment's look-back stops at its own first workgroup): nothing
+  // to publish
+  if (e0 >= send) return;
+  const uint32_t nvalid = send - e0 < TILE ? send - e0 : TILE;
 
   // load: wave w holds elements [w * 64 * ITEMS, (w + 1) * 64 * ITEMS) of the tile
   uint32_t k[ITEMS], v[ITEMS], r[ITEMS];
@@ -1052,6 +1058,21 @@ hipError_t radix_histogram(const uint32_t* keys, const SegTable* seg, int n_segm
   return hipGetLastError();
 }
 
+// Workgroups of `kernel` (kThreads each) resident on the whole device at once;
+// 0 when unknown (then every launch takes tickets).
+template <typename K>
+uint32_t resident_blocks(K kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
+      per_cu < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return 0u;
+  }
+  return uint32_t(per_cu) * uint32_t(cus);
+}
+
 hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* key_bufs[2],
                          uint32_t* val_bufs[2], const SegTable* seg, uint64_t capacity_elems,
                          int passes, int items, const uint32_t* hist, uint32_t* status,
@@ -1062,6 +1083,13 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
   const uint64_t tile = uint64_t(kThreads) * items;
   const uint32_t blocks = uint32_t((capacity_elems + tile - 1) / tile);
   const uint32_t words = blocks * 256u;
+  // launch-order tickets are needed only when the grid does not fit the
+  // device at once (a workgroup must never wait on one that cannot start)
+  static const uint32_t resident[3] = {resident_blocks(onesweep_kernel<4>),
+                                       resident_blocks(onesweep_kernel<8>),
+                                       resident_blocks(onesweep_kernel<16>)};
+  const int which = items == 4 ? 0 : (items == 8 ? 1 : 2);
+  const bool ticketed = blocks > resident[which];
   for (int p = 0; p < passes; ++p) {
     const uint32_t* ki = p == 0 ? keys_in : key_bufs[(p - 1) & 1];
     const uint32_t* vi = p == 0 ? vals_in : val_bufs[(p - 1) & 1];
@@ -1072,15 +1100,15 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
     switch (items) {
       case 4:
         hipLaunchKernelGGL(onesweep_kernel<4>, dim3(blocks), dim3(kThreads), 0, stream, ki, vi,
-                           ko, vo, seg, h, st, tickets + p, error, 8 * p);
+                           ko, vo, seg, h, st, ticketed ? tickets + p : nullptr, error, 8 * p);
         break;
       case 8:
         hipLaunchKernelGGL(onesweep_kernel<8>, dim3(blocks), dim3(kThreads), 0, stream, ki, vi,
-                           ko, vo, seg, h, st, tickets + p, error, 8 * p);
+                           ko, vo, seg, h, st, ticketed ? tickets + p : nullptr, error, 8 * p);
         break;
       case 16:
         hipLaunchKernelGGL(onesweep_kernel<16>, dim3(blocks), dim3(kThreads), 0, stream, ki, vi,
-                           ko, vo, seg, h, st, tickets + p, error, 8 * p);
+                           ko, vo, seg, h, st, ticketed ? tickets + p : nullptr, error, 8 * p);
         break;
       default: return hipErrorInvalidValue;
     }
