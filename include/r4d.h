@@ -122,6 +122,21 @@ typedef struct {
                           8 or 16 = (tile id, index) pairs sorted by a onesweep
                           radix sort with this many keys per lane.  With
                           tile_size 0 the autotuner picks 0 or 16.  (0)           */
+  float front_fraction; /* front lists: with n_vis visible Gaussians in depth
+                          order, those at positions from ceil(front_fraction *
+                          n_vis) on are listed only in tiles covered by at most
+                          front_keep Gaussians' tile boxes; any other tile's list
+                          ends there, and when its pixels outlast that front
+                          list the forward collects the rest of the list
+                          itself.  The rasteriser sees every list in full up to
+                          where its pixels stop (Sec. 3.1 compositing rule), so
+                          images and gradients do not depend on this; it saves
+                          sorting entries that lie behind saturated pixels.
+                          >= 1: whole lists.  Renders whose
+                          (tiles_x + 1) * (tiles_y + 1) exceeds 16384 get
+                          whole lists.  (0.1)                                    */
+  int32_t front_keep;   /* see front_fraction; negative: no tile is kept whole
+                          (4096)                                                 */
 } r4d_settings;
 
 /* How a call with several views is executed.
@@ -590,10 +605,18 @@ r4d_status r4d_saved_config(const r4d_saved *saved, int32_t *tile_size, int32_t 
 
 /* Introspection of saved state (tests and the benchmark).
  * r4d_saved_stats writes, for view v: n_visible (Gaussians with at least one
- * tile), n_dup (tile entries D), tiles_x, tiles_y.  It waits for the forward
- * call to finish. */
+ * tile), n_dup (tile entries D of the whole lists), tiles_x, tiles_y.  It waits
+ * for the forward call to finish. */
 r4d_status r4d_saved_stats(const r4d_saved *saved, int view, int64_t *n_visible, int64_t *n_dup,
                            int32_t *tiles_x, int32_t *tiles_y);
+
+/* Front lists of view v (see front_fraction): n_front, the entries emitted and
+ * sorted (n_dup with whole lists); n_values, the length of R4D_BUF_VALUES;
+ * rest_tiles, the tiles whose forward collected a rest; rest_entries, the
+ * rest area those took (each tile's share rounded up to 256).  Any pointer
+ * may be NULL.  Waits for the forward call to finish. */
+r4d_status r4d_saved_front_stats(const r4d_saved *saved, int view, int64_t *n_front,
+                                 int64_t *n_values, int64_t *rest_tiles, int64_t *rest_entries);
 
 /* Copies one saved buffer of view v into dst (DEVICE, at least `bytes`).
  *   R4D_BUF_RECORDS   per Gaussian, 12 floats (or doubles for the f64 path):
@@ -611,10 +634,17 @@ r4d_status r4d_saved_stats(const r4d_saved *saved, int view, int64_t *n_visible,
  *                     rule; every row of the box holds a run)
  *   R4D_BUF_DEPTHKEY  per Gaussian uint32: float32 bit pattern of the depth,
  *                     0xffffffff when culled
- *   R4D_BUF_VALUES    D uint32: Gaussian index of each tile entry, sorted by
- *                     (tile, depth, index)
+ *   R4D_BUF_VALUES    n_values uint32 (r4d_saved_front_stats; D with whole
+ *                     lists): Gaussian index of each tile entry, sorted by
+ *                     (tile, depth, index); with front lists the front lists,
+ *                     then the rest area
  *   R4D_BUF_RANGES    tiles_x*tiles_y pairs of uint32 [start, end) into VALUES
- *                     (of this view)
+ *                     (of this view): each tile's whole or front list
+ *   R4D_BUF_REST      tiles_x*tiles_y pairs of uint32 [start, end) into VALUES:
+ *                     the rest the forward collected for a tile's front list
+ *                     ([0, 0) for none); front and rest together are the
+ *                     list's first entries, up to past the tile's last
+ *                     contributor
  *   R4D_BUF_TFINAL    H*W float (double): final transmittance per pixel
  *   R4D_BUF_NCONTRIB  H*W uint32: tile-list entries up to the last contributor
  *   R4D_BUF_NEVAL     H*W uint32: tile-list entries the forward evaluated for the
@@ -637,7 +667,8 @@ enum {
   R4D_BUF_NCONTRIB = 6,
   R4D_BUF_NEVAL = 7,
   R4D_BUF_FLOW = 8,
-  R4D_BUF_NBLEND = 9
+  R4D_BUF_NBLEND = 9,
+  R4D_BUF_REST = 10
 };
 r4d_status r4d_saved_copy(const r4d_saved *saved, int view, int buffer, void *dst, size_t bytes,
                           void *stream);

@@ -32,10 +32,11 @@ LIB_PATH = os.path.join(_HERE, "libr4d.so")
 __all__ = ["render", "render_flow", "Renderer", "TrainState", "adam_config", "R4DError",
            "default_settings", "LIB_PATH", "BUF_RECORDS", "BUF_RECT", "BUF_DEPTHKEY",
            "BUF_VALUES", "BUF_RANGES", "BUF_TFINAL", "BUF_NCONTRIB", "BUF_NEVAL", "BUF_FLOW",
-           "BUF_NBLEND", "EXPORTED_SYMBOLS", "MODE_PER_VIEW", "MODE_FUSED", "MODE_GRAPH"]
+           "BUF_NBLEND", "BUF_REST", "EXPORTED_SYMBOLS", "MODE_PER_VIEW", "MODE_FUSED",
+           "MODE_GRAPH"]
 
 (BUF_RECORDS, BUF_RECT, BUF_DEPTHKEY, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB,
- BUF_NEVAL, BUF_FLOW, BUF_NBLEND) = range(10)
+ BUF_NEVAL, BUF_FLOW, BUF_NBLEND, BUF_REST) = range(11)
 
 # execution modes of a multi-view call (see R4D_MODE_* in include/r4d.h)
 MODE_PER_VIEW, MODE_FUSED, MODE_GRAPH = 0, 1, 2
@@ -52,7 +53,7 @@ EXPORTED_SYMBOLS = (
     "r4d_default_densify_config", "r4d_densify", "r4d_render_forward_3d",
     "r4d_render_backward_3d", "r4d_render_forward_3d_f64", "r4d_render_backward_3d_f64",
     "r4d_saved_release", "r4d_l1_loss_grad", "r4d_l1_loss_grad_views", "r4d_saved_stats",
-    "r4d_saved_copy", "r4d_saved_check", "r4d_check_pending", "r4d_saved_config",
+    "r4d_saved_front_stats", "r4d_saved_copy", "r4d_saved_check", "r4d_check_pending", "r4d_saved_config",
     "r4d_status_string",
     "r4d_last_error", "r4d_set_timing", "r4d_get_timings", "r4d_stage_name",
 )
@@ -82,7 +83,8 @@ class _Settings(ctypes.Structure):
                 ("extent_sigma", c_f32), ("alpha_min", c_f32), ("alpha_max", c_f32),
                 ("T_min", c_f32), ("dilation", c_f32), ("guard_band", c_f32),
                 ("fwd_pixels_per_thread", c_i32), ("bwd_pixels_per_thread", c_i32),
-                ("mode", c_i32), ("sort_items", c_i32)]
+                ("mode", c_i32), ("sort_items", c_i32), ("front_fraction", c_f32),
+                ("front_keep", c_i32)]
 
 
 class _AdamConfig(ctypes.Structure):
@@ -190,6 +192,8 @@ def _load():
     lib.r4d_saved_stats.argtypes = [c_vp, ctypes.c_int, P(ctypes.c_int64), P(ctypes.c_int64),
                                     P(c_i32), P(c_i32)]
     lib.r4d_saved_stats.restype = ctypes.c_int
+    lib.r4d_saved_front_stats.argtypes = [c_vp, ctypes.c_int] + [P(ctypes.c_int64)] * 4
+    lib.r4d_saved_front_stats.restype = ctypes.c_int
     lib.r4d_saved_copy.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]
     lib.r4d_saved_copy.restype = ctypes.c_int
     lib.r4d_status_string.argtypes = [ctypes.c_int]
@@ -215,6 +219,10 @@ def library():
 def default_settings() -> dict:
     s = _Settings()
     _lib.r4d_default_settings(ctypes.byref(s))
+    return {name: getattr(s, name) for name, _ in _Settings._fields_}
+
+
+def _settings_dict(s: _Settings) -> dict:
     return {name: getattr(s, name) for name, _ in _Settings._fields_}
 
 
@@ -319,11 +327,13 @@ def _release_all():
 class SavedState:
     """Opaque per-forward state kept for the backward pass."""
 
-    def __init__(self, renderer: "Renderer", handle: ctypes.c_void_p, views, dtype):
+    def __init__(self, renderer: "Renderer", handle: ctypes.c_void_p, views, dtype,
+                 settings: dict | None = None):
         self.renderer = renderer
         self.handle = handle
         self.views = views
         self.dtype = dtype
+        self.settings = dict(settings or {})  # as passed to the library (defaults filled in)
         _live_saved.add(self)
 
     def release(self):
@@ -359,7 +369,14 @@ class SavedState:
         st = _lib.r4d_saved_stats(self.handle, view, ctypes.byref(nv), ctypes.byref(nd),
                                   ctypes.byref(tx), ctypes.byref(ty))
         self.renderer._check(st, "r4d_saved_stats")
-        return {"n_visible": nv.value, "n_dup": nd.value, "tiles_x": tx.value, "tiles_y": ty.value}
+        out = {"n_visible": nv.value, "n_dup": nd.value, "tiles_x": tx.value,
+               "tiles_y": ty.value}
+        f = [ctypes.c_int64() for _ in range(4)]
+        st = _lib.r4d_saved_front_stats(self.handle, view, *[ctypes.byref(x) for x in f])
+        self.renderer._check(st, "r4d_saved_front_stats")
+        out.update(zip(("n_front", "n_values", "rest_tiles", "rest_entries"),
+                       (x.value for x in f)))
+        return out
 
     def copy(self, view: int, buffer: int, n_gaussians: int) -> torch.Tensor:
         """Device copy of one saved buffer (see r4d_saved_copy)."""
@@ -369,8 +386,9 @@ class SavedState:
         fdt = self.dtype
         shapes = {BUF_RECORDS: ((n_gaussians, 12), fdt), BUF_RECT: ((n_gaussians, 4), torch.int16),
                   BUF_DEPTHKEY: ((n_gaussians,), torch.int32),
-                  BUF_VALUES: ((s["n_dup"],), torch.int32),
+                  BUF_VALUES: ((s["n_values"],), torch.int32),
                   BUF_RANGES: ((s["tiles_x"] * s["tiles_y"], 2), torch.int32),
+                  BUF_REST: ((s["tiles_x"] * s["tiles_y"], 2), torch.int32),
                   BUF_TFINAL: ((hw,), fdt), BUF_NCONTRIB: ((hw,), torch.int32),
                   BUF_NEVAL: ((hw,), torch.int32), BUF_NBLEND: ((hw,), torch.int32),
                   BUF_FLOW: ((n_gaussians, 2), fdt)}
@@ -462,7 +480,7 @@ class Renderer:
             status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st),
                         _ptr(out), hptr, _stream(self.device))
             self._check(status, "r4d_render_forward")
-        saved = SavedState(self, handle, views, dtype) if save else None
+        saved = (SavedState(self, handle, views, dtype, _settings_dict(st)) if save else None)
         if flat:
             return (out, fout, saved) if flow else (out, saved)
         images = _split(out, views, 3)
@@ -653,7 +671,7 @@ class Renderer:
         status = fn(self.handle, ctypes.byref(g), varr, len(views), ctypes.byref(st), _ptr(out),
                     ctypes.byref(handle) if save else None, _stream(self.device))
         self._check(status, "r4d_render_forward_3d")
-        saved = SavedState(self, handle, views, dtype) if save else None
+        saved = (SavedState(self, handle, views, dtype, _settings_dict(st)) if save else None)
         return (out, saved) if flat else (_split(out, views, 3), saved)
 
     def backward_static(self, params: dict, views, settings: dict | None, saved: SavedState,

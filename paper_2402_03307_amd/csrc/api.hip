@@ -32,10 +32,18 @@
 
 #include <sys/stat.h>
 
+#include "front.hpp"
 #include "r4d.h"
 #include "r4d_internal.hpp"
 
 using namespace r4d;
+
+namespace {
+// What one run reports back in one copy: the status words (overflow, sort
+// look-back error; 16 bytes), two totals per render (visible Gaussians, tile
+// entries of the whole lists) and the front-list table.
+constexpr size_t kReadbackBytes = 16 + 2 * size_t(kMaxViews) * 8 + sizeof(FrontTable);
+}  // namespace
 
 // Device memory of r4d_render_forward_noalloc: every buffer of its runs lives
 // in this region, one copy per GPU, held until the process ends.  Host code
@@ -78,8 +86,9 @@ struct GraphEntry;
 struct RunLayout {
   // fixed block
   size_t meta, recs, flows, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp,
-      ranges, T_final, n_contrib, n_eval, img_copy, flow_copy, walk, ptemp_fwd, zero_begin,
-      status, totals, dhist, tickets, dstatus, zero_end, fixed_bytes;
+      ranges, T_final, n_contrib, n_eval, img_copy, flow_copy, walk, ptemp_fwd, keep, fcount,
+      srect, queue, zero_begin, status, totals, front, rest, dhist, tickets, dstatus, zero_end,
+      fixed_bytes;
   // entries block
   size_t tkA, tkB, tvA, tvB, tdig, thi, t16, etemp, ptemp, ck, ckf, tstatus, entries_bytes;
 };
@@ -104,6 +113,11 @@ struct Plan {
   bool count_evals = false;
   bool flow = false;    // also composite the 2D flow (flow images)
   bool static3d = false;  // static 3D Gaussians (means 3, log-scales 3, quaternions 4 rows)
+  // front lists (front.hpp): some render has a depth cut; the keep threshold;
+  // size of all renders' keep bitmaps (words)
+  bool front = false;
+  int32_t front_keep = 0;
+  size_t keep_words_total = 0;
 };
 
 }  // namespace
@@ -170,13 +184,14 @@ struct RunState {
   // no-allocation runs: bytes available to the entries block, which the sized
   // path checks instead of allocating (0: the block is allocated)
   size_t entries_limit = 0;
-  // per-view counts (valid after `done`)
-  std::vector<uint64_t> n_visible, n_dup;
+  // per-view counts (valid after `done`); front lists: entries in the front
+  // (or whole) lists, tiles that collected a rest, rest area taken
+  std::vector<uint64_t> n_visible, n_dup, n_front, rest_tiles, rest_entries;
   uint32_t flags[2] = {0, 0};  // overflow, look-back error
   bool counts_valid = false;
   // pinned readback of totals + flags, filled at the end of the run
   r4d_ctx::Pinned* slot = nullptr;
-  unsigned long long* pinned = nullptr;  // status word pair, then 2 V totals (2 kMaxViews + 2 words)
+  unsigned long long* pinned = nullptr;  // kReadbackBytes: status words, totals, front table
   hipEvent_t done = nullptr;
   size_t image_offset = 0;     // first image element of this run in the call's images
   size_t flow_offset = 0;      // first flow element of this run in the call's flow images
@@ -302,6 +317,7 @@ bool valid_settings(const r4d_settings* s) {
   if (s->tile_size == 0 && (s->fwd_pixels_per_thread || s->bwd_pixels_per_thread)) return false;
   if (s->mode < R4D_MODE_PER_VIEW || s->mode > R4D_MODE_GRAPH) return false;
   if (s->sort_items != 0 && s->sort_items != 8 && s->sort_items != 16) return false;
+  if (!(s->front_fraction >= 0.f)) return false;  // (NaN fails too)
   return s->near_plane >= 0.f && s->time_cull >= 0.f && s->extent_sigma > 0.f &&
          s->alpha_min > 0.f && s->alpha_max > s->alpha_min && s->alpha_max < 1.f &&
          s->T_min > 0.f && s->T_min < 1.f && s->dilation >= 0.f && s->guard_band > 0.f;
@@ -455,6 +471,21 @@ Plan make_plan(const r4d_view* views, int V, uint32_t n, int deg, const r4d_sett
   }
   p.tile_passes = (bits + 7) / 8;
   p.packed = s.sort_items == 0 && packed_tile_sort_ok(n, p.max_tiles);
+  // front lists: the depth cut as a fraction of 65536 (at least 1), for the
+  // renders whose tile grid fits the keep kernel
+  const uint32_t f16 =
+      s.front_fraction >= 1.0f
+          ? 0u
+          : uint32_t(std::min(65536.0, std::max(1.0, std::ceil(double(s.front_fraction) * 65536.0))));
+  p.front_keep = s.front_keep;
+  for (ViewSlot& sl : p.slots) {
+    sl.front16 = (f16 && front_grid_ok(sl.v.tiles_x, sl.v.tiles_y)) ? f16 : 0u;
+    sl.keep_base = uint32_t(p.keep_words_total);
+    if (sl.front16) {
+      p.front = true;
+      p.keep_words_total += size_t(keep_words(sl.v.tiles_x)) * size_t(sl.v.tiles_y);
+    }
+  }
   p.dseg.count = uint32_t(V);
   p.dseg.overflow = 0;
   for (int v = 0; v <= V; ++v) p.dseg.start[v] = uint32_t(uint64_t(v) * p.n_pad);
@@ -502,12 +533,18 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.flow_copy = p.flow ? take(2 * size_t(p.total_pix) * p.scal) : 0;
   L.walk = take(size_t(p.total_tiles) * 4);
   L.ptemp_fwd = take(preprocess_temp_bytes(p.n, p.V));
+  L.keep = take(p.keep_words_total * 8);
+  L.fcount = p.front ? take(V * np * 4) : 0;
+  L.srect = p.front ? take(V * np * sizeof(Rect16)) : 0;
+  L.queue = p.front ? take(size_t(p.total_tiles) * 4) : 0;
   L.zero_begin = off;
   L.ranges = take(size_t(p.total_tiles) * 8);  // tiles without entries keep [0, 0)
   // status words (overflow, sort look-back error) followed by the per-render
-  // totals, so that one copy returns all a run reports
-  L.status = take(16 + 2 * size_t(kMaxViews) * 8);
+  // totals and the front-list table, so that one copy returns all a run reports
+  L.status = take(kReadbackBytes);
   L.totals = L.status + 16;
+  L.front = L.totals + 2 * size_t(kMaxViews) * 8;
+  L.rest = take(size_t(p.total_tiles) * 8);
   L.dhist = take(4 * size_t(kMaxViews) * 256 * 4);
   L.tickets = take(16 * 4);
   L.dstatus = take(4 * size_t(sort_status_words(uint64_t(V) * np, kDepthItems)) * 4);
@@ -579,7 +616,7 @@ RasterSaved<T> saved_of(const RunState& r) {
   const bool fl = r.plan.flow;
   return RasterSaved<T>{at<Ck<T>>(E, r.L.ck), at<T>(F, r.L.img_copy), at<uint32_t>(F, r.L.walk),
                         fl ? at<Vec2<T>>(E, r.L.ckf) : nullptr,
-                        fl ? at<T>(F, r.L.flow_copy) : nullptr};
+                        fl ? at<T>(F, r.L.flow_copy) : nullptr, at<uint2>(F, r.L.rest)};
 }
 
 // Enqueues the forward of a run.  sized = false: entries block and capacity
@@ -605,13 +642,13 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   if (p.n == 0) R4D_HIP(fill_zero(F + L.zero_begin, zero_bytes, stream));
   const uint32_t* order = nullptr;
   if (p.n > 0) {
-    R4D_TIMED(kPreprocessFwd,
-              launch_preprocess_fwd<T>(g, slots, p.V, st, p.n_pad, at<Rec<T>>(F, L.recs),
-                                       p.flow ? at<Vec2<T>>(F, L.flows) : nullptr,
-                                       at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
-                                       at<uint32_t>(F, L.dkeys), totals, at<uint32_t>(F, L.kA),
-                                       at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd,
-                                       F + L.zero_begin, zero_bytes, p.static3d, stream));
+    StageTimer tm(ctx, kPreprocessFwd, stream, timed);
+    R4D_HIP(launch_preprocess_fwd<T>(g, slots, p.V, st, p.n_pad, at<Rec<T>>(F, L.recs),
+                                     p.flow ? at<Vec2<T>>(F, L.flows) : nullptr,
+                                     at<Rect16>(F, L.rects), at<uint32_t>(F, L.tiles),
+                                     at<uint32_t>(F, L.dkeys), totals, at<uint32_t>(F, L.kA),
+                                     at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd,
+                                     F + L.zero_begin, zero_bytes, p.static3d, stream));
   }
   hipEvent_t totals_ready = nullptr;
   if (sized) {
@@ -641,7 +678,7 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
       if (d >= (uint64_t(1) << 30))
         return fail(ctx, R4D_ERR_CAPACITY, "view %d has %llu tile entries (limit 2^30)", v,
                     (unsigned long long)d);
-      cap += round_seg(d);
+      cap += seg_extent(d, p.slots[size_t(v)]);
     }
     if (cap >= (uint64_t(1) << 32))
       return fail(ctx, R4D_ERR_CAPACITY, "%llu tile entries in one call (limit 2^32)",
@@ -677,21 +714,37 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
   uint8_t* E = r.entries;
   auto* ranges = at<uint2>(F, L.ranges);
   // the segment table of the emitted list (with the count scan when there are Gaussians)
-  if (p.n == 0) R4D_HIP(seg_table(totals, p.V, r.capacity, tseg, status, stream));
+  if (p.n == 0) R4D_HIP(seg_table(totals, slots, p.V, r.capacity, tseg, status, stream));
   uint32_t* values = at<uint32_t>(E, L.tvA);
   const void* sorted_tiles = nullptr;
   if (p.n > 0) {
     auto* offsets = at<uint64_t>(F, L.offsets);
-    R4D_TIMED(kCountScan, count_scan_seg(order, at<uint32_t>(F, L.tiles), totals, p.n, p.n_pad,
-                                         p.V, offsets, F + L.scan_tmp, r.capacity, tseg, status,
-                                         at<uint32_t>(E, L.etemp), stream));
+    {
+      StageTimer tm(ctx, kCountScan, stream, timed);
+      if (p.front) {
+        // which tiles keep their whole list, then each Gaussian's entries
+        R4D_HIP(front_keep(slots, p.V, order, at<Rect16>(F, L.rects), totals, p.n, p.n_pad,
+                           p.front_keep, at<uint64_t>(F, L.keep), stream));
+        R4D_HIP(front_counts<T>(order, at<uint32_t>(F, L.tiles), at<Rect16>(F, L.rects),
+                                at<Rec<T>>(F, L.recs), slots, totals, at<uint64_t>(F, L.keep),
+                                p.n, p.n_pad, p.V, at<uint32_t>(F, L.fcount),
+                                at<Rect16>(F, L.srect), stream));
+      }
+      R4D_HIP(count_scan_seg(order, at<uint32_t>(F, L.tiles),
+                             p.front ? at<uint32_t>(F, L.fcount) : nullptr, totals, slots, p.n,
+                             p.n_pad, p.V, offsets, F + L.scan_tmp, r.capacity, tseg,
+                             p.front ? at<FrontTable>(F, L.front) : nullptr, status,
+                             at<uint32_t>(E, L.etemp), stream));
+    }
     // packed: (index | high tile byte) words into tvA and low tile bytes into
     // tdig; otherwise tile ids into tkA and indices into tvA
     uint32_t* out_a = p.packed ? at<uint32_t>(E, L.tvA) : at<uint32_t>(E, L.tkA);
     void* out_b = p.packed ? static_cast<void*>(E + L.tdig) : static_cast<void*>(E + L.tvA);
     R4D_TIMED(kEmit, emit_blocks<T>(order, offsets, at<Rect16>(F, L.rects),
-                                    at<Rec<T>>(F, L.recs), slots, tseg, p.n, p.n_pad, p.V,
-                                    r.capacity, p.packed, E + L.etemp, out_a, out_b,
+                                    at<Rec<T>>(F, L.recs), slots, tseg, totals,
+                                    p.front ? at<uint64_t>(F, L.keep) : nullptr,
+                                    p.front ? at<uint32_t>(F, L.fcount) : nullptr, p.n, p.n_pad,
+                                    p.V, r.capacity, p.packed, E + L.etemp, out_a, out_b,
                                     p.packed ? E + L.ptemp : nullptr, stream));
     if (p.packed) {
       // low tile byte pass into (tkA, thi), high byte pass into (tvA, t16)
@@ -722,10 +775,15 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
                                      p.n > 0 ? r.capacity : 0, ranges, stream));
   r.values = values;
   const RasterSaved<T> sv = saved_of<T>(r);
+  FrontCollect fc{};
+  if (p.front && p.n > 0)
+    fc = FrontCollect{at<uint64_t>(F, L.keep), order,       at<Rect16>(F, L.srect),
+                      totals,                  at<FrontTable>(F, L.front), at<uint32_t>(F, L.queue),
+                      status,                  p.n_pad};
   R4D_TIMED(kRasterFwd,
             launch_raster_fwd<T>(at<Rec<T>>(F, L.recs),
                                  p.flow ? at<Vec2<T>>(F, L.flows) : nullptr, p.n, values, ranges,
-                                 slots, p.V, p.total_tiles, p.ts, st, p.fppt, images,
+                                 fc, slots, p.V, p.total_tiles, p.ts, st, p.fppt, images,
                                  p.flow ? flow_images : nullptr, at<T>(F, L.T_final),
                                  at<uint32_t>(F, L.n_contrib),
                                  p.count_evals ? at<uint32_t>(F, L.n_eval) : nullptr, sv,
@@ -736,11 +794,11 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
 // Copies totals and flags to the run's pinned area and records its `done`
 // event (outside any capture).
 r4d_status finish_run(r4d_ctx* ctx, RunState& r, hipStream_t stream) {
-  const Plan& p = r.plan;
-  // status words and totals in one copy: pinned[0] = (overflow, error),
-  // pinned[1] unused, pinned[2 + 2v], [3 + 2v] = render v's totals
-  R4D_HIP(hipMemcpyAsync(r.pinned, r.fixed + r.L.status, 16 + 2 * size_t(p.V) * 8,
-                         hipMemcpyDeviceToHost, stream));
+  // status words, totals and front table in one copy: pinned[0] = (overflow,
+  // error), pinned[1] unused, pinned[2 + 2v], [3 + 2v] = render v's totals,
+  // the front table from pinned[2 + 2 kMaxViews] on
+  R4D_HIP(hipMemcpyAsync(r.pinned, r.fixed + r.L.status, kReadbackBytes, hipMemcpyDeviceToHost,
+                         stream));
   R4D_HIP(hipEventRecord(r.done, stream));
   r.counts_valid = false;
   return R4D_OK;
@@ -752,9 +810,16 @@ r4d_status wait_run(r4d_ctx* ctx, RunState& r) {
   const int V = r.plan.V;
   r.n_visible.assign(size_t(V), 0);
   r.n_dup.assign(size_t(V), 0);
+  const FrontTable* ft = reinterpret_cast<const FrontTable*>(r.pinned + 2 + 2 * kMaxViews);
+  r.n_front.assign(size_t(V), 0);
+  r.rest_tiles.assign(size_t(V), 0);
+  r.rest_entries.assign(size_t(V), 0);
   for (int v = 0; v < V; ++v) {
     r.n_visible[size_t(v)] = r.pinned[2 + 2 * v];
     r.n_dup[size_t(v)] = r.pinned[3 + 2 * v];
+    r.n_front[size_t(v)] = r.plan.front ? ft->n_front[v] : r.n_dup[size_t(v)];
+    r.rest_tiles[size_t(v)] = ft->rest_tiles[v];
+    r.rest_entries[size_t(v)] = ft->cursor[v];
   }
   const uint32_t* fl = reinterpret_cast<const uint32_t*>(r.pinned);
   r.flags[0] = fl[0];
@@ -765,6 +830,14 @@ r4d_status wait_run(r4d_ctx* ctx, RunState& r) {
 
 // A readback area nobody holds whose last copy has completed (or a new one),
 // returned with one reference.
+// Entries of render vi's part of the list buffer that VALUES copies (after
+// wait_run): its front (or whole) lists, and with rest ranges the rest area
+// up to the last one.
+uint64_t values_count(const RunState& r, int vi) {
+  const uint64_t nf = r.n_front[size_t(vi)], rest = r.rest_entries[size_t(vi)];
+  return rest ? (nf + kSegment - 1) / kSegment * kSegment + rest : nf;
+}
+
 r4d_status acquire_slot(r4d_ctx* ctx, r4d_ctx::Pinned** out) {
   r4d_ctx::Pinned* slot = nullptr;
   for (r4d_ctx::Pinned* q : ctx->pinned_pool) {
@@ -778,7 +851,7 @@ r4d_status acquire_slot(r4d_ctx* ctx, r4d_ctx::Pinned** out) {
   }
   if (!slot) {
     auto q = std::make_unique<r4d_ctx::Pinned>();
-    R4D_HIP(hipHostMalloc(reinterpret_cast<void**>(&q->host), (2 * size_t(kMaxViews) + 2) * 8,
+    R4D_HIP(hipHostMalloc(reinterpret_cast<void**>(&q->host), kReadbackBytes,
                           hipHostMallocDefault));
     const hipError_t e = hipEventCreateWithFlags(&q->done, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -936,14 +1009,15 @@ r4d_status run_sized(r4d_ctx* ctx, const GaussPtrs<T>& g, const Plan& p, T* imag
 template <typename T>
 std::string fwd_graph_key(const GaussPtrs<T>& g, const void* images, const void* flows,
                           const r4d_view* views, int V, const r4d_settings& s, bool static3d) {
-  char buf[512];
-  snprintf(buf, sizeof(buf), "%zu|%d|%d|%d|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%a|%a|%a|%a|%a|%a|%a|",
+  char buf[640];
+  snprintf(buf, sizeof(buf),
+           "%zu|%d|%d|%d|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%a|%a|%a|%a|%a|%a|%a|%a|%a|%d|",
            sizeof(T), int(static3d), g.n, g.deg, (const void*)g.means, (const void*)g.log_scales,
            (const void*)g.rotors, (const void*)g.opacity, (const void*)g.sh, images, flows,
            s.tile_size,
            s.fwd_pixels_per_thread, s.bwd_pixels_per_thread, s.sort_items, s.near_plane,
            s.time_cull, s.extent_sigma, s.alpha_min, s.alpha_max, s.T_min, s.dilation,
-           s.guard_band);
+           s.guard_band, s.front_fraction, s.front_keep);
   return std::string(buf) + view_shape_key(views, V);
 }
 
@@ -971,7 +1045,8 @@ r4d_status run_graph(r4d_ctx* ctx, const GaussPtrs<T>& g, const r4d_view* views,
     if (e) {
       // the overflowed replay still counted every view's entries
       uint64_t needed = 0;
-      for (int v = 0; v < V; ++v) needed += round_seg(e->run.pinned[3 + 2 * v]);
+      for (int v = 0; v < V; ++v)
+        needed += seg_extent(e->run.pinned[3 + 2 * v], p.slots[size_t(v)]);
       cap = std::max(e->run.capacity * 2, needed + needed / 4 + uint64_t(V) * kSegAlign);
       R4D_HIP(hipStreamSynchronize(stream));
       if (e->fwd) (void)hipGraphExecDestroy(e->fwd);
@@ -1541,6 +1616,8 @@ void r4d_default_settings(r4d_settings* s) {
   s->bwd_pixels_per_thread = 0;
   s->mode = R4D_MODE_PER_VIEW;
   s->sort_items = 0;
+  s->front_fraction = 0.1f;
+  s->front_keep = 4096;
 }
 
 r4d_status r4d_create(r4d_ctx** out, int device) {
@@ -1593,8 +1670,8 @@ r4d_status r4d_create(r4d_ctx** out, int device) {
     return R4D_ERR_HIP;
   }
   ctx->noalloc_slot = new r4d_ctx::Pinned();
-  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->noalloc_slot->host),
-                    (2 * size_t(kMaxViews) + 2) * 8, hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->noalloc_slot->host), kReadbackBytes,
+                    hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->noalloc_slot->done, hipEventDisableTiming) != hipSuccess) {
     r4d_destroy(ctx.release());
     return R4D_ERR_OOM;
@@ -2124,6 +2201,22 @@ r4d_status r4d_saved_stats(const r4d_saved* saved, int view, int64_t* n_visible,
   return R4D_OK;
 }
 
+r4d_status r4d_saved_front_stats(const r4d_saved* saved, int view, int64_t* n_front,
+                                 int64_t* n_values, int64_t* rest_tiles, int64_t* rest_entries) {
+  if (!saved || !saved->ctx || view < 0 || view >= int(saved->views.size()))
+    return R4D_ERR_INVALID_ARG;
+  if (saved->graph && saved->generation != saved->graph->generation) return R4D_ERR_STATE;
+  const auto [ri, vi] = saved->where[size_t(view)];
+  RunState* r = saved->run_of(ri);
+  r4d_status s = wait_run(saved->ctx, *r);
+  if (s != R4D_OK) return s;
+  if (n_front) *n_front = int64_t(r->n_front[size_t(vi)]);
+  if (n_values) *n_values = int64_t(values_count(*r, vi));
+  if (rest_tiles) *rest_tiles = int64_t(r->rest_tiles[size_t(vi)]);
+  if (rest_entries) *rest_entries = int64_t(r->rest_entries[size_t(vi)]);
+  return R4D_OK;
+}
+
 r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* dst, size_t bytes,
                           void* stream_) {
   if (!saved || !saved->ctx || view < 0 || view >= int(saved->views.size()) || !dst)
@@ -2155,13 +2248,17 @@ r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* ds
       R4D_HIP(hipMemcpy(&tseg, tseg_of(F, r->L, p.V), sizeof(SegTable), hipMemcpyDeviceToHost));
       if (buffer == R4D_BUF_VALUES) {
         src = r->values + tseg.start[vi];
-        need = size_t(tseg.len[vi]);
-        need *= 4;
+        need = size_t(values_count(*r, vi)) * 4;
       } else {
         need = ntiles * 8;
       }
       break;
     }
+    case R4D_BUF_REST:
+      R4D_HIP(hipSetDevice(ctx->device));
+      R4D_HIP(hipMemcpy(&tseg, tseg_of(F, r->L, p.V), sizeof(SegTable), hipMemcpyDeviceToHost));
+      need = ntiles * 8;
+      break;
     case R4D_BUF_TFINAL: src = F + r->L.T_final + size_t(sl.pix_base) * scal; need = hw * scal; break;
     case R4D_BUF_NCONTRIB: src = F + r->L.n_contrib + size_t(sl.pix_base) * 4; need = hw * 4; break;
     case R4D_BUF_FLOW:
@@ -2183,9 +2280,10 @@ r4d_status r4d_saved_copy(const r4d_saved* saved, int view, int buffer, void* ds
                 bytes);
   if (need == 0) return R4D_OK;
   R4D_HIP(hipSetDevice(ctx->device));
-  if (buffer == R4D_BUF_RANGES) {
-    R4D_HIP(copy_ranges_rebased(at<uint2>(F, r->L.ranges) + sl.tile_base, uint32_t(ntiles),
-                                tseg.start[vi], static_cast<uint2*>(dst), stream));
+  if (buffer == R4D_BUF_RANGES || buffer == R4D_BUF_REST) {
+    R4D_HIP(copy_ranges_rebased(
+        at<uint2>(F, buffer == R4D_BUF_RANGES ? r->L.ranges : r->L.rest) + sl.tile_base,
+        uint32_t(ntiles), tseg.start[vi], static_cast<uint2*>(dst), stream));
     return R4D_OK;
   }
   if (buffer == R4D_BUF_NEVAL || buffer == R4D_BUF_NBLEND) {

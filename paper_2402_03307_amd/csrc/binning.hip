@@ -30,6 +30,7 @@
 
 #include <type_traits>
 
+#include "front.hpp"
 #include "r4d_internal.hpp"
 #include "rowwalk.hpp"
 #include "tileset.hpp"
@@ -84,15 +85,6 @@ __device__ __forceinline__ T block_excl_scan(T x, T* s_w, T* total) {
 // ---- device-wide exclusive scan (multi-level: tile sums are scanned recursively)
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kThreads * kScanItems;
-
-// Row-run constants of a Gaussian from its record and the bounding box of its
-// runs.
-template <typename T>
-__device__ __forceinline__ SpanGeom geom_of(const Rec<T>& r, const Rect16& box, const ViewDev& v) {
-  return span_geom(double(r.mx), double(r.my), double(r.ca), double(r.cb), double(r.cc),
-                   double(r.qmax), v.W, v.H, __builtin_ctz(unsigned(v.tile_size)), box.x0,
-                   box.x1);
-}
 
 template <typename T>
 struct LoadT {
@@ -342,14 +334,15 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
 // the earlier renders' counts, each rounded up to 4096.  When the entries do
 // not fit the capacity (or a render exceeds the per-segment limit) every
 // segment is empty and `overflow` is set.
-__device__ void write_seg_table(const unsigned long long* __restrict__ totals, int n_views,
+__device__ void write_seg_table(const unsigned long long* __restrict__ totals,
+                                const ViewSlot* __restrict__ slots, int n_views,
                                 unsigned long long capacity, SegTable* __restrict__ seg,
                                 uint32_t* __restrict__ overflow_out) {
   unsigned long long total = 0;
   bool too_long = false;
   for (int v = 0; v < n_views; ++v) {
     const unsigned long long d = totals[2 * v + 1];
-    total += (d + kSegAlign - 1) / kSegAlign * kSegAlign;
+    total += seg_extent(d, slots[v]);
     too_long |= d > kStatMask;
   }
   const bool overflow = too_long || total > capacity;
@@ -358,7 +351,7 @@ __device__ void write_seg_table(const unsigned long long* __restrict__ totals, i
     const unsigned long long d = totals[2 * v + 1];
     seg->start[v] = overflow ? 0u : uint32_t(base);
     seg->len[v] = overflow ? 0u : uint32_t(d);
-    base += (d + kSegAlign - 1) / kSegAlign * kSegAlign;
+    base += seg_extent(d, slots[v]);
   }
   seg->start[n_views] = overflow ? 0u : uint32_t(total);
   seg->count = uint32_t(n_views);
@@ -366,15 +359,14 @@ __device__ void write_seg_table(const unsigned long long* __restrict__ totals, i
   if (overflow_out) *overflow_out = overflow ? 1u : 0u;
 }
 
-__global__ void seg_table_kernel(const unsigned long long* __restrict__ totals, int n_views,
+__global__ void seg_table_kernel(const unsigned long long* __restrict__ totals,
+                                 const ViewSlot* __restrict__ slots, int n_views,
                                  unsigned long long capacity, SegTable* __restrict__ seg,
                                  uint32_t* __restrict__ overflow_out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  write_seg_table(totals, n_views, capacity, seg, overflow_out);
+  write_seg_table(totals, slots, n_views, capacity, seg, overflow_out);
 }
 
-// Exclusive scan input: tile counts of every render's Gaussians in depth order,
-// render-major, each render padded to n_pad entries with zeros.
 struct LoadCountGatherSeg {
   const uint32_t* order;  // [V][n_pad] Gaussian index in depth order
   const uint32_t* counts; // [V][n]
@@ -461,18 +453,28 @@ __device__ __forceinline__ bool block_span(const SegTable* seg, uint32_t e0, uin
 // order (renders back to back, each padded to n_pad), in two launches over
 // tiles of kScanTile elements; the first also writes the segment table of the
 // emitted list (workgroup 0), the second the first Gaussian of every emission
-// block (first_gaussian_kernel's map).  With at most kCountDirectTiles tiles
-// every tile adds up the sums of the tiles before it itself; beyond, the tile
-// sums are scanned in between (device_exclusive_scan).
+// block (first_gaussian_kernel's map) and, when the counts are those of front
+// lists, each render's front entry count (its segment length) and rest area.
+// With at most kCountDirectTiles tiles every tile adds up the sums of the
+// tiles before it itself; beyond, the tile sums are scanned in between
+// (device_exclusive_scan).
 constexpr uint32_t kCountDirectTiles = 2048;
 
+// Per-Gaussian counts as front_counts_kernel wrote them ([V][n_pad]).
+struct LoadCountPlain {
+  const uint32_t* counts;
+  uint64_t total;
+  __device__ uint64_t operator()(uint64_t i) const { return i < total ? counts[i] : 0ull; }
+};
+
+template <typename Loader>
 __global__ __launch_bounds__(kThreads) void count_sums_kernel(
-    LoadCountGatherSeg ld, uint64_t* __restrict__ tile_sums,
-    const unsigned long long* __restrict__ totals, int n_views, unsigned long long capacity,
+    Loader ld, uint64_t* __restrict__ tile_sums, const unsigned long long* __restrict__ totals,
+    const ViewSlot* __restrict__ slots, int n_views, unsigned long long capacity,
     SegTable* __restrict__ seg, uint32_t* __restrict__ overflow_out) {
   __shared__ uint64_t s_w[kThreads / 64];
   if (blockIdx.x == 0 && threadIdx.x == 0)
-    write_seg_table(totals, n_views, capacity, seg, overflow_out);
+    write_seg_table(totals, slots, n_views, capacity, seg, overflow_out);
   const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
   uint64_t sum = 0;
 #pragma unroll
@@ -483,18 +485,22 @@ __global__ __launch_bounds__(kThreads) void count_sums_kernel(
 }
 
 // scanned: exclusive scan of the tile sums, or null (direct: add them here).
+// front (nullable): the counts are front-list counts; the render's last tile
+// sets its segment length and rest area.
+template <typename Loader>
 __global__ __launch_bounds__(kThreads) void count_offsets_kernel(
-    LoadCountGatherSeg ld, uint64_t n_elems, const uint64_t* __restrict__ tile_sums,
-    const uint64_t* __restrict__ scanned, const SegTable* __restrict__ seg,
-    uint64_t* __restrict__ offsets, uint32_t* __restrict__ first) {
+    Loader ld, uint32_t n, uint32_t n_pad, uint64_t n_elems,
+    const uint64_t* __restrict__ tile_sums, const uint64_t* __restrict__ scanned,
+    SegTable* __restrict__ seg, FrontTable* __restrict__ front, uint64_t* __restrict__ offsets,
+    uint32_t* __restrict__ first) {
   __shared__ uint64_t s_w[kThreads / 64];
   __shared__ uint64_t s_pre[2];
   const uint32_t b = blockIdx.x;
   // the render of this tile (tiles never straddle renders: n_pad is a
   // multiple of kScanTile) and the tile where the render starts
   const uint64_t e_first = uint64_t(b) * kScanTile;
-  const uint32_t v = uint32_t(e_first / ld.n_pad);
-  const uint64_t row = uint64_t(v) * ld.n_pad;
+  const uint32_t v = uint32_t(e_first / n_pad);
+  const uint64_t row = uint64_t(v) * n_pad;
   const uint32_t rt = uint32_t(row / kScanTile);
   if (scanned) {
     if (threadIdx.x == 0) {
@@ -534,13 +540,280 @@ __global__ __launch_bounds__(kThreads) void count_offsets_kernel(
     // the Gaussian at depth position k holds entries [a, b) of its render;
     // it starts block blk when blk * kChunk lies in [a, b)
     const uint32_t k = uint32_t(i - row);
-    if (map && i < n_elems && k < ld.n && x[j] != 0) {
+    if (map && i < n_elems && k < n && x[j] != 0) {
       const uint32_t a = uint32_t(run - o0), e = uint32_t(run + x[j] - o0);
       for (uint32_t blk = (a + kChunk - 1) / kChunk; blk * uint32_t(kChunk) < e; ++blk)
         first[sb + blk] = k;
     }
     run += x[j];
   }
+  // front lists: the render's entries are its front entries
+  if (front && map && e_first + kScanTile == row + n_pad && threadIdx.x == kThreads - 1) {
+    const uint32_t d = uint32_t(run - o0);
+    seg->len[v] = d;
+    front->n_front[v] = d;
+    front->app_base[v] = seg->start[v] + (d + kSegment - 1) / kSegment * kSegment;
+    front->app_end[v] = seg->start[v + 1];
+  }
+}
+
+// ---- front lists (front.hpp)
+// Keep bitmap of every render with a depth cut: a tile is kept when at most
+// `keep` tile boxes of visible Gaussians cover it.  The boxes of every s-th
+// Gaussian of the depth order (s = ceil(n_vis / kKeepSample)) are added as
+// +1 / -1 at their corners to a grid in LDS, whose 2D prefix sums times s
+// estimate the cover counts.  One workgroup per render; renders with more than
+// kKeepGrid grid cells get no cut (the host leaves front16 at 0 for them).
+constexpr int kKeepThreads = 1024;
+constexpr int kKeepGrid = 16384;
+constexpr uint32_t kKeepSample = 4096;
+constexpr int kKeepWordsMax = 512;  // keep bitmap words of a render (LDS copies)
+
+// The render's keep bitmap into LDS (the row walks test it for every row).
+__device__ __forceinline__ void load_keep(uint64_t* s_keep, const uint64_t* __restrict__ bits,
+                                          const ViewSlot& sl) {
+  const int nw = int(keep_words(sl.v.tiles_x)) * sl.v.tiles_y;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) s_keep[i] = bits[sl.keep_base + i];
+}
+
+__global__ __launch_bounds__(kKeepThreads) void front_keep_kernel(
+    const ViewSlot* __restrict__ slots, const uint32_t* __restrict__ order,
+    const Rect16* __restrict__ rects, const unsigned long long* __restrict__ totals, uint32_t n,
+    uint32_t n_pad, int32_t keep, uint64_t* __restrict__ bits) {
+  __shared__ int32_t s_c[kKeepGrid];
+  const uint32_t v = blockIdx.x;
+  const ViewSlot& sl = slots[v];
+  if (!sl.front16) return;
+  const int tx = sl.v.tiles_x, ty = sl.v.tiles_y, w1 = tx + 1, h1 = ty + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = kKeepThreads / 64;
+  for (int i = threadIdx.x; i < w1 * h1; i += kKeepThreads) s_c[i] = 0;
+  __syncthreads();
+  const uint32_t nvis = uint32_t(totals[2 * v]);
+  const uint32_t step = (nvis + kKeepSample - 1) / kKeepSample;
+  const uint32_t* __restrict__ ord = order + size_t(v) * n_pad;
+  const Rect16* __restrict__ rc = rects + size_t(v) * n;
+  {
+    // the sample's boxes, all loads in flight at once (kKeepSample / kKeepThreads each)
+    constexpr int kPer = int(kKeepSample) / kKeepThreads;
+    uint32_t gi[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t j = threadIdx.x + uint32_t(q) * kKeepThreads;
+      gi[q] = j * step < nvis ? ord[j * step] : 0xffffffffu;
+    }
+    Rect16 box[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      box[q] = gi[q] != 0xffffffffu ? rc[gi[q]] : Rect16{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const Rect16 r = box[q];
+      if (r.x0 >= r.x1) continue;
+      // (corners on the last row or column change no tile's sum)
+      atomicAdd(&s_c[int(r.y0) * w1 + int(r.x0)], 1);
+      if (int(r.x1) < tx) atomicAdd(&s_c[int(r.y0) * w1 + int(r.x1)], -1);
+      if (int(r.y1) < ty) {
+        atomicAdd(&s_c[int(r.y1) * w1 + int(r.x0)], -1);
+        if (int(r.x1) < tx) atomicAdd(&s_c[int(r.y1) * w1 + int(r.x1)], 1);
+      }
+    }
+  }
+  __syncthreads();
+  // prefix sums along the rows, then down the columns: a wavefront per line,
+  // four lines interleaved
+  for (int r0 = wave * 4; r0 < ty; r0 += NW * 4) {
+    int32_t carry[4] = {0, 0, 0, 0};
+    for (int c0 = 0; c0 < tx; c0 += 64) {
+      const int c = c0 + lane;
+      int32_t x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = (r0 + q < ty && c < tx) ? s_c[(r0 + q) * w1 + c] : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = wave_incl_scan(x[q], lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (r0 + q < ty && c < tx) s_c[(r0 + q) * w1 + c] = carry[q] + x[q];
+        carry[q] += __shfl(x[q], 63, 64);
+      }
+    }
+  }
+  __syncthreads();
+  for (int c0w = wave * 4; c0w < tx; c0w += NW * 4) {
+    int32_t carry[4] = {0, 0, 0, 0};
+    for (int rr = 0; rr < ty; rr += 64) {
+      const int r = rr + lane;
+      int32_t x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = (c0w + q < tx && r < ty) ? s_c[r * w1 + c0w + q] : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = wave_incl_scan(x[q], lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (c0w + q < tx && r < ty) s_c[r * w1 + c0w + q] = carry[q] + x[q];
+        carry[q] += __shfl(x[q], 63, 64);
+      }
+    }
+  }
+  __syncthreads();
+  const int words = int(keep_words(tx));
+  const int64_t lim = int64_t(keep);
+  for (int q = wave; q < ty * words; q += NW) {
+    const int y = q / words, x = (q % words) * 64 + lane;
+    const unsigned long long m =
+        __ballot(x < tx && int64_t(s_c[y * w1 + x]) * int64_t(step) <= lim);
+    if (lane == 0) bits[sl.keep_base + q] = m;
+  }
+}
+
+// Per-Gaussian entry counts in depth order for front lists, counts[v][k]
+// (k < n_pad): the whole count below the render's depth cut r0, from r0 on the
+// kept tiles of the Gaussian's row runs, 0 past the visible Gaussians.  Also
+// copies the tile boxes of positions [r0, n_vis) into depth order (srect), for
+// the rasteriser's collection of a tile's rest entries.  The rows of a
+// wavefront's Gaussians are walked together (rowwalk.hpp).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void front_counts_kernel(
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ whole,
+    const Rect16* __restrict__ rects, const Rec<T>* __restrict__ recs,
+    const ViewSlot* __restrict__ slots, const unsigned long long* __restrict__ totals,
+    const uint64_t* __restrict__ bits, uint32_t n, uint32_t n_pad, uint64_t total,
+    uint32_t* __restrict__ counts, Rect16* __restrict__ srect) {
+  __shared__ uint32_t s_cnt[kThreads];
+  __shared__ uint64_t s_keep[kKeepWordsMax];
+  const uint64_t i0 = uint64_t(blockIdx.x) * kThreads;
+  if (i0 >= total) return;  // (whole workgroups only)
+  const uint64_t i = i0 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint32_t v = uint32_t(i0 / n_pad);  // n_pad % kThreads == 0: one render per workgroup
+  const uint32_t k = uint32_t(i - uint64_t(v) * n_pad);
+  const ViewSlot& sl = slots[v];
+  const uint32_t nvis = uint32_t(totals[2 * v]);
+  const uint32_t r0 = front_cut(nvis, sl.front16);
+  const uint32_t kfirst = uint32_t(i0 - uint64_t(v) * n_pad);
+  if (kfirst >= nvis || kfirst + kThreads <= r0) {
+    // no Gaussian of this workgroup is cut: whole counts (0 past the visible ones)
+    counts[i] = k < nvis ? whole[size_t(v) * n + order[i]] : 0u;
+    return;
+  }
+  if (sl.front16) load_keep(s_keep, bits, sl);  // (only renders with a cut have a bitmap)
+  const uint32_t words = keep_words(sl.v.tiles_x);
+  __syncthreads();
+  uint32_t c = 0;
+  SpanGeom sg = {};
+  sg.W = sl.v.W;
+  sg.H = sl.v.H;
+  sg.sh = __builtin_ctz(unsigned(sl.v.tile_size));
+  int y0 = 0, y1 = 0;
+  if (k < nvis) {
+    const uint32_t gi = order[i];
+    if (k < r0) {
+      c = whole[size_t(v) * n + gi];
+    } else {
+      const Rect16 r = rects[size_t(v) * n + gi];
+      srect[i] = r;
+      // rows walked only where the box holds a kept tile
+      if (any_kept_in_box(s_keep, words, r.x0, r.y0, r.x1, r.y1)) {
+        sg = geom_of(recs[size_t(v) * n + gi], r, sl.v);
+        y0 = r.y0;
+        y1 = r.y1;
+      }
+    }
+  }
+  s_cnt[threadIdx.x] = c;
+  __syncthreads();
+  const int wave0 = threadIdx.x & ~63;
+  wave_rows(sg, y0, y1, lane, [&](bool ok, int o, int y, int x0, int x1) {
+    if (ok && x0 < x1) atomicAdd(&s_cnt[wave0 + o], kept_in_run(s_keep + size_t(y) * words, x0, x1));
+  });
+  __syncthreads();
+  counts[i] = s_cnt[threadIdx.x];
+}
+
+// Entries of the Gaussians from each render's depth cut on (front lists,
+// front.hpp): their kept tiles only, at their places in the emitted list
+// (offsets; counts from front_counts), row by row and in column order.  The
+// rows of a wavefront's Gaussians are walked together (rowwalk.hpp); each row
+// finds its place from a wavefront scan of the rows' entry counts within its
+// Gaussian's run of rows, plus what the Gaussian's earlier rows took (s_pos).
+// Runs before emit_block_kernel, which reads the digits back for its counts.
+template <typename T, bool PACKED>
+__global__ __launch_bounds__(kThreads) void emit_cut_kernel(
+    const uint32_t* __restrict__ order, const uint64_t* __restrict__ offsets,
+    const uint32_t* __restrict__ counts, const Rect16* __restrict__ rects,
+    const Rec<T>* __restrict__ recs, const ViewSlot* __restrict__ slots,
+    const SegTable* __restrict__ seg, const unsigned long long* __restrict__ totals,
+    const uint64_t* __restrict__ keep, uint32_t n, uint32_t n_pad, uint64_t total,
+    uint32_t* __restrict__ out_a, void* __restrict__ out_b) {
+  using BType = typename std::conditional<PACKED, uint8_t, uint32_t>::type;
+  __shared__ uint64_t s_keep[kKeepWordsMax];
+  __shared__ uint32_t s_pos[kThreads];
+  const uint64_t i0 = uint64_t(blockIdx.x) * kThreads;
+  if (i0 >= total || seg->overflow) return;
+  const uint32_t v = uint32_t(i0 / n_pad);
+  if (v >= seg->count) return;
+  const ViewSlot& sl = slots[v];
+  const uint32_t nvis = uint32_t(totals[2 * v]);
+  const uint32_t r0 = front_cut(nvis, sl.front16);
+  const uint32_t kfirst = uint32_t(i0 - uint64_t(v) * n_pad);
+  if (!sl.front16 || kfirst >= nvis || kfirst + kThreads <= r0) return;
+  load_keep(s_keep, keep, sl);
+  const uint32_t words = keep_words(sl.v.tiles_x);
+  const int lane = threadIdx.x & 63, wave0 = threadIdx.x & ~63;
+  const uint64_t i = i0 + threadIdx.x;
+  const uint32_t k = kfirst + threadIdx.x;
+  const size_t row = size_t(v) * n_pad;
+  SpanGeom sg = {};
+  sg.W = sl.v.W;
+  sg.H = sl.v.H;
+  sg.sh = __builtin_ctz(unsigned(sl.v.tile_size));
+  int y0 = 0, y1 = 0;
+  uint32_t gi = 0;
+  if (k >= r0 && k < nvis && counts[i] != 0u) {
+    gi = order[i];
+    const Rect16 r = rects[size_t(v) * n + gi];
+    sg = geom_of(recs[size_t(v) * n + gi], r, sl.v);
+    y0 = r.y0;
+    y1 = r.y1;
+    s_pos[threadIdx.x] = seg->start[v] + uint32_t(offsets[i] - offsets[row]);
+  }
+  __syncthreads();
+  const uint32_t tx = uint32_t(sl.v.tiles_x);
+  wave_rows(sg, y0, y1, lane, [&](bool ok, int o, int y, int x0, int x1) {
+    const uint64_t* __restrict__ krow = s_keep + size_t(ok ? y : 0) * words;
+    const uint32_t c = (ok && x0 < x1) ? kept_in_run(krow, x0, x1) : 0u;
+    const uint32_t incl = wave_incl_scan(c, lane), excl = incl - c;
+    // the lanes of one Gaussian's rows are consecutive: where its run starts
+    const int prev_o = __shfl_up(o, 1, 64);
+    const int next_o = __shfl_down(o, 1, 64);
+    const bool next_ok = __shfl_down(ok ? 1 : 0, 1, 64) != 0;
+    const unsigned long long starts = __ballot(ok && (lane == 0 || prev_o != o));
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int first_lane = 63 - __builtin_clzll(starts & upto | 1ull);
+    const uint32_t base_excl = __shfl(excl, first_lane, 64);
+    const uint32_t gg = __shfl(gi, o, 64);
+    if (ok && c) {
+      uint32_t pos = s_pos[wave0 + o] + (excl - base_excl);
+      for (int w = x0 >> 6; w <= (x1 - 1) >> 6; ++w) {
+        uint64_t m = krow[w];
+        const int wl = w << 6;
+        if (x0 > wl) m &= ~0ull << (x0 - wl);
+        if (x1 - wl < 64) m &= (1ull << (x1 - wl)) - 1ull;
+        for (; m; m &= m - 1ull, ++pos) {
+          const uint32_t tile = uint32_t(y) * tx + uint32_t(wl + __builtin_ctzll(m));
+          if (PACKED) {
+            out_a[pos] = gg | ((tile >> 8) << 24);
+            static_cast<BType*>(out_b)[pos] = BType(tile & 255u);
+          } else {
+            out_a[pos] = tile;
+            static_cast<BType*>(out_b)[pos] = BType(gg);
+          }
+        }
+      }
+    }
+    // the last lane of a Gaussian's run carries the run's entries forward
+    if (ok && (lane == 63 || next_o != o || !next_ok)) s_pos[wave0 + o] += incl - base_excl;
+  });
 }
 
 // Emission of the tile entries, one block of 4096 entries (in emission order:
@@ -552,12 +825,15 @@ __global__ __launch_bounds__(kThreads) void count_offsets_kernel(
 // run lengths, and its entries inside the block written to LDS; the block is
 // then written out coalesced.  PACKED: out_a = Gaussian index | high tile
 // byte << 24, out_b = low tile byte (bytes); otherwise out_a = tile id, out_b
-// = Gaussian index (words).
+// = Gaussian index (words).  With a depth cut (front lists, front.hpp) the
+// entries of the Gaussians from the cut on, which emit_cut_kernel has already
+// written, are only read back for the digit counts.
 template <typename T, bool PACKED>
 __global__ __launch_bounds__(kThreads) void emit_block_kernel(
     const uint32_t* __restrict__ order, const uint64_t* __restrict__ offsets,
     const Rect16* __restrict__ rects, const Rec<T>* __restrict__ recs,
     const ViewSlot* __restrict__ slots, const SegTable* __restrict__ seg,
+    const unsigned long long* __restrict__ totals, const uint64_t* __restrict__ keep,
     const uint32_t* __restrict__ first, uint32_t n, uint32_t n_pad, uint32_t* __restrict__ out_a,
     void* __restrict__ out_b, uint32_t* __restrict__ lo_counts) {
   // (packed: the low tile bytes as bytes, so that more workgroups fit a CU)
@@ -586,15 +862,21 @@ __global__ __launch_bounds__(kThreads) void emit_block_kernel(
   const uint64_t o0 = offsets[row];
   const ViewDev vd = slots[s].v;
   const uint32_t tx = uint32_t(vd.tiles_x);
-  for (uint32_t q = tid; q < nvalid; q += kThreads) {  // (every slot is written below)
+  // depth positions [0, r0) emitted here, their entries [0, f0) of the render
+  // (r0 = n: no cut, every entry)
+  const uint32_t r0 =
+      (keep && slots[s].front16) ? front_cut(uint32_t(totals[2 * s]), slots[s].front16) : n;
+  const uint32_t f0 = r0 < n ? uint32_t(offsets[row + r0] - o0) : 0xffffffffu;
+  const uint32_t nf = lo >= f0 ? 0u : (hi <= f0 ? nvalid : f0 - lo);  // block entries emitted here
+  for (uint32_t q = tid; q < nf; q += kThreads) {  // (every slot is written below)
     s_a[q] = 0u;
     s_b[q] = 0u;
   }
-  for (uint32_t kb = first[b];; kb += kThreads) {
+  for (uint32_t kb = first[b]; nf > 0u; kb += kThreads) {
     const uint32_t k = kb + uint32_t(tid);
     uint32_t a = hi, rows = 0;
     if (k < n) a = uint32_t(offsets[row + k] - o0);
-    const bool has = k < n && a < hi;
+    const bool has = k < r0 && a < hi;
     if (has) {
       const uint32_t gi = order[row + k];
       const Rect16 r = rects[size_t(s) * n + gi];
@@ -669,9 +951,15 @@ __global__ __launch_bounds__(kThreads) void emit_block_kernel(
   __syncthreads();
   const uint32_t e0 = b * uint32_t(kChunk);
   for (uint32_t q = tid; q < nvalid; q += kThreads) {
-    out_a[e0 + q] = s_a[q];
-    static_cast<BType*>(out_b)[e0 + q] = s_b[q];
-    if (count) atomicAdd(&s_hist[uint32_t(s_b[q]) & 255u], 1u);
+    BType d;
+    if (q < nf) {
+      d = s_b[q];
+      out_a[e0 + q] = s_a[q];
+      static_cast<BType*>(out_b)[e0 + q] = d;
+    } else {
+      d = static_cast<const BType*>(out_b)[e0 + q];
+    }
+    if (count) atomicAdd(&s_hist[uint32_t(d) & 255u], 1u);
   }
   if (count) {
     __syncthreads();
@@ -1118,10 +1406,11 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
   return hipSuccess;
 }
 
-hipError_t seg_table(const unsigned long long* totals, int n_views, unsigned long long capacity,
-                     SegTable* seg, uint32_t* overflow_out, hipStream_t stream) {
-  hipLaunchKernelGGL(seg_table_kernel, dim3(1), dim3(64), 0, stream, totals, n_views, capacity,
-                     seg, overflow_out);
+hipError_t seg_table(const unsigned long long* totals, const ViewSlot* slots, int n_views,
+                     unsigned long long capacity, SegTable* seg, uint32_t* overflow_out,
+                     hipStream_t stream) {
+  hipLaunchKernelGGL(seg_table_kernel, dim3(1), dim3(64), 0, stream, totals, slots, n_views,
+                     capacity, seg, overflow_out);
   return hipGetLastError();
 }
 
@@ -1131,31 +1420,51 @@ size_t emit_temp_bytes(uint64_t capacity) {
 
 template <typename T>
 hipError_t emit_blocks(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                       const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg, uint32_t n,
+                       const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
+                       const unsigned long long* totals, const uint64_t* keep,
+                       const uint32_t* counts, uint32_t n,
                        uint32_t n_pad, int n_views, uint64_t capacity, bool packed, void* temp,
                        uint32_t* out_a, void* out_b, void* sort_temp, hipStream_t stream) {
   const uint32_t blocks = uint32_t((capacity + kChunk - 1) / kChunk);
   if (n == 0 || n_views <= 0 || blocks == 0) return hipSuccess;
   const uint32_t* first = static_cast<const uint32_t*>(temp);  // written by the count scan
+  if (keep) {
+    const uint64_t total = uint64_t(n_pad) * uint64_t(n_views);
+    const dim3 grid(uint32_t((total + kThreads - 1) / kThreads));
+    if (packed)
+      hipLaunchKernelGGL((emit_cut_kernel<T, true>), grid, dim3(kThreads), 0, stream, order,
+                         offsets, counts, rects, recs, slots, seg, totals, keep, n, n_pad, total,
+                         out_a, out_b);
+    else
+      hipLaunchKernelGGL((emit_cut_kernel<T, false>), grid, dim3(kThreads), 0, stream, order,
+                         offsets, counts, rects, recs, slots, seg, totals, keep, n, n_pad, total,
+                         out_a, out_b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (packed)
     hipLaunchKernelGGL((emit_block_kernel<T, true>), dim3(blocks), dim3(kThreads), 0, stream,
-                       order, offsets, rects, recs, slots, seg, first, n, n_pad, out_a, out_b,
-                       static_cast<uint32_t*>(sort_temp));
+                       order, offsets, rects, recs, slots, seg, totals, keep, first, n, n_pad,
+                       out_a, out_b, static_cast<uint32_t*>(sort_temp));
   else
     hipLaunchKernelGGL((emit_block_kernel<T, false>), dim3(blocks), dim3(kThreads), 0, stream,
-                       order, offsets, rects, recs, slots, seg, first, n, n_pad, out_a, out_b,
-                       (uint32_t*)nullptr);
+                       order, offsets, rects, recs, slots, seg, totals, keep, first, n, n_pad,
+                       out_a, out_b, (uint32_t*)nullptr);
   return hipGetLastError();
 }
 
 template hipError_t emit_blocks<float>(const uint32_t*, const uint64_t*, const Rect16*,
                                        const Rec<float>*, const ViewSlot*, const SegTable*,
-                                       uint32_t, uint32_t, int, uint64_t, bool, void*, uint32_t*,
-                                       void*, void*, hipStream_t);
+                                       const unsigned long long*, const uint64_t*,
+                                       const uint32_t*, uint32_t,
+                                       uint32_t, int, uint64_t, bool, void*, uint32_t*, void*,
+                                       void*, hipStream_t);
 template hipError_t emit_blocks<double>(const uint32_t*, const uint64_t*, const Rect16*,
                                         const Rec<double>*, const ViewSlot*, const SegTable*,
-                                        uint32_t, uint32_t, int, uint64_t, bool, void*, uint32_t*,
-                                        void*, void*, hipStream_t);
+                                        const unsigned long long*, const uint64_t*,
+                                        const uint32_t*, uint32_t,
+                                        uint32_t, int, uint64_t, bool, void*, uint32_t*, void*,
+                                        void*, hipStream_t);
 
 hipError_t tile_ranges(const void* sorted_tiles, bool tiles16, const SegTable* seg,
                        const ViewSlot* slots, uint32_t total_tiles, uint64_t capacity,
@@ -1202,30 +1511,72 @@ size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views) {
 }
 
 hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
-                          const unsigned long long* totals, uint32_t n, uint32_t n_pad,
-                          int n_views, uint64_t* offsets, void* temp, unsigned long long capacity,
-                          SegTable* seg, uint32_t* overflow_out, uint32_t* first,
-                          hipStream_t stream) {
+                          const uint32_t* front_counts, const unsigned long long* totals,
+                          const ViewSlot* slots, uint32_t n, uint32_t n_pad, int n_views,
+                          uint64_t* offsets, void* temp, unsigned long long capacity,
+                          SegTable* seg, FrontTable* front, uint32_t* overflow_out,
+                          uint32_t* first, hipStream_t stream) {
   const uint64_t total = uint64_t(n_pad) * uint64_t(n_views);
   const uint64_t n_elems = total + 1;
   const uint64_t tiles = (n_elems + kScanTile - 1) / kScanTile;
-  const LoadCountGatherSeg ld{order, counts, totals, n, n_pad, total};
   uint64_t* sums = static_cast<uint64_t*>(temp);
   uint64_t* scanned = sums + tiles;
-  hipLaunchKernelGGL(count_sums_kernel, dim3(uint32_t(tiles)), dim3(kThreads), 0, stream, ld,
-                     sums, totals, n_views, capacity, seg, overflow_out);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   const bool direct = tiles <= kCountDirectTiles;
-  if (!direct) {
-    e = device_exclusive_scan<uint64_t, LoadT<uint64_t>>(LoadT<uint64_t>{sums, tiles}, scanned,
-                                                         tiles, scanned + tiles, stream);
+  auto run = [&](auto ld, FrontTable* ft) -> hipError_t {
+    hipLaunchKernelGGL(count_sums_kernel<decltype(ld)>, dim3(uint32_t(tiles)), dim3(kThreads), 0,
+                       stream, ld, sums, totals, slots, n_views, capacity, seg, overflow_out);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(count_offsets_kernel, dim3(uint32_t(tiles)), dim3(kThreads), 0, stream, ld,
-                     n_elems, sums, direct ? nullptr : scanned, seg, offsets, first);
+    if (!direct) {
+      e = device_exclusive_scan<uint64_t, LoadT<uint64_t>>(LoadT<uint64_t>{sums, tiles}, scanned,
+                                                           tiles, scanned + tiles, stream);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(count_offsets_kernel<decltype(ld)>, dim3(uint32_t(tiles)), dim3(kThreads),
+                       0, stream, ld, n, n_pad, n_elems, sums, direct ? nullptr : scanned, seg, ft,
+                       offsets, first);
+    return hipGetLastError();
+  };
+  if (front_counts) return run(LoadCountPlain{front_counts, total}, front);
+  return run(LoadCountGatherSeg{order, counts, totals, n, n_pad, total}, nullptr);
+}
+
+hipError_t front_keep(const ViewSlot* slots, int n_views, const uint32_t* order,
+                      const Rect16* rects, const unsigned long long* totals, uint32_t n,
+                      uint32_t n_pad, int32_t keep, uint64_t* bits, hipStream_t stream) {
+  if (n_views <= 0) return hipSuccess;
+  hipLaunchKernelGGL(front_keep_kernel, dim3(uint32_t(n_views)), dim3(kKeepThreads), 0, stream,
+                     slots, order, rects, totals, n, n_pad, keep, bits);
   return hipGetLastError();
 }
+
+bool front_grid_ok(int tiles_x, int tiles_y) {
+  return int64_t(tiles_x + 1) * int64_t(tiles_y + 1) <= int64_t(kKeepGrid) &&
+         int64_t(keep_words(tiles_x)) * int64_t(tiles_y) <= int64_t(kKeepWordsMax);
+}
+
+template <typename T>
+hipError_t front_counts(const uint32_t* order, const uint32_t* whole, const Rect16* rects,
+                        const Rec<T>* recs, const ViewSlot* slots,
+                        const unsigned long long* totals, const uint64_t* bits, uint32_t n,
+                        uint32_t n_pad, int n_views, uint32_t* counts, Rect16* srect,
+                        hipStream_t stream) {
+  const uint64_t total = uint64_t(n_pad) * uint64_t(n_views);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(front_counts_kernel<T>, dim3(uint32_t((total + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, stream, order, whole, rects, recs, slots, totals, bits, n,
+                     n_pad, total, counts, srect);
+  return hipGetLastError();
+}
+
+template hipError_t front_counts<float>(const uint32_t*, const uint32_t*, const Rect16*,
+                                        const Rec<float>*, const ViewSlot*,
+                                        const unsigned long long*, const uint64_t*, uint32_t,
+                                        uint32_t, int, uint32_t*, Rect16*, hipStream_t);
+template hipError_t front_counts<double>(const uint32_t*, const uint32_t*, const Rect16*,
+                                         const Rec<double>*, const ViewSlot*,
+                                         const unsigned long long*, const uint64_t*, uint32_t,
+                                         uint32_t, int, uint32_t*, Rect16*, hipStream_t);
 
 bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view) {
   return n <= (1u << 24) && max_tiles_per_view <= 65536u;

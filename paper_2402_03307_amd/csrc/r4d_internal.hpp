@@ -44,6 +44,24 @@ struct ViewSlot {
   ViewDev v;
   uint32_t tile_base;   // index of the render's first tile among all tiles of the batch
   uint64_t pix_base;    // index of its first pixel among all pixels of the batch
+  // front lists (front.hpp): depth cut fraction x 65536 (0: whole lists) and
+  // the render's keep bitmap (word offset)
+  uint32_t front16;
+  uint32_t keep_base;
+};
+
+// Per-render state of the front lists: where the rest area starts (absolute
+// list position, a multiple of kSegment) and ends, the rest entries taken so
+// far (each tile's share rounded up to kSegment), the tiles that took one,
+// and the front entries.  Zeroed with the run's counters; app_base, app_end
+// and n_front are set by the count scan.
+struct FrontTable {
+  uint32_t app_base[kMaxViews];
+  uint32_t app_end[kMaxViews];
+  uint32_t cursor[kMaxViews];
+  uint32_t rest_tiles[kMaxViews];
+  uint32_t n_front[kMaxViews];
+  uint32_t queued;  // tiles the forward's main pass left to its rest pass
 };
 
 // Segments of a segmented sort: segment s holds len[s] elements starting at
@@ -110,11 +128,14 @@ hipError_t onesweep_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint3
                          hipStream_t stream);
 
 // Segment table of the emitted list from the per-render entry counts
-// (totals[2v + 1]): render v starts at the sum of the earlier renders' counts,
-// each rounded up to kSegAlign; all segments empty and `overflow` set when
-// they exceed `capacity` (also written to *overflow_out when not null).
-hipError_t seg_table(const unsigned long long* totals, int n_views, unsigned long long capacity,
-                     SegTable* seg, uint32_t* overflow_out, hipStream_t stream);
+// (totals[2v + 1]): render v starts at the sum of the earlier renders'
+// segment extents (seg_extent: the count, with a depth cut plus room for the
+// rest ranges, rounded up to kSegAlign); all segments empty and `overflow`
+// set when they exceed `capacity` (also written to *overflow_out when not
+// null).
+hipError_t seg_table(const unsigned long long* totals, const ViewSlot* slots, int n_views,
+                     unsigned long long capacity, SegTable* seg, uint32_t* overflow_out,
+                     hipStream_t stream);
 
 size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
 // offsets[v * n_pad + k] = sum over renders u < v of all their entries plus the
@@ -122,12 +143,39 @@ size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
 // order[v] holds render v's totals[2v] visible Gaussians (the rest is unset).
 // Also writes the segment table of the emitted list (as seg_table, for
 // `capacity`) and first[b], the depth position of the Gaussian whose entries
-// hold the first entry of emission block b (emit_blocks' temp).
+// hold the first entry of emission block b (emit_blocks' temp).  The counts
+// are counts[v][order[v][k]] (whole lists) or, when front_counts is not null,
+// front_counts[v * n_pad + k] (front lists, front_counts below); then the
+// segment lengths become the renders' front entry counts and `front` gets
+// their rest areas.
 hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
-                          const unsigned long long* totals, uint32_t n, uint32_t n_pad,
-                          int n_views, uint64_t* offsets, void* temp, unsigned long long capacity,
-                          SegTable* seg, uint32_t* overflow_out, uint32_t* first,
-                          hipStream_t stream);
+                          const uint32_t* front_counts, const unsigned long long* totals,
+                          const ViewSlot* slots, uint32_t n, uint32_t n_pad, int n_views,
+                          uint64_t* offsets, void* temp, unsigned long long capacity,
+                          SegTable* seg, FrontTable* front, uint32_t* overflow_out,
+                          uint32_t* first, hipStream_t stream);
+
+// ---- front lists (front.hpp)
+// Keep bitmaps (rows of keep_words(tiles_x) words at each render's keep_base)
+// of the renders with front16 != 0: a tile is kept when at most `keep` tile
+// boxes of visible Gaussians cover it, counted on every s-th Gaussian of the
+// depth order (order: [V][n_pad]; s keeps the sample within 4096 boxes) and
+// scaled by s.  front_grid_ok: the render's tile grid fits the kernel
+// (otherwise the host gives it no cut).
+bool front_grid_ok(int tiles_x, int tiles_y);
+hipError_t front_keep(const ViewSlot* slots, int n_views, const uint32_t* order,
+                      const Rect16* rects, const unsigned long long* totals, uint32_t n,
+                      uint32_t n_pad, int32_t keep, uint64_t* bits, hipStream_t stream);
+// counts[v * n_pad + k]: entries of the front lists from render v's Gaussian at
+// depth position k (order[v][k]); whole: per-Gaussian counts of the whole
+// lists ([v][n]); srect[v * n_pad + k] = its tile box for k from the render's
+// depth cut to its visible count.
+template <typename T>
+hipError_t front_counts(const uint32_t* order, const uint32_t* whole, const Rect16* rects,
+                        const Rec<T>* recs, const ViewSlot* slots,
+                        const unsigned long long* totals, const uint64_t* bits, uint32_t n,
+                        uint32_t n_pad, int n_views, uint32_t* counts, Rect16* srect,
+                        hipStream_t stream);
 
 // Emission of every render's tile entries in depth order (each Gaussian's
 // tiles row by row, its row runs from tileset.hpp) into its segment, one
@@ -137,10 +185,15 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
 // temp: emit_temp_bytes(capacity), holding the first-Gaussian map of the count
 // scan.  packed: sort_temp is packed_tile_sort's temp, where the emission
 // writes the low-byte digit counts of its blocks (the sort's first histogram).
+// keep (nullable): the keep bitmaps; the Gaussians from a render's depth cut
+// on (totals[2v] visible) list only their kept tiles, counts[v * n_pad + k]
+// of them (front_counts).
 size_t emit_temp_bytes(uint64_t capacity);
 template <typename T>
 hipError_t emit_blocks(const uint32_t* order, const uint64_t* offsets, const Rect16* rects,
-                       const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg, uint32_t n,
+                       const Rec<T>* recs, const ViewSlot* slots, const SegTable* seg,
+                       const unsigned long long* totals, const uint64_t* keep,
+                       const uint32_t* counts, uint32_t n,
                        uint32_t n_pad, int n_views, uint64_t capacity, bool packed, void* temp,
                        uint32_t* out_a, void* out_b, void* sort_temp, hipStream_t stream);
 
@@ -181,7 +234,9 @@ hipError_t scan_u32(const uint32_t* a, uint32_t n, uint32_t* out, void* temp, hi
 // list, each pixel's transmittance and accumulated colour (Ck) in slot
 // ck_slot(list start, global tile, boundary index) of TS*TS pixels, the final
 // colour of every pixel, and each tile's walk length (its furthest last
-// contributor).  Slots stay below capacity / kSegment + tiles + 1.
+// contributor).  Slots stay below capacity / kSegment + tiles + 1.  With
+// front lists a tile's list is its front range followed by its rest range
+// (front.hpp: list_pos, boundary_slot).
 constexpr uint32_t kSegment = 256;
 
 template <typename T>
@@ -203,6 +258,26 @@ struct RasterSaved {
   // pixel, laid out like the flow images; null otherwise
   Vec2<T>* ckf;
   T* flow;
+  // per global tile, [start, end) of its rest range ([0, 0): none), zeroed
+  // before the forward
+  uint2* rest;
+};
+
+// What the forward needs to collect a front list's rest (front.hpp); keep
+// null: whole lists.  order and srect: [V][n_pad], the depth order and the
+// tile boxes in depth order from each render's cut on; totals[2v]: visible
+// Gaussians; table: the rest areas (cursors and tile counts advanced) and the
+// count of queue, the tiles left to the rest pass (room for every tile);
+// overflow: set if a rest area were too small (its size rules that out).
+struct FrontCollect {
+  const uint64_t* keep;
+  const uint32_t* order;
+  const Rect16* srect;
+  const unsigned long long* totals;
+  FrontTable* table;
+  uint32_t* queue;
+  uint32_t* overflow;
+  uint32_t n_pad;
 };
 
 // (tile size, pixels per lane) pairs the rasteriser is compiled for.
@@ -216,10 +291,13 @@ int raster_default_ppt(int tile_size, bool backward);
 // segment walks need (see kSegment).  A flow render (flows: [V][n] per-Gaussian
 // 2D flow, not null) also composites the flow into flow_image ([2][pixels] at
 // 2 * pix_base, background 0) and fills sv.ckf and sv.flow; it counts no
-// evaluations (n_eval must be null).
+// evaluations (n_eval must be null).  Front lists (fc.keep not null): a tile
+// whose front list runs out before its pixels stop collects its rest entries
+// into `values` and records them in sv.rest.
 template <typename T>
 hipError_t launch_raster_fwd(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
-                             const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
+                             uint32_t* values, const uint2* ranges, const FrontCollect& fc,
+                             const ViewSlot* slots,
                              int n_views, uint32_t total_tiles, int tile_size,
                              const SettingsDev& st, int ppt, T* image, T* flow_image, T* T_final,
                              uint32_t* n_contrib, uint32_t* n_eval, const RasterSaved<T>& sv,

@@ -19,6 +19,7 @@
 // (Sec. 3.2.2), which the backward differentiates like a colour.
 #include <hip/hip_runtime.h>
 
+#include "front.hpp"
 #include "r4d_internal.hpp"
 #include "rowwalk.hpp"
 
@@ -237,19 +238,118 @@ struct TileCfg {
   static_assert(kThreads % 64 == 0, "a tile must map onto whole wavefronts");
 };
 
+// Collection of a tile's rest entries (front.hpp): the Gaussians at depth
+// positions [r0, n_vis) of render vi whose row run in tile row ty covers
+// column tx, in depth order, into a range of the render's rest area.  Two
+// passes over the depth-ordered tile boxes, kItems positions per thread per
+// step: a count, then (after one reservation) the writes, each thread's hits
+// placed by a workgroup scan.  Returns [start, end) ([0, 0) for none).
+// s_red: NT / 64 + 1 words of LDS.
+template <typename T, int NT>
+__device__ uint2 collect_rest(const FrontCollect& fc, uint32_t vi, uint32_t front16,
+                              const Rec<T>* __restrict__ recs, const ViewDev& v, int tx, int ty,
+                              uint32_t* __restrict__ values, uint32_t* s_red) {
+  // (one position per thread and step, and loops kept rolled: this code shares
+  // the forward kernel's register budget)
+  constexpr int kItems = 1;
+  const uint32_t nvis = uint32_t(fc.totals[2 * vi]);
+  const uint32_t r0 = front_cut(nvis, front16);
+  const size_t row = size_t(vi) * fc.n_pad;
+  const Rect16* __restrict__ sr = fc.srect + row;
+  const uint32_t* __restrict__ ord = fc.order + row;
+  auto hit = [&](uint32_t k) -> bool {
+    const Rect16 r = sr[k];
+    if (tx < int(r.x0) || tx >= int(r.x1) || ty < int(r.y0) || ty >= int(r.y1)) return false;
+    int x0, x1;
+    row_span(geom_of(recs[ord[k]], r, v), ty, x0, x1);
+    return tx >= x0 && tx < x1;
+  };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t c = 0;
+#pragma unroll 1
+  for (uint32_t k0 = r0; k0 < nvis; k0 += uint32_t(NT * kItems)) {
+    const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) c += (kt + i < nvis && hit(kt + i)) ? 1u : 0u;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+  if (lane == 0) s_red[wave] = c;
+  __syncthreads();
+  uint32_t total = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) total += s_red[w];
+  __syncthreads();
+  if (total == 0u) return make_uint2(0u, 0u);
+  if (threadIdx.x == 0) {
+    const uint32_t take = (total + kSegment - 1) / kSegment * kSegment;
+    uint32_t a = fc.table->app_base[vi] + atomicAdd(&fc.table->cursor[vi], take);
+    if (uint64_t(a) + total > uint64_t(fc.table->app_end[vi])) {
+      atomicOr(fc.overflow, 1u);
+      a = 0xffffffffu;
+    } else {
+      atomicAdd(&fc.table->rest_tiles[vi], 1u);
+    }
+    s_red[NT / 64] = a;
+  }
+  __syncthreads();
+  const uint32_t a = s_red[NT / 64];
+  if (a == 0xffffffffu) return make_uint2(0u, 0u);
+  uint32_t run = 0;
+#pragma unroll 1
+  for (uint32_t k0 = r0; k0 < nvis; k0 += uint32_t(NT * kItems)) {
+    const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
+    uint32_t hm = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) hm |= (kt + i < nvis && hit(kt + i)) ? (1u << i) : 0u;
+    const uint32_t cnt = uint32_t(__popc(hm));
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_red[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      const uint32_t t = s_red[w];
+      before += w < wave ? t : 0u;
+      all += t;
+    }
+    __syncthreads();
+    uint32_t p = a + run + before + inc - cnt;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i)
+      if ((hm >> i) & 1u) values[p++] = ord[kt + i];
+    run += all;
+  }
+  // the workgroup reads these entries next
+  __threadfence_block();
+  __syncthreads();
+  return make_uint2(a, a + total);
+}
+
 // Forward.  A pixel that has stopped keeps its final transmittance in Tf and
 // continues with T = 0, which makes every later contribution zero and every later
 // transmittance test fail, so no per-pixel "done" flag is carried through the
 // loop.  COUNT counts, per pixel, the entries evaluated and the entries
-// blended, stored as a pair in n_eval (measurement builds only).
-template <typename T, int TS, int PPT, bool COUNT, bool FLOW>
+// blended, stored as a pair in n_eval (measurement builds only).  cut: the
+// tile holds a front list (front.hpp).  If its pixels outlast it, the main
+// pass (REST false) queues the tile and leaves it; the rest pass (REST true)
+// renders a queued tile from the start, collecting the rest of its list when
+// the front list runs out.
+template <typename T, int TS, int PPT, bool COUNT, bool FLOW, bool REST>
 __device__ __forceinline__ void raster_fwd_tile(
-    Staged<T>* s_rec, uint32_t* s_walk, const Rec<T>* __restrict__ recs,
-    const Vec2<T>* __restrict__ flows, const uint32_t* __restrict__ values, const uint2 rg,
-    int tile, uint32_t gtile, const ViewDev& v, const SettingsDev& st, T* __restrict__ image,
+    Staged<T>* s_rec, uint32_t* s_walk, uint32_t* s_red, const Rec<T>* __restrict__ recs,
+    const Vec2<T>* __restrict__ flows, uint32_t* __restrict__ values, const uint2 rg, bool cut,
+    const FrontCollect& fc, uint32_t vi, uint32_t front16, uint32_t tile_end, int tile,
+    uint32_t gtile, const ViewDev& v, const SettingsDev& st, T* __restrict__ image,
     T* __restrict__ flow_image, T* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
     uint32_t* __restrict__ n_eval, Ck<T>* __restrict__ ck, Vec2<T>* __restrict__ ckf,
-    T* __restrict__ img_copy, T* __restrict__ flow_copy, uint32_t* __restrict__ walk) {
+    T* __restrict__ img_copy, T* __restrict__ flow_copy, uint32_t* __restrict__ walk,
+    uint2* __restrict__ rest_out) {
   using Cfg = TileCfg<TS, PPT>;
   constexpr int NT = Cfg::kThreads;
   constexpr int NB = Cfg::kBatch;
@@ -272,14 +372,34 @@ __device__ __forceinline__ void raster_fwd_tile(
     last[k] = evals[k] = blends[k] = 0u;
   }
   if (threadIdx.x == 0) *s_walk = 0u;
-  for (uint32_t base = rg.x; base < rg.y; base += NB) {
+  // list positions [0, len): the front (or whole) list, then the rest once collected
+  uint2 rest = make_uint2(0u, 0u);
+  uint32_t len = rg.y - rg.x;
+  bool pending = cut;
+  for (uint32_t jbase = 0;; jbase += NB) {
     bool lane_done = true;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) lane_done &= !(Tr[k] > T(0));
     if (__syncthreads_count(lane_done) == NT) break;
-    const uint32_t i = base + threadIdx.x;
-    if (threadIdx.x < NB && i < rg.y) {
-      const uint32_t idx = values[i];
+    if (pending && jbase + NB >= len) {
+      // the front list ends in this batch (or at its end) with pixels still
+      // running
+      if (!REST) {
+        if (threadIdx.x == 0) fc.queue[atomicAdd(&fc.table->queued, 1u)] = gtile;
+        return;
+      }
+      // collect the rest before the batch, so that the boundary state below is
+      // saved wherever the list goes on
+      rest = collect_rest<T, NT>(fc, vi, front16, recs, v, tile % v.tiles_x, tile / v.tiles_x,
+                                 values, s_red);
+      len += rest.y - rest.x;
+      pending = false;
+      if (threadIdx.x == 0 && rest.y > rest.x) rest_out[gtile] = rest;
+    }
+    if (jbase >= len) break;
+    const uint32_t i = jbase + threadIdx.x;
+    if (threadIdx.x < NB && i < len) {
+      const uint32_t idx = values[list_pos(rg, rest, i)];
       Staged<T> sr = stage(recs[idx], e_min, amin);
       if (FLOW) {
         const Vec2<T> fl = flows[idx];
@@ -289,8 +409,7 @@ __device__ __forceinline__ void raster_fwd_tile(
       s_rec[threadIdx.x] = sr;
     }
     __syncthreads();
-    const int nb = int(rg.y - base < uint32_t(NB) ? rg.y - base : uint32_t(NB));
-    const uint32_t jbase = base - rg.x;
+    const int nb = int(len - jbase < uint32_t(NB) ? len - jbase : uint32_t(NB));
     if (__ballot(!lane_done)) {
 #pragma unroll 2
       for (int j = 0; j < nb; ++j) {
@@ -325,8 +444,9 @@ __device__ __forceinline__ void raster_fwd_tile(
     // state after the first m segments of the list, for the backward's
     // independent segment walks (only where the list goes on)
     const uint32_t done_n = jbase + uint32_t(NB);
-    if (done_n % kSegment == 0u && base + NB < rg.y) {
-      const size_t slot = size_t(ck_slot(rg.x, gtile, done_n / kSegment)) * (TS * TS);
+    if (done_n % kSegment == 0u && done_n < len) {
+      const size_t slot =
+          size_t(boundary_slot(rg, rest, gtile, tile_end, done_n / kSegment)) * (TS * TS);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const int pt = (int(threadIdx.x / TS) + k * Cfg::kRowStep) * TS + int(threadIdx.x % TS);
@@ -391,7 +511,8 @@ template <typename T, int TS, int PPT, bool FLOW>
 __device__ __forceinline__ void raster_bwd_tile(
     BwdShared<T, TS, PPT, FLOW>& sh, const Rec<T>* __restrict__ recs,
     const Vec2<T>* __restrict__ flows, const uint32_t* __restrict__ values, const uint2 rg,
-    int tile, uint32_t gtile, uint32_t seg, uint32_t walk, const ViewDev& v,
+    const uint2 rest, uint32_t tile_end, int tile, uint32_t gtile, uint32_t seg, uint32_t walk,
+    const ViewDev& v,
     const SettingsDev& st, const T* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const T* __restrict__ img_copy, const T* __restrict__ flow_copy,
     const Ck<T>* __restrict__ ck, const Vec2<T>* __restrict__ ckf,
@@ -415,7 +536,7 @@ __device__ __forceinline__ void raster_bwd_tile(
   const uint32_t lo = seg * kSegment;
   const uint32_t seg_end = lo + kSegment;
   const uint32_t hi = walk < seg_end ? walk : seg_end;
-  const size_t cslot = size_t(ck_slot(rg.x, gtile, seg + 1)) * (TS * TS);
+  const size_t cslot = size_t(boundary_slot(rg, rest, gtile, tile_end, seg + 1)) * (TS * TS);
   // Per pixel: the upstream gradients g (colour, then flow) and gacc = g . (colour
   // accumulated behind the current Gaussian, background included).  Only that
   // dot product enters dL/da, and g is fixed per pixel, so one running sum
@@ -468,7 +589,7 @@ __device__ __forceinline__ void raster_bwd_tile(
     const int nb = int(bend - bstart);
     if (threadIdx.x < NB) {
       if (int(threadIdx.x) < nb) {
-        const uint32_t idx = values[rg.x + bstart + threadIdx.x];
+        const uint32_t idx = values[list_pos(rg, rest, bstart + threadIdx.x)];
         s_idx[threadIdx.x] = idx;
         Staged<T> sr = stage(recs[idx], e_min, amin);
         if (FLOW) {
@@ -586,11 +707,12 @@ __device__ __forceinline__ int slot_of_tile(const ViewSlot* __restrict__ slots, 
 template <typename T, int TS, int PPT, bool COUNT, bool FLOW>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     const Rec<T>* __restrict__ recs, const Vec2<T>* __restrict__ flows, uint32_t n,
-    const uint32_t* __restrict__ values, const uint2* __restrict__ ranges,
+    uint32_t* __restrict__ values, const uint2* __restrict__ ranges, FrontCollect fc,
     const ViewSlot* __restrict__ slots, int n_views, uint32_t total_tiles, SettingsDev st,
     T* __restrict__ image, T* __restrict__ flow_image, T* __restrict__ T_final,
     uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_eval, RasterSaved<T> sv,
     uint32_t* __restrict__ tickets) {
+  constexpr int NT = TS * TS / PPT;
   __shared__ Staged<T> s_rec[TileCfg<TS, PPT>::kBatch];
   __shared__ uint32_t s_ticket, s_walk;
   for (uint32_t g = blockIdx.x; g < total_tiles;) {
@@ -598,18 +720,65 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     const ViewSlot& sl = slots[vi];
     const ViewDev v = sl.v;
     const size_t pb = size_t(sl.pix_base);
-    raster_fwd_tile<T, TS, PPT, COUNT, FLOW>(
-        s_rec, &s_walk, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr, values,
-        ranges[g], int(g - sl.tile_base), g, v, st, image + 3 * pb,
-        FLOW ? flow_image + 2 * pb : nullptr, T_final + pb, n_contrib + pb,
+    const int tile = int(g - sl.tile_base);
+    const uint32_t front16 = sl.front16;
+    // a front list: the render has a depth cut and the tile is not kept whole
+    bool cut = false;
+    if (fc.keep && front16) {
+      const uint32_t nvis = uint32_t(fc.totals[2 * vi]);
+      if (front_cut(nvis, front16) < nvis)
+        cut = !tile_kept(fc.keep + sl.keep_base + size_t(tile / v.tiles_x) * keep_words(v.tiles_x),
+                         tile % v.tiles_x);
+    }
+    const uint32_t tile_end = sl.tile_base + uint32_t(v.tiles_x) * uint32_t(v.tiles_y);
+    raster_fwd_tile<T, TS, PPT, COUNT, FLOW, false>(
+        s_rec, &s_walk, nullptr, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr,
+        values, ranges[g], cut, fc, uint32_t(vi), front16, tile_end, tile, g, v, st,
+        image + 3 * pb, FLOW ? flow_image + 2 * pb : nullptr, T_final + pb, n_contrib + pb,
         COUNT ? n_eval + 2 * pb : nullptr, sv.ck, sv.ckf, sv.img + 3 * pb,
-        FLOW ? sv.flow + 2 * pb : nullptr, sv.walk);
+        FLOW ? sv.flow + 2 * pb : nullptr, sv.walk, sv.rest);
     if (threadIdx.x == 0) s_ticket = gridDim.x + atomicAdd(tickets, 1u);
     __syncthreads();
     g = s_ticket;
     __syncthreads();
   }
 }
+
+// The rest pass of the front lists (front.hpp): the tiles the main pass
+// queued (their pixels outlasted their front lists), each rendered again from
+// the start with its rest collected, by a small persistent grid; with nothing
+// queued every workgroup returns at once.
+template <typename T, int TS, int PPT, bool COUNT, bool FLOW>
+__global__ __launch_bounds__(TS* TS / PPT) void raster_rest_kernel(
+    const Rec<T>* __restrict__ recs, const Vec2<T>* __restrict__ flows, uint32_t n,
+    uint32_t* __restrict__ values, const uint2* __restrict__ ranges, FrontCollect fc,
+    const ViewSlot* __restrict__ slots, int n_views, SettingsDev st, T* __restrict__ image,
+    T* __restrict__ flow_image, T* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
+    uint32_t* __restrict__ n_eval, RasterSaved<T> sv) {
+  constexpr int NT = TS * TS / PPT;
+  __shared__ Staged<T> s_rec[TileCfg<TS, PPT>::kBatch];
+  __shared__ uint32_t s_walk;
+  __shared__ uint32_t s_red[NT / 64 + 1];
+  const uint32_t count = fc.table->queued;
+  for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const uint32_t g = fc.queue[it];
+    const int vi = slot_of_tile(slots, n_views, g);
+    const ViewSlot& sl = slots[vi];
+    const ViewDev v = sl.v;
+    const size_t pb = size_t(sl.pix_base);
+    const uint32_t tile_end = sl.tile_base + uint32_t(v.tiles_x) * uint32_t(v.tiles_y);
+    raster_fwd_tile<T, TS, PPT, COUNT, FLOW, true>(
+        s_rec, &s_walk, s_red, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr,
+        values, ranges[g], true, fc, uint32_t(vi), sl.front16, tile_end, int(g - sl.tile_base), g,
+        v, st, image + 3 * pb, FLOW ? flow_image + 2 * pb : nullptr, T_final + pb,
+        n_contrib + pb, COUNT ? n_eval + 2 * pb : nullptr, sv.ck, sv.ckf, sv.img + 3 * pb,
+        FLOW ? sv.flow + 2 * pb : nullptr, sv.walk, sv.rest);
+    __syncthreads();
+  }
+}
+
+// Workgroups of the rest pass.
+constexpr uint32_t kRestGroups = 256;
 
 // Length classes of the tiles' last segments (seg_queue_kernel) and where the
 // queue lengths sit in the backward's ticket words.
@@ -660,6 +829,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_bwd_kernel(
     const size_t pb = size_t(sl.pix_base);
     raster_bwd_tile<T, TS, PPT, FLOW>(
         sh, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr, values, ranges[g],
+        sv.rest[g], sl.tile_base + uint32_t(v.tiles_x) * uint32_t(v.tiles_y),
         int(g - sl.tile_base), g, seg, sv.walk[g], v, st, T_final + pb, n_contrib + pb,
         sv.img + 3 * pb, FLOW ? sv.flow + 2 * pb : nullptr, sv.ck, sv.ckf, dL_dimage + 3 * pb,
         FLOW ? dL_dflow + 2 * pb : nullptr, grad2d + size_t(vi) * kComps<FLOW> * n);
@@ -799,7 +969,8 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const float* __restri
 
 template <typename T, int TS, int PPT>
 hipError_t raster_fwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
-                          const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
+                          uint32_t* values, const uint2* ranges, const FrontCollect& fc,
+                          const ViewSlot* slots,
                           int n_views, uint32_t total_tiles, const SettingsDev& st, T* image,
                           T* flow_image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
                           const RasterSaved<T>& sv, uint32_t* tickets, hipStream_t stream) {
@@ -815,16 +986,31 @@ hipError_t raster_fwd_cfg(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
   if (grid == 0) return hipSuccess;
   if (flows)
     hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false, true>), dim3(grid), dim3(NT), 0,
-                       stream, recs, flows, n, values, ranges, slots, n_views, total_tiles, st,
-                       image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
+                       stream, recs, flows, n, values, ranges, fc, slots, n_views, total_tiles,
+                       st, image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
   else if (n_eval)
     hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, true, false>), dim3(grid), dim3(NT), 0,
-                       stream, recs, flows, n, values, ranges, slots, n_views, total_tiles, st,
-                       image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
+                       stream, recs, flows, n, values, ranges, fc, slots, n_views, total_tiles,
+                       st, image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
   else
     hipLaunchKernelGGL((raster_fwd_kernel<T, TS, PPT, false, false>), dim3(grid), dim3(NT), 0,
-                       stream, recs, flows, n, values, ranges, slots, n_views, total_tiles, st,
-                       image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
+                       stream, recs, flows, n, values, ranges, fc, slots, n_views, total_tiles,
+                       st, image, flow_image, T_final, n_contrib, n_eval, sv, tickets);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !fc.keep) return e;
+  const dim3 rgrid(total_tiles < kRestGroups ? total_tiles : kRestGroups);
+  if (flows)
+    hipLaunchKernelGGL((raster_rest_kernel<T, TS, PPT, false, true>), rgrid, dim3(NT), 0, stream,
+                       recs, flows, n, values, ranges, fc, slots, n_views, st, image, flow_image,
+                       T_final, n_contrib, n_eval, sv);
+  else if (n_eval)
+    hipLaunchKernelGGL((raster_rest_kernel<T, TS, PPT, true, false>), rgrid, dim3(NT), 0, stream,
+                       recs, flows, n, values, ranges, fc, slots, n_views, st, image, flow_image,
+                       T_final, n_contrib, n_eval, sv);
+  else
+    hipLaunchKernelGGL((raster_rest_kernel<T, TS, PPT, false, false>), rgrid, dim3(NT), 0,
+                       stream, recs, flows, n, values, ranges, fc, slots, n_views, st, image,
+                       flow_image, T_final, n_contrib, n_eval, sv);
   return hipGetLastError();
 }
 
@@ -901,12 +1087,12 @@ int raster_default_ppt(int tile_size, bool backward) {
 
 template <typename T>
 hipError_t launch_raster_fwd(const Rec<T>* recs, const Vec2<T>* flows, uint32_t n,
-                             const uint32_t* values, const uint2* ranges, const ViewSlot* slots,
-                             int n_views, uint32_t total_tiles, int tile_size,
-                             const SettingsDev& st, int ppt, T* image, T* flow_image, T* T_final,
-                             uint32_t* n_contrib, uint32_t* n_eval, const RasterSaved<T>& sv,
-                             uint32_t* tickets, hipStream_t stream) {
-  R4D_RASTER_DISPATCH(raster_fwd_cfg, recs, flows, n, values, ranges, slots, n_views,
+                             uint32_t* values, const uint2* ranges, const FrontCollect& fc,
+                             const ViewSlot* slots, int n_views, uint32_t total_tiles,
+                             int tile_size, const SettingsDev& st, int ppt, T* image,
+                             T* flow_image, T* T_final, uint32_t* n_contrib, uint32_t* n_eval,
+                             const RasterSaved<T>& sv, uint32_t* tickets, hipStream_t stream) {
+  R4D_RASTER_DISPATCH(raster_fwd_cfg, recs, flows, n, values, ranges, fc, slots, n_views,
                       total_tiles, st, image, flow_image, T_final, n_contrib, n_eval, sv, tickets,
                       stream)
 }
@@ -961,10 +1147,11 @@ hipError_t launch_l1_grad(const float* image, const float* target, int64_t count
 
 #define R4D_INST(T)                                                                          \
   template hipError_t launch_raster_fwd<T>(const Rec<T>*, const Vec2<T>*, uint32_t,           \
-                                           const uint32_t*, const uint2*, const ViewSlot*,    \
-                                           int, uint32_t, int, const SettingsDev&, int, T*,   \
-                                           T*, T*, uint32_t*, uint32_t*,                      \
-                                           const RasterSaved<T>&, uint32_t*, hipStream_t);    \
+                                           uint32_t*, const uint2*, const FrontCollect&,      \
+                                           const ViewSlot*, int, uint32_t, int,               \
+                                           const SettingsDev&, int, T*, T*, T*, uint32_t*,    \
+                                           uint32_t*, const RasterSaved<T>&, uint32_t*,       \
+                                           hipStream_t);                                      \
   template hipError_t launch_raster_bwd<T>(const Rec<T>*, const Vec2<T>*, uint32_t,           \
                                            const uint32_t*, const uint2*, const ViewSlot*,    \
                                            int, uint32_t, uint64_t, int, const SettingsDev&,  \

@@ -156,9 +156,74 @@ def cpu_tile_rows(rec: np.ndarray, rects: np.ndarray, depth_keys: np.ndarray, ti
     return total, out
 
 
+# ---- front lists (the library's depth cut of the tile lists, front.hpp)
+KEEP_GRID = 16384  # cover-grid cells a render may have and still get a cut
+
+
+def front_cut(n_vis: int, settings: dict, tiles_x: int, tiles_y: int):
+    """Depth position from which Gaussians are listed only in kept tiles, or
+    None when the render gets whole lists (front_fraction >= 1, or a cover
+    grid over KEEP_GRID cells)."""
+    f = float(settings.get("front_fraction", 1.0))
+    if f >= 1.0 or (tiles_x + 1) * (tiles_y + 1) > KEEP_GRID:
+        return None
+    f16 = int(min(65536, max(1, np.ceil(np.float64(np.float32(f)) * 65536.0))))
+    return min(n_vis, (n_vis * f16 + 65535) >> 16)
+
+
+def depth_positions(depth_keys: np.ndarray) -> np.ndarray:
+    """Position of every visible Gaussian in (depth key, index) order (-1 for
+    the rest)."""
+    vis = np.nonzero(depth_keys != 0xFFFFFFFF)[0]
+    order = vis[np.lexsort((vis, depth_keys[vis]))]
+    pos = np.full(depth_keys.size, -1, dtype=np.int64)
+    pos[order] = np.arange(order.size)
+    return pos
+
+
+KEEP_SAMPLE = 4096  # tile boxes the keep rule counts at most (every s-th in depth order)
+
+
+def kept_tiles(rects: np.ndarray, depth_keys: np.ndarray, tiles_x: int, tiles_y: int,
+               keep: int) -> np.ndarray:
+    """Kept tiles, [tiles] bool: those covered by at most `keep` tile boxes,
+    estimated from the boxes of every s-th visible Gaussian of the depth order
+    (s = ceil(n_vis / KEEP_SAMPLE)) times s."""
+    pos = depth_positions(depth_keys)
+    n_vis = int((pos >= 0).sum())
+    step = max(1, -(-n_vis // KEEP_SAMPLE))
+    order = np.argsort(np.where(pos >= 0, pos, np.iinfo(np.int64).max))[:n_vis]
+    r = rects[order[::step]].astype(np.int64)
+    cover = np.zeros((tiles_y, tiles_x), dtype=np.int64)
+    for x0, y0, x1, y1 in r:
+        cover[y0:y1, x0:x1] += 1
+    return (cover * step <= keep).reshape(-1)
+
+
+def front_lists(ref_vals: np.ndarray, ref_rng: np.ndarray, pos: np.ndarray, r0: int,
+                kept: np.ndarray):
+    """The front lists the library should emit from the whole lists: a kept
+    tile's whole list, any other tile's entries from depth positions below
+    r0.  Returns (values, ranges, {tile: the rest of its list})."""
+    lens = (ref_rng[:, 1].astype(np.int64) - ref_rng[:, 0].astype(np.int64))
+    tile = np.repeat(np.arange(lens.size), lens)
+    front = kept[tile] | (pos[ref_vals.astype(np.int64)] < r0)
+    counts = np.bincount(tile[front], minlength=lens.size)
+    ends = np.cumsum(counts)
+    rng = np.stack([np.where(counts > 0, ends - counts, 0), np.where(counts > 0, ends, 0)], 1)
+    rest = {}
+    for t in np.unique(tile[~front]):
+        rest[int(t)] = ref_vals[(tile == t) & ~front]
+    return ref_vals[front], rng.astype(np.uint32), rest
+
+
 def tile_lists(r4d, saved, view: int, n: int):
     """The GPU's tile lists of one render of a saved forward and their CPU
-    re-derivation: (values, ranges, ref_values, ref_ranges, stats)."""
+    re-derivation: (values, ranges, ref_values, ref_ranges, stats).  With
+    front lists, the values are the front lists (the first n_front entries of
+    VALUES) and the reference is derived from the whole lists by the front
+    rule; every rest the forward collected is checked here against the rest of
+    its tile's whole list."""
     s = saved.stats(view)
     ts = saved.config()["tile_size"]
     width, height = int(saved.views[view]["width"]), int(saved.views[view]["height"])
@@ -169,7 +234,21 @@ def tile_lists(r4d, saved, view: int, n: int):
     rng = saved.copy(view, r4d.BUF_RANGES, n).cpu().numpy().view(np.uint32)
     ref_vals, ref_rng = cpu_tile_lists(rec, rect, key, s["tiles_x"], s["tiles_y"], ts, width,
                                        height)
-    return vals, rng, ref_vals, ref_rng, s
+    settings = dict(r4d.default_settings(), **getattr(saved, "settings", {}))
+    r0 = front_cut(s["n_visible"], settings, s["tiles_x"], s["tiles_y"])
+    if r0 is None:
+        assert s["n_front"] == s["n_dup"] and s["rest_tiles"] == 0
+        return vals, rng, ref_vals, ref_rng, s
+    kept = kept_tiles(rect, key, s["tiles_x"], s["tiles_y"], int(settings["front_keep"]))
+    f_vals, f_rng, rest = front_lists(ref_vals, ref_rng, depth_positions(key), r0, kept)
+    rest_rng = saved.copy(view, r4d.BUF_REST, n).cpu().numpy().view(np.uint32)
+    got = np.nonzero(rest_rng[:, 1] > rest_rng[:, 0])[0]
+    assert got.size == s["rest_tiles"]
+    for t in got:
+        a, b = int(rest_rng[t, 0]), int(rest_rng[t, 1])
+        assert a >= s["n_front"] and a % 256 == 0
+        assert np.array_equal(vals[a:b], rest.get(int(t), np.zeros(0, np.uint32))), f"rest of {t}"
+    return vals[:s["n_front"]], rng, f_vals, f_rng, s
 
 
 def image_errors(gpu_img: np.ndarray, ref_img: np.ndarray, ambiguous: np.ndarray):

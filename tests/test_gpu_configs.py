@@ -30,7 +30,8 @@ import torch
 import workloads as W
 from oracle import render as O
 
-from helpers import PARAM_KEYS, cpu_tile_rows, image_errors, to_device
+from helpers import (PARAM_KEYS, cpu_tile_rows, depth_positions, front_cut, image_errors,
+                     kept_tiles, to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +66,9 @@ def large(r4d, device):
             "key": saved.copy(v, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32),
             "vals": saved.copy(v, r4d.BUF_VALUES, n).cpu().numpy().view(np.uint32),
             "rng": saved.copy(v, r4d.BUF_RANGES, n).cpu().numpy().view(np.uint32),
+            "rest": saved.copy(v, r4d.BUF_REST, n).cpu().numpy().view(np.uint32),
             "stats": saved.stats(v),
+            "settings": dict(r4d.default_settings(), **saved.settings),
         }
     cfg = saved.config()
     saved.release()
@@ -216,21 +219,32 @@ def test_3m_binning_bit_exact_on_tile_rows(large, vi):
     rows = sorted({0, ty // 3, ty // 2, (2 * ty) // 3, ty - 1})
     total, lists = cpu_tile_rows(o["rec"], o["rect"], o["key"], tx, rows, cfg["tile_size"],
                                  view["width"], view["height"])
-    print(f"render {vi}: D = {s['n_dup']} (CPU {total}), visible {s['n_visible']}", flush=True)
+    print(f"render {vi}: D = {s['n_dup']} (CPU {total}), visible {s['n_visible']}, front "
+          f"lists {s['n_front']}, rests {s['rest_tiles']}", flush=True)
     assert s["n_dup"] == total
     assert s["n_visible"] == int((o["key"] != 0xFFFFFFFF).sum())
-    rng, vals = o["rng"], o["vals"]
+    rng, vals, rest_rng = o["rng"], o["vals"], o["rest"]
+    # front lists: a kept tile's whole list, any other tile's entries from depth
+    # positions below the cut (the rest, when collected, is the remainder)
+    r0 = front_cut(s["n_visible"], o["settings"], tx, ty)
+    pos = depth_positions(o["key"])
+    kept = (kept_tiles(o["rect"], o["key"], tx, ty, int(o["settings"]["front_keep"]))
+            if r0 is not None else np.ones(tx * ty, dtype=bool))
     checked = 0
     for t, ref in lists.items():
+        front = kept[t] | (pos[ref.astype(np.int64)] < (r0 if r0 is not None else 1 << 62))
         a, b = int(rng[t, 0]), int(rng[t, 1])
         got = vals[a:b] if b > a else np.zeros(0, np.uint32)
-        assert np.array_equal(got, ref), f"tile {t}"
+        assert np.array_equal(got, ref[front]), f"tile {t}"
+        a, b = int(rest_rng[t, 0]), int(rest_rng[t, 1])
+        if b > a:
+            assert np.array_equal(vals[a:b], ref[~front]), f"rest of tile {t}"
         checked += ref.size
     print(f"{checked} entries on {len(lists)} tiles equal", flush=True)
     assert checked > 0
-    # ranges partition [0, D) in tile order
+    # ranges partition [0, n_front) in tile order
     lens = (rng[:, 1].astype(np.int64) - rng[:, 0].astype(np.int64))
-    assert lens.sum() == s["n_dup"]
+    assert lens.sum() == s["n_front"]
     nz = lens > 0
     assert np.all(rng[nz][1:, 0] == rng[nz][:-1, 1])
 

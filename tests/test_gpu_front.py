@@ -1,0 +1,199 @@
+"""Front tile lists: the tile lists cut at a depth position (settings
+front_fraction / front_keep, include/r4d.h), with the forward collecting the
+rest of a list whose pixels outlast it.  The rasteriser must see every list in
+full up to where its pixels stop, so renders through front lists equal renders
+through whole lists (front_fraction = 1):
+
+  * images, final transmittance and last-contributor counts bit-identical;
+  * gradients equal up to the order of the float atomics that sum them
+    (relative difference of each parameter group <= 1e-5);
+  * the emitted front lists and every collected rest bit-exact against the
+    CPU re-derivation of the rule (helpers.tile_lists).
+
+Cases: the 500k / 1352x1014 render at the default cut (0.1 of the visible
+Gaussians, tiles covered by at most 4096 tile boxes kept whole), and a forced
+collection on the 2k scene (the cut at the first depth position and no tile
+kept whole, or the cut at 0.3), so that nearly every tile collects its rest in
+the forward: three ragged views in per-view, fused and graph mode, a flow
+render, float64, and a static set.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+from helpers import tile_lists, to_device
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("means", "log_scales", "rotors", "opacity", "sh")
+WHOLE = {"front_fraction": 1.0}
+FORCED = ({"front_fraction": 0.0, "front_keep": -1}, {"front_fraction": 0.3, "front_keep": -1})
+
+
+@pytest.fixture(scope="module")
+def r4d():
+    import paper_2402_03307_amd as mod
+    return mod
+
+
+def ragged_views():
+    return [W.view((0.0, 0.0, -3.0), 128, 96, 150.0, 0.5),
+            W.view((2.5, -1.0, -2.0), 77, 131, 120.0, 0.2),
+            W.view((-1.0, 0.5, 3.0), 200, 64, 180.0, 0.9)]
+
+
+def _grads_close(a, b, tol=1e-5):
+    for k in a:
+        x = a[k].double().cpu()
+        y = b[k].double().cpu()
+        rel = float((x - y).norm() / max(float(y.norm()), 1e-30))
+        assert rel <= tol, (k, rel)
+
+
+def _step(r4d, rend, p, views, st, dl, n, flow=False, static=False):
+    """Forward (+ backward when dl is given); images, per-pixel saved buffers,
+    gradients, front stats of every view; the saved state's lists checked."""
+    if static:
+        imgs, saved = rend.forward_static(p, views, st, save=True)
+    elif flow:
+        imgs, fimgs, saved = rend.forward(p, views, st, save=True, flow=True)
+        imgs = list(imgs) + list(fimgs)
+    else:
+        imgs, saved = rend.forward(p, views, st, save=True)
+    imgs = [i.clone() for i in imgs]
+    saved.check()
+    bufs = [(saved.copy(v, r4d.BUF_TFINAL, n).clone(), saved.copy(v, r4d.BUF_NCONTRIB, n).clone())
+            for v in range(len(views))]
+    stats = [saved.stats(v) for v in range(len(views))]
+    if not static:
+        for v in range(len(views)):
+            vals, rng, ref_vals, ref_rng, _ = tile_lists(r4d, saved, v, n)
+            assert np.array_equal(vals, ref_vals), f"front lists of view {v}"
+            assert np.array_equal(rng, ref_rng), f"front ranges of view {v}"
+    grads = None
+    if dl is not None:
+        if static:
+            g = rend.backward_static(p, views, st, saved, dl)
+        elif flow:
+            g = rend.backward(p, views, st, saved, dl[:len(views)], grad_flows=dl[len(views):])
+        else:
+            g = rend.backward(p, views, st, saved, dl)
+        grads = {k: v.clone() for k, v in g.items()}
+    saved.release()
+    return imgs, bufs, grads, stats
+
+
+def _same(a, b):
+    imgs_a, bufs_a, grads_a, _ = a
+    imgs_b, bufs_b, grads_b, _ = b
+    for x, y in zip(imgs_a, imgs_b):
+        assert torch.equal(x, y)
+    for (t0, c0), (t1, c1) in zip(bufs_a, bufs_b):
+        assert torch.equal(t0, t1) and torch.equal(c0, c1)
+    if grads_a is not None:
+        _grads_close(grads_a, grads_b)
+
+
+def _upstream(views, seed, channels=3):
+    rng = np.random.default_rng(seed)
+    return [torch.as_tensor(rng.uniform(-1, 1, (channels, v["height"], v["width"])),
+                            dtype=torch.float32, device="cuda") for v in views]
+
+
+def test_front_lists_500k_equal_whole_lists(r4d, device):
+    g, views, st = W.scene_500k_step()
+    print("case: 500k 1352x1014, default cut vs whole lists", flush=True)
+    rend = r4d.Renderer(device)
+    p = to_device(g, device)
+    n = g["opacity"].shape[0]
+    dl = _upstream(views, 7)
+    front = _step(r4d, rend, p, views, st, dl, n)
+    whole = _step(r4d, rend, p, views, dict(st, **WHOLE), dl, n)
+    s = front[3][0]
+    print(f"whole lists {s['n_dup']} entries, front lists {s['n_front']}, "
+          f"rests {s['rest_tiles']} tiles / {s['rest_entries']} entries", flush=True)
+    assert whole[3][0]["n_front"] == s["n_dup"]
+    assert s["n_front"] < 0.5 * s["n_dup"]
+    _same(front, whole)
+
+
+@pytest.mark.parametrize("mode", ["per_view", "fused", "graph"])
+@pytest.mark.parametrize("cut", FORCED)
+def test_forced_rest_collection_ragged_views(r4d, device, mode, cut):
+    g, _, st = W.scene_2k()
+    views = ragged_views()
+    print(f"case: 2k scene, 3 ragged views, {mode}, cut {cut}", flush=True)
+    rend = r4d.Renderer(device)
+    p = to_device(g, device)
+    n = g["opacity"].shape[0]
+    dl = _upstream(views, 11)
+    whole = _step(r4d, rend, p, views, dict(st, mode=mode, **WHOLE), dl, n)
+    for rep in range(2 if mode == "graph" else 1):  # a graph is captured, then replayed
+        front = _step(r4d, rend, p, views, dict(st, mode=mode, **cut), dl, n)
+        rests = sum(s["rest_tiles"] for s in front[3])
+        print(f"replay {rep}: rests collected by {rests} tiles", flush=True)
+        assert rests > 10
+        _same(front, whole)
+
+
+@pytest.mark.parametrize("ts", [8, 32])
+def test_forced_rest_collection_tile_sizes(r4d, device, ts):
+    g, views, st = W.scene_2k()
+    print(f"case: 2k scene, tile {ts}, forced collection", flush=True)
+    rend = r4d.Renderer(device)
+    p = to_device(g, device)
+    n = g["opacity"].shape[0]
+    dl = _upstream(views, 13)
+    base = dict(st, tile_size=ts)
+    whole = _step(r4d, rend, p, views, dict(base, **WHOLE), dl, n)
+    front = _step(r4d, rend, p, views, dict(base, **FORCED[0]), dl, n)
+    assert front[3][0]["rest_tiles"] > 10
+    _same(front, whole)
+
+
+def test_forced_rest_collection_flow(r4d, device):
+    g, _, st = W.scene_2k()
+    views = ragged_views()[:2]
+    print("case: 2k scene flow render, forced collection", flush=True)
+    rend = r4d.Renderer(device)
+    p = to_device(g, device)
+    n = g["opacity"].shape[0]
+    dl = _upstream(views, 17) + _upstream(views, 19, channels=2)
+    whole = _step(r4d, rend, p, views, dict(st, mode="fused", **WHOLE), dl, n, flow=True)
+    front = _step(r4d, rend, p, views, dict(st, mode="fused", **FORCED[0]), dl, n, flow=True)
+    assert sum(s["rest_tiles"] for s in front[3]) > 10
+    _same(front, whole)
+
+
+def test_forced_rest_collection_f64(r4d, device):
+    g, views, st = W.scene_2k()
+    print("case: 2k scene float64, forced collection", flush=True)
+    g64 = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) else v) for k, v in g.items()}
+    rend = r4d.Renderer(device)
+    p = to_device(g64, device, torch.float64)
+    n = g["opacity"].shape[0]
+    dl = [x.double() for x in _upstream(views, 23)]
+    whole = _step(r4d, rend, p, views, dict(st, **WHOLE), dl, n)
+    front = _step(r4d, rend, p, views, dict(st, **FORCED[0]), dl, n)
+    assert front[3][0]["rest_tiles"] > 10
+    _same(front, whole)
+
+
+def test_forced_rest_collection_static(r4d, device):
+    g = W.static_gaussians(2000, 3)
+    views = ragged_views()
+    print("case: 2k static set, forced collection", flush=True)
+    st = W.settings(mode="fused")
+    rend = r4d.Renderer(device)
+    keys = ("means", "log_scales", "quats", "opacity", "sh")
+    p = {k: torch.as_tensor(np.ascontiguousarray(g[k])).to(device=device, dtype=torch.float32)
+         for k in keys}
+    p["sh_degree"] = int(g["sh_degree"])
+    n = g["opacity"].shape[0]
+    dl = _upstream(views, 29)
+    whole = _step(r4d, rend, p, views, dict(st, **WHOLE), dl, n, static=True)
+    front = _step(r4d, rend, p, views, dict(st, **FORCED[0]), dl, n, static=True)
+    assert sum(s["rest_tiles"] for s in front[3]) > 10
+    _same(front, whole)

@@ -89,7 +89,7 @@ def test_500k_binning_bit_exact(r4d, scene500k, device):
     n = g["opacity"].shape[0]
     vals, rng, ref_vals, ref_rng, s = tile_lists(r4d, saved, 0, n)
     print(f"D = {s['n_dup']}, visible = {s['n_visible']}", flush=True)
-    assert s["n_dup"] == ref_vals.size
+    assert s["n_front"] == ref_vals.size
     assert np.array_equal(vals, ref_vals)
     assert np.array_equal(rng, ref_rng)
 

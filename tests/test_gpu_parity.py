@@ -118,7 +118,7 @@ def test_binning_and_sort_bit_exact_2k(r4d, scene2k, device):
         n = g["opacity"].shape[0]
         vals, rng, ref_vals, ref_rng, s = tile_lists(r4d, saved, 0, n)
         key = saved.copy(0, r4d.BUF_DEPTHKEY, n).cpu().numpy().view(np.uint32)
-        assert s["n_dup"] == ref_vals.size
+        assert s["n_front"] == ref_vals.size
         assert np.array_equal(vals, ref_vals), f"tile {ts}: order differs"
         assert np.array_equal(rng, ref_rng), f"tile {ts}: ranges differ"
         assert s["n_visible"] == int((key != 0xFFFFFFFF).sum())
@@ -274,6 +274,50 @@ def test_gradients_fd_scene_vs_oracle(r4d, device):
         assert np.all(np.abs(gg - gr) <= 1e-3 * (np.abs(gr) + 1e-2 * np.abs(gr).max()) + 1e-7), k
 
 
+def test_degenerate_rotors_vs_oracle(r4d, device):
+    """Rotors whose squared norm is below 1e-12 before the App. A update (0,
+    all 1e-7) or after it (1 +- e0123 and a scaled copy) render as the
+    identity rotation and get an exactly zero rotor gradient, on five
+    Gaussians that contribute to the image; the rest of the scene keeps the
+    oracle's image and gradients."""
+    g, views, st = W.scene_fd_subset()
+    weight = np.random.default_rng(2).uniform(-1, 1, (3, 32, 32))
+    probe = O.render(g, views[0], st, requires_grad=True)
+    (probe["image"] * torch.as_tensor(weight)).sum().backward()
+    live = np.nonzero(probe["params"]["opacity"].grad.numpy())[0]
+    assert live.size >= 5
+    pick = live[:5]
+    g = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in g.items()}
+    rot = g["rotors"]
+    rot[:, pick] = 0.0
+    rot[:, pick[1]] = 1e-7
+    rot[0, pick[2]], rot[7, pick[2]] = 1.0, 1.0
+    rot[0, pick[3]], rot[7, pick[3]] = 1.0, -1.0
+    rot[0, pick[4]], rot[7, pick[4]] = 3.0, 3.0
+    print(f"case: degenerate rotors at {pick.tolist()}", flush=True)
+    ref = O.render(g, views[0], st, requires_grad=True)
+    (ref["image"] * torch.as_tensor(weight)).sum().backward()
+    assert np.all(ref["params"]["rotors"].grad.numpy()[:, pick] == 0.0)
+    p = to_device(g, device)
+    for k in ("means", "log_scales", "rotors", "opacity", "sh"):
+        p[k].requires_grad_(True)
+    img = r4d.render(p, views, st)[0]
+    err, n_amb = image_errors(img.detach().cpu().numpy().astype(np.float64),
+                              ref["image"].detach().numpy(), ref["ambiguous"].numpy())
+    print(f"max err {err:.3g}, ambiguous {n_amb}")
+    assert err <= IMG_TOL
+    (img * torch.as_tensor(weight, dtype=torch.float32, device=device)).sum().backward()
+    gro = p["rotors"].grad.cpu().numpy()
+    assert np.all(np.isfinite(gro))
+    assert np.all(gro[:, pick] == 0.0)
+    for k in ("means", "log_scales", "rotors", "opacity", "sh"):
+        gg = p[k].grad.cpu().numpy().astype(np.float64)
+        gr = ref["params"][k].grad.numpy()
+        rel = _rel(gg, gr)
+        print(f"{k}: rel {rel:.3g}")
+        assert rel <= 1e-3, k
+
+
 def test_gradients_fp64_match_central_differences(r4d, device):
     """The float64 instantiation of the same kernels: backward vs central
     differences of its own forward (h = 1e-6 max(1, |theta|))."""
@@ -343,7 +387,7 @@ def test_binning_paths_agree_on_large_image(r4d, device):
         _, _, imgs, saved = _render(r4d, g, [v], dict(st, tile_size=ts), device)
         n = g["opacity"].shape[0]
         vals, rng, ref_vals, ref_rng, s = tile_lists(r4d, saved, 0, n)
-        assert s["n_dup"] == ref_vals.size > 0
+        assert s["n_front"] == ref_vals.size > 0
         assert np.array_equal(vals, ref_vals), f"tile {ts}: order differs"
         assert np.array_equal(rng, ref_rng), f"tile {ts}: ranges differ"
         images.append(imgs[0].cpu().numpy())
