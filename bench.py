@@ -406,7 +406,8 @@ def kernel_source_digest():
 def stage_alg_bytes(n, k, renders, packed=True):
     """Algorithmic HBM bytes per launch of the memory-bound stages of one run.
     n Gaussians, k SH coefficients per channel; renders: (visible Gaussians,
-    tile entries, tiles) of each render in the run.  Every render reads the
+    tile entries emitted and sorted (the front lists), tiles) of each render in
+    the run.  Every render reads the
     parameters once; the preprocess backward reads them once for the run."""
     V = len(renders)
     vis = sum(r[0] for r in renders)
@@ -518,10 +519,11 @@ def main():
     print("stage ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stages.items()), file=sys.stderr,
           flush=True)
 
-    n_vis, D = stats["n_visible"], stats["n_dup"]
+    n_vis, D, D_front = stats["n_visible"], stats["n_dup"], stats["n_front"]
     k = (g["sh_degree"] + 1) ** 2
     tiles = stats["tiles_x"] * stats["tiles_y"]
-    alg_bytes = stage_alg_bytes(n, k, [(n_vis, D, tiles)])
+    # the binning stages emit and sort the front lists (D_front entries)
+    alg_bytes = stage_alg_bytes(n, k, [(n_vis, D_front, tiles)])
     dominant = max(stages, key=stages.get)
     dom_ms = stages[dominant]
     workload = "500k_1352x1014_tile16"
@@ -571,6 +573,8 @@ def main():
                   "fwd_frames_per_s": 1e3 / plain_fwd_ms, "fwd_ms": plain_fwd_ms},
         "n_visible": n_vis,
         "n_dup": D,
+        "front_lists": {"entries": D_front, "rest_tiles": stats["rest_tiles"],
+                        "rest_entries": stats["rest_entries"]},
         "pairs_evaluated_fwd": n_eval,
         "pairs_walked_bwd": n_contrib,
         "pairs_blended": n_blend,
@@ -660,9 +664,11 @@ def per_config(r4d, rend, dev, args):
     s = Stepper(r4d, rend, p, views, dict(st, mode="graph"), targets)
     ms = timed(s.step, 3, 1)
     s.check()
-    d_total = sum(s.last.stats(v)["n_dup"] for v in range(len(views)))
+    st3 = [s.last.stats(v) for v in range(len(views))]
     res["3m_16_renders_fwd_bwd"] = {"graph_ms_per_step": ms, "renders_per_s": 16e3 / ms,
-                                    "tile_entries_total": d_total}
+                                    "tile_entries_total": sum(x["n_dup"] for x in st3),
+                                    "front_entries_total": sum(x["n_front"] for x in st3),
+                                    "rest_tiles_total": sum(x["rest_tiles"] for x in st3)}
     # per-stage times of the same step in fused mode (one launch per stage over
     # all 16 renders), and the memory-bound stages' share of HBM peak
     fused = Stepper(r4d, rend, p, views, dict(st, mode="fused"), targets)
@@ -678,7 +684,7 @@ def per_config(r4d, rend, dev, args):
     renders = []
     for v in range(len(views)):
         sv = fused.last.stats(v)
-        renders.append((sv["n_visible"], sv["n_dup"], sv["tiles_x"] * sv["tiles_y"]))
+        renders.append((sv["n_visible"], sv["n_front"], sv["tiles_x"] * sv["tiles_y"]))
     fused.last.release()
     alg = stage_alg_bytes(int(g["opacity"].shape[0]), (g["sh_degree"] + 1) ** 2, renders)
     hbm = {}

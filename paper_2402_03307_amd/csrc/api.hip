@@ -87,7 +87,8 @@ struct RunLayout {
   // fixed block
   size_t meta, recs, flows, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp,
       ranges, T_final, n_contrib, n_eval, img_copy, flow_copy, walk, ptemp_fwd, keep, fcount,
-      srect, queue, zero_begin, status, totals, front, rest, dhist, tickets, dstatus, zero_end,
+      srect, queue, zero_begin, status, totals, front, rest, cover, dhist, tickets, dstatus,
+      zero_end,
       fixed_bytes;
   // entries block
   size_t tkA, tkB, tvA, tvB, tdig, thi, t16, etemp, ptemp, ck, ckf, tstatus, entries_bytes;
@@ -114,10 +115,10 @@ struct Plan {
   bool flow = false;    // also composite the 2D flow (flow images)
   bool static3d = false;  // static 3D Gaussians (means 3, log-scales 3, quaternions 4 rows)
   // front lists (front.hpp): some render has a depth cut; the keep threshold;
-  // size of all renders' keep bitmaps (words)
+  // sizes of all renders' keep bitmaps (words) and cover grids (ints)
   bool front = false;
   int32_t front_keep = 0;
-  size_t keep_words_total = 0;
+  size_t keep_words_total = 0, cover_total = 0;
 };
 
 }  // namespace
@@ -481,9 +482,11 @@ Plan make_plan(const r4d_view* views, int V, uint32_t n, int deg, const r4d_sett
   for (ViewSlot& sl : p.slots) {
     sl.front16 = (f16 && front_grid_ok(sl.v.tiles_x, sl.v.tiles_y)) ? f16 : 0u;
     sl.keep_base = uint32_t(p.keep_words_total);
+    sl.cover_base = uint32_t(p.cover_total);
     if (sl.front16) {
       p.front = true;
       p.keep_words_total += size_t(keep_words(sl.v.tiles_x)) * size_t(sl.v.tiles_y);
+      p.cover_total += size_t(sl.v.tiles_x + 1) * size_t(sl.v.tiles_y + 1);
     }
   }
   p.dseg.count = uint32_t(V);
@@ -545,6 +548,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.totals = L.status + 16;
   L.front = L.totals + 2 * size_t(kMaxViews) * 8;
   L.rest = take(size_t(p.total_tiles) * 8);
+  L.cover = take(p.cover_total * 4);
   L.dhist = take(4 * size_t(kMaxViews) * 256 * 4);
   L.tickets = take(16 * 4);
   L.dstatus = take(4 * size_t(sort_status_words(uint64_t(V) * np, kDepthItems)) * 4);
@@ -649,6 +653,11 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
                                      at<uint32_t>(F, L.dkeys), totals, at<uint32_t>(F, L.kA),
                                      at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd,
                                      F + L.zero_begin, zero_bytes, p.static3d, stream));
+    // front lists: which tiles keep their whole list
+    if (p.front)
+      R4D_HIP(front_keep(slots, p.V, at<Rect16>(F, L.rects), at<uint32_t>(F, L.dkeys), p.n,
+                         p.n_pad, p.front_keep, at<int32_t>(F, L.cover),
+                         at<uint64_t>(F, L.keep), stream));
   }
   hipEvent_t totals_ready = nullptr;
   if (sized) {
@@ -722,9 +731,6 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     {
       StageTimer tm(ctx, kCountScan, stream, timed);
       if (p.front) {
-        // which tiles keep their whole list, then each Gaussian's entries
-        R4D_HIP(front_keep(slots, p.V, order, at<Rect16>(F, L.rects), totals, p.n, p.n_pad,
-                           p.front_keep, at<uint64_t>(F, L.keep), stream));
         R4D_HIP(front_counts<T>(order, at<uint32_t>(F, L.tiles), at<Rect16>(F, L.rects),
                                 at<Rec<T>>(F, L.recs), slots, totals, at<uint64_t>(F, L.keep),
                                 p.n, p.n_pad, p.V, at<uint32_t>(F, L.fcount),

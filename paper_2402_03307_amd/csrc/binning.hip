@@ -559,14 +559,18 @@ __global__ __launch_bounds__(kThreads) void count_offsets_kernel(
 
 // ---- front lists (front.hpp)
 // Keep bitmap of every render with a depth cut: a tile is kept when at most
-// `keep` tile boxes of visible Gaussians cover it.  The boxes of every s-th
-// Gaussian of the depth order (s = ceil(n_vis / kKeepSample)) are added as
-// +1 / -1 at their corners to a grid in LDS, whose 2D prefix sums times s
-// estimate the cover counts.  One workgroup per render; renders with more than
-// kKeepGrid grid cells get no cut (the host leaves front16 at 0 for them).
+// `keep` tile boxes of visible Gaussians cover it.  The boxes of the visible
+// ones among every s-th Gaussian by index (s = ceil(n / kKeepSample)) are
+// counted as +1 / -1 at their corners into a grid, whose 2D prefix sums times
+// s estimate the cover counts: kKeepGroups workgroups per render each add
+// their share in LDS and then into the render's grid in memory (cover, zeroed
+// beforehand); front_bits_kernel then sums the grid and writes the bits.
+// Renders with more than kKeepGrid grid cells get no cut (the host leaves
+// front16 at 0 for them).
 constexpr int kKeepThreads = 1024;
+constexpr int kKeepGroups = 16;
 constexpr int kKeepGrid = 16384;
-constexpr uint32_t kKeepSample = 4096;
+constexpr uint32_t kKeepSample = uint32_t(kKeepGroups) * kKeepThreads;
 constexpr int kKeepWordsMax = 512;  // keep bitmap words of a render (LDS copies)
 
 // The render's keep bitmap into LDS (the row walks test it for every row).
@@ -577,9 +581,40 @@ __device__ __forceinline__ void load_keep(uint64_t* s_keep, const uint64_t* __re
 }
 
 __global__ __launch_bounds__(kKeepThreads) void front_keep_kernel(
-    const ViewSlot* __restrict__ slots, const uint32_t* __restrict__ order,
-    const Rect16* __restrict__ rects, const unsigned long long* __restrict__ totals, uint32_t n,
-    uint32_t n_pad, int32_t keep, uint64_t* __restrict__ bits) {
+    const ViewSlot* __restrict__ slots, const Rect16* __restrict__ rects,
+    const uint32_t* __restrict__ depth_keys, uint32_t n, uint32_t n_pad,
+    int32_t* __restrict__ cover) {
+  __shared__ int32_t s_c[kKeepGrid];
+  const uint32_t v = blockIdx.y;
+  const ViewSlot& sl = slots[v];
+  if (!sl.front16) return;
+  const int tx = sl.v.tiles_x, ty = sl.v.tiles_y, w1 = tx + 1, h1 = ty + 1;
+  for (int i = threadIdx.x; i < w1 * h1; i += kKeepThreads) s_c[i] = 0;
+  __syncthreads();
+  const uint32_t step = (n + kKeepSample - 1) / kKeepSample;
+  const uint32_t j = (blockIdx.x * uint32_t(kKeepThreads) + threadIdx.x) * step;
+  if (j < n && depth_keys[size_t(v) * n_pad + j] != 0xffffffffu) {
+    const Rect16 r = rects[size_t(v) * n + j];
+    // (corners on the last row or column change no tile's sum)
+    atomicAdd(&s_c[int(r.y0) * w1 + int(r.x0)], 1);
+    if (int(r.x1) < tx) atomicAdd(&s_c[int(r.y0) * w1 + int(r.x1)], -1);
+    if (int(r.y1) < ty) {
+      atomicAdd(&s_c[int(r.y1) * w1 + int(r.x0)], -1);
+      if (int(r.x1) < tx) atomicAdd(&s_c[int(r.y1) * w1 + int(r.x1)], 1);
+    }
+  }
+  __syncthreads();
+  int32_t* __restrict__ g = cover + sl.cover_base;
+  for (int i = threadIdx.x; i < w1 * h1; i += kKeepThreads) {
+    const int32_t x = s_c[i];
+    if (x) atomicAdd(&g[i], x);
+  }
+}
+
+// The bits from the summed cover grids: one workgroup per render.
+__global__ __launch_bounds__(kKeepThreads) void front_bits_kernel(
+    const ViewSlot* __restrict__ slots, const int32_t* __restrict__ cover, uint32_t n,
+    int32_t keep, uint64_t* __restrict__ bits) {
   __shared__ int32_t s_c[kKeepGrid];
   const uint32_t v = blockIdx.x;
   const ViewSlot& sl = slots[v];
@@ -587,38 +622,9 @@ __global__ __launch_bounds__(kKeepThreads) void front_keep_kernel(
   const int tx = sl.v.tiles_x, ty = sl.v.tiles_y, w1 = tx + 1, h1 = ty + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = kKeepThreads / 64;
-  for (int i = threadIdx.x; i < w1 * h1; i += kKeepThreads) s_c[i] = 0;
-  __syncthreads();
-  const uint32_t nvis = uint32_t(totals[2 * v]);
-  const uint32_t step = (nvis + kKeepSample - 1) / kKeepSample;
-  const uint32_t* __restrict__ ord = order + size_t(v) * n_pad;
-  const Rect16* __restrict__ rc = rects + size_t(v) * n;
-  {
-    // the sample's boxes, all loads in flight at once (kKeepSample / kKeepThreads each)
-    constexpr int kPer = int(kKeepSample) / kKeepThreads;
-    uint32_t gi[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const uint32_t j = threadIdx.x + uint32_t(q) * kKeepThreads;
-      gi[q] = j * step < nvis ? ord[j * step] : 0xffffffffu;
-    }
-    Rect16 box[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q)
-      box[q] = gi[q] != 0xffffffffu ? rc[gi[q]] : Rect16{0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const Rect16 r = box[q];
-      if (r.x0 >= r.x1) continue;
-      // (corners on the last row or column change no tile's sum)
-      atomicAdd(&s_c[int(r.y0) * w1 + int(r.x0)], 1);
-      if (int(r.x1) < tx) atomicAdd(&s_c[int(r.y0) * w1 + int(r.x1)], -1);
-      if (int(r.y1) < ty) {
-        atomicAdd(&s_c[int(r.y1) * w1 + int(r.x0)], -1);
-        if (int(r.x1) < tx) atomicAdd(&s_c[int(r.y1) * w1 + int(r.x1)], 1);
-      }
-    }
-  }
+  const uint32_t step = (n + kKeepSample - 1) / kKeepSample;
+  const int32_t* __restrict__ g = cover + sl.cover_base;
+  for (int i = threadIdx.x; i < w1 * h1; i += kKeepThreads) s_c[i] = g[i];
   __syncthreads();
   // prefix sums along the rows, then down the columns: a wavefront per line,
   // four lines interleaved
@@ -1541,12 +1547,16 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
   return run(LoadCountGatherSeg{order, counts, totals, n, n_pad, total}, nullptr);
 }
 
-hipError_t front_keep(const ViewSlot* slots, int n_views, const uint32_t* order,
-                      const Rect16* rects, const unsigned long long* totals, uint32_t n,
-                      uint32_t n_pad, int32_t keep, uint64_t* bits, hipStream_t stream) {
+hipError_t front_keep(const ViewSlot* slots, int n_views, const Rect16* rects,
+                      const uint32_t* depth_keys, uint32_t n, uint32_t n_pad, int32_t keep,
+                      int32_t* cover, uint64_t* bits, hipStream_t stream) {
   if (n_views <= 0) return hipSuccess;
-  hipLaunchKernelGGL(front_keep_kernel, dim3(uint32_t(n_views)), dim3(kKeepThreads), 0, stream,
-                     slots, order, rects, totals, n, n_pad, keep, bits);
+  hipLaunchKernelGGL(front_keep_kernel, dim3(uint32_t(kKeepGroups), uint32_t(n_views)),
+                     dim3(kKeepThreads), 0, stream, slots, rects, depth_keys, n, n_pad, cover);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(front_bits_kernel, dim3(uint32_t(n_views)), dim3(kKeepThreads), 0, stream,
+                     slots, cover, n, keep, bits);
   return hipGetLastError();
 }
 

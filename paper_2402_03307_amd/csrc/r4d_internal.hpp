@@ -44,10 +44,12 @@ struct ViewSlot {
   ViewDev v;
   uint32_t tile_base;   // index of the render's first tile among all tiles of the batch
   uint64_t pix_base;    // index of its first pixel among all pixels of the batch
-  // front lists (front.hpp): depth cut fraction x 65536 (0: whole lists) and
-  // the render's keep bitmap (word offset)
+  // front lists (front.hpp): depth cut fraction x 65536 (0: whole lists), the
+  // render's keep bitmap (word offset) and cover grid (int offset,
+  // (tiles_y + 1) x (tiles_x + 1))
   uint32_t front16;
   uint32_t keep_base;
+  uint32_t cover_base;
 };
 
 // Per-render state of the front lists: where the rest area starts (absolute
@@ -158,14 +160,15 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
 // ---- front lists (front.hpp)
 // Keep bitmaps (rows of keep_words(tiles_x) words at each render's keep_base)
 // of the renders with front16 != 0: a tile is kept when at most `keep` tile
-// boxes of visible Gaussians cover it, counted on every s-th Gaussian of the
-// depth order (order: [V][n_pad]; s keeps the sample within 4096 boxes) and
-// scaled by s.  front_grid_ok: the render's tile grid fits the kernel
-// (otherwise the host gives it no cut).
+// boxes of visible Gaussians cover it, counted on every s-th Gaussian by index
+// (depth_keys [v * n_pad + i], 0xffffffff: not visible; s keeps the sample
+// within 16384 Gaussians) and scaled by s.  cover: the renders' cover grids
+// (at cover_base), zeroed beforehand.  front_grid_ok: the render's tile grid
+// fits the kernels (otherwise the host gives it no cut).
 bool front_grid_ok(int tiles_x, int tiles_y);
-hipError_t front_keep(const ViewSlot* slots, int n_views, const uint32_t* order,
-                      const Rect16* rects, const unsigned long long* totals, uint32_t n,
-                      uint32_t n_pad, int32_t keep, uint64_t* bits, hipStream_t stream);
+hipError_t front_keep(const ViewSlot* slots, int n_views, const Rect16* rects,
+                      const uint32_t* depth_keys, uint32_t n, uint32_t n_pad, int32_t keep,
+                      int32_t* cover, uint64_t* bits, hipStream_t stream);
 // counts[v * n_pad + k]: entries of the front lists from render v's Gaussian at
 // depth position k (order[v][k]); whole: per-Gaussian counts of the whole
 // lists ([v][n]); srect[v * n_pad + k] = its tile box for k from the render's

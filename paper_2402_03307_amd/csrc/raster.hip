@@ -240,46 +240,82 @@ struct TileCfg {
 
 // Collection of a tile's rest entries (front.hpp): the Gaussians at depth
 // positions [r0, n_vis) of render vi whose row run in tile row ty covers
-// column tx, in depth order, into a range of the render's rest area.  Two
-// passes over the depth-ordered tile boxes, kItems positions per thread per
-// step: a count, then (after one reservation) the writes, each thread's hits
-// placed by a workgroup scan.  Returns [start, end) ([0, 0) for none).
-// s_red: NT / 64 + 1 words of LDS.
+// column tx, in depth order, into a range of the render's rest area.  A pass
+// over the depth-ordered tile boxes, kItems positions per thread per step
+// (their loads in flight together); each step's hits are placed by a
+// workgroup scan and kept in LDS (s_hits, kRestHits entries), so that after
+// one reservation they are written out; a list longer than that is found
+// again in a second pass that writes it directly.  Returns [start, end)
+// ([0, 0) for none).  s_red: NT / 64 + 1 words of LDS.
+constexpr uint32_t kRestHits = 4096;
+
 template <typename T, int NT>
 __device__ uint2 collect_rest(const FrontCollect& fc, uint32_t vi, uint32_t front16,
                               const Rec<T>* __restrict__ recs, const ViewDev& v, int tx, int ty,
-                              uint32_t* __restrict__ values, uint32_t* s_red) {
-  // (one position per thread and step, and loops kept rolled: this code shares
-  // the forward kernel's register budget)
-  constexpr int kItems = 1;
+                              uint32_t* __restrict__ values, uint32_t* s_red, uint32_t* s_hits) {
+  constexpr int kItems = 16;
   const uint32_t nvis = uint32_t(fc.totals[2 * vi]);
   const uint32_t r0 = front_cut(nvis, front16);
   const size_t row = size_t(vi) * fc.n_pad;
   const Rect16* __restrict__ sr = fc.srect + row;
   const uint32_t* __restrict__ ord = fc.order + row;
-  auto hit = [&](uint32_t k) -> bool {
-    const Rect16 r = sr[k];
-    if (tx < int(r.x0) || tx >= int(r.x1) || ty < int(r.y0) || ty >= int(r.y1)) return false;
-    int x0, x1;
-    row_span(geom_of(recs[ord[k]], r, v), ty, x0, x1);
-    return tx >= x0 && tx < x1;
-  };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t c = 0;
+  // hits of one step: bit i of the mask for position kt + i, their indices in gi
+  auto step_hits = [&](uint32_t kt, uint32_t (&gi)[kItems]) -> uint32_t {
+    Rect16 rr[kItems];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i)
+      rr[i] = kt + i < nvis ? sr[kt + i] : Rect16{0, 0, 0, 0};
+    uint32_t hm = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const Rect16 r = rr[i];
+      if (tx < int(r.x0) || tx >= int(r.x1) || ty < int(r.y0) || ty >= int(r.y1)) continue;
+      gi[i] = ord[kt + i];
+      int x0, x1;
+      row_span(geom_of(recs[gi[i]], r, v), ty, x0, x1);
+      if (tx >= x0 && tx < x1) hm |= 1u << i;
+    }
+    return hm;
+  };
+  // workgroup exclusive scan of one count per thread; *all: the sum
+  auto scan = [&](uint32_t c, uint32_t* all) -> uint32_t {
+    uint32_t inc = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_red[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, sum = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      const uint32_t t = s_red[w];
+      before += w < wave ? t : 0u;
+      sum += t;
+    }
+    __syncthreads();
+    *all = sum;
+    return before + inc - c;
+  };
+  uint32_t total = 0;
 #pragma unroll 1
   for (uint32_t k0 = r0; k0 < nvis; k0 += uint32_t(NT * kItems)) {
     const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
+    uint32_t gi[kItems];
+    uint32_t hm = step_hits(kt, gi);
+    uint32_t all;
+    uint32_t p = total + scan(uint32_t(__popc(hm)), &all);
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) c += (kt + i < nvis && hit(kt + i)) ? 1u : 0u;
+    for (int i = 0; i < kItems; ++i) {
+      if ((hm >> i) & 1u) {
+        if (p < kRestHits) s_hits[p] = gi[i];
+        ++p;
+      }
+    }
+    total += all;
   }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
-  if (lane == 0) s_red[wave] = c;
-  __syncthreads();
-  uint32_t total = 0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) total += s_red[w];
-  __syncthreads();
   if (total == 0u) return make_uint2(0u, 0u);
   if (threadIdx.x == 0) {
     const uint32_t take = (total + kSegment - 1) / kSegment * kSegment;
@@ -295,35 +331,22 @@ __device__ uint2 collect_rest(const FrontCollect& fc, uint32_t vi, uint32_t fron
   __syncthreads();
   const uint32_t a = s_red[NT / 64];
   if (a == 0xffffffffu) return make_uint2(0u, 0u);
-  uint32_t run = 0;
+  if (total <= kRestHits) {
+    for (uint32_t j = threadIdx.x; j < total; j += NT) values[a + j] = s_hits[j];
+  } else {
+    uint32_t run = 0;
 #pragma unroll 1
-  for (uint32_t k0 = r0; k0 < nvis; k0 += uint32_t(NT * kItems)) {
-    const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
-    uint32_t hm = 0;
+    for (uint32_t k0 = r0; k0 < nvis; k0 += uint32_t(NT * kItems)) {
+      const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
+      uint32_t gi[kItems];
+      const uint32_t hm = step_hits(kt, gi);
+      uint32_t all;
+      uint32_t p = a + run + scan(uint32_t(__popc(hm)), &all);
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) hm |= (kt + i < nvis && hit(kt + i)) ? (1u << i) : 0u;
-    const uint32_t cnt = uint32_t(__popc(hm));
-    uint32_t inc = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += y;
+      for (int i = 0; i < kItems; ++i)
+        if ((hm >> i) & 1u) values[p++] = gi[i];
+      run += all;
     }
-    if (lane == 63) s_red[wave] = inc;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w) {
-      const uint32_t t = s_red[w];
-      before += w < wave ? t : 0u;
-      all += t;
-    }
-    __syncthreads();
-    uint32_t p = a + run + before + inc - cnt;
-#pragma unroll
-    for (int i = 0; i < kItems; ++i)
-      if ((hm >> i) & 1u) values[p++] = ord[kt + i];
-    run += all;
   }
   // the workgroup reads these entries next
   __threadfence_block();
@@ -342,7 +365,8 @@ __device__ uint2 collect_rest(const FrontCollect& fc, uint32_t vi, uint32_t fron
 // the front list runs out.
 template <typename T, int TS, int PPT, bool COUNT, bool FLOW, bool REST>
 __device__ __forceinline__ void raster_fwd_tile(
-    Staged<T>* s_rec, uint32_t* s_walk, uint32_t* s_red, const Rec<T>* __restrict__ recs,
+    Staged<T>* s_rec, uint32_t* s_walk, uint32_t* s_red, uint32_t* s_hits,
+    const Rec<T>* __restrict__ recs,
     const Vec2<T>* __restrict__ flows, uint32_t* __restrict__ values, const uint2 rg, bool cut,
     const FrontCollect& fc, uint32_t vi, uint32_t front16, uint32_t tile_end, int tile,
     uint32_t gtile, const ViewDev& v, const SettingsDev& st, T* __restrict__ image,
@@ -391,7 +415,7 @@ __device__ __forceinline__ void raster_fwd_tile(
       // collect the rest before the batch, so that the boundary state below is
       // saved wherever the list goes on
       rest = collect_rest<T, NT>(fc, vi, front16, recs, v, tile % v.tiles_x, tile / v.tiles_x,
-                                 values, s_red);
+                                 values, s_red, s_hits);
       len += rest.y - rest.x;
       pending = false;
       if (threadIdx.x == 0 && rest.y > rest.x) rest_out[gtile] = rest;
@@ -732,7 +756,8 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
     }
     const uint32_t tile_end = sl.tile_base + uint32_t(v.tiles_x) * uint32_t(v.tiles_y);
     raster_fwd_tile<T, TS, PPT, COUNT, FLOW, false>(
-        s_rec, &s_walk, nullptr, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr,
+        s_rec, &s_walk, nullptr, nullptr, recs + size_t(vi) * n,
+        FLOW ? flows + size_t(vi) * n : nullptr,
         values, ranges[g], cut, fc, uint32_t(vi), front16, tile_end, tile, g, v, st,
         image + 3 * pb, FLOW ? flow_image + 2 * pb : nullptr, T_final + pb, n_contrib + pb,
         COUNT ? n_eval + 2 * pb : nullptr, sv.ck, sv.ckf, sv.img + 3 * pb,
@@ -759,6 +784,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_rest_kernel(
   __shared__ Staged<T> s_rec[TileCfg<TS, PPT>::kBatch];
   __shared__ uint32_t s_walk;
   __shared__ uint32_t s_red[NT / 64 + 1];
+  __shared__ uint32_t s_hits[kRestHits];
   const uint32_t count = fc.table->queued;
   for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
     const uint32_t g = fc.queue[it];
@@ -768,7 +794,8 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_rest_kernel(
     const size_t pb = size_t(sl.pix_base);
     const uint32_t tile_end = sl.tile_base + uint32_t(v.tiles_x) * uint32_t(v.tiles_y);
     raster_fwd_tile<T, TS, PPT, COUNT, FLOW, true>(
-        s_rec, &s_walk, s_red, recs + size_t(vi) * n, FLOW ? flows + size_t(vi) * n : nullptr,
+        s_rec, &s_walk, s_red, s_hits, recs + size_t(vi) * n,
+        FLOW ? flows + size_t(vi) * n : nullptr,
         values, ranges[g], true, fc, uint32_t(vi), sl.front16, tile_end, int(g - sl.tile_base), g,
         v, st, image + 3 * pb, FLOW ? flow_image + 2 * pb : nullptr, T_final + pb,
         n_contrib + pb, COUNT ? n_eval + 2 * pb : nullptr, sv.ck, sv.ckf, sv.img + 3 * pb,

@@ -181,21 +181,20 @@ def depth_positions(depth_keys: np.ndarray) -> np.ndarray:
     return pos
 
 
-KEEP_SAMPLE = 4096  # tile boxes the keep rule counts at most (every s-th in depth order)
+KEEP_SAMPLE = 16384  # Gaussians the keep rule samples at most (every s-th by index)
 
 
 def kept_tiles(rects: np.ndarray, depth_keys: np.ndarray, tiles_x: int, tiles_y: int,
                keep: int) -> np.ndarray:
-    """Kept tiles, [tiles] bool: those covered by at most `keep` tile boxes,
-    estimated from the boxes of every s-th visible Gaussian of the depth order
-    (s = ceil(n_vis / KEEP_SAMPLE)) times s."""
-    pos = depth_positions(depth_keys)
-    n_vis = int((pos >= 0).sum())
-    step = max(1, -(-n_vis // KEEP_SAMPLE))
-    order = np.argsort(np.where(pos >= 0, pos, np.iinfo(np.int64).max))[:n_vis]
-    r = rects[order[::step]].astype(np.int64)
+    """Kept tiles, [tiles] bool: those covered by at most `keep` tile boxes of
+    visible Gaussians, estimated from the visible ones among every s-th
+    Gaussian by index (s = ceil(n / KEEP_SAMPLE)) times s."""
+    n = depth_keys.size
+    step = max(1, -(-n // KEEP_SAMPLE))
+    idx = np.arange(0, n, step)
+    idx = idx[depth_keys[idx] != 0xFFFFFFFF]
     cover = np.zeros((tiles_y, tiles_x), dtype=np.int64)
-    for x0, y0, x1, y1 in r:
+    for x0, y0, x1, y1 in rects[idx].astype(np.int64):
         cover[y0:y1, x0:x1] += 1
     return (cover * step <= keep).reshape(-1)
 
