@@ -244,6 +244,16 @@ __global__ __launch_bounds__(kThreads) void onesweep_kernel(
   // to publish
   if (e0 >= send) return;
   const uint32_t nvalid = send - e0 < TILE ? send - e0 : TILE;
+  // a digit every key of the segment shares (one bin of the segment's
+  // histogram holds them all, as the top byte of depths within one binade):
+  // the pass keeps the order, so the tile is copied as it is
+  if (hist[size_t(s) * 256u + ((keys_in[sstart] >> shift) & 255u)] == send - sstart) {
+    for (uint32_t q = uint32_t(tid); q < nvalid; q += kThreads) {
+      if (keys_out) keys_out[e0 + q] = keys_in[e0 + q];
+      vals_out[e0 + q] = vals_in ? vals_in[e0 + q] : e0 + q - sstart;
+    }
+    return;
+  }
 
   // load: wave w holds elements [w * 64 * ITEMS, (w + 1) * 64 * ITEMS) of the tile
   uint32_t k[ITEMS], v[ITEMS], r[ITEMS];
