@@ -651,9 +651,15 @@ def per_config(r4d, rend, dev, args):
                                           flat=True), steps, 1)
     ms_graph = timed(lambda: rend.forward(p, views, dict(st, mode="graph"), save=False, flat=True),
                      steps, 1)
+    _, saved = rend.forward(p, views, dict(st, mode="graph"), save=True)
+    so = [saved.stats(v) for v in range(len(views))]
+    saved.release()
     res["300k_30_orbit_fwd"] = {"plain_ms_per_30": ms_plain, "graph_ms_per_30": ms_graph,
                                 "plain_frames_per_s": 30e3 / ms_plain,
-                                "graph_frames_per_s": 30e3 / ms_graph}
+                                "graph_frames_per_s": 30e3 / ms_graph,
+                                "tile_entries_total": sum(x["n_dup"] for x in so),
+                                "front_entries_total": sum(x["n_front"] for x in so),
+                                "rest_tiles_total": sum(x["rest_tiles"] for x in so)}
     del p
     torch.cuda.empty_cache()
     print(f"per config (so far): {res}", file=sys.stderr, flush=True)

@@ -123,12 +123,13 @@ typedef struct {
                           radix sort with this many keys per lane.  With
                           tile_size 0 the autotuner picks 0 or 16.  (0)           */
   float front_fraction; /* front lists: with n_vis visible Gaussians in depth
-                          order, those at positions from ceil(front_fraction *
-                          n_vis) on are listed only in tiles covered by at most
-                          front_keep Gaussians' tile boxes; any other tile's list
-                          ends there, and when its pixels outlast that front
-                          list the forward collects the rest of the list
-                          itself.  The rasteriser sees every list in full up to
+                          order, those at positions from r0 = ceil(front_fraction
+                          * n_vis) on are listed only in tiles covered by at most
+                          front_keep tile boxes of the Gaussians before r0 (a tile
+                          that few front Gaussians reach may not fill up); any
+                          other tile's list ends there, and when its pixels
+                          outlast that front list the forward collects the
+                          rest of the list itself.  The rasteriser sees every list in full up to
                           where its pixels stop (Sec. 3.1 compositing rule), so
                           images and gradients do not depend on this; it saves
                           sorting entries that lie behind saturated pixels.
@@ -136,7 +137,7 @@ typedef struct {
                           (tiles_x + 1) * (tiles_y + 1) exceeds 16384 get
                           whole lists.  (0.1)                                    */
   int32_t front_keep;   /* see front_fraction; negative: no tile is kept whole
-                          (4096)                                                 */
+                          (1024)                                                 */
 } r4d_settings;
 
 /* How a call with several views is executed.

@@ -653,11 +653,6 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
                                      at<uint32_t>(F, L.dkeys), totals, at<uint32_t>(F, L.kA),
                                      at<uint32_t>(F, L.vA), dseg, F + L.ptemp_fwd,
                                      F + L.zero_begin, zero_bytes, p.static3d, stream));
-    // front lists: which tiles keep their whole list
-    if (p.front)
-      R4D_HIP(front_keep(slots, p.V, at<Rect16>(F, L.rects), at<uint32_t>(F, L.dkeys), p.n,
-                         p.n_pad, p.front_keep, at<int32_t>(F, L.cover),
-                         at<uint64_t>(F, L.keep), stream));
   }
   hipEvent_t totals_ready = nullptr;
   if (sized) {
@@ -731,6 +726,10 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
     {
       StageTimer tm(ctx, kCountScan, stream, timed);
       if (p.front) {
+        // front lists: which tiles keep their whole list, then the entry counts
+        R4D_HIP(front_keep(slots, p.V, at<Rect16>(F, L.rects), order, totals, p.n, p.n_pad,
+                           p.front_keep, at<int32_t>(F, L.cover), at<uint64_t>(F, L.keep),
+                           stream));
         R4D_HIP(front_counts<T>(order, at<uint32_t>(F, L.tiles), at<Rect16>(F, L.rects),
                                 at<Rec<T>>(F, L.recs), slots, totals, at<uint64_t>(F, L.keep),
                                 p.n, p.n_pad, p.V, at<uint32_t>(F, L.fcount),
@@ -1623,7 +1622,7 @@ void r4d_default_settings(r4d_settings* s) {
   s->mode = R4D_MODE_PER_VIEW;
   s->sort_items = 0;
   s->front_fraction = 0.1f;
-  s->front_keep = 4096;
+  s->front_keep = 1024;
 }
 
 r4d_status r4d_create(r4d_ctx** out, int device) {

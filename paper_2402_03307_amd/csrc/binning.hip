@@ -569,18 +569,17 @@ __global__ __launch_bounds__(kThreads) void count_offsets_kernel(
 
 // ---- front lists (front.hpp)
 // Keep bitmap of every render with a depth cut: a tile is kept when at most
-// `keep` tile boxes of visible Gaussians cover it.  The boxes of the visible
-// ones among every s-th Gaussian by index (s = ceil(n / kKeepSample)) are
-// counted as +1 / -1 at their corners into a grid, whose 2D prefix sums times
-// s estimate the cover counts: kKeepGroups workgroups per render each add
-// their share in LDS and then into the render's grid in memory (cover, zeroed
+// `keep` tile boxes of the render's front Gaussians (depth positions below
+// its cut r0) cover it.  Each box is counted as +1 / -1 at its corners into a
+// grid whose 2D prefix sums are the cover counts: kKeepGroups workgroups per
+// render each take a share of the positions [0, r0) in depth order, count it
+// in LDS and add it into the render's grid in memory (cover, zeroed
 // beforehand); front_bits_kernel then sums the grid and writes the bits.
 // Renders with more than kKeepGrid grid cells get no cut (the host leaves
 // front16 at 0 for them).
 constexpr int kKeepThreads = 1024;
 constexpr int kKeepGroups = 16;
 constexpr int kKeepGrid = 16384;
-constexpr uint32_t kKeepSample = uint32_t(kKeepGroups) * kKeepThreads;
 constexpr int kKeepWordsMax = 512;  // keep bitmap words of a render (LDS copies)
 
 // The render's keep bitmap into LDS (the row walks test it for every row).
@@ -592,19 +591,22 @@ __device__ __forceinline__ void load_keep(uint64_t* s_keep, const uint64_t* __re
 
 __global__ __launch_bounds__(kKeepThreads) void front_keep_kernel(
     const ViewSlot* __restrict__ slots, const Rect16* __restrict__ rects,
-    const uint32_t* __restrict__ depth_keys, uint32_t n, uint32_t n_pad,
-    int32_t* __restrict__ cover) {
+    const uint32_t* __restrict__ order, const unsigned long long* __restrict__ totals, uint32_t n,
+    uint32_t n_pad, int32_t* __restrict__ cover) {
   __shared__ int32_t s_c[kKeepGrid];
   const uint32_t v = blockIdx.y;
   const ViewSlot& sl = slots[v];
   if (!sl.front16) return;
+  const uint32_t r0 = front_cut(uint32_t(totals[2 * v]), sl.front16);
+  const uint32_t share = (r0 + kKeepGroups - 1) / kKeepGroups;
+  const uint32_t kb = blockIdx.x * share;
+  const uint32_t ke = kb + share < r0 ? kb + share : r0;
+  if (kb >= ke) return;  // (the whole workgroup)
   const int tx = sl.v.tiles_x, ty = sl.v.tiles_y, w1 = tx + 1, h1 = ty + 1;
   for (int i = threadIdx.x; i < w1 * h1; i += kKeepThreads) s_c[i] = 0;
   __syncthreads();
-  const uint32_t step = (n + kKeepSample - 1) / kKeepSample;
-  const uint32_t j = (blockIdx.x * uint32_t(kKeepThreads) + threadIdx.x) * step;
-  if (j < n && depth_keys[size_t(v) * n_pad + j] != 0xffffffffu) {
-    const Rect16 r = rects[size_t(v) * n + j];
+  for (uint32_t k = kb + threadIdx.x; k < ke; k += kKeepThreads) {
+    const Rect16 r = rects[size_t(v) * n + order[size_t(v) * n_pad + k]];
     // (corners on the last row or column change no tile's sum)
     atomicAdd(&s_c[int(r.y0) * w1 + int(r.x0)], 1);
     if (int(r.x1) < tx) atomicAdd(&s_c[int(r.y0) * w1 + int(r.x1)], -1);
@@ -623,8 +625,8 @@ __global__ __launch_bounds__(kKeepThreads) void front_keep_kernel(
 
 // The bits from the summed cover grids: one workgroup per render.
 __global__ __launch_bounds__(kKeepThreads) void front_bits_kernel(
-    const ViewSlot* __restrict__ slots, const int32_t* __restrict__ cover, uint32_t n,
-    int32_t keep, uint64_t* __restrict__ bits) {
+    const ViewSlot* __restrict__ slots, const int32_t* __restrict__ cover, int32_t keep,
+    uint64_t* __restrict__ bits) {
   __shared__ int32_t s_c[kKeepGrid];
   const uint32_t v = blockIdx.x;
   const ViewSlot& sl = slots[v];
@@ -632,7 +634,6 @@ __global__ __launch_bounds__(kKeepThreads) void front_bits_kernel(
   const int tx = sl.v.tiles_x, ty = sl.v.tiles_y, w1 = tx + 1, h1 = ty + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = kKeepThreads / 64;
-  const uint32_t step = (n + kKeepSample - 1) / kKeepSample;
   const int32_t* __restrict__ g = cover + sl.cover_base;
   for (int i = threadIdx.x; i < w1 * h1; i += kKeepThreads) s_c[i] = g[i];
   __syncthreads();
@@ -673,11 +674,9 @@ __global__ __launch_bounds__(kKeepThreads) void front_bits_kernel(
   }
   __syncthreads();
   const int words = int(keep_words(tx));
-  const int64_t lim = int64_t(keep);
   for (int q = wave; q < ty * words; q += NW) {
     const int y = q / words, x = (q % words) * 64 + lane;
-    const unsigned long long m =
-        __ballot(x < tx && int64_t(s_c[y * w1 + x]) * int64_t(step) <= lim);
+    const unsigned long long m = __ballot(x < tx && s_c[y * w1 + x] <= keep);
     if (lane == 0) bits[sl.keep_base + q] = m;
   }
 }
@@ -1558,15 +1557,16 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
 }
 
 hipError_t front_keep(const ViewSlot* slots, int n_views, const Rect16* rects,
-                      const uint32_t* depth_keys, uint32_t n, uint32_t n_pad, int32_t keep,
-                      int32_t* cover, uint64_t* bits, hipStream_t stream) {
+                      const uint32_t* order, const unsigned long long* totals, uint32_t n,
+                      uint32_t n_pad, int32_t keep, int32_t* cover, uint64_t* bits,
+                      hipStream_t stream) {
   if (n_views <= 0) return hipSuccess;
   hipLaunchKernelGGL(front_keep_kernel, dim3(uint32_t(kKeepGroups), uint32_t(n_views)),
-                     dim3(kKeepThreads), 0, stream, slots, rects, depth_keys, n, n_pad, cover);
+                     dim3(kKeepThreads), 0, stream, slots, rects, order, totals, n, n_pad, cover);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(front_bits_kernel, dim3(uint32_t(n_views)), dim3(kKeepThreads), 0, stream,
-                     slots, cover, n, keep, bits);
+                     slots, cover, keep, bits);
   return hipGetLastError();
 }
 

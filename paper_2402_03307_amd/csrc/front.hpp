@@ -8,13 +8,15 @@
 // render numbered 0 .. n_vis - 1 in depth order, entries from depth positions
 // below r0 = ceil(f n_vis) are listed everywhere; entries from later
 // positions only in tiles whose whole list is kept, those covered by at most
-// `keep` Gaussians' tile boxes (a tile that few Gaussians reach may not fill
-// up).  Every other tile holds a front list, a prefix of its full list.  The
-// forward rasteriser walks a tile's list until its pixels stop; if a front
-// list runs out first, the workgroup itself collects the tile's remaining
-// entries (the later Gaussians whose row run covers the tile, in depth
-// order) into the render's rest area, records them as the tile's second
-// range and walks on.  Either way the walk sees the full list's entries in
+// `keep` tile boxes of the Gaussians before r0 (a tile that few of the front
+// Gaussians reach may not fill up with them: the front of a scene seen at an
+// angle covers only part of the screen).  Every other tile holds a front
+// list, a prefix of its full list.  The forward rasteriser walks a tile's
+// list until its pixels stop; if a front list runs out first, the tile is
+// queued, and a second pass collects the tile's remaining entries (the
+// later Gaussians whose row run covers the tile, in depth order) into the
+// render's rest area, records them as the tile's second range and renders
+// the tile again over both ranges.  Either way the walk sees the full list's entries in
 // the full list's order up to where it stops, so images, stop positions and
 // gradients are those of the full lists.
 //

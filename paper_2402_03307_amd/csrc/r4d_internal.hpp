@@ -160,15 +160,16 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
 // ---- front lists (front.hpp)
 // Keep bitmaps (rows of keep_words(tiles_x) words at each render's keep_base)
 // of the renders with front16 != 0: a tile is kept when at most `keep` tile
-// boxes of visible Gaussians cover it, counted on every s-th Gaussian by index
-// (depth_keys [v * n_pad + i], 0xffffffff: not visible; s keeps the sample
-// within 16384 Gaussians) and scaled by s.  cover: the renders' cover grids
-// (at cover_base), zeroed beforehand.  front_grid_ok: the render's tile grid
-// fits the kernels (otherwise the host gives it no cut).
+// boxes of the render's front Gaussians (depth order order[v * n_pad + k],
+// k below the cut of totals[2 v] visible Gaussians) cover it.  cover: the
+// renders' cover grids (at cover_base), zeroed beforehand.  front_grid_ok:
+// the render's tile grid fits the kernels (otherwise the host gives it no
+// cut).
 bool front_grid_ok(int tiles_x, int tiles_y);
 hipError_t front_keep(const ViewSlot* slots, int n_views, const Rect16* rects,
-                      const uint32_t* depth_keys, uint32_t n, uint32_t n_pad, int32_t keep,
-                      int32_t* cover, uint64_t* bits, hipStream_t stream);
+                      const uint32_t* order, const unsigned long long* totals, uint32_t n,
+                      uint32_t n_pad, int32_t keep, int32_t* cover, uint64_t* bits,
+                      hipStream_t stream);
 // counts[v * n_pad + k]: entries of the front lists from render v's Gaussian at
 // depth position k (order[v][k]); whole: per-Gaussian counts of the whole
 // lists ([v][n]); srect[v * n_pad + k] = its tile box for k from the render's

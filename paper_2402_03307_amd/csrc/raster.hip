@@ -804,8 +804,9 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_rest_kernel(
   }
 }
 
-// Workgroups of the rest pass.
-constexpr uint32_t kRestGroups = 256;
+// Workgroups of the rest pass: enough for the queued tiles of a render to run
+// at once (four per CU fit in LDS), since each is one of the longest walks.
+constexpr uint32_t kRestGroups = 1024;
 
 // Length classes of the tiles' last segments (seg_queue_kernel) and where the
 // queue lengths sit in the backward's ticket words.

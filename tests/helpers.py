@@ -181,22 +181,16 @@ def depth_positions(depth_keys: np.ndarray) -> np.ndarray:
     return pos
 
 
-KEEP_SAMPLE = 16384  # Gaussians the keep rule samples at most (every s-th by index)
-
-
 def kept_tiles(rects: np.ndarray, depth_keys: np.ndarray, tiles_x: int, tiles_y: int,
-               keep: int) -> np.ndarray:
+               keep: int, r0: int) -> np.ndarray:
     """Kept tiles, [tiles] bool: those covered by at most `keep` tile boxes of
-    visible Gaussians, estimated from the visible ones among every s-th
-    Gaussian by index (s = ceil(n / KEEP_SAMPLE)) times s."""
-    n = depth_keys.size
-    step = max(1, -(-n // KEEP_SAMPLE))
-    idx = np.arange(0, n, step)
-    idx = idx[depth_keys[idx] != 0xFFFFFFFF]
+    the front Gaussians (depth positions below r0)."""
+    pos = depth_positions(depth_keys)
+    idx = np.nonzero((pos >= 0) & (pos < r0))[0]
     cover = np.zeros((tiles_y, tiles_x), dtype=np.int64)
     for x0, y0, x1, y1 in rects[idx].astype(np.int64):
         cover[y0:y1, x0:x1] += 1
-    return (cover * step <= keep).reshape(-1)
+    return (cover <= keep).reshape(-1)
 
 
 def front_lists(ref_vals: np.ndarray, ref_rng: np.ndarray, pos: np.ndarray, r0: int,
@@ -238,7 +232,7 @@ def tile_lists(r4d, saved, view: int, n: int):
     if r0 is None:
         assert s["n_front"] == s["n_dup"] and s["rest_tiles"] == 0
         return vals, rng, ref_vals, ref_rng, s
-    kept = kept_tiles(rect, key, s["tiles_x"], s["tiles_y"], int(settings["front_keep"]))
+    kept = kept_tiles(rect, key, s["tiles_x"], s["tiles_y"], int(settings["front_keep"]), r0)
     f_vals, f_rng, rest = front_lists(ref_vals, ref_rng, depth_positions(key), r0, kept)
     rest_rng = saved.copy(view, r4d.BUF_REST, n).cpu().numpy().view(np.uint32)
     got = np.nonzero(rest_rng[:, 1] > rest_rng[:, 0])[0]

@@ -228,7 +228,7 @@ def test_3m_binning_bit_exact_on_tile_rows(large, vi):
     # positions below the cut (the rest, when collected, is the remainder)
     r0 = front_cut(s["n_visible"], o["settings"], tx, ty)
     pos = depth_positions(o["key"])
-    kept = (kept_tiles(o["rect"], o["key"], tx, ty, int(o["settings"]["front_keep"]))
+    kept = (kept_tiles(o["rect"], o["key"], tx, ty, int(o["settings"]["front_keep"]), r0)
             if r0 is not None else np.ones(tx * ty, dtype=bool))
     checked = 0
     for t, ref in lists.items():

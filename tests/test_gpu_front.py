@@ -11,7 +11,9 @@ through whole lists (front_fraction = 1):
     CPU re-derivation of the rule (helpers.tile_lists).
 
 Cases: the 500k / 1352x1014 render at the default cut (0.1 of the visible
-Gaussians, tiles covered by at most 4096 tile boxes kept whole), and a forced
+Gaussians, tiles covered by at most 1024 tile boxes of the front Gaussians
+kept whole), an orbit render seen along the cloud's diagonal (where the front
+of the cloud covers only the middle of the screen), and a forced
 collection on the 2k scene (the cut at the first depth position and no tile
 kept whole, or the cut at 0.3), so that nearly every tile collects its rest in
 the forward: three ragged views in per-view, fused and graph mode, a flow
@@ -116,6 +118,23 @@ def test_front_lists_500k_equal_whole_lists(r4d, device):
           f"rests {s['rest_tiles']} tiles / {s['rest_entries']} entries", flush=True)
     assert whole[3][0]["n_front"] == s["n_dup"]
     assert s["n_front"] < 0.5 * s["n_dup"]
+    _same(front, whole)
+
+
+def test_front_lists_diagonal_orbit_view_equal_whole_lists(r4d, device):
+    g, views, st = W.scene_300k_orbit()
+    views = [views[11]]
+    print("case: 300k orbit view 11 (diagonal), default cut vs whole lists", flush=True)
+    rend = r4d.Renderer(device)
+    p = to_device(g, device)
+    n = g["opacity"].shape[0]
+    dl = _upstream(views, 31)
+    front = _step(r4d, rend, p, views, st, dl, n)
+    whole = _step(r4d, rend, p, views, dict(st, **WHOLE), dl, n)
+    s = front[3][0]
+    print(f"whole lists {s['n_dup']} entries, front lists {s['n_front']}, "
+          f"rests {s['rest_tiles']} tiles / {s['rest_entries']} entries", flush=True)
+    assert s["n_front"] < s["n_dup"]
     _same(front, whole)
 
 
