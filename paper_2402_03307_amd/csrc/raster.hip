@@ -241,43 +241,33 @@ struct TileCfg {
 // Collection of a tile's rest entries (front.hpp): the Gaussians at depth
 // positions [r0, n_vis) of render vi whose row run in tile row ty covers
 // column tx, in depth order, into a range of the render's rest area.  A pass
-// over the depth-ordered tile boxes, kItems positions per thread per step
-// (their loads in flight together); each step's hits are placed by a
-// workgroup scan and kept in LDS (s_hits, kRestHits entries), so that after
-// one reservation they are written out; a list longer than that is found
-// again in a second pass that writes it directly.  Returns [start, end)
-// ([0, 0) for none).  s_red: NT / 64 + 1 words of LDS.
+// over the depth-ordered tile boxes, kRestItems positions per thread per step
+// (loaded together, the next step's while this one is finished): the
+// positions whose box holds the tile are placed by a workgroup scan into a
+// candidate list in LDS (in depth order), whose entries the threads then test
+// one each against the row run, so that the dependent loads (index, record)
+// of all candidates are in flight together; the hits are placed by a second
+// scan and kept in LDS (kRestHits entries), so that after one reservation
+// they are written out.  A list longer than that is found again in a second
+// pass that writes it directly.  Returns [start, end) ([0, 0) for none).
+// s_red: NT / 64 + 1 words of LDS; s_buf: kRestHits + NT * kRestItems words.
 constexpr uint32_t kRestHits = 4096;
+constexpr int kRestItems = 16;
 
 template <typename T, int NT>
 __device__ uint2 collect_rest(const FrontCollect& fc, uint32_t vi, uint32_t front16,
                               const Rec<T>* __restrict__ recs, const ViewDev& v, int tx, int ty,
-                              uint32_t* __restrict__ values, uint32_t* s_red, uint32_t* s_hits) {
-  constexpr int kItems = 16;
+                              uint32_t* __restrict__ values, uint32_t* s_red, uint32_t* s_buf) {
+  constexpr int kItems = kRestItems;
+  constexpr uint32_t kStep = uint32_t(NT) * kItems;
+  uint32_t* s_hits = s_buf;
+  uint32_t* s_cand = s_buf + kRestHits;
   const uint32_t nvis = uint32_t(fc.totals[2 * vi]);
   const uint32_t r0 = front_cut(nvis, front16);
   const size_t row = size_t(vi) * fc.n_pad;
   const Rect16* __restrict__ sr = fc.srect + row;
   const uint32_t* __restrict__ ord = fc.order + row;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // hits of one step: bit i of the mask for position kt + i, their indices in gi
-  auto step_hits = [&](uint32_t kt, uint32_t (&gi)[kItems]) -> uint32_t {
-    Rect16 rr[kItems];
-#pragma unroll
-    for (int i = 0; i < kItems; ++i)
-      rr[i] = kt + i < nvis ? sr[kt + i] : Rect16{0, 0, 0, 0};
-    uint32_t hm = 0;
-#pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const Rect16 r = rr[i];
-      if (tx < int(r.x0) || tx >= int(r.x1) || ty < int(r.y0) || ty >= int(r.y1)) continue;
-      gi[i] = ord[kt + i];
-      int x0, x1;
-      row_span(geom_of(recs[gi[i]], r, v), ty, x0, x1);
-      if (tx >= x0 && tx < x1) hm |= 1u << i;
-    }
-    return hm;
-  };
   // workgroup exclusive scan of one count per thread; *all: the sum
   auto scan = [&](uint32_t c, uint32_t* all) -> uint32_t {
     uint32_t inc = c;
@@ -299,23 +289,57 @@ __device__ uint2 collect_rest(const FrontCollect& fc, uint32_t vi, uint32_t fron
     *all = sum;
     return before + inc - c;
   };
-  uint32_t total = 0;
-#pragma unroll 1
-  for (uint32_t k0 = r0; k0 < nvis; k0 += uint32_t(NT * kItems)) {
-    const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
-    uint32_t gi[kItems];
-    uint32_t hm = step_hits(kt, gi);
-    uint32_t all;
-    uint32_t p = total + scan(uint32_t(__popc(hm)), &all);
+  auto covers = [&](const Rect16& r) {
+    return tx >= int(r.x0) && tx < int(r.x1) && ty >= int(r.y0) && ty < int(r.y1);
+  };
+  // one pass over the positions; out(p, gi) receives hit number p
+  auto pass = [&](auto&& out) -> uint32_t {
+    uint32_t total = 0;
+    Rect16 rr[kItems];
+    auto load = [&](uint32_t k0) {
+      const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      if ((hm >> i) & 1u) {
-        if (p < kRestHits) s_hits[p] = gi[i];
-        ++p;
+      for (int i = 0; i < kItems; ++i)
+        rr[i] = kt + i < nvis ? sr[kt + i] : Rect16{0, 0, 0, 0};
+    };
+    load(r0);
+#pragma unroll 1
+    for (uint32_t k0 = r0; k0 < nvis; k0 += kStep) {
+      const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
+      uint32_t bm = 0;
+#pragma unroll
+      for (int i = 0; i < kItems; ++i) bm |= covers(rr[i]) ? 1u << i : 0u;
+      if (k0 + kStep < nvis) load(k0 + kStep);
+      uint32_t nc;
+      uint32_t c = scan(uint32_t(__popc(bm)), &nc);
+#pragma unroll
+      for (int i = 0; i < kItems; ++i)
+        if ((bm >> i) & 1u) s_cand[c++] = kt + uint32_t(i);
+      __syncthreads();
+      // (the scans' barriers keep the next step's writes of s_cand behind these reads)
+#pragma unroll 1
+      for (uint32_t b = 0; b < nc; b += NT) {
+        const uint32_t ci = b + threadIdx.x;
+        bool hit = false;
+        uint32_t gi = 0;
+        if (ci < nc) {
+          const uint32_t k = s_cand[ci];
+          gi = ord[k];
+          int x0, x1;
+          row_span(geom_of(recs[gi], sr[k], v), ty, x0, x1);
+          hit = tx >= x0 && tx < x1;
+        }
+        uint32_t nh;
+        const uint32_t p = total + scan(hit ? 1u : 0u, &nh);
+        if (hit) out(p, gi);
+        total += nh;
       }
     }
-    total += all;
-  }
+    return total;
+  };
+  const uint32_t total = pass([&](uint32_t p, uint32_t gi) {
+    if (p < kRestHits) s_hits[p] = gi;
+  });
   if (total == 0u) return make_uint2(0u, 0u);
   if (threadIdx.x == 0) {
     const uint32_t take = (total + kSegment - 1) / kSegment * kSegment;
@@ -331,23 +355,10 @@ __device__ uint2 collect_rest(const FrontCollect& fc, uint32_t vi, uint32_t fron
   __syncthreads();
   const uint32_t a = s_red[NT / 64];
   if (a == 0xffffffffu) return make_uint2(0u, 0u);
-  if (total <= kRestHits) {
+  if (total <= kRestHits)
     for (uint32_t j = threadIdx.x; j < total; j += NT) values[a + j] = s_hits[j];
-  } else {
-    uint32_t run = 0;
-#pragma unroll 1
-    for (uint32_t k0 = r0; k0 < nvis; k0 += uint32_t(NT * kItems)) {
-      const uint32_t kt = k0 + uint32_t(threadIdx.x) * kItems;
-      uint32_t gi[kItems];
-      const uint32_t hm = step_hits(kt, gi);
-      uint32_t all;
-      uint32_t p = a + run + scan(uint32_t(__popc(hm)), &all);
-#pragma unroll
-      for (int i = 0; i < kItems; ++i)
-        if ((hm >> i) & 1u) values[p++] = gi[i];
-      run += all;
-    }
-  }
+  else
+    pass([&](uint32_t p, uint32_t gi) { values[a + p] = gi; });
   // the workgroup reads these entries next
   __threadfence_block();
   __syncthreads();
@@ -784,7 +795,7 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_rest_kernel(
   __shared__ Staged<T> s_rec[TileCfg<TS, PPT>::kBatch];
   __shared__ uint32_t s_walk;
   __shared__ uint32_t s_red[NT / 64 + 1];
-  __shared__ uint32_t s_hits[kRestHits];
+  __shared__ uint32_t s_hits[kRestHits + NT * kRestItems];
   const uint32_t count = fc.table->queued;
   for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
     const uint32_t g = fc.queue[it];

@@ -17,7 +17,8 @@ of the cloud covers only the middle of the screen), and a forced
 collection on the 2k scene (the cut at the first depth position and no tile
 kept whole, or the cut at 0.3), so that nearly every tile collects its rest in
 the forward: three ragged views in per-view, fused and graph mode, a flow
-render, float64, and a static set.
+render, float64, and a static set; and the 500k set on a small image, whose
+forced rests run past the collection's LDS buffer.
 """
 import numpy as np
 import pytest
@@ -169,6 +170,31 @@ def test_forced_rest_collection_tile_sizes(r4d, device, ts):
     whole = _step(r4d, rend, p, views, dict(base, **WHOLE), dl, n)
     front = _step(r4d, rend, p, views, dict(base, **FORCED[0]), dl, n)
     assert front[3][0]["rest_tiles"] > 10
+    _same(front, whole)
+
+
+def test_forced_rest_collection_long_rests(r4d, device):
+    """The 500k set on a 128 x 96 image: a few thousand entries per tile, so
+    that forced rests exceed the collection's LDS buffer (4096 entries) and are
+    written by its second pass."""
+    g, _, st = W.scene_500k_step()
+    views = [W.view((0.0, 0.0, -4.0), 128, 96, 100.0, 0.5)]
+    print("case: 500k set, 128x96, forced collection of long rests", flush=True)
+    rend = r4d.Renderer(device)
+    p = to_device(g, device)
+    n = g["opacity"].shape[0]
+    dl = _upstream(views, 37)
+    whole = _step(r4d, rend, p, views, dict(st, **WHOLE), dl, n)
+    front = _step(r4d, rend, p, views, dict(st, **FORCED[0]), dl, n)
+    s = front[3][0]
+    print(f"whole lists {s['n_dup']} entries over {s['tiles_x'] * s['tiles_y']} tiles, rests "
+          f"{s['rest_tiles']} tiles / {s['rest_entries']} entries", flush=True)
+    _, saved = rend.forward(p, views, dict(st, **FORCED[0]), save=True)
+    rr = saved.copy(0, r4d.BUF_REST, n).long().cpu()
+    saved.release()
+    longest = int((rr[:, 1] - rr[:, 0]).max())
+    print(f"longest rest {longest}", flush=True)
+    assert s["rest_tiles"] > 10 and longest > 4096
     _same(front, whole)
 
 
