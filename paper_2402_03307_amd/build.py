@@ -3,7 +3,11 @@
     python paper_2402_03307_amd/build.py
 
 Every source is compiled with hipcc for gfx950 (packed FP32 instructions
-disabled) and linked into one shared library next to this file.
+disabled) and linked into one shared library next to this file.  The same
+objects also make abi_host_check, the C ABI's host-layer check
+(tests/abi_host_check.cpp): the host layer (api.hip) compiled again with
+AddressSanitizer and UndefinedBehaviorSanitizer on its host code only
+(-Xarch_host), linked with the other objects as they are.
 """
 from __future__ import annotations
 
@@ -19,6 +23,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libr4d.so")
+HOST_CHECK = os.path.join(PKG, "abi_host_check")
 SOURCES = ("api.hip", "preprocess.hip", "binning.hip", "raster.hip", "consistency.hip",
            "training.hip")
 ARCH = "gfx950"
@@ -35,6 +40,38 @@ def compile_flags():
     return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", INCLUDE, "-I", CSRC]
+
+
+# host code only: no sanitizer reaches the device code
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host",
+            "-fno-omit-frame-pointer"]
+
+
+def _run(cmd, what):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"{what} failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+
+
+def build_host_check(verbose: bool = False) -> str:
+    """abi_host_check from the objects of build() (which must have run)."""
+    cc = hipcc()
+    api = os.path.join(BUILD_DIR, "api_hostcheck.o")
+    drv = os.path.join(BUILD_DIR, "abi_host_check.o")
+    flags = [*compile_flags(), *SANITIZE, "-g"]
+    flags[flags.index("-O3")] = "-O1"
+    _run([cc, *flags, "-c", os.path.join(CSRC, "api.hip"), "-o", api], "compile")
+    _run([cc, "-O1", "-g", "-std=c++17", *SANITIZE, "-I", INCLUDE, "-c",
+          os.path.join(ROOT, "tests", "abi_host_check.cpp"), "-o", drv], "compile")
+    others = [os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+              for src in SOURCES if src != "api.hip"]
+    tmp = HOST_CHECK + ".tmp"
+    _run([cc, f"--offload-arch={ARCH}", "-g", *SANITIZE, "-o", tmp, drv, api, *others], "link")
+    os.replace(tmp, HOST_CHECK)
+    if verbose:
+        print("linked", HOST_CHECK, flush=True)
+    return HOST_CHECK
 
 
 def build(verbose: bool = False) -> str:
@@ -61,6 +98,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print("linked", LIB, flush=True)
+    build_host_check(verbose)
     return LIB
 
 

@@ -58,3 +58,31 @@ def test_build_writes_library_in_package():
     import paper_2402_03307_amd as r4d
     assert os.path.dirname(r4d.LIB_PATH) == os.path.join(ROOT, "paper_2402_03307_amd")
     assert os.path.getsize(r4d.LIB_PATH) > 0
+
+
+def _host_check_binary():
+    """The sanitized host-layer check (paper_2402_03307_amd/build.py), built
+    here from the library's objects when it is missing."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_r4d_build", os.path.join(ROOT, "paper_2402_03307_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    if not os.path.exists(mod.HOST_CHECK):
+        mod.build(verbose=False)
+    return mod.HOST_CHECK
+
+
+def test_host_layer_under_sanitizers_without_a_device():
+    """The C ABI's host layer built with AddressSanitizer and UBSan
+    (tests/abi_host_check.cpp, cpu mode): defaults, names, r4d_create's error
+    without a device and the refusal of null arguments run without a memory
+    error, leak or undefined operation."""
+    import subprocess
+    exe = _host_check_binary()
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="", ASAN_OPTIONS="detect_leaks=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe, "cpu"], capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "abi_host_check cpu: ok" in r.stdout
+    assert "Sanitizer" not in r.stderr, r.stderr
