@@ -87,7 +87,7 @@ struct RunLayout {
   // fixed block
   size_t meta, recs, flows, rects, tiles, dkeys, kA, kB, vA, vB, thist, offsets, scan_tmp,
       ranges, T_final, n_contrib, n_eval, img_copy, flow_copy, walk, ptemp_fwd, keep, fcount,
-      srect, queue, zero_begin, status, totals, front, rest, cover, dhist, tickets, dstatus,
+      srect, queue, zero_begin, status, totals, front, rest, cover, tsums, dhist, tickets, dstatus,
       zero_end,
       fixed_bytes;
   // entries block
@@ -549,6 +549,7 @@ RunLayout make_layout(const Plan& p, uint64_t capacity) {
   L.front = L.totals + 2 * size_t(kMaxViews) * 8;
   L.rest = take(size_t(p.total_tiles) * 8);
   L.cover = take(p.cover_total * 4);
+  L.tsums = p.front ? take(count_tile_sums_bytes(p.n_pad, p.V)) : 0;
   L.dhist = take(4 * size_t(kMaxViews) * 256 * 4);
   L.tickets = take(16 * 4);
   L.dstatus = take(4 * size_t(sort_status_words(uint64_t(V) * np, kDepthItems)) * 4);
@@ -733,13 +734,15 @@ r4d_status enqueue_forward(r4d_ctx* ctx, const GaussPtrs<T>& g, RunState& r, T* 
         R4D_HIP(front_counts<T>(order, at<uint32_t>(F, L.tiles), at<Rect16>(F, L.rects),
                                 at<Rec<T>>(F, L.recs), slots, totals, at<uint64_t>(F, L.keep),
                                 p.n, p.n_pad, p.V, at<uint32_t>(F, L.fcount),
-                                at<Rect16>(F, L.srect), stream));
+                                at<Rect16>(F, L.srect), at<uint64_t>(F, L.tsums), r.capacity,
+                                tseg, status, stream));
       }
       R4D_HIP(count_scan_seg(order, at<uint32_t>(F, L.tiles),
                              p.front ? at<uint32_t>(F, L.fcount) : nullptr, totals, slots, p.n,
                              p.n_pad, p.V, offsets, F + L.scan_tmp, r.capacity, tseg,
                              p.front ? at<FrontTable>(F, L.front) : nullptr, status,
-                             at<uint32_t>(E, L.etemp), stream));
+                             at<uint32_t>(E, L.etemp),
+                             p.front ? at<uint64_t>(F, L.tsums) : nullptr, stream));
     }
     // packed: (index | high tile byte) words into tvA and low tile bytes into
     // tdig; otherwise tile ids into tkA and indices into tvA

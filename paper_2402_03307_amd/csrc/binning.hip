@@ -693,13 +693,33 @@ __global__ __launch_bounds__(kThreads) void front_counts_kernel(
     const Rect16* __restrict__ rects, const Rec<T>* __restrict__ recs,
     const ViewSlot* __restrict__ slots, const unsigned long long* __restrict__ totals,
     const uint64_t* __restrict__ bits, uint32_t n, uint32_t n_pad, uint64_t total,
-    uint32_t* __restrict__ counts, Rect16* __restrict__ srect) {
+    uint32_t* __restrict__ counts, Rect16* __restrict__ srect, uint64_t* __restrict__ tile_sums,
+    int n_views, unsigned long long capacity, SegTable* __restrict__ seg,
+    uint32_t* __restrict__ overflow_out) {
   __shared__ uint32_t s_cnt[kThreads];
   __shared__ uint64_t s_keep[kKeepWordsMax];
+  __shared__ uint32_t s_part[kThreads / 64];
   const uint64_t i0 = uint64_t(blockIdx.x) * kThreads;
   if (i0 >= total) return;  // (whole workgroups only)
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    write_seg_table(totals, slots, n_views, capacity, seg, overflow_out);
   const uint64_t i = i0 + threadIdx.x;
   const int lane = threadIdx.x & 63;
+  // the workgroup's counts into its tile of the count scan (the whole
+  // workgroup; a tile holds kScanTile / kThreads workgroups)
+  auto add_sum = [&](uint32_t c) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) s_part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) t += s_part[w];
+      if (t) atomicAdd(reinterpret_cast<unsigned long long*>(&tile_sums[i0 / kScanTile]),
+                       static_cast<unsigned long long>(t));
+    }
+  };
   const uint32_t v = uint32_t(i0 / n_pad);  // n_pad % kThreads == 0: one render per workgroup
   const uint32_t k = uint32_t(i - uint64_t(v) * n_pad);
   const ViewSlot& sl = slots[v];
@@ -708,7 +728,9 @@ __global__ __launch_bounds__(kThreads) void front_counts_kernel(
   const uint32_t kfirst = uint32_t(i0 - uint64_t(v) * n_pad);
   if (kfirst >= nvis || kfirst + kThreads <= r0) {
     // no Gaussian of this workgroup is cut: whole counts (0 past the visible ones)
-    counts[i] = k < nvis ? whole[size_t(v) * n + order[i]] : 0u;
+    const uint32_t c = k < nvis ? whole[size_t(v) * n + order[i]] : 0u;
+    counts[i] = c;
+    add_sum(c);
     return;
   }
   if (sl.front16) load_keep(s_keep, bits, sl);  // (only renders with a cut have a bitmap)
@@ -743,6 +765,7 @@ __global__ __launch_bounds__(kThreads) void front_counts_kernel(
   });
   __syncthreads();
   counts[i] = s_cnt[threadIdx.x];
+  add_sum(s_cnt[threadIdx.x]);
 }
 
 // Entries of the Gaussians from each render's depth cut on (front lists,
@@ -1520,6 +1543,11 @@ hipError_t scan_u32(const uint32_t* a, uint32_t n, uint32_t* out, void* temp, hi
                                                           static_cast<uint32_t*>(temp), stream);
 }
 
+size_t count_tile_sums_bytes(uint32_t n_pad, int n_views) {
+  const uint64_t tiles = (uint64_t(n_pad) * uint64_t(n_views) + 1 + kScanTile - 1) / kScanTile;
+  return tiles * sizeof(uint64_t);
+}
+
 size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views) {
   const uint64_t tiles = (uint64_t(n_pad) * uint64_t(n_views) + 1 + kScanTile - 1) / kScanTile;
   return (2 * tiles + scan_temp_elems(tiles) + 2) * sizeof(uint64_t);
@@ -1530,18 +1558,23 @@ hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
                           const ViewSlot* slots, uint32_t n, uint32_t n_pad, int n_views,
                           uint64_t* offsets, void* temp, unsigned long long capacity,
                           SegTable* seg, FrontTable* front, uint32_t* overflow_out,
-                          uint32_t* first, hipStream_t stream) {
+                          uint32_t* first, uint64_t* tile_sums, hipStream_t stream) {
   const uint64_t total = uint64_t(n_pad) * uint64_t(n_views);
   const uint64_t n_elems = total + 1;
   const uint64_t tiles = (n_elems + kScanTile - 1) / kScanTile;
-  uint64_t* sums = static_cast<uint64_t*>(temp);
-  uint64_t* scanned = sums + tiles;
+  // (front lists: front_counts added up the tile sums and wrote the table)
+  const bool summed = front_counts != nullptr;
+  uint64_t* sums = summed ? tile_sums : static_cast<uint64_t*>(temp);
+  uint64_t* scanned = static_cast<uint64_t*>(temp) + tiles;
   const bool direct = tiles <= kCountDirectTiles;
   auto run = [&](auto ld, FrontTable* ft) -> hipError_t {
-    hipLaunchKernelGGL(count_sums_kernel<decltype(ld)>, dim3(uint32_t(tiles)), dim3(kThreads), 0,
-                       stream, ld, sums, totals, slots, n_views, capacity, seg, overflow_out);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (!summed) {
+      hipLaunchKernelGGL(count_sums_kernel<decltype(ld)>, dim3(uint32_t(tiles)), dim3(kThreads),
+                         0, stream, ld, sums, totals, slots, n_views, capacity, seg, overflow_out);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     if (!direct) {
       e = device_exclusive_scan<uint64_t, LoadT<uint64_t>>(LoadT<uint64_t>{sums, tiles}, scanned,
                                                            tiles, scanned + tiles, stream);
@@ -1580,23 +1613,28 @@ hipError_t front_counts(const uint32_t* order, const uint32_t* whole, const Rect
                         const Rec<T>* recs, const ViewSlot* slots,
                         const unsigned long long* totals, const uint64_t* bits, uint32_t n,
                         uint32_t n_pad, int n_views, uint32_t* counts, Rect16* srect,
-                        hipStream_t stream) {
+                        uint64_t* tile_sums, unsigned long long capacity, SegTable* seg,
+                        uint32_t* overflow_out, hipStream_t stream) {
   const uint64_t total = uint64_t(n_pad) * uint64_t(n_views);
   if (total == 0) return hipSuccess;
+  static_assert(kScanTile % kThreads == 0, "a scan tile holds whole workgroups");
   hipLaunchKernelGGL(front_counts_kernel<T>, dim3(uint32_t((total + kThreads - 1) / kThreads)),
                      dim3(kThreads), 0, stream, order, whole, rects, recs, slots, totals, bits, n,
-                     n_pad, total, counts, srect);
+                     n_pad, total, counts, srect, tile_sums, n_views, capacity, seg,
+                     overflow_out);
   return hipGetLastError();
 }
 
 template hipError_t front_counts<float>(const uint32_t*, const uint32_t*, const Rect16*,
                                         const Rec<float>*, const ViewSlot*,
                                         const unsigned long long*, const uint64_t*, uint32_t,
-                                        uint32_t, int, uint32_t*, Rect16*, hipStream_t);
+                                        uint32_t, int, uint32_t*, Rect16*, uint64_t*,
+                                        unsigned long long, SegTable*, uint32_t*, hipStream_t);
 template hipError_t front_counts<double>(const uint32_t*, const uint32_t*, const Rect16*,
                                          const Rec<double>*, const ViewSlot*,
                                          const unsigned long long*, const uint64_t*, uint32_t,
-                                         uint32_t, int, uint32_t*, Rect16*, hipStream_t);
+                                         uint32_t, int, uint32_t*, Rect16*, uint64_t*,
+                                         unsigned long long, SegTable*, uint32_t*, hipStream_t);
 
 bool packed_tile_sort_ok(uint32_t n, uint32_t max_tiles_per_view) {
   return n <= (1u << 24) && max_tiles_per_view <= 65536u;

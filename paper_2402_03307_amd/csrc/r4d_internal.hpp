@@ -140,6 +140,9 @@ hipError_t seg_table(const unsigned long long* totals, const ViewSlot* slots, in
                      hipStream_t stream);
 
 size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
+// Bytes of the scan's tile sums when front_counts adds them up itself (they
+// must be zero before front_counts runs).
+size_t count_tile_sums_bytes(uint32_t n_pad, int n_views);
 // offsets[v * n_pad + k] = sum over renders u < v of all their entries plus the
 // entries of render v's Gaussians order[v][0..k-1]; offsets[V * n_pad] = total.
 // order[v] holds render v's totals[2v] visible Gaussians (the rest is unset).
@@ -149,13 +152,14 @@ size_t count_scan_seg_temp_bytes(uint32_t n_pad, int n_views);
 // are counts[v][order[v][k]] (whole lists) or, when front_counts is not null,
 // front_counts[v * n_pad + k] (front lists, front_counts below); then the
 // segment lengths become the renders' front entry counts and `front` gets
-// their rest areas.
+// their rest areas; front_counts has then also written the segment table and
+// the scan's tile sums (tile_sums), so the scan starts from those.
 hipError_t count_scan_seg(const uint32_t* order, const uint32_t* counts,
                           const uint32_t* front_counts, const unsigned long long* totals,
                           const ViewSlot* slots, uint32_t n, uint32_t n_pad, int n_views,
                           uint64_t* offsets, void* temp, unsigned long long capacity,
                           SegTable* seg, FrontTable* front, uint32_t* overflow_out,
-                          uint32_t* first, hipStream_t stream);
+                          uint32_t* first, uint64_t* tile_sums, hipStream_t stream);
 
 // ---- front lists (front.hpp)
 // Keep bitmaps (rows of keep_words(tiles_x) words at each render's keep_base)
@@ -173,13 +177,17 @@ hipError_t front_keep(const ViewSlot* slots, int n_views, const Rect16* rects,
 // counts[v * n_pad + k]: entries of the front lists from render v's Gaussian at
 // depth position k (order[v][k]); whole: per-Gaussian counts of the whole
 // lists ([v][n]); srect[v * n_pad + k] = its tile box for k from the render's
-// depth cut to its visible count.
+// depth cut to its visible count.  Also adds the counts up per tile of the
+// count scan into tile_sums (count_tile_sums_bytes, zeroed beforehand) and
+// writes the segment table of the emitted list for `capacity` (as seg_table),
+// the count scan's first step.
 template <typename T>
 hipError_t front_counts(const uint32_t* order, const uint32_t* whole, const Rect16* rects,
                         const Rec<T>* recs, const ViewSlot* slots,
                         const unsigned long long* totals, const uint64_t* bits, uint32_t n,
                         uint32_t n_pad, int n_views, uint32_t* counts, Rect16* srect,
-                        hipStream_t stream);
+                        uint64_t* tile_sums, unsigned long long capacity, SegTable* seg,
+                        uint32_t* overflow_out, hipStream_t stream);
 
 // Emission of every render's tile entries in depth order (each Gaussian's
 // tiles row by row, its row runs from tileset.hpp) into its segment, one
