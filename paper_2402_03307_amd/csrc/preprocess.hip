@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
     GaussPtrs<T> g, const ViewSlot* __restrict__ slots, SettingsDev st, uint32_t n_pad,
     Rec<T>* __restrict__ recs, Vec2<T>* __restrict__ flows, Rect16* __restrict__ rects,
     uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_keys,
-    ulonglong2* __restrict__ block_totals, uint4* __restrict__ zero, uint64_t zero16) {
+    ulonglong2* __restrict__ block_totals, uint4* __restrict__ zero, uint64_t zero16,
+    uint32_t n_views) {
   // per-Gaussian aggregates of the row walk, in kCopies copies picked by the
   // row's lane (consecutive rows of one Gaussian sit in consecutive lanes, so
   // its atomics spread over the copies instead of piling onto one address);
@@ -73,11 +74,14 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
   __shared__ int s_x0[kCopies * kStride], s_x1[kCopies * kStride], s_y0[kCopies * kStride],
       s_y1[kCopies * kStride];
   const int n = g.n;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int vi = blockIdx.y;
+  // renders vary fastest over the workgroups, so that the workgroups of one
+  // block of Gaussians run together and share its parameters in the caches
+  const uint32_t vi = blockIdx.x % n_views, blk = blockIdx.x / n_views;
+  const uint32_t nblk = gridDim.x / n_views;
+  const int i = int(blk) * kBlock + int(threadIdx.x);
   // the run's counters and status words, cleared here for the later stages
-  for (uint64_t z = (uint64_t(blockIdx.y) * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
-       z < zero16; z += uint64_t(gridDim.x) * gridDim.y * kBlock)
+  for (uint64_t z = uint64_t(blockIdx.x) * kBlock + threadIdx.x; z < zero16;
+       z += uint64_t(gridDim.x) * kBlock)
     zero[z] = make_uint4(0u, 0u, 0u, 0u);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const ViewDev v = slots[vi].v;
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_fwd_kernel(
       a += s_tot[0][w];
       b += s_tot[1][w];
     }
-    block_totals[size_t(vi) * gridDim.x + blockIdx.x] = make_ulonglong2(a, b);
+    block_totals[size_t(vi) * nblk + blk] = make_ulonglong2(a, b);
   }
 }
 
@@ -385,16 +389,17 @@ hipError_t launch_preprocess_fwd(const GaussPtrs<T>& g, const ViewSlot* slots, i
     return hipErrorInvalidValue;
   const uint32_t blocks = uint32_t((g.n + kBlock - 1) / kBlock);
   const dim3 grid(blocks, uint32_t(n_views));
+  const dim3 grid_fwd(blocks * uint32_t(n_views));  // (render fastest)
   ulonglong2* block_totals = static_cast<ulonglong2*>(temp);
   uint4* z = static_cast<uint4*>(zero);
   const uint64_t z16 = zero_bytes / 16;
   if (static3d) {
     if (flows) return hipErrorInvalidValue;  // static Gaussians do not move
-    R4D_DEG_DISPATCH(preprocess_fwd_kernel, true, grid, g, slots, st, n_pad, recs, flows, rects,
-                     tiles_touched, depth_keys, block_totals, z, z16)
+    R4D_DEG_DISPATCH(preprocess_fwd_kernel, true, grid_fwd, g, slots, st, n_pad, recs, flows,
+                     rects, tiles_touched, depth_keys, block_totals, z, z16, uint32_t(n_views))
   } else {
-    R4D_DEG_DISPATCH(preprocess_fwd_kernel, false, grid, g, slots, st, n_pad, recs, flows, rects,
-                     tiles_touched, depth_keys, block_totals, z, z16)
+    R4D_DEG_DISPATCH(preprocess_fwd_kernel, false, grid_fwd, g, slots, st, n_pad, recs, flows,
+                     rects, tiles_touched, depth_keys, block_totals, z, z16, uint32_t(n_views))
   }
   hipLaunchKernelGGL(compact_keys_kernel, grid, dim3(kBlock), 0, stream, depth_keys, uint32_t(g.n),
                      n_pad, block_totals, totals, dseg, vis_keys, vis_index);
