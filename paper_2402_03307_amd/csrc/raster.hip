@@ -978,10 +978,30 @@ __global__ __launch_bounds__(256) void l1_grad_views_kernel(const float* __restr
   const int64_t b0 = lv.base[v], cnt = lv.count[v];
   const float inv = 1.0f / float(cnt);
   const int64_t stride = int64_t(gridDim.x) * 256;
+  auto one = [&](float d) { return d > 0.f ? inv : (d < 0.f ? -inv : 0.f); };
   float part = 0.f;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < cnt; i += stride) {
-    const float d = image[b0 + i] - target[b0 + i];
-    grad[b0 + i] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+  int64_t done = 0;
+  const float* im = image + b0;
+  const float* tg = target + b0;
+  float* gr = grad + b0;
+  if (((reinterpret_cast<uintptr_t>(im) | reinterpret_cast<uintptr_t>(tg) |
+        reinterpret_cast<uintptr_t>(gr)) & 15u) == 0) {
+    // 16-byte accesses (four values per thread and step), the rest below
+    const int64_t n4 = cnt / 4;
+    const float4* im4 = reinterpret_cast<const float4*>(im);
+    const float4* tg4 = reinterpret_cast<const float4*>(tg);
+    float4* gr4 = reinterpret_cast<float4*>(gr);
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n4; i += stride) {
+      const float4 a = im4[i], t = tg4[i];
+      const float4 d = make_float4(a.x - t.x, a.y - t.y, a.z - t.z, a.w - t.w);
+      gr4[i] = make_float4(one(d.x), one(d.y), one(d.z), one(d.w));
+      part += (fabsf(d.x) + fabsf(d.y)) + (fabsf(d.z) + fabsf(d.w));
+    }
+    done = n4 * 4;
+  }
+  for (int64_t i = done + int64_t(blockIdx.x) * 256 + threadIdx.x; i < cnt; i += stride) {
+    const float d = im[i] - tg[i];
+    gr[i] = one(d);
     part += fabsf(d);
   }
   if (partials) {
