@@ -54,12 +54,18 @@ __device__ __forceinline__ void store_relaxed(uint32_t* p, uint32_t v) {
 
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    // (32-bit values: lane moves, rowwalk.hpp; two's complement makes it hold
+    // for signed values too)
+    return T(wave_incl_scan_u32(uint32_t(x), lane));
+  } else {
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
+    for (int off = 1; off < 64; off <<= 1) {
+      const T y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    return x;
   }
-  return x;
 }
 
 // Exclusive scan of one value per thread over a workgroup of NT threads;

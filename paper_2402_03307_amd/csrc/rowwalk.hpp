@@ -14,12 +14,24 @@
 
 namespace r4d {
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
+// x plus the value the DPP lane move CTRL brings, in the rows ROWS (a lane of
+// another row, or one whose source lies outside its row under BOUND, adds 0).
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_plus(uint32_t x) {
+  return x + uint32_t(__builtin_amdgcn_update_dpp(0, int(x), CTRL, ROWS, 0xf, BOUND));
+}
+
+// Inclusive scan over the wavefront's 64 lanes with DPP lane moves (no LDS):
+// within each row of 16 lanes by row shifts of 1, 2, 4 and 8, then across
+// rows by adding lane 15 of the row before to rows 1 and 3 (row_bcast:15)
+// and lane 31 to rows 2 and 3 (row_bcast:31).
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x, int /*lane*/) {
+  x = dpp_plus<0x111, 0xf, true>(x);   // row_shr:1
+  x = dpp_plus<0x112, 0xf, true>(x);   // row_shr:2
+  x = dpp_plus<0x114, 0xf, true>(x);   // row_shr:4
+  x = dpp_plus<0x118, 0xf, true>(x);   // row_shr:8
+  x = dpp_plus<0x142, 0xa, false>(x);  // row_bcast:15 into rows 1, 3
+  x = dpp_plus<0x143, 0xc, false>(x);  // row_bcast:31 into rows 2, 3
   return x;
 }
 
