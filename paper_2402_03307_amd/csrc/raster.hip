@@ -782,8 +782,8 @@ __global__ __launch_bounds__(TS* TS / PPT) void raster_fwd_kernel(
 
 // The rest pass of the front lists (front.hpp): the tiles the main pass
 // queued (their pixels outlasted their front lists), each rendered again from
-// the start with its rest collected, by a small persistent grid; with nothing
-// queued every workgroup returns at once.
+// the start with its rest collected, by a persistent grid of kRestGroups
+// workgroups; with nothing queued every workgroup returns at once.
 template <typename T, int TS, int PPT, bool COUNT, bool FLOW>
 __global__ __launch_bounds__(TS* TS / PPT) void raster_rest_kernel(
     const Rec<T>* __restrict__ recs, const Vec2<T>* __restrict__ flows, uint32_t n,
