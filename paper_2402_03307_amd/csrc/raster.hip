@@ -904,15 +904,39 @@ __global__ __launch_bounds__(256) void seg_queue_kernel(const uint32_t* __restri
   const uint32_t w = t < total_tiles ? walk[t] : 0u;
   const uint32_t cnt = (w + kSegment - 1) / kSegment;
   const uint32_t f = cnt > 0u ? cnt - 1u : 0u;
-  // full segments: a wavefront scan of the counts, one reservation, then the
-  // wavefront writes its segments 64 at a time, each lane finding the tile of
-  // its segment by a binary search over the tiles' first positions
+  // full segments: a wavefront scan of the counts
   const uint32_t incl = wave_incl_scan_u32(f, lane);
   const uint32_t excl = incl - f;
   const uint32_t total_w = __shfl(incl, 63, 64);
-  uint32_t base = 0;
-  if (lane == 63 && total_w) base = atomicAdd(&q_count[0], total_w);
-  base = __shfl(base, 63, 64);
+  // last segments by length class: a ballot per class, this lane's class mask
+  const uint32_t cls = cnt > 0u ? len_bucket(w - f * kSegment) : kLenBuckets;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  unsigned long long mine = 0ull;
+  uint32_t n_cls = 0;  // lane k < kLenBuckets: the wavefront's tiles of class k
+#pragma unroll
+  for (uint32_t k = 0; k < kLenBuckets; ++k) {
+    const unsigned long long m = __ballot(cls == k);
+    if (cls == k) mine = m;
+    if (uint32_t(lane) == k) n_cls = uint32_t(__popcll(m));
+  }
+  // every reservation of the wavefront in one atomic instruction: lanes
+  // 0 .. kLenBuckets-1 for the classes, lane 63 for the full segments
+  uint32_t* q = nullptr;
+  uint32_t amount = 0;
+  if (uint32_t(lane) < kLenBuckets) {
+    q = &q_count[1 + lane];
+    amount = n_cls;
+  } else if (lane == 63) {
+    q = &q_count[0];
+    amount = total_w;
+  }
+  uint32_t got = 0;
+  if (amount) got = atomicAdd(q, amount);
+  const uint32_t base = __shfl(got, 63, 64);
+  const uint32_t cb = __shfl(got, int(cls < kLenBuckets ? cls : 0u), 64);
+  // full segments: the wavefront writes its segments 64 at a time, each lane
+  // finding the tile of its segment by a binary search over the tiles' first
+  // positions
   for (uint32_t c = 0; c < total_w; c += 64) {
     const uint32_t i = c + uint32_t(lane);
     const int o = wave_upper_lane(excl, i);
@@ -920,20 +944,8 @@ __global__ __launch_bounds__(256) void seg_queue_kernel(const uint32_t* __restri
     const uint32_t seg = i - __shfl(excl, o, 64);
     if (i < total_w) q_full[base + i] = make_uint2(tile, seg);
   }
-  // last segments by length class: a ballot rank and one atomic per class
-  const uint32_t cls = cnt > 0u ? len_bucket(w - f * kSegment) : kLenBuckets;
-  const unsigned long long lt = (1ull << lane) - 1ull;
-#pragma unroll
-  for (uint32_t k = 0; k < kLenBuckets; ++k) {
-    const unsigned long long m = __ballot(cls == k);
-    if (m == 0ull) continue;
-    const int leader = __ffsll(static_cast<long long>(m)) - 1;
-    uint32_t cb = 0;
-    if (lane == leader) cb = atomicAdd(&q_count[1 + k], uint32_t(__popcll(m)));
-    cb = __shfl(cb, leader, 64);
-    if (cls == k)
-      q_last[size_t(k) * total_tiles + cb + uint32_t(__popcll(m & lt))] = make_uint2(t, f);
-  }
+  if (cls < kLenBuckets)
+    q_last[size_t(cls) * total_tiles + cb + uint32_t(__popcll(mine & lt))] = make_uint2(t, f);
 }
 
 int compute_units() {
