@@ -184,11 +184,17 @@ __global__ __launch_bounds__(kThreads) void fill_zero_kernel(uint4* __restrict__
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Digit histograms of keys, PASSES digits of 8 bits, per segment (blockIdx.y).
+// Digit histograms of keys, PASSES digits of 8 bits, per segment (blockIdx.y),
+// kHistItems keys per thread, all loaded before the first count.  Same-address
+// LDS atomics are serialised, and the top two digits of depths are shared by
+// many keys: for those, the lanes of a wavefront whose digit equals the first
+// lane's add their number with one atomic.
+constexpr uint32_t kHistItems = 8;
+constexpr uint32_t kHistChunk = uint32_t(kThreads) * kHistItems;
+
 template <int PASSES>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                               const SegTable* __restrict__ seg,
-                                                              uint32_t chunk,
                                                               uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[PASSES][256];
 #pragma unroll
@@ -197,13 +203,32 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
   const uint32_t s = blockIdx.y;
   if (s < seg->count) {
     const uint32_t s0 = seg->start[s];
-    const uint32_t begin = s0 + blockIdx.x * chunk;
+    const uint32_t begin = s0 + blockIdx.x * kHistChunk + threadIdx.x;
     const uint32_t send = s0 + seg->len[s];
-    const uint32_t end = send < begin + chunk ? send : begin + chunk;
-    for (uint32_t i = begin + threadIdx.x; i < end; i += kThreads) {
-      const uint32_t key = keys[i];
+    const int lane = threadIdx.x & 63;
+    uint32_t k[kHistItems];
 #pragma unroll
-      for (int p = 0; p < PASSES; ++p) atomicAdd(&h[p][(key >> (8 * p)) & 255u], 1u);
+    for (uint32_t i = 0; i < kHistItems; ++i) {
+      const uint32_t j = begin + i * kThreads;
+      k[i] = j < send ? keys[j] : 0u;
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kHistItems; ++i) {
+      // lane 0 holds the wavefront's first key of the step: when it is past
+      // the end, so is every other lane's
+      const bool ok = begin + i * kThreads < send;
+#pragma unroll
+      for (int p = 0; p < PASSES; ++p) {
+        const uint32_t d = (k[i] >> (8 * p)) & 255u;
+        if (p < 2) {
+          if (ok) atomicAdd(&h[p][d], 1u);
+          continue;
+        }
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const unsigned long long same = __ballot(ok && d == d0);
+        if (ok && d != d0) atomicAdd(&h[p][d], 1u);
+        if (same && lane == 0) atomicAdd(&h[p][d0], uint32_t(__popcll(same)));
+      }
     }
   }
   __syncthreads();
@@ -1083,7 +1108,10 @@ __global__ __launch_bounds__(kThreads) void tile_hist_kernel(const uint32_t* __r
   }
 }
 
-// Low-digit counts per block of the emitted entries (digits: one byte each).
+// Digit counts per block of entries whose digits are one byte each (the
+// digits buffer 16-byte aligned): each thread counts 16 consecutive digits,
+// read with one 16-byte load where all 16 lie in the block.
+static_assert(kChunk == kThreads * 16, "one 16-byte digit word per thread and block");
 __global__ __launch_bounds__(kThreads) void lo_count_kernel(const uint8_t* __restrict__ digits,
                                                             const SegTable* __restrict__ seg,
                                                             uint32_t* __restrict__ cnt) {
@@ -1095,8 +1123,15 @@ __global__ __launch_bounds__(kThreads) void lo_count_kernel(const uint8_t* __res
   const uint32_t b = blockIdx.x;
   uint32_t s, sstart, nvalid = 0;
   if (!seg->overflow && block_span(seg, b * uint32_t(kChunk), s, sstart, nvalid)) {
-    const uint32_t e0 = b * uint32_t(kChunk);
-    for (uint32_t q = tid; q < nvalid; q += kThreads) atomicAdd(&s_h[wave][digits[e0 + q]], 1u);
+    const uint32_t e0 = b * uint32_t(kChunk), q0 = uint32_t(tid) * 16u;
+    if (q0 + 16u <= nvalid) {
+      const uint4 w4 = *reinterpret_cast<const uint4*>(digits + e0 + q0);
+      const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+      for (int j = 0; j < 16; ++j) atomicAdd(&s_h[wave][(w[j >> 2] >> (8 * (j & 3))) & 255u], 1u);
+    } else {
+      for (uint32_t q = q0; q < nvalid; ++q) atomicAdd(&s_h[wave][digits[e0 + q]], 1u);
+    }
   }
   __syncthreads();
   uint32_t c = 0;
@@ -1378,13 +1413,12 @@ uint32_t sort_status_words(uint64_t capacity_elems, int items) {
 hipError_t radix_histogram(const uint32_t* keys, const SegTable* seg, int n_segments,
                            uint32_t max_len, int passes, uint32_t* hist, hipStream_t stream) {
   if (max_len == 0 || n_segments <= 0) return hipSuccess;
-  const uint32_t chunk = 4096;
-  const dim3 grid((max_len + chunk - 1) / chunk, uint32_t(n_segments));
+  const dim3 grid((max_len + kHistChunk - 1) / kHistChunk, uint32_t(n_segments));
   switch (passes) {
-    case 1: hipLaunchKernelGGL(radix_hist_kernel<1>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
-    case 2: hipLaunchKernelGGL(radix_hist_kernel<2>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
-    case 3: hipLaunchKernelGGL(radix_hist_kernel<3>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
-    case 4: hipLaunchKernelGGL(radix_hist_kernel<4>, grid, dim3(kThreads), 0, stream, keys, seg, chunk, hist); break;
+    case 1: hipLaunchKernelGGL(radix_hist_kernel<1>, grid, dim3(kThreads), 0, stream, keys, seg, hist); break;
+    case 2: hipLaunchKernelGGL(radix_hist_kernel<2>, grid, dim3(kThreads), 0, stream, keys, seg, hist); break;
+    case 3: hipLaunchKernelGGL(radix_hist_kernel<3>, grid, dim3(kThreads), 0, stream, keys, seg, hist); break;
+    case 4: hipLaunchKernelGGL(radix_hist_kernel<4>, grid, dim3(kThreads), 0, stream, keys, seg, hist); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
