@@ -274,6 +274,43 @@ def test_gradients_fd_scene_vs_oracle(r4d, device):
         assert np.all(np.abs(gg - gr) <= 1e-3 * (np.abs(gr) + 1e-2 * np.abs(gr).max()) + 1e-7), k
 
 
+@pytest.mark.parametrize("k", [1, 2, 63, 65])
+def test_few_visible_gaussians_vs_oracle(r4d, device, k):
+    """k of 200 Gaussians left after the time cull (the others far past the
+    render time): single-key and partial-wavefront segments in every stage
+    (histogram, depth sort, counts, emission, tile sort, both rasterisers);
+    the visible count exact, image and gradients against the oracle (the
+    loss weighted off the pixels the oracle flags as ambiguous)."""
+    g = W.gaussians(200, 3, xyz_half_extent=0.5)
+    g["means"][3, :k] = 0.5
+    g["means"][3, k:] = 50.0
+    v = W.view((0.0, 0.0, -4.0), 64, 48, 60.0, 0.5)
+    st = W.settings()
+    print(f"case: {k} visible of 200, 64x48", flush=True)
+    _, _, _, saved = _render(r4d, g, [v], st, device)
+    assert saved.stats(0)["n_visible"] == k
+    saved.release()
+    weight = np.random.default_rng(5).uniform(-1, 1, (3, 48, 64))
+    ref = O.render(g, v, st, requires_grad=True)
+    weight[:, ref["ambiguous"].numpy().astype(bool)] = 0.0  # no weight where a decision is a tie
+    (ref["image"] * torch.as_tensor(weight)).sum().backward()
+    p = to_device(g, device)
+    for key in ("means", "log_scales", "rotors", "opacity", "sh"):
+        p[key].requires_grad_(True)
+    img = r4d.render(p, [v], st)[0]
+    err, n_amb = image_errors(img.detach().cpu().numpy().astype(np.float64),
+                              ref["image"].detach().numpy(), ref["ambiguous"].numpy())
+    assert err <= IMG_TOL and n_amb <= 8
+    (img * torch.as_tensor(weight, dtype=torch.float32, device=device)).sum().backward()
+    for key in ("means", "log_scales", "rotors", "opacity", "sh"):
+        gg = p[key].grad.cpu().numpy().astype(np.float64)
+        gr = ref["params"][key].grad.numpy()
+        assert not np.any(gg[..., k:]) and not np.any(gr[..., k:]), key
+        rel = _rel(gg, gr)
+        print(f"{key}: rel {rel:.3g}")
+        assert rel <= 1e-3, key
+
+
 def test_degenerate_rotors_vs_oracle(r4d, device):
     """Rotors whose squared norm is below 1e-12 before the App. A update (0,
     all 1e-7) or after it (1 +- e0123 and a scaled copy) render as the
