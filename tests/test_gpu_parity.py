@@ -311,6 +311,32 @@ def test_few_visible_gaussians_vs_oracle(r4d, device, k):
         assert rel <= 1e-3, key
 
 
+@pytest.mark.parametrize("mode", ["fused", "graph"])
+@pytest.mark.parametrize("k", [0, 1, 63])
+def test_empty_and_tiny_segments_in_one_call(r4d, device, mode, k):
+    """Two renders in one call whose visible sets split 200 Gaussians into k
+    and 200 - k (the second render's time is where the others live): empty
+    and single-key segments next to full ones in the segmented sorts.  Each
+    render equals the same render made alone, bit for bit, and its visible
+    count is exact."""
+    g = W.gaussians(200, 3, xyz_half_extent=0.5)
+    g["means"][3, :k] = 0.5
+    g["means"][3, k:] = 50.0
+    views = [W.view((0.0, 0.0, -4.0), 64, 48, 60.0, 0.5),
+             W.view((0.3, -0.2, -4.0), 56, 40, 55.0, 50.0, bg=(0.1, 0.2, 0.3))]
+    st = dict(W.settings(), mode=mode)
+    print(f"case: {mode}, {k} and {200 - k} visible", flush=True)
+    for rep in range(2 if mode == "graph" else 1):  # a graph is captured, then replayed
+        _, _, imgs, saved = _render(r4d, g, views, st, device)
+        assert [saved.stats(v)["n_visible"] for v in range(2)] == [k, 200 - k]
+        imgs = [i.clone() for i in imgs]
+        saved.release()
+        for v, im in zip(views, imgs):
+            _, _, single, s1 = _render(r4d, g, [v], W.settings(), device)
+            s1.release()
+            assert torch.equal(im, single[0]), (rep, v["t"])
+
+
 def test_degenerate_rotors_vs_oracle(r4d, device):
     """Rotors whose squared norm is below 1e-12 before the App. A update (0,
     all 1e-7) or after it (1 +- e0123 and a scaled copy) render as the
